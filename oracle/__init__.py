@@ -1,0 +1,28 @@
+"""CPU FP64 oracle for MLMC with stabilized leapfrog local time-stepping.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+baseline leg of the benchmark may import anything in this package; the
+library's product path never does (it fails loudly when its HIP extension is
+missing instead of falling back here).
+
+The oracle is a plain, slow, deliberately unfused restatement of what the
+method computes (Grote, Michel, Nobile: "Uncertainty quantification by MLMC
+and local time-stepping for wave propagation"):
+
+* ``mesh``     -- rectilinear level meshes (tensor grids split into P1
+                  triangles), Dirichlet mask, coefficient blocks, fine-element
+                  flags, projector P (Sec. 3.3), lumped mass, QoI weights.
+* ``fem``      -- general P1 assembly of K(kappa) and the lumped M
+                  (Sec. 3.1, mass-lumped Galerkin system).
+* ``rng``      -- Philox4x64-10 samples via numpy's independent Philox,
+                  Box-Muller normals, per-sample step counts.
+* ``cheby``    -- the stabilized Chebyshev constants delta, omega, beta_k,
+                  beta_{k+1/2} (Sec. 3.3), in exact rational arithmetic.
+* ``lts``      -- Algorithm 2 (stabilized LF-LTS), literally, on all DOFs;
+                  plain leapfrog; discrete energy.
+* ``mlmc``     -- QoI, coupled differences, two-pass moments, optimal N_l,
+                  bias estimate, Algorithm 1 (Sec. 2.2).
+* ``adjoint``  -- discrete adjoint of the LF-LTS recurrence (dQ/d log c).
+
+It shares no code with the HIP path and imports nothing from it.
+"""

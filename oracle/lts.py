@@ -1,0 +1,114 @@
+"""Leapfrog and stabilized LF-LTS time stepping, oracle side (test infrastructure only).
+
+Everything runs in the symmetrized variables of Sec. 3.1, z = M^1/2 u,
+A = M^-1/2 K M^-1/2, on *all* DOFs, with the projector P kept as a 0/1
+diagonal, exactly as Algorithm 2 (stabilized LF-LTS, Sec. 3.3) is stated:
+
+  w_n      = A (I - P) q_0,                       q_0 = z_n
+  q_{1/p}  = q_0 - 1/2 (dt/p)^2 (2p^2/(omega delta)) (w_n + A P q_0)
+  q_{(m+1)/p} = (1 + beta_m) q_{m/p} - beta_m q_{(m-1)/p}
+               - (dt/p)^2 (2p^2/omega) beta_{m+1/2} (w_n + A P q_{m/p}),  m = 1..p-1
+  z_{n+1}  = -z_{n-1} + 2 q_1
+
+Reading: the index k of beta_k, beta_{k+1/2} inside the substep loop is the
+loop index m.  Start-up (the paper gives none for LTS): z_1 = q_1(z_0) +
+dt M^1/2 v_0, the LTS analogue of the leapfrog start-up of Sec. 3.1 (for
+P = 0 the two coincide).  The sign of the v_0 term follows the Taylor
+expansion (+).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .cheby import ChebConsts, cheb_consts
+from .fem import Operators, sym_operator
+
+
+def lts_q1(A, Pd, z, dt, cc: ChebConsts):
+    """q_1^n of Algorithm 2 for q_0 = z (lines 1-4).  Linear in z."""
+    p = cc.p
+    w = A @ ((1.0 - Pd) * z)
+    c1 = 0.5 * (dt / p) * (dt / p) * (2.0 * p * p / (cc.omega * cc.delta))
+    q_prev = z
+    q = z - c1 * (w + A @ (Pd * z))
+    for m in range(1, p):
+        c2 = (dt / p) * (dt / p) * (2.0 * p * p / cc.omega) * cc.beta_half[m]
+        q_next = (1.0 + cc.beta[m]) * q - cc.beta[m] * q_prev - c2 * (w + A @ (Pd * q))
+        q_prev, q = q, q_next
+    return q
+
+
+def lts_step(A, Pd, z_n, z_nm1, dt, cc):
+    """One stabilized LF-LTS step: z_{n+1} = -z_{n-1} + 2 q_1^n."""
+    return -z_nm1 + 2.0 * lts_q1(A, Pd, z_n, dt, cc)
+
+
+def lf_step(A, z_n, z_nm1, dt):
+    """Plain leapfrog of Sec. 3.1 with zero forcing: z_{n+1} = 2 z_n - z_{n-1} - dt^2 A z_n."""
+    return 2.0 * z_n - z_nm1 - dt * dt * (A @ z_n)
+
+
+def pulse(ops: Operators, x0, width: float = 0.05) -> np.ndarray:
+    """Nodal values of exp(-|x - x0|^2 / width^2) on the DOFs."""
+    lv = ops.lv
+    X, Y = np.meshgrid(lv.xs, lv.ys)
+    ids = lv.dof_ids
+    px, py = X.ravel()[ids], Y.ravel()[ids]
+    r2 = (px - x0[0]) ** 2 + (py - x0[1]) ** 2
+    return np.exp(-r2 / (width * width))
+
+
+class Solver:
+    """One sample on one level: z-form Algorithm 2 with start-up."""
+
+    def __init__(self, ops: Operators, kappa_blocks, nu: float | None = None, p: int | None = None,
+                 Pd=None):
+        self.ops = ops
+        self.A = sym_operator(ops, kappa_blocks)
+        self.p = ops.lv.p if p is None else p
+        self.nu = ops.lv.nu if nu is None else nu
+        self.cc = cheb_consts(self.p, self.nu)
+        self.Pd = ops.Pd if Pd is None else Pd
+        self.sqm = np.sqrt(ops.m)
+
+    def q1(self, z, dt):
+        return lts_q1(self.A, self.Pd, z, dt, self.cc)
+
+    def run(self, u0, dt, n_steps, v0=None, keep=False):
+        """Return u(T) = M^-1/2 z_{n_steps} (and all z_n when ``keep``)."""
+        z0 = self.sqm * u0
+        z1 = self.q1(z0, dt)
+        if v0 is not None:
+            z1 = z1 + dt * self.sqm * v0
+        zs = [z0, z1] if keep else None
+        zm, zc = z0, z1
+        for _ in range(1, n_steps):
+            zn = lts_step(self.A, self.Pd, zc, zm, dt, self.cc)
+            zm, zc = zc, zn
+            if keep:
+                zs.append(zc)
+        u = zc / self.sqm
+        return (u, zs) if keep else u
+
+    def run_lf(self, u0, dt, n_steps, v0=None):
+        """Plain leapfrog (Sec. 3.1): z_1 = z_0 + dt M^1/2 v_0 - dt^2/2 A z_0."""
+        z0 = self.sqm * u0
+        z1 = z0 - 0.5 * dt * dt * (self.A @ z0)
+        if v0 is not None:
+            z1 = z1 + dt * self.sqm * v0
+        zm, zc = z0, z1
+        for _ in range(1, n_steps):
+            zm, zc = zc, lf_step(self.A, zc, zm, dt)
+        return zc / self.sqm
+
+    def energy(self, z_np1, z_n, dt):
+        """E_{n+1/2} = 1/2 |z_{n+1} - z_n|^2 / dt^2 + 1/2 z_{n+1}^T A_p z_n with the
+        effective LTS operator A_p y = 2 (y - q_1(y)) / dt^2 (symmetric)."""
+        d = z_np1 - z_n
+        Apz = 2.0 * (z_n - self.q1(z_n, dt)) / (dt * dt)
+        return 0.5 * float(d @ d) / (dt * dt) + 0.5 * float(z_np1 @ Apz)
+
+
+def qoi(ops: Operators, u) -> float:
+    """Q = sum_i w_i u_i(T): lumped-mass quadrature of u over the QoI region."""
+    return ops.qoi_w @ u
