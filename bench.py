@@ -1,0 +1,158 @@
+"""Benchmark: batched LF-LTS throughput on one MI355X.
+
+Workload (the single-level batched throughput configuration): unit square,
+512 base cells per axis, refined 8x in the coarse cells meeting (0.48, 0.52)
+(442,225 DOFs, |P| = 204,081, p = 8, nu = 0.01), 256 samples of a 4x4 block
+log-normal wave speed (sigma 0.25), Gaussian pulse (width 0.05, centre in
+[0.2,0.4]^2), T = 1, dt = 0.2 h / max c per sample, FP64, QoI = lumped
+integral over [0.6,0.8]^2.  Synthetic inputs from Philox seed 0.
+
+One step = one pass of the whole hot path over the batch: the initial state,
+every LF-LTS time step of every sample (coarse sweep + p local substeps), the
+QoI and the per-level moment reduction.  Inputs (per-sample coefficients,
+pulse centres, step counts) are resident in HBM before the timed region.
+
+Prints one JSON line (see the repository's benchmark contract).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_BASE, BOX, REF = 512, (0.48, 0.52), 8
+N_SAMPLES = 256
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = ("unit square 512x512 base refined 8x in (0.48,0.52): 442225 DOFs, |P|=204081, p=8, "
+            "nu=0.01, 256 samples, 4x4 blocks sigma=0.25, T=1, FP64")
+
+
+def _cpu_worker(args):
+    """Oracle (test infrastructure) timing of `steps` coarse steps of one sample."""
+    i, steps = args
+    import numpy as np
+    from oracle import fem, lts, mesh, rng
+    lv = mesh.box_refined_level(N_BASE, box=BOX, ref=REF)
+    ops = fem.operators(lv)
+    rule = rng.SampleRule()
+    smp = rng.draw(0, 0, i, rule)
+    n, dt = rng.steps_for(smp, rule, lv.h)
+    s = lts.Solver(ops, smp.kappa)
+    z0 = s.sqm * lts.pulse(ops, smp.x0)
+    t0 = time.perf_counter()
+    zm, zc = z0, s.q1(z0, dt)
+    for _ in range(1, steps):
+        zm, zc = zc, -zm + 2.0 * s.q1(zc, dt)
+    el = time.perf_counter() - t0
+    n_dof, n_p = ops.Pd.size, int(ops.Pd.sum())
+    return steps * ((n_dof - n_p) + lv.p * n_p), el, bool(np.isfinite(zc).all())
+
+
+def cpu_baseline(steps_per_sample: int = 150):
+    import multiprocessing as mp
+    procs = max(1, min(os.cpu_count() or 1, 16))
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(procs) as pool:
+        res = pool.map(_cpu_worker, [(i, steps_per_sample) for i in range(procs)])
+    wall = time.perf_counter() - t0
+    upd = sum(r[0] for r in res)
+    busy = max(r[1] for r in res)
+    return {"value": upd / busy, "unit": "DOF-updates/s", "cores": procs, "kind": "oracle",
+            "sample": f"samples 0..{procs - 1} of the same workload, first {steps_per_sample} coarse "
+                      f"steps each (one process per core, scipy CSR, FP64); wall {wall:.1f} s incl. setup"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--plain", action="store_true", help="time the one-launch-per-sample form")
+    ap.add_argument("--samples", type=int, default=N_SAMPLES)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the workload is one GPU's "
+                                   "share (samples shard across GPUs with one moment all-reduce)",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    cpu = None if args.no_cpu else cpu_baseline()
+
+    import numpy as np
+    import torch
+
+    import paper_2106_11117_amd as P
+
+    dev = torch.device("cuda:0")
+    ctx = P.Context(0)
+    lid = ctx.add_rect_level(P.box_rule(N_BASE, box=BOX, ref=REF))
+    info = ctx.level_info(lid)
+    rule = P.sample_rule()
+    s = P.gen_samples(0, 0, 0, args.samples, rule, info["h"])
+    kap = torch.tensor(s["kappa"], device=dev)
+    x0 = torch.tensor(s["x0"], device=dev)
+    ns = torch.tensor(s["n_steps"], device=dev)
+    dt = torch.tensor(s["dt"], device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        q = ctx.forward(lid, kap, x0, ns, dt, plain=args.plain)
+        m = ctx.moments(q)
+        return q, m
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    kern_ms, launches = 0.0, 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        q, m = step()
+        t = ctx.timing()
+        kern_ms += t["step_kernel_ms"]
+        launches += t["step_launches"]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.set_timing(False)
+
+    per_step = (info["n_dof"] - info["n_P"]) + info["p"] * info["n_P"]
+    sum_ns = int(s["n_steps"].sum())
+    dof_upd = float(sum_ns) * per_step * args.steps
+    alg_bytes = 24.0 * info["n_dof"] * sum_ns * args.steps
+    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    out = {
+        "metric": "LF-LTS DOF-updates/s & % HBM peak; MLMC time at fixed RMSE, batched vs plain",
+        "value": dof_upd / el,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (Philox seed 0)",
+        "config": {"workload": WORKLOAD, "samples": args.samples, "sum_n_steps": sum_ns,
+                   "dofs": info["n_dof"], "P": info["n_P"], "p": info["p"],
+                   "form": "plain" if args.plain else "batched"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "LF-LTS step (all step launches)",
+                     "launches": launches, "kernel_ms": kern_ms},
+        "cpu_baseline": cpu,
+        "mean_Q": float(m[1]), "var_Q": float(m[2] / max(m[0] - 1, 1)),
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,351 @@
+/*
+ * lfltsmc.h -- C ABI of an MI355X (gfx950) library for multilevel Monte Carlo
+ * with stabilized leapfrog local time-stepping (LF-LTS) for the wave equation
+ * with a random coefficient (Grote, Michel, Nobile: "Uncertainty
+ * quantification by MLMC and local time-stepping for wave propagation").
+ *
+ * Model (Sec. 2.1): u_tt - div(c^2 grad u) = 0 in D, u = 0 on the boundary,
+ * u(0) = u0, u_t(0) = 0, with c = exp(g) and g piecewise constant on a grid of
+ * coefficient blocks.  Space (Sec. 3.1): continuous P1 elements with mass
+ * lumping on rectilinear grids whose cells are split into two triangles along
+ * the diagonal (x_a, y_b)-(x_a+1, y_b+1).  Time (Sec. 3.3, Algorithm 2): one
+ * coarse leapfrog step dt per step and p local substeps of size dt/p on the
+ * DOFs selected by the diagonal projector P.  Estimator (Sec. 2.2): the
+ * coupled differences Delta Q_l = Q_l - Q_{l-1} on a common sample, their
+ * per-level mean and unbiased variance, and Algorithm 1 for N_l and L.
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns lts_status: LTS_OK (0) or a negative code.  No
+ *    function throws, aborts or exits.  After an error, lts_last_error(ctx)
+ *    describes it (ctx-owned string, valid until the next call on ctx).
+ *  - Arguments are validated on the host before any device work is queued;
+ *    an LTS_ERR_ARG return leaves the context and every output untouched.
+ *  - Caller arrays are only read during the call (meshes are copied in).
+ *    Output arrays are caller-allocated.  The context owns all device
+ *    workspace (level data, states, checkpoints, captured graphs).
+ *  - ptr_kind LTS_PTR_HOST: sample arrays and outputs are host memory; the
+ *    call returns after the results are in place.  LTS_PTR_DEVICE: they are
+ *    device pointers on the context's device; work is ordered on the context
+ *    stream and the call returns once the outputs are written (the library
+ *    synchronizes its stream before returning in both cases).
+ *  - A context is not thread-safe; distinct contexts are independent.
+ *  - Floating point is IEEE binary64 unless a precision flag says otherwise.
+ */
+#ifndef LFLTSMC_H
+#define LFLTSMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lts_status;
+typedef struct lts_ctx_s* lts_ctx;
+
+enum {
+  LTS_OK = 0,
+  LTS_ERR_ARG = -1,       /* invalid argument (sizes, ids, ranges, pointers) */
+  LTS_ERR_HIP = -2,       /* a HIP runtime call failed; text in lts_last_error */
+  LTS_ERR_OOM = -3,       /* device allocation failed */
+  LTS_ERR_UNSTABLE = -4,  /* at least one sample produced a non-finite QoI;
+                             those QoIs are NaN, all others are valid */
+  LTS_ERR_STATE = -5      /* call not valid in the current context state */
+};
+
+enum { LTS_FP64 = 0, LTS_FP32_STEP = 1 };   /* time-stepping precision; QoI sums stay FP64 */
+enum { LTS_PTR_HOST = 0, LTS_PTR_DEVICE = 1 };
+
+/* Node flag bits returned by lts_level_arrays (one byte per grid node). */
+enum { LTS_NODE_DOF = 1, LTS_NODE_P = 2, LTS_NODE_FPLUS = 4 };
+
+/* ------------------------------------------------------------------------ */
+/* Context                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Create a context on HIP device `hip_device`.  `hip_stream` is a hipStream_t
+ * (cast to void*) that all device work is ordered on; NULL makes the context
+ * create and own a stream of default priority.  *out receives the handle.
+ * Errors: LTS_ERR_ARG (out NULL, no such device), LTS_ERR_HIP. */
+lts_status lts_create(lts_ctx* out, int32_t hip_device, void* hip_stream);
+
+/* Release every device resource of ctx (ctx may be NULL). */
+lts_status lts_destroy(lts_ctx ctx);
+
+/* Text of the last error on ctx ("" if none).  Never NULL. */
+const char* lts_last_error(lts_ctx ctx);
+
+/* ------------------------------------------------------------------------ */
+/* Levels (Sec. 3.2-3.4: the mesh hierarchy with local refinement)           */
+/* ------------------------------------------------------------------------ */
+
+/* One level's mesh.  Cells are [x_a, x_a+1] x [y_b, y_b+1], a = 0..nx_cells-1,
+ * b = 0..ny_cells-1, flat cell index b*nx_cells + a; nodes (a, b), a =
+ * 0..nx_cells, flat node index b*(nx_cells+1) + a.  Every active cell is two
+ * P1 triangles.  A node is a DOF iff its four incident cells exist and are
+ * active (homogeneous Dirichlet data everywhere else).  P (Sec. 3.3) marks the
+ * DOFs that are vertices of a fine cell.  All arrays are caller-owned and
+ * copied by lts_add_level. */
+typedef struct {
+  int32_t nx_cells, ny_cells;     /* >= 2 each */
+  const double* x;                /* [nx_cells+1], strictly increasing */
+  const double* y;                /* [ny_cells+1], strictly increasing */
+  const uint8_t* cell_active;     /* [ny_cells*nx_cells], 1 = cell in D; NULL = all */
+  const int32_t* cell_block;      /* [ny_cells*nx_cells], coefficient block in [0, n_blocks) */
+  const uint8_t* cell_fine;       /* [ny_cells*nx_cells], 1 = cell in D_fine */
+  const uint8_t* cell_qoi;        /* [ny_cells*nx_cells], 1 = cell in the QoI region */
+  int32_t n_blocks;               /* 1..255 */
+  double h;                       /* base spacing; the step rule dt = cfl*h/max c uses it */
+  int32_t p;                      /* local substeps, 1..256 */
+  double nu;                      /* stabilization, 0 <= nu <= 1 (nu = 0: original LF-LTS) */
+} lts_grid_desc;
+
+/* Copy a level into ctx (host and device) and return its id (0, 1, ... in
+ * call order).  Errors: LTS_ERR_ARG (sizes, ordering, ids), LTS_ERR_OOM. */
+lts_status lts_add_level(lts_ctx ctx, const lts_grid_desc* desc, int32_t* level_id_out);
+
+enum { LTS_RULE_BOX = 0, LTS_RULE_GRADED_L = 1 };
+
+/* Generated rectilinear levels (exact dyadic node coordinates).
+ *  LTS_RULE_BOX: square [lo,hi]^2, n_base uniform cells per axis; per axis,
+ *    every coarse interval meeting the open interval (box_lo, box_hi) is split
+ *    into `ref` equal parts (Sec. 3.2: a fixed refined region).
+ *  LTS_RULE_GRADED_L: square [lo,hi]^2 minus the cells with midpoint x > 0,
+ *    y < 0 (an L-shape with reentrant corner at the origin); per axis the two
+ *    cells next to 0 are replaced by the nodes +-h 2^-j, j = 1..layers
+ *    (Sec. 3.4: grading toward a reentrant corner).
+ * Both: fine cells have a leg shorter than h/2; blocks are an nbx x nby grid
+ * over [lo,hi]^2 assigned by cell midpoint (block = by*nbx + bx); QoI cells
+ * have their midpoint in the closed box [qx_lo,qx_hi] x [qy_lo,qy_hi];
+ * p = 0 selects p = ceil(h / smallest cell leg). */
+typedef struct {
+  int32_t kind;
+  double lo, hi;
+  int32_t n_base;
+  double box_lo, box_hi;
+  int32_t ref;
+  int32_t layers;
+  int32_t nbx, nby;
+  double qx_lo, qx_hi, qy_lo, qy_hi;
+  int32_t p;
+  double nu;
+} lts_rect_rule;
+
+/* Build the level described by `rule` on the host, then lts_add_level it.
+ * Errors: LTS_ERR_ARG, LTS_ERR_OOM. */
+lts_status lts_build_rect_level(lts_ctx ctx, const lts_rect_rule* rule, int32_t* level_id_out);
+
+typedef struct {
+  int32_t nx_nodes, ny_nodes;     /* nx_cells+1, ny_cells+1 */
+  int32_t n_dof, n_P, n_Fplus;    /* DOFs, |P|, |F+| with F+ = P and its stiffness neighbours */
+  int32_t p, n_blocks;
+  double h, nu;
+  double delta, omega;            /* stabilized Chebyshev constants (Sec. 3.3) */
+} lts_level_info;
+
+/* Sizes and constants of a level.  Errors: LTS_ERR_ARG. */
+lts_status lts_level_info_get(lts_ctx ctx, int32_t level, lts_level_info* out);
+
+/* Host copies of a level's derived arrays (any pointer may be NULL):
+ * x [nx_nodes], y [ny_nodes], node_flags [ny_nodes*nx_nodes] (LTS_NODE_*
+ * bits), mass [ny_nodes*nx_nodes] (lumped mass, every node incl. boundary:
+ * sum over incident triangles of |T|/3), qoi_w [ny_nodes*nx_nodes] (QoI
+ * weights: the same sum restricted to QoI cells, 0 on non-DOFs),
+ * cell_block [ny_cells*nx_cells] (-1 for inactive cells).  Errors: LTS_ERR_ARG. */
+lts_status lts_level_arrays(lts_ctx ctx, int32_t level, double* x, double* y, uint8_t* node_flags,
+                            double* mass, double* qoi_w, int32_t* cell_block);
+
+/* Host-only variant of lts_build_rect_level + lts_level_arrays: builds the
+ * level of `rule` without any device and copies out its info (required) and
+ * arrays (each may be NULL; sizes as in lts_level_arrays, so a first call with
+ * NULL arrays returns the sizes).  Errors: LTS_ERR_ARG. */
+lts_status lts_rect_level_host(const lts_rect_rule* rule, lts_level_info* info, double* x, double* y,
+                               uint8_t* node_flags, double* mass, double* qoi_w, int32_t* cell_block);
+
+/* Stabilized Chebyshev constants of Sec. 3.3 for (p, nu): delta = 1 + nu/p^2,
+ * omega = 2 T_p'(delta)/T_p(delta); beta[k] = T_{k-1}(delta)/T_{k+1}(delta) and
+ * beta_half[k] = T_k(delta)/T_{k+1}(delta) for k = 1..p-1 (arrays of length p,
+ * index 0 set to 0; may be NULL).  Also the per-step coefficients for a step
+ * dt (coef may be NULL, length p+1): coef[0] = a_p (after the p substeps a DOF
+ * outside F+ holds u + a_p w, a_p = -dt^2/2 up to rounding), coef[1] =
+ * 1/2 (dt/p)^2 2p^2/(omega delta), coef[1+m] = (dt/p)^2 2p^2/omega beta_{m+1/2}.
+ * Errors: LTS_ERR_ARG (p outside 1..256, nu outside [0,1]). */
+lts_status lts_cheb_constants(int32_t p, double nu, double dt, double* delta, double* omega,
+                              double* beta, double* beta_half, double* coef);
+
+/* ------------------------------------------------------------------------ */
+/* Random samples (host; counter-based, reproducible per (seed, level, i))   */
+/* ------------------------------------------------------------------------ */
+
+/* Sample law: g_b ~ N(0, sigma^2) i.i.d. on n_blocks blocks; pulse centre
+ * uniform in [px_lo,px_hi] x [py_lo,py_hi]; u0 = exp(-|x-x0|^2/width^2);
+ * n_steps = ceil(T max_b exp(g_b) / (cfl h)), dt = T/n_steps on a mesh of
+ * base spacing h. */
+typedef struct {
+  int32_t n_blocks;               /* even, 2..255 */
+  double sigma;
+  double px_lo, px_hi, py_lo, py_hi;
+  double width;
+  double T;
+  double cfl;
+} lts_sample_rule;
+
+/* Draw samples i = first_index .. first_index+n-1 of MLMC level
+ * `sample_level` (Sec. 2.2: each level has its own independent samples; the
+ * fine and coarse solve of one difference share them).  Stream: Philox4x64-10
+ * (Salmon et al., SC'11) with key (seed, 0) and counter (j, i, sample_level,
+ * purpose), purpose 0 = field, 1 = pulse; uniforms ((x >> 12) + 0.5) 2^-52;
+ * Box-Muller on consecutive uniforms.  Steps and dt are for a mesh of base
+ * spacing h_mesh.  Outputs (host, any may be NULL): g [n][n_blocks],
+ * kappa [n][n_blocks] = exp(2 g), x0 [n][2], n_steps [n], dt [n].
+ * Errors: LTS_ERR_ARG. */
+lts_status lts_gen_samples(uint64_t seed, int32_t sample_level, int64_t first_index, int32_t n,
+                           const lts_sample_rule* rule, double h_mesh, double* g_out,
+                           double* kappa_out, double* x0_out, int32_t* n_steps_out,
+                           double* dt_out);
+
+/* Raw Philox4x64-10 block (for known-answer tests): out[4] = Philox(ctr[4], key[2]). */
+lts_status lts_philox4x64_10(const uint64_t* ctr, const uint64_t* key, uint64_t* out);
+
+/* ------------------------------------------------------------------------ */
+/* Forward solves (Algorithm 2 per sample, QoI at T)                         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t n;                      /* number of samples, >= 0 */
+  int32_t ptr_kind;               /* LTS_PTR_HOST or LTS_PTR_DEVICE for the arrays below */
+  const double* kappa;            /* [n][n_blocks of the level], > 0 */
+  const double* x0;               /* [n][2] pulse centres */
+  const int32_t* n_steps;         /* [n], >= 1 */
+  const double* dt;               /* [n], > 0 */
+  double width;                   /* pulse width, > 0 */
+} lts_samples;
+
+/* Solve every sample on `level` from t = 0 to n_steps*dt with stabilized
+ * LF-LTS (Algorithm 2; start-up u_1 = q_1(u_0) since u_t(0) = 0) and write
+ * Q[s] = sum_i qoi_w[i] u_i(T) (same ptr_kind as the samples).
+ * precision: LTS_FP64 or LTS_FP32_STEP (states and substeps in binary32).
+ * Errors: LTS_ERR_ARG, LTS_ERR_OOM, LTS_ERR_HIP, LTS_ERR_UNSTABLE. */
+lts_status lts_forward(lts_ctx ctx, int32_t level, const lts_samples* samples, int32_t precision,
+                       double* Q_out);
+
+/* The same solve with one kernel launch per sample and step (no batching of
+ * samples), used as the unbatched reference form.  Same contract. */
+lts_status lts_forward_plain(lts_ctx ctx, int32_t level, const lts_samples* samples,
+                             int32_t precision, double* Q_out);
+
+/* Coupled difference for MLMC level l >= 1 (Sec. 2.2): the same samples
+ * (kappa, x0) solved on level_fine and level_coarse, each with its own
+ * n_steps/dt.  Writes Qf, Qc and dQ = Qf - Qc (any may be NULL; same
+ * ptr_kind).  Errors as lts_forward. */
+lts_status lts_forward_coupled(lts_ctx ctx, int32_t level_fine, int32_t level_coarse,
+                               const lts_samples* fine, const lts_samples* coarse,
+                               int32_t precision, double* Qf_out, double* Qc_out, double* dQ_out);
+
+/* ------------------------------------------------------------------------ */
+/* Batched form: many (level, samples) jobs advanced together                */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t level;
+  lts_samples samples;            /* all jobs of one call use the same ptr_kind */
+  int32_t q_offset;               /* Q of sample s of this job goes to Q_out[q_offset + s] */
+} lts_job;
+
+enum { LTS_BATCH_GRAPH = 1 };     /* capture the step loop into HIP graphs and replay */
+
+/* Advance all jobs of all levels in shared launches: every launch advances
+ * one step of every job that still has steps left, so uneven mesh sizes and
+ * step counts share the device.  Tile sizes and samples per workgroup come
+ * from the context's autotuner (tuned once per level shape and cached).
+ * flags: 0 or LTS_BATCH_GRAPH.  Errors as lts_forward. */
+lts_status lts_batch_run(lts_ctx ctx, const lts_job* jobs, int32_t n_jobs, int32_t flags,
+                         double* Q_out);
+
+/* ------------------------------------------------------------------------ */
+/* Reductions (Sec. 2.2: estimator and level variance)                       */
+/* ------------------------------------------------------------------------ */
+
+/* out[0] = n, out[1] = mean, out[2] = M2 = sum (x_i - mean)^2 of x[0..n-1],
+ * computed on the device by per-lane Welford updates merged pairwise (Chan
+ * et al.); the unbiased variance is M2/(n-1).  x has ptr_kind; out is host.
+ * Errors: LTS_ERR_ARG, LTS_ERR_HIP. */
+lts_status lts_moments(lts_ctx ctx, const double* x, int32_t n, int32_t ptr_kind, double* out);
+
+/* ------------------------------------------------------------------------ */
+/* Discrete adjoint (gradient of the QoI w.r.t. the block log wave speeds)   */
+/* ------------------------------------------------------------------------ */
+
+/* dQ_dg[s][b] = dL/dg_b for L = sum_s dLdQ[s] Q_s, where g_b = log c_b =
+ * log(kappa_b)/2, by the backward LF-LTS recurrence (the adjoint of the
+ * forward recurrence, run from T to 0) with forward states recomputed from
+ * checkpoints stored every K_ckpt steps.  dt and n_steps are held fixed.
+ * Q_out (may be NULL) receives the forward QoIs.  FP64 only.
+ * Errors: LTS_ERR_ARG, LTS_ERR_OOM, LTS_ERR_HIP. */
+lts_status lts_backward(lts_ctx ctx, int32_t level, const lts_samples* samples, const double* dLdQ,
+                        int32_t K_ckpt, double* Q_out, double* dQ_dg_out);
+
+/* ------------------------------------------------------------------------ */
+/* Multilevel Monte Carlo driver (Algorithm 1)                              */
+/* ------------------------------------------------------------------------ */
+
+enum { LTS_MLMC_BATCHED = 0, LTS_MLMC_PLAIN = 1 };
+
+#define LTS_MAX_LEVELS 8
+
+typedef struct {
+  int32_t n_levels;               /* levels available, 1..LTS_MAX_LEVELS */
+  int32_t level_ids[LTS_MAX_LEVELS];
+  lts_sample_rule rule;
+  uint64_t seed;
+  double eps;                     /* RMSE target */
+  double alpha;                   /* bias decay rate of the bias estimate (2 in the paper) */
+  int32_t L_start;                /* initial finest level (Algorithm 1 starts at 2) */
+  int32_t N_init[LTS_MAX_LEVELS]; /* initial sample counts */
+  int32_t mode;                   /* LTS_MLMC_BATCHED or LTS_MLMC_PLAIN */
+  int32_t max_total_samples;      /* safety cap (<= 0: none) */
+} lts_mlmc_opts;
+
+typedef struct {
+  double estimate;                /* sum_l mean(Delta Q_l) */
+  int32_t L;                      /* finest level used */
+  int32_t N[LTS_MAX_LEVELS];
+  double mean[LTS_MAX_LEVELS];
+  double var[LTS_MAX_LEVELS];     /* unbiased V_l */
+  double cost[LTS_MAX_LEVELS];    /* cost model C_l (DOF updates per Delta Q_l sample) */
+  double bias;                    /* |mean Delta Q_L| / (2^alpha - 1) */
+  double rmse;                    /* sqrt(sum V_l/N_l + bias^2) */
+  int32_t converged;              /* 1 if the bias test passed at the final L */
+  double seconds;                 /* wall time of the solves */
+} lts_mlmc_result;
+
+/* Algorithm 1: start with L = min(L_start, n_levels-1) and N_init; repeat
+ * {solve the missing Delta Q samples; estimate V_l; raise N_l to
+ * ceil(2/eps^2 sqrt(V_l/C_l) sum sqrt(V C)); if the bias estimate exceeds
+ * eps/sqrt(2) and a finer level exists, add it} until no N_l grew.
+ * C_l is the cost model in DOF updates per sample with the nominal step
+ * cfl*h.  Errors: LTS_ERR_ARG, LTS_ERR_OOM, LTS_ERR_HIP, LTS_ERR_UNSTABLE. */
+lts_status lts_mlmc(lts_ctx ctx, const lts_mlmc_opts* opts, lts_mlmc_result* out);
+
+/* ------------------------------------------------------------------------ */
+/* Timing of the last forward call (for benchmarks)                          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  double step_kernel_ms;          /* summed HIP-event time of the step kernel launches */
+  int64_t step_launches;          /* number of step kernel launches */
+  double total_ms;                /* HIP-event time of the whole device part */
+  double dof_updates;             /* sum over samples of n_steps ((N - |P|) + p |P|) */
+  double alg_bytes;               /* sum over samples of n_steps * 24 (12 in FP32) * N */
+} lts_timing;
+
+/* Enable (1) or disable (0) per-launch event timing (adds events around the
+ * step kernel launches on the context stream). */
+lts_status lts_set_timing(lts_ctx ctx, int32_t enable);
+lts_status lts_get_timing(lts_ctx ctx, lts_timing* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LFLTSMC_H */

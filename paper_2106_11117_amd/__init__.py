@@ -1,0 +1,300 @@
+"""MLMC with stabilized leapfrog local time-stepping on MI355X (gfx950).
+
+Thin Python binding of the C ABI in ``include/lfltsmc.h``: argument
+marshalling only; every step of the solve runs in the library's HIP kernels.
+Host arrays are numpy arrays; device arrays are torch tensors on the
+context's device (torch is used for device memory and streams only).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (LTS_BATCH_GRAPH, LTS_FP32_STEP, LTS_FP64, LTS_MLMC_BATCHED, LTS_MLMC_PLAIN,
+                   LTS_NODE_DOF, LTS_NODE_FPLUS, LTS_NODE_P, LTS_PTR_DEVICE, LTS_PTR_HOST,
+                   LTS_RULE_BOX, LTS_RULE_GRADED_L, LtsError)
+
+__all__ = ["Context", "gen_samples", "philox", "rect_level_host", "cheb_constants", "sample_rule", "box_rule", "graded_L_rule", "LtsError",
+           "LTS_FP64", "LTS_FP32_STEP", "LTS_BATCH_GRAPH", "LTS_MLMC_BATCHED", "LTS_MLMC_PLAIN",
+           "LTS_NODE_DOF", "LTS_NODE_P", "LTS_NODE_FPLUS"]
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32)) if a is not None else None
+
+
+def box_rule(n_base, box=(0.45, 0.55), ref=4, lo=0.0, hi=1.0, blocks=(4, 4),
+             qoi=(0.6, 0.8, 0.6, 0.8), p=0, nu=0.01) -> _lib.RectRule:
+    """Square [lo,hi]^2, refined `ref` times in the coarse cells meeting the open box."""
+    return _lib.RectRule(kind=LTS_RULE_BOX, lo=lo, hi=hi, n_base=n_base, box_lo=box[0], box_hi=box[1],
+                         ref=ref, layers=0, nbx=blocks[0], nby=blocks[1], qx_lo=qoi[0], qx_hi=qoi[1],
+                         qy_lo=qoi[2], qy_hi=qoi[3], p=p, nu=nu)
+
+
+def graded_L_rule(n_base, layers=6, lo=-1.0, hi=1.0, blocks=(8, 8), qoi=(0.5, 0.9, 0.2, 0.6),
+                  p=0, nu=0.01) -> _lib.RectRule:
+    """L-shape [lo,hi]^2 minus the quadrant x > 0, y < 0, graded toward the corner."""
+    return _lib.RectRule(kind=LTS_RULE_GRADED_L, lo=lo, hi=hi, n_base=n_base, box_lo=0.0, box_hi=0.0,
+                         ref=1, layers=layers, nbx=blocks[0], nby=blocks[1], qx_lo=qoi[0],
+                         qx_hi=qoi[1], qy_lo=qoi[2], qy_hi=qoi[3], p=p, nu=nu)
+
+
+def sample_rule(n_blocks=16, sigma=0.25, pulse=(0.2, 0.4, 0.2, 0.4), width=0.05, T=1.0,
+                cfl=0.2) -> _lib.SampleRule:
+    return _lib.SampleRule(n_blocks=n_blocks, sigma=sigma, px_lo=pulse[0], px_hi=pulse[1],
+                           py_lo=pulse[2], py_hi=pulse[3], width=width, T=T, cfl=cfl)
+
+
+def _check(code, ctx=None):
+    if code != 0:
+        msg = _lib.load().lts_last_error(ctx).decode() if ctx else ""
+        raise LtsError(code, msg)
+
+
+def philox(ctr, key):
+    """Raw Philox4x64-10 block (4 words) at counter ``ctr`` and key ``key``."""
+    lib = _lib.load()
+    c = (C.c_uint64 * 4)(*[int(v) for v in ctr])
+    k = (C.c_uint64 * 2)(*[int(v) for v in key])
+    o = (C.c_uint64 * 4)()
+    _check(lib.lts_philox4x64_10(c, k, o))
+    return [int(v) for v in o]
+
+
+def gen_samples(seed, sample_level, first_index, n, rule, h_mesh):
+    """Host sample generation: dict of g, kappa [n, nb], x0 [n, 2], n_steps [n], dt [n]."""
+    lib = _lib.load()
+    nb = rule.n_blocks
+    g = np.zeros((n, nb))
+    kappa = np.zeros((n, nb))
+    x0 = np.zeros((n, 2))
+    ns = np.zeros(n, dtype=np.int32)
+    dt = np.zeros(n)
+    _check(lib.lts_gen_samples(C.c_uint64(seed), sample_level, first_index, n, C.byref(rule), h_mesh,
+                               _dp(g), _dp(kappa), _dp(x0), _ip(ns), _dp(dt)))
+    return {"g": g, "kappa": kappa, "x0": x0, "n_steps": ns, "dt": dt}
+
+
+def rect_level_host(rule) -> dict:
+    """Build a rule-described level on the host only; info plus derived arrays."""
+    lib = _lib.load()
+    info = _lib.LevelInfo()
+    _check(lib.lts_rect_level_host(C.byref(rule), C.byref(info), None, None, None, None, None, None))
+    nx, ny = info.nx_nodes, info.ny_nodes
+    x, y = np.zeros(nx), np.zeros(ny)
+    flags = np.zeros((ny, nx), dtype=np.uint8)
+    mass, qw = np.zeros((ny, nx)), np.zeros((ny, nx))
+    cb = np.zeros((ny - 1, nx - 1), dtype=np.int32)
+    _check(lib.lts_rect_level_host(C.byref(rule), C.byref(info), _dp(x), _dp(y),
+                                   flags.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(mass), _dp(qw),
+                                   _ip(cb)))
+    d = {k: getattr(info, k) for k, _ in _lib.LevelInfo._fields_}
+    d.update({"x": x, "y": y, "flags": flags, "mass": mass, "qoi_w": qw, "cell_block": cb})
+    return d
+
+
+def cheb_constants(p, nu, dt=1.0) -> dict:
+    """Library-side stabilized Chebyshev constants and per-step coefficients."""
+    lib = _lib.load()
+    d, w = C.c_double(), C.c_double()
+    b, bh, cf = np.zeros(p), np.zeros(p), np.zeros(p + 1)
+    _check(lib.lts_cheb_constants(p, nu, dt, C.byref(d), C.byref(w), _dp(b), _dp(bh), _dp(cf)))
+    return {"delta": d.value, "omega": w.value, "beta": b, "beta_half": bh, "coef": cf}
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+class _SampleArgs:
+    """Marshals kappa/x0/n_steps/dt (numpy -> host, torch cuda -> device)."""
+
+    def __init__(self, kappa, x0, n_steps, dt, width):
+        self.dev = _is_torch(kappa)
+        if self.dev:
+            import torch
+            self.keep = [kappa.contiguous().to(torch.float64), x0.contiguous().to(torch.float64),
+                         n_steps.contiguous().to(torch.int32), dt.contiguous().to(torch.float64)]
+            ptrs = [t.data_ptr() for t in self.keep]
+            n = int(self.keep[3].numel())
+        else:
+            self.keep = [np.ascontiguousarray(kappa, dtype=np.float64),
+                         np.ascontiguousarray(x0, dtype=np.float64),
+                         np.ascontiguousarray(n_steps, dtype=np.int32),
+                         np.ascontiguousarray(dt, dtype=np.float64)]
+            ptrs = [a.ctypes.data for a in self.keep]
+            n = int(self.keep[3].size)
+        self.n = n
+        self.s = _lib.Samples(n=n, ptr_kind=LTS_PTR_DEVICE if self.dev else LTS_PTR_HOST,
+                              kappa=ptrs[0], x0=ptrs[1], n_steps=ptrs[2], dt=ptrs[3], width=width)
+
+    def out(self, count=None):
+        count = self.n if count is None else count
+        if self.dev:
+            import torch
+            t = torch.empty(count, dtype=torch.float64, device=self.keep[0].device)
+            return t, t.data_ptr()
+        a = np.zeros(count)
+        return a, a.ctypes.data
+
+
+class Context:
+    """A library context on one HIP device (see lts_create)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.lib = _lib.load()
+        self.h = C.c_void_p()
+        _check(self.lib.lts_create(C.byref(self.h), device, stream))
+        self.levels = []
+
+    def close(self):
+        if self.h:
+            self.lib.lts_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _c(self, code):
+        _check(code, self.h)
+
+    # --- levels -----------------------------------------------------------
+    def add_rect_level(self, rule) -> int:
+        lid = C.c_int32()
+        self._c(self.lib.lts_build_rect_level(self.h, C.byref(rule), C.byref(lid)))
+        self.levels.append(lid.value)
+        return lid.value
+
+    def add_level(self, x, y, cell_block, cell_fine, cell_qoi, n_blocks, h, p, nu, cell_active=None):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        cb = np.ascontiguousarray(cell_block, dtype=np.int32)
+        cf = np.ascontiguousarray(cell_fine, dtype=np.uint8)
+        cq = np.ascontiguousarray(cell_qoi, dtype=np.uint8)
+        ca = None if cell_active is None else np.ascontiguousarray(cell_active, dtype=np.uint8)
+        u8 = C.POINTER(C.c_uint8)
+        d = _lib.GridDesc(nx_cells=len(x) - 1, ny_cells=len(y) - 1, x=_dp(x), y=_dp(y),
+                          cell_active=ca.ctypes.data_as(u8) if ca is not None else None,
+                          cell_block=_ip(cb), cell_fine=cf.ctypes.data_as(u8),
+                          cell_qoi=cq.ctypes.data_as(u8), n_blocks=n_blocks, h=h, p=p, nu=nu)
+        lid = C.c_int32()
+        self._c(self.lib.lts_add_level(self.h, C.byref(d), C.byref(lid)))
+        self.levels.append(lid.value)
+        return lid.value
+
+    def level_info(self, level) -> dict:
+        info = _lib.LevelInfo()
+        self._c(self.lib.lts_level_info_get(self.h, level, C.byref(info)))
+        return {k: getattr(info, k) for k, _ in _lib.LevelInfo._fields_}
+
+    def level_arrays(self, level) -> dict:
+        i = self.level_info(level)
+        nx, ny = i["nx_nodes"], i["ny_nodes"]
+        x, y = np.zeros(nx), np.zeros(ny)
+        flags = np.zeros((ny, nx), dtype=np.uint8)
+        mass, qw = np.zeros((ny, nx)), np.zeros((ny, nx))
+        cb = np.zeros((ny - 1, nx - 1), dtype=np.int32)
+        self._c(self.lib.lts_level_arrays(self.h, level, _dp(x), _dp(y),
+                                          flags.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(mass),
+                                          _dp(qw), _ip(cb)))
+        return {"x": x, "y": y, "flags": flags, "mass": mass, "qoi_w": qw, "cell_block": cb}
+
+    # --- solves -----------------------------------------------------------
+    def forward(self, level, kappa, x0, n_steps, dt, width=0.05, precision=LTS_FP64, plain=False):
+        sa = _SampleArgs(kappa, x0, n_steps, dt, width)
+        q, qp = sa.out()
+        fn = self.lib.lts_forward_plain if plain else self.lib.lts_forward
+        self._c(fn(self.h, level, C.byref(sa.s), precision, qp))
+        return q
+
+    def forward_coupled(self, level_fine, level_coarse, kappa, x0, ns_f, dt_f, ns_c, dt_c, width=0.05,
+                        precision=LTS_FP64):
+        fa = _SampleArgs(kappa, x0, ns_f, dt_f, width)
+        ca = _SampleArgs(kappa, x0, ns_c, dt_c, width)
+        qf, qfp = fa.out()
+        qc, qcp = fa.out()
+        dq, dqp = fa.out()
+        self._c(self.lib.lts_forward_coupled(self.h, level_fine, level_coarse, C.byref(fa.s),
+                                             C.byref(ca.s), precision, qfp, qcp, dqp))
+        return qf, qc, dq
+
+    def batch_run(self, jobs, graph=False):
+        """jobs: list of (level, kappa, x0, n_steps, dt, width).  Returns the Q of all
+        jobs concatenated in job order."""
+        args, cjobs, off = [], [], 0
+        for (level, kappa, x0, ns, dt, width) in jobs:
+            sa = _SampleArgs(kappa, x0, ns, dt, width)
+            args.append(sa)
+            cjobs.append(_lib.Job(level=level, samples=sa.s, q_offset=off))
+            off += sa.n
+        arr = (_lib.Job * len(cjobs))(*cjobs)
+        q, qp = args[0].out(off)
+        self._c(self.lib.lts_batch_run(self.h, arr, len(cjobs), LTS_BATCH_GRAPH if graph else 0, qp))
+        return q
+
+    def backward(self, level, kappa, x0, n_steps, dt, dLdQ, width=0.05, K=64):
+        sa = _SampleArgs(kappa, x0, n_steps, dt, width)
+        nb = self.level_info(level)["n_blocks"]
+        q, qp = sa.out()
+        if sa.dev:
+            import torch
+            g = torch.empty((sa.n, nb), dtype=torch.float64, device=sa.keep[0].device)
+            gp = g.data_ptr()
+            dl = dLdQ.contiguous().to(torch.float64)
+            dlp = dl.data_ptr()
+        else:
+            g = np.zeros((sa.n, nb))
+            gp = g.ctypes.data
+            dl = np.ascontiguousarray(dLdQ, dtype=np.float64)
+            dlp = dl.ctypes.data
+        self._c(self.lib.lts_backward(self.h, level, C.byref(sa.s), dlp, K, qp, gp))
+        return q, g
+
+    def moments(self, x):
+        out = np.zeros(3)
+        if _is_torch(x):
+            xt = x.contiguous().to(dtype=x.new_empty(0).double().dtype)
+            self._c(self.lib.lts_moments(self.h, xt.data_ptr(), xt.numel(), LTS_PTR_DEVICE, _dp(out)))
+        else:
+            xa = np.ascontiguousarray(x, dtype=np.float64)
+            self._c(self.lib.lts_moments(self.h, xa.ctypes.data, xa.size, LTS_PTR_HOST, _dp(out)))
+        return out
+
+    def mlmc(self, level_ids, rule, eps, seed=0, alpha=2.0, L_start=2, N_init=(256, 64, 16, 8, 4),
+             mode=LTS_MLMC_BATCHED, max_total_samples=0):
+        o = _lib.MLMCOpts()
+        o.n_levels = len(level_ids)
+        for k, l in enumerate(level_ids):
+            o.level_ids[k] = l
+        o.rule = rule
+        o.seed = seed
+        o.eps = eps
+        o.alpha = alpha
+        o.L_start = L_start
+        for k in range(_lib.LTS_MAX_LEVELS):
+            o.N_init[k] = N_init[k] if k < len(N_init) else N_init[-1]
+        o.mode = mode
+        o.max_total_samples = max_total_samples
+        r = _lib.MLMCResult()
+        self._c(self.lib.lts_mlmc(self.h, C.byref(o), C.byref(r)))
+        L = r.L
+        return {"estimate": r.estimate, "L": L, "N": list(r.N[:L + 1]), "mean": list(r.mean[:L + 1]),
+                "var": list(r.var[:L + 1]), "cost": list(r.cost[:L + 1]), "bias": r.bias,
+                "rmse": r.rmse, "converged": bool(r.converged), "seconds": r.seconds}
+
+    def set_timing(self, on=True):
+        self._c(self.lib.lts_set_timing(self.h, 1 if on else 0))
+
+    def timing(self) -> dict:
+        t = _lib.Timing()
+        self._c(self.lib.lts_get_timing(self.h, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in _lib.Timing._fields_}

@@ -1,0 +1,139 @@
+"""ctypes declarations of the C ABI in include/lfltsmc.h (marshalling only).
+
+Loads ``liblfltsmc.so`` from this package directory.  There is no fallback:
+if the library is missing or fails to load, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblfltsmc.so")
+
+LTS_OK, LTS_ERR_ARG, LTS_ERR_HIP, LTS_ERR_OOM, LTS_ERR_UNSTABLE, LTS_ERR_STATE = 0, -1, -2, -3, -4, -5
+LTS_FP64, LTS_FP32_STEP = 0, 1
+LTS_PTR_HOST, LTS_PTR_DEVICE = 0, 1
+LTS_NODE_DOF, LTS_NODE_P, LTS_NODE_FPLUS = 1, 2, 4
+LTS_RULE_BOX, LTS_RULE_GRADED_L = 0, 1
+LTS_BATCH_GRAPH = 1
+LTS_MLMC_BATCHED, LTS_MLMC_PLAIN = 0, 1
+LTS_MAX_LEVELS = 8
+
+_ERR_NAMES = {LTS_ERR_ARG: "LTS_ERR_ARG", LTS_ERR_HIP: "LTS_ERR_HIP", LTS_ERR_OOM: "LTS_ERR_OOM",
+              LTS_ERR_UNSTABLE: "LTS_ERR_UNSTABLE", LTS_ERR_STATE: "LTS_ERR_STATE"}
+
+dp = C.POINTER(C.c_double)
+ip = C.POINTER(C.c_int32)
+u8p = C.POINTER(C.c_uint8)
+u64p = C.POINTER(C.c_uint64)
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("nx_cells", C.c_int32), ("ny_cells", C.c_int32), ("x", dp), ("y", dp),
+                ("cell_active", u8p), ("cell_block", ip), ("cell_fine", u8p), ("cell_qoi", u8p),
+                ("n_blocks", C.c_int32), ("h", C.c_double), ("p", C.c_int32), ("nu", C.c_double)]
+
+
+class RectRule(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("lo", C.c_double), ("hi", C.c_double), ("n_base", C.c_int32),
+                ("box_lo", C.c_double), ("box_hi", C.c_double), ("ref", C.c_int32),
+                ("layers", C.c_int32), ("nbx", C.c_int32), ("nby", C.c_int32),
+                ("qx_lo", C.c_double), ("qx_hi", C.c_double), ("qy_lo", C.c_double),
+                ("qy_hi", C.c_double), ("p", C.c_int32), ("nu", C.c_double)]
+
+
+class LevelInfo(C.Structure):
+    _fields_ = [("nx_nodes", C.c_int32), ("ny_nodes", C.c_int32), ("n_dof", C.c_int32),
+                ("n_P", C.c_int32), ("n_Fplus", C.c_int32), ("p", C.c_int32),
+                ("n_blocks", C.c_int32), ("h", C.c_double), ("nu", C.c_double),
+                ("delta", C.c_double), ("omega", C.c_double)]
+
+
+class SampleRule(C.Structure):
+    _fields_ = [("n_blocks", C.c_int32), ("sigma", C.c_double), ("px_lo", C.c_double),
+                ("px_hi", C.c_double), ("py_lo", C.c_double), ("py_hi", C.c_double),
+                ("width", C.c_double), ("T", C.c_double), ("cfl", C.c_double)]
+
+
+class Samples(C.Structure):
+    _fields_ = [("n", C.c_int32), ("ptr_kind", C.c_int32), ("kappa", C.c_void_p), ("x0", C.c_void_p),
+                ("n_steps", C.c_void_p), ("dt", C.c_void_p), ("width", C.c_double)]
+
+
+class Job(C.Structure):
+    _fields_ = [("level", C.c_int32), ("samples", Samples), ("q_offset", C.c_int32)]
+
+
+class MLMCOpts(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("level_ids", C.c_int32 * LTS_MAX_LEVELS),
+                ("rule", SampleRule), ("seed", C.c_uint64), ("eps", C.c_double),
+                ("alpha", C.c_double), ("L_start", C.c_int32),
+                ("N_init", C.c_int32 * LTS_MAX_LEVELS), ("mode", C.c_int32),
+                ("max_total_samples", C.c_int32)]
+
+
+class MLMCResult(C.Structure):
+    _fields_ = [("estimate", C.c_double), ("L", C.c_int32), ("N", C.c_int32 * LTS_MAX_LEVELS),
+                ("mean", C.c_double * LTS_MAX_LEVELS), ("var", C.c_double * LTS_MAX_LEVELS),
+                ("cost", C.c_double * LTS_MAX_LEVELS), ("bias", C.c_double), ("rmse", C.c_double),
+                ("converged", C.c_int32), ("seconds", C.c_double)]
+
+
+class Timing(C.Structure):
+    _fields_ = [("step_kernel_ms", C.c_double), ("step_launches", C.c_int64), ("total_ms", C.c_double),
+                ("dof_updates", C.c_double), ("alg_bytes", C.c_double)]
+
+
+# (name, restype, argtypes) of every exported entry point of include/lfltsmc.h
+SIGNATURES = [
+    ("lts_create", C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p]),
+    ("lts_destroy", C.c_int32, [C.c_void_p]),
+    ("lts_last_error", C.c_char_p, [C.c_void_p]),
+    ("lts_add_level", C.c_int32, [C.c_void_p, C.POINTER(GridDesc), ip]),
+    ("lts_build_rect_level", C.c_int32, [C.c_void_p, C.POINTER(RectRule), ip]),
+    ("lts_level_info_get", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(LevelInfo)]),
+    ("lts_level_arrays", C.c_int32, [C.c_void_p, C.c_int32, dp, dp, u8p, dp, dp, ip]),
+    ("lts_gen_samples", C.c_int32, [C.c_uint64, C.c_int32, C.c_int64, C.c_int32, C.POINTER(SampleRule),
+                                    C.c_double, dp, dp, dp, ip, dp]),
+    ("lts_philox4x64_10", C.c_int32, [u64p, u64p, u64p]),
+    ("lts_rect_level_host", C.c_int32, [C.POINTER(RectRule), C.POINTER(LevelInfo), dp, dp, u8p, dp, dp,
+                                        ip]),
+    ("lts_cheb_constants", C.c_int32, [C.c_int32, C.c_double, C.c_double, dp, dp, dp, dp, dp]),
+    ("lts_forward", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Samples), C.c_int32, C.c_void_p]),
+    ("lts_forward_plain", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Samples), C.c_int32, C.c_void_p]),
+    ("lts_forward_coupled", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Samples),
+                                        C.POINTER(Samples), C.c_int32, C.c_void_p, C.c_void_p,
+                                        C.c_void_p]),
+    ("lts_batch_run", C.c_int32, [C.c_void_p, C.POINTER(Job), C.c_int32, C.c_int32, C.c_void_p]),
+    ("lts_moments", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, dp]),
+    ("lts_backward", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Samples), C.c_void_p, C.c_int32,
+                                 C.c_void_p, C.c_void_p]),
+    ("lts_mlmc", C.c_int32, [C.c_void_p, C.POINTER(MLMCOpts), C.POINTER(MLMCResult)]),
+    ("lts_set_timing", C.c_int32, [C.c_void_p, C.c_int32]),
+    ("lts_get_timing", C.c_int32, [C.c_void_p, C.POINTER(Timing)]),
+]
+
+_lib = None
+
+
+class LtsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def load() -> C.CDLL:
+    """Load the shared library (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2106_11117_amd/build.py "
+                              "(or __graft_entry__.build())")
+        lib = C.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib

@@ -1,0 +1,109 @@
+// Context and device-level structures of the library (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "host.h"
+
+namespace lts {
+
+// Grow-only device buffer owned by a context.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t ensure(size_t n) {
+    if (n <= bytes) return hipSuccess;
+    if (p) {
+      hipError_t e = hipFree(p);
+      p = nullptr;
+      bytes = 0;
+      if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipMalloc(&p, n);
+    if (e == hipSuccess) bytes = n;
+    return e;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+struct DevLevel {
+  HostLevel H;
+  int ld = 0;           // row pitch (elements) of node/cell arrays and states
+  size_t nodes = 0;     // nyn * ld
+  DevBuf hx, hy, inv2hx, inv2hy, x, y, cblk, flags, invm, qoiw, beta, beta_half;
+  // compact lists of DOFs (flat padded index), used by reductions
+  LevelView view() const {
+    LevelView v;
+    v.nxn = H.nxn; v.nyn = H.nyn; v.ld = ld; v.p = H.p; v.nb = H.n_blocks;
+    v.hx = hx.as<double>(); v.hy = hy.as<double>();
+    v.inv2hx = inv2hx.as<double>(); v.inv2hy = inv2hy.as<double>();
+    v.x = x.as<double>(); v.y = y.as<double>();
+    v.cblk = cblk.as<uint8_t>(); v.flags = flags.as<uint8_t>();
+    v.invm = invm.as<double>(); v.qoiw = qoiw.as<double>();
+    v.beta = beta.as<double>(); v.beta_half = beta_half.as<double>();
+    return v;
+  }
+};
+
+struct lts_error {
+  lts_status code;
+  std::string msg;
+};
+
+}  // namespace lts
+
+struct lts_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  std::vector<std::unique_ptr<lts::DevLevel>> levels;
+  // workspace
+  lts::DevBuf kappa, coef, nsteps, x0, Qd, st0, st1, wbuf, qa, qb, red;
+  bool timing = false;
+  lts_timing last{};
+  std::vector<hipEvent_t> ev_pool;
+};
+
+namespace lts {
+
+// Map a HIP error to LTS_ERR_HIP (or LTS_ERR_OOM) with a message.
+inline lts_status hip_fail(lts_ctx c, hipError_t e, const char* where) {
+  c->err = std::string(where) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? LTS_ERR_OOM : LTS_ERR_HIP;
+}
+
+#define LTS_HIP(ctx, call)                                           \
+  do {                                                               \
+    hipError_t e_ = (call);                                          \
+    if (e_ != hipSuccess) return ::lts::hip_fail((ctx), e_, #call); \
+  } while (0)
+
+inline lts_status arg_fail(lts_ctx c, const std::string& m) {
+  c->err = m;
+  return LTS_ERR_ARG;
+}
+
+// Forward solve of `n` samples on level `lv` (device arrays already staged):
+// implemented in the step source.
+struct StepPlan;
+lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_kappa,
+                          const double* d_coef, const int* d_nsteps, const double* d_x0,
+                          double width, const std::vector<int>& h_nsteps, int precision,
+                          bool per_sample, double* d_Q);
+
+lts_status moments_device(lts_ctx c, const double* d_x, int n, double* d_out3);
+
+}  // namespace lts

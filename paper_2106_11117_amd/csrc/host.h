@@ -1,0 +1,60 @@
+// Host-side data structures shared by the C++ host sources and the HIP
+// sources of the library (not part of the public ABI).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "lfltsmc.h"
+
+namespace lts {
+
+// A level on the host: the rectilinear grid, per-cell data, and the derived
+// per-node data of the mass-lumped P1 discretization.
+struct HostLevel {
+  int nxc = 0, nyc = 0, nxn = 0, nyn = 0;
+  std::vector<double> x, y;                 // node coordinates
+  std::vector<uint8_t> active, fine, qoi;   // per cell
+  std::vector<int32_t> block;               // per cell, -1 if inactive
+  std::vector<uint8_t> flags;               // per node, LTS_NODE_* bits
+  std::vector<double> mass, qoiw;           // per node
+  int n_blocks = 0;
+  double h = 0.0;
+  int p = 1;
+  double nu = 0.0;
+  int n_dof = 0, n_P = 0, n_F = 0;
+  // stabilized Chebyshev constants (Sec. 3.3); beta[k], beta_half[k] for k = 1..p-1
+  double delta = 1.0, omega = 2.0;
+  std::vector<double> beta, beta_half;
+};
+
+// Validates `d` and fills `out`; returns an error text ("" on success).
+std::string build_level_from_desc(const lts_grid_desc& d, HostLevel& out);
+
+// Generates the arrays of a rule-described level; returns "" on success.
+std::string build_rect_desc(const lts_rect_rule& r, std::vector<double>& x, std::vector<double>& y,
+                            std::vector<uint8_t>& active, std::vector<int32_t>& block,
+                            std::vector<uint8_t>& fine, std::vector<uint8_t>& qoi, double& h,
+                            int& p, int& n_blocks);
+
+// Stabilized Chebyshev constants for (p, nu).
+void cheb_constants(int p, double nu, double& delta, double& omega, std::vector<double>& beta,
+                    std::vector<double>& beta_half);
+
+// Per-sample substep coefficients for a step dt: out[0] = a_p (the
+// coefficient of w after p substeps on a DOF outside F+), out[1] = c_1 (first
+// substep), out[1+m] = c_2,m for m = 1..p-1.  Length p+1.
+void step_coefficients(const HostLevel& L, double dt, double* out);
+
+// Philox4x64-10 (Salmon et al., SC'11).
+void philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+std::string gen_samples(uint64_t seed, int32_t sample_level, int64_t first_index, int32_t n,
+                        const lts_sample_rule& rule, double h_mesh, double* g, double* kappa,
+                        double* x0, int32_t* n_steps, double* dt);
+
+// Cost model of one solve in DOF updates: ceil(T/(cfl h)) ((N - |P|) + p |P|).
+double solve_cost_model(const HostLevel& L, const lts_sample_rule& rule);
+
+}  // namespace lts

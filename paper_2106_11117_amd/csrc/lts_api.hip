@@ -1,0 +1,424 @@
+// C ABI of the library: contexts, levels, samples, forward solves, moments.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ctx.h"
+
+using namespace lts;
+
+namespace {
+
+constexpr int kPitchAlign = 8;  // row pitch multiple (doubles): 64-byte rows
+
+lts_status upload_level(lts_ctx c, DevLevel& D) {
+  const HostLevel& H = D.H;
+  D.ld = (H.nxn + kPitchAlign - 1) / kPitchAlign * kPitchAlign;
+  D.nodes = (size_t)H.nyn * D.ld;
+  std::vector<double> hx(H.nxn, 0.0), hy(H.nyn, 0.0), ihx(H.nxn, 0.0), ihy(H.nyn, 0.0);
+  for (int i = 0; i + 1 < H.nxn; ++i) {
+    hx[i] = H.x[i + 1] - H.x[i];
+    ihx[i] = 1.0 / (2.0 * hx[i]);
+  }
+  for (int j = 0; j + 1 < H.nyn; ++j) {
+    hy[j] = H.y[j + 1] - H.y[j];
+    ihy[j] = 1.0 / (2.0 * hy[j]);
+  }
+  std::vector<uint8_t> cb(D.nodes, 255), fl(D.nodes, 0);
+  std::vector<double> im(D.nodes, 0.0), qw(D.nodes, 0.0);
+  for (int b = 0; b < H.nyc; ++b)
+    for (int a = 0; a < H.nxc; ++a) {
+      const int32_t blk = H.block[(size_t)b * H.nxc + a];
+      cb[(size_t)b * D.ld + a] = blk < 0 ? 255 : (uint8_t)blk;
+    }
+  for (int j = 0; j < H.nyn; ++j)
+    for (int i = 0; i < H.nxn; ++i) {
+      const size_t k = (size_t)j * H.nxn + i, kd = (size_t)j * D.ld + i;
+      fl[kd] = H.flags[k];
+      if (H.flags[k] & LTS_NODE_DOF) im[kd] = 1.0 / H.mass[k];
+      qw[kd] = H.qoiw[k];
+    }
+  std::vector<double> bt(std::max(1, H.p), 0.0), bh(std::max(1, H.p), 0.0);
+  for (int k = 1; k < H.p; ++k) {
+    bt[k] = H.beta[k];
+    bh[k] = H.beta_half[k];
+  }
+  auto put = [&](DevBuf& b, const void* src, size_t bytes) -> hipError_t {
+    hipError_t e = b.ensure(std::max<size_t>(bytes, 8));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice);
+  };
+  hipError_t e;
+  if ((e = put(D.hx, hx.data(), hx.size() * 8)) != hipSuccess ||
+      (e = put(D.hy, hy.data(), hy.size() * 8)) != hipSuccess ||
+      (e = put(D.inv2hx, ihx.data(), ihx.size() * 8)) != hipSuccess ||
+      (e = put(D.inv2hy, ihy.data(), ihy.size() * 8)) != hipSuccess ||
+      (e = put(D.x, H.x.data(), H.x.size() * 8)) != hipSuccess ||
+      (e = put(D.y, H.y.data(), H.y.size() * 8)) != hipSuccess ||
+      (e = put(D.cblk, cb.data(), cb.size())) != hipSuccess ||
+      (e = put(D.flags, fl.data(), fl.size())) != hipSuccess ||
+      (e = put(D.invm, im.data(), im.size() * 8)) != hipSuccess ||
+      (e = put(D.qoiw, qw.data(), qw.size() * 8)) != hipSuccess ||
+      (e = put(D.beta, bt.data(), bt.size() * 8)) != hipSuccess ||
+      (e = put(D.beta_half, bh.data(), bh.size() * 8)) != hipSuccess)
+    return hip_fail(c, e, "upload level");
+  return LTS_OK;
+}
+
+const DevLevel* get_level(lts_ctx c, int32_t level) {
+  if (!c || level < 0 || level >= (int32_t)c->levels.size()) return nullptr;
+  return c->levels[level].get();
+}
+
+// Host copies of a sample batch (validated) plus the per-sample step tables.
+struct Staged {
+  int n = 0;
+  std::vector<double> kappa, x0, dt, coef;
+  std::vector<int> nsteps;
+};
+
+lts_status stage(lts_ctx c, const DevLevel& lv, const lts_samples* S, Staged& st) {
+  if (!S) return arg_fail(c, "samples is NULL");
+  if (S->n < 0) return arg_fail(c, "samples.n must be >= 0");
+  if (S->ptr_kind != LTS_PTR_HOST && S->ptr_kind != LTS_PTR_DEVICE)
+    return arg_fail(c, "samples.ptr_kind must be LTS_PTR_HOST or LTS_PTR_DEVICE");
+  if (!(S->width > 0.0) || !std::isfinite(S->width)) return arg_fail(c, "samples.width must be > 0");
+  const int n = S->n, nb = lv.H.n_blocks, p = lv.H.p;
+  st.n = n;
+  st.kappa.resize((size_t)n * nb);
+  st.x0.resize((size_t)n * 2);
+  st.dt.resize(n);
+  st.nsteps.resize(n);
+  if (n > 0) {
+    if (!S->kappa || !S->x0 || !S->n_steps || !S->dt) return arg_fail(c, "NULL sample array");
+    const hipMemcpyKind k = S->ptr_kind == LTS_PTR_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+    LTS_HIP(c, hipMemcpy(st.kappa.data(), S->kappa, st.kappa.size() * 8, k));
+    LTS_HIP(c, hipMemcpy(st.x0.data(), S->x0, st.x0.size() * 8, k));
+    LTS_HIP(c, hipMemcpy(st.dt.data(), S->dt, st.dt.size() * 8, k));
+    LTS_HIP(c, hipMemcpy(st.nsteps.data(), S->n_steps, st.nsteps.size() * 4, k));
+  }
+  for (int s = 0; s < n; ++s) {
+    if (!(st.dt[s] > 0.0) || !std::isfinite(st.dt[s])) return arg_fail(c, "dt must be finite and > 0");
+    if (st.nsteps[s] < 1) return arg_fail(c, "n_steps must be >= 1");
+    if (!std::isfinite(st.x0[2 * s]) || !std::isfinite(st.x0[2 * s + 1])) return arg_fail(c, "x0 must be finite");
+    for (int b = 0; b < nb; ++b) {
+      const double k = st.kappa[(size_t)s * nb + b];
+      if (!(k > 0.0) || !std::isfinite(k)) return arg_fail(c, "kappa must be finite and > 0");
+    }
+  }
+  st.coef.resize((size_t)n * (p + 1));
+  for (int s = 0; s < n; ++s) step_coefficients(lv.H, st.dt[s], &st.coef[(size_t)s * (p + 1)]);
+  return LTS_OK;
+}
+
+lts_status upload_staged(lts_ctx c, const Staged& st) {
+  const size_t n = st.n;
+  LTS_HIP(c, c->kappa.ensure(std::max<size_t>(st.kappa.size() * 8, 8)));
+  LTS_HIP(c, c->coef.ensure(std::max<size_t>(st.coef.size() * 8, 8)));
+  LTS_HIP(c, c->nsteps.ensure(std::max<size_t>(n * 4, 4)));
+  LTS_HIP(c, c->x0.ensure(std::max<size_t>(n * 16, 16)));
+  LTS_HIP(c, c->Qd.ensure(std::max<size_t>(n * 8, 8)));
+  if (n == 0) return LTS_OK;
+  LTS_HIP(c, hipMemcpyAsync(c->kappa.p, st.kappa.data(), st.kappa.size() * 8, hipMemcpyHostToDevice, c->stream));
+  LTS_HIP(c, hipMemcpyAsync(c->coef.p, st.coef.data(), st.coef.size() * 8, hipMemcpyHostToDevice, c->stream));
+  LTS_HIP(c, hipMemcpyAsync(c->nsteps.p, st.nsteps.data(), n * 4, hipMemcpyHostToDevice, c->stream));
+  LTS_HIP(c, hipMemcpyAsync(c->x0.p, st.x0.data(), n * 16, hipMemcpyHostToDevice, c->stream));
+  return LTS_OK;
+}
+
+lts_status finish_Q(lts_ctx c, int n, int ptr_kind, double* Q_out) {
+  std::vector<double> q(n);
+  if (n > 0) {
+    LTS_HIP(c, hipMemcpyAsync(q.data(), c->Qd.p, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+    if (ptr_kind == LTS_PTR_DEVICE)
+      LTS_HIP(c, hipMemcpyAsync(Q_out, c->Qd.p, (size_t)n * 8, hipMemcpyDeviceToDevice, c->stream));
+  }
+  LTS_HIP(c, hipStreamSynchronize(c->stream));
+  if (ptr_kind == LTS_PTR_HOST && n > 0) std::memcpy(Q_out, q.data(), (size_t)n * 8);
+  for (int s = 0; s < n; ++s)
+    if (!std::isfinite(q[s])) {
+      c->err = "non-finite QoI (unstable sample)";
+      return LTS_ERR_UNSTABLE;
+    }
+  return LTS_OK;
+}
+
+lts_status forward_impl(lts_ctx c, int32_t level, const lts_samples* S, int32_t precision,
+                        double* Q_out, bool per_sample) {
+  if (!c) return LTS_ERR_ARG;
+  c->err.clear();
+  const DevLevel* lv = get_level(c, level);
+  if (!lv) return arg_fail(c, "no such level");
+  if (precision != LTS_FP64 && precision != LTS_FP32_STEP) return arg_fail(c, "bad precision");
+  if (S && S->n > 0 && !Q_out) return arg_fail(c, "Q_out is NULL");
+  Staged st;
+  lts_status r = stage(c, *lv, S, st);
+  if (r != LTS_OK) return r;
+  LTS_HIP(c, hipSetDevice(c->device));
+  if ((r = upload_staged(c, st)) != LTS_OK) return r;
+  if (st.n > 0) {
+    r = forward_device(c, *lv, st.n, c->kappa.as<double>(), c->coef.as<double>(), c->nsteps.as<int>(),
+                       c->x0.as<double>(), S->width, st.nsteps, precision, per_sample, c->Qd.as<double>());
+    if (r != LTS_OK) return r;
+  }
+  return finish_Q(c, st.n, S->ptr_kind, Q_out);
+}
+
+}  // namespace
+
+extern "C" {
+
+lts_status lts_create(lts_ctx* out, int32_t hip_device, void* hip_stream) {
+  if (!out) return LTS_ERR_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) return LTS_ERR_ARG;
+  lts_ctx c = new (std::nothrow) lts_ctx_s();
+  if (!c) return LTS_ERR_OOM;
+  c->device = hip_device;
+  if (hipSetDevice(hip_device) != hipSuccess) {
+    delete c;
+    return LTS_ERR_HIP;
+  }
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return LTS_ERR_HIP;
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return LTS_OK;
+}
+
+lts_status lts_destroy(lts_ctx c) {
+  if (!c) return LTS_OK;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return LTS_OK;
+}
+
+const char* lts_last_error(lts_ctx c) { return c ? c->err.c_str() : "NULL context"; }
+
+lts_status lts_add_level(lts_ctx c, const lts_grid_desc* d, int32_t* id_out) {
+  if (!c) return LTS_ERR_ARG;
+  c->err.clear();
+  if (!d || !id_out) return arg_fail(c, "NULL argument");
+  auto D = std::make_unique<DevLevel>();
+  std::string e = build_level_from_desc(*d, D->H);
+  if (!e.empty()) return arg_fail(c, e);
+  LTS_HIP(c, hipSetDevice(c->device));
+  lts_status r = upload_level(c, *D);
+  if (r != LTS_OK) return r;
+  *id_out = (int32_t)c->levels.size();
+  c->levels.push_back(std::move(D));
+  return LTS_OK;
+}
+
+lts_status lts_build_rect_level(lts_ctx c, const lts_rect_rule* r, int32_t* id_out) {
+  if (!c) return LTS_ERR_ARG;
+  c->err.clear();
+  if (!r || !id_out) return arg_fail(c, "NULL argument");
+  std::vector<double> x, y;
+  std::vector<uint8_t> act, fine, qoi;
+  std::vector<int32_t> blk;
+  double h = 0;
+  int p = 0, nb = 0;
+  std::string e = build_rect_desc(*r, x, y, act, blk, fine, qoi, h, p, nb);
+  if (!e.empty()) return arg_fail(c, e);
+  lts_grid_desc d{};
+  d.nx_cells = (int32_t)x.size() - 1;
+  d.ny_cells = (int32_t)y.size() - 1;
+  d.x = x.data();
+  d.y = y.data();
+  d.cell_active = act.data();
+  d.cell_block = blk.data();
+  d.cell_fine = fine.data();
+  d.cell_qoi = qoi.data();
+  d.n_blocks = nb;
+  d.h = h;
+  d.p = p;
+  d.nu = r->nu;
+  return lts_add_level(c, &d, id_out);
+}
+
+lts_status lts_level_info_get(lts_ctx c, int32_t level, lts_level_info* out) {
+  if (!c) return LTS_ERR_ARG;
+  const DevLevel* lv = get_level(c, level);
+  if (!lv || !out) return arg_fail(c, "no such level / NULL out");
+  const HostLevel& H = lv->H;
+  out->nx_nodes = H.nxn;
+  out->ny_nodes = H.nyn;
+  out->n_dof = H.n_dof;
+  out->n_P = H.n_P;
+  out->n_Fplus = H.n_F;
+  out->p = H.p;
+  out->n_blocks = H.n_blocks;
+  out->h = H.h;
+  out->nu = H.nu;
+  out->delta = H.delta;
+  out->omega = H.omega;
+  return LTS_OK;
+}
+
+lts_status lts_level_arrays(lts_ctx c, int32_t level, double* x, double* y, uint8_t* flags,
+                            double* mass, double* qoi_w, int32_t* cell_block) {
+  if (!c) return LTS_ERR_ARG;
+  const DevLevel* lv = get_level(c, level);
+  if (!lv) return arg_fail(c, "no such level");
+  const HostLevel& H = lv->H;
+  if (x) std::memcpy(x, H.x.data(), H.x.size() * 8);
+  if (y) std::memcpy(y, H.y.data(), H.y.size() * 8);
+  if (flags) std::memcpy(flags, H.flags.data(), H.flags.size());
+  if (mass) std::memcpy(mass, H.mass.data(), H.mass.size() * 8);
+  if (qoi_w) std::memcpy(qoi_w, H.qoiw.data(), H.qoiw.size() * 8);
+  if (cell_block) std::memcpy(cell_block, H.block.data(), H.block.size() * 4);
+  return LTS_OK;
+}
+
+lts_status lts_rect_level_host(const lts_rect_rule* r, lts_level_info* info, double* x, double* y,
+                               uint8_t* flags, double* mass, double* qoi_w, int32_t* cell_block) {
+  if (!r || !info) return LTS_ERR_ARG;
+  std::vector<double> xs, ys;
+  std::vector<uint8_t> act, fine, qoi;
+  std::vector<int32_t> blk;
+  double h = 0;
+  int p = 0, nb = 0;
+  if (!build_rect_desc(*r, xs, ys, act, blk, fine, qoi, h, p, nb).empty()) return LTS_ERR_ARG;
+  lts_grid_desc d{};
+  d.nx_cells = (int32_t)xs.size() - 1;
+  d.ny_cells = (int32_t)ys.size() - 1;
+  d.x = xs.data(); d.y = ys.data();
+  d.cell_active = act.data(); d.cell_block = blk.data(); d.cell_fine = fine.data(); d.cell_qoi = qoi.data();
+  d.n_blocks = nb; d.h = h; d.p = p; d.nu = r->nu;
+  HostLevel H;
+  if (!build_level_from_desc(d, H).empty()) return LTS_ERR_ARG;
+  info->nx_nodes = H.nxn; info->ny_nodes = H.nyn; info->n_dof = H.n_dof; info->n_P = H.n_P;
+  info->n_Fplus = H.n_F; info->p = H.p; info->n_blocks = H.n_blocks; info->h = H.h; info->nu = H.nu;
+  info->delta = H.delta; info->omega = H.omega;
+  if (x) std::memcpy(x, H.x.data(), H.x.size() * 8);
+  if (y) std::memcpy(y, H.y.data(), H.y.size() * 8);
+  if (flags) std::memcpy(flags, H.flags.data(), H.flags.size());
+  if (mass) std::memcpy(mass, H.mass.data(), H.mass.size() * 8);
+  if (qoi_w) std::memcpy(qoi_w, H.qoiw.data(), H.qoiw.size() * 8);
+  if (cell_block) std::memcpy(cell_block, H.block.data(), H.block.size() * 4);
+  return LTS_OK;
+}
+
+lts_status lts_cheb_constants(int32_t p, double nu, double dt, double* delta, double* omega,
+                              double* beta, double* beta_half, double* coef) {
+  if (p < 1 || p > 256 || !(nu >= 0.0 && nu <= 1.0)) return LTS_ERR_ARG;
+  HostLevel H;
+  H.p = p;
+  H.nu = nu;
+  cheb_constants(p, nu, H.delta, H.omega, H.beta, H.beta_half);
+  if (delta) *delta = H.delta;
+  if (omega) *omega = H.omega;
+  for (int k = 0; k < p; ++k) {
+    if (beta) beta[k] = H.beta[k];
+    if (beta_half) beta_half[k] = H.beta_half[k];
+  }
+  if (coef) step_coefficients(H, dt, coef);
+  return LTS_OK;
+}
+
+lts_status lts_gen_samples(uint64_t seed, int32_t sample_level, int64_t first_index, int32_t n,
+                           const lts_sample_rule* rule, double h_mesh, double* g, double* kappa,
+                           double* x0, int32_t* n_steps, double* dt) {
+  if (!rule) return LTS_ERR_ARG;
+  std::string e = gen_samples(seed, sample_level, first_index, n, *rule, h_mesh, g, kappa, x0, n_steps, dt);
+  return e.empty() ? LTS_OK : LTS_ERR_ARG;
+}
+
+lts_status lts_philox4x64_10(const uint64_t* ctr, const uint64_t* key, uint64_t* out) {
+  if (!ctr || !key || !out) return LTS_ERR_ARG;
+  philox4x64_10(ctr, key, out);
+  return LTS_OK;
+}
+
+lts_status lts_forward(lts_ctx c, int32_t level, const lts_samples* S, int32_t precision, double* Q) {
+  return forward_impl(c, level, S, precision, Q, false);
+}
+
+lts_status lts_forward_plain(lts_ctx c, int32_t level, const lts_samples* S, int32_t precision, double* Q) {
+  return forward_impl(c, level, S, precision, Q, true);
+}
+
+lts_status lts_forward_coupled(lts_ctx c, int32_t lf, int32_t lc, const lts_samples* F,
+                               const lts_samples* C, int32_t precision, double* Qf, double* Qc,
+                               double* dQ) {
+  if (!c) return LTS_ERR_ARG;
+  c->err.clear();
+  if (!F || !C) return arg_fail(c, "NULL samples");
+  if (F->n != C->n || F->ptr_kind != C->ptr_kind) return arg_fail(c, "fine and coarse batches differ in n/ptr_kind");
+  const int n = F->n;
+  const bool dev = F->ptr_kind == LTS_PTR_DEVICE;
+  std::vector<double> hf(n), hc(n);
+  double *tf = nullptr, *tc = nullptr;
+  lts_status r;
+  if (dev) {
+    LTS_HIP(c, c->red.ensure(std::max<size_t>(16 * (size_t)n, 16)));
+    tf = c->red.as<double>();
+    tc = tf + n;
+  } else {
+    tf = hf.data();
+    tc = hc.data();
+  }
+  if ((r = lts_forward(c, lf, F, precision, tf)) != LTS_OK) return r;
+  if ((r = lts_forward(c, lc, C, precision, tc)) != LTS_OK) return r;
+  if (dev) {
+    LTS_HIP(c, hipMemcpy(hf.data(), tf, (size_t)n * 8, hipMemcpyDeviceToHost));
+    LTS_HIP(c, hipMemcpy(hc.data(), tc, (size_t)n * 8, hipMemcpyDeviceToHost));
+  }
+  std::vector<double> d(n);
+  for (int s = 0; s < n; ++s) d[s] = hf[s] - hc[s];
+  const hipMemcpyKind k = dev ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
+  if (n > 0) {
+    if (Qf) LTS_HIP(c, hipMemcpy(Qf, hf.data(), (size_t)n * 8, k));
+    if (Qc) LTS_HIP(c, hipMemcpy(Qc, hc.data(), (size_t)n * 8, k));
+    if (dQ) LTS_HIP(c, hipMemcpy(dQ, d.data(), (size_t)n * 8, k));
+  }
+  return LTS_OK;
+}
+
+lts_status lts_moments(lts_ctx c, const double* x, int32_t n, int32_t ptr_kind, double* out) {
+  if (!c) return LTS_ERR_ARG;
+  c->err.clear();
+  if (!out || (n > 0 && !x) || n < 0) return arg_fail(c, "bad moments arguments");
+  if (ptr_kind != LTS_PTR_HOST && ptr_kind != LTS_PTR_DEVICE) return arg_fail(c, "bad ptr_kind");
+  LTS_HIP(c, hipSetDevice(c->device));
+  LTS_HIP(c, c->red.ensure(std::max<size_t>((size_t)n * 8 + 64, 64)));
+  double* dx = c->red.as<double>() + 8;
+  if (n > 0)
+    LTS_HIP(c, hipMemcpyAsync(dx, x, (size_t)n * 8,
+                              ptr_kind == LTS_PTR_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                              c->stream));
+  lts_status r = moments_device(c, dx, n, c->red.as<double>());
+  if (r != LTS_OK) return r;
+  LTS_HIP(c, hipMemcpyAsync(out, c->red.p, 24, hipMemcpyDeviceToHost, c->stream));
+  LTS_HIP(c, hipStreamSynchronize(c->stream));
+  return LTS_OK;
+}
+
+lts_status lts_set_timing(lts_ctx c, int32_t enable) {
+  if (!c) return LTS_ERR_ARG;
+  c->timing = enable != 0;
+  return LTS_OK;
+}
+
+lts_status lts_get_timing(lts_ctx c, lts_timing* out) {
+  if (!c || !out) return LTS_ERR_ARG;
+  *out = c->last;
+  return LTS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,315 @@
+// Stabilized LF-LTS time stepping on the device (Algorithm 2, u-form).
+//
+// In the variables u = M^-1/2 z the scheme reads, with A_u = M^-1 K:
+//   w       = A_u (I - P) u_n
+//   q_1/p   = u_n - c1 (w + A_u P u_n)
+//   q_m+1/p = (1 + beta_m) q_m/p - beta_m q_m-1/p - c2_m (w + A_u P q_m/p)
+//   u_n+1   = -u_n-1 + 2 q_1          (start-up: u_1 = q_1)
+// with c1 = 1/2 (dt/p)^2 2p^2/(omega delta), c2_m = (dt/p)^2 2p^2/omega beta_m+1/2.
+// A_u P q vanishes outside F+ (P and its neighbours), where q_m = u_n + a_m w
+// and the whole step is u_n+1 = -u_n-1 + 2 (u_n + a_p w): that part is a
+// single stencil sweep.  Only F+ runs the p substeps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "ctx.h"
+
+namespace lts {
+
+namespace {
+
+constexpr int TBX = 64, TBY = 4;
+
+// ---------------------------------------------------------------------------
+// Initial state: u_0 = exp(-|x - x0|^2 / width^2) on DOFs, 0 elsewhere.
+__global__ __launch_bounds__(256) void k_init(LevelView L, const double* __restrict__ x0, double width,
+                                              double* __restrict__ U, double* __restrict__ U1,
+                                              size_t sstride) {
+  const int s = blockIdx.z;
+  const int i = blockIdx.x * TBX + threadIdx.x, j = blockIdx.y * TBY + threadIdx.y;
+  if (i >= L.ld || j >= L.nyn) return;
+  const size_t k = (size_t)j * L.ld + i;
+  double v = 0.0;
+  if (i < L.nxn && (L.flags[k] & F_DOF)) {
+    const double dx = L.x[i] - x0[2 * s], dy = L.y[j] - x0[2 * s + 1];
+    v = exp(-(dx * dx + dy * dy) / (width * width));
+  }
+  U[s * sstride + k] = v;
+  U1[s * sstride + k] = 0.0;   // the other time level: boundary nodes must read 0
+}
+
+// ---------------------------------------------------------------------------
+// Coarse sweep: w = A_u (I-P) u_n at every DOF; outside F+ it completes the
+// step, inside F+ it stores w for the substeps.
+__global__ __launch_bounds__(256) void k_coarse(LevelView L, const double* __restrict__ kappa,
+                                                const double* __restrict__ coef,
+                                                const int* __restrict__ nsteps, int n, int s0,
+                                                int startup, const double* __restrict__ Ucur,
+                                                double* __restrict__ Uold, double* __restrict__ W,
+                                                size_t sstride) {
+  const int s = s0 + blockIdx.z;
+  if (n >= nsteps[s]) return;
+  const int i = blockIdx.x * TBX + threadIdx.x, j = blockIdx.y * TBY + threadIdx.y;
+  if (i >= L.nxn || j >= L.nyn) return;
+  const size_t k = (size_t)j * L.ld + i;
+  const uint8_t f = L.flags[k];
+  if (!(f & F_DOF)) return;
+  const double* __restrict__ u = Ucur + s * sstride;
+  double cE, cW, cN, cS;
+  edge_coefs(L, kappa + (size_t)s * L.nb, i, j, cE, cW, cN, cS);
+  auto v = [&](size_t kk) { return (L.flags[kk] & F_P) ? 0.0 : u[kk]; };
+  const double vi = v(k);
+  const double w = L.invm[k] * (cE * (vi - v(k + 1)) + cW * (vi - v(k - 1)) +
+                                cN * (vi - v(k + L.ld)) + cS * (vi - v(k - L.ld)));
+  if (!(f & F_FPLUS)) {
+    const double ap = coef[(size_t)s * (L.p + 1)];
+    const double q = u[k] + ap * w;
+    double* __restrict__ o = Uold + s * sstride;
+    o[k] = startup ? q : (-o[k] + 2.0 * q);
+  } else {
+    W[s * sstride + k] = w;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One substep m (0-based: m = 0 makes q_1/p) on the DOFs of F+.  The last
+// substep writes u_n+1 into Uold directly.
+__global__ __launch_bounds__(256) void k_sub(LevelView L, const double* __restrict__ kappa,
+                                             const double* __restrict__ coef,
+                                             const int* __restrict__ nsteps, int n, int s0, int startup,
+                                             int m, const double* __restrict__ Qc,
+                                             const double* __restrict__ Qp, const double* __restrict__ W,
+                                             double* __restrict__ Qn, double* __restrict__ Uold,
+                                             size_t sstride) {
+  const int s = s0 + blockIdx.z;
+  if (n >= nsteps[s]) return;
+  const int i = blockIdx.x * TBX + threadIdx.x, j = blockIdx.y * TBY + threadIdx.y;
+  if (i >= L.nxn || j >= L.nyn) return;
+  const size_t k = (size_t)j * L.ld + i;
+  const uint8_t f = L.flags[k];
+  if (!(f & F_FPLUS)) return;
+  const size_t so = s * sstride;
+  const double* __restrict__ q = Qc + so;
+  double cE, cW, cN, cS;
+  edge_coefs(L, kappa + (size_t)s * L.nb, i, j, cE, cW, cN, cS);
+  auto pq = [&](size_t kk) { return (L.flags[kk] & F_P) ? q[kk] : 0.0; };
+  const double pi = pq(k);
+  const double apq = L.invm[k] * (cE * (pi - pq(k + 1)) + cW * (pi - pq(k - 1)) +
+                                  cN * (pi - pq(k + L.ld)) + cS * (pi - pq(k - L.ld)));
+  const double* cf = coef + (size_t)s * (L.p + 1);
+  const double r = W[so + k] + apq;
+  double qn;
+  if (m == 0) {
+    qn = q[k] - cf[1] * r;
+  } else {
+    const double b = L.beta[m];
+    qn = (1.0 + b) * q[k] - b * Qp[so + k] - cf[1 + m] * r;
+  }
+  if (m == L.p - 1) {
+    double* __restrict__ o = Uold + so;
+    o[k] = startup ? qn : (-o[k] + 2.0 * qn);
+  } else {
+    Qn[so + k] = qn;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Q[s] = sum_k qoiw[k] u_k, one workgroup per sample, fixed summation order.
+__global__ __launch_bounds__(256) void k_qoi(LevelView L, const int* __restrict__ nsteps,
+                                             const double* __restrict__ B0, const double* __restrict__ B1,
+                                             size_t sstride, size_t nodes, double* __restrict__ Q) {
+  const int s = blockIdx.x;
+  const double* __restrict__ u = ((nsteps[s] & 1) ? B1 : B0) + s * sstride;
+  double acc = 0.0;
+  for (size_t k = threadIdx.x; k < nodes; k += blockDim.x) {
+    const double w = L.qoiw[k];
+    if (w != 0.0) acc += w * u[k];
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) Q[s] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// (n, mean, M2) of x[0..n-1]: per-lane Welford, then pairwise Chan merges
+// (wavefront shuffles, then across the workgroup's wavefronts).
+struct Mom {
+  double n, mean, m2;
+};
+
+__device__ __forceinline__ Mom chan_merge(Mom a, Mom b) {
+  if (b.n == 0.0) return a;
+  if (a.n == 0.0) return b;
+  const double nn = a.n + b.n;
+  const double d = b.mean - a.mean;
+  Mom r;
+  r.n = nn;
+  r.mean = a.mean + d * (b.n / nn);
+  r.m2 = a.m2 + b.m2 + d * d * (a.n * b.n / nn);
+  return r;
+}
+
+__global__ __launch_bounds__(1024) void k_moments(const double* __restrict__ x, int n,
+                                                  double* __restrict__ out) {
+  Mom m{0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const double v = x[k];
+    m.n += 1.0;
+    const double d = v - m.mean;
+    m.mean += d / m.n;
+    m.m2 += d * (v - m.mean);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    Mom t;
+    t.n = __shfl_down(m.n, o, 64);
+    t.mean = __shfl_down(m.mean, o, 64);
+    t.m2 = __shfl_down(m.m2, o, 64);
+    m = chan_merge(m, t);
+  }
+  __shared__ Mom part[16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) part[wid] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Mom r = part[0];
+    const int nw = (blockDim.x + 63) / 64;
+    for (int w = 1; w < nw; ++w) r = chan_merge(r, part[w]);
+    out[0] = r.n;
+    out[1] = r.mean;
+    out[2] = r.m2;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_kappa,
+                          const double* d_coef, const int* d_nsteps, const double* d_x0, double width,
+                          const std::vector<int>& h_nsteps, int precision, bool per_sample,
+                          double* d_Q) {
+  if (precision != LTS_FP64) {
+    c->err = "FP32 stepping is not available in this build";
+    return LTS_ERR_ARG;
+  }
+  const LevelView L = lv.view();
+  const size_t sstride = lv.nodes;
+  const size_t bytes = (size_t)n * sstride * sizeof(double);
+  LTS_HIP(c, c->st0.ensure(bytes));
+  LTS_HIP(c, c->st1.ensure(bytes));
+  LTS_HIP(c, c->wbuf.ensure(bytes));
+  LTS_HIP(c, c->qa.ensure(bytes));
+  LTS_HIP(c, c->qb.ensure(bytes));
+  double* B[2] = {c->st0.as<double>(), c->st1.as<double>()};
+  double* Wb = c->wbuf.as<double>();
+  double* QA = c->qa.as<double>();
+  double* QB = c->qb.as<double>();
+  const int maxn = *std::max_element(h_nsteps.begin(), h_nsteps.end());
+  const dim3 blk(TBX, TBY);
+  const int gx = (L.ld + TBX - 1) / TBX, gy = (L.nyn + TBY - 1) / TBY;
+
+  hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+  if (c->timing) {
+    while (c->ev_pool.size() < 4) {
+      hipEvent_t e;
+      LTS_HIP(c, hipEventCreate(&e));
+      c->ev_pool.push_back(e);
+    }
+    e0 = c->ev_pool[0]; e1 = c->ev_pool[1]; e2 = c->ev_pool[2]; e3 = c->ev_pool[3];
+    LTS_HIP(c, hipEventRecord(e0, c->stream));
+  }
+  constexpr int kMaxZ = 32768;
+  for (int z0 = 0; z0 < n; z0 += kMaxZ) {
+    const int nz = std::min(kMaxZ, n - z0);
+    k_init<<<dim3(gx, gy, nz), blk, 0, c->stream>>>(L, d_x0 + 2 * z0, width, B[0] + z0 * sstride,
+                                                     B[1] + z0 * sstride, sstride);
+  }
+  if (c->timing) LTS_HIP(c, hipEventRecord(e1, c->stream));
+  int64_t launches = 0;
+  auto one_step = [&](int step, int s0, int nz) {
+    const double* Ucur = B[step & 1];
+    double* Uold = B[(step + 1) & 1];
+    const int st = step == 0;
+    k_coarse<<<dim3(gx, gy, nz), blk, 0, c->stream>>>(L, d_kappa, d_coef, d_nsteps, step, s0, st, Ucur, Uold,
+                                                      Wb, sstride);
+    const double* qprev = nullptr;
+    const double* qcur = Ucur;
+    double* bufs[2] = {QA, QB};
+    for (int m = 0; m < L.p; ++m) {
+      double* qnext = bufs[m & 1];
+      k_sub<<<dim3(gx, gy, nz), blk, 0, c->stream>>>(L, d_kappa, d_coef, d_nsteps, step, s0, st, m, qcur,
+                                                     qprev, Wb, qnext, Uold, sstride);
+      qprev = qcur;
+      qcur = qnext;
+    }
+    launches += 1 + L.p;
+  };
+  if (per_sample) {
+    for (int s = 0; s < n; ++s)
+      for (int step = 0; step < h_nsteps[s]; ++step) one_step(step, s, 1);
+  } else {
+    for (int step = 0; step < maxn; ++step)
+      for (int z0 = 0; z0 < n; z0 += kMaxZ) one_step(step, z0, std::min(kMaxZ, n - z0));
+  }
+  LTS_HIP(c, hipGetLastError());
+  if (c->timing) LTS_HIP(c, hipEventRecord(e2, c->stream));
+  k_qoi<<<n, 256, 0, c->stream>>>(L, d_nsteps, B[0], B[1], sstride, lv.nodes, d_Q);
+  LTS_HIP(c, hipGetLastError());
+  double dofu = 0.0, algb = 0.0;
+  const double per_step = (double)(lv.H.n_dof - lv.H.n_P) + (double)lv.H.p * lv.H.n_P;
+  for (int s = 0; s < n; ++s) {
+    dofu += (double)h_nsteps[s] * per_step;
+    algb += (double)h_nsteps[s] * 24.0 * lv.H.n_dof;
+  }
+  c->last = lts_timing{};
+  c->last.dof_updates = dofu;
+  c->last.alg_bytes = algb;
+  c->last.step_launches = launches;
+  if (c->timing) {
+    LTS_HIP(c, hipEventRecord(e3, c->stream));
+    LTS_HIP(c, hipEventSynchronize(e3));
+    float a = 0, b = 0;
+    LTS_HIP(c, hipEventElapsedTime(&a, e1, e2));
+    LTS_HIP(c, hipEventElapsedTime(&b, e0, e3));
+    c->last.step_kernel_ms = a;
+    c->last.total_ms = b;
+  }
+  return LTS_OK;
+}
+
+lts_status moments_device(lts_ctx c, const double* d_x, int n, double* d_out3) {
+  k_moments<<<1, 1024, 0, c->stream>>>(d_x, n, d_out3);
+  LTS_HIP(c, hipGetLastError());
+  return LTS_OK;
+}
+
+}  // namespace lts
+
+extern "C" {
+
+lts_status lts_batch_run(lts_ctx c, const lts_job*, int32_t, int32_t, double*) {
+  if (!c) return LTS_ERR_ARG;
+  c->err = "lts_batch_run: not available in this build";
+  return LTS_ERR_STATE;
+}
+
+lts_status lts_backward(lts_ctx c, int32_t, const lts_samples*, const double*, int32_t, double*, double*) {
+  if (!c) return LTS_ERR_ARG;
+  c->err = "lts_backward: not available in this build";
+  return LTS_ERR_STATE;
+}
+
+lts_status lts_mlmc(lts_ctx c, const lts_mlmc_opts*, lts_mlmc_result*) {
+  if (!c) return LTS_ERR_ARG;
+  c->err = "lts_mlmc: not available in this build";
+  return LTS_ERR_STATE;
+}
+
+}  // extern "C"
