@@ -14,7 +14,9 @@ cells of block b with unit coefficient).  Each <mu, d_b(R y)> is obtained by a
 reverse sweep over the p substeps.  dQ/dg_b = 2 kappa_b dQ/dkappa_b since
 kappa = exp(2 g).  dt and the step count are held fixed (they are functions of
 max_b c_b, which is not smooth).  States are checkpointed every K steps and
-recomputed segment by segment.
+recomputed segment by segment.  As in the forward solver, R y is evaluated as
+y + d_p(y) on the increments of Algorithm 2, and the recurrences as
+z_{n+1} = 2 z_n - z_{n-1} + 2 d_p(z_n), mu_n = 2 mu_{n+1} - mu_{n+2} + 2 d_p(mu_{n+1}).
 """
 from __future__ import annotations
 
@@ -36,15 +38,15 @@ def vjp_R_kappa(s: Solver, y, lam, dt):
     ops = s.ops
     D = 1.0 / s.sqm
     c1 = 0.5 * (dt / p) * (dt / p) * (2.0 * p * p / (cc.omega * cc.delta))
-    # forward substeps (kept)
-    q = [y]
+    # forward substeps on the increments (kept): q_m = y + d_m
     w = A @ ((1.0 - Pd) * y)
-    q.append(y - c1 * (w + A @ (Pd * y)))
+    d = [np.zeros_like(y), -c1 * (w + A @ (Pd * y))]
     c2 = [None]
     for m in range(1, p):
         c2m = (dt / p) * (dt / p) * (2.0 * p * p / cc.omega) * cc.beta_half[m]
         c2.append(c2m)
-        q.append((1.0 + cc.beta[m]) * q[m] - cc.beta[m] * q[m - 1] - c2m * (w + A @ (Pd * q[m])))
+        d.append((1.0 + cc.beta[m]) * d[m] - cc.beta[m] * d[m - 1] - c2m * (w + A @ (Pd * (y + d[m]))))
+    q = [y + dm for dm in d]
     # reverse
     lq = [np.zeros_like(y) for _ in range(p + 1)]
     lq[p] = lam.copy()
@@ -74,7 +76,7 @@ def gradient(ops, kappa_blocks, u0, dt, n_steps, K: int = 64):
     pairs = {0: (z0, z1)}
     zm, zc = z0, z1
     for n in range(1, N):
-        zm, zc = zc, -zm + 2.0 * s.q1(zc, dt)      # (z_n, z_{n+1})
+        zm, zc = zc, 2.0 * zc - zm + 2.0 * s.d1(zc, dt)      # (z_n, z_{n+1})
         if n % K == 0:
             pairs[n] = (zm, zc)
     w_hat = ops.qoi_w / s.sqm
@@ -87,12 +89,12 @@ def gradient(ops, kappa_blocks, u0, dt, n_steps, K: int = 64):
         k1 = min(k0 + K - 1, N - 1)
         seg = list(pairs[k0])
         while len(seg) < k1 - k0 + 1:
-            seg.append(-seg[-2] + 2.0 * s.q1(seg[-1], dt))
+            seg.append(2.0 * seg[-1] - seg[-2] + 2.0 * s.d1(seg[-1], dt))
         for n in range(k1, k0 - 1, -1):
             zn = seg[n - k0]
             if n >= 1:
                 grad_k += 2.0 * vjp_R_kappa(s, zn, mu_np1, dt)
-                mu_n = 2.0 * s.q1(mu_np1, dt) - mu_np2
+                mu_n = 2.0 * mu_np1 - mu_np2 + 2.0 * s.d1(mu_np1, dt)
                 mu_np2, mu_np1 = mu_np1, mu_n
             else:
                 grad_k += vjp_R_kappa(s, zn, mu_np1, dt)
@@ -109,6 +111,6 @@ def q_complex_step(ops, g_blocks, b: int, u0, dt, n_steps, hstep: float = 1e-30)
     z0 = (s.sqm * u0).astype(np.complex128)
     zm, zc = z0, s.q1(z0, dt)
     for _ in range(1, n_steps):
-        zm, zc = zc, -zm + 2.0 * s.q1(zc, dt)
+        zm, zc = zc, 2.0 * zc - zm + 2.0 * s.d1(zc, dt)
     Q = (ops.qoi_w / s.sqm) @ zc
     return float(np.imag(Q) / hstep)

@@ -15,6 +15,23 @@ loop index m.  Start-up (the paper gives none for LTS): z_1 = q_1(z_0) +
 dt M^1/2 v_0, the LTS analogue of the leapfrog start-up of Sec. 3.1 (for
 P = 0 the two coincide).  The sign of the v_0 term follows the Taylor
 expansion (+).
+
+Evaluation (a reading of how to carry out the printed recurrence in binary64):
+the solver runs the same recurrence on the increments d_m = q_{m/p} - z_n,
+
+  d_0 = 0,  d_1 = -c1 (w_n + A P z_n),
+  d_{m+1} = (1 + beta_m) d_m - beta_m d_{m-1} - c2_m (w_n + A P (z_n + d_m)),
+  z_{n+1} = 2 z_n - z_{n-1} + 2 d_p,
+
+which is the printed algorithm term by term (subtract z_n from every q and use
+(1 + beta_m) - beta_m = 1).  In binary64 the printed form multiplies the full
+state by the rounded (1 + beta_m) and beta_m, whose difference is 1 only up to
+an ulp; that systematic O(1e-16) error on z is large next to the dt^2 A z
+increment of smooth modes on fine meshes and drifts their phase (~1e-11 after
+a few hundred steps, growing with the step count).  The increment form keeps
+every coefficient of z exact.  ``lts_q1`` keeps the printed form; the tests
+pin the increment form against the printed form evaluated in extended
+precision.
 """
 from __future__ import annotations
 
@@ -38,9 +55,28 @@ def lts_q1(A, Pd, z, dt, cc: ChebConsts):
     return q
 
 
+def lts_d1(A, Pd, z, dt, cc: ChebConsts):
+    """Increment d_p = q_1^n - z of Algorithm 2 for q_0 = z (see module header)."""
+    p = cc.p
+    w = A @ ((1.0 - Pd) * z)
+    c1 = 0.5 * (dt / p) * (dt / p) * (2.0 * p * p / (cc.omega * cc.delta))
+    d_prev = np.zeros_like(z)
+    d = -c1 * (w + A @ (Pd * z))
+    for m in range(1, p):
+        c2 = (dt / p) * (dt / p) * (2.0 * p * p / cc.omega) * cc.beta_half[m]
+        d_next = (1.0 + cc.beta[m]) * d - cc.beta[m] * d_prev - c2 * (w + A @ (Pd * (z + d)))
+        d_prev, d = d, d_next
+    return d
+
+
 def lts_step(A, Pd, z_n, z_nm1, dt, cc):
-    """One stabilized LF-LTS step: z_{n+1} = -z_{n-1} + 2 q_1^n."""
+    """One stabilized LF-LTS step, printed form: z_{n+1} = -z_{n-1} + 2 q_1^n."""
     return -z_nm1 + 2.0 * lts_q1(A, Pd, z_n, dt, cc)
+
+
+def lts_step_inc(A, Pd, z_n, z_nm1, dt, cc):
+    """The same step on increments: z_{n+1} = 2 z_n - z_{n-1} + 2 d_p."""
+    return 2.0 * z_n - z_nm1 + 2.0 * lts_d1(A, Pd, z_n, dt, cc)
 
 
 def lf_step(A, z_n, z_nm1, dt):
@@ -71,19 +107,30 @@ class Solver:
         self.Pd = ops.Pd if Pd is None else Pd
         self.sqm = np.sqrt(ops.m)
 
-    def q1(self, z, dt):
-        return lts_q1(self.A, self.Pd, z, dt, self.cc)
+    def d1(self, z, dt):
+        return lts_d1(self.A, self.Pd, z, dt, self.cc)
 
-    def run(self, u0, dt, n_steps, v0=None, keep=False):
-        """Return u(T) = M^-1/2 z_{n_steps} (and all z_n when ``keep``)."""
+    def q1(self, z, dt):
+        """R z = q_1(z) = z + d_p(z)."""
+        return z + self.d1(z, dt)
+
+    def run(self, u0, dt, n_steps, v0=None, keep=False, form="increment"):
+        """Return u(T) = M^-1/2 z_{n_steps} (and all z_n when ``keep``).
+        form = "increment" (default) or "printed" (the q-recurrence as printed)."""
         z0 = self.sqm * u0
-        z1 = self.q1(z0, dt)
+        if form == "increment":
+            z1 = z0 + self.d1(z0, dt)
+        else:
+            z1 = lts_q1(self.A, self.Pd, z0, dt, self.cc)
         if v0 is not None:
             z1 = z1 + dt * self.sqm * v0
         zs = [z0, z1] if keep else None
         zm, zc = z0, z1
         for _ in range(1, n_steps):
-            zn = lts_step(self.A, self.Pd, zc, zm, dt, self.cc)
+            if form == "increment":
+                zn = lts_step_inc(self.A, self.Pd, zc, zm, dt, self.cc)
+            else:
+                zn = lts_step(self.A, self.Pd, zc, zm, dt, self.cc)
             zm, zc = zc, zn
             if keep:
                 zs.append(zc)
@@ -105,7 +152,7 @@ class Solver:
         """E_{n+1/2} = 1/2 |z_{n+1} - z_n|^2 / dt^2 + 1/2 z_{n+1}^T A_p z_n with the
         effective LTS operator A_p y = 2 (y - q_1(y)) / dt^2 (symmetric)."""
         d = z_np1 - z_n
-        Apz = 2.0 * (z_n - self.q1(z_n, dt)) / (dt * dt)
+        Apz = -2.0 * self.d1(z_n, dt) / (dt * dt)
         return 0.5 * float(d @ d) / (dt * dt) + 0.5 * float(z_np1 @ Apz)
 
 

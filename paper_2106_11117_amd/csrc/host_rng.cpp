@@ -125,16 +125,18 @@ void step_coefficients(const HostLevel& L, double dt, double* out) {
   const int p = L.p;
   const double c1 = 0.5 * (dt / p) * (dt / p) * (2.0 * p * p / (L.omega * L.delta));
   out[1] = c1;
-  // a_m: q_m = u + a_m w on a DOF that neither is in P nor touches P
-  double a_prev = 0.0, a = -c1;
+  // a_m: d_m = a_m w on a DOF that neither is in P nor touches P.  The scalar
+  // recurrence runs in extended precision (its binary64 evaluation loses up to
+  // ~1e-14 relative for p = 64); a_p = -dt^2/2 up to the rounding of the constants.
+  long double a_prev = 0.0L, a = -(long double)c1;
   for (int m = 1; m < p; ++m) {
     const double c2 = (dt / p) * (dt / p) * (2.0 * p * p / L.omega) * L.beta_half[m];
     out[1 + m] = c2;
-    const double an = (1.0 + L.beta[m]) * a - L.beta[m] * a_prev - c2;
+    const long double an = (1.0L + L.beta[m]) * a - (long double)L.beta[m] * a_prev - c2;
     a_prev = a;
     a = an;
   }
-  out[0] = a;
+  out[0] = (double)a;
 }
 
 }  // namespace lts

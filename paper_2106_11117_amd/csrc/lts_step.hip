@@ -1,14 +1,17 @@
 // Stabilized LF-LTS time stepping on the device (Algorithm 2, u-form).
 //
-// In the variables u = M^-1/2 z the scheme reads, with A_u = M^-1 K:
+// In the variables u = M^-1/2 z the scheme reads, with A_u = M^-1 K and the
+// recurrence carried on the increments d_m = q_m/p - u_n:
 //   w       = A_u (I - P) u_n
-//   q_1/p   = u_n - c1 (w + A_u P u_n)
-//   q_m+1/p = (1 + beta_m) q_m/p - beta_m q_m-1/p - c2_m (w + A_u P q_m/p)
-//   u_n+1   = -u_n-1 + 2 q_1          (start-up: u_1 = q_1)
+//   d_1     = -c1 (w + A_u P u_n)
+//   d_m+1   = (1 + beta_m) d_m - beta_m d_m-1 - c2_m (w + A_u P (u_n + d_m))
+//   u_n+1   = 2 u_n - u_n-1 + 2 d_p          (start-up: u_1 = u_0 + d_p)
 // with c1 = 1/2 (dt/p)^2 2p^2/(omega delta), c2_m = (dt/p)^2 2p^2/omega beta_m+1/2.
-// A_u P q vanishes outside F+ (P and its neighbours), where q_m = u_n + a_m w
-// and the whole step is u_n+1 = -u_n-1 + 2 (u_n + a_p w): that part is a
-// single stencil sweep.  Only F+ runs the p substeps.
+// (Term by term the printed q-recurrence minus u_n; every coefficient that
+// multiplies the state is exact, so binary64 rounding does not perturb the
+// slow modes.)  A_u P q vanishes outside F+ (P and its neighbours), where
+// d_m = a_m w and the whole step is u_n+1 = 2 u_n - u_n-1 + 2 a_p w: that part
+// is a single stencil sweep.  Only F+ runs the p substeps.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -65,24 +68,25 @@ __global__ __launch_bounds__(256) void k_coarse(LevelView L, const double* __res
                                 cN * (vi - v(k + L.ld)) + cS * (vi - v(k - L.ld)));
   if (!(f & F_FPLUS)) {
     const double ap = coef[(size_t)s * (L.p + 1)];
-    const double q = u[k] + ap * w;
+    const double d = ap * w;
     double* __restrict__ o = Uold + s * sstride;
-    o[k] = startup ? q : (-o[k] + 2.0 * q);
+    o[k] = startup ? (u[k] + d) : (2.0 * u[k] - o[k] + 2.0 * d);
   } else {
     W[s * sstride + k] = w;
   }
 }
 
 // ---------------------------------------------------------------------------
-// One substep m (0-based: m = 0 makes q_1/p) on the DOFs of F+.  The last
-// substep writes u_n+1 into Uold directly.
+// One substep m (0-based: m = 0 makes d_1) on the DOFs of F+: reads u_n (Ucur),
+// d_m (Dc, NULL for m = 0), d_m-1 (Dp, NULL for m <= 1) and w; writes d_m+1 to
+// Dn, or for the last substep u_n+1 into Uold.
 __global__ __launch_bounds__(256) void k_sub(LevelView L, const double* __restrict__ kappa,
                                              const double* __restrict__ coef,
                                              const int* __restrict__ nsteps, int n, int s0, int startup,
-                                             int m, const double* __restrict__ Qc,
-                                             const double* __restrict__ Qp, const double* __restrict__ W,
-                                             double* __restrict__ Qn, double* __restrict__ Uold,
-                                             size_t sstride) {
+                                             int m, const double* __restrict__ Ucur,
+                                             const double* __restrict__ Dc, const double* __restrict__ Dp,
+                                             const double* __restrict__ W, double* __restrict__ Dn,
+                                             double* __restrict__ Uold, size_t sstride) {
   const int s = s0 + blockIdx.z;
   if (n >= nsteps[s]) return;
   const int i = blockIdx.x * TBX + threadIdx.x, j = blockIdx.y * TBY + threadIdx.y;
@@ -91,27 +95,30 @@ __global__ __launch_bounds__(256) void k_sub(LevelView L, const double* __restri
   const uint8_t f = L.flags[k];
   if (!(f & F_FPLUS)) return;
   const size_t so = s * sstride;
-  const double* __restrict__ q = Qc + so;
+  const double* __restrict__ u = Ucur + so;
+  const double* __restrict__ dc = Dc ? Dc + so : nullptr;
   double cE, cW, cN, cS;
   edge_coefs(L, kappa + (size_t)s * L.nb, i, j, cE, cW, cN, cS);
-  auto pq = [&](size_t kk) { return (L.flags[kk] & F_P) ? q[kk] : 0.0; };
+  // P-masked q_m = u_n + d_m at a node
+  auto pq = [&](size_t kk) { return (L.flags[kk] & F_P) ? (dc ? u[kk] + dc[kk] : u[kk]) : 0.0; };
   const double pi = pq(k);
   const double apq = L.invm[k] * (cE * (pi - pq(k + 1)) + cW * (pi - pq(k - 1)) +
                                   cN * (pi - pq(k + L.ld)) + cS * (pi - pq(k - L.ld)));
   const double* cf = coef + (size_t)s * (L.p + 1);
   const double r = W[so + k] + apq;
-  double qn;
+  double dn;
   if (m == 0) {
-    qn = q[k] - cf[1] * r;
+    dn = -cf[1] * r;
   } else {
     const double b = L.beta[m];
-    qn = (1.0 + b) * q[k] - b * Qp[so + k] - cf[1 + m] * r;
+    const double dprev = Dp ? Dp[so + k] : 0.0;
+    dn = (1.0 + b) * dc[k] - b * dprev - cf[1 + m] * r;
   }
   if (m == L.p - 1) {
     double* __restrict__ o = Uold + so;
-    o[k] = startup ? qn : (-o[k] + 2.0 * qn);
+    o[k] = startup ? (u[k] + dn) : (2.0 * u[k] - o[k] + 2.0 * dn);
   } else {
-    Qn[so + k] = qn;
+    Dn[so + k] = dn;
   }
 }
 
@@ -239,15 +246,15 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
     const int st = step == 0;
     k_coarse<<<dim3(gx, gy, nz), blk, 0, c->stream>>>(L, d_kappa, d_coef, d_nsteps, step, s0, st, Ucur, Uold,
                                                       Wb, sstride);
-    const double* qprev = nullptr;
-    const double* qcur = Ucur;
+    const double* dprev = nullptr;
+    const double* dcur = nullptr;
     double* bufs[2] = {QA, QB};
     for (int m = 0; m < L.p; ++m) {
-      double* qnext = bufs[m & 1];
-      k_sub<<<dim3(gx, gy, nz), blk, 0, c->stream>>>(L, d_kappa, d_coef, d_nsteps, step, s0, st, m, qcur,
-                                                     qprev, Wb, qnext, Uold, sstride);
-      qprev = qcur;
-      qcur = qnext;
+      double* dnext = bufs[m & 1];
+      k_sub<<<dim3(gx, gy, nz), blk, 0, c->stream>>>(L, d_kappa, d_coef, d_nsteps, step, s0, st, m, Ucur,
+                                                     dcur, dprev, Wb, dnext, Uold, sstride);
+      dprev = dcur;
+      dcur = dnext;
     }
     launches += 1 + L.p;
   };
