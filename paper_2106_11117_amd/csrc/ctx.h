@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "device.h"
+#include "fused.h"
 #include "host.h"
 
 namespace lts {
@@ -38,8 +39,15 @@ struct DevBuf {
   }
 };
 
+struct TilingDev {
+  int TX = 0, TY = 0, n_fine = 0, n_coarse = 0, wg_per_sample = 0;
+  double halo_ratio = 1.0;
+  DevBuf ent, tiles, citems;
+};
+
 struct DevLevel {
   HostLevel H;
+  TilingDev tiling;     // fused-step tiling in use
   int ld = 0;           // row pitch (elements) of node/cell arrays and states
   size_t nodes = 0;     // nyn * ld
   DevBuf hx, hy, inv2hx, inv2hy, x, y, cblk, flags, invm, qoiw, beta, beta_half;
@@ -105,5 +113,18 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
                           bool per_sample, double* d_Q);
 
 lts_status moments_device(lts_ctx c, const double* d_x, int n, double* d_out3);
+
+lts_status upload_tiling(lts_ctx c, const TilingHost& T, TilingDev& D);
+
+// Tile-size candidates (TX, TY) tried for the fused step, in order.
+const std::vector<std::pair<int, int>>& tile_candidates();
+
+// Choose and upload a default tiling (smallest region overhead that fits).
+lts_status default_tiling(lts_ctx c, DevLevel& lv);
+
+// One fused step launch for samples s0 .. s0+active-1 (sorted order).
+lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const double* d_kappa,
+                       const double* d_coef, const double* Ucur, double* Uold, size_t sstride, int s0,
+                       int active, int startup, hipStream_t stream);
 
 }  // namespace lts

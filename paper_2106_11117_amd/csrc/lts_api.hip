@@ -79,6 +79,7 @@ struct Staged {
   int n = 0;
   std::vector<double> kappa, x0, dt, coef;
   std::vector<int> nsteps;
+  std::vector<int> perm;   // sorted position -> caller index (decreasing n_steps)
 };
 
 lts_status stage(lts_ctx c, const DevLevel& lv, const lts_samples* S, Staged& st) {
@@ -110,6 +111,27 @@ lts_status stage(lts_ctx c, const DevLevel& lv, const lts_samples* S, Staged& st
       if (!(k > 0.0) || !std::isfinite(k)) return arg_fail(c, "kappa must be finite and > 0");
     }
   }
+  // sort by decreasing step count (stable): running samples form a prefix
+  st.perm.resize(n);
+  for (int s = 0; s < n; ++s) st.perm[s] = s;
+  std::stable_sort(st.perm.begin(), st.perm.end(),
+                   [&](int a, int b) { return st.nsteps[a] > st.nsteps[b]; });
+  {
+    std::vector<double> k2(st.kappa.size()), x2(st.x0.size()), d2(n);
+    std::vector<int> n2(n);
+    for (int t = 0; t < n; ++t) {
+      const int s = st.perm[t];
+      std::copy(&st.kappa[(size_t)s * nb], &st.kappa[(size_t)s * nb] + nb, &k2[(size_t)t * nb]);
+      x2[2 * t] = st.x0[2 * s];
+      x2[2 * t + 1] = st.x0[2 * s + 1];
+      d2[t] = st.dt[s];
+      n2[t] = st.nsteps[s];
+    }
+    st.kappa.swap(k2);
+    st.x0.swap(x2);
+    st.dt.swap(d2);
+    st.nsteps.swap(n2);
+  }
   st.coef.resize((size_t)n * (p + 1));
   for (int s = 0; s < n; ++s) step_coefficients(lv.H, st.dt[s], &st.coef[(size_t)s * (p + 1)]);
   return LTS_OK;
@@ -130,15 +152,20 @@ lts_status upload_staged(lts_ctx c, const Staged& st) {
   return LTS_OK;
 }
 
-lts_status finish_Q(lts_ctx c, int n, int ptr_kind, double* Q_out) {
-  std::vector<double> q(n);
-  if (n > 0) {
-    LTS_HIP(c, hipMemcpyAsync(q.data(), c->Qd.p, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
-    if (ptr_kind == LTS_PTR_DEVICE)
-      LTS_HIP(c, hipMemcpyAsync(Q_out, c->Qd.p, (size_t)n * 8, hipMemcpyDeviceToDevice, c->stream));
-  }
+lts_status finish_Q(lts_ctx c, const Staged& st, int ptr_kind, double* Q_out) {
+  const int n = st.n;
+  std::vector<double> qs(n), q(n);
+  if (n > 0) LTS_HIP(c, hipMemcpyAsync(qs.data(), c->Qd.p, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
   LTS_HIP(c, hipStreamSynchronize(c->stream));
-  if (ptr_kind == LTS_PTR_HOST && n > 0) std::memcpy(Q_out, q.data(), (size_t)n * 8);
+  for (int t = 0; t < n; ++t) q[st.perm[t]] = qs[t];
+  if (n > 0) {
+    if (ptr_kind == LTS_PTR_DEVICE) {
+      LTS_HIP(c, hipMemcpyAsync(Q_out, q.data(), (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
+      LTS_HIP(c, hipStreamSynchronize(c->stream));
+    } else {
+      std::memcpy(Q_out, q.data(), (size_t)n * 8);
+    }
+  }
   for (int s = 0; s < n; ++s)
     if (!std::isfinite(q[s])) {
       c->err = "non-finite QoI (unstable sample)";
@@ -165,7 +192,7 @@ lts_status forward_impl(lts_ctx c, int32_t level, const lts_samples* S, int32_t 
                        c->x0.as<double>(), S->width, st.nsteps, precision, per_sample, c->Qd.as<double>());
     if (r != LTS_OK) return r;
   }
-  return finish_Q(c, st.n, S->ptr_kind, Q_out);
+  return finish_Q(c, st, S->ptr_kind, Q_out);
 }
 
 }  // namespace
@@ -219,6 +246,7 @@ lts_status lts_add_level(lts_ctx c, const lts_grid_desc* d, int32_t* id_out) {
   LTS_HIP(c, hipSetDevice(c->device));
   lts_status r = upload_level(c, *D);
   if (r != LTS_OK) return r;
+  if ((r = default_tiling(c, *D)) != LTS_OK) return r;
   *id_out = (int32_t)c->levels.size();
   c->levels.push_back(std::move(D));
   return LTS_OK;

@@ -44,85 +44,6 @@ __global__ __launch_bounds__(256) void k_init(LevelView L, const double* __restr
 }
 
 // ---------------------------------------------------------------------------
-// Coarse sweep: w = A_u (I-P) u_n at every DOF; outside F+ it completes the
-// step, inside F+ it stores w for the substeps.
-__global__ __launch_bounds__(256) void k_coarse(LevelView L, const double* __restrict__ kappa,
-                                                const double* __restrict__ coef,
-                                                const int* __restrict__ nsteps, int n, int s0,
-                                                int startup, const double* __restrict__ Ucur,
-                                                double* __restrict__ Uold, double* __restrict__ W,
-                                                size_t sstride) {
-  const int s = s0 + blockIdx.z;
-  if (n >= nsteps[s]) return;
-  const int i = blockIdx.x * TBX + threadIdx.x, j = blockIdx.y * TBY + threadIdx.y;
-  if (i >= L.nxn || j >= L.nyn) return;
-  const size_t k = (size_t)j * L.ld + i;
-  const uint8_t f = L.flags[k];
-  if (!(f & F_DOF)) return;
-  const double* __restrict__ u = Ucur + s * sstride;
-  double cE, cW, cN, cS;
-  edge_coefs(L, kappa + (size_t)s * L.nb, i, j, cE, cW, cN, cS);
-  auto v = [&](size_t kk) { return (L.flags[kk] & F_P) ? 0.0 : u[kk]; };
-  const double vi = v(k);
-  const double w = L.invm[k] * (cE * (vi - v(k + 1)) + cW * (vi - v(k - 1)) +
-                                cN * (vi - v(k + L.ld)) + cS * (vi - v(k - L.ld)));
-  if (!(f & F_FPLUS)) {
-    const double ap = coef[(size_t)s * (L.p + 1)];
-    const double d = ap * w;
-    double* __restrict__ o = Uold + s * sstride;
-    o[k] = startup ? (u[k] + d) : (2.0 * u[k] - o[k] + 2.0 * d);
-  } else {
-    W[s * sstride + k] = w;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// One substep m (0-based: m = 0 makes d_1) on the DOFs of F+: reads u_n (Ucur),
-// d_m (Dc, NULL for m = 0), d_m-1 (Dp, NULL for m <= 1) and w; writes d_m+1 to
-// Dn, or for the last substep u_n+1 into Uold.
-__global__ __launch_bounds__(256) void k_sub(LevelView L, const double* __restrict__ kappa,
-                                             const double* __restrict__ coef,
-                                             const int* __restrict__ nsteps, int n, int s0, int startup,
-                                             int m, const double* __restrict__ Ucur,
-                                             const double* __restrict__ Dc, const double* __restrict__ Dp,
-                                             const double* __restrict__ W, double* __restrict__ Dn,
-                                             double* __restrict__ Uold, size_t sstride) {
-  const int s = s0 + blockIdx.z;
-  if (n >= nsteps[s]) return;
-  const int i = blockIdx.x * TBX + threadIdx.x, j = blockIdx.y * TBY + threadIdx.y;
-  if (i >= L.nxn || j >= L.nyn) return;
-  const size_t k = (size_t)j * L.ld + i;
-  const uint8_t f = L.flags[k];
-  if (!(f & F_FPLUS)) return;
-  const size_t so = s * sstride;
-  const double* __restrict__ u = Ucur + so;
-  const double* __restrict__ dc = Dc ? Dc + so : nullptr;
-  double cE, cW, cN, cS;
-  edge_coefs(L, kappa + (size_t)s * L.nb, i, j, cE, cW, cN, cS);
-  // P-masked q_m = u_n + d_m at a node
-  auto pq = [&](size_t kk) { return (L.flags[kk] & F_P) ? (dc ? u[kk] + dc[kk] : u[kk]) : 0.0; };
-  const double pi = pq(k);
-  const double apq = L.invm[k] * (cE * (pi - pq(k + 1)) + cW * (pi - pq(k - 1)) +
-                                  cN * (pi - pq(k + L.ld)) + cS * (pi - pq(k - L.ld)));
-  const double* cf = coef + (size_t)s * (L.p + 1);
-  const double r = W[so + k] + apq;
-  double dn;
-  if (m == 0) {
-    dn = -cf[1] * r;
-  } else {
-    const double b = L.beta[m];
-    const double dprev = Dp ? Dp[so + k] : 0.0;
-    dn = (1.0 + b) * dc[k] - b * dprev - cf[1 + m] * r;
-  }
-  if (m == L.p - 1) {
-    double* __restrict__ o = Uold + so;
-    o[k] = startup ? (u[k] + dn) : (2.0 * u[k] - o[k] + 2.0 * dn);
-  } else {
-    Dn[so + k] = dn;
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Q[s] = sum_k qoiw[k] u_k, one workgroup per sample, fixed summation order.
 __global__ __launch_bounds__(256) void k_qoi(LevelView L, const int* __restrict__ nsteps,
                                              const double* __restrict__ B0, const double* __restrict__ B1,
@@ -202,6 +123,8 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
                           const double* d_coef, const int* d_nsteps, const double* d_x0, double width,
                           const std::vector<int>& h_nsteps, int precision, bool per_sample,
                           double* d_Q) {
+  // Samples arrive sorted by decreasing step count, so the samples still
+  // running at step `step` are a prefix of the batch.
   if (precision != LTS_FP64) {
     c->err = "FP32 stepping is not available in this build";
     return LTS_ERR_ARG;
@@ -211,14 +134,8 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
   const size_t bytes = (size_t)n * sstride * sizeof(double);
   LTS_HIP(c, c->st0.ensure(bytes));
   LTS_HIP(c, c->st1.ensure(bytes));
-  LTS_HIP(c, c->wbuf.ensure(bytes));
-  LTS_HIP(c, c->qa.ensure(bytes));
-  LTS_HIP(c, c->qb.ensure(bytes));
   double* B[2] = {c->st0.as<double>(), c->st1.as<double>()};
-  double* Wb = c->wbuf.as<double>();
-  double* QA = c->qa.as<double>();
-  double* QB = c->qb.as<double>();
-  const int maxn = *std::max_element(h_nsteps.begin(), h_nsteps.end());
+  const int maxn = h_nsteps[0];
   const dim3 blk(TBX, TBY);
   const int gx = (L.ld + TBX - 1) / TBX, gy = (L.nyn + TBY - 1) / TBY;
 
@@ -238,32 +155,27 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
     k_init<<<dim3(gx, gy, nz), blk, 0, c->stream>>>(L, d_x0 + 2 * z0, width, B[0] + z0 * sstride,
                                                      B[1] + z0 * sstride, sstride);
   }
+  LTS_HIP(c, hipGetLastError());
   if (c->timing) LTS_HIP(c, hipEventRecord(e1, c->stream));
   int64_t launches = 0;
-  auto one_step = [&](int step, int s0, int nz) {
-    const double* Ucur = B[step & 1];
-    double* Uold = B[(step + 1) & 1];
-    const int st = step == 0;
-    k_coarse<<<dim3(gx, gy, nz), blk, 0, c->stream>>>(L, d_kappa, d_coef, d_nsteps, step, s0, st, Ucur, Uold,
-                                                      Wb, sstride);
-    const double* dprev = nullptr;
-    const double* dcur = nullptr;
-    double* bufs[2] = {QA, QB};
-    for (int m = 0; m < L.p; ++m) {
-      double* dnext = bufs[m & 1];
-      k_sub<<<dim3(gx, gy, nz), blk, 0, c->stream>>>(L, d_kappa, d_coef, d_nsteps, step, s0, st, m, Ucur,
-                                                     dcur, dprev, Wb, dnext, Uold, sstride);
-      dprev = dcur;
-      dcur = dnext;
-    }
-    launches += 1 + L.p;
-  };
+  lts_status r;
   if (per_sample) {
     for (int s = 0; s < n; ++s)
-      for (int step = 0; step < h_nsteps[s]; ++step) one_step(step, s, 1);
+      for (int step = 0; step < h_nsteps[s]; ++step) {
+        r = launch_step(c, lv, lv.tiling, d_kappa, d_coef, B[step & 1], B[(step + 1) & 1], sstride, s, 1,
+                        step == 0, c->stream);
+        if (r != LTS_OK) return r;
+        ++launches;
+      }
   } else {
-    for (int step = 0; step < maxn; ++step)
-      for (int z0 = 0; z0 < n; z0 += kMaxZ) one_step(step, z0, std::min(kMaxZ, n - z0));
+    int active = n;
+    for (int step = 0; step < maxn; ++step) {
+      while (active > 0 && h_nsteps[active - 1] <= step) --active;
+      r = launch_step(c, lv, lv.tiling, d_kappa, d_coef, B[step & 1], B[(step + 1) & 1], sstride, 0,
+                      active, step == 0, c->stream);
+      if (r != LTS_OK) return r;
+      ++launches;
+    }
   }
   LTS_HIP(c, hipGetLastError());
   if (c->timing) LTS_HIP(c, hipEventRecord(e2, c->stream));
@@ -282,11 +194,11 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
   if (c->timing) {
     LTS_HIP(c, hipEventRecord(e3, c->stream));
     LTS_HIP(c, hipEventSynchronize(e3));
-    float a = 0, b = 0;
-    LTS_HIP(c, hipEventElapsedTime(&a, e1, e2));
-    LTS_HIP(c, hipEventElapsedTime(&b, e0, e3));
-    c->last.step_kernel_ms = a;
-    c->last.total_ms = b;
+    float ta = 0, tb = 0;
+    LTS_HIP(c, hipEventElapsedTime(&ta, e1, e2));
+    LTS_HIP(c, hipEventElapsedTime(&tb, e0, e3));
+    c->last.step_kernel_ms = ta;
+    c->last.total_ms = tb;
   }
   return LTS_OK;
 }
