@@ -11,19 +11,26 @@
 namespace lts {
 
 constexpr int kFineThreads = 1024;                  // threads per workgroup
-constexpr int kNPT = 5;                             // region nodes per thread
+constexpr int kNPT = 4;                             // region nodes per thread
 constexpr int kRegionCap = kFineThreads * kNPT;     // nodes of one fine-tile region
 constexpr int kCoarseRows = 16;                     // rows walked by one coarse wavefront
+constexpr int kRectCap = 7992;                      // LDS slots of one rectangular region buffer
+constexpr int kPitch = 96;                          // LDS row pitch of the rectangle (slots)
+constexpr int kCoarseThreads = 256;                 // coarse workgroup: 4 wavefronts, one item each
 
 struct TilingHost {
   int TX = 0, TY = 0;
-  int n_fine = 0, n_coarse = 0, wg_per_sample = 0;
+  int ox = 0, oy = 0;               // origin of the tile grid
+  bool rect = false;                // region stored as a zero-padded rectangle in LDS
+  int pitch = 0, rect_slots = 0;    // rect mode: LDS row pitch and slots in use
+  int n_fine = 0, n_coarse = 0, wg_per_sample = 0;   // wg_per_sample: fine + coarse workgroups
   double halo_ratio = 1.0;          // region nodes / F+ nodes
   std::vector<int4> ent;            // region entries (see lts_fused.hip)
   std::vector<int2> tiles;          // (offset, length)
   std::vector<int2> citems;         // (i0, j0)
 };
 
-std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, TilingHost& T);
+std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int oy, bool rect,
+                         TilingHost& T);
 
 }  // namespace lts
