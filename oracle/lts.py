@@ -1,8 +1,12 @@
 """Leapfrog and stabilized LF-LTS time stepping, oracle side (test infrastructure only).
 
-Everything runs in the symmetrized variables of Sec. 3.1, z = M^1/2 u,
-A = M^-1/2 K M^-1/2, on *all* DOFs, with the projector P kept as a 0/1
-diagonal, exactly as Algorithm 2 (stabilized LF-LTS, Sec. 3.3) is stated:
+Algorithm 2 (stabilized LF-LTS, Sec. 3.3) is stated for z = M^1/2 u and
+A = M^-1/2 K M^-1/2; because M and P are diagonal they commute, and the same
+algorithm written for u with A_u = M^-1 K produces the iterates
+u_n = M^-1/2 z_n.  The oracle runs it in u (reading: in binary64 the rounded
+entries of M^-1/2 K M^-1/2 no longer annihilate the discrete constants, which
+shifts the frequencies of smooth modes by far more than the rounding of
+(K v)/m does), on *all* DOFs, with P kept as a 0/1 diagonal:
 
   w_n      = A (I - P) q_0,                       q_0 = z_n
   q_{1/p}  = q_0 - 1/2 (dt/p)^2 (2p^2/(omega delta)) (w_n + A P q_0)
@@ -38,7 +42,7 @@ from __future__ import annotations
 import numpy as np
 
 from .cheby import ChebConsts, cheb_consts
-from .fem import Operators, sym_operator
+from .fem import Operators, mass_scaled_operator
 
 
 def lts_q1(A, Pd, z, dt, cc: ChebConsts):
@@ -95,17 +99,20 @@ def pulse(ops: Operators, x0, width: float = 0.05) -> np.ndarray:
 
 
 class Solver:
-    """One sample on one level: z-form Algorithm 2 with start-up."""
+    """One sample on one level: Algorithm 2 in u = M^-1/2 z with start-up.
+
+    The iterates are named z below as in the algorithm; they are nodal values
+    u of the finite element function."""
 
     def __init__(self, ops: Operators, kappa_blocks, nu: float | None = None, p: int | None = None,
                  Pd=None):
         self.ops = ops
-        self.A = sym_operator(ops, kappa_blocks)
+        self.A = mass_scaled_operator(ops, kappa_blocks)
         self.p = ops.lv.p if p is None else p
         self.nu = ops.lv.nu if nu is None else nu
         self.cc = cheb_consts(self.p, self.nu)
         self.Pd = ops.Pd if Pd is None else Pd
-        self.sqm = np.sqrt(ops.m)
+        self.m = ops.m
 
     def d1(self, z, dt):
         return lts_d1(self.A, self.Pd, z, dt, self.cc)
@@ -115,15 +122,15 @@ class Solver:
         return z + self.d1(z, dt)
 
     def run(self, u0, dt, n_steps, v0=None, keep=False, form="increment"):
-        """Return u(T) = M^-1/2 z_{n_steps} (and all z_n when ``keep``).
+        """Return u(T) (and all u_n when ``keep``).
         form = "increment" (default) or "printed" (the q-recurrence as printed)."""
-        z0 = self.sqm * u0
+        z0 = u0
         if form == "increment":
             z1 = z0 + self.d1(z0, dt)
         else:
             z1 = lts_q1(self.A, self.Pd, z0, dt, self.cc)
         if v0 is not None:
-            z1 = z1 + dt * self.sqm * v0
+            z1 = z1 + dt * v0
         zs = [z0, z1] if keep else None
         zm, zc = z0, z1
         for _ in range(1, n_steps):
@@ -134,26 +141,25 @@ class Solver:
             zm, zc = zc, zn
             if keep:
                 zs.append(zc)
-        u = zc / self.sqm
-        return (u, zs) if keep else u
+        return (zc, zs) if keep else zc
 
     def run_lf(self, u0, dt, n_steps, v0=None):
-        """Plain leapfrog (Sec. 3.1): z_1 = z_0 + dt M^1/2 v_0 - dt^2/2 A z_0."""
-        z0 = self.sqm * u0
+        """Plain leapfrog (Sec. 3.1) in u: u_1 = u_0 + dt v_0 - dt^2/2 A_u u_0."""
+        z0 = u0
         z1 = z0 - 0.5 * dt * dt * (self.A @ z0)
         if v0 is not None:
-            z1 = z1 + dt * self.sqm * v0
+            z1 = z1 + dt * v0
         zm, zc = z0, z1
         for _ in range(1, n_steps):
             zm, zc = zc, lf_step(self.A, zc, zm, dt)
-        return zc / self.sqm
+        return zc
 
     def energy(self, z_np1, z_n, dt):
-        """E_{n+1/2} = 1/2 |z_{n+1} - z_n|^2 / dt^2 + 1/2 z_{n+1}^T A_p z_n with the
-        effective LTS operator A_p y = 2 (y - q_1(y)) / dt^2 (symmetric)."""
+        """E_{n+1/2} = 1/2 |u_{n+1} - u_n|_M^2 / dt^2 + 1/2 u_{n+1}^T M A_p u_n with the
+        effective LTS operator A_p y = 2 (y - q_1(y)) / dt^2 (M-self-adjoint)."""
         d = z_np1 - z_n
         Apz = -2.0 * self.d1(z_n, dt) / (dt * dt)
-        return 0.5 * float(d @ d) / (dt * dt) + 0.5 * float(z_np1 @ Apz)
+        return 0.5 * float(d @ (self.m * d)) / (dt * dt) + 0.5 * float(z_np1 @ (self.m * Apz))
 
 
 def qoi(ops: Operators, u) -> float:

@@ -284,11 +284,11 @@ def test_lts_all_fine_nu0_equals_leapfrog_substeps():
     dt = 0.3 / n
     u_lts = s.run(v, dt, 1)
     # p leapfrog steps of size dt/p from rest (start-up included) give the same q_1
-    z0 = s.sqm * v
+    z0 = v
     zm, zc = z0, z0 - 0.5 * (dt / p) ** 2 * (s.A @ z0)
     for _ in range(1, p):
         zm, zc = zc, lts.lf_step(s.A, zc, zm, dt / p)
-    assert np.max(np.abs(u_lts - zc / s.sqm)) < 1e-13
+    assert np.max(np.abs(u_lts - zc)) < 1e-13
 
 
 @pytest.mark.parametrize("which", ["P0", "p1"])
@@ -350,8 +350,13 @@ def test_effective_operator_symmetric_and_stable():
     I = np.eye(n)
     R = np.stack([s.q1(I[:, k], dt) for k in range(n)], axis=1)
     Ap = 2 * (I - R) / (dt * dt)
-    assert np.max(np.abs(Ap - Ap.T)) < 1e-12 * np.max(np.abs(Ap))
-    ev = np.linalg.eigvalsh(0.5 * (Ap + Ap.T)) * dt * dt
+    # M A_p is symmetric (A_p self-adjoint in the M inner product)
+    MAp = ops.m[:, None] * Ap
+    assert np.max(np.abs(MAp - MAp.T)) < 1e-12 * np.max(np.abs(MAp))
+    # spectrum of dt^2 A_p (similar to the symmetric M^1/2 A_p M^-1/2) inside (0, 4)
+    sq = np.sqrt(ops.m)
+    S = sq[:, None] * Ap / sq[None, :]
+    ev = np.linalg.eigvalsh(0.5 * (S + S.T)) * dt * dt
     assert ev.min() > 0 and ev.max() < 4
 
 
@@ -485,13 +490,17 @@ def test_increment_form_equals_printed_form_one_step():
 
 def _printed_extended(ops, kappa, u0, dt, n):
     """The printed recurrence of Algorithm 2 evaluated in x87 extended precision
-    (64-bit significand; coefficients promoted from their binary64 values)."""
-    import scipy.sparse as sp
+    (64-bit significand; coefficients, masses and stiffness entries promoted from
+    their binary64 values) for z = M^1/2 u with A = M^-1/2 K M^-1/2, K in edge form."""
     LD = np.longdouble
-    K = fem.stiffness(ops.ed, kappa).astype(LD)
+    K = fem.EdgeStiffness(ops.ed, kappa)
     sqm = np.sqrt(ops.m.astype(LD))
-    D = sp.diags(LD(1) / sqm)
-    A = (D @ K @ D).tocsr()
+
+    class A:
+        def __matmul__(self, v):
+            return (K @ (v / sqm)) / sqm
+
+    A = A()
     Pd = ops.Pd.astype(LD)
     cc = cheby.cheb_consts(ops.lv.p, ops.lv.nu)
     p = cc.p
@@ -533,3 +542,27 @@ def test_increment_form_tracks_extended_precision(n_base, i):
     if n_base == 64:
         qp = float(lts.qoi(ops, s.run(u0, dt, n, form="printed")))
         assert abs(qp - qL) > 100 * abs(qi - qL)
+
+
+def test_edge_form_stiffness():
+    """K v in edge form: the same matrix as the assembled one, constants exactly in
+    its kernel away from the boundary, symmetric."""
+    lv = mesh.box_refined_level(16)
+    ops = fem.operators(lv)
+    kap = np.exp(np.linspace(-0.7, 0.6, 16))
+    Ke = fem.EdgeStiffness(ops.ed, kap)
+    Km = Ke.matrix()
+    v = np.random.default_rng(4).standard_normal(ops.Pd.size)
+    assert np.max(np.abs(Ke @ v - Km @ v)) < 1e-12 * np.max(np.abs(Km @ v))
+    assert abs(Km - Km.T).max() == 0.0
+    # interior rows whose neighbours are all DOFs annihilate constants exactly
+    ones = np.ones(ops.Pd.size)
+    # rows with a nonzero coupling to a Dirichlet node (an incidence row with one entry)
+    single = np.diff(Ke.E.indptr) == 1
+    ge = np.flatnonzero(single & (Ke.w != 0.0))
+    boundary_row = np.zeros(ops.Pd.size, dtype=bool)
+    boundary_row[Ke.E.indices[Ke.E.indptr[ge]]] = True
+    r = Ke @ ones
+    assert np.all(r[~boundary_row] == 0.0)
+    # and Dirichlet couplings act like u = 0 outside: K 1 = sum of couplings to the boundary
+    assert np.all(r[boundary_row] > 0.0)
