@@ -81,7 +81,7 @@ struct lts_ctx_s {
   std::string err;
   std::vector<std::unique_ptr<lts::DevLevel>> levels;
   // workspace
-  lts::DevBuf kappa, coef, nsteps, x0, Qd, st0, st1, wbuf, qa, qb, red;
+  lts::DevBuf kappa, coef, nsteps, x0, Qd, st0, st1, wbuf, qa, qb, red, adj, dldq, gout;
   bool timing = false;
   lts_timing last{};
   std::vector<hipEvent_t> ev_pool;
@@ -115,6 +115,20 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
                           bool per_sample, double* d_Q);
 
 lts_status moments_device(lts_ctx c, const double* d_x, int n, double* d_out3);
+
+// u_0 (pulse) into B0 and zeros into B1 for samples 0..n-1.
+lts_status init_states(lts_ctx c, const DevLevel& lv, int n, const double* d_x0, double width, double* B0,
+                       double* B1);
+
+// Q[s] = w^T u_{n_steps[s]} with the final state in B[n_steps[s] % 2].
+lts_status qoi_device(lts_ctx c, const DevLevel& lv, int n, const int* d_nsteps, const double* B0,
+                      const double* B1, double* d_Q);
+
+// Checkpointed discrete adjoint for one sub-batch (see lts_adjoint.hip).
+lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_kappa,
+                          const double* d_coef, const int* d_nsteps, const double* d_x0, double width,
+                          const std::vector<int>& h_nsteps, int K, const double* d_dldq, double* d_Q,
+                          double* d_out, int s_base);
 
 lts_status upload_tiling(lts_ctx c, const TilingHost& T, TilingDev& D);
 

@@ -17,6 +17,7 @@ constexpr int kCoarseRows = 16;                     // rows walked by one coarse
 constexpr int kRectCap = 7992;                      // LDS slots of one rectangular region buffer
 constexpr int kPitch = 96;                          // LDS row pitch of the rectangle (slots)
 constexpr int kCoarseThreads = 256;                 // coarse workgroup: 4 wavefronts, one item each
+constexpr int kMaxAdjP = 64;                        // largest p supported by the adjoint
 
 struct TilingHost {
   int TX = 0, TY = 0;

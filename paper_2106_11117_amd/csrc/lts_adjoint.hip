@@ -1,0 +1,378 @@
+// Discrete adjoint of stabilized LF-LTS: dQ/d(block log wave speed) per sample.
+//
+// With R y = q_1(y) = y + d_p(y) (Algorithm 2 on increments, u-form, A_u =
+// M^-1 K), the forward recurrence is u_1 = R u_0, u_n+1 = 2 R u_n - u_n-1 and
+// Q = w^T u_N.  R is self-adjoint in the M inner product, so the adjoint runs
+// the same recurrence backward:
+//   mu_N = M^-1 w, mu_N+1 = 0, mu_n = 2 R mu_n+1 - mu_n+2   (n = N-1 .. 1),
+//   dQ/dkappa = sum_{n>=1} 2 <mu_n+1, d(R u_n)>_M + <mu_1, d(R u_0)>_M.
+// Each <mu, d(R y)/dkappa>_M is a reverse sweep over the p substeps for fixed
+// y: with Lambda_p = f M mu (f = 2 or 1), Lambda_p+1 = 0,
+//   Lambda_m = (1 + beta_m) Lambda_m+1 - c2_m P K (Lambda_m+1 / m) - beta_m+1 Lambda_m+2,
+//   lw = -c1 Lambda_1 - sum_{m=1}^{p-1} c2_m Lambda_m+1,
+// and the derivative pairs (a, b) = (-c2_m Lambda_m+1, P q_m), (-c1 Lambda_1, P q_0),
+// (lw, (I - P) y) contract with dK/dkappa_cell: for every side (i, j) of a cell
+// with leg weight g (hy/(2 hx) or hx/(2 hy)), g (a_i/m_i - a_j/m_j)(b_i - b_j),
+// with a = b = 0 on Dirichlet nodes.  One thread owns one cell, so the
+// accumulation is deterministic.  dQ/dg_b = 2 kappa_b sum_{cells of b} dQ/dkappa_cell.
+// Forward states are checkpointed every K steps (pairs (u_k, u_k+1)) and
+// recomputed one segment at a time with the forward step kernels; mu is
+// advanced by the forward step kernels too (the recurrence is the same).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ctx.h"
+
+namespace lts {
+
+namespace {
+
+constexpr int BX = 64, BY = 4;
+
+struct AdjArgs {
+  LevelView L;
+  const double* __restrict__ kappa;  // [S][nb]
+  const double* __restrict__ coef;   // [S][p+1]
+  size_t sstride;
+  int s_active;                      // samples 0..s_active-1 take part
+};
+
+// w = A_u (I - P) y at every DOF.
+__global__ __launch_bounds__(256) void k_adj_w(AdjArgs a, const double* __restrict__ Y,
+                                               double* __restrict__ W) {
+  const int s = blockIdx.z;
+  if (s >= a.s_active) return;
+  const LevelView& L = a.L;
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+  if (i >= L.nxn || j >= L.nyn) return;
+  const size_t k = (size_t)j * L.ld + i, so = (size_t)s * a.sstride;
+  if (!(L.flags[k] & F_DOF)) {
+    W[so + k] = 0.0;
+    return;
+  }
+  const double* __restrict__ y = Y + so;
+  double cE, cW, cN, cS;
+  edge_coefs(L, a.kappa + (size_t)s * L.nb, i, j, cE, cW, cN, cS);
+  auto v = [&](size_t kk) { return (L.flags[kk] & F_P) ? 0.0 : y[kk]; };
+  const double vi = v(k);
+  W[so + k] = L.invm[k] * (cE * (vi - v(k + 1)) + cW * (vi - v(k - 1)) + cN * (vi - v(k + L.ld)) +
+                           cS * (vi - v(k - L.ld)));
+}
+
+// d_m+1 from d_m (Dc, NULL: 0), d_m-1 (Dp, NULL: 0), w, at every DOF (m = 0 .. p-1).
+__global__ __launch_bounds__(256) void k_adj_sub(AdjArgs a, int m, const double* __restrict__ Y,
+                                                 const double* __restrict__ Dc,
+                                                 const double* __restrict__ Dp,
+                                                 const double* __restrict__ W, double* __restrict__ Dn) {
+  const int s = blockIdx.z;
+  if (s >= a.s_active) return;
+  const LevelView& L = a.L;
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+  if (i >= L.nxn || j >= L.nyn) return;
+  const size_t k = (size_t)j * L.ld + i, so = (size_t)s * a.sstride;
+  if (!(L.flags[k] & F_DOF)) {
+    Dn[so + k] = 0.0;
+    return;
+  }
+  const double* __restrict__ y = Y + so;
+  const double* __restrict__ dc = Dc ? Dc + so : nullptr;
+  double cE, cW, cN, cS;
+  edge_coefs(L, a.kappa + (size_t)s * L.nb, i, j, cE, cW, cN, cS);
+  auto pq = [&](size_t kk) { return (L.flags[kk] & F_P) ? (dc ? y[kk] + dc[kk] : y[kk]) : 0.0; };
+  const double pi = pq(k);
+  const double apq = L.invm[k] * (cE * (pi - pq(k + 1)) + cW * (pi - pq(k - 1)) +
+                                  cN * (pi - pq(k + L.ld)) + cS * (pi - pq(k - L.ld)));
+  const double* cf = a.coef + (size_t)s * (L.p + 1);
+  const double r = W[so + k] + apq;
+  double dn;
+  if (m == 0) {
+    dn = -cf[1] * r;
+  } else {
+    const double b = L.beta[m];
+    dn = (1.0 + b) * dc[k] - b * (Dp ? Dp[so + k] : 0.0) - cf[1 + m] * r;
+  }
+  Dn[so + k] = dn;
+}
+
+// Lambda_p = f m mu (and lw = 0).
+__global__ __launch_bounds__(256) void k_adj_lam_init(AdjArgs a, double f, const double* __restrict__ MU,
+                                                      double* __restrict__ Lp, double* __restrict__ LW) {
+  const int s = blockIdx.z;
+  if (s >= a.s_active) return;
+  const LevelView& L = a.L;
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+  if (i >= L.ld || j >= L.nyn) return;
+  const size_t k = (size_t)j * L.ld + i, so = (size_t)s * a.sstride;
+  const double im = L.invm[k];
+  Lp[so + k] = im != 0.0 ? f * MU[so + k] / im : 0.0;
+  LW[so + k] = 0.0;
+}
+
+// Lambda_m from Lambda_m+1 (L1) and Lambda_m+2 (L2, NULL: 0), m = p-1 .. 1;
+// lw -= c2_m Lambda_m+1.  For m = 0 only lw -= c1 Lambda_1 (Lout unused).
+__global__ __launch_bounds__(256) void k_adj_rev(AdjArgs a, int m, const double* __restrict__ L1,
+                                                 const double* __restrict__ L2, double* __restrict__ Lout,
+                                                 double* __restrict__ LW) {
+  const int s = blockIdx.z;
+  if (s >= a.s_active) return;
+  const LevelView& L = a.L;
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+  if (i >= L.nxn || j >= L.nyn) return;
+  const size_t k = (size_t)j * L.ld + i, so = (size_t)s * a.sstride;
+  const uint8_t f = L.flags[k];
+  if (!(f & F_DOF)) {
+    if (m > 0) Lout[so + k] = 0.0;
+    return;
+  }
+  const double* cf = a.coef + (size_t)s * (L.p + 1);
+  const double* __restrict__ l1 = L1 + so;
+  const double lam = l1[k];
+  if (m == 0) {
+    LW[so + k] -= cf[1] * lam;
+    return;
+  }
+  const double c2 = cf[1 + m];
+  LW[so + k] -= c2 * lam;
+  double kt = 0.0;   // (K (Lambda / m))_k at P rows
+  if (f & F_P) {
+    double cE, cW, cN, cS;
+    edge_coefs(L, a.kappa + (size_t)s * L.nb, i, j, cE, cW, cN, cS);
+    auto t = [&](size_t kk) { return l1[kk] * L.invm[kk]; };   // invm = 0 on Dirichlet nodes
+    const double ti = t(k);
+    kt = cE * (ti - t(k + 1)) + cW * (ti - t(k - 1)) + cN * (ti - t(k + L.ld)) + cS * (ti - t(k - L.ld));
+  }
+  const double bm = L.beta[m];
+  const double bm1 = (m + 1 < L.p) ? L.beta[m + 1] : 0.0;
+  const double l2 = L2 ? L2[so + k] : 0.0;
+  Lout[so + k] = (1.0 + bm) * lam - c2 * kt - bm1 * l2;
+}
+
+// Per-cell accumulation of dQ/dkappa_cell over the derivative pairs of one step.
+struct ContractArgs {
+  const double* D[kMaxAdjP + 1];     // D[m] = d_m, m = 1..p (D[0] unused: d_0 = 0)
+  const double* Lam[kMaxAdjP + 2];   // Lam[m] = Lambda_m, m = 1..p
+};
+
+__global__ __launch_bounds__(256) void k_adj_contract(AdjArgs a, ContractArgs c,
+                                                      const double* __restrict__ Y,
+                                                      const double* __restrict__ LW,
+                                                      double* __restrict__ G) {
+  const int s = blockIdx.z;
+  if (s >= a.s_active) return;
+  const LevelView& L = a.L;
+  const int ia = blockIdx.x * BX + threadIdx.x, jb = blockIdx.y * BY + threadIdx.y;
+  if (ia >= L.nxn - 1 || jb >= L.nyn - 1) return;
+  const size_t kc = (size_t)jb * L.ld + ia;          // cell (ia, jb)
+  if (L.cblk[kc] == 255) return;
+  const size_t so = (size_t)s * a.sstride;
+  const size_t n00 = kc, n10 = kc + 1, n01 = kc + L.ld, n11 = kc + L.ld + 1;
+  const double gx = L.hy[jb] * L.inv2hx[ia];   // bottom and top legs
+  const double gy = L.hx[ia] * L.inv2hy[jb];   // left and right legs
+  const double im00 = L.invm[n00], im10 = L.invm[n10], im01 = L.invm[n01], im11 = L.invm[n11];
+  const bool p00 = L.flags[n00] & F_P, p10 = L.flags[n10] & F_P, p01 = L.flags[n01] & F_P,
+             p11 = L.flags[n11] & F_P;
+  const double* __restrict__ y = Y + so;
+  const double y00 = y[n00], y10 = y[n10], y01 = y[n01], y11 = y[n11];
+  const double* cf = a.coef + (size_t)s * (L.p + 1);
+  auto side = [&](double a0, double a1, double a2, double a3, double b0, double b1, double b2,
+                  double b3) {
+    // corners 0 = (ia,jb), 1 = (ia+1,jb), 2 = (ia,jb+1), 3 = (ia+1,jb+1); a already divided by m
+    return gx * ((a0 - a1) * (b0 - b1) + (a2 - a3) * (b2 - b3)) +
+           gy * ((a0 - a2) * (b0 - b2) + (a1 - a3) * (b1 - b3));
+  };
+  double acc = 0.0;
+  // (lw, (I - P) y)
+  {
+    const double* lw = LW + so;
+    acc += side(lw[n00] * im00, lw[n10] * im10, lw[n01] * im01, lw[n11] * im11, p00 ? 0.0 : y00,
+                p10 ? 0.0 : y10, p01 ? 0.0 : y01, p11 ? 0.0 : y11);
+  }
+  // (-c1 Lambda_1, P y) and (-c2_m Lambda_m+1, P (y + d_m)), m = 1..p-1
+  for (int m = 0; m < L.p; ++m) {
+    const double cm = m == 0 ? cf[1] : cf[1 + m];
+    const double* la = c.Lam[m + 1] + so;
+    const double* dm = m == 0 ? nullptr : c.D[m] + so;
+    const double q00 = p00 ? y00 + (dm ? dm[n00] : 0.0) : 0.0;
+    const double q10 = p10 ? y10 + (dm ? dm[n10] : 0.0) : 0.0;
+    const double q01 = p01 ? y01 + (dm ? dm[n01] : 0.0) : 0.0;
+    const double q11 = p11 ? y11 + (dm ? dm[n11] : 0.0) : 0.0;
+    acc -= cm * side(la[n00] * im00, la[n10] * im10, la[n01] * im01, la[n11] * im11, q00, q10, q01, q11);
+  }
+  G[so + kc] += acc;
+}
+
+// mu_N = M^-1 w into buffer N_s % 2, 0 into the other.
+__global__ __launch_bounds__(256) void k_adj_mu_init(AdjArgs a, const int* __restrict__ nsteps,
+                                                     double* __restrict__ B0, double* __restrict__ B1) {
+  const int s = blockIdx.z;
+  const LevelView& L = a.L;
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
+  if (i >= L.ld || j >= L.nyn) return;
+  const size_t k = (size_t)j * L.ld + i, so = (size_t)s * a.sstride;
+  const double v = L.qoiw[k] * L.invm[k];
+  double* a0 = (nsteps[s] & 1) ? B1 : B0;
+  double* a1 = (nsteps[s] & 1) ? B0 : B1;
+  a0[so + k] = v;
+  a1[so + k] = 0.0;
+}
+
+// dQ/dg_b = 2 kappa_b sum over the cells of block b, times dLdQ[s]; one workgroup per sample.
+__global__ __launch_bounds__(256) void k_adj_blocks(AdjArgs a, const double* __restrict__ G,
+                                                    const double* __restrict__ dldq, int s_base,
+                                                    double* __restrict__ out) {
+  const int s = blockIdx.x;
+  const LevelView& L = a.L;
+  __shared__ double part[256];
+  const double* g = G + (size_t)s * a.sstride;
+  for (int b = 0; b < L.nb; ++b) {
+    double acc = 0.0;
+    for (int c = threadIdx.x; c < (L.nyn - 1) * L.ld; c += blockDim.x)
+      if (L.cblk[c] == b) acc += g[c];
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0)
+      out[(size_t)(s_base + s) * L.nb + b] = 2.0 * a.kappa[(size_t)s * L.nb + b] * part[0] * dldq[s];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill(double* __restrict__ p, size_t n, double v) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+
+}  // namespace
+
+// Backward solve of one sub-batch (samples already sorted by decreasing n_steps,
+// device tables staged).  Writes Q (sorted order) and dQ/dg * dLdQ rows
+// s_base .. s_base+n-1 of out (sorted order).
+lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_kappa,
+                          const double* d_coef, const int* d_nsteps, const double* d_x0, double width,
+                          const std::vector<int>& h_nsteps, int K, const double* d_dldq, double* d_Q,
+                          double* d_out, int s_base) {
+  const LevelView Lv = lv.view();
+  const int p = lv.H.p;
+  const size_t ss = lv.nodes;
+  const size_t one = (size_t)n * ss;            // doubles in one batch-wide state array
+  const int maxn = h_nsteps[0];
+  const int n_ck = (maxn + K - 1) / K;
+  // workspace layout (doubles): checkpoints 2*n_ck, segment K+1, d 1..p, Lambda 1..p+1 (+1 spare),
+  // w, lw, mu 2, G, state 2
+  const size_t n_arrays = 2 * (size_t)n_ck + (K + 1) + p + (p + 2) + 2 + 2 + 1;
+  LTS_HIP(c, c->adj.ensure(n_arrays * one * sizeof(double)));
+  double* base = c->adj.as<double>();
+  auto arr = [&](size_t idx) { return base + idx * one; };
+  size_t at = 0;
+  const size_t ck0 = at; at += 2 * (size_t)n_ck;
+  const size_t seg0 = at; at += K + 1;
+  const size_t d0 = at; at += p;          // d_m at d0 + m - 1
+  const size_t l0 = at; at += p + 2;      // Lambda_m at l0 + m - 1, m = 1..p+1
+  const size_t iw = at++, ilw = at++, imu0 = at++, imu1 = at++, iG = at++;
+  (void)ilw;
+
+  AdjArgs a;
+  a.L = Lv;
+  a.kappa = d_kappa;
+  a.coef = d_coef;
+  a.sstride = ss;
+  const dim3 blk(BX, BY);
+  auto grid = [&](int cols, int nz) { return dim3((cols + BX - 1) / BX, (Lv.nyn + BY - 1) / BY, nz); };
+  // zero the whole workspace region used (cells of G, Lambda spare, ...)
+  {
+    const size_t tot = at * one;
+    k_fill<<<(unsigned)((tot + 255) / 256), 256, 0, c->stream>>>(base, tot, 0.0);
+  }
+  // ---- forward with checkpoints: states in the two state buffers
+  LTS_HIP(c, c->st0.ensure(one * sizeof(double)));
+  LTS_HIP(c, c->st1.ensure(one * sizeof(double)));
+  double* B[2] = {c->st0.as<double>(), c->st1.as<double>()};
+  lts_status r = init_states(c, lv, n, d_x0, width, B[0], B[1]);
+  if (r != LTS_OK) return r;
+  const size_t bytes1 = one * sizeof(double);
+  int active = n;
+  for (int step = 0; step < maxn; ++step) {
+    if (step % K == 0) {
+      // pair (u_step, u_step+1): copy u_step now, u_step+1 after the step
+      LTS_HIP(c, hipMemcpyAsync(arr(ck0 + 2 * (step / K)), B[step & 1], bytes1, hipMemcpyDeviceToDevice, c->stream));
+    }
+    while (active > 0 && h_nsteps[active - 1] <= step) --active;
+    r = launch_step(c, lv, lv.tiling, d_kappa, d_coef, B[step & 1], B[(step + 1) & 1], ss, 0, active,
+                    step == 0, c->stream);
+    if (r != LTS_OK) return r;
+    if (step % K == 0)
+      LTS_HIP(c, hipMemcpyAsync(arr(ck0 + 2 * (step / K) + 1), B[(step + 1) & 1], bytes1,
+                                hipMemcpyDeviceToDevice, c->stream));
+  }
+  r = qoi_device(c, lv, n, d_nsteps, B[0], B[1], d_Q);
+  if (r != LTS_OK) return r;
+
+  // ---- backward
+  double* MU[2] = {arr(imu0), arr(imu1)};
+  k_adj_mu_init<<<grid(Lv.ld, n), blk, 0, c->stream>>>(a, d_nsteps, MU[0], MU[1]);
+  ContractArgs ca;
+  for (int m = 1; m <= p; ++m) ca.D[m] = arr(d0 + m - 1);
+  ca.D[0] = nullptr;
+  for (int m = 1; m <= p + 1; ++m) ca.Lam[m] = arr(l0 + m - 1);
+  ca.Lam[0] = nullptr;
+  for (int k0 = (n_ck - 1) * K; k0 >= 0; k0 -= K) {
+    const int k1 = std::min(k0 + K - 1, maxn - 1);
+    // recompute the segment u_k0 .. u_k1 for every sample that reaches k0
+    int seg_active = 0;
+    while (seg_active < n && h_nsteps[seg_active] > k0) ++seg_active;
+    if (seg_active == 0) continue;
+    const size_t sb = (size_t)seg_active * ss * sizeof(double);
+    LTS_HIP(c, hipMemcpyAsync(arr(seg0), arr(ck0 + 2 * (k0 / K)), sb, hipMemcpyDeviceToDevice, c->stream));
+    LTS_HIP(c, hipMemcpyAsync(arr(seg0 + 1), arr(ck0 + 2 * (k0 / K) + 1), sb, hipMemcpyDeviceToDevice, c->stream));
+    for (int jn = k0 + 1; jn < k1; ++jn) {
+      int act = 0;
+      while (act < n && h_nsteps[act] > jn) ++act;
+      if (act == 0) break;
+      const size_t ab = (size_t)act * ss * sizeof(double);
+      double* dst = arr(seg0 + (jn - k0) + 1);
+      LTS_HIP(c, hipMemcpyAsync(dst, arr(seg0 + (jn - k0) - 1), ab, hipMemcpyDeviceToDevice, c->stream));
+      r = launch_step(c, lv, lv.tiling, d_kappa, d_coef, arr(seg0 + (jn - k0)), dst, ss, 0, act, 0, c->stream);
+      if (r != LTS_OK) return r;
+    }
+    for (int nn = k1; nn >= k0; --nn) {
+      int act = 0;
+      while (act < n && h_nsteps[act] - 1 >= nn) ++act;
+      if (act == 0) continue;
+      a.s_active = act;
+      const double* y = arr(seg0 + (nn - k0));
+      const double f = nn >= 1 ? 2.0 : 1.0;
+      double* mu1 = MU[(nn + 1) & 1];   // mu_{n+1}
+      double* mu2 = MU[nn & 1];         // mu_{n+2} (overwritten by mu_n)
+      // forward substeps of y
+      k_adj_w<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, y, arr(iw));
+      for (int m = 0; m < p; ++m)
+        k_adj_sub<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, m, y, m == 0 ? nullptr : arr(d0 + m - 1),
+                                                            m <= 1 ? nullptr : arr(d0 + m - 2), arr(iw),
+                                                            arr(d0 + m));
+      // reverse sweep
+      k_adj_lam_init<<<grid(Lv.ld, act), blk, 0, c->stream>>>(a, f, mu1, arr(l0 + p - 1), arr(ilw));
+      for (int m = p - 1; m >= 0; --m)
+        k_adj_rev<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, m, arr(l0 + m), m + 1 < p ? arr(l0 + m + 1) : nullptr,
+                                                            m > 0 ? arr(l0 + m - 1) : nullptr, arr(ilw));
+      k_adj_contract<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, ca, y, arr(ilw), arr(iG));
+      // mu_n = 2 R mu_{n+1} - mu_{n+2}
+      if (nn >= 1) {
+        r = launch_step(c, lv, lv.tiling, d_kappa, d_coef, mu1, mu2, ss, 0, act, 0, c->stream);
+        if (r != LTS_OK) return r;
+      }
+    }
+  }
+  LTS_HIP(c, hipGetLastError());
+  k_adj_blocks<<<n, 256, 0, c->stream>>>(a, arr(iG), d_dldq, s_base, d_out);
+  LTS_HIP(c, hipGetLastError());
+  return LTS_OK;
+}
+
+}  // namespace lts

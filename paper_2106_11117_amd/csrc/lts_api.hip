@@ -418,6 +418,58 @@ lts_status lts_forward_coupled(lts_ctx c, int32_t lf, int32_t lc, const lts_samp
   return LTS_OK;
 }
 
+lts_status lts_backward(lts_ctx c, int32_t level, const lts_samples* S, const double* dLdQ, int32_t K,
+                        double* Q_out, double* dQ_dg_out) {
+  if (!c) return LTS_ERR_ARG;
+  c->err.clear();
+  const DevLevel* lv = get_level(c, level);
+  if (!lv) return arg_fail(c, "no such level");
+  if (K < 1 || K > 4096) return arg_fail(c, "K_ckpt must be in 1..4096");
+  if (lv->H.p > kMaxAdjP) return arg_fail(c, "p too large for the adjoint");
+  if (S && S->n > 0 && (!dLdQ || !dQ_dg_out)) return arg_fail(c, "NULL dLdQ / output");
+  Staged st;
+  lts_status r = stage(c, *lv, S, st);
+  if (r != LTS_OK) return r;
+  const int n = st.n, nb = lv->H.n_blocks;
+  if (n == 0) return LTS_OK;
+  LTS_HIP(c, hipSetDevice(c->device));
+  std::vector<double> dl(n), dls(n);
+  LTS_HIP(c, hipMemcpy(dl.data(), dLdQ, (size_t)n * 8,
+                       S->ptr_kind == LTS_PTR_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+  for (int t = 0; t < n; ++t) dls[t] = dl[st.perm[t]];
+  if ((r = upload_staged(c, st)) != LTS_OK) return r;
+  LTS_HIP(c, c->dldq.ensure((size_t)n * 8));
+  LTS_HIP(c, c->gout.ensure((size_t)n * nb * 8));
+  LTS_HIP(c, hipMemcpyAsync(c->dldq.p, dls.data(), (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
+  // sub-batches sized so the checkpoint workspace stays below ~48 GiB
+  const int n_ck = (st.nsteps[0] + K - 1) / K;
+  const double per_sample = (2.0 * n_ck + K + 2.0 * lv->H.p + 8.0) * (double)lv->nodes * 8.0;
+  const int chunk = std::max(1, std::min(n, (int)(48.0 * (1ull << 30) / per_sample)));
+  const int p1 = lv->H.p + 1;
+  for (int s0 = 0; s0 < n; s0 += chunk) {
+    const int m = std::min(chunk, n - s0);
+    std::vector<int> ns(st.nsteps.begin() + s0, st.nsteps.begin() + s0 + m);
+    r = adjoint_device(c, *lv, m, c->kappa.as<double>() + (size_t)s0 * nb, c->coef.as<double>() + (size_t)s0 * p1,
+                       c->nsteps.as<int>() + s0, c->x0.as<double>() + 2 * (size_t)s0, S->width, ns, K,
+                       c->dldq.as<double>() + s0, c->Qd.as<double>() + s0, c->gout.as<double>(), s0);
+    if (r != LTS_OK) return r;
+  }
+  std::vector<double> g((size_t)n * nb), gs((size_t)n * nb);
+  LTS_HIP(c, hipMemcpyAsync(gs.data(), c->gout.p, gs.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  LTS_HIP(c, hipStreamSynchronize(c->stream));
+  for (int t = 0; t < n; ++t)
+    std::copy(&gs[(size_t)t * nb], &gs[(size_t)t * nb] + nb, &g[(size_t)st.perm[t] * nb]);
+  const hipMemcpyKind k = S->ptr_kind == LTS_PTR_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
+  LTS_HIP(c, hipMemcpy(dQ_dg_out, g.data(), g.size() * 8, k));
+  for (double v : g)
+    if (!std::isfinite(v)) {
+      c->err = "non-finite gradient (unstable sample)";
+      return LTS_ERR_UNSTABLE;
+    }
+  if (Q_out) return finish_Q(c, st, S->ptr_kind, Q_out);
+  return LTS_OK;
+}
+
 lts_status lts_moments(lts_ctx c, const double* x, int32_t n, int32_t ptr_kind, double* out) {
   if (!c) return LTS_ERR_ARG;
   c->err.clear();

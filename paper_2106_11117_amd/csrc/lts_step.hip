@@ -136,8 +136,6 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
   LTS_HIP(c, c->st1.ensure(bytes));
   double* B[2] = {c->st0.as<double>(), c->st1.as<double>()};
   const int maxn = h_nsteps[0];
-  const dim3 blk(TBX, TBY);
-  const int gx = (L.ld + TBX - 1) / TBX, gy = (L.nyn + TBY - 1) / TBY;
 
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
   if (c->timing) {
@@ -149,16 +147,10 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
     e0 = c->ev_pool[0]; e1 = c->ev_pool[1]; e2 = c->ev_pool[2]; e3 = c->ev_pool[3];
     LTS_HIP(c, hipEventRecord(e0, c->stream));
   }
-  constexpr int kMaxZ = 32768;
-  for (int z0 = 0; z0 < n; z0 += kMaxZ) {
-    const int nz = std::min(kMaxZ, n - z0);
-    k_init<<<dim3(gx, gy, nz), blk, 0, c->stream>>>(L, d_x0 + 2 * z0, width, B[0] + z0 * sstride,
-                                                     B[1] + z0 * sstride, sstride);
-  }
-  LTS_HIP(c, hipGetLastError());
+  lts_status r = init_states(c, lv, n, d_x0, width, B[0], B[1]);
+  if (r != LTS_OK) return r;
   if (c->timing) LTS_HIP(c, hipEventRecord(e1, c->stream));
   int64_t launches = 0;
-  lts_status r;
   if (per_sample) {
     for (int s = 0; s < n; ++s)
       for (int step = 0; step < h_nsteps[s]; ++step) {
@@ -179,8 +171,7 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
   }
   LTS_HIP(c, hipGetLastError());
   if (c->timing) LTS_HIP(c, hipEventRecord(e2, c->stream));
-  k_qoi<<<n, 256, 0, c->stream>>>(L, d_nsteps, B[0], B[1], sstride, lv.nodes, d_Q);
-  LTS_HIP(c, hipGetLastError());
+  if ((r = qoi_device(c, lv, n, d_nsteps, B[0], B[1], d_Q)) != LTS_OK) return r;
   double dofu = 0.0, algb = 0.0;
   const double per_step = (double)(lv.H.n_dof - lv.H.n_P) + (double)lv.H.p * lv.H.n_P;
   for (int s = 0; s < n; ++s) {
@@ -203,6 +194,30 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
   return LTS_OK;
 }
 
+lts_status init_states(lts_ctx c, const DevLevel& lv, int n, const double* d_x0, double width, double* B0,
+                       double* B1) {
+  const LevelView L = lv.view();
+  const size_t sstride = lv.nodes;
+  const dim3 blk(TBX, TBY);
+  const int gx = (L.ld + TBX - 1) / TBX, gy = (L.nyn + TBY - 1) / TBY;
+  constexpr int kMaxZ = 32768;
+  for (int z0 = 0; z0 < n; z0 += kMaxZ) {
+    const int nz = std::min(kMaxZ, n - z0);
+    k_init<<<dim3(gx, gy, nz), blk, 0, c->stream>>>(L, d_x0 + 2 * z0, width, B0 + z0 * sstride,
+                                                     B1 + z0 * sstride, sstride);
+  }
+  LTS_HIP(c, hipGetLastError());
+  return LTS_OK;
+}
+
+lts_status qoi_device(lts_ctx c, const DevLevel& lv, int n, const int* d_nsteps, const double* B0,
+                      const double* B1, double* d_Q) {
+  if (n <= 0) return LTS_OK;
+  k_qoi<<<n, 256, 0, c->stream>>>(lv.view(), d_nsteps, B0, B1, lv.nodes, lv.nodes, d_Q);
+  LTS_HIP(c, hipGetLastError());
+  return LTS_OK;
+}
+
 lts_status moments_device(lts_ctx c, const double* d_x, int n, double* d_out3) {
   k_moments<<<1, 1024, 0, c->stream>>>(d_x, n, d_out3);
   LTS_HIP(c, hipGetLastError());
@@ -216,18 +231,6 @@ extern "C" {
 lts_status lts_batch_run(lts_ctx c, const lts_job*, int32_t, int32_t, double*) {
   if (!c) return LTS_ERR_ARG;
   c->err = "lts_batch_run: not available in this build";
-  return LTS_ERR_STATE;
-}
-
-lts_status lts_backward(lts_ctx c, int32_t, const lts_samples*, const double*, int32_t, double*, double*) {
-  if (!c) return LTS_ERR_ARG;
-  c->err = "lts_backward: not available in this build";
-  return LTS_ERR_STATE;
-}
-
-lts_status lts_mlmc(lts_ctx c, const lts_mlmc_opts*, lts_mlmc_result*) {
-  if (!c) return LTS_ERR_ARG;
-  c->err = "lts_mlmc: not available in this build";
   return LTS_ERR_STATE;
 }
 
