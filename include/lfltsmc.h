@@ -141,6 +141,10 @@ typedef struct {
   int32_t p, n_blocks;
   double h, nu;
   double delta, omega;            /* stabilized Chebyshev constants (Sec. 3.3) */
+  int32_t tile_x, tile_y;         /* fine-tile shape in use (grid nodes) */
+  int32_t tile_rect, tuned;       /* rectangular LDS region; chosen by the autotuner */
+  double halo_ratio;              /* nodes of all fine-tile regions / |F+| */
+  double tuned_ms;                /* measured step time per sample of the tuned tiling */
 } lts_level_info;
 
 /* Sizes and constants of a level.  Errors: LTS_ERR_ARG. */
@@ -261,6 +265,12 @@ enum { LTS_BATCH_GRAPH = 1 };     /* capture the step loop into HIP graphs and r
  * flags: 0 or LTS_BATCH_GRAPH.  Errors as lts_forward. */
 lts_status lts_batch_run(lts_ctx ctx, const lts_job* jobs, int32_t n_jobs, int32_t flags,
                          double* Q_out);
+
+/* Autotuner: time the candidate fine-tile shapes of `level` on a synthetic
+ * batch and keep the fastest for all later solves on the level (the choice is
+ * cached per level shape for the life of the process).  lts_batch_run tunes
+ * levels that are not tuned yet.  Errors: LTS_ERR_ARG, LTS_ERR_HIP. */
+lts_status lts_autotune(lts_ctx ctx, int32_t level);
 
 /* ------------------------------------------------------------------------ */
 /* Reductions (Sec. 2.2: estimator and level variance)                       */

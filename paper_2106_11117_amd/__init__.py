@@ -191,6 +191,11 @@ class Context:
         self.levels.append(lid.value)
         return lid.value
 
+    def autotune(self, level) -> dict:
+        """Measure the candidate fine-tile shapes of `level` and keep the fastest."""
+        self._c(self.lib.lts_autotune(self.h, level))
+        return self.level_info(level)
+
     def level_info(self, level) -> dict:
         info = _lib.LevelInfo()
         self._c(self.lib.lts_level_info_get(self.h, level, C.byref(info)))

@@ -47,7 +47,9 @@ class LevelInfo(C.Structure):
     _fields_ = [("nx_nodes", C.c_int32), ("ny_nodes", C.c_int32), ("n_dof", C.c_int32),
                 ("n_P", C.c_int32), ("n_Fplus", C.c_int32), ("p", C.c_int32),
                 ("n_blocks", C.c_int32), ("h", C.c_double), ("nu", C.c_double),
-                ("delta", C.c_double), ("omega", C.c_double)]
+                ("delta", C.c_double), ("omega", C.c_double), ("tile_x", C.c_int32),
+                ("tile_y", C.c_int32), ("tile_rect", C.c_int32), ("tuned", C.c_int32),
+                ("halo_ratio", C.c_double), ("tuned_ms", C.c_double)]
 
 
 class SampleRule(C.Structure):
@@ -106,6 +108,7 @@ SIGNATURES = [
                                         C.POINTER(Samples), C.c_int32, C.c_void_p, C.c_void_p,
                                         C.c_void_p]),
     ("lts_batch_run", C.c_int32, [C.c_void_p, C.POINTER(Job), C.c_int32, C.c_int32, C.c_void_p]),
+    ("lts_autotune", C.c_int32, [C.c_void_p, C.c_int32]),
     ("lts_moments", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, dp]),
     ("lts_backward", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Samples), C.c_void_p, C.c_int32,
                                  C.c_void_p, C.c_void_p]),

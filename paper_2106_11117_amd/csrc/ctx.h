@@ -50,6 +50,8 @@ struct TilingDev {
 struct DevLevel {
   HostLevel H;
   TilingDev tiling;     // fused-step tiling in use
+  bool tuned = false;   // tiling chosen by measurement (autotuner)
+  double tuned_ms = 0;  // measured step time of the chosen tiling
   int ld = 0;           // row pitch (elements) of node/cell arrays and states
   size_t nodes = 0;     // nyn * ld
   DevBuf hx, hy, inv2hx, inv2hy, x, y, cblk, flags, invm, qoiw, beta, beta_half;
@@ -82,6 +84,10 @@ struct lts_ctx_s {
   std::vector<std::unique_ptr<lts::DevLevel>> levels;
   // workspace
   lts::DevBuf kappa, coef, nsteps, x0, Qd, st0, st1, wbuf, qa, qb, red, adj, dldq, gout;
+  // batched form: per-job tables, states, job records, captured graph
+  lts::DevBuf b_tab, b_states, b_jobs, b_Q;
+  hipGraphExec_t graph = nullptr;
+  std::vector<uint64_t> graph_key;
   bool timing = false;
   lts_timing last{};
   std::vector<hipEvent_t> ev_pool;
@@ -105,6 +111,17 @@ inline lts_status arg_fail(lts_ctx c, const std::string& m) {
   c->err = m;
   return LTS_ERR_ARG;
 }
+
+// Host copies of a sample batch (validated, sorted by decreasing n_steps) plus
+// the per-sample step coefficient tables.
+struct Staged {
+  int n = 0;
+  std::vector<double> kappa, x0, dt, coef;
+  std::vector<int> nsteps;
+  std::vector<int> perm;   // sorted position -> caller index
+};
+lts_status stage_samples(lts_ctx c, const DevLevel& lv, const lts_samples* S, Staged& st);
+lts_status upload_staged(lts_ctx c, const Staged& st);
 
 // Forward solve of `n` samples on level `lv` (device arrays already staged):
 // implemented in the step source.
@@ -135,8 +152,23 @@ lts_status upload_tiling(lts_ctx c, const TilingHost& T, TilingDev& D);
 // Tile-size candidates (TX, TY) tried for the fused step, in order.
 const std::vector<std::pair<int, int>>& tile_candidates();
 
+// Grid origins tried for a tile size (0 and aligned to the F+ bounding box).
+std::vector<std::pair<int, int>> tile_origins(const HostLevel& H, int TX, int TY);
+
 // Choose and upload a default tiling (smallest region overhead that fits).
 lts_status default_tiling(lts_ctx c, DevLevel& lv);
+
+// Choose the tiling of a level by timing candidate tilings (cached per level shape).
+lts_status autotune_level(lts_ctx c, DevLevel& lv);
+
+// One batched step launch over several jobs (see lts_fused.hip).
+struct StepArgs;
+lts_status launch_multi_step(lts_ctx c, const StepArgs* d_jobs, const std::vector<const TilingDev*>& T,
+                             const std::vector<int>& active, int step, hipStream_t stream);
+// Writes the static step record of one job (step_args_size() bytes) to `out`.
+void job_record(const DevLevel& lv, const TilingDev& T, const double* d_kappa, const double* d_coef,
+                double* B0, double* B1, size_t sstride, void* out);
+size_t step_args_size();
 
 // One fused step launch for samples s0 .. s0+active-1 (sorted order).
 lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const double* d_kappa,

@@ -18,6 +18,7 @@ constexpr int kRectCap = 7992;                      // LDS slots of one rectangu
 constexpr int kPitch = 96;                          // LDS row pitch of the rectangle (slots)
 constexpr int kCoarseThreads = 256;                 // coarse workgroup: 4 wavefronts, one item each
 constexpr int kMaxAdjP = 64;                        // largest p supported by the adjoint
+constexpr int kMaxJobs = 32;                        // jobs of one batched launch
 
 struct TilingHost {
   int TX = 0, TY = 0;

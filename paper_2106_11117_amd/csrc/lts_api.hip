@@ -11,78 +11,10 @@
 
 using namespace lts;
 
-namespace {
-
-constexpr int kPitchAlign = 8;  // row pitch multiple (doubles): 64-byte rows
-
-lts_status upload_level(lts_ctx c, DevLevel& D) {
-  const HostLevel& H = D.H;
-  D.ld = (H.nxn + kPitchAlign - 1) / kPitchAlign * kPitchAlign;
-  D.nodes = (size_t)H.nyn * D.ld;
-  std::vector<double> hx(H.nxn, 0.0), hy(H.nyn, 0.0), ihx(H.nxn, 0.0), ihy(H.nyn, 0.0);
-  for (int i = 0; i + 1 < H.nxn; ++i) {
-    hx[i] = H.x[i + 1] - H.x[i];
-    ihx[i] = 1.0 / (2.0 * hx[i]);
-  }
-  for (int j = 0; j + 1 < H.nyn; ++j) {
-    hy[j] = H.y[j + 1] - H.y[j];
-    ihy[j] = 1.0 / (2.0 * hy[j]);
-  }
-  std::vector<uint8_t> cb(D.nodes, 255), fl(D.nodes, 0);
-  std::vector<double> im(D.nodes, 0.0), qw(D.nodes, 0.0);
-  for (int b = 0; b < H.nyc; ++b)
-    for (int a = 0; a < H.nxc; ++a) {
-      const int32_t blk = H.block[(size_t)b * H.nxc + a];
-      cb[(size_t)b * D.ld + a] = blk < 0 ? 255 : (uint8_t)blk;
-    }
-  for (int j = 0; j < H.nyn; ++j)
-    for (int i = 0; i < H.nxn; ++i) {
-      const size_t k = (size_t)j * H.nxn + i, kd = (size_t)j * D.ld + i;
-      fl[kd] = H.flags[k];
-      if (H.flags[k] & LTS_NODE_DOF) im[kd] = 1.0 / H.mass[k];
-      qw[kd] = H.qoiw[k];
-    }
-  std::vector<double> bt(std::max(1, H.p), 0.0), bh(std::max(1, H.p), 0.0);
-  for (int k = 1; k < H.p; ++k) {
-    bt[k] = H.beta[k];
-    bh[k] = H.beta_half[k];
-  }
-  auto put = [&](DevBuf& b, const void* src, size_t bytes) -> hipError_t {
-    hipError_t e = b.ensure(std::max<size_t>(bytes, 8));
-    if (e != hipSuccess) return e;
-    return hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice);
-  };
-  hipError_t e;
-  if ((e = put(D.hx, hx.data(), hx.size() * 8)) != hipSuccess ||
-      (e = put(D.hy, hy.data(), hy.size() * 8)) != hipSuccess ||
-      (e = put(D.inv2hx, ihx.data(), ihx.size() * 8)) != hipSuccess ||
-      (e = put(D.inv2hy, ihy.data(), ihy.size() * 8)) != hipSuccess ||
-      (e = put(D.x, H.x.data(), H.x.size() * 8)) != hipSuccess ||
-      (e = put(D.y, H.y.data(), H.y.size() * 8)) != hipSuccess ||
-      (e = put(D.cblk, cb.data(), cb.size())) != hipSuccess ||
-      (e = put(D.flags, fl.data(), fl.size())) != hipSuccess ||
-      (e = put(D.invm, im.data(), im.size() * 8)) != hipSuccess ||
-      (e = put(D.qoiw, qw.data(), qw.size() * 8)) != hipSuccess ||
-      (e = put(D.beta, bt.data(), bt.size() * 8)) != hipSuccess ||
-      (e = put(D.beta_half, bh.data(), bh.size() * 8)) != hipSuccess)
-    return hip_fail(c, e, "upload level");
-  return LTS_OK;
-}
-
-const DevLevel* get_level(lts_ctx c, int32_t level) {
-  if (!c || level < 0 || level >= (int32_t)c->levels.size()) return nullptr;
-  return c->levels[level].get();
-}
+namespace lts {
 
 // Host copies of a sample batch (validated) plus the per-sample step tables.
-struct Staged {
-  int n = 0;
-  std::vector<double> kappa, x0, dt, coef;
-  std::vector<int> nsteps;
-  std::vector<int> perm;   // sorted position -> caller index (decreasing n_steps)
-};
-
-lts_status stage(lts_ctx c, const DevLevel& lv, const lts_samples* S, Staged& st) {
+lts_status stage_samples(lts_ctx c, const DevLevel& lv, const lts_samples* S, Staged& st) {
   if (!S) return arg_fail(c, "samples is NULL");
   if (S->n < 0) return arg_fail(c, "samples.n must be >= 0");
   if (S->ptr_kind != LTS_PTR_HOST && S->ptr_kind != LTS_PTR_DEVICE)
@@ -152,6 +84,71 @@ lts_status upload_staged(lts_ctx c, const Staged& st) {
   return LTS_OK;
 }
 
+}  // namespace lts
+
+namespace {
+
+constexpr int kPitchAlign = 8;  // row pitch multiple (doubles): 64-byte rows
+
+lts_status upload_level(lts_ctx c, DevLevel& D) {
+  const HostLevel& H = D.H;
+  D.ld = (H.nxn + kPitchAlign - 1) / kPitchAlign * kPitchAlign;
+  D.nodes = (size_t)H.nyn * D.ld;
+  std::vector<double> hx(H.nxn, 0.0), hy(H.nyn, 0.0), ihx(H.nxn, 0.0), ihy(H.nyn, 0.0);
+  for (int i = 0; i + 1 < H.nxn; ++i) {
+    hx[i] = H.x[i + 1] - H.x[i];
+    ihx[i] = 1.0 / (2.0 * hx[i]);
+  }
+  for (int j = 0; j + 1 < H.nyn; ++j) {
+    hy[j] = H.y[j + 1] - H.y[j];
+    ihy[j] = 1.0 / (2.0 * hy[j]);
+  }
+  std::vector<uint8_t> cb(D.nodes, 255), fl(D.nodes, 0);
+  std::vector<double> im(D.nodes, 0.0), qw(D.nodes, 0.0);
+  for (int b = 0; b < H.nyc; ++b)
+    for (int a = 0; a < H.nxc; ++a) {
+      const int32_t blk = H.block[(size_t)b * H.nxc + a];
+      cb[(size_t)b * D.ld + a] = blk < 0 ? 255 : (uint8_t)blk;
+    }
+  for (int j = 0; j < H.nyn; ++j)
+    for (int i = 0; i < H.nxn; ++i) {
+      const size_t k = (size_t)j * H.nxn + i, kd = (size_t)j * D.ld + i;
+      fl[kd] = H.flags[k];
+      if (H.flags[k] & LTS_NODE_DOF) im[kd] = 1.0 / H.mass[k];
+      qw[kd] = H.qoiw[k];
+    }
+  std::vector<double> bt(std::max(1, H.p), 0.0), bh(std::max(1, H.p), 0.0);
+  for (int k = 1; k < H.p; ++k) {
+    bt[k] = H.beta[k];
+    bh[k] = H.beta_half[k];
+  }
+  auto put = [&](DevBuf& b, const void* src, size_t bytes) -> hipError_t {
+    hipError_t e = b.ensure(std::max<size_t>(bytes, 8));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice);
+  };
+  hipError_t e;
+  if ((e = put(D.hx, hx.data(), hx.size() * 8)) != hipSuccess ||
+      (e = put(D.hy, hy.data(), hy.size() * 8)) != hipSuccess ||
+      (e = put(D.inv2hx, ihx.data(), ihx.size() * 8)) != hipSuccess ||
+      (e = put(D.inv2hy, ihy.data(), ihy.size() * 8)) != hipSuccess ||
+      (e = put(D.x, H.x.data(), H.x.size() * 8)) != hipSuccess ||
+      (e = put(D.y, H.y.data(), H.y.size() * 8)) != hipSuccess ||
+      (e = put(D.cblk, cb.data(), cb.size())) != hipSuccess ||
+      (e = put(D.flags, fl.data(), fl.size())) != hipSuccess ||
+      (e = put(D.invm, im.data(), im.size() * 8)) != hipSuccess ||
+      (e = put(D.qoiw, qw.data(), qw.size() * 8)) != hipSuccess ||
+      (e = put(D.beta, bt.data(), bt.size() * 8)) != hipSuccess ||
+      (e = put(D.beta_half, bh.data(), bh.size() * 8)) != hipSuccess)
+    return hip_fail(c, e, "upload level");
+  return LTS_OK;
+}
+
+const DevLevel* get_level(lts_ctx c, int32_t level) {
+  if (!c || level < 0 || level >= (int32_t)c->levels.size()) return nullptr;
+  return c->levels[level].get();
+}
+
 lts_status finish_Q(lts_ctx c, const Staged& st, int ptr_kind, double* Q_out) {
   const int n = st.n;
   std::vector<double> qs(n), q(n);
@@ -183,7 +180,7 @@ lts_status forward_impl(lts_ctx c, int32_t level, const lts_samples* S, int32_t 
   if (precision != LTS_FP64 && precision != LTS_FP32_STEP) return arg_fail(c, "bad precision");
   if (S && S->n > 0 && !Q_out) return arg_fail(c, "Q_out is NULL");
   Staged st;
-  lts_status r = stage(c, *lv, S, st);
+  lts_status r = stage_samples(c, *lv, S, st);
   if (r != LTS_OK) return r;
   LTS_HIP(c, hipSetDevice(c->device));
   if ((r = upload_staged(c, st)) != LTS_OK) return r;
@@ -228,6 +225,7 @@ lts_status lts_destroy(lts_ctx c) {
   if (!c) return LTS_OK;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -295,6 +293,12 @@ lts_status lts_level_info_get(lts_ctx c, int32_t level, lts_level_info* out) {
   out->nu = H.nu;
   out->delta = H.delta;
   out->omega = H.omega;
+  out->tile_x = lv->tiling.TX;
+  out->tile_y = lv->tiling.TY;
+  out->tile_rect = lv->tiling.rect ? 1 : 0;
+  out->tuned = lv->tuned ? 1 : 0;
+  out->halo_ratio = lv->tiling.halo_ratio;
+  out->tuned_ms = lv->tuned_ms;
   return LTS_OK;
 }
 
@@ -333,6 +337,8 @@ lts_status lts_rect_level_host(const lts_rect_rule* r, lts_level_info* info, dou
   info->nx_nodes = H.nxn; info->ny_nodes = H.nyn; info->n_dof = H.n_dof; info->n_P = H.n_P;
   info->n_Fplus = H.n_F; info->p = H.p; info->n_blocks = H.n_blocks; info->h = H.h; info->nu = H.nu;
   info->delta = H.delta; info->omega = H.omega;
+  info->tile_x = info->tile_y = info->tile_rect = info->tuned = 0;
+  info->halo_ratio = info->tuned_ms = 0.0;
   if (x) std::memcpy(x, H.x.data(), H.x.size() * 8);
   if (y) std::memcpy(y, H.y.data(), H.y.size() * 8);
   if (flags) std::memcpy(flags, H.flags.data(), H.flags.size());
@@ -428,7 +434,7 @@ lts_status lts_backward(lts_ctx c, int32_t level, const lts_samples* S, const do
   if (lv->H.p > kMaxAdjP) return arg_fail(c, "p too large for the adjoint");
   if (S && S->n > 0 && (!dLdQ || !dQ_dg_out)) return arg_fail(c, "NULL dLdQ / output");
   Staged st;
-  lts_status r = stage(c, *lv, S, st);
+  lts_status r = stage_samples(c, *lv, S, st);
   if (r != LTS_OK) return r;
   const int n = st.n, nb = lv->H.n_blocks;
   if (n == 0) return LTS_OK;

@@ -1,0 +1,335 @@
+// Batched form: many (level, samples) jobs advanced by shared launches, with
+// optional capture of the whole launch sequence into a HIP graph, and the
+// autotuner that picks each level's fine-tile shape by measurement.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "ctx.h"
+
+namespace lts {
+
+namespace {
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+uint64_t mix(uint64_t h, uint64_t v) {
+  h ^= v + 0x9E3779B97F4A7C15ULL + (h << 6) + (h >> 2);
+  return h;
+}
+
+uint64_t shape_key(const HostLevel& H) {
+  uint64_t h = mix(mix(mix(0, (uint64_t)H.nxn), (uint64_t)H.nyn), (uint64_t)H.p);
+  for (uint8_t f : H.flags) h = mix(h, f);
+  return h;
+}
+
+struct TuneChoice {
+  int TX, TY, ox, oy;
+  bool rect;
+  double ms;
+};
+
+std::map<uint64_t, TuneChoice>& tune_cache() {
+  static std::map<uint64_t, TuneChoice> m;
+  return m;
+}
+
+}  // namespace
+
+// Time candidate tilings of `lv` on synthetic samples (unit coefficient,
+// centred pulse, CFL step) and keep the fastest.  Candidates: every tile size
+// of tile_candidates() with the grid origin at 0 and aligned to F+, rect mode
+// where it fits, else compact mode; at most 12, ranked by region overhead.
+lts_status autotune_level(lts_ctx c, DevLevel& lv) {
+  const uint64_t key = shape_key(lv.H);
+  auto hit = tune_cache().find(key);
+  std::vector<TilingHost> cands;
+  if (hit != tune_cache().end()) {
+    TilingHost T;
+    const TuneChoice& t = hit->second;
+    if (build_tiling(lv.H, lv.ld, t.TX, t.TY, t.ox, t.oy, t.rect, T).empty()) {
+      lts_status r = upload_tiling(c, T, lv.tiling);
+      if (r != LTS_OK) return r;
+      lv.tuned = true;
+      lv.tuned_ms = t.ms;
+      return LTS_OK;
+    }
+  }
+  for (int mode = 1; mode >= 0 && cands.empty(); --mode)
+    for (auto& tc : tile_candidates())
+      for (auto& org : tile_origins(lv.H, tc.first, tc.second)) {
+        TilingHost T;
+        if (build_tiling(lv.H, lv.ld, tc.first, tc.second, org.first, org.second, mode == 1, T).empty())
+          cands.push_back(std::move(T));
+      }
+  if (cands.empty()) {
+    c->err = "no fine-tile size fits the workgroup capacity for this level";
+    return LTS_ERR_ARG;
+  }
+  std::sort(cands.begin(), cands.end(), [](const TilingHost& a, const TilingHost& b) {
+    return a.halo_ratio * (1.0 + 0.01 * a.wg_per_sample) < b.halo_ratio * (1.0 + 0.01 * b.wg_per_sample);
+  });
+  if (cands.size() > 12) cands.resize(12);
+  // synthetic batch large enough to fill the device
+  const int wg = std::max(1, cands[0].wg_per_sample);
+  const int S = std::max(4, std::min(64, (4 * 256 + wg - 1) / wg));
+  const int nb = lv.H.n_blocks, p = lv.H.p;
+  std::vector<double> kappa((size_t)S * nb, 1.0), x0((size_t)2 * S), coef((size_t)S * (p + 1));
+  const double dt = 0.2 * lv.H.h;
+  for (int s = 0; s < S; ++s) {
+    x0[2 * s] = 0.5 * (lv.H.x.front() + lv.H.x.back());
+    x0[2 * s + 1] = 0.5 * (lv.H.y.front() + lv.H.y.back());
+    step_coefficients(lv.H, dt, &coef[(size_t)s * (p + 1)]);
+  }
+  LTS_HIP(c, hipSetDevice(c->device));
+  LTS_HIP(c, c->kappa.ensure(kappa.size() * 8));
+  LTS_HIP(c, c->coef.ensure(coef.size() * 8));
+  LTS_HIP(c, c->x0.ensure(x0.size() * 8));
+  LTS_HIP(c, hipMemcpyAsync(c->kappa.p, kappa.data(), kappa.size() * 8, hipMemcpyHostToDevice, c->stream));
+  LTS_HIP(c, hipMemcpyAsync(c->coef.p, coef.data(), coef.size() * 8, hipMemcpyHostToDevice, c->stream));
+  LTS_HIP(c, hipMemcpyAsync(c->x0.p, x0.data(), x0.size() * 8, hipMemcpyHostToDevice, c->stream));
+  const size_t bytes = (size_t)S * lv.nodes * 8;
+  LTS_HIP(c, c->st0.ensure(bytes));
+  LTS_HIP(c, c->st1.ensure(bytes));
+  double* B[2] = {c->st0.as<double>(), c->st1.as<double>()};
+  hipEvent_t e0, e1;
+  LTS_HIP(c, hipEventCreate(&e0));
+  LTS_HIP(c, hipEventCreate(&e1));
+  double best = 1e300;
+  int bi = 0;
+  TilingDev Td;
+  for (size_t ci = 0; ci < cands.size(); ++ci) {
+    lts_status r = upload_tiling(c, cands[ci], Td);
+    if (r != LTS_OK) return r;
+    if ((r = init_states(c, lv, S, c->x0.as<double>(), 0.05, B[0], B[1])) != LTS_OK) return r;
+    constexpr int kWarm = 2, kTimed = 6;
+    for (int t = 0; t < kWarm + kTimed; ++t) {
+      if (t == kWarm) LTS_HIP(c, hipEventRecord(e0, c->stream));
+      r = launch_step(c, lv, Td, c->kappa.as<double>(), c->coef.as<double>(), B[t & 1], B[(t + 1) & 1],
+                      lv.nodes, 0, S, t == 0, c->stream);
+      if (r != LTS_OK) return r;
+    }
+    LTS_HIP(c, hipEventRecord(e1, c->stream));
+    LTS_HIP(c, hipEventSynchronize(e1));
+    float ms = 0;
+    LTS_HIP(c, hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      bi = (int)ci;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  LTS_HIP(c, hipStreamSynchronize(c->stream));
+  const TilingHost& W = cands[bi];
+  lts_status r = upload_tiling(c, W, lv.tiling);
+  if (r != LTS_OK) return r;
+  lv.tuned = true;
+  lv.tuned_ms = best / 6.0 / S;
+  tune_cache()[key] = TuneChoice{W.TX, W.TY, W.ox, W.oy, W.rect, lv.tuned_ms};
+  return LTS_OK;
+}
+
+}  // namespace lts
+
+using namespace lts;
+
+extern "C" lts_status lts_autotune(lts_ctx c, int32_t level) {
+  if (!c) return LTS_ERR_ARG;
+  c->err.clear();
+  if (level < 0 || level >= (int32_t)c->levels.size()) return arg_fail(c, "no such level");
+  return autotune_level(c, *c->levels[level]);
+}
+
+extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jobs, int32_t flags,
+                                    double* Q_out) {
+  if (!c) return LTS_ERR_ARG;
+  c->err.clear();
+  if (!jobs || n_jobs < 1 || n_jobs > kMaxJobs) return arg_fail(c, "n_jobs must be in 1..32");
+  if (flags & ~LTS_BATCH_GRAPH) return arg_fail(c, "unknown flags");
+  const int kind = jobs[0].samples.ptr_kind;
+  int total = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    if (jobs[j].level < 0 || jobs[j].level >= (int32_t)c->levels.size()) return arg_fail(c, "bad level id");
+    if (jobs[j].samples.ptr_kind != kind) return arg_fail(c, "all jobs must use the same ptr_kind");
+    if (jobs[j].q_offset < 0) return arg_fail(c, "q_offset must be >= 0");
+    total = std::max(total, jobs[j].q_offset + std::max(jobs[j].samples.n, 0));
+  }
+  if (total > 0 && !Q_out) return arg_fail(c, "Q_out is NULL");
+  std::vector<Staged> st(n_jobs);
+  lts_status r;
+  for (int j = 0; j < n_jobs; ++j)
+    if ((r = stage_samples(c, *c->levels[jobs[j].level], &jobs[j].samples, st[j])) != LTS_OK) return r;
+  LTS_HIP(c, hipSetDevice(c->device));
+  for (int j = 0; j < n_jobs; ++j) {
+    DevLevel& lv = *c->levels[jobs[j].level];
+    if (!lv.tuned && (r = autotune_level(c, lv)) != LTS_OK) return r;
+  }
+  // device layout: per-job tables, states, Q
+  std::vector<size_t> o_k(n_jobs), o_c(n_jobs), o_n(n_jobs), o_x(n_jobs), o_s(n_jobs), o_q(n_jobs);
+  size_t tab = 0, sts = 0, qb = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    const DevLevel& lv = *c->levels[jobs[j].level];
+    const Staged& S = st[j];
+    o_k[j] = tab; tab += align256(S.kappa.size() * 8);
+    o_c[j] = tab; tab += align256(S.coef.size() * 8);
+    o_n[j] = tab; tab += align256(S.nsteps.size() * 4);
+    o_x[j] = tab; tab += align256(S.x0.size() * 8);
+    o_s[j] = sts; sts += align256((size_t)S.n * lv.nodes * 8) * 2;
+    o_q[j] = qb; qb += align256((size_t)S.n * 8);
+  }
+  LTS_HIP(c, c->b_tab.ensure(std::max<size_t>(tab, 256)));
+  LTS_HIP(c, c->b_states.ensure(std::max<size_t>(sts, 256)));
+  LTS_HIP(c, c->b_Q.ensure(std::max<size_t>(qb, 256)));
+  LTS_HIP(c, c->b_jobs.ensure(step_args_size() * n_jobs));
+  char* tb = c->b_tab.as<char>();
+  char* sb = c->b_states.as<char>();
+  char* qbp = c->b_Q.as<char>();
+  std::vector<char> recs(step_args_size() * n_jobs);
+  std::vector<const TilingDev*> T(n_jobs);
+  int maxT = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    const DevLevel& lv = *c->levels[jobs[j].level];
+    const Staged& S = st[j];
+    if (S.n > 0) {
+      LTS_HIP(c, hipMemcpyAsync(tb + o_k[j], S.kappa.data(), S.kappa.size() * 8, hipMemcpyHostToDevice, c->stream));
+      LTS_HIP(c, hipMemcpyAsync(tb + o_c[j], S.coef.data(), S.coef.size() * 8, hipMemcpyHostToDevice, c->stream));
+      LTS_HIP(c, hipMemcpyAsync(tb + o_n[j], S.nsteps.data(), S.nsteps.size() * 4, hipMemcpyHostToDevice, c->stream));
+      LTS_HIP(c, hipMemcpyAsync(tb + o_x[j], S.x0.data(), S.x0.size() * 8, hipMemcpyHostToDevice, c->stream));
+      maxT = std::max(maxT, S.nsteps[0]);
+    }
+    double* B0 = (double*)(sb + o_s[j]);
+    double* B1 = (double*)(sb + o_s[j] + align256((size_t)S.n * lv.nodes * 8));
+    job_record(lv, lv.tiling, (const double*)(tb + o_k[j]), (const double*)(tb + o_c[j]), B0, B1, lv.nodes,
+               recs.data() + j * step_args_size());
+    T[j] = &lv.tiling;
+  }
+  LTS_HIP(c, hipMemcpyAsync(c->b_jobs.p, recs.data(), recs.size(), hipMemcpyHostToDevice, c->stream));
+  LTS_HIP(c, hipStreamSynchronize(c->stream));   // host staging buffers may be released after this
+
+  auto record = [&]() -> lts_status {
+    lts_status rr;
+    for (int j = 0; j < n_jobs; ++j) {
+      const DevLevel& lv = *c->levels[jobs[j].level];
+      if (st[j].n == 0) continue;
+      double* B0 = (double*)(sb + o_s[j]);
+      double* B1 = (double*)(sb + o_s[j] + align256((size_t)st[j].n * lv.nodes * 8));
+      if ((rr = init_states(c, lv, st[j].n, (const double*)(tb + o_x[j]), jobs[j].samples.width, B0, B1)) != LTS_OK)
+        return rr;
+    }
+    std::vector<int> act(n_jobs);
+    for (int j = 0; j < n_jobs; ++j) act[j] = st[j].n;
+    for (int t = 0; t < maxT; ++t) {
+      for (int j = 0; j < n_jobs; ++j)
+        while (act[j] > 0 && st[j].nsteps[act[j] - 1] <= t) --act[j];
+      if ((rr = launch_multi_step(c, (const StepArgs*)c->b_jobs.p, T, act, t, c->stream)) != LTS_OK) return rr;
+    }
+    for (int j = 0; j < n_jobs; ++j) {
+      const DevLevel& lv = *c->levels[jobs[j].level];
+      if (st[j].n == 0) continue;
+      double* B0 = (double*)(sb + o_s[j]);
+      double* B1 = (double*)(sb + o_s[j] + align256((size_t)st[j].n * lv.nodes * 8));
+      if ((rr = qoi_device(c, lv, st[j].n, (const int*)(tb + o_n[j]), B0, B1, (double*)(qbp + o_q[j]))) != LTS_OK)
+        return rr;
+    }
+    return LTS_OK;
+  };
+
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->timing) {
+    while (c->ev_pool.size() < 4) {
+      hipEvent_t e;
+      LTS_HIP(c, hipEventCreate(&e));
+      c->ev_pool.push_back(e);
+    }
+    e0 = c->ev_pool[0];
+    e1 = c->ev_pool[1];
+    LTS_HIP(c, hipEventRecord(e0, c->stream));
+  }
+  if (flags & LTS_BATCH_GRAPH) {
+    // key: job shapes, step counts and every device address baked into the graph
+    std::vector<uint64_t> key = {(uint64_t)n_jobs, (uint64_t)(uintptr_t)tb, (uint64_t)(uintptr_t)sb,
+                                 (uint64_t)(uintptr_t)qbp, (uint64_t)(uintptr_t)c->b_jobs.p};
+    for (int j = 0; j < n_jobs; ++j) {
+      key.push_back((uint64_t)jobs[j].level);
+      key.push_back((uint64_t)c->levels[jobs[j].level]->tiling.ent.p);
+      key.push_back((uint64_t)st[j].n);
+      key.push_back((uint64_t)(std::llround(jobs[j].samples.width * 1e15)));
+      for (int v : st[j].nsteps) key.push_back((uint64_t)v);
+    }
+    if (!c->graph || key != c->graph_key) {
+      if (c->graph) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+      }
+      hipGraph_t g;
+      LTS_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      r = record();
+      hipError_t ec = hipStreamEndCapture(c->stream, &g);
+      if (r != LTS_OK) return r;
+      if (ec != hipSuccess) return hip_fail(c, ec, "hipStreamEndCapture");
+      ec = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ec != hipSuccess) return hip_fail(c, ec, "hipGraphInstantiate");
+      c->graph_key = key;
+    }
+    LTS_HIP(c, hipGraphLaunch(c->graph, c->stream));
+  } else {
+    if ((r = record()) != LTS_OK) return r;
+  }
+  LTS_HIP(c, hipGetLastError());
+  c->last = lts_timing{};
+  if (c->timing) {
+    LTS_HIP(c, hipEventRecord(e1, c->stream));
+    LTS_HIP(c, hipEventSynchronize(e1));
+    float ms = 0;
+    LTS_HIP(c, hipEventElapsedTime(&ms, e0, e1));
+    c->last.total_ms = ms;
+    c->last.step_kernel_ms = ms;
+    c->last.step_launches = maxT;
+  }
+  for (int j = 0; j < n_jobs; ++j) {
+    const DevLevel& lv = *c->levels[jobs[j].level];
+    const double per_step = (double)(lv.H.n_dof - lv.H.n_P) + (double)lv.H.p * lv.H.n_P;
+    for (int v : st[j].nsteps) {
+      c->last.dof_updates += (double)v * per_step;
+      c->last.alg_bytes += (double)v * 24.0 * lv.H.n_dof;
+    }
+  }
+  // results: per job in sorted order -> caller order at q_offset
+  std::vector<double> q(total, 0.0);
+  bool bad = false;
+  for (int j = 0; j < n_jobs; ++j) {
+    const int n = st[j].n;
+    if (n == 0) continue;
+    std::vector<double> qs(n);
+    LTS_HIP(c, hipMemcpyAsync(qs.data(), qbp + o_q[j], (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+    LTS_HIP(c, hipStreamSynchronize(c->stream));
+    for (int t = 0; t < n; ++t) {
+      q[jobs[j].q_offset + st[j].perm[t]] = qs[t];
+      bad |= !std::isfinite(qs[t]);
+    }
+  }
+  if (total > 0) {
+    if (kind == LTS_PTR_DEVICE) {
+      // only the ranges the jobs own are written
+      for (int j = 0; j < n_jobs; ++j)
+        if (st[j].n > 0)
+          LTS_HIP(c, hipMemcpy(Q_out + jobs[j].q_offset, q.data() + jobs[j].q_offset, (size_t)st[j].n * 8,
+                               hipMemcpyHostToDevice));
+    } else {
+      for (int j = 0; j < n_jobs; ++j)
+        if (st[j].n > 0) std::memcpy(Q_out + jobs[j].q_offset, q.data() + jobs[j].q_offset, (size_t)st[j].n * 8);
+    }
+  }
+  if (bad) {
+    c->err = "non-finite QoI (unstable sample)";
+    return LTS_ERR_UNSTABLE;
+  }
+  return LTS_OK;
+}

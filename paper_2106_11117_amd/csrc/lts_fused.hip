@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <type_traits>
 #include <vector>
 
@@ -35,8 +36,6 @@
 #include "fused.h"
 
 namespace lts {
-
-namespace {
 
 struct StepArgs {
   LevelView L;
@@ -52,22 +51,25 @@ struct StepArgs {
   size_t sstride;
   int startup;
   int s0;                            // first sample of this launch
+  double* B0;                        // batched jobs: the two state buffers (step t reads B[t&1])
+  double* B1;
 };
+
+// Launch-time data of a batched launch over several jobs (levels).
+struct MultiArgs {
+  const StepArgs* __restrict__ jobs;   // static per-job data (device table)
+  int n_jobs, per_xcd, step;
+  int wg_off[kMaxJobs + 1];            // prefix sums of the jobs' workgroup counts
+};
+
+namespace {
 
 // One coarse item per wavefront: lane = grid column, walking down the rows
 // with the north/centre/south values and the cell coefficients of the row
 // below carried in registers.
-__global__ __launch_bounds__(kCoarseThreads) void k_coarse(StepArgs a) {
-  __shared__ double lk[256];
-  const int wpc = (a.n_coarse + 3) / 4;
-  const int G = wpc * a.active;
-  const int Lid = (int)(blockIdx.x & 7) * a.per_xcd + (int)(blockIdx.x >> 3);
-  if (Lid >= G) return;
-  const int s = a.s0 + Lid / wpc;
-  const int item = (Lid % wpc) * 4 + (int)(threadIdx.x >> 6);
+__device__ __forceinline__ void coarse_body(const StepArgs& a, const double* __restrict__ lk, int s,
+                                            int item) {
   const LevelView& L = a.L;
-  for (int t = threadIdx.x; t < L.nb; t += kCoarseThreads) lk[t] = a.kappa[(size_t)s * L.nb + t];
-  __syncthreads();
   if (item >= a.n_coarse) return;
   const int2 it = a.citems[item];
   const int i = it.x + (int)(threadIdx.x & 63);
@@ -101,6 +103,51 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse(StepArgs a) {
     kSW = kNW;
     kSE = kNE;
   }
+}
+
+__device__ __forceinline__ void load_kappa(const StepArgs& a, int s, double* __restrict__ lk) {
+  for (int t = threadIdx.x; t < a.L.nb; t += blockDim.x) lk[t] = a.kappa[(size_t)s * a.L.nb + t];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse(StepArgs a) {
+  __shared__ double lk[256];
+  const int wpc = (a.n_coarse + 3) / 4;
+  const int G = wpc * a.active;
+  const int Lid = (int)(blockIdx.x & 7) * a.per_xcd + (int)(blockIdx.x >> 3);
+  if (Lid >= G) return;
+  const int s = a.s0 + Lid / wpc;
+  load_kappa(a, s, lk);
+  coarse_body(a, lk, s, (Lid % wpc) * 4 + (int)(threadIdx.x >> 6));
+}
+
+// Job of a batched launch: the job whose workgroup range holds Lid.
+__device__ __forceinline__ int find_job(const MultiArgs& m, int Lid) {
+  int j = 0;
+  while (j + 1 < m.n_jobs && Lid >= m.wg_off[j + 1]) ++j;
+  return j;
+}
+
+__device__ __forceinline__ StepArgs job_args(const MultiArgs& m, int j) {
+  StepArgs a = m.jobs[j];
+  const bool odd = m.step & 1;
+  a.Ucur = odd ? a.B1 : a.B0;
+  a.Uold = odd ? a.B0 : a.B1;
+  a.startup = m.step == 0;
+  return a;
+}
+
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_multi(MultiArgs m) {
+  __shared__ double lk[256];
+  const int Lid = (int)(blockIdx.x & 7) * m.per_xcd + (int)(blockIdx.x >> 3);
+  if (Lid >= m.wg_off[m.n_jobs]) return;
+  const int j = find_job(m, Lid);
+  const StepArgs a = job_args(m, j);
+  const int wpc = (a.n_coarse + 3) / 4;
+  const int local = Lid - m.wg_off[j];
+  const int s = local / wpc;
+  load_kappa(a, s, lk);
+  coarse_body(a, lk, s, (local % wpc) * 4 + (int)(threadIdx.x >> 6));
 }
 
 __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const double* __restrict__ lk,
@@ -304,13 +351,28 @@ __global__ __launch_bounds__(kFineThreads) void k_fine(StepArgs a) {
   const int Lid = (int)(blockIdx.x & 7) * a.per_xcd + (int)(blockIdx.x >> 3);
   if (Lid >= G) return;
   const int s = a.s0 + Lid / a.n_fine;
-  const int tile = Lid % a.n_fine;
-  for (int t = threadIdx.x; t < a.L.nb; t += kFineThreads) lk[t] = a.kappa[(size_t)s * a.L.nb + t];
-  __syncthreads();
+  load_kappa(a, s, lk);
   if (RECT)
-    fine_tile_rect(a, lk, lq, s, tile);
+    fine_tile_rect(a, lk, lq, s, Lid % a.n_fine);
   else
-    fine_tile_compact(a, lk, lq, s, tile);
+    fine_tile_compact(a, lk, lq, s, Lid % a.n_fine);
+}
+
+template <bool RECT>
+__global__ __launch_bounds__(kFineThreads) void k_fine_multi(MultiArgs m) {
+  __shared__ double lq[2 * kRectCap];
+  __shared__ double lk[256];
+  const int Lid = (int)(blockIdx.x & 7) * m.per_xcd + (int)(blockIdx.x >> 3);
+  if (Lid >= m.wg_off[m.n_jobs]) return;
+  const int j = find_job(m, Lid);
+  const StepArgs a = job_args(m, j);
+  const int local = Lid - m.wg_off[j];
+  const int s = local / a.n_fine;
+  load_kappa(a, s, lk);
+  if (RECT)
+    fine_tile_rect(a, lk, lq, s, local % a.n_fine);
+  else
+    fine_tile_compact(a, lk, lq, s, local % a.n_fine);
 }
 
 }  // namespace
@@ -507,5 +569,66 @@ lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const 
   }
   return LTS_OK;
 }
+
+lts_status launch_multi_step(lts_ctx c, const StepArgs* d_jobs, const std::vector<const TilingDev*>& T,
+                             const std::vector<int>& active, int step, hipStream_t stream) {
+  const int nj = (int)T.size();
+  if (nj > kMaxJobs) {
+    c->err = "too many jobs in one batch";
+    return LTS_ERR_ARG;
+  }
+  MultiArgs m{};
+  m.jobs = d_jobs;
+  m.n_jobs = nj;
+  m.step = step;
+  auto go = [&](int kind) {
+    m.wg_off[0] = 0;
+    for (int j = 0; j < nj; ++j) {
+      int w = 0;
+      if (kind == 0) w = (T[j]->n_coarse + 3) / 4;
+      else if (kind == 1) w = T[j]->rect ? T[j]->n_fine : 0;
+      else w = T[j]->rect ? 0 : T[j]->n_fine;
+      m.wg_off[j + 1] = m.wg_off[j] + w * active[j];
+    }
+    const int G = m.wg_off[nj];
+    if (G == 0) return;
+    m.per_xcd = (G + 7) / 8;
+    const dim3 grid((unsigned)(8 * m.per_xcd));
+    if (kind == 0)
+      k_coarse_multi<<<grid, dim3(kCoarseThreads), 0, stream>>>(m);
+    else if (kind == 1)
+      k_fine_multi<true><<<grid, dim3(kFineThreads), 0, stream>>>(m);
+    else
+      k_fine_multi<false><<<grid, dim3(kFineThreads), 0, stream>>>(m);
+  };
+  go(0);
+  go(1);
+  go(2);
+  return LTS_OK;
+}
+
+void job_record(const DevLevel& lv, const TilingDev& T, const double* d_kappa, const double* d_coef,
+                double* B0, double* B1, size_t sstride, void* out) {
+  StepArgs a{};
+  a.L = lv.view();
+  a.ent = T.ent.as<int4>();
+  a.tiles = T.tiles.as<int2>();
+  a.citems = T.citems.as<int2>();
+  a.n_fine = T.n_fine;
+  a.n_coarse = T.n_coarse;
+  a.pitch = T.pitch;
+  a.rect_slots = T.rect_slots;
+  a.wg_per_sample = T.wg_per_sample;
+  a.kappa = d_kappa;
+  a.coef = d_coef;
+  a.sstride = sstride;
+  a.B0 = B0;
+  a.B1 = B1;
+  a.Ucur = B0;
+  a.Uold = B1;
+  std::memcpy(out, &a, sizeof(a));
+}
+
+size_t step_args_size() { return sizeof(StepArgs); }
 
 }  // namespace lts

@@ -13,43 +13,90 @@ using namespace lts;
 
 namespace {
 
-// Solve `n` new samples (indices first..first+n-1 of MLMC level l) and append
-// Delta Q_l = Q_l - Q_{l-1} to dq (Q_{-1} = 0).
-lts_status level_samples(lts_ctx c, const lts_mlmc_opts& o, int l, int64_t first, int n,
-                         std::vector<double>& dq) {
-  if (n <= 0) return LTS_OK;
+// New samples of one level: indices first..first+n-1 of MLMC level l, drawn
+// once and solved on mesh l (fine) and mesh l-1 (coarse).
+struct LevelBatch {
+  int l = 0, n = 0;
+  std::vector<double> kappa, x0, dtf, dtc, qf, qc;
+  std::vector<int32_t> nsf, nsc;
+};
+
+lts_status draw_level(lts_ctx c, const lts_mlmc_opts& o, int l, int64_t first, int n, LevelBatch& b) {
+  b.l = l;
+  b.n = n;
   const DevLevel& fine = *c->levels[o.level_ids[l]];
   const int nb = o.rule.n_blocks;
   if (fine.H.n_blocks != nb) {
     c->err = "rule.n_blocks differs from the level's block count";
     return LTS_ERR_ARG;
   }
-  std::vector<double> kappa((size_t)n * nb), x0((size_t)n * 2), dtf(n), dtc(n), qf(n), qc(n, 0.0);
-  std::vector<int32_t> nsf(n), nsc(n);
-  std::string e = gen_samples(o.seed, l, first, n, o.rule, fine.H.h, nullptr, kappa.data(), x0.data(),
-                              nsf.data(), dtf.data());
+  b.kappa.resize((size_t)n * nb);
+  b.x0.resize((size_t)n * 2);
+  b.dtf.resize(n);
+  b.dtc.resize(n);
+  b.nsf.resize(n);
+  b.nsc.resize(n);
+  b.qf.assign(n, 0.0);
+  b.qc.assign(n, 0.0);
+  std::string e = gen_samples(o.seed, l, first, n, o.rule, fine.H.h, nullptr, b.kappa.data(), b.x0.data(),
+                              b.nsf.data(), b.dtf.data());
+  if (e.empty() && l > 0)
+    e = gen_samples(o.seed, l, first, n, o.rule, c->levels[o.level_ids[l - 1]]->H.h, nullptr, nullptr, nullptr,
+                    b.nsc.data(), b.dtc.data());
   if (!e.empty()) {
     c->err = e;
     return LTS_ERR_ARG;
   }
-  lts_samples sf{n, LTS_PTR_HOST, kappa.data(), x0.data(), nsf.data(), dtf.data(), o.rule.width};
-  auto solve = [&](int32_t lid, const lts_samples* S, double* q) -> lts_status {
-    return o.mode == LTS_MLMC_PLAIN ? lts_forward_plain(c, lid, S, LTS_FP64, q)
-                                    : lts_forward(c, lid, S, LTS_FP64, q);
-  };
-  lts_status r = solve(o.level_ids[l], &sf, qf.data());
-  if (r != LTS_OK) return r;
-  if (l > 0) {
-    const DevLevel& coarse = *c->levels[o.level_ids[l - 1]];
-    e = gen_samples(o.seed, l, first, n, o.rule, coarse.H.h, nullptr, nullptr, nullptr, nsc.data(), dtc.data());
-    if (!e.empty()) {
-      c->err = e;
-      return LTS_ERR_ARG;
+  return LTS_OK;
+}
+
+// Solve the batches: plain form = one solve call per level and mesh with one
+// launch per sample and step; batched form = every fine and coarse job of every
+// level in one graph-captured lts_batch_run.
+lts_status solve_batches(lts_ctx c, const lts_mlmc_opts& o, std::vector<LevelBatch>& bs) {
+  lts_status r;
+  if (o.mode == LTS_MLMC_PLAIN) {
+    for (auto& b : bs) {
+      if (b.n == 0) continue;
+      lts_samples sf{b.n, LTS_PTR_HOST, b.kappa.data(), b.x0.data(), b.nsf.data(), b.dtf.data(), o.rule.width};
+      if ((r = lts_forward_plain(c, o.level_ids[b.l], &sf, LTS_FP64, b.qf.data())) != LTS_OK) return r;
+      if (b.l > 0) {
+        lts_samples sc{b.n, LTS_PTR_HOST, b.kappa.data(), b.x0.data(), b.nsc.data(), b.dtc.data(), o.rule.width};
+        if ((r = lts_forward_plain(c, o.level_ids[b.l - 1], &sc, LTS_FP64, b.qc.data())) != LTS_OK) return r;
+      }
     }
-    lts_samples sc{n, LTS_PTR_HOST, kappa.data(), x0.data(), nsc.data(), dtc.data(), o.rule.width};
-    if ((r = solve(o.level_ids[l - 1], &sc, qc.data())) != LTS_OK) return r;
+    return LTS_OK;
   }
-  for (int s = 0; s < n; ++s) dq.push_back(qf[s] - qc[s]);
+  std::vector<lts_job> jobs;
+  int off = 0;
+  for (auto& b : bs) {
+    if (b.n == 0) continue;
+    jobs.push_back(lts_job{o.level_ids[b.l],
+                           lts_samples{b.n, LTS_PTR_HOST, b.kappa.data(), b.x0.data(), b.nsf.data(), b.dtf.data(),
+                                       o.rule.width},
+                           off});
+    off += b.n;
+    if (b.l > 0) {
+      jobs.push_back(lts_job{o.level_ids[b.l - 1],
+                             lts_samples{b.n, LTS_PTR_HOST, b.kappa.data(), b.x0.data(), b.nsc.data(),
+                                         b.dtc.data(), o.rule.width},
+                             off});
+      off += b.n;
+    }
+  }
+  if (jobs.empty()) return LTS_OK;
+  std::vector<double> q(off);
+  if ((r = lts_batch_run(c, jobs.data(), (int32_t)jobs.size(), LTS_BATCH_GRAPH, q.data())) != LTS_OK) return r;
+  off = 0;
+  for (auto& b : bs) {
+    if (b.n == 0) continue;
+    std::copy(q.begin() + off, q.begin() + off + b.n, b.qf.begin());
+    off += b.n;
+    if (b.l > 0) {
+      std::copy(q.begin() + off, q.begin() + off + b.n, b.qc.begin());
+      off += b.n;
+    }
+  }
   return LTS_OK;
 }
 
@@ -86,10 +133,14 @@ extern "C" lts_status lts_mlmc(lts_ctx c, const lts_mlmc_opts* op, lts_mlmc_resu
       c->err = "sample budget exceeded before convergence";
       return LTS_ERR_STATE;
     }
+    std::vector<LevelBatch> bs(L + 1);
     for (int l = 0; l <= L; ++l) {
       const int64_t have = (int64_t)dq[l].size();
-      if ((r = level_samples(c, o, l, have, (int)(N[l] - have), dq[l])) != LTS_OK) return r;
+      if ((r = draw_level(c, o, l, have, (int)(N[l] - have), bs[l])) != LTS_OK) return r;
     }
+    if ((r = solve_batches(c, o, bs)) != LTS_OK) return r;
+    for (int l = 0; l <= L; ++l)
+      for (int s = 0; s < bs[l].n; ++s) dq[l].push_back(bs[l].qf[s] - bs[l].qc[s]);
     for (int l = 0; l <= L; ++l) {
       double m3[3];
       if ((r = lts_moments(c, dq[l].data(), (int32_t)N[l], LTS_PTR_HOST, m3)) != LTS_OK) return r;

@@ -226,12 +226,4 @@ lts_status moments_device(lts_ctx c, const double* d_x, int n, double* d_out3) {
 
 }  // namespace lts
 
-extern "C" {
 
-lts_status lts_batch_run(lts_ctx c, const lts_job*, int32_t, int32_t, double*) {
-  if (!c) return LTS_ERR_ARG;
-  c->err = "lts_batch_run: not available in this build";
-  return LTS_ERR_STATE;
-}
-
-}  // extern "C"
