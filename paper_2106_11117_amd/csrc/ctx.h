@@ -42,9 +42,10 @@ struct DevBuf {
 struct TilingDev {
   int TX = 0, TY = 0, n_fine = 0, n_coarse = 0, wg_per_sample = 0;
   bool rect = false;
-  int pitch = 0, rect_slots = 0;
+  int pitch = 0;
   double halo_ratio = 1.0;
-  DevBuf ent, tiles, citems;
+  uint64_t gen = 0;     // distinct for every upload (keys captured graphs)
+  DevBuf ent, tiles, rtiles, citems;
 };
 
 struct DevLevel {

@@ -24,11 +24,12 @@ struct TilingHost {
   int TX = 0, TY = 0;
   int ox = 0, oy = 0;               // origin of the tile grid
   bool rect = false;                // region stored as a zero-padded rectangle in LDS
-  int pitch = 0, rect_slots = 0;    // rect mode: LDS row pitch and slots in use
+  int pitch = 0;                    // rect mode: LDS row pitch (slots)
   int n_fine = 0, n_coarse = 0, wg_per_sample = 0;   // wg_per_sample: fine + coarse workgroups
-  double halo_ratio = 1.0;          // region nodes / F+ nodes
-  std::vector<int4> ent;            // region entries (see lts_fused.hip)
-  std::vector<int2> tiles;          // (offset, length)
+  double halo_ratio = 1.0;          // region lanes / F+ nodes
+  std::vector<int4> ent;            // compact mode: region entries (see lts_fused.hip)
+  std::vector<int2> tiles;          // compact mode: (offset, length)
+  std::vector<int4> rtiles;         // rect mode: region rectangle and tile interior (packed)
   std::vector<int2> citems;         // (i0, j0)
 };
 

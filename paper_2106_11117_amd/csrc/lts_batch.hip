@@ -257,7 +257,7 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
                                  (uint64_t)(uintptr_t)qbp, (uint64_t)(uintptr_t)c->b_jobs.p};
     for (int j = 0; j < n_jobs; ++j) {
       key.push_back((uint64_t)jobs[j].level);
-      key.push_back((uint64_t)c->levels[jobs[j].level]->tiling.ent.p);
+      key.push_back(c->levels[jobs[j].level]->tiling.gen);
       key.push_back((uint64_t)st[j].n);
       key.push_back((uint64_t)(std::llround(jobs[j].samples.width * 1e15)));
       for (int v : st[j].nsteps) key.push_back((uint64_t)v);

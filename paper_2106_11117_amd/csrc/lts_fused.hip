@@ -6,19 +6,20 @@
 //  * coarse items: 64 grid columns x CR rows.  One wavefront per item, one
 //    lane per column walking down the rows; it updates the DOFs outside F+
 //    (no P neighbour there, so w = A_u u and u_n+1 = 2u_n - u_n-1 + 2 a_p w).
-//  * fine tiles: a rectangle of the node grid; its "region" is every F+ node
-//    of the rectangle grown by p nodes in each direction.  One workgroup runs
-//    all p substeps with the P-masked q = u + d of the region in LDS (double
-//    buffered, one barrier per substep) and the per-node state (u, d_m,
-//    d_m-1, w and the scaled edge coefficients) in registers; threads are
-//    assigned to the region's F+ nodes only (compact list).  Rect mode keeps
-//    the region in LDS as a zero-padded rectangle, so the four neighbours of
-//    a node sit at fixed offsets (+-1, +-pitch) from its slot; compact mode
-//    (used when the rectangle does not fit, e.g. large p) stores the region
-//    compacted with per-node neighbour indices.  Values near the region
-//    border are wrong after a few substeps (missing neighbours read 0) but the
-//    error front moves one node per substep, so after p substeps the
-//    rectangle is exact; only its nodes are written back.
+//  * fine tiles: a rectangle of the node grid; its "region" is the rectangle
+//    grown by p nodes in each direction (only F+ nodes of it take part).  One
+//    workgroup runs all p substeps with the P-masked q = u + d of the region
+//    in LDS (double buffered, one barrier per substep) and the per-node state
+//    (u, d_m, d_m-1, w and the scaled edge coefficients) in registers.  Rect
+//    mode keeps the region in LDS as a zero-padded rectangle with one lane per
+//    node, so the four neighbours of a node sit at fixed offsets (+-1,
+//    +-pitch) from its slot and a lane finds its node by arithmetic; compact
+//    mode (used when the rectangle does not fit, e.g. large p) assigns lanes
+//    to the region's F+ nodes only and stores them compacted with per-node
+//    neighbour indices.  Values near the region border are wrong after a few
+//    substeps (missing neighbours read 0) but the error front moves one node
+//    per substep, so after p substeps the tile is exact; only its nodes are
+//    written back.
 // Coarse items and fine tiles are two kernels launched back to back on the
 // stream (they write disjoint nodes and only read u_n): the coarse kernel uses
 // no LDS beyond the sample's coefficient table, so it runs at high occupancy,
@@ -40,10 +41,10 @@ namespace lts {
 struct StepArgs {
   LevelView L;
   const int4* __restrict__ ent;      // region entries of all fine tiles
-  const int2* __restrict__ tiles;    // (offset, length) per fine tile
+  const int2* __restrict__ tiles;    // compact mode: (offset, length) per fine tile
+  const int4* __restrict__ rtiles;   // rect mode: packed region / interior per fine tile
   const int2* __restrict__ citems;   // (i0, j0) per coarse item
   int n_fine, n_coarse, wg_per_sample, per_xcd, active;
-  int pitch, rect_slots;             // rect mode
   const double* __restrict__ kappa;  // [S][nb] (sorted sample order)
   const double* __restrict__ coef;   // [S][p+1]
   const double* __restrict__ Ucur;   // u_n of sample s at Ucur + s*sstride
@@ -239,67 +240,145 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const doubl
 }
 
 
-// Rect mode.  Entry of a region node: x = flat grid index, y = LDS slot in the
-// padded rectangle (row pitch kPitch), z = bit 0: node in P, bit 1: node
-// inside the tile, w = i | j << 16.  Buffer b of q starts at b * kRectCap, so
-// every neighbour read of a node is its base address plus a compile-time
-// offset (all within the 16-bit immediate of the LDS instructions).
-__device__ __forceinline__ void fine_tile_rect(const StepArgs& a, const double* __restrict__ lk,
-                                               double* __restrict__ lq, int s, int tile) {
+// Rect mode.  A tile's region is a rectangle of RX x RY grid nodes (the tile
+// grown by p, clipped to the grid and to the bounding box of its F+ nodes
+// grown by one), held in LDS with row pitch kPitch and a one-slot zero ring, so
+// the four neighbours of a node sit at compile-time offsets (+-1, +-kPitch)
+// from its slot.  Region lane e of the workgroup is node (e % RX, e / RX); the
+// tile descriptor is x = x0 | y0 << 16 (region origin), y = RX | RY << 16,
+// z = ix0 | ix1 << 16, w = iy0 | iy1 << 16 (tile interior [ix0, ix1) x
+// [iy0, iy1)).  All global reads of the tile are issued in one batch before
+// the first barrier: buffer 0 receives q_0 = P u_n and buffer 1 receives
+// v = (I - P) u_n, from which w = A_u v is formed in LDS.  A region node next
+// to the ring sees zeros there instead of the true values of v and q, which is
+// the same one-node-per-substep error front as for q alone, so the interior
+// (at distance >= p from the ring) stays exact.
+__device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __restrict__ lk,
+                                               double* __restrict__ lg, double* __restrict__ lq, int s,
+                                               int tile) {
   constexpr int P = kPitch;
+  constexpr int kDummy = kRectCap - P - 1;           // read-only slot of lanes without a node
   const LevelView& L = a.L;
-  const int2 tl = a.tiles[tile];
-  const int len = tl.y;
-  const int nzero = a.rect_slots + 2 * P + 1;         // rectangle plus the dummy node's pad
-  const int dummy = a.rect_slots + P;                 // slot of threads without a node
+  const int4 td = a.rtiles[tile];
+  const int x0 = td.x & 0xFFFF, y0 = td.x >> 16;
+  const int RX = td.y & 0xFFFF, RY = td.y >> 16;
+  const int ix0 = td.z & 0xFFFF, ix1 = td.z >> 16, iy0 = td.w & 0xFFFF, iy1 = td.w >> 16;
+  const int n = RX * RY;
+  const float inv_rx = 1.0f / (float)RX;
   const double* __restrict__ u_g = a.Ucur + (size_t)s * a.sstride;
   double* __restrict__ uo_g = a.Uold + (size_t)s * a.sstride;
   const double* __restrict__ cf = a.coef + (size_t)s * (L.p + 1);
+  const int tid = threadIdx.x;
+  const bool startup = a.startup;
 
-  for (int t = threadIdx.x; t < nzero; t += kFineThreads) {
-    lq[t] = 0.0;
-    lq[kRectCap + t] = 0.0;
-  }
-  double u[kNPT], d[kNPT], dp[kNPT], w[kNPT];
-  double aE[kNPT], aW[kNPT], aN[kNPT], aS[kNPT], aD[kNPT];
-  int base[kNPT], fl[kNPT];
-#pragma unroll
-  for (int r = 0; r < kNPT; ++r) {
-    const int e = threadIdx.x + r * kFineThreads;
-    d[r] = dp[r] = u[r] = w[r] = 0.0;
-    aE[r] = aW[r] = aN[r] = aS[r] = aD[r] = 0.0;
-    base[r] = dummy - P;
-    fl[r] = 0;
-    if (e < len) {
-      const int4 en = a.ent[tl.x + e];
-      const size_t k = (size_t)en.x;
-      const int i = en.w & 0xFFFF, j = en.w >> 16;
-      base[r] = en.y - P;
-      fl[r] = en.z;
-      double cE, cW, cN, cS;
-      edge_coefs(L, lk, i, j, cE, cW, cN, cS);
-      const double im = L.invm[k];
-      aE[r] = im * cE;
-      aW[r] = im * cW;
-      aN[r] = im * cN;
-      aS[r] = im * cS;
-      aD[r] = (aE[r] + aW[r]) + (aN[r] + aS[r]);
-      const bool pi = en.z & 1;
-      const double uc = u_g[k];
-      u[r] = uc;
-      // w = A_u (I - P) u_n
-      const double vi = pi ? 0.0 : uc;
-      const double vE = (L.flags[k + 1] & F_P) ? 0.0 : u_g[k + 1];
-      const double vW = (L.flags[k - 1] & F_P) ? 0.0 : u_g[k - 1];
-      const double vN = (L.flags[k + L.ld] & F_P) ? 0.0 : u_g[k + L.ld];
-      const double vS = (L.flags[k - L.ld] & F_P) ? 0.0 : u_g[k - L.ld];
-      w[r] = aE[r] * (vi - vE) + aW[r] * (vi - vW) + aN[r] * (vi - vN) + aS[r] * (vi - vS);
+  // ---- one batch of global reads: nothing read here decides another read
+  const double kv = tid < L.nb ? a.kappa[(size_t)s * L.nb + tid] : 0.0;
+  double gv0 = 0.0, gv1 = 0.0;   // geometry of one column (lanes 0..RX) or row (128..128+RY)
+  if (tid <= RX) {
+    const int g = x0 - 1 + tid;
+    if (g >= 0) {
+      gv0 = L.hx[g];
+      gv1 = L.inv2hx[g];
+    }
+  } else if (tid >= 128 && tid <= 128 + RY) {
+    const int g = y0 - 1 + (tid - 128);
+    if (g >= 0) {
+      gv0 = L.hy[g];
+      gv1 = L.inv2hy[g];
     }
   }
-  __syncthreads();   // zero fill done before the first values land
+  // Branch-free: lanes off the grid read node (1, 1) and discard it, so every
+  // load of every lane is issued before the first wait.
+  double u[kNPT], uo[kNPT], im[kNPT];
+  int slot[kNPT], kk[kNPT], fl[kNPT], xy[kNPT];
+  uint32_t cb[kNPT];
 #pragma unroll
-  for (int r = 0; r < kNPT; ++r) lq[base[r] + P] = (fl[r] & 1) ? u[r] : 0.0;
+  for (int r = 0; r < kNPT; ++r) {
+    const int e = tid + r * kFineThreads;
+    const int y = (int)(((float)e + 0.5f) * inv_rx);
+    const int x = e - y * RX;
+    const int gx = x0 + x, gy = y0 + y;
+    const bool has = e < n;
+    const bool ok = has && gx < L.nxn && gy < L.nyn;
+    const bool in = ok && gx >= ix0 && gx < ix1 && gy >= iy0 && gy < iy1;
+    const int k = ok ? gy * L.ld + gx : L.ld + 1;
+    const int kb = (ok && gx >= 1 && gy >= 1) ? k : L.ld + 1;   // cell reads stay in bounds
+    slot[r] = has ? (y + 1) * P + x + 1 : kDummy;
+    xy[r] = x | y << 16;
+    kk[r] = k;
+    const uint32_t f = L.flags[k];
+    const double uc = u_g[k];
+    const double imc = L.invm[k];
+    const double uoc = uo_g[k];
+    const uint32_t c0 = L.cblk[kb], c1 = L.cblk[kb - 1], c2 = L.cblk[kb - L.ld], c3 = L.cblk[kb - L.ld - 1];
+    fl[r] = (ok ? f : 0u) | (has ? 256 : 0) | (in ? 512 : 0);
+    u[r] = ok ? uc : 0.0;
+    im[r] = imc;
+    uo[r] = startup ? 0.0 : uoc;
+    cb[r] = c0 | c1 << 8 | c2 << 16 | c3 << 24;
+  }
+  // ---- LDS fill: kappa table, geometry, zero ring of both buffers, q_0 and v
+  if (tid < L.nb) lk[tid] = kv;
+  if (tid <= RX) {
+    lg[tid] = gv0;
+    lg[128 + tid] = gv1;
+  } else if (tid >= 128 && tid <= 128 + RY) {
+    lg[256 + tid - 128] = gv0;
+    lg[384 + tid - 128] = gv1;
+  }
+  {
+    const int nr = 2 * (RX + 2) + 2 * RY;
+    if (tid < nr) {
+      int z;
+      if (tid < RX + 2) z = tid;                                        // row 0
+      else if (tid < 2 * (RX + 2)) z = (RY + 1) * P + (tid - (RX + 2));   // row RY + 1
+      else {
+        const int t = tid - 2 * (RX + 2);
+        z = (t >> 1) + 1;                                                 // rows 1..RY
+        z = z * P + ((t & 1) ? RX + 1 : 0);
+      }
+      lq[z] = 0.0;
+      lq[kRectCap + z] = 0.0;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kNPT; ++r) {
+    if (!(fl[r] & 256)) continue;
+    const bool pi = fl[r] & F_P;
+    lq[slot[r]] = pi ? u[r] : 0.0;
+    lq[kRectCap + slot[r]] = pi ? 0.0 : u[r];
+  }
   __syncthreads();
+
+  // ---- scaled edge coefficients and w = A_u (I - P) u_n; fl becomes
+  //      bit 0: in P, bit 1: interior F+ node (written back), bit 3: lane has a slot
+  double d[kNPT], dp[kNPT], w[kNPT];
+  double aE[kNPT], aW[kNPT], aN[kNPT], aS[kNPT];
+#pragma unroll
+  for (int r = 0; r < kNPT; ++r) {
+    d[r] = dp[r] = w[r] = 0.0;
+    aE[r] = aW[r] = aN[r] = aS[r] = 0.0;
+    const int f = fl[r];
+    fl[r] = ((f & F_P) ? 1 : 0) | (((f & F_FPLUS) && (f & 512)) ? 2 : 0) | ((f & 256) ? 8 : 0);
+    if (f & F_FPLUS) {
+      const int x = xy[r] & 0xFFFF, y = xy[r] >> 16;
+      const double kNE = lk[cb[r] & 0xFF], kNW = lk[(cb[r] >> 8) & 0xFF];
+      const double kSE = lk[(cb[r] >> 16) & 0xFF], kSW = lk[cb[r] >> 24];
+      const double hxE = lg[x + 1], hxW = lg[x], hyN = lg[256 + y + 1], hyS = lg[256 + y];
+      const double cE = (kNE * hyN + kSE * hyS) * lg[128 + x + 1];
+      const double cW = (kNW * hyN + kSW * hyS) * lg[128 + x];
+      const double cN = (kNE * hxE + kNW * hxW) * lg[384 + y + 1];
+      const double cS = (kSE * hxE + kSW * hxW) * lg[384 + y];
+      aE[r] = im[r] * cE;
+      aW[r] = im[r] * cW;
+      aN[r] = im[r] * cN;
+      aS[r] = im[r] * cS;
+      const double* v = lq + kRectCap + slot[r];
+      const double vi = v[0];
+      w[r] = aE[r] * (vi - v[1]) + aW[r] * (vi - v[-1]) + aN[r] * (vi - v[P]) + aS[r] * (vi - v[-P]);
+    }
+  }
+  __syncthreads();   // buffer 1 is overwritten by the first substep
 
   const int p = L.p;
   // substep m reads buffer B = m & 1 and writes buffer 1 - B
@@ -311,14 +390,11 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, const double* 
     double qn[kNPT];
 #pragma unroll
     for (int r = 0; r < kNPT; ++r) {
-      const double* q = lq + B * kRectCap + base[r];
-      const double qS = q[0], qW = q[P - 1], qi = q[P];
-      const double qE = q[P + 1], qN = q[2 * P];
-      double acc = aD[r] * qi;
-      acc -= aE[r] * qE;
-      acc -= aW[r] * qW;
-      acc -= aN[r] * qN;
-      acc -= aS[r] * qS;
+      const double* q = lq + B * kRectCap + slot[r];
+      const double qS = q[-P], qW = q[-1], qi = q[0];
+      const double qE = q[1], qN = q[P];
+      // edge form: constants are annihilated exactly (no assembled diagonal)
+      const double acc = aE[r] * (qi - qE) + aW[r] * (qi - qW) + aN[r] * (qi - qN) + aS[r] * (qi - qS);
       const double rr = w[r] + acc;
       const double dn = b1 * d[r] - b * dp[r] - c * rr;
       dp[r] = d[r];
@@ -327,7 +403,8 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, const double* 
     }
     if (m + 1 < p) {
 #pragma unroll
-      for (int r = 0; r < kNPT; ++r) lq[(1 - B) * kRectCap + base[r] + P] = qn[r];
+      for (int r = 0; r < kNPT; ++r)
+        if (fl[r] & 8) lq[(1 - B) * kRectCap + slot[r]] = qn[r];
       __syncthreads();
     }
   };
@@ -338,8 +415,7 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, const double* 
 #pragma unroll
   for (int r = 0; r < kNPT; ++r) {
     if (!(fl[r] & 2)) continue;
-    const size_t k = (size_t)a.ent[tl.x + threadIdx.x + r * kFineThreads].x;
-    uo_g[k] = a.startup ? (u[r] + d[r]) : (2.0 * u[r] - uo_g[k] + 2.0 * d[r]);
+    uo_g[kk[r]] = startup ? (u[r] + d[r]) : (2.0 * u[r] - uo[r] + 2.0 * d[r]);
   }
 }
 
@@ -347,32 +423,36 @@ template <bool RECT>
 __global__ __launch_bounds__(kFineThreads) void k_fine(StepArgs a) {
   __shared__ double lq[2 * kRectCap];
   __shared__ double lk[256];
+  __shared__ double lg[RECT ? 512 : 1];   // rect mode: column / row geometry of the region
   const int G = a.n_fine * a.active;
   const int Lid = (int)(blockIdx.x & 7) * a.per_xcd + (int)(blockIdx.x >> 3);
   if (Lid >= G) return;
   const int s = a.s0 + Lid / a.n_fine;
-  load_kappa(a, s, lk);
-  if (RECT)
-    fine_tile_rect(a, lk, lq, s, Lid % a.n_fine);
-  else
+  if (RECT) {
+    fine_tile_rect(a, lk, lg, lq, s, Lid % a.n_fine);
+  } else {
+    load_kappa(a, s, lk);
     fine_tile_compact(a, lk, lq, s, Lid % a.n_fine);
+  }
 }
 
 template <bool RECT>
 __global__ __launch_bounds__(kFineThreads) void k_fine_multi(MultiArgs m) {
   __shared__ double lq[2 * kRectCap];
   __shared__ double lk[256];
+  __shared__ double lg[RECT ? 512 : 1];
   const int Lid = (int)(blockIdx.x & 7) * m.per_xcd + (int)(blockIdx.x >> 3);
   if (Lid >= m.wg_off[m.n_jobs]) return;
   const int j = find_job(m, Lid);
   const StepArgs a = job_args(m, j);
   const int local = Lid - m.wg_off[j];
   const int s = local / a.n_fine;
-  load_kappa(a, s, lk);
-  if (RECT)
-    fine_tile_rect(a, lk, lq, s, local % a.n_fine);
-  else
+  if (RECT) {
+    fine_tile_rect(a, lk, lg, lq, s, local % a.n_fine);
+  } else {
+    load_kappa(a, s, lk);
     fine_tile_compact(a, lk, lq, s, local % a.n_fine);
+  }
 }
 
 }  // namespace
@@ -389,15 +469,14 @@ std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int
   T.oy = oy;
   T.rect = rect;
   const int nxn = H.nxn, nyn = H.nyn, p = H.p;
+  if (nxn > 0xFFFF || nyn > 0xFFFF) return "grid too large for the fine-tile descriptors";
   auto fl = [&](int i, int j) -> uint8_t { return H.flags[(size_t)j * nxn + i]; };
   const int RX = TX + 2 * p, RY = TY + 2 * p;
-  if (rect) {
+  std::vector<int32_t> loc;
+  if (rect)
     T.pitch = kPitch;
-    T.rect_slots = kPitch * (RY + 2);
-    if (RX + 2 > kPitch || T.rect_slots + 2 * kPitch + 1 > kRectCap)
-      return "region rectangle exceeds LDS capacity";
-  }
-  std::vector<int32_t> loc((size_t)RX * RY);
+  else
+    loc.resize((size_t)RX * RY);
   size_t n_region = 0, n_fplus = 0;
   for (int ty = oy - ((oy + TY - 1) / TY) * TY; ty < nyn; ty += TY)
     for (int tx = ox - ((ox + TX - 1) / TX) * TX; tx < nxn; tx += TX) {
@@ -410,6 +489,36 @@ std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int
           }
       if (!any) continue;
       const int x0 = tx - p, y0 = ty - p;
+      if (rect) {
+        // rectangle: F+ bounding box inside the grown tile, grown by one node (the
+        // v = (I - P) u neighbours of its F+ nodes), clipped to the grown tile
+        const int gx0 = std::max(x0, 0), gx1 = std::min(x0 + RX, nxn);
+        const int gy0 = std::max(y0, 0), gy1 = std::min(y0 + RY, nyn);
+        int bx0 = gx1, bx1 = gx0, by0 = gy1, by1 = gy0;
+        for (int j = gy0; j < gy1; ++j)
+          for (int i = gx0; i < gx1; ++i)
+            if (fl(i, j) & LTS_NODE_FPLUS) {
+              bx0 = std::min(bx0, i);
+              bx1 = std::max(bx1, i + 1);
+              by0 = std::min(by0, j);
+              by1 = std::max(by1, j + 1);
+            }
+        bx0 = std::max(bx0 - 1, gx0);
+        bx1 = std::min(bx1 + 1, gx1);
+        by0 = std::max(by0 - 1, gy0);
+        by1 = std::min(by1 + 1, gy1);
+        const int rx = bx1 - bx0, ry = by1 - by0;
+        if (rx + 2 > kPitch || (ry + 1) * kPitch + rx + 1 >= kRectCap || rx * ry > kRegionCap)
+          return "region rectangle exceeds LDS capacity";
+        const int ix0 = std::max(tx, 0), ix1 = std::min(tx + TX, nxn);
+        const int iy0 = std::max(ty, 0), iy1 = std::min(ty + TY, nyn);
+        T.rtiles.push_back(make_int4(bx0 | by0 << 16, rx | ry << 16, ix0 | ix1 << 16, iy0 | iy1 << 16));
+        for (int j = iy0; j < iy1; ++j)
+          for (int i = ix0; i < ix1; ++i)
+            if (fl(i, j) & LTS_NODE_FPLUS) ++n_fplus;
+        n_region += (size_t)rx * ry;
+        continue;
+      }
       std::fill(loc.begin(), loc.end(), -1);
       int len = 0;
       for (int j = std::max(y0, 0); j < std::min(y0 + RY, nyn); ++j)
@@ -431,13 +540,8 @@ std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int
           const bool isP = fl(i, j) & LTS_NODE_P;
           int4 e;
           e.x = j * ld + i;
-          if (rect) {
-            e.y = (j - y0 + 1) * T.pitch + (i - x0 + 1);
-            e.z = (isP ? 1 : 0) | (interior ? 2 : 0);
-          } else {
-            e.y = nb(i + 1, j) | (isP ? 0x8000 : 0) | (nb(i - 1, j) << 16) | (interior ? (int)0x80000000u : 0);
-            e.z = nb(i, j + 1) | (nb(i, j - 1) << 16);
-          }
+          e.y = nb(i + 1, j) | (isP ? 0x8000 : 0) | (nb(i - 1, j) << 16) | (interior ? (int)0x80000000u : 0);
+          e.z = nb(i, j + 1) | (nb(i, j - 1) << 16);
           e.w = i | (j << 16);
           T.ent.push_back(e);
           if (interior) ++n_fplus;
@@ -456,7 +560,7 @@ std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int
           }
       if (any) T.citems.push_back(make_int2(tx, ty));
     }
-  T.n_fine = (int)T.tiles.size();
+  T.n_fine = (int)(rect ? T.rtiles.size() : T.tiles.size());
   T.n_coarse = (int)T.citems.size();
   T.wg_per_sample = T.n_fine + (T.n_coarse + 3) / 4;
   T.halo_ratio = n_fplus ? (double)n_region / n_fplus : 1.0;
@@ -472,14 +576,18 @@ lts_status upload_tiling(lts_ctx c, const TilingHost& T, TilingDev& D) {
   D.halo_ratio = T.halo_ratio;
   D.rect = T.rect;
   D.pitch = T.pitch;
-  D.rect_slots = T.rect_slots;
+  static uint64_t gen_counter = 0;
+  D.gen = ++gen_counter;
   LTS_HIP(c, D.ent.ensure(std::max<size_t>(T.ent.size() * sizeof(int4), 16)));
   LTS_HIP(c, D.tiles.ensure(std::max<size_t>(T.tiles.size() * sizeof(int2), 8)));
+  LTS_HIP(c, D.rtiles.ensure(std::max<size_t>(T.rtiles.size() * sizeof(int4), 16)));
   LTS_HIP(c, D.citems.ensure(std::max<size_t>(T.citems.size() * sizeof(int2), 8)));
   if (!T.ent.empty())
     LTS_HIP(c, hipMemcpy(D.ent.p, T.ent.data(), T.ent.size() * sizeof(int4), hipMemcpyHostToDevice));
   if (!T.tiles.empty())
     LTS_HIP(c, hipMemcpy(D.tiles.p, T.tiles.data(), T.tiles.size() * sizeof(int2), hipMemcpyHostToDevice));
+  if (!T.rtiles.empty())
+    LTS_HIP(c, hipMemcpy(D.rtiles.p, T.rtiles.data(), T.rtiles.size() * sizeof(int4), hipMemcpyHostToDevice));
   if (!T.citems.empty())
     LTS_HIP(c, hipMemcpy(D.citems.p, T.citems.data(), T.citems.size() * sizeof(int2), hipMemcpyHostToDevice));
   return LTS_OK;
@@ -543,8 +651,7 @@ lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const 
   a.citems = T.citems.as<int2>();
   a.n_fine = T.n_fine;
   a.n_coarse = T.n_coarse;
-  a.pitch = T.pitch;
-  a.rect_slots = T.rect_slots;
+  a.rtiles = T.rtiles.as<int4>();
   a.wg_per_sample = T.wg_per_sample;
   a.active = active;
   a.kappa = d_kappa;
@@ -616,8 +723,7 @@ void job_record(const DevLevel& lv, const TilingDev& T, const double* d_kappa, c
   a.citems = T.citems.as<int2>();
   a.n_fine = T.n_fine;
   a.n_coarse = T.n_coarse;
-  a.pitch = T.pitch;
-  a.rect_slots = T.rect_slots;
+  a.rtiles = T.rtiles.as<int4>();
   a.wg_per_sample = T.wg_per_sample;
   a.kappa = d_kappa;
   a.coef = d_coef;
