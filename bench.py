@@ -28,8 +28,22 @@ sys.path.insert(0, ROOT)
 N_BASE, BOX, REF = 512, (0.48, 0.52), 8
 N_SAMPLES = 256
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per step launch from the FETCH_SIZE / WRITE_SIZE counter runs
+# (scaled by a plain copy kernel; profiles/lts_step_kernels_C1_256samples_counters.md),
+# valid only for the step-kernel sources they were taken with.
+TRAFFIC = {"bytes_per_launch": 1.2951e9, "sources_sha256": "a50972bc2a98db81e04a360eaa96ae7c043da7a9def5df4b74c4213681086895"}
+STEP_SOURCES = ("lts_fused.hip", "fused.h", "device.h", "lts_step.hip")
 WORKLOAD = ("unit square 512x512 base refined 8x in (0.48,0.52): 442225 DOFs, |P|=204081, p=8, "
             "nu=0.01, 256 samples, 4x4 blocks sigma=0.25, T=1, FP64")
+
+
+def step_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in STEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2106_11117_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def _cpu_worker(args):
@@ -68,6 +82,22 @@ def cpu_baseline(steps_per_sample: int = 150):
                       f"steps each (one process per core, scipy CSR, FP64); wall {wall:.1f} s incl. setup"}
 
 
+def copy_check(mib: int):
+    """Four device-to-device copies of `mib` MiB (read mib, write mib each): the
+    reference point that turns the FETCH_SIZE / WRITE_SIZE counters of a profiled
+    run into bytes."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(4):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_check_mib": mib, "copies": 4, "bytes_read_per_copy": n * 8,
+                      "bytes_written_per_copy": n * 8}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,7 +106,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--plain", action="store_true", help="time the one-launch-per-sample form")
     ap.add_argument("--samples", type=int, default=N_SAMPLES)
+    ap.add_argument("--copy-check", type=int, default=0, metavar="MIB",
+                    help="only run 4 plain device copies of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_check:
+        copy_check(args.copy_check)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the workload is one GPU's "
                                    "share (samples shard across GPUs with one moment all-reduce)",
@@ -127,6 +162,7 @@ def main():
     dof_upd = float(sum_ns) * per_step * args.steps
     alg_bytes = 24.0 * info["n_dof"] * sum_ns * args.steps
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    traffic = TRAFFIC["bytes_per_launch"] if step_sources_sha256() == TRAFFIC["sources_sha256"] else None
     out = {
         "metric": "LF-LTS DOF-updates/s & % HBM peak; MLMC time at fixed RMSE, batched vs plain",
         "value": dof_upd / el,
@@ -142,10 +178,13 @@ def main():
         "data": "synthetic (Philox seed 0)",
         "config": {"workload": WORKLOAD, "samples": args.samples, "sum_n_steps": sum_ns,
                    "dofs": info["n_dof"], "P": info["n_P"], "p": info["p"],
-                   "form": "plain" if args.plain else "batched"},
+                   "form": "plain" if args.plain else "batched",
+                   "fine_tile": [info["tile_x"], info["tile_y"]], "tile_rect": info["tile_rect"],
+                   "halo_ratio": info["halo_ratio"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "LF-LTS step (all step launches)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "LF-LTS step (k_coarse + k_fine launches)",
+                     "algorithmic_bytes_per_launch": alg_bytes / max(launches, 1),
                      "launches": launches, "kernel_ms": kern_ms},
         "cpu_baseline": cpu,
         "mean_Q": float(m[1]), "var_Q": float(m[2] / max(m[0] - 1, 1)),
