@@ -28,10 +28,10 @@ sys.path.insert(0, ROOT)
 N_BASE, BOX, REF = 512, (0.48, 0.52), 8
 N_SAMPLES = 256
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per step launch from the FETCH_SIZE / WRITE_SIZE counter runs
+# HBM bytes per step launch (one k_coarse + one k_fine) from the FETCH_SIZE / WRITE_SIZE counter runs
 # (scaled by a plain copy kernel; profiles/lts_step_kernels_C1_256samples_counters.md),
 # valid only for the step-kernel sources they were taken with.
-TRAFFIC = {"bytes_per_launch": 1.2951e9, "sources_sha256": "a50972bc2a98db81e04a360eaa96ae7c043da7a9def5df4b74c4213681086895"}
+TRAFFIC = {"bytes_per_launch": 2.5902e9, "sources_sha256": "a50972bc2a98db81e04a360eaa96ae7c043da7a9def5df4b74c4213681086895"}
 STEP_SOURCES = ("lts_fused.hip", "fused.h", "device.h", "lts_step.hip")
 WORKLOAD = ("unit square 512x512 base refined 8x in (0.48,0.52): 442225 DOFs, |P|=204081, p=8, "
             "nu=0.01, 256 samples, 4x4 blocks sigma=0.25, T=1, FP64")
@@ -106,6 +106,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--plain", action="store_true", help="time the one-launch-per-sample form")
     ap.add_argument("--samples", type=int, default=N_SAMPLES)
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-stepping run")
     ap.add_argument("--copy-check", type=int, default=0, metavar="MIB",
                     help="only run 4 plain device copies of MIB MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -157,6 +158,24 @@ def main():
     el = time.perf_counter() - t0
     ctx.set_timing(False)
 
+    fp32 = None
+    if not args.no_fp32:
+        # FP32 stepping beside FP64: one timed solve of the same batch (after one
+        # untimed solve), QoI error against the FP64 results of the same samples
+        ctx.forward(lid, kap, x0, ns, dt, precision=P.LTS_FP32_STEP)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        q32 = ctx.forward(lid, kap, x0, ns, dt, precision=P.LTS_FP32_STEP)
+        torch.cuda.synchronize()
+        el32 = time.perf_counter() - t1
+        q64 = q.cpu().numpy()
+        d = np.abs(q32.cpu().numpy() - q64)
+        fp32 = {"ms_per_solve": el32 * 1e3,
+                "dof_updates_per_s": float(s["n_steps"].sum()) * ((info["n_dof"] - info["n_P"]) + info["p"] * info["n_P"]) / el32,
+                "qoi_max_abs_err_vs_fp64": float(d.max()),
+                "qoi_max_err_rel_to_max_abs_q": float(d.max() / np.abs(q64).max()),
+                "qoi_median_rel_err": float(np.median(d / np.maximum(np.abs(q64), 1e-300)))}
+
     per_step = (info["n_dof"] - info["n_P"]) + info["p"] * info["n_P"]
     sum_ns = int(s["n_steps"].sum())
     dof_upd = float(sum_ns) * per_step * args.steps
@@ -187,6 +206,7 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes / max(launches, 1),
                      "launches": launches, "kernel_ms": kern_ms},
         "cpu_baseline": cpu,
+        "fp32_step": fp32,
         "mean_Q": float(m[1]), "var_Q": float(m[2] / max(m[0] - 1, 1)),
     }
     print(json.dumps(out), flush=True)

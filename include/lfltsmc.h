@@ -228,7 +228,10 @@ typedef struct {
 /* Solve every sample on `level` from t = 0 to n_steps*dt with stabilized
  * LF-LTS (Algorithm 2; start-up u_1 = q_1(u_0) since u_t(0) = 0) and write
  * Q[s] = sum_i qoi_w[i] u_i(T) (same ptr_kind as the samples).
- * precision: LTS_FP64 or LTS_FP32_STEP (states and substeps in binary32).
+ * precision: LTS_FP64, or LTS_FP32_STEP: states, increments, the LDS copies
+ * and the stencil / recurrence arithmetic in binary32 (edge coefficients and
+ * Chebyshev scalars are formed in binary64 and rounded once); the QoI sum is
+ * accumulated in binary64 in both cases.
  * Errors: LTS_ERR_ARG, LTS_ERR_OOM, LTS_ERR_HIP, LTS_ERR_UNSTABLE. */
 lts_status lts_forward(lts_ctx ctx, int32_t level, const lts_samples* samples, int32_t precision,
                        double* Q_out);
@@ -260,8 +263,8 @@ enum { LTS_BATCH_GRAPH = 1 };     /* capture the step loop into HIP graphs and r
 
 /* Advance all jobs of all levels in shared launches: every launch advances
  * one step of every job that still has steps left, so uneven mesh sizes and
- * step counts share the device.  Tile sizes and samples per workgroup come
- * from the context's autotuner (tuned once per level shape and cached).
+ * step counts share the device.  Fine-tile shapes come from the context's
+ * autotuner (tuned once per level shape and cached).  FP64.
  * flags: 0 or LTS_BATCH_GRAPH.  Errors as lts_forward. */
 lts_status lts_batch_run(lts_ctx ctx, const lts_job* jobs, int32_t n_jobs, int32_t flags,
                          double* Q_out);
@@ -271,6 +274,17 @@ lts_status lts_batch_run(lts_ctx ctx, const lts_job* jobs, int32_t n_jobs, int32
  * cached per level shape for the life of the process).  lts_batch_run tunes
  * levels that are not tuned yet.  Errors: LTS_ERR_ARG, LTS_ERR_HIP. */
 lts_status lts_autotune(lts_ctx ctx, int32_t level);
+
+/* Pin the fine-tile shape of `level` to tile_x x tile_y grid nodes in rect
+ * mode (rect = 1: each region held as a zero-padded rectangle in LDS) or
+ * compact mode (rect = 0: the region's F+ nodes compacted with neighbour
+ * indices), with the tile-grid origin chosen to minimise region overhead.
+ * Later solves use it and lts_batch_run does not re-tune the level (a later
+ * lts_autotune does).  A tiling decides which workgroup updates a node, not
+ * the arithmetic applied to it.  Errors: LTS_ERR_ARG (no such
+ * level, sizes outside 1..4096, or the region does not fit the workgroup or
+ * its LDS), LTS_ERR_HIP. */
+lts_status lts_set_tiling(lts_ctx ctx, int32_t level, int32_t tile_x, int32_t tile_y, int32_t rect);
 
 /* ------------------------------------------------------------------------ */
 /* Reductions (Sec. 2.2: estimator and level variance)                       */

@@ -18,7 +18,7 @@ from ._lib import (LTS_BATCH_GRAPH, LTS_FP32_STEP, LTS_FP64, LTS_MLMC_BATCHED, L
 
 __all__ = ["Context", "gen_samples", "philox", "rect_level_host", "cheb_constants", "sample_rule", "box_rule", "graded_L_rule", "LtsError",
            "LTS_FP64", "LTS_FP32_STEP", "LTS_BATCH_GRAPH", "LTS_MLMC_BATCHED", "LTS_MLMC_PLAIN",
-           "LTS_NODE_DOF", "LTS_NODE_P", "LTS_NODE_FPLUS"]
+           "LTS_NODE_DOF", "LTS_NODE_P", "LTS_NODE_FPLUS", "LtsQoI"]
 
 
 def _dp(a):
@@ -196,6 +196,11 @@ class Context:
         self._c(self.lib.lts_autotune(self.h, level))
         return self.level_info(level)
 
+    def set_tiling(self, level, tile_x, tile_y, rect=True):
+        """Pin the fine-tile shape and mode of a level (see lts_set_tiling)."""
+        self._c(self.lib.lts_set_tiling(self.h, level, tile_x, tile_y, 1 if rect else 0))
+        return self.level_info(level)
+
     def level_info(self, level) -> dict:
         info = _lib.LevelInfo()
         self._c(self.lib.lts_level_info_get(self.h, level, C.byref(info)))
@@ -303,3 +308,39 @@ class Context:
         t = _lib.Timing()
         self._c(self.lib.lts_get_timing(self.h, C.byref(t)))
         return {k: getattr(t, k) for k, _ in _lib.Timing._fields_}
+
+
+def _make_autograd():
+    try:
+        import torch
+    except ImportError:                      # the C ABI itself does not need torch
+        return None
+
+    class LtsQoI(torch.autograd.Function):
+        """Q[s] of the LF-LTS solves as a differentiable function of the block
+        log-wave-speeds g[s, b] (kappa = c^2 = exp(2 g)).  Forward runs
+        lts_forward; backward runs the discrete adjoint lts_backward with the
+        incoming gradient as dL/dQ, returning dL/dg at fixed step counts and dt.
+
+        apply(g, ctx, level, x0, n_steps, dt, width=0.05, K=64): g float64 on the
+        context's device, x0 [S, 2], n_steps [S] int32, dt [S] on the same device."""
+
+        @staticmethod
+        def forward(fctx, g, lctx, level, x0, n_steps, dt, width=0.05, K=64):
+            kappa = torch.exp(2.0 * g.detach())
+            q = lctx.forward(level, kappa, x0, n_steps, dt, width)
+            fctx.save_for_backward(kappa, x0, n_steps, dt)
+            fctx.lctx, fctx.level, fctx.width, fctx.K = lctx, level, width, K
+            return q
+
+        @staticmethod
+        def backward(fctx, gq):
+            kappa, x0, n_steps, dt = fctx.saved_tensors
+            _, dg = fctx.lctx.backward(fctx.level, kappa, x0, n_steps, dt, gq.contiguous(), fctx.width,
+                                       fctx.K)
+            return dg, None, None, None, None, None, None, None
+
+    return LtsQoI
+
+
+LtsQoI = _make_autograd()

@@ -109,6 +109,7 @@ SIGNATURES = [
                                         C.c_void_p]),
     ("lts_batch_run", C.c_int32, [C.c_void_p, C.POINTER(Job), C.c_int32, C.c_int32, C.c_void_p]),
     ("lts_autotune", C.c_int32, [C.c_void_p, C.c_int32]),
+    ("lts_set_tiling", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     ("lts_moments", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, dp]),
     ("lts_backward", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Samples), C.c_void_p, C.c_int32,
                                  C.c_void_p, C.c_void_p]),

@@ -52,6 +52,7 @@ struct DevLevel {
   HostLevel H;
   TilingDev tiling;     // fused-step tiling in use
   bool tuned = false;   // tiling chosen by measurement (autotuner)
+  bool pinned = false;  // tiling set by the caller (lts_set_tiling); not re-tuned
   double tuned_ms = 0;  // measured step time of the chosen tiling
   int ld = 0;           // row pitch (elements) of node/cell arrays and states
   size_t nodes = 0;     // nyn * ld
@@ -136,11 +137,11 @@ lts_status moments_device(lts_ctx c, const double* d_x, int n, double* d_out3);
 
 // u_0 (pulse) into B0 and zeros into B1 for samples 0..n-1.
 lts_status init_states(lts_ctx c, const DevLevel& lv, int n, const double* d_x0, double width, double* B0,
-                       double* B1);
+                       double* B1, bool fp32 = false);
 
 // Q[s] = w^T u_{n_steps[s]} with the final state in B[n_steps[s] % 2].
 lts_status qoi_device(lts_ctx c, const DevLevel& lv, int n, const int* d_nsteps, const double* B0,
-                      const double* B1, double* d_Q);
+                      const double* B1, double* d_Q, bool fp32 = false);
 
 // Checkpointed discrete adjoint for one sub-batch (see lts_adjoint.hip).
 lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_kappa,
@@ -171,9 +172,10 @@ void job_record(const DevLevel& lv, const TilingDev& T, const double* d_kappa, c
                 double* B0, double* B1, size_t sstride, void* out);
 size_t step_args_size();
 
-// One fused step launch for samples s0 .. s0+active-1 (sorted order).
+// One fused step launch for samples s0 .. s0+active-1 (sorted order).  With
+// fp32 the state buffers hold binary32 values (stride sstride elements).
 lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const double* d_kappa,
                        const double* d_coef, const double* Ucur, double* Uold, size_t sstride, int s0,
-                       int active, int startup, hipStream_t stream);
+                       int active, int startup, hipStream_t stream, bool fp32 = false);
 
 }  // namespace lts

@@ -143,7 +143,40 @@ extern "C" lts_status lts_autotune(lts_ctx c, int32_t level) {
   if (!c) return LTS_ERR_ARG;
   c->err.clear();
   if (level < 0 || level >= (int32_t)c->levels.size()) return arg_fail(c, "no such level");
+  c->levels[level]->pinned = false;
   return autotune_level(c, *c->levels[level]);
+}
+
+extern "C" lts_status lts_set_tiling(lts_ctx c, int32_t level, int32_t tile_x, int32_t tile_y, int32_t rect) {
+  if (!c) return LTS_ERR_ARG;
+  c->err.clear();
+  if (level < 0 || level >= (int32_t)c->levels.size()) return arg_fail(c, "no such level");
+  if (tile_x < 1 || tile_y < 1 || tile_x > 4096 || tile_y > 4096) return arg_fail(c, "tile size out of range");
+  if (rect != 0 && rect != 1) return arg_fail(c, "rect must be 0 or 1");
+  DevLevel& lv = *c->levels[level];
+  TilingHost best;
+  bool have = false;
+  std::string why;
+  for (auto& org : tile_origins(lv.H, tile_x, tile_y)) {
+    TilingHost T;
+    std::string e = build_tiling(lv.H, lv.ld, tile_x, tile_y, org.first, org.second, rect == 1, T);
+    if (!e.empty()) {
+      why = e;
+      continue;
+    }
+    if (!have || T.halo_ratio * T.n_fine < best.halo_ratio * best.n_fine) {
+      best = std::move(T);
+      have = true;
+    }
+  }
+  if (!have) return arg_fail(c, "tiling does not fit: " + why);
+  LTS_HIP(c, hipSetDevice(c->device));
+  lts_status r = upload_tiling(c, best, lv.tiling);
+  if (r != LTS_OK) return r;
+  lv.tuned = false;
+  lv.pinned = true;
+  lv.tuned_ms = 0.0;
+  return LTS_OK;
 }
 
 extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jobs, int32_t flags,
@@ -168,7 +201,7 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
   LTS_HIP(c, hipSetDevice(c->device));
   for (int j = 0; j < n_jobs; ++j) {
     DevLevel& lv = *c->levels[jobs[j].level];
-    if (!lv.tuned && (r = autotune_level(c, lv)) != LTS_OK) return r;
+    if (!lv.tuned && !lv.pinned && (r = autotune_level(c, lv)) != LTS_OK) return r;
   }
   // device layout: per-job tables, states, Q
   std::vector<size_t> o_k(n_jobs), o_c(n_jobs), o_n(n_jobs), o_x(n_jobs), o_s(n_jobs), o_q(n_jobs);

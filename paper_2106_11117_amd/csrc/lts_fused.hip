@@ -68,6 +68,7 @@ namespace {
 // One coarse item per wavefront: lane = grid column, walking down the rows
 // with the north/centre/south values and the cell coefficients of the row
 // below carried in registers.
+template <class T>
 __device__ __forceinline__ void coarse_body(const StepArgs& a, const double* __restrict__ lk, int s,
                                             int item) {
   const LevelView& L = a.L;
@@ -75,18 +76,18 @@ __device__ __forceinline__ void coarse_body(const StepArgs& a, const double* __r
   const int2 it = a.citems[item];
   const int i = it.x + (int)(threadIdx.x & 63);
   if (i < 1 || i > L.nxn - 2) return;
-  const double* __restrict__ u = a.Ucur + (size_t)s * a.sstride;
-  double* __restrict__ uo = a.Uold + (size_t)s * a.sstride;
-  const double ap = a.coef[(size_t)s * (L.p + 1)];
+  const T* __restrict__ u = reinterpret_cast<const T*>(a.Ucur) + (size_t)s * a.sstride;
+  T* __restrict__ uo = reinterpret_cast<T*>(a.Uold) + (size_t)s * a.sstride;
+  const T ap = (T)a.coef[(size_t)s * (L.p + 1)];
   const int jb = max(it.y, 1), je = min(it.y + kCoarseRows, L.nyn - 1);
   if (jb >= je) return;
   const double hxE = L.hx[i], hxW = L.hx[i - 1], ihE = L.inv2hx[i], ihW = L.inv2hx[i - 1];
   size_t k = (size_t)jb * L.ld + i;
-  double uS = u[k - L.ld], uC = u[k];
+  T uS = u[k - L.ld], uC = u[k];
   double kSW = lk[L.cblk[k - L.ld - 1]], kSE = lk[L.cblk[k - L.ld]];
 #pragma unroll 2
   for (int j = jb; j < je; ++j, k += L.ld) {
-    const double uN = u[k + L.ld], uE = u[k + 1], uW = u[k - 1];
+    const T uN = u[k + L.ld], uE = u[k + 1], uW = u[k - 1];
     const uint8_t f = L.flags[k];
     const double kNW = lk[L.cblk[k - 1]], kNE = lk[L.cblk[k]];
     if ((f & (F_DOF | F_FPLUS)) == F_DOF) {
@@ -95,9 +96,9 @@ __device__ __forceinline__ void coarse_body(const StepArgs& a, const double* __r
       const double cW = (kNW * hyN + kSW * hyS) * ihW;
       const double cN = (kNE * hxE + kNW * hxW) * L.inv2hy[j];
       const double cS = (kSE * hxE + kSW * hxW) * L.inv2hy[j - 1];
-      const double w = L.invm[k] * (cE * (uC - uE) + cW * (uC - uW) + cN * (uC - uN) + cS * (uC - uS));
-      const double d = ap * w;
-      uo[k] = a.startup ? (uC + d) : (2.0 * uC - uo[k] + 2.0 * d);
+      const T w = (T)L.invm[k] * ((T)cE * (uC - uE) + (T)cW * (uC - uW) + (T)cN * (uC - uN) + (T)cS * (uC - uS));
+      const T d = ap * w;
+      uo[k] = a.startup ? (uC + d) : ((T)2 * uC - uo[k] + (T)2 * d);
     }
     uS = uC;
     uC = uN;
@@ -111,6 +112,7 @@ __device__ __forceinline__ void load_kappa(const StepArgs& a, int s, double* __r
   __syncthreads();
 }
 
+template <class T>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse(StepArgs a) {
   __shared__ double lk[256];
   const int wpc = (a.n_coarse + 3) / 4;
@@ -119,7 +121,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse(StepArgs a) {
   if (Lid >= G) return;
   const int s = a.s0 + Lid / wpc;
   load_kappa(a, s, lk);
-  coarse_body(a, lk, s, (Lid % wpc) * 4 + (int)(threadIdx.x >> 6));
+  coarse_body<T>(a, lk, s, (Lid % wpc) * 4 + (int)(threadIdx.x >> 6));
 }
 
 // Job of a batched launch: the job whose workgroup range holds Lid.
@@ -148,28 +150,29 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_multi(MultiArgs m) {
   const int local = Lid - m.wg_off[j];
   const int s = local / wpc;
   load_kappa(a, s, lk);
-  coarse_body(a, lk, s, (local % wpc) * 4 + (int)(threadIdx.x >> 6));
+  coarse_body<double>(a, lk, s, (local % wpc) * 4 + (int)(threadIdx.x >> 6));
 }
 
+template <class T>
 __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const double* __restrict__ lk,
-                                                  double* __restrict__ lq, int s, int tile) {
+                                                  T* __restrict__ lq, int s, int tile) {
   const LevelView& L = a.L;
   const int2 tl = a.tiles[tile];
   const int len = tl.y;
-  const double* __restrict__ u_g = a.Ucur + (size_t)s * a.sstride;
-  double* __restrict__ uo_g = a.Uold + (size_t)s * a.sstride;
+  const T* __restrict__ u_g = reinterpret_cast<const T*>(a.Ucur) + (size_t)s * a.sstride;
+  T* __restrict__ uo_g = reinterpret_cast<T*>(a.Uold) + (size_t)s * a.sstride;
   const double* __restrict__ cf = a.coef + (size_t)s * (L.p + 1);
 
-  double u[kNPT], d[kNPT], dp[kNPT], w[kNPT], aE[kNPT], aW[kNPT], aN[kNPT], aS[kNPT];
+  T u[kNPT], d[kNPT], dp[kNPT], w[kNPT], aE[kNPT], aW[kNPT], aN[kNPT], aS[kNPT];
   int ew[kNPT], ns[kNPT], kk[kNPT];
 #pragma unroll
   for (int r = 0; r < kNPT; ++r) {
     const int e = threadIdx.x + r * kFineThreads;
-    d[r] = 0.0;
-    dp[r] = 0.0;
-    u[r] = 0.0;
-    w[r] = 0.0;
-    aE[r] = aW[r] = aN[r] = aS[r] = 0.0;
+    d[r] = (T)0;
+    dp[r] = (T)0;
+    u[r] = (T)0;
+    w[r] = (T)0;
+    aE[r] = aW[r] = aN[r] = aS[r] = (T)0;
     ew[r] = 0;
     ns[r] = 0;
     kk[r] = -1;
@@ -183,40 +186,40 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const doubl
       double cE, cW, cN, cS;
       edge_coefs(L, lk, i, j, cE, cW, cN, cS);
       const double im = L.invm[k];
-      aE[r] = im * cE;
-      aW[r] = im * cW;
-      aN[r] = im * cN;
-      aS[r] = im * cS;
+      aE[r] = (T)(im * cE);
+      aW[r] = (T)(im * cW);
+      aN[r] = (T)(im * cN);
+      aS[r] = (T)(im * cS);
       const bool pi = (en.y >> 15) & 1;
-      const double uc = u_g[k];
+      const T uc = u_g[k];
       u[r] = uc;
       // w = A_u (I - P) u_n
-      const double vi = pi ? 0.0 : uc;
-      const double vE = (L.flags[k + 1] & F_P) ? 0.0 : u_g[k + 1];
-      const double vW = (L.flags[k - 1] & F_P) ? 0.0 : u_g[k - 1];
-      const double vN = (L.flags[k + L.ld] & F_P) ? 0.0 : u_g[k + L.ld];
-      const double vS = (L.flags[k - L.ld] & F_P) ? 0.0 : u_g[k - L.ld];
+      const T vi = pi ? (T)0 : uc;
+      const T vE = (L.flags[k + 1] & F_P) ? (T)0 : u_g[k + 1];
+      const T vW = (L.flags[k - 1] & F_P) ? (T)0 : u_g[k - 1];
+      const T vN = (L.flags[k + L.ld] & F_P) ? (T)0 : u_g[k + L.ld];
+      const T vS = (L.flags[k - L.ld] & F_P) ? (T)0 : u_g[k - L.ld];
       w[r] = aE[r] * (vi - vE) + aW[r] * (vi - vW) + aN[r] * (vi - vN) + aS[r] * (vi - vS);
-      lq[e] = pi ? uc : 0.0;
+      lq[e] = pi ? uc : (T)0;
     }
   }
-  if (threadIdx.x == 0) lq[len] = 0.0;   // slot read for absent / non-P neighbours
+  if (threadIdx.x == 0) lq[len] = (T)0;   // slot read for absent / non-P neighbours
   __syncthreads();
 
   const int p = L.p;
   for (int m = 0; m < p; ++m) {
-    const double c = cf[1 + m];   // c1 for m = 0, c2_m otherwise
-    const double b = m > 0 ? L.beta[m] : 0.0;
+    const T c = (T)cf[1 + m];   // c1 for m = 0, c2_m otherwise
+    const T b = m > 0 ? (T)L.beta[m] : (T)0;
 #pragma unroll
     for (int r = 0; r < kNPT; ++r) {
       if (kk[r] < 0) continue;
       const bool pi = (ew[r] >> 15) & 1;
-      const double qi = pi ? u[r] + d[r] : 0.0;
-      const double qE = lq[ew[r] & 0x7FFF], qW = lq[(ew[r] >> 16) & 0x7FFF];
-      const double qN = lq[ns[r] & 0x7FFF], qS = lq[(ns[r] >> 16) & 0x7FFF];
-      const double apq = aE[r] * (qi - qE) + aW[r] * (qi - qW) + aN[r] * (qi - qN) + aS[r] * (qi - qS);
-      const double rr = w[r] + apq;
-      const double dn = (m == 0) ? -c * rr : (1.0 + b) * d[r] - b * dp[r] - c * rr;
+      const T qi = pi ? u[r] + d[r] : (T)0;
+      const T qE = lq[ew[r] & 0x7FFF], qW = lq[(ew[r] >> 16) & 0x7FFF];
+      const T qN = lq[ns[r] & 0x7FFF], qS = lq[(ns[r] >> 16) & 0x7FFF];
+      const T apq = aE[r] * (qi - qE) + aW[r] * (qi - qW) + aN[r] * (qi - qN) + aS[r] * (qi - qS);
+      const T rr = w[r] + apq;
+      const T dn = (m == 0) ? -c * rr : ((T)1 + b) * d[r] - b * dp[r] - c * rr;
       dp[r] = d[r];
       d[r] = dn;
     }
@@ -226,7 +229,7 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const doubl
       for (int r = 0; r < kNPT; ++r) {
         if (kk[r] < 0) continue;
         const int e = threadIdx.x + r * kFineThreads;
-        lq[e] = ((ew[r] >> 15) & 1) ? u[r] + d[r] : 0.0;
+        lq[e] = ((ew[r] >> 15) & 1) ? u[r] + d[r] : (T)0;
       }
       __syncthreads();
     }
@@ -235,7 +238,7 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const doubl
   for (int r = 0; r < kNPT; ++r) {
     if (kk[r] < 0 || !((unsigned)ew[r] >> 31)) continue;
     const size_t k = (size_t)kk[r];
-    uo_g[k] = a.startup ? (u[r] + d[r]) : (2.0 * u[r] - uo_g[k] + 2.0 * d[r]);
+    uo_g[k] = a.startup ? (u[r] + d[r]) : ((T)2 * u[r] - uo_g[k] + (T)2 * d[r]);
   }
 }
 
@@ -253,8 +256,9 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const doubl
 // to the ring sees zeros there instead of the true values of v and q, which is
 // the same one-node-per-substep error front as for q alone, so the interior
 // (at distance >= p from the ring) stays exact.
+template <class T>
 __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __restrict__ lk,
-                                               double* __restrict__ lg, double* __restrict__ lq, int s,
+                                               double* __restrict__ lg, T* __restrict__ lq, int s,
                                                int tile) {
   constexpr int P = kPitch;
   constexpr int kDummy = kRectCap - P - 1;           // read-only slot of lanes without a node
@@ -265,8 +269,8 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __rest
   const int ix0 = td.z & 0xFFFF, ix1 = td.z >> 16, iy0 = td.w & 0xFFFF, iy1 = td.w >> 16;
   const int n = RX * RY;
   const float inv_rx = 1.0f / (float)RX;
-  const double* __restrict__ u_g = a.Ucur + (size_t)s * a.sstride;
-  double* __restrict__ uo_g = a.Uold + (size_t)s * a.sstride;
+  const T* __restrict__ u_g = reinterpret_cast<const T*>(a.Ucur) + (size_t)s * a.sstride;
+  T* __restrict__ uo_g = reinterpret_cast<T*>(a.Uold) + (size_t)s * a.sstride;
   const double* __restrict__ cf = a.coef + (size_t)s * (L.p + 1);
   const int tid = threadIdx.x;
   const bool startup = a.startup;
@@ -289,7 +293,8 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __rest
   }
   // Branch-free: lanes off the grid read node (1, 1) and discard it, so every
   // load of every lane is issued before the first wait.
-  double u[kNPT], uo[kNPT], im[kNPT];
+  T u[kNPT], uo[kNPT];
+  double im[kNPT];
   int slot[kNPT], kk[kNPT], fl[kNPT], xy[kNPT];
   uint32_t cb[kNPT];
 #pragma unroll
@@ -307,14 +312,14 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __rest
     xy[r] = x | y << 16;
     kk[r] = k;
     const uint32_t f = L.flags[k];
-    const double uc = u_g[k];
+    const T uc = u_g[k];
     const double imc = L.invm[k];
-    const double uoc = uo_g[k];
+    const T uoc = uo_g[k];
     const uint32_t c0 = L.cblk[kb], c1 = L.cblk[kb - 1], c2 = L.cblk[kb - L.ld], c3 = L.cblk[kb - L.ld - 1];
     fl[r] = (ok ? f : 0u) | (has ? 256 : 0) | (in ? 512 : 0);
-    u[r] = ok ? uc : 0.0;
+    u[r] = ok ? uc : (T)0;
     im[r] = imc;
-    uo[r] = startup ? 0.0 : uoc;
+    uo[r] = startup ? (T)0 : uoc;
     cb[r] = c0 | c1 << 8 | c2 << 16 | c3 << 24;
   }
   // ---- LDS fill: kappa table, geometry, zero ring of both buffers, q_0 and v
@@ -337,27 +342,27 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __rest
         z = (t >> 1) + 1;                                                 // rows 1..RY
         z = z * P + ((t & 1) ? RX + 1 : 0);
       }
-      lq[z] = 0.0;
-      lq[kRectCap + z] = 0.0;
+      lq[z] = (T)0;
+      lq[kRectCap + z] = (T)0;
     }
   }
 #pragma unroll
   for (int r = 0; r < kNPT; ++r) {
     if (!(fl[r] & 256)) continue;
     const bool pi = fl[r] & F_P;
-    lq[slot[r]] = pi ? u[r] : 0.0;
-    lq[kRectCap + slot[r]] = pi ? 0.0 : u[r];
+    lq[slot[r]] = pi ? u[r] : (T)0;
+    lq[kRectCap + slot[r]] = pi ? (T)0 : u[r];
   }
   __syncthreads();
 
   // ---- scaled edge coefficients and w = A_u (I - P) u_n; fl becomes
   //      bit 0: in P, bit 1: interior F+ node (written back), bit 3: lane has a slot
-  double d[kNPT], dp[kNPT], w[kNPT];
-  double aE[kNPT], aW[kNPT], aN[kNPT], aS[kNPT];
+  T d[kNPT], dp[kNPT], w[kNPT];
+  T aE[kNPT], aW[kNPT], aN[kNPT], aS[kNPT];
 #pragma unroll
   for (int r = 0; r < kNPT; ++r) {
-    d[r] = dp[r] = w[r] = 0.0;
-    aE[r] = aW[r] = aN[r] = aS[r] = 0.0;
+    d[r] = dp[r] = w[r] = (T)0;
+    aE[r] = aW[r] = aN[r] = aS[r] = (T)0;
     const int f = fl[r];
     fl[r] = ((f & F_P) ? 1 : 0) | (((f & F_FPLUS) && (f & 512)) ? 2 : 0) | ((f & 256) ? 8 : 0);
     if (f & F_FPLUS) {
@@ -369,12 +374,12 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __rest
       const double cW = (kNW * hyN + kSW * hyS) * lg[128 + x];
       const double cN = (kNE * hxE + kNW * hxW) * lg[384 + y + 1];
       const double cS = (kSE * hxE + kSW * hxW) * lg[384 + y];
-      aE[r] = im[r] * cE;
-      aW[r] = im[r] * cW;
-      aN[r] = im[r] * cN;
-      aS[r] = im[r] * cS;
-      const double* v = lq + kRectCap + slot[r];
-      const double vi = v[0];
+      aE[r] = (T)(im[r] * cE);
+      aW[r] = (T)(im[r] * cW);
+      aN[r] = (T)(im[r] * cN);
+      aS[r] = (T)(im[r] * cS);
+      const T* v = lq + kRectCap + slot[r];
+      const T vi = v[0];
       w[r] = aE[r] * (vi - v[1]) + aW[r] * (vi - v[-1]) + aN[r] * (vi - v[P]) + aS[r] * (vi - v[-P]);
     }
   }
@@ -384,22 +389,22 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __rest
   // substep m reads buffer B = m & 1 and writes buffer 1 - B
   auto substep = [&](int m, auto Bc) {
     constexpr int B = decltype(Bc)::value;
-    const double c = cf[1 + m];   // c1 for m = 0, c2_m otherwise
-    const double b = m > 0 ? L.beta[m] : 0.0;
-    const double b1 = 1.0 + b;
-    double qn[kNPT];
+    const T c = (T)cf[1 + m];   // c1 for m = 0, c2_m otherwise
+    const T b = m > 0 ? (T)L.beta[m] : (T)0;
+    const T b1 = (T)1 + b;
+    T qn[kNPT];
 #pragma unroll
     for (int r = 0; r < kNPT; ++r) {
-      const double* q = lq + B * kRectCap + slot[r];
-      const double qS = q[-P], qW = q[-1], qi = q[0];
-      const double qE = q[1], qN = q[P];
+      const T* q = lq + B * kRectCap + slot[r];
+      const T qS = q[-P], qW = q[-1], qi = q[0];
+      const T qE = q[1], qN = q[P];
       // edge form: constants are annihilated exactly (no assembled diagonal)
-      const double acc = aE[r] * (qi - qE) + aW[r] * (qi - qW) + aN[r] * (qi - qN) + aS[r] * (qi - qS);
-      const double rr = w[r] + acc;
-      const double dn = b1 * d[r] - b * dp[r] - c * rr;
+      const T acc = aE[r] * (qi - qE) + aW[r] * (qi - qW) + aN[r] * (qi - qN) + aS[r] * (qi - qS);
+      const T rr = w[r] + acc;
+      const T dn = b1 * d[r] - b * dp[r] - c * rr;
       dp[r] = d[r];
       d[r] = dn;
-      qn[r] = (fl[r] & 1) ? u[r] + dn : 0.0;
+      qn[r] = (fl[r] & 1) ? u[r] + dn : (T)0;
     }
     if (m + 1 < p) {
 #pragma unroll
@@ -415,13 +420,13 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __rest
 #pragma unroll
   for (int r = 0; r < kNPT; ++r) {
     if (!(fl[r] & 2)) continue;
-    uo_g[kk[r]] = startup ? (u[r] + d[r]) : (2.0 * u[r] - uo[r] + 2.0 * d[r]);
+    uo_g[kk[r]] = startup ? (u[r] + d[r]) : ((T)2 * u[r] - uo[r] + (T)2 * d[r]);
   }
 }
 
-template <bool RECT>
+template <bool RECT, class T>
 __global__ __launch_bounds__(kFineThreads) void k_fine(StepArgs a) {
-  __shared__ double lq[2 * kRectCap];
+  __shared__ T lq[2 * kRectCap];
   __shared__ double lk[256];
   __shared__ double lg[RECT ? 512 : 1];   // rect mode: column / row geometry of the region
   const int G = a.n_fine * a.active;
@@ -429,10 +434,10 @@ __global__ __launch_bounds__(kFineThreads) void k_fine(StepArgs a) {
   if (Lid >= G) return;
   const int s = a.s0 + Lid / a.n_fine;
   if (RECT) {
-    fine_tile_rect(a, lk, lg, lq, s, Lid % a.n_fine);
+    fine_tile_rect<T>(a, lk, lg, lq, s, Lid % a.n_fine);
   } else {
     load_kappa(a, s, lk);
-    fine_tile_compact(a, lk, lq, s, Lid % a.n_fine);
+    fine_tile_compact<T>(a, lk, lq, s, Lid % a.n_fine);
   }
 }
 
@@ -448,10 +453,10 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_multi(MultiArgs m) {
   const int local = Lid - m.wg_off[j];
   const int s = local / a.n_fine;
   if (RECT) {
-    fine_tile_rect(a, lk, lg, lq, s, local % a.n_fine);
+    fine_tile_rect<double>(a, lk, lg, lq, s, local % a.n_fine);
   } else {
     load_kappa(a, s, lk);
-    fine_tile_compact(a, lk, lq, s, local % a.n_fine);
+    fine_tile_compact<double>(a, lk, lq, s, local % a.n_fine);
   }
 }
 
@@ -642,7 +647,7 @@ lts_status default_tiling(lts_ctx c, DevLevel& lv) {
 
 lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const double* d_kappa,
                        const double* d_coef, const double* Ucur, double* Uold, size_t sstride, int s0,
-                       int active, int startup, hipStream_t stream) {
+                       int active, int startup, hipStream_t stream, bool fp32) {
   if (active <= 0) return LTS_OK;
   StepArgs a;
   a.L = lv.view();
@@ -664,15 +669,24 @@ lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const 
   if (T.n_coarse > 0) {
     const long long G = (long long)((T.n_coarse + 3) / 4) * active;
     a.per_xcd = (int)((G + 7) / 8);
-    k_coarse<<<dim3((unsigned)(8LL * a.per_xcd)), dim3(kCoarseThreads), 0, stream>>>(a);
+    const dim3 grid((unsigned)(8LL * a.per_xcd));
+    if (fp32)
+      k_coarse<float><<<grid, dim3(kCoarseThreads), 0, stream>>>(a);
+    else
+      k_coarse<double><<<grid, dim3(kCoarseThreads), 0, stream>>>(a);
   }
   if (T.n_fine > 0) {
     const long long G = (long long)T.n_fine * active;
     a.per_xcd = (int)((G + 7) / 8);
-    if (T.rect)
-      k_fine<true><<<dim3((unsigned)(8LL * a.per_xcd)), dim3(kFineThreads), 0, stream>>>(a);
+    const dim3 grid((unsigned)(8LL * a.per_xcd));
+    if (T.rect && fp32)
+      k_fine<true, float><<<grid, dim3(kFineThreads), 0, stream>>>(a);
+    else if (T.rect)
+      k_fine<true, double><<<grid, dim3(kFineThreads), 0, stream>>>(a);
+    else if (fp32)
+      k_fine<false, float><<<grid, dim3(kFineThreads), 0, stream>>>(a);
     else
-      k_fine<false><<<dim3((unsigned)(8LL * a.per_xcd)), dim3(kFineThreads), 0, stream>>>(a);
+      k_fine<false, double><<<grid, dim3(kFineThreads), 0, stream>>>(a);
   }
   return LTS_OK;
 }

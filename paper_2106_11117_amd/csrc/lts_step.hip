@@ -27,9 +27,9 @@ constexpr int TBX = 64, TBY = 4;
 
 // ---------------------------------------------------------------------------
 // Initial state: u_0 = exp(-|x - x0|^2 / width^2) on DOFs, 0 elsewhere.
+template <class T>
 __global__ __launch_bounds__(256) void k_init(LevelView L, const double* __restrict__ x0, double width,
-                                              double* __restrict__ U, double* __restrict__ U1,
-                                              size_t sstride) {
+                                              T* __restrict__ U, T* __restrict__ U1, size_t sstride) {
   const int s = blockIdx.z;
   const int i = blockIdx.x * TBX + threadIdx.x, j = blockIdx.y * TBY + threadIdx.y;
   if (i >= L.ld || j >= L.nyn) return;
@@ -39,21 +39,23 @@ __global__ __launch_bounds__(256) void k_init(LevelView L, const double* __restr
     const double dx = L.x[i] - x0[2 * s], dy = L.y[j] - x0[2 * s + 1];
     v = exp(-(dx * dx + dy * dy) / (width * width));
   }
-  U[s * sstride + k] = v;
-  U1[s * sstride + k] = 0.0;   // the other time level: boundary nodes must read 0
+  U[s * sstride + k] = (T)v;
+  U1[s * sstride + k] = (T)0;   // the other time level: boundary nodes must read 0
 }
 
 // ---------------------------------------------------------------------------
-// Q[s] = sum_k qoiw[k] u_k, one workgroup per sample, fixed summation order.
+// Q[s] = sum_k qoiw[k] u_k, one workgroup per sample, fixed summation order,
+// accumulated in binary64 also for binary32 states.
+template <class T>
 __global__ __launch_bounds__(256) void k_qoi(LevelView L, const int* __restrict__ nsteps,
-                                             const double* __restrict__ B0, const double* __restrict__ B1,
+                                             const T* __restrict__ B0, const T* __restrict__ B1,
                                              size_t sstride, size_t nodes, double* __restrict__ Q) {
   const int s = blockIdx.x;
-  const double* __restrict__ u = ((nsteps[s] & 1) ? B1 : B0) + s * sstride;
+  const T* __restrict__ u = ((nsteps[s] & 1) ? B1 : B0) + s * sstride;
   double acc = 0.0;
   for (size_t k = threadIdx.x; k < nodes; k += blockDim.x) {
     const double w = L.qoiw[k];
-    if (w != 0.0) acc += w * u[k];
+    if (w != 0.0) acc += w * (double)u[k];
   }
   __shared__ double red[256];
   red[threadIdx.x] = acc;
@@ -124,14 +126,11 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
                           const std::vector<int>& h_nsteps, int precision, bool per_sample,
                           double* d_Q) {
   // Samples arrive sorted by decreasing step count, so the samples still
-  // running at step `step` are a prefix of the batch.
-  if (precision != LTS_FP64) {
-    c->err = "FP32 stepping is not available in this build";
-    return LTS_ERR_ARG;
-  }
-  const LevelView L = lv.view();
+  // running at step `step` are a prefix of the batch.  FP32 stepping keeps
+  // binary32 states (sstride elements of 4 bytes per sample) in the same buffers.
+  const bool fp32 = precision == LTS_FP32_STEP;
   const size_t sstride = lv.nodes;
-  const size_t bytes = (size_t)n * sstride * sizeof(double);
+  const size_t bytes = (size_t)n * sstride * (fp32 ? sizeof(float) : sizeof(double));
   LTS_HIP(c, c->st0.ensure(bytes));
   LTS_HIP(c, c->st1.ensure(bytes));
   double* B[2] = {c->st0.as<double>(), c->st1.as<double>()};
@@ -147,7 +146,7 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
     e0 = c->ev_pool[0]; e1 = c->ev_pool[1]; e2 = c->ev_pool[2]; e3 = c->ev_pool[3];
     LTS_HIP(c, hipEventRecord(e0, c->stream));
   }
-  lts_status r = init_states(c, lv, n, d_x0, width, B[0], B[1]);
+  lts_status r = init_states(c, lv, n, d_x0, width, B[0], B[1], fp32);
   if (r != LTS_OK) return r;
   if (c->timing) LTS_HIP(c, hipEventRecord(e1, c->stream));
   int64_t launches = 0;
@@ -155,7 +154,7 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
     for (int s = 0; s < n; ++s)
       for (int step = 0; step < h_nsteps[s]; ++step) {
         r = launch_step(c, lv, lv.tiling, d_kappa, d_coef, B[step & 1], B[(step + 1) & 1], sstride, s, 1,
-                        step == 0, c->stream);
+                        step == 0, c->stream, fp32);
         if (r != LTS_OK) return r;
         ++launches;
       }
@@ -164,19 +163,19 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
     for (int step = 0; step < maxn; ++step) {
       while (active > 0 && h_nsteps[active - 1] <= step) --active;
       r = launch_step(c, lv, lv.tiling, d_kappa, d_coef, B[step & 1], B[(step + 1) & 1], sstride, 0,
-                      active, step == 0, c->stream);
+                      active, step == 0, c->stream, fp32);
       if (r != LTS_OK) return r;
       ++launches;
     }
   }
   LTS_HIP(c, hipGetLastError());
   if (c->timing) LTS_HIP(c, hipEventRecord(e2, c->stream));
-  if ((r = qoi_device(c, lv, n, d_nsteps, B[0], B[1], d_Q)) != LTS_OK) return r;
+  if ((r = qoi_device(c, lv, n, d_nsteps, B[0], B[1], d_Q, fp32)) != LTS_OK) return r;
   double dofu = 0.0, algb = 0.0;
   const double per_step = (double)(lv.H.n_dof - lv.H.n_P) + (double)lv.H.p * lv.H.n_P;
   for (int s = 0; s < n; ++s) {
     dofu += (double)h_nsteps[s] * per_step;
-    algb += (double)h_nsteps[s] * 24.0 * lv.H.n_dof;
+    algb += (double)h_nsteps[s] * (fp32 ? 12.0 : 24.0) * lv.H.n_dof;
   }
   c->last = lts_timing{};
   c->last.dof_updates = dofu;
@@ -195,7 +194,7 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
 }
 
 lts_status init_states(lts_ctx c, const DevLevel& lv, int n, const double* d_x0, double width, double* B0,
-                       double* B1) {
+                       double* B1, bool fp32) {
   const LevelView L = lv.view();
   const size_t sstride = lv.nodes;
   const dim3 blk(TBX, TBY);
@@ -203,17 +202,26 @@ lts_status init_states(lts_ctx c, const DevLevel& lv, int n, const double* d_x0,
   constexpr int kMaxZ = 32768;
   for (int z0 = 0; z0 < n; z0 += kMaxZ) {
     const int nz = std::min(kMaxZ, n - z0);
-    k_init<<<dim3(gx, gy, nz), blk, 0, c->stream>>>(L, d_x0 + 2 * z0, width, B0 + z0 * sstride,
-                                                     B1 + z0 * sstride, sstride);
+    if (fp32)
+      k_init<float><<<dim3(gx, gy, nz), blk, 0, c->stream>>>(L, d_x0 + 2 * z0, width,
+                                                              reinterpret_cast<float*>(B0) + z0 * sstride,
+                                                              reinterpret_cast<float*>(B1) + z0 * sstride, sstride);
+    else
+      k_init<double><<<dim3(gx, gy, nz), blk, 0, c->stream>>>(L, d_x0 + 2 * z0, width, B0 + z0 * sstride,
+                                                               B1 + z0 * sstride, sstride);
   }
   LTS_HIP(c, hipGetLastError());
   return LTS_OK;
 }
 
 lts_status qoi_device(lts_ctx c, const DevLevel& lv, int n, const int* d_nsteps, const double* B0,
-                      const double* B1, double* d_Q) {
+                      const double* B1, double* d_Q, bool fp32) {
   if (n <= 0) return LTS_OK;
-  k_qoi<<<n, 256, 0, c->stream>>>(lv.view(), d_nsteps, B0, B1, lv.nodes, lv.nodes, d_Q);
+  if (fp32)
+    k_qoi<float><<<n, 256, 0, c->stream>>>(lv.view(), d_nsteps, reinterpret_cast<const float*>(B0),
+                                           reinterpret_cast<const float*>(B1), lv.nodes, lv.nodes, d_Q);
+  else
+    k_qoi<double><<<n, 256, 0, c->stream>>>(lv.view(), d_nsteps, B0, B1, lv.nodes, lv.nodes, d_Q);
   LTS_HIP(c, hipGetLastError());
   return LTS_OK;
 }

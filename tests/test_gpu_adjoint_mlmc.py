@@ -127,3 +127,23 @@ def test_mlmc_plain_equals_batched(ctx):
     a = ctx.mlmc(ids, rule, eps=1e-3, N_init=(8, 4), L_start=1)
     b = ctx.mlmc(ids, rule, eps=1e-3, N_init=(8, 4), L_start=1, mode=P.LTS_MLMC_PLAIN)
     assert a["N"] == b["N"] and a["estimate"] == b["estimate"]
+
+
+def test_autograd_function(ctx):
+    """LtsQoI: forward equals lts_forward, backward equals the adjoint gradient
+    contracted with the incoming dL/dQ."""
+    torch = _torch()
+    lid = ctx.add_rect_level(P.box_rule(16))
+    lv, ops, s = _case(n=3)
+    d = torch.device("cuda:0")
+    g = torch.tensor(np.log(s["kappa"]) / 2, device=d, requires_grad=True)
+    x0 = torch.tensor(s["x0"], device=d)
+    ns = torch.tensor(s["n_steps"], device=d)
+    dt = torch.tensor(s["dt"], device=d)
+    q = P.LtsQoI.apply(g, ctx, lid, x0, ns, dt, 0.05, 8)
+    qf = ctx.forward(lid, torch.exp(2.0 * g.detach()), x0, ns, dt)
+    assert torch.equal(q, qf)
+    wts = torch.tensor([0.5, -1.0, 2.0], dtype=torch.float64, device=d)
+    (wts * q).sum().backward()
+    _, gref = ctx.backward(lid, torch.exp(2.0 * g.detach()), x0, ns, dt, wts, K=8)
+    assert torch.equal(g.grad, gref)

@@ -203,3 +203,77 @@ def test_c1_full_size_sampled(ctx):
     for g in gold["samples"]:
         assert int(s["n_steps"][g["i"]]) == g["n_steps"] and s["dt"][g["i"]] == g["dt"]
         check(q[g["i"]], g["Q"], g["abs_wu"])
+
+
+def _fp32_bound(n_steps, p):
+    """Derived bound for FP32 stepping: every coarse step applies n_s * p binary32
+    stencil/recurrence updates to O(|u|) values (relative rounding 2^-24 each); in a
+    stable, non-dissipative three-term recurrence these errors add up at most
+    linearly, so |dQ| <= 4 * n_s * p * 2^-24 * sum_i w_i |u_i| (factor 4: the few
+    roundings per update)."""
+    return 4.0 * n_steps * p * 2.0 ** -24
+
+
+def _fp32_case(ctx, graded):
+    if not graded:
+        lid = ctx.add_rect_level(P.box_rule(32))
+        lv = mesh.box_refined_level(32)
+        s = P.gen_samples(0, 0, 0, 12, _c0_rule(), lv.h)
+    else:
+        lid = ctx.add_rect_level(P.graded_L_rule(32))
+        lv = mesh.graded_L_level(32)
+        r = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), T=0.5)
+        s = P.gen_samples(0, 0, 0, 3, r, lv.h)
+    return lid, lv, s
+
+
+@pytest.mark.parametrize("graded,rect", [(False, True), (False, False), (True, True), (True, False)])
+def test_fp32_stepping(ctx, graded, rect):
+    """FP32 stepping (binary32 states, increments and stencil; binary64 QoI sum)
+    against the FP64 oracle in both fine-tile modes: within the derived bound,
+    and measurably not FP64."""
+    lid, lv, s = _fp32_case(ctx, graded)
+    info = ctx.set_tiling(lid, 48, 48, rect) if not graded else ctx.set_tiling(lid, 16, 16, rect)
+    assert bool(info["tile_rect"]) == rect
+    ops = fem.operators(lv)
+    q32 = ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"], precision=P.LTS_FP32_STEP)
+    q32b = ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"], precision=P.LTS_FP32_STEP,
+                       plain=True)
+    assert np.array_equal(q32, q32b)
+    worst = 0.0
+    for k in range(len(q32)):
+        qo, sc = oracle_solve(ops, lv, s["kappa"][k], s["x0"][k], int(s["n_steps"][k]), s["dt"][k])
+        e = abs(q32[k] - qo) / sc
+        worst = max(worst, e / _fp32_bound(int(s["n_steps"][k]), lv.p))
+        assert e <= _fp32_bound(int(s["n_steps"][k]), lv.p), (k, e)
+        assert e > 1e-12          # binary32 really ran
+    print(f"fp32 worst error / bound = {worst:.3g}")
+
+
+@pytest.mark.parametrize("graded", [False, True])
+def test_fine_tile_modes_and_shapes(ctx, graded):
+    """FP64 parity in compact mode and in rect mode at several tile shapes: rect
+    shapes agree bitwise (same per-node arithmetic), compact within rounding."""
+    lid, lv, s = _fp32_case(ctx, graded)
+    ops = fem.operators(lv)
+    shapes = [(48, 48), (64, 16), (24, 40)] if not graded else [(16, 16), (32, 8), (8, 24)]
+    ref = None
+    for tx, ty in shapes:
+        ctx.set_tiling(lid, tx, ty, True)
+        q = ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"])
+        if ref is None:
+            ref = q
+        assert np.array_equal(q, ref), (tx, ty)
+    ctx.set_tiling(lid, *shapes[0], False)
+    qc = ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"])
+    for k in range(len(qc)):
+        qo, sc = oracle_solve(ops, lv, s["kappa"][k], s["x0"][k], int(s["n_steps"][k]), s["dt"][k])
+        check(qc[k], qo, sc)
+        check(ref[k], qo, sc)
+    for bad in [(0, 8), (8, 5000)]:
+        with pytest.raises(P.LtsError):
+            ctx.set_tiling(lid, *bad, True)
+    big = ctx.add_rect_level(P.box_rule(128))      # 200 x 200 tiles: region beyond one workgroup
+    for rect in (True, False):
+        with pytest.raises(P.LtsError):
+            ctx.set_tiling(big, 200, 200, rect)
