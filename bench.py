@@ -82,6 +82,107 @@ def cpu_baseline(steps_per_sample: int = 150):
                       f"steps each (one process per core, scipy CSR, FP64); wall {wall:.1f} s incl. setup"}
 
 
+# MLMC workload: graded L-shape hierarchy, 5 levels, Algorithm 1 at fixed RMSE
+MLMC_BASES = (32, 64, 128, 256, 512)      # cells across [-1, 1]: h = 1/16 .. 1/256
+MLMC_EPS = (1e-3, 1e-4)                   # the workload's eps, and a tighter extra point
+MLMC_N_INIT = (256, 64, 16, 8, 4)
+
+
+def _mlmc_rule_oracle():
+    from oracle import rng
+    return rng.SampleRule(n_blocks=64, sigma=0.3, pulse_box=(-0.8, -0.4, 0.4, 0.8), T=2.0)
+
+
+def _mlmc_cpu_worker(args):
+    """Oracle (test infrastructure) seconds per coarse step of one sample on level `lvl`."""
+    lvl, i, steps = args
+    from oracle import fem, lts, mesh, rng
+    lv = mesh.graded_L_level(MLMC_BASES[lvl])
+    ops = fem.operators(lv)
+    rule = _mlmc_rule_oracle()
+    smp = rng.draw(0, lvl, i, rule)
+    n, dt = rng.steps_for(smp, rule, lv.h)
+    s = lts.Solver(ops, smp.kappa)
+    z0 = lts.pulse(ops, smp.x0)
+    t0 = time.perf_counter()
+    zm, zc = z0, s.q1(z0, dt)
+    for _ in range(1, steps):
+        zm, zc = zc, 2.0 * zc - zm + 2.0 * s.d1(zc, dt)
+    return lvl, (time.perf_counter() - t0) / steps
+
+
+def mlmc_bench(no_cpu: bool):
+    """Algorithm 1 on the graded L-shape hierarchy (h = 1/16 .. 1/256, p = 64, 8x8
+    blocks sigma 0.3, T = 2) at the workload's eps = 1e-3 and a tighter 1e-4: wall
+    time of the batched + graph form and of the plain form (one launch per sample
+    and step) at identical N_l, and an extrapolated CPU-oracle time for the same N_l.
+    The CPU timing runs first, before this process touches the GPU."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    procs = max(1, min(os.cpu_count() or 1, 16))
+    per_step = None
+    if not no_cpu:
+        # oracle seconds per coarse step on every level (4 samples each, 10 steps,
+        # one process per core)
+        work = [(l, i, 10) for l in range(len(MLMC_BASES)) for i in range(4)]
+        with mp.get_context("spawn").Pool(procs) as pool:
+            res = pool.map(_mlmc_cpu_worker, work)
+        per_step = {l: float(np.mean([t for (ll, t) in res if ll == l])) for l in range(len(MLMC_BASES))}
+
+    import paper_2106_11117_amd as P
+
+    ctx = P.Context(0)
+    ids = [ctx.add_rect_level(P.graded_L_rule(nb)) for nb in MLMC_BASES]
+    rule = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), width=0.05, T=2.0)
+    t0 = time.perf_counter()
+    for lid in ids:
+        ctx.autotune(lid)
+    setup = time.perf_counter() - t0
+    info = [ctx.level_info(l) for l in ids]
+    runs = []
+    for eps in MLMC_EPS:
+        t0 = time.perf_counter()
+        rb = ctx.mlmc(ids, rule, eps=eps, N_init=MLMC_N_INIT, L_start=2)
+        wall_b = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        rp = ctx.mlmc(ids, rule, eps=eps, N_init=MLMC_N_INIT, L_start=2, mode=P.LTS_MLMC_PLAIN)
+        wall_p = time.perf_counter() - t0
+        assert rb["N"] == rp["N"] and rb["estimate"] == rp["estimate"]
+        run = {"eps": eps, "batched_graph_s": wall_b, "plain_s": wall_p, "speedup_vs_plain": wall_p / wall_b,
+               "L": rb["L"], "N": rb["N"], "estimate": rb["estimate"], "rmse": rb["rmse"],
+               "bias": rb["bias"], "var": rb["var"], "converged": rb["converged"]}
+        if per_step is not None:
+            # the run's own step counts for the same N_l, spread over the cores
+            total = 0.0
+            for l in range(rb["L"] + 1):
+                n = rb["N"][l]
+                total += float(P.gen_samples(0, l, 0, n, rule, info[l]["h"])["n_steps"].sum()) * per_step[l]
+                if l > 0:
+                    total += float(P.gen_samples(0, l, 0, n, rule, info[l - 1]["h"])["n_steps"].sum()) \
+                        * per_step[l - 1]
+            run["cpu_oracle_s_extrapolated"] = total / procs
+            run["speedup_vs_cpu"] = total / procs / wall_b
+        runs.append(run)
+    out = {"metric": "MLMC wall time at fixed RMSE (Algorithm 1), batched + graph vs plain",
+           "unit": "s", "higher_is_better": False, "data": "synthetic (Philox seed 0)",
+           "config": {"workload": "graded L-shape, 5 levels h = 1/16..1/256, 6 graded layers "
+                                  "(h_min = h/64, p = 64), 8x8 blocks sigma 0.3, T = 2, "
+                                  "QoI [0.5,0.9]x[0.2,0.6]; eps absolute",
+                      "N_init": list(MLMC_N_INIT), "L_start": 2,
+                      "dofs": [i["n_dof"] for i in info], "P": [i["n_P"] for i in info]},
+           "setup_autotune_s": setup, "runs": runs,
+           "cpu_oracle": None if per_step is None else {
+               "seconds_per_step_by_level": [per_step[l] for l in range(len(ids))], "cores": procs,
+               "kind": "oracle",
+               "sample": "oracle seconds per coarse step timed on every level (4 samples x 10 steps, one "
+                         "process per core), times each run's step counts for the same N_l, divided by "
+                         "the cores (an extrapolation, not a full oracle run)"}}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def copy_check(mib: int):
     """Four device-to-device copies of `mib` MiB (read mib, write mib each): the
     reference point that turns the FETCH_SIZE / WRITE_SIZE counters of a profiled
@@ -109,7 +210,12 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-stepping run")
     ap.add_argument("--copy-check", type=int, default=0, metavar="MIB",
                     help="only run 4 plain device copies of MIB MiB (calibrates HBM byte counters)")
+    ap.add_argument("--mlmc", action="store_true",
+                    help="only run the MLMC wall-time comparison (graded L-shape, Algorithm 1)")
     args = ap.parse_args()
+    if args.mlmc:
+        mlmc_bench(args.no_cpu)
+        return
     if args.copy_check:
         copy_check(args.copy_check)
         return
