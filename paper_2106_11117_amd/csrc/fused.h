@@ -14,10 +14,14 @@ constexpr int kFineThreads = 1024;                  // threads per workgroup
 constexpr int kNPT = 4;                             // region nodes per thread
 constexpr int kRegionCap = kFineThreads * kNPT;     // nodes of one fine-tile region
 constexpr int kCoarseRows = 16;                     // rows walked by one coarse wavefront
-constexpr int kRectCap = 7992;                      // LDS slots of one rectangular region buffer
-constexpr int kPitch = 96;                          // LDS row pitch of the rectangle (slots)
+constexpr int kRectW = 64;                          // rect mode: region columns (one per lane)
+constexpr int kRectH = 4 * (kFineThreads / 64);     // rect mode: region rows (4 per lane)
+constexpr int kPitch = kRectW + 2;                  // LDS row pitch of the rectangle (zero ring)
+constexpr int kRectCap = kPitch * (kRectH + 2);     // LDS slots of one rectangle buffer
+constexpr int kLdsSlots = 2 * kRectCap > kRegionCap + 1 ? 2 * kRectCap : kRegionCap + 1;
 constexpr int kCoarseThreads = 256;                 // coarse workgroup: 4 wavefronts, one item each
 constexpr int kMaxAdjP = 64;                        // largest p supported by the adjoint
+constexpr int kMaxP = 256;                          // largest p of a level (substep scalars in LDS)
 constexpr int kMaxJobs = 32;                        // jobs of one batched launch
 
 struct TilingHost {

@@ -243,198 +243,228 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const doubl
 }
 
 
-// Rect mode.  A tile's region is a rectangle of RX x RY grid nodes (the tile
-// grown by p, clipped to the grid and to the bounding box of its F+ nodes
-// grown by one), held in LDS with row pitch kPitch and a one-slot zero ring, so
-// the four neighbours of a node sit at compile-time offsets (+-1, +-kPitch)
-// from its slot.  Region lane e of the workgroup is node (e % RX, e / RX); the
-// tile descriptor is x = x0 | y0 << 16 (region origin), y = RX | RY << 16,
-// z = ix0 | ix1 << 16, w = iy0 | iy1 << 16 (tile interior [ix0, ix1) x
-// [iy0, iy1)).  All global reads of the tile are issued in one batch before
-// the first barrier: buffer 0 receives q_0 = P u_n and buffer 1 receives
-// v = (I - P) u_n, from which w = A_u v is formed in LDS.  A region node next
-// to the ring sees zeros there instead of the true values of v and q, which is
-// the same one-node-per-substep error front as for q alone, so the interior
-// (at distance >= p from the ring) stays exact.
+// Rect mode.  A tile's region is a rectangle of RX x RY <= 64 x 64 grid nodes
+// (the tile grown by p, clipped to the grid and to the bounding box of its F+
+// nodes grown by one).  Lane x of wavefront v owns column x and the four
+// vertically adjacent rows 4v .. 4v+3, so a node's own value and its north /
+// south neighbours inside the lane's rows live in registers; east / west
+// neighbours and the rows next to another wavefront's come from LDS, where
+// the region is a rectangle with row pitch kPitch and a zero ring (two
+// buffers: substep m reads buffer m & 1 and writes the other).  Lanes and rows
+// outside the rectangle hold zeros.  The tile descriptor is x = x0 | y0 << 16
+// (region origin), y = RX | RY << 16, z = ix0 | ix1 << 16, w = iy0 | iy1 << 16
+// (tile interior [ix0, ix1) x [iy0, iy1)).  All global reads of a tile are
+// issued in one batch before the first barrier; buffer 0 receives q_0 = P u_n
+// and buffer 1 v = (I - P) u_n, from which w = A_u v is formed.  A node next to
+// the ring sees zeros there instead of the true values of v and q: the same
+// one-node-per-substep error front as for q alone, so the tile interior (at
+// distance >= p from the ring) stays exact.
 template <class T>
 __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __restrict__ lk,
-                                               double* __restrict__ lg, T* __restrict__ lq, int s,
-                                               int tile) {
+                                               T* __restrict__ lq, T* __restrict__ ls,
+                                               double* __restrict__ lc, int s, int tile) {
   constexpr int P = kPitch;
-  constexpr int kDummy = kRectCap - P - 1;           // read-only slot of lanes without a node
+  constexpr int R = 4;                                  // rows per lane
   const LevelView& L = a.L;
   const int4 td = a.rtiles[tile];
   const int x0 = td.x & 0xFFFF, y0 = td.x >> 16;
   const int RX = td.y & 0xFFFF, RY = td.y >> 16;
   const int ix0 = td.z & 0xFFFF, ix1 = td.z >> 16, iy0 = td.w & 0xFFFF, iy1 = td.w >> 16;
-  const int n = RX * RY;
-  const float inv_rx = 1.0f / (float)RX;
+  const int tid = threadIdx.x;
+  const int x = tid & 63;
+  const int yb = 4 * __builtin_amdgcn_readfirstlane(tid >> 6);   // first row of this wavefront
+  const bool wave_on = yb < RY;                                  // wavefront holds region rows
+  const int gx = x0 + x;
+  const bool col_on = x < RX && gx < L.nxn;
   const T* __restrict__ u_g = reinterpret_cast<const T*>(a.Ucur) + (size_t)s * a.sstride;
   T* __restrict__ uo_g = reinterpret_cast<T*>(a.Uold) + (size_t)s * a.sstride;
   const double* __restrict__ cf = a.coef + (size_t)s * (L.p + 1);
-  const int tid = threadIdx.x;
   const bool startup = a.startup;
+  const int ld = L.ld;
 
-  // ---- one batch of global reads: nothing read here decides another read
+  // ---- one batch of global reads (nothing read here decides another read)
   const double kv = tid < L.nb ? a.kappa[(size_t)s * L.nb + tid] : 0.0;
-  double gv0 = 0.0, gv1 = 0.0;   // geometry of one column (lanes 0..RX) or row (128..128+RY)
-  if (tid <= RX) {
-    const int g = x0 - 1 + tid;
-    if (g >= 0) {
-      gv0 = L.hx[g];
-      gv1 = L.inv2hx[g];
-    }
-  } else if (tid >= 128 && tid <= 128 + RY) {
-    const int g = y0 - 1 + (tid - 128);
-    if (g >= 0) {
-      gv0 = L.hy[g];
-      gv1 = L.inv2hy[g];
-    }
-  }
-  // Branch-free: lanes off the grid read node (1, 1) and discard it, so every
-  // load of every lane is issued before the first wait.
-  T u[kNPT], uo[kNPT];
-  double im[kNPT];
-  int slot[kNPT], kk[kNPT], fl[kNPT], xy[kNPT];
-  uint32_t cb[kNPT];
+  // per-substep scalars: lc[m] = c1 (m = 0) or c2_m, lc[kMaxP + m] = beta_m
+  const int p = L.p;
+  double cv = 0.0;
+  if (tid < p) cv = cf[1 + tid];
+  else if (tid >= 256 && tid < 256 + p) cv = tid == 256 ? 0.0 : L.beta[tid - 256];
+  const int gxs = min(max(gx, 1), L.nxn - 1);          // geometry column, in bounds off the grid
+  const double hxE = L.hx[gxs], hxW = L.hx[gxs - 1];
+  const double ihE = L.inv2hx[gxs], ihW = L.inv2hx[gxs - 1];
+  double hyv[R + 1], ihy[R + 1];                       // rows gy-1 .. gy+3 (wavefront-uniform)
 #pragma unroll
-  for (int r = 0; r < kNPT; ++r) {
-    const int e = tid + r * kFineThreads;
-    const int y = (int)(((float)e + 0.5f) * inv_rx);
-    const int x = e - y * RX;
-    const int gx = x0 + x, gy = y0 + y;
-    const bool has = e < n;
-    const bool ok = has && gx < L.nxn && gy < L.nyn;
-    const bool in = ok && gx >= ix0 && gx < ix1 && gy >= iy0 && gy < iy1;
-    const int k = ok ? gy * L.ld + gx : L.ld + 1;
-    const int kb = (ok && gx >= 1 && gy >= 1) ? k : L.ld + 1;   // cell reads stay in bounds
-    slot[r] = has ? (y + 1) * P + x + 1 : kDummy;
-    xy[r] = x | y << 16;
-    kk[r] = k;
-    const uint32_t f = L.flags[k];
-    const T uc = u_g[k];
-    const double imc = L.invm[k];
-    const T uoc = uo_g[k];
-    const uint32_t c0 = L.cblk[kb], c1 = L.cblk[kb - 1], c2 = L.cblk[kb - L.ld], c3 = L.cblk[kb - L.ld - 1];
-    fl[r] = (ok ? f : 0u) | (has ? 256 : 0) | (in ? 512 : 0);
-    u[r] = ok ? uc : (T)0;
-    im[r] = imc;
-    uo[r] = startup ? (T)0 : uoc;
-    cb[r] = c0 | c1 << 8 | c2 << 16 | c3 << 24;
+  for (int q = 0; q <= R; ++q) {
+    const int g = min(max(y0 + yb - 1 + q, 0), L.nyn - 1);
+    hyv[q] = L.hy[g];
+    ihy[q] = L.inv2hy[g];
   }
-  // ---- LDS fill: kappa table, geometry, zero ring of both buffers, q_0 and v
-  if (tid < L.nb) lk[tid] = kv;
-  if (tid <= RX) {
-    lg[tid] = gv0;
-    lg[128 + tid] = gv1;
-  } else if (tid >= 128 && tid <= 128 + RY) {
-    lg[256 + tid - 128] = gv0;
-    lg[384 + tid - 128] = gv1;
-  }
+  T u[R], uo[R];
+  double im[R];
+  uint32_t f[R];
+  uint32_t cbE[R + 1], cbW[R + 1];                     // cell blocks of cell rows gy-1 .. gy+3
+  const int gyb = y0 + yb;
   {
-    const int nr = 2 * (RX + 2) + 2 * RY;
-    if (tid < nr) {
-      int z;
-      if (tid < RX + 2) z = tid;                                        // row 0
-      else if (tid < 2 * (RX + 2)) z = (RY + 1) * P + (tid - (RX + 2));   // row RY + 1
-      else {
-        const int t = tid - 2 * (RX + 2);
-        z = (t >> 1) + 1;                                                 // rows 1..RY
-        z = z * P + ((t & 1) ? RX + 1 : 0);
-      }
-      lq[z] = (T)0;
-      lq[kRectCap + z] = (T)0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool ok = wave_on && col_on && yb + r < RY && gyb + r < L.nyn;
+      const int k = ok ? (gyb + r) * ld + gx : ld + 1;
+      f[r] = ok ? (uint32_t)L.flags[k] : 0u;
+      u[r] = ok ? u_g[k] : (T)0;
+      im[r] = L.invm[k];
+      uo[r] = startup ? (T)0 : uo_g[k];
+    }
+#pragma unroll
+    for (int q = 0; q <= R; ++q) {
+      const int cy = min(max(gyb - 1 + q, 0), L.nyn - 2);
+      const int kc = cy * ld + gxs;
+      cbE[q] = L.cblk[kc];
+      cbW[q] = L.cblk[kc - 1];
     }
   }
+  // ---- LDS fill: kappa table, q_0 = P u and v = (I - P) u of all rows, the zero ring
+  if (tid < L.nb) lk[tid] = kv;
+  if (tid < p) lc[tid] = cv;
+  else if (tid >= 256 && tid < 256 + p) lc[kMaxP + tid - 256] = cv;
+  const int base = (yb + 1) * P + x;                   // slot of (x - 1, yb)
 #pragma unroll
-  for (int r = 0; r < kNPT; ++r) {
-    if (!(fl[r] & 256)) continue;
-    const bool pi = fl[r] & F_P;
-    lq[slot[r]] = pi ? u[r] : (T)0;
-    lq[kRectCap + slot[r]] = pi ? (T)0 : u[r];
+  for (int r = 0; r < R; ++r) {
+    const bool pi = f[r] & F_P;
+    lq[base + r * P + 1] = pi ? u[r] : (T)0;
+    lq[kRectCap + base + r * P + 1] = pi ? (T)0 : u[r];
+  }
+  if (tid < 2 * P) {                                   // rows -1 and kRectH
+    const int z = tid < P ? tid : (kRectH + 1) * P + (tid - P);
+    lq[z] = (T)0;
+    lq[kRectCap + z] = (T)0;
+  } else if (tid < 2 * P + 2 * kRectH) {               // columns -1 and kRectW
+    const int t = tid - 2 * P;
+    const int z = ((t >> 1) + 1) * P + ((t & 1) ? P - 1 : 0);
+    lq[z] = (T)0;
+    lq[kRectCap + z] = (T)0;
   }
   __syncthreads();
 
-  // ---- scaled edge coefficients and w = A_u (I - P) u_n; fl becomes
-  //      bit 0: in P, bit 1: interior F+ node (written back), bit 3: lane has a slot
-  T d[kNPT], dp[kNPT], w[kNPT];
-  T aE[kNPT], aW[kNPT], aN[kNPT], aS[kNPT];
+  // ---- scaled edge coefficients and w = A_u (I - P) u_n
+  T aE[R], aW[R], aN[R], aS[R], w[R], q[R], up[R], pm[R];
+  uint32_t wmask = 0;                                  // bit r: row r is written back
+  {
+    double kE[R + 1], kW[R + 1];
 #pragma unroll
-  for (int r = 0; r < kNPT; ++r) {
-    d[r] = dp[r] = w[r] = (T)0;
-    aE[r] = aW[r] = aN[r] = aS[r] = (T)0;
-    const int f = fl[r];
-    fl[r] = ((f & F_P) ? 1 : 0) | (((f & F_FPLUS) && (f & 512)) ? 2 : 0) | ((f & 256) ? 8 : 0);
-    if (f & F_FPLUS) {
-      const int x = xy[r] & 0xFFFF, y = xy[r] >> 16;
-      const double kNE = lk[cb[r] & 0xFF], kNW = lk[(cb[r] >> 8) & 0xFF];
-      const double kSE = lk[(cb[r] >> 16) & 0xFF], kSW = lk[cb[r] >> 24];
-      const double hxE = lg[x + 1], hxW = lg[x], hyN = lg[256 + y + 1], hyS = lg[256 + y];
-      const double cE = (kNE * hyN + kSE * hyS) * lg[128 + x + 1];
-      const double cW = (kNW * hyN + kSW * hyS) * lg[128 + x];
-      const double cN = (kNE * hxE + kNW * hxW) * lg[384 + y + 1];
-      const double cS = (kSE * hxE + kSW * hxW) * lg[384 + y];
-      aE[r] = (T)(im[r] * cE);
-      aW[r] = (T)(im[r] * cW);
-      aN[r] = (T)(im[r] * cN);
-      aS[r] = (T)(im[r] * cS);
-      const T* v = lq + kRectCap + slot[r];
-      const T vi = v[0];
-      w[r] = aE[r] * (vi - v[1]) + aW[r] * (vi - v[-1]) + aN[r] * (vi - v[P]) + aS[r] * (vi - v[-P]);
+    for (int c = 0; c <= R; ++c) {
+      kE[c] = lk[cbE[c]];
+      kW[c] = lk[cbW[c]];
+    }
+    // vertical edges: row r's south edge is row r-1's north edge (same value)
+    double cV[R + 1];
+#pragma unroll
+    for (int c = 0; c <= R; ++c) cV[c] = (kE[c] * hxE + kW[c] * hxW) * ihy[c];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool fp = f[r] & F_FPLUS;
+      const double cE = (kE[r + 1] * hyv[r + 1] + kE[r] * hyv[r]) * ihE;
+      const double cW = (kW[r + 1] * hyv[r + 1] + kW[r] * hyv[r]) * ihW;
+      aE[r] = fp ? (T)(im[r] * cE) : (T)0;
+      aW[r] = fp ? (T)(im[r] * cW) : (T)0;
+      aN[r] = fp ? (T)(im[r] * cV[r + 1]) : (T)0;
+      aS[r] = fp ? (T)(im[r] * cV[r]) : (T)0;
+      const bool pi = f[r] & F_P;
+      const bool in = gx >= ix0 && gx < ix1 && y0 + yb + r >= iy0 && y0 + yb + r < iy1;
+      if (fp && in) wmask |= 1u << r;
+      up[r] = pi ? u[r] : (T)0;
+      pm[r] = pi ? (T)1 : (T)0;
+      q[r] = up[r];
+      ls[r * kFineThreads + tid] = startup ? u[r] : (T)2 * u[r] - uo[r];   // this lane's own slots
+    }
+    T v[R + 2];                                        // v of rows yb-1 .. yb+4
+    const T* vb = lq + kRectCap + base + 1;
+    v[0] = vb[-P];
+    v[R + 1] = vb[R * P];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r + 1] = (f[r] & F_P) ? (T)0 : u[r];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const T vi = v[r + 1];
+      const T vW = lq[kRectCap + base + r * P], vE = lq[kRectCap + base + r * P + 2];
+      w[r] = aE[r] * (vi - vE) + aW[r] * (vi - vW) + aN[r] * (vi - v[r + 2]) + aS[r] * (vi - v[r]);
     }
   }
   __syncthreads();   // buffer 1 is overwritten by the first substep
 
-  const int p = L.p;
-  // substep m reads buffer B = m & 1 and writes buffer 1 - B
+  // Per-lane LDS slots in the two buffers, hidden from the compiler's address
+  // folding so that every neighbour read is a base plus an immediate offset:
+  // oW = slot of (x - 1, yb), oS = slot of (x, yb - 1).
+  int oW[2] = {base, kRectCap + base};
+  int oS[2] = {base + 1 - P, kRectCap + base + 1 - P};
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    asm volatile("" : "+v"(oW[k]));
+    asm volatile("" : "+v"(oS[k]));
+  }
+  // Substep m reads buffer B = m & 1 and writes buffer 1 - B.  The increments
+  // d_m+1 and d_m-1 share a register: at even m, d0 holds d_m and d1 d_m-1
+  // (overwritten by d_m+1); at odd m the roles swap, so no copies are needed.
+  T d0[R], d1[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) d0[r] = d1[r] = (T)0;
   auto substep = [&](int m, auto Bc) {
     constexpr int B = decltype(Bc)::value;
-    const T c = (T)cf[1 + m];   // c1 for m = 0, c2_m otherwise
-    const T b = m > 0 ? (T)L.beta[m] : (T)0;
+    T* dc = B == 0 ? d0 : d1;       // d_m
+    T* dq = B == 0 ? d1 : d0;       // d_m-1 in, d_m+1 out
+    const T c = (T)lc[m];           // c1 for m = 0, c2_m otherwise
+    const T b = (T)lc[kMaxP + m];   // beta_m (0 for m = 0)
     const T b1 = (T)1 + b;
-    T qn[kNPT];
+    if (wave_on) {
+      const T* lb = lq + oW[B];
+      const T qS0 = lq[oS[B]], qN3 = lb[R * P + 1];
+      T qn[R];
 #pragma unroll
-    for (int r = 0; r < kNPT; ++r) {
-      const T* q = lq + B * kRectCap + slot[r];
-      const T qS = q[-P], qW = q[-1], qi = q[0];
-      const T qE = q[1], qN = q[P];
-      // edge form: constants are annihilated exactly (no assembled diagonal)
-      const T acc = aE[r] * (qi - qE) + aW[r] * (qi - qW) + aN[r] * (qi - qN) + aS[r] * (qi - qS);
-      const T rr = w[r] + acc;
-      const T dn = b1 * d[r] - b * dp[r] - c * rr;
-      dp[r] = d[r];
-      d[r] = dn;
-      qn[r] = (fl[r] & 1) ? u[r] + dn : (T)0;
-    }
-    if (m + 1 < p) {
+      for (int r = 0; r < R; ++r) {
+        const T qW = lb[r * P], qE = lb[r * P + 2];
+        const T qi = q[r];
+        const T qN = r + 1 < R ? q[r + 1] : qN3;
+        const T qS = r > 0 ? q[r - 1] : qS0;
+        // edge form: constants are annihilated exactly (no assembled diagonal)
+        const T acc = aE[r] * (qi - qE) + aW[r] * (qi - qW) + aN[r] * (qi - qN) + aS[r] * (qi - qS);
+        const T rr = w[r] + acc;
+        const T dn = b1 * dc[r] - b * dq[r] - c * rr;
+        dq[r] = dn;
+        qn[r] = pm[r] * dn + up[r];          // P (u_n + d_m+1): u_n + d exactly on P, 0 elsewhere
+      }
 #pragma unroll
-      for (int r = 0; r < kNPT; ++r)
-        if (fl[r] & 8) lq[(1 - B) * kRectCap + slot[r]] = qn[r];
-      __syncthreads();
+      for (int r = 0; r < R; ++r) q[r] = qn[r];
+      if (m + 1 < p) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) lq[oW[1 - B] + r * P + 1] = q[r];
+      }
     }
+    if (m + 1 < p) __syncthreads();
   };
   for (int m = 0; m < p; m += 2) {
     substep(m, std::integral_constant<int, 0>{});
     if (m + 1 < p) substep(m + 1, std::integral_constant<int, 1>{});
   }
+  T d[R];
 #pragma unroll
-  for (int r = 0; r < kNPT; ++r) {
-    if (!(fl[r] & 2)) continue;
-    uo_g[kk[r]] = startup ? (u[r] + d[r]) : ((T)2 * u[r] - uo[r] + (T)2 * d[r]);
-  }
+  for (int r = 0; r < R; ++r) d[r] = (p & 1) ? d1[r] : d0[r];   // d_p
+  const T ds = startup ? (T)1 : (T)2;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (wmask & (1u << r)) uo_g[(gyb + r) * ld + gx] = ls[r * kFineThreads + tid] + ds * d[r];
 }
 
 template <bool RECT, class T>
 __global__ __launch_bounds__(kFineThreads) void k_fine(StepArgs a) {
-  __shared__ T lq[2 * kRectCap];
+  __shared__ T lq[kLdsSlots];
+  __shared__ T ls[RECT ? 4 * kFineThreads : 1];   // rect mode: final-update term per node
   __shared__ double lk[256];
-  __shared__ double lg[RECT ? 512 : 1];   // rect mode: column / row geometry of the region
+  __shared__ double lc[RECT ? 2 * kMaxP : 1];     // rect mode: per-substep scalars
   const int G = a.n_fine * a.active;
   const int Lid = (int)(blockIdx.x & 7) * a.per_xcd + (int)(blockIdx.x >> 3);
   if (Lid >= G) return;
   const int s = a.s0 + Lid / a.n_fine;
   if (RECT) {
-    fine_tile_rect<T>(a, lk, lg, lq, s, Lid % a.n_fine);
+    fine_tile_rect<T>(a, lk, lq, ls, lc, s, Lid % a.n_fine);
   } else {
     load_kappa(a, s, lk);
     fine_tile_compact<T>(a, lk, lq, s, Lid % a.n_fine);
@@ -443,9 +473,10 @@ __global__ __launch_bounds__(kFineThreads) void k_fine(StepArgs a) {
 
 template <bool RECT>
 __global__ __launch_bounds__(kFineThreads) void k_fine_multi(MultiArgs m) {
-  __shared__ double lq[2 * kRectCap];
+  __shared__ double lq[kLdsSlots];
+  __shared__ double ls[RECT ? 4 * kFineThreads : 1];
   __shared__ double lk[256];
-  __shared__ double lg[RECT ? 512 : 1];
+  __shared__ double lc[RECT ? 2 * kMaxP : 1];
   const int Lid = (int)(blockIdx.x & 7) * m.per_xcd + (int)(blockIdx.x >> 3);
   if (Lid >= m.wg_off[m.n_jobs]) return;
   const int j = find_job(m, Lid);
@@ -453,7 +484,7 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_multi(MultiArgs m) {
   const int local = Lid - m.wg_off[j];
   const int s = local / a.n_fine;
   if (RECT) {
-    fine_tile_rect<double>(a, lk, lg, lq, s, local % a.n_fine);
+    fine_tile_rect<double>(a, lk, lq, ls, lc, s, local % a.n_fine);
   } else {
     load_kappa(a, s, lk);
     fine_tile_compact<double>(a, lk, lq, s, local % a.n_fine);
@@ -513,8 +544,7 @@ std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int
         by0 = std::max(by0 - 1, gy0);
         by1 = std::min(by1 + 1, gy1);
         const int rx = bx1 - bx0, ry = by1 - by0;
-        if (rx + 2 > kPitch || (ry + 1) * kPitch + rx + 1 >= kRectCap || rx * ry > kRegionCap)
-          return "region rectangle exceeds LDS capacity";
+        if (rx > kRectW || ry > kRectH) return "region rectangle exceeds 64 x 64 nodes";
         const int ix0 = std::max(tx, 0), ix1 = std::min(tx + TX, nxn);
         const int iy0 = std::max(ty, 0), iy1 = std::min(ty + TY, nyn);
         T.rtiles.push_back(make_int4(bx0 | by0 << 16, rx | ry << 16, ix0 | ix1 << 16, iy0 | iy1 << 16));
