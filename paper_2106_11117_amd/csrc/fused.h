@@ -13,16 +13,18 @@ namespace lts {
 constexpr int kFineThreads = 1024;                  // threads per workgroup
 constexpr int kNPT = 4;                             // region nodes per thread
 constexpr int kRegionCap = kFineThreads * kNPT;     // nodes of one fine-tile region
-constexpr int kCoarseRows = 16;                     // rows walked by one coarse wavefront
+constexpr int kCoarseRows = 16;                     // rows of one coarse item (4 per wavefront)
 constexpr int kRectW = 64;                          // rect mode: region columns (one per lane)
 constexpr int kRectH = 4 * (kFineThreads / 64);     // rect mode: region rows (4 per lane)
 constexpr int kPitch = kRectW + 2;                  // LDS row pitch of the rectangle (zero ring)
 constexpr int kRectCap = kPitch * (kRectH + 2);     // LDS slots of one rectangle buffer
 constexpr int kLdsSlots = 2 * kRectCap > kRegionCap + 1 ? 2 * kRectCap : kRegionCap + 1;
-constexpr int kCoarseThreads = 256;                 // coarse workgroup: 4 wavefronts, one item each
+constexpr int kCoarseThreads = 256;                 // coarse workgroup: one item, 4 rows per wavefront
 constexpr int kMaxAdjP = 64;                        // largest p supported by the adjoint
 constexpr int kMaxP = 256;                          // largest p of a level (substep scalars in LDS)
 constexpr int kMaxJobs = 32;                        // jobs of one batched launch
+static_assert(kCoarseRows == 4 * (kCoarseThreads / 64), "coarse item rows = 4 per wavefront");
+static_assert(kCoarseRows <= 16, "coarse row mask is 16 bits");
 
 struct TilingHost {
   int TX = 0, TY = 0;
@@ -34,7 +36,7 @@ struct TilingHost {
   std::vector<int4> ent;            // compact mode: region entries (see lts_fused.hip)
   std::vector<int2> tiles;          // compact mode: (offset, length)
   std::vector<int4> rtiles;         // rect mode: region rectangle and tile interior (packed)
-  std::vector<int2> citems;         // (i0, j0)
+  std::vector<int4> citems;         // coarse items: origin, column mask, row mask
 };
 
 std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int oy, bool rect,

@@ -43,7 +43,7 @@ struct StepArgs {
   const int4* __restrict__ ent;      // region entries of all fine tiles
   const int2* __restrict__ tiles;    // compact mode: (offset, length) per fine tile
   const int4* __restrict__ rtiles;   // rect mode: packed region / interior per fine tile
-  const int2* __restrict__ citems;   // (i0, j0) per coarse item
+  const int4* __restrict__ citems;   // per coarse item: origin, column mask, row mask
   int n_fine, n_coarse, wg_per_sample, per_xcd, active;
   const double* __restrict__ kappa;  // [S][nb] (sorted sample order)
   const double* __restrict__ coef;   // [S][p+1]
@@ -65,45 +65,84 @@ struct MultiArgs {
 
 namespace {
 
-// One coarse item per wavefront: lane = grid column, walking down the rows
-// with the north/centre/south values and the cell coefficients of the row
-// below carried in registers.
+// One coarse item (64 grid columns x kCoarseRows rows) per workgroup: lane =
+// column, wavefront v = rows 4v .. 4v+3 of the item.  Every global read of a
+// wavefront is issued in one batch (u of its rows and the rows above and
+// below, u_n-1, 1/m, flags, cell blocks), then the four rows are updated.  The
+// item descriptor is x = i0 | j0 << 16, (y, z) = 64-bit mask of the columns
+// holding a DOF outside F+, w = 16-bit mask of such rows; lanes and wavefronts
+// without such a DOF return at once.
 template <class T>
-__device__ __forceinline__ void coarse_body(const StepArgs& a, const double* __restrict__ lk, int s,
-                                            int item) {
+__device__ __forceinline__ void coarse_body(const StepArgs& a, double* __restrict__ lk, int s, int item) {
   const LevelView& L = a.L;
-  if (item >= a.n_coarse) return;
-  const int2 it = a.citems[item];
-  const int i = it.x + (int)(threadIdx.x & 63);
-  if (i < 1 || i > L.nxn - 2) return;
+  const int4 it = a.citems[item];
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const uint32_t rows = ((uint32_t)it.w >> (4 * wv)) & 0xFu;
+  const int lane = threadIdx.x & 63;
+  const uint64_t lm = (uint64_t)(uint32_t)it.y | (uint64_t)(uint32_t)it.z << 32;
+  const bool live = rows != 0 && ((lm >> lane) & 1);
+  // a live lane's column holds a DOF, so 1 <= i <= nxn - 2; other lanes read a
+  // clamped column and store nothing
+  const int i = min(max((it.x & 0xFFFF) + lane, 1), L.nxn - 2);
+  const int j0 = (it.x >> 16) + 4 * wv;               // rows j0 .. j0 + 3
+  const int ld = L.ld;
   const T* __restrict__ u = reinterpret_cast<const T*>(a.Ucur) + (size_t)s * a.sstride;
   T* __restrict__ uo = reinterpret_cast<T*>(a.Uold) + (size_t)s * a.sstride;
   const T ap = (T)a.coef[(size_t)s * (L.p + 1)];
-  const int jb = max(it.y, 1), je = min(it.y + kCoarseRows, L.nyn - 1);
-  if (jb >= je) return;
+  const bool startup = a.startup;
+  constexpr int R = 4;
+  // ---- one batch of reads (with the sample's kappa table); rows off the grid
+  //      are clamped and never used
+  const double kv = (int)threadIdx.x < L.nb ? a.kappa[(size_t)s * L.nb + threadIdx.x] : 0.0;
   const double hxE = L.hx[i], hxW = L.hx[i - 1], ihE = L.inv2hx[i], ihW = L.inv2hx[i - 1];
-  size_t k = (size_t)jb * L.ld + i;
-  T uS = u[k - L.ld], uC = u[k];
-  double kSW = lk[L.cblk[k - L.ld - 1]], kSE = lk[L.cblk[k - L.ld]];
-#pragma unroll 2
-  for (int j = jb; j < je; ++j, k += L.ld) {
-    const T uN = u[k + L.ld], uE = u[k + 1], uW = u[k - 1];
-    const uint8_t f = L.flags[k];
-    const double kNW = lk[L.cblk[k - 1]], kNE = lk[L.cblk[k]];
-    if ((f & (F_DOF | F_FPLUS)) == F_DOF) {
-      const double hyN = L.hy[j], hyS = L.hy[j - 1];
-      const double cE = (kNE * hyN + kSE * hyS) * ihE;
-      const double cW = (kNW * hyN + kSW * hyS) * ihW;
-      const double cN = (kNE * hxE + kNW * hxW) * L.inv2hy[j];
-      const double cS = (kSE * hxE + kSW * hxW) * L.inv2hy[j - 1];
-      const T w = (T)L.invm[k] * ((T)cE * (uC - uE) + (T)cW * (uC - uW) + (T)cN * (uC - uN) + (T)cS * (uC - uS));
-      const T d = ap * w;
-      uo[k] = a.startup ? (uC + d) : ((T)2 * uC - uo[k] + (T)2 * d);
-    }
-    uS = uC;
-    uC = uN;
-    kSW = kNW;
-    kSE = kNE;
+  T uc[R + 2], ue[R], uw[R], uold[R];
+  double im[R], hy[R + 1], ihy[R + 1];
+  uint32_t f[R], cE[R + 1], cW[R + 1];
+#pragma unroll
+  for (int q = 0; q < R + 2; ++q) {
+    const int j = min(max(j0 - 1 + q, 0), L.nyn - 1);
+    uc[q] = u[(size_t)j * ld + i];
+  }
+#pragma unroll
+  for (int q = 0; q <= R; ++q) {
+    const int j = min(max(j0 - 1 + q, 0), L.nyn - 2);  // cell row below node row j0 + q
+    hy[q] = L.hy[j];
+    ihy[q] = L.inv2hy[j];
+    cE[q] = L.cblk[(size_t)j * ld + i];
+    cW[q] = L.cblk[(size_t)j * ld + i - 1];
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = min(j0 + r, L.nyn - 1);
+    const size_t k = (size_t)j * ld + i;
+    f[r] = L.flags[k];        // a clamped row is a boundary row: never a DOF
+    ue[r] = u[k + 1];
+    uw[r] = u[k - 1];
+    im[r] = L.invm[k];
+    uold[r] = startup ? (T)0 : uo[k];
+  }
+  if ((int)threadIdx.x < L.nb) lk[threadIdx.x] = kv;
+  __syncthreads();
+  if (!live) return;
+  // ---- update the rows' DOFs outside F+ (edge form)
+  double kE[R + 1], kW[R + 1];
+#pragma unroll
+  for (int q = 0; q <= R; ++q) {
+    kE[q] = lk[cE[q]];
+    kW[q] = lk[cW[q]];
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if ((f[r] & (F_DOF | F_FPLUS)) != F_DOF) continue;
+    const T uS = uc[r], uC = uc[r + 1], uN = uc[r + 2];
+    const double cEg = (kE[r + 1] * hy[r + 1] + kE[r] * hy[r]) * ihE;
+    const double cWg = (kW[r + 1] * hy[r + 1] + kW[r] * hy[r]) * ihW;
+    const double cNg = (kE[r + 1] * hxE + kW[r + 1] * hxW) * ihy[r + 1];
+    const double cSg = (kE[r] * hxE + kW[r] * hxW) * ihy[r];
+    const T w = (T)im[r] * ((T)cEg * (uC - ue[r]) + (T)cWg * (uC - uw[r]) + (T)cNg * (uC - uN) +
+                            (T)cSg * (uC - uS));
+    const T d = ap * w;
+    uo[(size_t)(j0 + r) * ld + i] = startup ? (uC + d) : ((T)2 * uC - uold[r] + (T)2 * d);
   }
 }
 
@@ -112,16 +151,16 @@ __device__ __forceinline__ void load_kappa(const StepArgs& a, int s, double* __r
   __syncthreads();
 }
 
+// Workgroups run sample-fastest over (item, sample): consecutive workgroups of
+// an XCD share the item's mesh arrays in that XCD's L2.
 template <class T>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse(StepArgs a) {
   __shared__ double lk[256];
-  const int wpc = (a.n_coarse + 3) / 4;
-  const int G = wpc * a.active;
+  const int G = a.n_coarse * a.active;
   const int Lid = (int)(blockIdx.x & 7) * a.per_xcd + (int)(blockIdx.x >> 3);
   if (Lid >= G) return;
-  const int s = a.s0 + Lid / wpc;
-  load_kappa(a, s, lk);
-  coarse_body<T>(a, lk, s, (Lid % wpc) * 4 + (int)(threadIdx.x >> 6));
+  const int s = a.s0 + Lid % a.active;
+  coarse_body<T>(a, lk, s, Lid / a.active);
 }
 
 // Job of a batched launch: the job whose workgroup range holds Lid.
@@ -146,11 +185,10 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_multi(MultiArgs m) {
   if (Lid >= m.wg_off[m.n_jobs]) return;
   const int j = find_job(m, Lid);
   const StepArgs a = job_args(m, j);
-  const int wpc = (a.n_coarse + 3) / 4;
   const int local = Lid - m.wg_off[j];
-  const int s = local / wpc;
-  load_kappa(a, s, lk);
-  coarse_body<double>(a, lk, s, (local % wpc) * 4 + (int)(threadIdx.x >> 6));
+  const int act = (m.wg_off[j + 1] - m.wg_off[j]) / a.n_coarse;   // active samples of the job
+  const int s = local % act;
+  coarse_body<double>(a, lk, s, local / act);
 }
 
 template <class T>
@@ -584,20 +622,23 @@ std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int
       T.tiles.push_back(make_int2(off, len));
       n_region += len;
     }
+  // coarse items: 64 columns x kCoarseRows rows holding a DOF outside F+, with
+  // the masks of such columns and rows
   for (int ty = 0; ty < nyn; ty += kCoarseRows)
     for (int tx = 0; tx < nxn; tx += 64) {
-      bool any = false;
-      for (int j = ty; j < std::min(ty + kCoarseRows, nyn) && !any; ++j)
+      uint64_t cm = 0;
+      uint32_t rm = 0;
+      for (int j = ty; j < std::min(ty + kCoarseRows, nyn); ++j)
         for (int i = tx; i < std::min(tx + 64, nxn); ++i)
           if ((fl(i, j) & (LTS_NODE_DOF | LTS_NODE_FPLUS)) == LTS_NODE_DOF) {
-            any = true;
-            break;
+            cm |= 1ull << (i - tx);
+            rm |= 1u << (j - ty);
           }
-      if (any) T.citems.push_back(make_int2(tx, ty));
+      if (cm) T.citems.push_back(make_int4(tx | ty << 16, (int)(uint32_t)cm, (int)(uint32_t)(cm >> 32), (int)rm));
     }
   T.n_fine = (int)(rect ? T.rtiles.size() : T.tiles.size());
   T.n_coarse = (int)T.citems.size();
-  T.wg_per_sample = T.n_fine + (T.n_coarse + 3) / 4;
+  T.wg_per_sample = T.n_fine + T.n_coarse;
   T.halo_ratio = n_fplus ? (double)n_region / n_fplus : 1.0;
   return "";
 }
@@ -616,7 +657,7 @@ lts_status upload_tiling(lts_ctx c, const TilingHost& T, TilingDev& D) {
   LTS_HIP(c, D.ent.ensure(std::max<size_t>(T.ent.size() * sizeof(int4), 16)));
   LTS_HIP(c, D.tiles.ensure(std::max<size_t>(T.tiles.size() * sizeof(int2), 8)));
   LTS_HIP(c, D.rtiles.ensure(std::max<size_t>(T.rtiles.size() * sizeof(int4), 16)));
-  LTS_HIP(c, D.citems.ensure(std::max<size_t>(T.citems.size() * sizeof(int2), 8)));
+  LTS_HIP(c, D.citems.ensure(std::max<size_t>(T.citems.size() * sizeof(int4), 16)));
   if (!T.ent.empty())
     LTS_HIP(c, hipMemcpy(D.ent.p, T.ent.data(), T.ent.size() * sizeof(int4), hipMemcpyHostToDevice));
   if (!T.tiles.empty())
@@ -624,7 +665,7 @@ lts_status upload_tiling(lts_ctx c, const TilingHost& T, TilingDev& D) {
   if (!T.rtiles.empty())
     LTS_HIP(c, hipMemcpy(D.rtiles.p, T.rtiles.data(), T.rtiles.size() * sizeof(int4), hipMemcpyHostToDevice));
   if (!T.citems.empty())
-    LTS_HIP(c, hipMemcpy(D.citems.p, T.citems.data(), T.citems.size() * sizeof(int2), hipMemcpyHostToDevice));
+    LTS_HIP(c, hipMemcpy(D.citems.p, T.citems.data(), T.citems.size() * sizeof(int4), hipMemcpyHostToDevice));
   return LTS_OK;
 }
 
@@ -683,7 +724,7 @@ lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const 
   a.L = lv.view();
   a.ent = T.ent.as<int4>();
   a.tiles = T.tiles.as<int2>();
-  a.citems = T.citems.as<int2>();
+  a.citems = T.citems.as<int4>();
   a.n_fine = T.n_fine;
   a.n_coarse = T.n_coarse;
   a.rtiles = T.rtiles.as<int4>();
@@ -697,7 +738,7 @@ lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const 
   a.startup = startup;
   a.s0 = s0;
   if (T.n_coarse > 0) {
-    const long long G = (long long)((T.n_coarse + 3) / 4) * active;
+    const long long G = (long long)T.n_coarse * active;
     a.per_xcd = (int)((G + 7) / 8);
     const dim3 grid((unsigned)(8LL * a.per_xcd));
     if (fp32)
@@ -736,7 +777,7 @@ lts_status launch_multi_step(lts_ctx c, const StepArgs* d_jobs, const std::vecto
     m.wg_off[0] = 0;
     for (int j = 0; j < nj; ++j) {
       int w = 0;
-      if (kind == 0) w = (T[j]->n_coarse + 3) / 4;
+      if (kind == 0) w = T[j]->n_coarse;
       else if (kind == 1) w = T[j]->rect ? T[j]->n_fine : 0;
       else w = T[j]->rect ? 0 : T[j]->n_fine;
       m.wg_off[j + 1] = m.wg_off[j] + w * active[j];
@@ -764,7 +805,7 @@ void job_record(const DevLevel& lv, const TilingDev& T, const double* d_kappa, c
   a.L = lv.view();
   a.ent = T.ent.as<int4>();
   a.tiles = T.tiles.as<int2>();
-  a.citems = T.citems.as<int2>();
+  a.citems = T.citems.as<int4>();
   a.n_fine = T.n_fine;
   a.n_coarse = T.n_coarse;
   a.rtiles = T.rtiles.as<int4>();
