@@ -19,6 +19,7 @@ constexpr int kRectH = 4 * (kFineThreads / 64);     // rect mode: region rows (4
 constexpr int kPitch = kRectW + 2;                  // LDS row pitch of the rectangle (zero ring)
 constexpr int kRectCap = kPitch * (kRectH + 2);     // LDS slots of one rectangle buffer
 constexpr int kLdsSlots = 2 * kRectCap > kRegionCap + 1 ? 2 * kRectCap : kRegionCap + 1;
+constexpr int kCoarseGroup = 8;                     // samples per group in the coarse launch order
 constexpr int kCoarseThreads = 256;                 // coarse workgroup: one item, 4 rows per wavefront
 constexpr int kMaxAdjP = 64;                        // largest p supported by the adjoint
 constexpr int kMaxP = 256;                          // largest p of a level (substep scalars in LDS)

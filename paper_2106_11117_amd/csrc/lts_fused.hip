@@ -151,16 +151,36 @@ __device__ __forceinline__ void load_kappa(const StepArgs& a, int s, double* __r
   __syncthreads();
 }
 
-// Workgroups run sample-fastest over (item, sample): consecutive workgroups of
-// an XCD share the item's mesh arrays in that XCD's L2.
+// Workgroup order over (item, sample): samples in groups of kCoarseGroup,
+// item-major inside a group, sample fastest.  Consecutive workgroups of an
+// XCD then share an item's mesh arrays in that XCD's L2 (kCoarseGroup times),
+// and the halo lines of neighbouring items of the same sample were loaded
+// shortly before (kCoarseGroup workgroups back horizontally, one item row of
+// groups vertically).
+__device__ __forceinline__ void coarse_order(int Lid, int n_items, int active, int& item, int& s) {
+  const int full = active / kCoarseGroup;
+  const int span = n_items * kCoarseGroup;
+  if (Lid < full * span) {
+    const int g = Lid / span, rem = Lid - g * span;
+    item = rem / kCoarseGroup;
+    s = g * kCoarseGroup + rem % kCoarseGroup;
+  } else {
+    const int last = active - full * kCoarseGroup;   // ragged last group
+    const int rem = Lid - full * span;
+    item = rem / last;
+    s = full * kCoarseGroup + rem % last;
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse(StepArgs a) {
   __shared__ double lk[256];
   const int G = a.n_coarse * a.active;
   const int Lid = (int)(blockIdx.x & 7) * a.per_xcd + (int)(blockIdx.x >> 3);
   if (Lid >= G) return;
-  const int s = a.s0 + Lid % a.active;
-  coarse_body<T>(a, lk, s, Lid / a.active);
+  int item, s;
+  coarse_order(Lid, a.n_coarse, a.active, item, s);
+  coarse_body<T>(a, lk, a.s0 + s, item);
 }
 
 // Job of a batched launch: the job whose workgroup range holds Lid.
@@ -187,8 +207,9 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_multi(MultiArgs m) {
   const StepArgs a = job_args(m, j);
   const int local = Lid - m.wg_off[j];
   const int act = (m.wg_off[j + 1] - m.wg_off[j]) / a.n_coarse;   // active samples of the job
-  const int s = local % act;
-  coarse_body<double>(a, lk, s, local / act);
+  int item, s;
+  coarse_order(local, a.n_coarse, act, item, s);
+  coarse_body<double>(a, lk, s, item);
 }
 
 template <class T>
