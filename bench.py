@@ -183,6 +183,47 @@ def mlmc_bench(no_cpu: bool):
     ctx.close()
 
 
+def adjoint_bench(samples: int, K: int):
+    """Discrete adjoint (backward LF-LTS) on the throughput workload: time of one
+    lts_backward over the batch (checkpoints every K steps, forward states
+    recomputed per segment) against one forward solve of the same batch."""
+    import numpy as np
+    import torch
+
+    import paper_2106_11117_amd as P
+
+    dev = torch.device("cuda:0")
+    ctx = P.Context(0)
+    lid = ctx.add_rect_level(P.box_rule(N_BASE, box=BOX, ref=REF))
+    info = ctx.level_info(lid)
+    s = P.gen_samples(0, 0, 0, samples, P.sample_rule(), info["h"])
+    kap = torch.tensor(s["kappa"], device=dev)
+    x0 = torch.tensor(s["x0"], device=dev)
+    ns = torch.tensor(s["n_steps"], device=dev)
+    dt = torch.tensor(s["dt"], device=dev)
+    dl = torch.ones(samples, dtype=torch.float64, device=dev)
+    ctx.forward(lid, kap[:8], x0[:8], ns[:8], dt[:8])      # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    qf = ctx.forward(lid, kap, x0, ns, dt)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    q, g = ctx.backward(lid, kap, x0, ns, dt, dl, K=K)
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    per_step = (info["n_dof"] - info["n_P"]) + info["p"] * info["n_P"]
+    out = {"metric": "discrete adjoint (backward LF-LTS) time, relative to the forward solve",
+           "unit": "s", "higher_is_better": False, "data": "synthetic (Philox seed 0)",
+           "config": {"workload": WORKLOAD, "samples": samples, "K_ckpt": K, "dtype": "f64"},
+           "forward_s": t_fwd, "backward_s": t_bwd, "backward_over_forward": t_bwd / t_fwd,
+           "forward_dof_updates_per_s": float(s["n_steps"].sum()) * per_step / t_fwd,
+           "qoi_equal_to_forward": bool(torch.equal(q, qf)),
+           "grad_abs_max": float(g.abs().max())}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def copy_check(mib: int):
     """Four device-to-device copies of `mib` MiB (read mib, write mib each): the
     reference point that turns the FETCH_SIZE / WRITE_SIZE counters of a profiled
@@ -210,9 +251,14 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-stepping run")
     ap.add_argument("--copy-check", type=int, default=0, metavar="MIB",
                     help="only run 4 plain device copies of MIB MiB (calibrates HBM byte counters)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="only time the discrete adjoint against the forward solve (K = 64)")
     ap.add_argument("--mlmc", action="store_true",
                     help="only run the MLMC wall-time comparison (graded L-shape, Algorithm 1)")
     args = ap.parse_args()
+    if args.adjoint:
+        adjoint_bench(args.samples, 64)
+        return
     if args.mlmc:
         mlmc_bench(args.no_cpu)
         return
