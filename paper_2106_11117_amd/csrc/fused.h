@@ -16,13 +16,12 @@ constexpr int kRegionCap = kFineThreads * kNPT;     // nodes of one fine-tile re
 constexpr int kCoarseRows = 16;                     // rows of one coarse item (4 per wavefront)
 constexpr int kRectW = 64;                          // rect mode: region columns (one per lane)
 constexpr int kRectH = 4 * (kFineThreads / 64);     // rect mode: region rows (4 per lane)
-constexpr int kPitch = kRectW + 2;                  // LDS row pitch of the rectangle (zero ring)
-constexpr int kRectCap = kPitch * (kRectH + 2);     // LDS slots of one rectangle buffer
-constexpr int kLdsSlots = 2 * kRectCap > kRegionCap + 1 ? 2 * kRectCap : kRegionCap + 1;
+constexpr int kBndRows = 2 * (kFineThreads / 64) + 2;   // rect mode: boundary rows + 2 zero rows
+constexpr int kBndSlots = kBndRows * 64;                 // rect mode: slots of one buffer
+constexpr int kLdsSlots = 2 * kBndSlots > kRegionCap + 1 ? 2 * kBndSlots : kRegionCap + 1;
 constexpr int kCoarseGroup = 8;                     // samples per group in the coarse launch order
 constexpr int kCoarseThreads = 256;                 // coarse workgroup: one item, 4 rows per wavefront
 constexpr int kMaxAdjP = 64;                        // largest p supported by the adjoint
-constexpr int kMaxP = 256;                          // largest p of a level (substep scalars in LDS)
 constexpr int kMaxJobs = 32;                        // jobs of one batched launch
 static_assert(kCoarseRows == 4 * (kCoarseThreads / 64), "coarse item rows = 4 per wavefront");
 static_assert(kCoarseRows <= 16, "coarse row mask is 16 bits");

@@ -302,28 +302,57 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const doubl
 }
 
 
+// Value of the next / previous lane of the wavefront (DPP wavefront shift by
+// one lane); the last / first lane reads 0.  All lanes must be active.
+__device__ __forceinline__ double lane_next(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x130, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_prev(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x138, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float lane_next(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float lane_prev(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+// Broadcast lane m's value of v (m wavefront-uniform).
+__device__ __forceinline__ double lane_bcast(double v, int m) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), m);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), m);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Rect mode.  A tile's region is a rectangle of RX x RY <= 64 x 64 grid nodes
 // (the tile grown by p, clipped to the grid and to the bounding box of its F+
 // nodes grown by one).  Lane x of wavefront v owns column x and the four
-// vertically adjacent rows 4v .. 4v+3, so a node's own value and its north /
-// south neighbours inside the lane's rows live in registers; east / west
-// neighbours and the rows next to another wavefront's come from LDS, where
-// the region is a rectangle with row pitch kPitch and a zero ring (two
-// buffers: substep m reads buffer m & 1 and writes the other).  Lanes and rows
-// outside the rectangle hold zeros.  The tile descriptor is x = x0 | y0 << 16
-// (region origin), y = RX | RY << 16, z = ix0 | ix1 << 16, w = iy0 | iy1 << 16
-// (tile interior [ix0, ix1) x [iy0, iy1)).  All global reads of a tile are
-// issued in one batch before the first barrier; buffer 0 receives q_0 = P u_n
-// and buffer 1 v = (I - P) u_n, from which w = A_u v is formed.  A node next to
-// the ring sees zeros there instead of the true values of v and q: the same
-// one-node-per-substep error front as for q alone, so the tile interior (at
-// distance >= p from the ring) stays exact.
+// vertically adjacent rows 4v .. 4v+3, all in registers: east / west
+// neighbours come from the adjacent lanes by DPP wavefront shifts (lanes 0 and
+// 63 read 0, the zero ring of the region), north / south neighbours inside the
+// four rows from the lane's own registers, and only the rows next to another
+// wavefront's go through LDS, where each wavefront publishes its top and
+// bottom row (two buffers: substep m reads buffer m & 1 and writes the other;
+// zero rows above wavefront 0 and below the last).  Lanes and rows outside the
+// rectangle hold zeros.  The tile descriptor is x = x0 | y0 << 16 (region
+// origin), y = RX | RY << 16, z = ix0 | ix1 << 16, w = iy0 | iy1 << 16 (tile
+// interior [ix0, ix1) x [iy0, iy1)).  All global reads of a tile are issued in
+// one batch before the first barrier.  w = A_u (I - P) u_n is formed from
+// v = (I - P) u_n the same way.  A node next to the region border sees zeros
+// beyond it instead of the true values of v and q: the same one-node-per-
+// substep error front as for q alone, so the tile interior (at distance >= p
+// from the border) stays exact.
 template <class T>
 __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __restrict__ lk,
-                                               T* __restrict__ lq, T* __restrict__ ls,
-                                               double* __restrict__ lc, int s, int tile) {
-  constexpr int P = kPitch;
+                                               T* __restrict__ lq, T* __restrict__ ls, int s, int tile) {
   constexpr int R = 4;                                  // rows per lane
+  constexpr int W = 64;                                 // boundary-row buffer pitch
   const LevelView& L = a.L;
   const int4 td = a.rtiles[tile];
   const int x0 = td.x & 0xFFFF, y0 = td.x >> 16;
@@ -331,8 +360,9 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __rest
   const int ix0 = td.z & 0xFFFF, ix1 = td.z >> 16, iy0 = td.w & 0xFFFF, iy1 = td.w >> 16;
   const int tid = threadIdx.x;
   const int x = tid & 63;
-  const int yb = 4 * __builtin_amdgcn_readfirstlane(tid >> 6);   // first row of this wavefront
-  const bool wave_on = yb < RY;                                  // wavefront holds region rows
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int yb = 4 * wv;                                // first row of this wavefront
+  const bool wave_on = yb < RY;                         // wavefront holds region rows
   const int gx = x0 + x;
   const bool col_on = x < RX && gx < L.nxn;
   const T* __restrict__ u_g = reinterpret_cast<const T*>(a.Ucur) + (size_t)s * a.sstride;
@@ -340,14 +370,13 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __rest
   const double* __restrict__ cf = a.coef + (size_t)s * (L.p + 1);
   const bool startup = a.startup;
   const int ld = L.ld;
+  const int p = L.p;                                    // <= 64 in rect mode
 
   // ---- one batch of global reads (nothing read here decides another read)
   const double kv = tid < L.nb ? a.kappa[(size_t)s * L.nb + tid] : 0.0;
-  // per-substep scalars: lc[m] = c1 (m = 0) or c2_m, lc[kMaxP + m] = beta_m
-  const int p = L.p;
-  double cv = 0.0;
-  if (tid < p) cv = cf[1 + tid];
-  else if (tid >= 256 && tid < 256 + p) cv = tid == 256 ? 0.0 : L.beta[tid - 256];
+  // per-substep scalars, lane m of every wavefront: c1 (m = 0) or c2_m, beta_m
+  const double cvec = x < p ? cf[1 + x] : 0.0;
+  const double bvec = (x >= 1 && x < p) ? L.beta[x] : 0.0;
   const int gxs = min(max(gx, 1), L.nxn - 1);          // geometry column, in bounds off the grid
   const double hxE = L.hx[gxs], hxW = L.hx[gxs - 1];
   const double ihE = L.inv2hx[gxs], ihW = L.inv2hx[gxs - 1];
@@ -363,44 +392,39 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __rest
   uint32_t f[R];
   uint32_t cbE[R + 1], cbW[R + 1];                     // cell blocks of cell rows gy-1 .. gy+3
   const int gyb = y0 + yb;
-  {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const bool ok = wave_on && col_on && yb + r < RY && gyb + r < L.nyn;
-      const int k = ok ? (gyb + r) * ld + gx : ld + 1;
-      f[r] = ok ? (uint32_t)L.flags[k] : 0u;
-      u[r] = ok ? u_g[k] : (T)0;
-      im[r] = L.invm[k];
-      uo[r] = startup ? (T)0 : uo_g[k];
-    }
-#pragma unroll
-    for (int q = 0; q <= R; ++q) {
-      const int cy = min(max(gyb - 1 + q, 0), L.nyn - 2);
-      const int kc = cy * ld + gxs;
-      cbE[q] = L.cblk[kc];
-      cbW[q] = L.cblk[kc - 1];
-    }
-  }
-  // ---- LDS fill: kappa table, q_0 = P u and v = (I - P) u of all rows, the zero ring
-  if (tid < L.nb) lk[tid] = kv;
-  if (tid < p) lc[tid] = cv;
-  else if (tid >= 256 && tid < 256 + p) lc[kMaxP + tid - 256] = cv;
-  const int base = (yb + 1) * P + x;                   // slot of (x - 1, yb)
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const bool pi = f[r] & F_P;
-    lq[base + r * P + 1] = pi ? u[r] : (T)0;
-    lq[kRectCap + base + r * P + 1] = pi ? (T)0 : u[r];
+    const bool ok = wave_on && col_on && yb + r < RY && gyb + r < L.nyn;
+    const int k = ok ? (gyb + r) * ld + gx : ld + 1;
+    f[r] = ok ? (uint32_t)L.flags[k] : 0u;
+    u[r] = ok ? u_g[k] : (T)0;
+    im[r] = L.invm[k];
+    uo[r] = startup ? (T)0 : uo_g[k];
   }
-  if (tid < 2 * P) {                                   // rows -1 and kRectH
-    const int z = tid < P ? tid : (kRectH + 1) * P + (tid - P);
-    lq[z] = (T)0;
-    lq[kRectCap + z] = (T)0;
-  } else if (tid < 2 * P + 2 * kRectH) {               // columns -1 and kRectW
-    const int t = tid - 2 * P;
-    const int z = ((t >> 1) + 1) * P + ((t & 1) ? P - 1 : 0);
-    lq[z] = (T)0;
-    lq[kRectCap + z] = (T)0;
+#pragma unroll
+  for (int q = 0; q <= R; ++q) {
+    const int cy = min(max(gyb - 1 + q, 0), L.nyn - 2);
+    const int kc = cy * ld + gxs;
+    cbE[q] = L.cblk[kc];
+    cbW[q] = L.cblk[kc - 1];
+  }
+  // ---- LDS: kappa table, boundary rows of q_0 = P u (buffer 0) and v = (I - P) u
+  //      (buffer 1), the zero rows
+  T* const lb0 = lq;
+  T* const lb1 = lq + kBndSlots;
+  const int top = (2 * wv + 1) * W + x, bot = (2 * wv + 2) * W + x;   // this wavefront's rows
+  const int below = 2 * wv * W + x, above = (2 * wv + 3) * W + x;     // neighbours' rows
+  if (tid < L.nb) lk[tid] = kv;
+  {
+    const bool p0 = f[0] & F_P, p3 = f[R - 1] & F_P;
+    lb0[top] = p0 ? u[0] : (T)0;
+    lb0[bot] = p3 ? u[R - 1] : (T)0;
+    lb1[top] = p0 ? (T)0 : u[0];
+    lb1[bot] = p3 ? (T)0 : u[R - 1];
+  }
+  if (tid < 4 * W) {                                   // zero rows 0 and kBndRows - 1
+    const int z = (tid & (2 * W - 1)) < W ? (tid & (W - 1)) : (kBndRows - 1) * W + (tid & (W - 1));
+    (tid < 2 * W ? lb0 : lb1)[z] = (T)0;
   }
   __syncthreads();
 
@@ -428,7 +452,7 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __rest
       aN[r] = fp ? (T)(im[r] * cV[r + 1]) : (T)0;
       aS[r] = fp ? (T)(im[r] * cV[r]) : (T)0;
       const bool pi = f[r] & F_P;
-      const bool in = gx >= ix0 && gx < ix1 && y0 + yb + r >= iy0 && y0 + yb + r < iy1;
+      const bool in = gx >= ix0 && gx < ix1 && gyb + r >= iy0 && gyb + r < iy1;
       if (fp && in) wmask |= 1u << r;
       up[r] = pi ? u[r] : (T)0;
       pm[r] = pi ? (T)1 : (T)0;
@@ -436,30 +460,19 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __rest
       ls[r * kFineThreads + tid] = startup ? u[r] : (T)2 * u[r] - uo[r];   // this lane's own slots
     }
     T v[R + 2];                                        // v of rows yb-1 .. yb+4
-    const T* vb = lq + kRectCap + base + 1;
-    v[0] = vb[-P];
-    v[R + 1] = vb[R * P];
+    v[0] = lb1[below];
+    v[R + 1] = lb1[above];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r + 1] = (f[r] & F_P) ? (T)0 : u[r];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const T vi = v[r + 1];
-      const T vW = lq[kRectCap + base + r * P], vE = lq[kRectCap + base + r * P + 2];
+      const T vE = lane_next(vi), vW = lane_prev(vi);
       w[r] = aE[r] * (vi - vE) + aW[r] * (vi - vW) + aN[r] * (vi - v[r + 2]) + aS[r] * (vi - v[r]);
     }
   }
   __syncthreads();   // buffer 1 is overwritten by the first substep
 
-  // Per-lane LDS slots in the two buffers, hidden from the compiler's address
-  // folding so that every neighbour read is a base plus an immediate offset:
-  // oW = slot of (x - 1, yb), oS = slot of (x, yb - 1).
-  int oW[2] = {base, kRectCap + base};
-  int oS[2] = {base + 1 - P, kRectCap + base + 1 - P};
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    asm volatile("" : "+v"(oW[k]));
-    asm volatile("" : "+v"(oS[k]));
-  }
   // Substep m reads buffer B = m & 1 and writes buffer 1 - B.  The increments
   // d_m+1 and d_m-1 share a register: at even m, d0 holds d_m and d1 d_m-1
   // (overwritten by d_m+1); at odd m the roles swap, so no copies are needed.
@@ -470,17 +483,18 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __rest
     constexpr int B = decltype(Bc)::value;
     T* dc = B == 0 ? d0 : d1;       // d_m
     T* dq = B == 0 ? d1 : d0;       // d_m-1 in, d_m+1 out
-    const T c = (T)lc[m];           // c1 for m = 0, c2_m otherwise
-    const T b = (T)lc[kMaxP + m];   // beta_m (0 for m = 0)
+    const T c = (T)lane_bcast(cvec, m);   // c1 for m = 0, c2_m otherwise
+    const T b = (T)lane_bcast(bvec, m);   // beta_m (0 for m = 0)
     const T b1 = (T)1 + b;
     if (wave_on) {
-      const T* lb = lq + oW[B];
-      const T qS0 = lq[oS[B]], qN3 = lb[R * P + 1];
+      const T* rb = B == 0 ? lb0 : lb1;
+      T* wb = B == 0 ? lb1 : lb0;
+      const T qS0 = rb[below], qN3 = rb[above];
       T qn[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const T qW = lb[r * P], qE = lb[r * P + 2];
         const T qi = q[r];
+        const T qE = lane_next(qi), qW = lane_prev(qi);
         const T qN = r + 1 < R ? q[r + 1] : qN3;
         const T qS = r > 0 ? q[r - 1] : qS0;
         // edge form: constants are annihilated exactly (no assembled diagonal)
@@ -493,8 +507,8 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __rest
 #pragma unroll
       for (int r = 0; r < R; ++r) q[r] = qn[r];
       if (m + 1 < p) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) lq[oW[1 - B] + r * P + 1] = q[r];
+        wb[top] = q[0];
+        wb[bot] = q[R - 1];
       }
     }
     if (m + 1 < p) __syncthreads();
@@ -517,13 +531,12 @@ __global__ __launch_bounds__(kFineThreads) void k_fine(StepArgs a) {
   __shared__ T lq[kLdsSlots];
   __shared__ T ls[RECT ? 4 * kFineThreads : 1];   // rect mode: final-update term per node
   __shared__ double lk[256];
-  __shared__ double lc[RECT ? 2 * kMaxP : 1];     // rect mode: per-substep scalars
   const int G = a.n_fine * a.active;
   const int Lid = (int)(blockIdx.x & 7) * a.per_xcd + (int)(blockIdx.x >> 3);
   if (Lid >= G) return;
   const int s = a.s0 + Lid / a.n_fine;
   if (RECT) {
-    fine_tile_rect<T>(a, lk, lq, ls, lc, s, Lid % a.n_fine);
+    fine_tile_rect<T>(a, lk, lq, ls, s, Lid % a.n_fine);
   } else {
     load_kappa(a, s, lk);
     fine_tile_compact<T>(a, lk, lq, s, Lid % a.n_fine);
@@ -535,7 +548,6 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_multi(MultiArgs m) {
   __shared__ double lq[kLdsSlots];
   __shared__ double ls[RECT ? 4 * kFineThreads : 1];
   __shared__ double lk[256];
-  __shared__ double lc[RECT ? 2 * kMaxP : 1];
   const int Lid = (int)(blockIdx.x & 7) * m.per_xcd + (int)(blockIdx.x >> 3);
   if (Lid >= m.wg_off[m.n_jobs]) return;
   const int j = find_job(m, Lid);
@@ -543,7 +555,7 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_multi(MultiArgs m) {
   const int local = Lid - m.wg_off[j];
   const int s = local / a.n_fine;
   if (RECT) {
-    fine_tile_rect<double>(a, lk, lq, ls, lc, s, local % a.n_fine);
+    fine_tile_rect<double>(a, lk, lq, ls, s, local % a.n_fine);
   } else {
     load_kappa(a, s, lk);
     fine_tile_compact<double>(a, lk, lq, s, local % a.n_fine);
@@ -569,7 +581,7 @@ std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int
   const int RX = TX + 2 * p, RY = TY + 2 * p;
   std::vector<int32_t> loc;
   if (rect)
-    T.pitch = kPitch;
+    T.pitch = kRectW;
   else
     loc.resize((size_t)RX * RY);
   size_t n_region = 0, n_fplus = 0;
@@ -604,6 +616,7 @@ std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int
         by1 = std::min(by1 + 1, gy1);
         const int rx = bx1 - bx0, ry = by1 - by0;
         if (rx > kRectW || ry > kRectH) return "region rectangle exceeds 64 x 64 nodes";
+        if (p > 64) return "rect mode needs p <= 64";
         const int ix0 = std::max(tx, 0), ix1 = std::min(tx + TX, nxn);
         const int iy0 = std::max(ty, 0), iy1 = std::min(ty + TY, nyn);
         T.rtiles.push_back(make_int4(bx0 | by0 << 16, rx | ry << 16, ix0 | ix1 << 16, iy0 | iy1 << 16));
