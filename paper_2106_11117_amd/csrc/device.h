@@ -47,4 +47,32 @@ __device__ __forceinline__ void edge_coefs(const LevelView& L, const double* __r
   cS = (kSE * hxE + kSW * hxW) * L.inv2hy[j - 1];
 }
 
+// Value of the next / previous lane of the wavefront (DPP wavefront shift by
+// one lane); the last / first lane reads 0.  All lanes must be active.
+__device__ __forceinline__ double lane_next(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x130, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_prev(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x138, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float lane_next(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float lane_prev(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+// Broadcast lane m's value of v (m wavefront-uniform).
+__device__ __forceinline__ double lane_bcast(double v, int m) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), m);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), m);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 }  // namespace lts

@@ -244,9 +244,346 @@ __global__ __launch_bounds__(256) void k_adj_blocks(AdjArgs a, const double* __r
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fused form of one backward step on rect fine tiles.  One workgroup per
+// (sample, fine tile), lane x of wavefront v = column x, rows 4v .. 4v+3 of the
+// tile's region (the layout of the forward fine kernel).  For y = u_n and
+// mu = mu_n+1 it recomputes the substep increments d_1 .. d_p-1 of R y
+// (stored in a per-tile global scratch), runs the reverse sweep over the p
+// substeps with Lambda, lw in registers, and contracts every derivative pair
+// on the cells it owns: cells whose lower-left node is inside the tile and
+// that have a node of P among their corners.  The other cells see Lambda_m =
+// rho_m Lambda_p (no stencil acts there), so lw / m = gamma f mu and only the
+// pair (lw, (I - P) y) contributes; k_adj_cells handles them.  Every value the
+// contraction uses is exact at distance >= p - 1 from the region border (the
+// forward increments d_m at >= m, Lambda_m+1 at >= p - m - 1), which covers
+// the corners of all interior cells.
+struct AdjTileArgs {
+  LevelView L;
+  const int4* __restrict__ rtiles;
+  int n_fine, per_xcd, active;
+  const double* __restrict__ kappa;  // [S][nb]
+  const double* __restrict__ coef;   // [S][p+1]
+  const double* __restrict__ Y;      // y = u_n of sample s at Y + s*sstride
+  const double* __restrict__ MU;     // mu_n+1
+  double* __restrict__ G;            // per-cell accumulators
+  double* __restrict__ scr;          // d_1 .. d_p-1 per (sample, tile)
+  size_t sstride;
+  double f;                          // 2 (n >= 1) or 1 (n = 0)
+};
+
+__device__ __forceinline__ uint32_t lane_next_u(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xF, 0xF, true);
+}
+
+__global__ __launch_bounds__(kFineThreads) void k_adj_fine(AdjTileArgs a) {
+  constexpr int R = 4, W = 64;
+  __shared__ double lk[256];
+  __shared__ double lb[4 * kBndSlots];                 // boundary rows: 2 buffers x (q or t, b)
+  __shared__ double lL[4 * kFineThreads];              // Lambda_p of this lane's rows
+  const int G_ = a.n_fine * a.active;
+  const int Lid = (int)(blockIdx.x & 7) * a.per_xcd + (int)(blockIdx.x >> 3);
+  if (Lid >= G_) return;
+  const int s = Lid / a.n_fine, tile = Lid % a.n_fine;
+  const LevelView& L = a.L;
+  const int4 td = a.rtiles[tile];
+  const int x0 = td.x & 0xFFFF, y0 = td.x >> 16;
+  const int RX = td.y & 0xFFFF, RY = td.y >> 16;
+  const int ix0 = td.z & 0xFFFF, ix1 = td.z >> 16, iy0 = td.w & 0xFFFF, iy1 = td.w >> 16;
+  const int tid = threadIdx.x;
+  const int x = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int yb = 4 * wv;
+  const bool wave_on = yb < RY;
+  const int gx = x0 + x, gyb = y0 + yb;
+  const bool col_on = x < RX && gx < L.nxn;
+  const double* __restrict__ y_g = a.Y + (size_t)s * a.sstride;
+  const double* __restrict__ mu_g = a.MU + (size_t)s * a.sstride;
+  const double* __restrict__ cf = a.coef + (size_t)s * (L.p + 1);
+  const int ld = L.ld, p = L.p;
+  double* __restrict__ scr = a.scr + ((size_t)s * a.n_fine + tile) * (size_t)(p - 1) * (R * kFineThreads);
+
+  // ---- one batch of global reads
+  const double kv = tid < L.nb ? a.kappa[(size_t)s * L.nb + tid] : 0.0;
+  const double cvec = x < p ? cf[1 + x] : 0.0;                 // lane m: c1 (m = 0) or c2_m
+  const double bvec = (x >= 1 && x < p) ? L.beta[x] : 0.0;     // lane m: beta_m
+  const int gxs = min(max(gx, 1), L.nxn - 1);
+  const double hxE = L.hx[gxs], hxW = L.hx[gxs - 1], ihE = L.inv2hx[gxs], ihW = L.inv2hx[gxs - 1];
+  double hyv[R + 1], ihy[R + 1];
+#pragma unroll
+  for (int q = 0; q <= R; ++q) {
+    const int g = min(max(gyb - 1 + q, 0), L.nyn - 1);
+    hyv[q] = L.hy[g];
+    ihy[q] = L.inv2hy[g];
+  }
+  double y[R], im[R];
+  uint32_t f[R + 1], cbE[R + 1], cbW[R + 1];                    // f[R]: row yb+4
+#pragma unroll
+  for (int r = 0; r <= R; ++r) {
+    const bool ok = wave_on && col_on && yb + r < RY && gyb + r < L.nyn;
+    const int k = ok ? (gyb + r) * ld + gx : ld + 1;
+    f[r] = ok ? (uint32_t)L.flags[k] : 0u;
+    if (r < R) {
+      y[r] = ok ? y_g[k] : 0.0;
+      const double mu = ok ? mu_g[k] : 0.0;
+      im[r] = ok ? L.invm[k] : 0.0;
+      lL[r * kFineThreads + tid] = im[r] != 0.0 ? a.f * mu / im[r] : 0.0;   // Lambda_p = f M mu
+    }
+  }
+#pragma unroll
+  for (int q = 0; q <= R; ++q) {
+    const int cy = min(max(gyb - 1 + q, 0), L.nyn - 2);
+    const int kc = cy * ld + gxs;
+    cbE[q] = L.cblk[kc];
+    cbW[q] = L.cblk[kc - 1];
+  }
+  // Cell (gx, gyb + r), computed by the lane of its lower-left node, belongs to
+  // this tile if its first corner in P (order: lower-left, lower-right,
+  // upper-left, upper-right) is inside the tile: that node is in F+, so its
+  // tile exists, and the cell's lower-left node, one node away at most, lies
+  // in the region (the F+ bounding box grown by one).  Corner flags of the next
+  // lane and row come by DPP and from the row above.
+  uint32_t own = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t fn = lane_next_u(f[r]), fu = f[r + 1], fun = lane_next_u(f[r + 1]);
+    const int gy = gyb + r;
+    int cx = -1, cy = -1;
+    if (f[r] & F_P) { cx = gx; cy = gy; }
+    else if (fn & F_P) { cx = gx + 1; cy = gy; }
+    else if (fu & F_P) { cx = gx; cy = gy + 1; }
+    else if (fun & F_P) { cx = gx + 1; cy = gy + 1; }
+    const bool in = cx >= ix0 && cx < ix1 && cy >= iy0 && cy < iy1;
+    if (wave_on && col_on && yb + r < RY && in && cbE[r + 1] != 255u) own |= 1u << r;
+  }
+  // ---- LDS: kappa, boundary rows of q_0 = P y (buffer 0) and v = (I - P) y (buffer 1)
+  double* const q0b = lb;
+  double* const q1b = lb + kBndSlots;
+  const int top = (2 * wv + 1) * W + x, bot = (2 * wv + 2) * W + x;
+  const int below = 2 * wv * W + x, above = (2 * wv + 3) * W + x;
+  if (tid < L.nb) lk[tid] = kv;
+  {
+    const bool p0 = f[0] & F_P, p3 = f[R - 1] & F_P;
+    q0b[top] = p0 ? y[0] : 0.0;
+    q0b[bot] = p3 ? y[R - 1] : 0.0;
+    q1b[top] = p0 ? 0.0 : y[0];
+    q1b[bot] = p3 ? 0.0 : y[R - 1];
+  }
+  for (int t = tid; t < 8 * W; t += kFineThreads) {           // zero rows of all four buffers
+    const int buf = t / (2 * W), z = (t % (2 * W)) < W ? (t % W) : (kBndRows - 1) * W + (t % W);
+    lb[buf * kBndSlots + z] = 0.0;
+  }
+  __syncthreads();
+
+  // ---- edge coefficients (unscaled; row r's south edge = row r-1's north edge) and w
+  double cE[R], cW[R], cV[R + 1];
+  {
+    double kE[R + 1], kW[R + 1];
+#pragma unroll
+    for (int c = 0; c <= R; ++c) {
+      kE[c] = lk[cbE[c]];
+      kW[c] = lk[cbW[c]];
+    }
+#pragma unroll
+    for (int c = 0; c <= R; ++c) cV[c] = (kE[c] * hxE + kW[c] * hxW) * ihy[c];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      cE[r] = (kE[r + 1] * hyv[r + 1] + kE[r] * hyv[r]) * ihE;
+      cW[r] = (kW[r + 1] * hyv[r + 1] + kW[r] * hyv[r]) * ihW;
+    }
+  }
+  auto stencil = [&](const double* vv, double vS0, double vN3, int r) {   // sum_x c_x (v_i - v_x)
+    const double vi = vv[r];
+    const double vE = lane_next(vi), vW = lane_prev(vi);
+    const double vN = r + 1 < R ? vv[r + 1] : vN3;
+    const double vS = r > 0 ? vv[r - 1] : vS0;
+    return cE[r] * (vi - vE) + cW[r] * (vi - vW) + cV[r + 1] * (vi - vN) + cV[r] * (vi - vS);
+  };
+  double w[R], q[R];
+  {
+    double v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = (f[r] & F_P) ? 0.0 : y[r];
+    const double vS0 = q1b[below], vN3 = q1b[above];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double st = stencil(v, vS0, vN3, r);
+      w[r] = (f[r] & F_FPLUS) ? im[r] * st : 0.0;
+      q[r] = (f[r] & F_P) ? y[r] : 0.0;
+    }
+  }
+  __syncthreads();   // buffer 1 is overwritten by the first substep
+
+  // ---- forward substeps: d_1 .. d_p-1 into the scratch (q_m = P (y + d_m))
+  double d0[R], d1[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) d0[r] = d1[r] = 0.0;
+  auto fsub = [&](int m, auto Bc) {
+    constexpr int B = decltype(Bc)::value;
+    double* dc = B == 0 ? d0 : d1;
+    double* dq = B == 0 ? d1 : d0;
+    const double c = lane_bcast(cvec, m), b = lane_bcast(bvec, m);
+    const double* rb = B == 0 ? q0b : q1b;
+    double* wb = B == 0 ? q1b : q0b;
+    if (wave_on) {
+      const double qS0 = rb[below], qN3 = rb[above];
+      double qn[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double st = stencil(q, qS0, qN3, r);   // DPP: every lane takes part
+        const double apq = (f[r] & F_FPLUS) ? im[r] * st : 0.0;
+        const double rr = w[r] + apq;
+        const double dn = m == 0 ? -c * rr : (1.0 + b) * dc[r] - b * dq[r] - c * rr;
+        dq[r] = dn;
+        qn[r] = (f[r] & F_P) ? y[r] + dn : 0.0;
+        scr[((size_t)m * R + r) * kFineThreads + tid] = dn;    // d_m+1
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) q[r] = qn[r];
+      wb[top] = q[0];
+      wb[bot] = q[R - 1];
+    }
+    __syncthreads();
+  };
+  for (int m = 0; m < p - 1; m += 2) {
+    fsub(m, std::integral_constant<int, 0>{});
+    if (m + 1 < p - 1) fsub(m + 1, std::integral_constant<int, 1>{});
+  }
+
+  // ---- reverse sweep: Lambda_p = f M mu, Lambda_p+1 = 0; m = p-1 .. 0
+  double l1[R], l2[R], lw[R], acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    l1[r] = lL[r * kFineThreads + tid];
+    l2[r] = lw[r] = acc[r] = 0.0;
+  }
+  // cell legs: hy / (2 hx) along x and hx / (2 hy) along y of cell row gyb + r
+  auto side = [&](int r, double a0, double a1, double a2, double a3, double b0, double b1, double b2,
+                  double b3) {
+    return hyv[r + 1] * ihE * ((a0 - a1) * (b0 - b1) + (a2 - a3) * (b2 - b3)) +
+           hxE * ihy[r + 1] * ((a0 - a2) * (b0 - b2) + (a1 - a3) * (b1 - b3));
+  };
+  for (int m = p - 1; m >= 0; --m) {
+    const int B = m & 1;
+    const double cm = lane_bcast(cvec, m);
+    double t[R], bq[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      t[r] = l1[r] * im[r];
+      const double dm = m == 0 ? 0.0 : scr[((size_t)(m - 1) * R + r) * kFineThreads + tid];
+      bq[r] = (f[r] & F_P) ? y[r] + dm : 0.0;
+    }
+    double* const tb = lb + B * kBndSlots;                 // t = Lambda / m boundary rows
+    double* const bb = lb + (2 + B) * kBndSlots;           // b = P q_m top rows
+    if (wave_on) {
+      tb[top] = t[0];
+      tb[bot] = t[R - 1];
+      bb[top] = bq[0];
+    }
+    __syncthreads();
+    if (wave_on) {
+      const double tS0 = tb[below], tN3 = tb[above], bN3 = bb[above];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        // pair (-c_m Lambda_m+1, P q_m) on cell (x, r)
+        const double t0 = t[r], t1 = lane_next(t0), t2 = r + 1 < R ? t[r + 1] : tN3, t3 = lane_next(t2);
+        const double b0 = bq[r], b1 = lane_next(b0), b2 = r + 1 < R ? bq[r + 1] : bN3, b3 = lane_next(b2);
+        acc[r] -= cm * side(r, t0, t1, t2, t3, b0, b1, b2, b3);
+        lw[r] -= cm * l1[r];
+      }
+      if (m > 0) {
+        const double bm = lane_bcast(bvec, m);
+        const double bm1 = m + 1 < p ? lane_bcast(bvec, m + 1) : 0.0;
+        double ln[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double st = stencil(t, tS0, tN3, r);   // DPP: every lane takes part
+          const double kt = (f[r] & F_P) ? st : 0.0;
+          ln[r] = (1.0 + bm) * l1[r] - cm * kt - bm1 * l2[r];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          l2[r] = l1[r];
+          l1[r] = ln[r];
+        }
+      }
+    }
+  }
+  // ---- pair (lw, (I - P) y)
+  {
+    double aw[R], v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      aw[r] = lw[r] * im[r];
+      v[r] = (f[r] & F_P) ? 0.0 : y[r];
+    }
+    // buffers of the parity not read in the last reverse step (m = 0 used parity 0)
+    double* const tb = lb + kBndSlots;
+    double* const bb = lb + 3 * kBndSlots;
+    if (wave_on) {
+      tb[top] = aw[0];
+      bb[top] = v[0];
+    }
+    __syncthreads();
+    if (wave_on) {
+      const double aN3 = tb[above], vN3 = bb[above];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double a0 = aw[r], a1 = lane_next(a0), a2 = r + 1 < R ? aw[r + 1] : aN3, a3 = lane_next(a2);
+        const double b0 = v[r], b1 = lane_next(b0), b2 = r + 1 < R ? v[r + 1] : vN3, b3 = lane_next(b2);
+        acc[r] += side(r, a0, a1, a2, a3, b0, b1, b2, b3);
+      }
+    }
+  }
+  double* __restrict__ Gs = a.G + (size_t)s * a.sstride;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (own & (1u << r)) Gs[(size_t)(gyb + r) * ld + gx] += acc[r];
+}
+
+// Cells without a node of P: with lw / m = gamma f mu (gamma from the substep
+// scalars), only the pair (lw, (I - P) y) = (lw, y) contributes.
+__global__ __launch_bounds__(256) void k_adj_cells(AdjArgs a, const double* __restrict__ Y,
+                                                   const double* __restrict__ MU, double f,
+                                                   double* __restrict__ G) {
+  const int s = blockIdx.z;
+  if (s >= a.s_active) return;
+  const LevelView& L = a.L;
+  const int ia = blockIdx.x * BX + threadIdx.x, jb = blockIdx.y * BY + threadIdx.y;
+  if (ia >= L.nxn - 1 || jb >= L.nyn - 1) return;
+  const size_t kc = (size_t)jb * L.ld + ia;
+  if (L.cblk[kc] == 255) return;
+  const size_t n00 = kc, n10 = kc + 1, n01 = kc + L.ld, n11 = kc + L.ld + 1;
+  if ((L.flags[n00] | L.flags[n10] | L.flags[n01] | L.flags[n11]) & F_P) return;
+  // gamma = -(c1 rho_1 + sum_{m=1}^{p-1} c2_m rho_m+1), rho_p = 1, rho_p+1 = 0,
+  // rho_m = (1 + beta_m) rho_m+1 - beta_m+1 rho_m+2
+  const double* cf = a.coef + (size_t)s * (L.p + 1);
+  const int p = L.p;
+  double r1 = 1.0, r2 = 0.0, gam = 0.0;            // rho_m+1, rho_m+2
+  for (int m = p - 1; m >= 1; --m) {
+    gam -= cf[1 + m] * r1;
+    const double bm1 = m + 1 < p ? L.beta[m + 1] : 0.0;
+    const double rm = (1.0 + L.beta[m]) * r1 - bm1 * r2;
+    r2 = r1;
+    r1 = rm;
+  }
+  gam -= cf[1] * r1;
+  const size_t so = (size_t)s * a.sstride;
+  const double* __restrict__ y = Y + so;
+  const double* __restrict__ mu = MU + so;
+  const double gx = L.hy[jb] * L.inv2hx[ia], gy = L.hx[ia] * L.inv2hy[jb];
+  const double a0 = mu[n00], a1 = mu[n10], a2 = mu[n01], a3 = mu[n11];
+  const double b0 = y[n00], b1 = y[n10], b2 = y[n01], b3 = y[n11];
+  const double sd = gx * ((a0 - a1) * (b0 - b1) + (a2 - a3) * (b2 - b3)) +
+                    gy * ((a0 - a2) * (b0 - b2) + (a1 - a3) * (b1 - b3));
+  G[so + kc] += gam * f * sd;
+}
+
+// p[0 .. n-1] = v with a grid-stride loop: the workspace can hold more than
+// 2^32 doubles, beyond what one grid dimension can count in work-items.
 __global__ __launch_bounds__(256) void k_fill(double* __restrict__ p, size_t n, double v) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) p[t] = v;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) p[t] = v;
 }
 
 }  // namespace
@@ -288,7 +625,8 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
   // zero the whole workspace region used (cells of G, Lambda spare, ...)
   {
     const size_t tot = at * one;
-    k_fill<<<(unsigned)((tot + 255) / 256), 256, 0, c->stream>>>(base, tot, 0.0);
+    const size_t blocks = std::min<size_t>((tot + 255) / 256, 65536);
+    k_fill<<<(unsigned)blocks, 256, 0, c->stream>>>(base, tot, 0.0);
   }
   // ---- forward with checkpoints: states in the two state buffers
   LTS_HIP(c, c->st0.ensure(one * sizeof(double)));
@@ -315,6 +653,12 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
   if (r != LTS_OK) return r;
 
   // ---- backward
+  // fused form on rect fine tiles: per-(sample, tile) scratch for d_1 .. d_p-1
+  const TilingDev& T = lv.tiling;
+  const bool fused = T.rect && T.n_fine > 0;
+  if (fused)
+    LTS_HIP(c, c->adjscr.ensure(std::max<size_t>((size_t)T.n_fine * n * (size_t)std::max(p - 1, 1) *
+                                                 (4 * kFineThreads) * sizeof(double), 8)));
   double* MU[2] = {arr(imu0), arr(imu1)};
   k_adj_mu_init<<<grid(Lv.ld, n), blk, 0, c->stream>>>(a, d_nsteps, MU[0], MU[1]);
   ContractArgs ca;
@@ -350,6 +694,31 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
       const double f = nn >= 1 ? 2.0 : 1.0;
       double* mu1 = MU[(nn + 1) & 1];   // mu_{n+1}
       double* mu2 = MU[nn & 1];         // mu_{n+2} (overwritten by mu_n)
+      if (fused) {
+        // fine tiles (cells with a node of P) and the remaining cells
+        AdjTileArgs ta;
+        ta.L = Lv;
+        ta.rtiles = T.rtiles.as<int4>();
+        ta.n_fine = T.n_fine;
+        ta.active = act;
+        ta.kappa = d_kappa;
+        ta.coef = d_coef;
+        ta.Y = y;
+        ta.MU = mu1;
+        ta.G = arr(iG);
+        ta.scr = c->adjscr.as<double>();
+        ta.sstride = ss;
+        ta.f = f;
+        const long long Gw = (long long)T.n_fine * act;
+        ta.per_xcd = (int)((Gw + 7) / 8);
+        if (Gw > 0) k_adj_fine<<<dim3((unsigned)(8LL * ta.per_xcd)), dim3(kFineThreads), 0, c->stream>>>(ta);
+        k_adj_cells<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, y, mu1, f, arr(iG));
+        if (nn >= 1) {
+          r = launch_step(c, lv, lv.tiling, d_kappa, d_coef, mu1, mu2, ss, 0, act, 0, c->stream);
+          if (r != LTS_OK) return r;
+        }
+        continue;
+      }
       // forward substeps of y
       k_adj_w<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, y, arr(iw));
       for (int m = 0; m < p; ++m)

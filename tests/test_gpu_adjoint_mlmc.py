@@ -34,9 +34,13 @@ def _case(n_base=16, T=0.3, n=3, level=0):
     return lv, ops, s
 
 
-@pytest.mark.parametrize("K", [1, 7, 64])
-def test_adjoint_matches_oracle(ctx, K):
+@pytest.mark.parametrize("K,rect", [(1, True), (7, True), (64, True), (7, False)])
+def test_adjoint_matches_oracle(ctx, K, rect):
+    """Fused backward step on rect fine tiles, and the general per-kernel form
+    (compact tiling), against the oracle adjoint."""
     lid = ctx.add_rect_level(P.box_rule(16))
+    if not rect:
+        ctx.set_tiling(lid, 16, 16, False)
     lv, ops, s = _case()
     dl = np.array([1.0, -0.5, 2.0])
     q, g = ctx.backward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"], dl, K=K)
@@ -180,3 +184,15 @@ def test_adjoint_c1_full_size_vs_finite_differences(ctx):
         worst = max(worst, e)
         assert e <= 1e-5, (k, e)
     print(f"C1 adjoint vs central differences: worst relative error {worst:.3g}")
+
+
+def test_adjoint_repeat_call_large_workspace(ctx):
+    """Regression: with 40 samples on the 442,225-DOF mesh the workspace holds more
+    than 2^32 doubles; it must be cleared completely on every call, so a repeated
+    call gives the same gradients (stale per-cell accumulators would add up)."""
+    lid = ctx.add_rect_level(P.box_rule(512, box=(0.48, 0.52), ref=8))
+    s = P.gen_samples(0, 0, 100, 40, P.sample_rule(), 1 / 512)
+    q1, g1 = ctx.backward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"], np.ones(40), K=64)
+    q2, g2 = ctx.backward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"], np.ones(40), K=64)
+    assert np.array_equal(g1, g2) and np.array_equal(q1, q2)
+    assert np.max(np.abs(g1)) < 1.0          # dQ/dg is O(|Q|) here, about 1e-2
