@@ -28,10 +28,14 @@ sys.path.insert(0, ROOT)
 N_BASE, BOX, REF = 512, (0.48, 0.52), 8
 N_SAMPLES = 256
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per step launch (one k_coarse + one k_fine) from the FETCH_SIZE / WRITE_SIZE counter runs
-# (scaled by a plain copy kernel; profiles/lts_step_kernels_C1_256samples_counters.md),
-# valid only for the step-kernel sources they were taken with.
-TRAFFIC = {"bytes_per_launch": 2.5902e9, "sources_sha256": "a50972bc2a98db81e04a360eaa96ae7c043da7a9def5df4b74c4213681086895"}
+# HBM bytes per step launch (one k_coarse + one k_fine) from the FETCH_SIZE /
+# WRITE_SIZE counter runs, scaled by a plain copy kernel
+# (profiles/lts_step_kernels_C1_256samples_counters.md): counter bytes are 1.346x
+# the algorithmic bytes on the profiled launches (all samples active), applied
+# to the average launch's 1.7105e9 algorithmic bytes.  Valid only for the
+# step-kernel sources the counters were taken with.
+TRAFFIC = {"bytes_per_launch": 1.346 * 1.7105e9,
+           "sources_sha256": "0a194d49a3b128ffdeecfa365c4ce7ed807ad314439d184947477080d9d41cd6"}
 STEP_SOURCES = ("lts_fused.hip", "fused.h", "device.h", "lts_step.hip")
 WORKLOAD = ("unit square 512x512 base refined 8x in (0.48,0.52): 442225 DOFs, |P|=204081, p=8, "
             "nu=0.01, 256 samples, 4x4 blocks sigma=0.25, T=1, FP64")
