@@ -56,7 +56,7 @@ struct DevLevel {
   double tuned_ms = 0;  // measured step time of the chosen tiling
   int ld = 0;           // row pitch (elements) of node/cell arrays and states
   size_t nodes = 0;     // nyn * ld
-  DevBuf hx, hy, inv2hx, inv2hy, x, y, cblk, flags, invm, qoiw, beta, beta_half;
+  DevBuf hx, hy, inv2hx, inv2hy, x, y, cblk, flags, ninfo, invm, qoiw, beta, beta_half;
   // compact lists of DOFs (flat padded index), used by reductions
   LevelView view() const {
     LevelView v;
@@ -64,7 +64,7 @@ struct DevLevel {
     v.hx = hx.as<double>(); v.hy = hy.as<double>();
     v.inv2hx = inv2hx.as<double>(); v.inv2hy = inv2hy.as<double>();
     v.x = x.as<double>(); v.y = y.as<double>();
-    v.cblk = cblk.as<uint8_t>(); v.flags = flags.as<uint8_t>();
+    v.cblk = cblk.as<uint8_t>(); v.flags = flags.as<uint8_t>(); v.ninfo = ninfo.as<uint32_t>();
     v.invm = invm.as<double>(); v.qoiw = qoiw.as<double>();
     v.beta = beta.as<double>(); v.beta_half = beta_half.as<double>();
     return v;

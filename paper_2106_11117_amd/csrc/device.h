@@ -24,6 +24,10 @@ struct LevelView {
   const double* __restrict__ y;       // [nyn]
   const uint8_t* __restrict__ cblk;   // [nyn*ld] block of cell (a,b) at b*ld+a; 255 = none
   const uint8_t* __restrict__ flags;  // [nyn*ld] F_* bits
+  // [nyn*ld] per node (i, j): F_* bits | block of cell (i, j) << 8 | block of
+  // cell (i-1, j) << 16 (255: no cell), so one 32-bit read gives a node's flags
+  // and the blocks of the two cells above-right and above-left of it
+  const uint32_t* __restrict__ ninfo;
   const double* __restrict__ invm;    // [nyn*ld] 1/m for DOFs, 0 elsewhere
   const double* __restrict__ qoiw;    // [nyn*ld]
   const double* __restrict__ beta;    // [p] beta_k, k = 1..p-1

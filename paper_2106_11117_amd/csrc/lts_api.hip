@@ -117,6 +117,15 @@ lts_status upload_level(lts_ctx c, DevLevel& D) {
       if (H.flags[k] & LTS_NODE_DOF) im[kd] = 1.0 / H.mass[k];
       qw[kd] = H.qoiw[k];
     }
+  // packed node word: flags | block of cell (i, j) << 8 | block of cell (i-1, j) << 16
+  std::vector<uint32_t> ni(D.nodes, 0);
+  for (int j = 0; j < H.nyn; ++j)
+    for (int i = 0; i < (int)D.ld; ++i) {
+      const size_t kd = (size_t)j * D.ld + i;
+      const uint32_t ne = i < H.nxc && j < H.nyc ? cb[kd] : 255u;
+      const uint32_t nw = i >= 1 && i - 1 < H.nxc && j < H.nyc ? cb[kd - 1] : 255u;
+      ni[kd] = (uint32_t)fl[kd] | ne << 8 | nw << 16;
+    }
   std::vector<double> bt(std::max(1, H.p), 0.0), bh(std::max(1, H.p), 0.0);
   for (int k = 1; k < H.p; ++k) {
     bt[k] = H.beta[k];
@@ -136,6 +145,7 @@ lts_status upload_level(lts_ctx c, DevLevel& D) {
       (e = put(D.y, H.y.data(), H.y.size() * 8)) != hipSuccess ||
       (e = put(D.cblk, cb.data(), cb.size())) != hipSuccess ||
       (e = put(D.flags, fl.data(), fl.size())) != hipSuccess ||
+      (e = put(D.ninfo, ni.data(), ni.size() * 4)) != hipSuccess ||
       (e = put(D.invm, im.data(), im.size() * 8)) != hipSuccess ||
       (e = put(D.qoiw, qw.data(), qw.size() * 8)) != hipSuccess ||
       (e = put(D.beta, bt.data(), bt.size() * 8)) != hipSuccess ||

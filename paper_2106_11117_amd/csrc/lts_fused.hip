@@ -68,7 +68,8 @@ namespace {
 // One coarse item (64 grid columns x kCoarseRows rows) per workgroup: lane =
 // column, wavefront v = rows 4v .. 4v+3 of the item.  Every global read of a
 // wavefront is issued in one batch (u of its rows and the rows above and
-// below, u_n-1, 1/m, flags, cell blocks), then the four rows are updated.  The
+// below, the two columns just outside the item, u_n-1, 1/m, the node words
+// with flags and cell blocks), then the four rows are updated.  The
 // item descriptor is x = i0 | j0 << 16, (y, z) = 64-bit mask of the columns
 // holding a DOF outside F+, w = 16-bit mask of such rows; lanes and wavefronts
 // without such a DOF return at once.
@@ -81,9 +82,13 @@ __device__ __forceinline__ void coarse_body(const StepArgs& a, double* __restric
   const int lane = threadIdx.x & 63;
   const uint64_t lm = (uint64_t)(uint32_t)it.y | (uint64_t)(uint32_t)it.z << 32;
   const bool live = rows != 0 && ((lm >> lane) & 1);
-  // a live lane's column holds a DOF, so 1 <= i <= nxn - 2; other lanes read a
-  // clamped column and store nothing
-  const int i = min(max((it.x & 0xFFFF) + lane, 1), L.nxn - 2);
+  // Lane = column x0 + lane.  Values are read at the column clamped into the
+  // grid (a live lane's column holds a DOF, 1 <= i <= nxn - 2; the boundary
+  // columns hold u = 0), so the east / west neighbours of a live lane are the
+  // adjacent lanes' values (DPP), except past the item's first and last lane.
+  const int i0 = it.x & 0xFFFF;
+  const int iv = min(i0 + lane, L.nxn - 1);          // value column
+  const int i = min(max(i0 + lane, 1), L.nxn - 2);   // geometry column
   const int j0 = (it.x >> 16) + 4 * wv;               // rows j0 .. j0 + 3
   const int ld = L.ld;
   const T* __restrict__ u = reinterpret_cast<const T*>(a.Ucur) + (size_t)s * a.sstride;
@@ -95,45 +100,51 @@ __device__ __forceinline__ void coarse_body(const StepArgs& a, double* __restric
   //      are clamped and never used
   const double kv = (int)threadIdx.x < L.nb ? a.kappa[(size_t)s * L.nb + threadIdx.x] : 0.0;
   const double hxE = L.hx[i], hxW = L.hx[i - 1], ihE = L.inv2hx[i], ihW = L.inv2hx[i - 1];
-  T uc[R + 2], ue[R], uw[R], uold[R];
+  T uc[R + 2], ued[R], uold[R];
   double im[R], hy[R + 1], ihy[R + 1];
-  uint32_t f[R], cE[R + 1], cW[R + 1];
+  uint32_t ni[R + 1];                                  // node words of rows j0-1 .. j0+3
 #pragma unroll
   for (int q = 0; q < R + 2; ++q) {
     const int j = min(max(j0 - 1 + q, 0), L.nyn - 1);
-    uc[q] = u[(size_t)j * ld + i];
+    uc[q] = u[(size_t)j * ld + iv];
   }
 #pragma unroll
   for (int q = 0; q <= R; ++q) {
     const int j = min(max(j0 - 1 + q, 0), L.nyn - 2);  // cell row below node row j0 + q
     hy[q] = L.hy[j];
     ihy[q] = L.inv2hy[j];
-    cE[q] = L.cblk[(size_t)j * ld + i];
-    cW[q] = L.cblk[(size_t)j * ld + i - 1];
+    ni[q] = L.ninfo[(size_t)min(max(j0 - 1 + q, 0), L.nyn - 1) * ld + i];
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int j = min(j0 + r, L.nyn - 1);
     const size_t k = (size_t)j * ld + i;
-    f[r] = L.flags[k];        // a clamped row is a boundary row: never a DOF
-    ue[r] = u[k + 1];
-    uw[r] = u[k - 1];
+    ued[r] = (T)0;
+    if (lane == 0 || lane == 63) ued[r] = u[(size_t)j * ld + min(max(i0 + lane + (lane ? 1 : -1), 0), L.nxn - 1)];
     im[r] = L.invm[k];
     uold[r] = startup ? (T)0 : uo[k];
   }
   if ((int)threadIdx.x < L.nb) lk[threadIdx.x] = kv;
   __syncthreads();
+  // east / west values of rows j0 .. j0+3 (every lane still active for DPP)
+  T ue[R], uw[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const T e = lane_next(uc[r + 1]), w = lane_prev(uc[r + 1]);
+    ue[r] = lane == 63 ? ued[r] : e;
+    uw[r] = lane == 0 ? ued[r] : w;
+  }
   if (!live) return;
   // ---- update the rows' DOFs outside F+ (edge form)
   double kE[R + 1], kW[R + 1];
 #pragma unroll
   for (int q = 0; q <= R; ++q) {
-    kE[q] = lk[cE[q]];
-    kW[q] = lk[cW[q]];
+    kE[q] = lk[(ni[q] >> 8) & 0xFF];
+    kW[q] = lk[(ni[q] >> 16) & 0xFF];
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    if ((f[r] & (F_DOF | F_FPLUS)) != F_DOF) continue;
+    if ((ni[r + 1] & (F_DOF | F_FPLUS)) != F_DOF) continue;
     const T uS = uc[r], uC = uc[r + 1], uN = uc[r + 2];
     const double cEg = (kE[r + 1] * hy[r + 1] + kE[r] * hy[r]) * ihE;
     const double cWg = (kW[r + 1] * hy[r + 1] + kW[r] * hy[r]) * ihW;
