@@ -357,54 +357,52 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __rest
 
   // ---- one batch of global reads (nothing read here decides another read)
   const double kv = tid < L.nb ? a.kappa[(size_t)s * L.nb + tid] : 0.0;
-  // per-substep scalars, lane m of every wavefront: c1 (m = 0) or c2_m, beta_m
-  const double cvec = x < p ? cf[1 + x] : 0.0;
-  const double bvec = (x >= 1 && x < p) ? L.beta[x] : 0.0;
-  const int gxs = min(max(gx, 1), L.nxn - 1);          // geometry column, in bounds off the grid
-  const double hxE = L.hx[gxs], hxW = L.hx[gxs - 1];
-  const double ihE = L.inv2hx[gxs], ihW = L.inv2hx[gxs - 1];
+  const int gxc = min(gx, L.nxn - 1);                  // column, in bounds off the grid
+  const int gxw = max(gxc - 1, 0);
+  const double hxE = L.hx[gxc], hxW = L.hx[gxw];
+  const double ihE = L.inv2hx[gxc];
+  const int gyb = y0 + yb;
   double hyv[R + 1], ihy[R + 1];                       // rows gy-1 .. gy+3 (wavefront-uniform)
+  uint32_t ni[R + 1];                                  // node words of rows gy-1 .. gy+3
 #pragma unroll
   for (int q = 0; q <= R; ++q) {
-    const int g = min(max(y0 + yb - 1 + q, 0), L.nyn - 1);
+    const int g = min(max(gyb - 1 + q, 0), L.nyn - 1);
     hyv[q] = L.hy[g];
     ihy[q] = L.inv2hy[g];
+    ni[q] = L.ninfo[g * ld + gxc];
   }
   T u[R], uo[R];
   double im[R];
   uint32_t f[R];
-  uint32_t cbE[R + 1], cbW[R + 1];                     // cell blocks of cell rows gy-1 .. gy+3
-  const int gyb = y0 + yb;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const bool ok = wave_on && col_on && yb + r < RY && gyb + r < L.nyn;
     const int k = ok ? (gyb + r) * ld + gx : ld + 1;
-    f[r] = ok ? (uint32_t)L.flags[k] : 0u;
     u[r] = ok ? u_g[k] : (T)0;
     im[r] = L.invm[k];
     uo[r] = startup ? (T)0 : uo_g[k];
+    f[r] = ok ? ni[r + 1] & 0xFFu : 0u;
   }
-#pragma unroll
-  for (int q = 0; q <= R; ++q) {
-    const int cy = min(max(gyb - 1 + q, 0), L.nyn - 2);
-    const int kc = cy * ld + gxs;
-    cbE[q] = L.cblk[kc];
-    cbW[q] = L.cblk[kc - 1];
-  }
-  // ---- LDS: kappa table, boundary rows of q_0 = P u (buffer 0) and v = (I - P) u
-  //      (buffer 1), the zero rows
+  // ---- LDS: kappa table (zero past the last block, so that the missing cells
+  //      off the grid read 0), boundary rows of q_0 = P u (buffer 0) and of
+  //      v = (I - P) u (buffer 1), the zero rows
   T* const lb0 = lq;
   T* const lb1 = lq + kBndSlots;
   const int top = (2 * wv + 1) * W + x, bot = (2 * wv + 2) * W + x;   // this wavefront's rows
   const int below = 2 * wv * W + x, above = (2 * wv + 3) * W + x;     // neighbours' rows
-  if (tid < L.nb) lk[tid] = kv;
-  {
-    const bool p0 = f[0] & F_P, p3 = f[R - 1] & F_P;
-    lb0[top] = p0 ? u[0] : (T)0;
-    lb0[bot] = p3 ? u[R - 1] : (T)0;
-    lb1[top] = p0 ? (T)0 : u[0];
-    lb1[bot] = p3 ? (T)0 : u[R - 1];
+  if (tid < 256) lk[tid] = kv;
+  T up[R], pm[R], v[R + 2];                            // v of rows gy-1 .. gy+4
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const bool pi = f[r] & F_P;
+    up[r] = pi ? u[r] : (T)0;
+    pm[r] = pi ? (T)1 : (T)0;
+    v[r + 1] = u[r] - up[r];
   }
+  lb0[top] = up[0];
+  lb0[bot] = up[R - 1];
+  lb1[top] = v[1];
+  lb1[bot] = v[R];
   if (tid < 4 * W) {                                   // zero rows 0 and kBndRows - 1
     const int z = (tid & (2 * W - 1)) < W ? (tid & (W - 1)) : (kBndRows - 1) * W + (tid & (W - 1));
     (tid < 2 * W ? lb0 : lb1)[z] = (T)0;
@@ -412,46 +410,45 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __rest
   __syncthreads();
 
   // ---- scaled edge coefficients and w = A_u (I - P) u_n
-  T aE[R], aW[R], aN[R], aS[R], w[R], q[R], up[R], pm[R];
+  T aE[R], aW[R], aN[R], aS[R], w[R], q[R];
   uint32_t wmask = 0;                                  // bit r: row r is written back
   {
-    double kE[R + 1], kW[R + 1];
+    double kE[R + 1], kW[R + 1];                       // kappa of the cells east / west of the node
 #pragma unroll
     for (int c = 0; c <= R; ++c) {
-      kE[c] = lk[cbE[c]];
-      kW[c] = lk[cbW[c]];
+      kE[c] = lk[(ni[c] >> 8) & 0xFFu];
+      kW[c] = lk[(ni[c] >> 16) & 0xFFu];
     }
     // vertical edges: row r's south edge is row r-1's north edge (same value)
     double cV[R + 1];
 #pragma unroll
     for (int c = 0; c <= R; ++c) cV[c] = (kE[c] * hxE + kW[c] * hxW) * ihy[c];
+    const bool col_in = gx >= ix0 && gx < ix1;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const bool fp = f[r] & F_FPLUS;
+      const double imf = fp ? im[r] : 0.0;             // coefficients vanish off F+
+      // a node's west edge is its west neighbour's east edge (same value)
       const double cE = (kE[r + 1] * hyv[r + 1] + kE[r] * hyv[r]) * ihE;
-      const double cW = (kW[r + 1] * hyv[r + 1] + kW[r] * hyv[r]) * ihW;
-      aE[r] = fp ? (T)(im[r] * cE) : (T)0;
-      aW[r] = fp ? (T)(im[r] * cW) : (T)0;
-      aN[r] = fp ? (T)(im[r] * cV[r + 1]) : (T)0;
-      aS[r] = fp ? (T)(im[r] * cV[r]) : (T)0;
-      const bool pi = f[r] & F_P;
-      const bool in = gx >= ix0 && gx < ix1 && gyb + r >= iy0 && gyb + r < iy1;
-      if (fp && in) wmask |= 1u << r;
-      up[r] = pi ? u[r] : (T)0;
-      pm[r] = pi ? (T)1 : (T)0;
+      const double cW = lane_prev(cE);
+      aE[r] = (T)(imf * cE);
+      aW[r] = (T)(imf * cW);
+      aN[r] = (T)(imf * cV[r + 1]);
+      aS[r] = (T)(imf * cV[r]);
+      if (fp && col_in && gyb + r >= iy0 && gyb + r < iy1) wmask |= 1u << r;
       q[r] = up[r];
       ls[r * kFineThreads + tid] = startup ? u[r] : (T)2 * u[r] - uo[r];   // this lane's own slots
     }
-    T v[R + 2];                                        // v of rows yb-1 .. yb+4
     v[0] = lb1[below];
     v[R + 1] = lb1[above];
+    T dN[R + 1];                                       // dN[c] = v of row c-1 minus v of row c
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r + 1] = (f[r] & F_P) ? (T)0 : u[r];
+    for (int c = 0; c <= R; ++c) dN[c] = v[c] - v[c + 1];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const T vi = v[r + 1];
-      const T vE = lane_next(vi), vW = lane_prev(vi);
-      w[r] = aE[r] * (vi - vE) + aW[r] * (vi - vW) + aN[r] * (vi - v[r + 2]) + aS[r] * (vi - v[r]);
+      const T dE = v[r + 1] - lane_next(v[r + 1]);
+      const T dWn = lane_prev(dE);
+      w[r] = aS[r] * -dN[r] + (aN[r] * dN[r + 1] + (aW[r] * -dWn + aE[r] * dE));
     }
   }
   __syncthreads();   // buffer 1 is overwritten by the first substep
@@ -466,24 +463,33 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __rest
     constexpr int B = decltype(Bc)::value;
     T* dc = B == 0 ? d0 : d1;       // d_m
     T* dq = B == 0 ? d1 : d0;       // d_m-1 in, d_m+1 out
-    const T c = (T)lane_bcast(cvec, m);   // c1 for m = 0, c2_m otherwise
-    const T b = (T)lane_bcast(bvec, m);   // beta_m (0 for m = 0)
-    const T b1 = (T)1 + b;
-    if (wave_on) {
+    const T c = (T)cf[1 + m];             // c1 for m = 0, c2_m otherwise (scalar loads)
+    const T b = m > 0 ? (T)L.beta[m] : (T)0;   // beta_m
+    // d_m+1 is needed only within distance p-1-m of the tile interior (it
+    // reaches the interior through p-1-m more stencil applications); a
+    // wavefront whose rows all lie farther out skips the substep.  Rows it
+    // leaves stale are read only by rows that are themselves outside the next
+    // band, so stale values never reach the interior.
+    const int reach = p - 1 - m;
+    if (wave_on && gyb + R > iy0 - reach && gyb < iy1 + reach) {
       const T* rb = B == 0 ? lb0 : lb1;
       T* wb = B == 0 ? lb1 : lb0;
-      const T qS0 = rb[below], qN3 = rb[above];
+      // edge form: K q at a node is the sum of c_k (q_i - q_k), so constants
+      // are annihilated exactly.  Each difference is formed once: the west
+      // difference of a node is minus the east difference of its west
+      // neighbour (one DPP shift), the south one minus the north one of the
+      // row below.
+      T dN[R + 1];                                     // dN[r + 1] = q_r - q_r+1, dN[0] = q_-1 - q_0
+      dN[0] = rb[below] - q[0];
+#pragma unroll
+      for (int r = 0; r < R; ++r) dN[r + 1] = q[r] - (r + 1 < R ? q[r + 1] : rb[above]);
       T qn[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const T qi = q[r];
-        const T qE = lane_next(qi), qW = lane_prev(qi);
-        const T qN = r + 1 < R ? q[r + 1] : qN3;
-        const T qS = r > 0 ? q[r - 1] : qS0;
-        // edge form: constants are annihilated exactly (no assembled diagonal)
-        const T acc = aE[r] * (qi - qE) + aW[r] * (qi - qW) + aN[r] * (qi - qN) + aS[r] * (qi - qS);
-        const T rr = w[r] + acc;
-        const T dn = b1 * dc[r] - b * dq[r] - c * rr;
+        const T dE = q[r] - lane_next(q[r]);
+        const T dWn = lane_prev(dE);                   // q_x-1 - q_x
+        const T rr = aS[r] * -dN[r] + (aN[r] * dN[r + 1] + (aW[r] * -dWn + (aE[r] * dE + w[r])));
+        const T dn = (dc[r] + b * (dc[r] - dq[r])) - c * rr;
         dq[r] = dn;
         qn[r] = pm[r] * dn + up[r];          // P (u_n + d_m+1): u_n + d exactly on P, 0 elsewhere
       }
