@@ -248,16 +248,27 @@ __global__ __launch_bounds__(256) void k_adj_blocks(AdjArgs a, const double* __r
 // Fused form of one backward step on rect fine tiles.  One workgroup per
 // (sample, fine tile), lane x of wavefront v = column x, rows 4v .. 4v+3 of the
 // tile's region (the layout of the forward fine kernel).  For y = u_n and
-// mu = mu_n+1 it recomputes the substep increments d_1 .. d_p-1 of R y
-// (stored in a per-tile global scratch), runs the reverse sweep over the p
-// substeps with Lambda, lw in registers, and contracts every derivative pair
-// on the cells it owns: cells whose lower-left node is inside the tile and
-// that have a node of P among their corners.  The other cells see Lambda_m =
-// rho_m Lambda_p (no stencil acts there), so lw / m = gamma f mu and only the
-// pair (lw, (I - P) y) contributes; k_adj_cells handles them.  Every value the
+// mu = mu_n+1 it recomputes the masked substep vectors q_0 .. q_p-1 of R y
+// (stored in a per-tile global scratch, only at the nodes the contraction
+// reads), runs the reverse sweep over the p substeps with Lambda in registers,
+// and contracts every derivative pair on the cells it owns: the cells whose
+// first corner in P (order: lower-left, lower-right, upper-left, upper-right)
+// is inside the tile interior.  The other cells see Lambda_m = rho_m Lambda_p
+// (no stencil acts there), so lw / m = gamma f mu and only the pair
+// (lw, (I - P) y) contributes; k_adj_cells handles them.  Every value the
 // contraction uses is exact at distance >= p - 1 from the region border (the
-// forward increments d_m at >= m, Lambda_m+1 at >= p - m - 1), which covers
-// the corners of all interior cells.
+// forward q_m at >= m, Lambda_m+1 at >= p - m - 1), which covers the corners of
+// all owned cells.
+//
+// The contraction of a pair (a, b) on cell (x, y) is
+//   hy/(2 hx) [(a00 - a10)(b00 - b10) + (a01 - a11)(b01 - b11)]
+// + hx/(2 hy) [(a00 - a01)(b00 - b01) + (a10 - a11)(b10 - b11)]
+// (corners a_ij at (x + i, y + j)): a sum of products of differences along the
+// cell's four edges with weights that do not depend on the pair.  So each
+// lane accumulates, over all pairs, the products along its node's east edge
+// (SH) and north edge (SV) with the pair's scalar factor, and the cell sums
+// are formed once at the end; the differences are the ones the Lambda stencil
+// uses anyway.
 struct AdjTileArgs {
   LevelView L;
   const int4* __restrict__ rtiles;
@@ -267,7 +278,7 @@ struct AdjTileArgs {
   const double* __restrict__ Y;      // y = u_n of sample s at Y + s*sstride
   const double* __restrict__ MU;     // mu_n+1
   double* __restrict__ G;            // per-cell accumulators
-  double* __restrict__ scr;          // d_1 .. d_p-1 per (sample, tile)
+  double* __restrict__ scr;          // q_0 .. q_p-1 per (sample, tile)
   size_t sstride;
   double f;                          // 2 (n >= 1) or 1 (n = 0)
 };
@@ -279,7 +290,7 @@ __device__ __forceinline__ uint32_t lane_next_u(uint32_t v) {
 __global__ __launch_bounds__(kFineThreads) void k_adj_fine(AdjTileArgs a) {
   constexpr int R = 4, W = 64;
   __shared__ double lk[256];
-  __shared__ double lb[4 * kBndSlots];                 // boundary rows: 2 buffers x (q or t, b)
+  __shared__ double lb[4 * kBndSlots];                 // boundary rows: 2 buffers x 2 quantities
   __shared__ double lL[4 * kFineThreads];              // Lambda_p of this lane's rows
   const int G_ = a.n_fine * a.active;
   const int Lid = (int)(blockIdx.x & 7) * a.per_xcd + (int)(blockIdx.x >> 3);
@@ -301,48 +312,46 @@ __global__ __launch_bounds__(kFineThreads) void k_adj_fine(AdjTileArgs a) {
   const double* __restrict__ mu_g = a.MU + (size_t)s * a.sstride;
   const double* __restrict__ cf = a.coef + (size_t)s * (L.p + 1);
   const int ld = L.ld, p = L.p;
-  double* __restrict__ scr = a.scr + ((size_t)s * a.n_fine + tile) * (size_t)(p - 1) * (R * kFineThreads);
+  double* __restrict__ scr = a.scr + ((size_t)s * a.n_fine + tile) * (size_t)p * (R * kFineThreads);
+  // nodes whose q_m the contraction reads: corners of owned cells
+  const bool col_b = gx >= ix0 - 1 && gx <= ix1;
+  auto need_b = [&](int r) { return col_b && gyb + r >= iy0 - 1 && gyb + r <= iy1; };
 
   // ---- one batch of global reads
   const double kv = tid < L.nb ? a.kappa[(size_t)s * L.nb + tid] : 0.0;
-  const double cvec = x < p ? cf[1 + x] : 0.0;                 // lane m: c1 (m = 0) or c2_m
-  const double bvec = (x >= 1 && x < p) ? L.beta[x] : 0.0;     // lane m: beta_m
-  const int gxs = min(max(gx, 1), L.nxn - 1);
-  const double hxE = L.hx[gxs], hxW = L.hx[gxs - 1], ihE = L.inv2hx[gxs], ihW = L.inv2hx[gxs - 1];
+  const int gxc = min(gx, L.nxn - 1);                  // column, in bounds off the grid
+  const int gxw = max(gxc - 1, 0);
+  const double hxE = L.hx[gxc], hxW = L.hx[gxw], ihE = L.inv2hx[gxc];
   double hyv[R + 1], ihy[R + 1];
+  uint32_t ni[R + 2];                                  // node words of rows gy-1 .. gy+4
 #pragma unroll
-  for (int q = 0; q <= R; ++q) {
+  for (int q = 0; q <= R + 1; ++q) {
     const int g = min(max(gyb - 1 + q, 0), L.nyn - 1);
-    hyv[q] = L.hy[g];
-    ihy[q] = L.inv2hy[g];
+    if (q <= R) {
+      hyv[q] = L.hy[g];
+      ihy[q] = L.inv2hy[g];
+    }
+    ni[q] = L.ninfo[g * ld + gxc];
   }
   double y[R], im[R];
-  uint32_t f[R + 1], cbE[R + 1], cbW[R + 1];                    // f[R]: row yb+4
+  uint32_t f[R + 1];                                   // f[R]: row yb + 4
 #pragma unroll
   for (int r = 0; r <= R; ++r) {
     const bool ok = wave_on && col_on && yb + r < RY && gyb + r < L.nyn;
-    const int k = ok ? (gyb + r) * ld + gx : ld + 1;
-    f[r] = ok ? (uint32_t)L.flags[k] : 0u;
+    f[r] = ok ? ni[r + 1] & 0xFFu : 0u;
     if (r < R) {
+      const int k = ok ? (gyb + r) * ld + gx : ld + 1;
       y[r] = ok ? y_g[k] : 0.0;
       const double mu = ok ? mu_g[k] : 0.0;
       im[r] = ok ? L.invm[k] : 0.0;
       lL[r * kFineThreads + tid] = im[r] != 0.0 ? a.f * mu / im[r] : 0.0;   // Lambda_p = f M mu
     }
   }
-#pragma unroll
-  for (int q = 0; q <= R; ++q) {
-    const int cy = min(max(gyb - 1 + q, 0), L.nyn - 2);
-    const int kc = cy * ld + gxs;
-    cbE[q] = L.cblk[kc];
-    cbW[q] = L.cblk[kc - 1];
-  }
   // Cell (gx, gyb + r), computed by the lane of its lower-left node, belongs to
-  // this tile if its first corner in P (order: lower-left, lower-right,
-  // upper-left, upper-right) is inside the tile: that node is in F+, so its
-  // tile exists, and the cell's lower-left node, one node away at most, lies
-  // in the region (the F+ bounding box grown by one).  Corner flags of the next
-  // lane and row come by DPP and from the row above.
+  // this tile if its first corner in P is inside the tile: that node is in F+,
+  // so its tile exists, and the cell's lower-left node, one node away at most,
+  // lies in the region (the F+ bounding box grown by one).  Corner flags of the
+  // next lane and row come by DPP and from the row above.
   uint32_t own = 0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -354,67 +363,78 @@ __global__ __launch_bounds__(kFineThreads) void k_adj_fine(AdjTileArgs a) {
     else if (fu & F_P) { cx = gx; cy = gy + 1; }
     else if (fun & F_P) { cx = gx + 1; cy = gy + 1; }
     const bool in = cx >= ix0 && cx < ix1 && cy >= iy0 && cy < iy1;
-    if (wave_on && col_on && yb + r < RY && in && cbE[r + 1] != 255u) own |= 1u << r;
+    const bool cell = ((ni[r + 1] >> 8) & 0xFFu) != 255u;
+    if (wave_on && col_on && yb + r < RY && in && cell) own |= 1u << r;
   }
-  // ---- LDS: kappa, boundary rows of q_0 = P y (buffer 0) and v = (I - P) y (buffer 1)
+  // ---- LDS: kappa (zero past the last block), boundary rows of q_0 = P y
+  //      (buffer 0) and v = (I - P) y (buffer 1), zero rows of all four buffers
   double* const q0b = lb;
   double* const q1b = lb + kBndSlots;
   const int top = (2 * wv + 1) * W + x, bot = (2 * wv + 2) * W + x;
   const int below = 2 * wv * W + x, above = (2 * wv + 3) * W + x;
-  if (tid < L.nb) lk[tid] = kv;
-  {
-    const bool p0 = f[0] & F_P, p3 = f[R - 1] & F_P;
-    q0b[top] = p0 ? y[0] : 0.0;
-    q0b[bot] = p3 ? y[R - 1] : 0.0;
-    q1b[top] = p0 ? 0.0 : y[0];
-    q1b[bot] = p3 ? 0.0 : y[R - 1];
+  if (tid < 256) lk[tid] = kv;
+  double up[R], pm[R], v[R + 2];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const bool pi = f[r] & F_P;
+    up[r] = pi ? y[r] : 0.0;
+    pm[r] = pi ? 1.0 : 0.0;
+    v[r + 1] = y[r] - up[r];
   }
-  for (int t = tid; t < 8 * W; t += kFineThreads) {           // zero rows of all four buffers
+  q0b[top] = up[0];
+  q0b[bot] = up[R - 1];
+  q1b[top] = v[1];
+  q1b[bot] = v[R];
+  for (int t = tid; t < 8 * W; t += kFineThreads) {
     const int buf = t / (2 * W), z = (t % (2 * W)) < W ? (t % W) : (kBndRows - 1) * W + (t % W);
     lb[buf * kBndSlots + z] = 0.0;
   }
   __syncthreads();
 
-  // ---- edge coefficients (unscaled; row r's south edge = row r-1's north edge) and w
-  double cE[R], cW[R], cV[R + 1];
+  // ---- edge coefficients: kappa of the cells east / west of the node, the
+  //      vertical edges shared by consecutive rows, the west edge of a node the
+  //      east edge of its west neighbour
+  double cE[R], cV[R + 1];
   {
     double kE[R + 1], kW[R + 1];
 #pragma unroll
     for (int c = 0; c <= R; ++c) {
-      kE[c] = lk[cbE[c]];
-      kW[c] = lk[cbW[c]];
+      kE[c] = lk[(ni[c] >> 8) & 0xFFu];
+      kW[c] = lk[(ni[c] >> 16) & 0xFFu];
     }
 #pragma unroll
     for (int c = 0; c <= R; ++c) cV[c] = (kE[c] * hxE + kW[c] * hxW) * ihy[c];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      cE[r] = (kE[r + 1] * hyv[r + 1] + kE[r] * hyv[r]) * ihE;
-      cW[r] = (kW[r + 1] * hyv[r + 1] + kW[r] * hyv[r]) * ihW;
-    }
+    for (int r = 0; r < R; ++r) cE[r] = (kE[r + 1] * hyv[r + 1] + kE[r] * hyv[r]) * ihE;
   }
-  auto stencil = [&](const double* vv, double vS0, double vN3, int r) {   // sum_x c_x (v_i - v_x)
-    const double vi = vv[r];
-    const double vE = lane_next(vi), vW = lane_prev(vi);
-    const double vN = r + 1 < R ? vv[r + 1] : vN3;
-    const double vS = r > 0 ? vv[r - 1] : vS0;
-    return cE[r] * (vi - vE) + cW[r] * (vi - vW) + cV[r + 1] * (vi - vN) + cV[r] * (vi - vS);
-  };
-  double w[R], q[R];
+  // forward: coefficients scaled by 1/m on F+, w = A_u (I - P) y
+  double aE[R], aW[R], aN[R], aS[R], w[R], q[R];
   {
-    double v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = (f[r] & F_P) ? 0.0 : y[r];
-    const double vS0 = q1b[below], vN3 = q1b[above];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const double st = stencil(v, vS0, vN3, r);
-      w[r] = (f[r] & F_FPLUS) ? im[r] * st : 0.0;
-      q[r] = (f[r] & F_P) ? y[r] : 0.0;
+      const double imf = (f[r] & F_FPLUS) ? im[r] : 0.0;
+      aE[r] = imf * cE[r];
+      aW[r] = imf * lane_prev(cE[r]);
+      aN[r] = imf * cV[r + 1];
+      aS[r] = imf * cV[r];
+      q[r] = up[r];
+      if (need_b(r)) scr[(size_t)r * kFineThreads + tid] = up[r];   // q_0
+    }
+    v[0] = q1b[below];
+    v[R + 1] = q1b[above];
+    double dN[R + 1];
+#pragma unroll
+    for (int c = 0; c <= R; ++c) dN[c] = v[c] - v[c + 1];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const double dE = v[r + 1] - lane_next(v[r + 1]);
+      const double dWn = lane_prev(dE);
+      w[r] = aS[r] * -dN[r] + (aN[r] * dN[r + 1] + (aW[r] * -dWn + aE[r] * dE));
     }
   }
   __syncthreads();   // buffer 1 is overwritten by the first substep
 
-  // ---- forward substeps: d_1 .. d_p-1 into the scratch (q_m = P (y + d_m))
+  // ---- forward substeps: q_1 .. q_p-1 into the scratch (q_m = P (y + d_m))
   double d0[R], d1[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) d0[r] = d1[r] = 0.0;
@@ -422,21 +442,25 @@ __global__ __launch_bounds__(kFineThreads) void k_adj_fine(AdjTileArgs a) {
     constexpr int B = decltype(Bc)::value;
     double* dc = B == 0 ? d0 : d1;
     double* dq = B == 0 ? d1 : d0;
-    const double c = lane_bcast(cvec, m), b = lane_bcast(bvec, m);
+    const double c = cf[1 + m];
+    const double b = m > 0 ? L.beta[m] : 0.0;
     const double* rb = B == 0 ? q0b : q1b;
     double* wb = B == 0 ? q1b : q0b;
     if (wave_on) {
-      const double qS0 = rb[below], qN3 = rb[above];
+      double dN[R + 1];
+      dN[0] = rb[below] - q[0];
+#pragma unroll
+      for (int r = 0; r < R; ++r) dN[r + 1] = q[r] - (r + 1 < R ? q[r + 1] : rb[above]);
       double qn[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const double st = stencil(q, qS0, qN3, r);   // DPP: every lane takes part
-        const double apq = (f[r] & F_FPLUS) ? im[r] * st : 0.0;
-        const double rr = w[r] + apq;
-        const double dn = m == 0 ? -c * rr : (1.0 + b) * dc[r] - b * dq[r] - c * rr;
+        const double dE = q[r] - lane_next(q[r]);
+        const double dWn = lane_prev(dE);
+        const double rr = aS[r] * -dN[r] + (aN[r] * dN[r + 1] + (aW[r] * -dWn + (aE[r] * dE + w[r])));
+        const double dn = (dc[r] + b * (dc[r] - dq[r])) - c * rr;
         dq[r] = dn;
-        qn[r] = (f[r] & F_P) ? y[r] + dn : 0.0;
-        scr[((size_t)m * R + r) * kFineThreads + tid] = dn;    // d_m+1
+        qn[r] = pm[r] * dn + up[r];
+        if (need_b(r)) scr[((size_t)(m + 1) * R + r) * kFineThreads + tid] = qn[r];   // q_m+1
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) q[r] = qn[r];
@@ -451,30 +475,27 @@ __global__ __launch_bounds__(kFineThreads) void k_adj_fine(AdjTileArgs a) {
   }
 
   // ---- reverse sweep: Lambda_p = f M mu, Lambda_p+1 = 0; m = p-1 .. 0
-  double l1[R], l2[R], lw[R], acc[R];
+  double l1[R], l2[R], lw[R], SH[R], SV[R], imr[R];
+  bool pr[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     l1[r] = lL[r * kFineThreads + tid];
-    l2[r] = lw[r] = acc[r] = 0.0;
+    l2[r] = lw[r] = SH[r] = SV[r] = 0.0;
+    const bool ok = wave_on && col_on && yb + r < RY && gyb + r < L.nyn;
+    imr[r] = ok ? L.invm[(gyb + r) * ld + gx] : 0.0;
+    pr[r] = f[r] & F_P;
   }
-  // cell legs: hy / (2 hx) along x and hx / (2 hy) along y of cell row gyb + r
-  auto side = [&](int r, double a0, double a1, double a2, double a3, double b0, double b1, double b2,
-                  double b3) {
-    return hyv[r + 1] * ihE * ((a0 - a1) * (b0 - b1) + (a2 - a3) * (b2 - b3)) +
-           hxE * ihy[r + 1] * ((a0 - a2) * (b0 - b2) + (a1 - a3) * (b1 - b3));
-  };
   for (int m = p - 1; m >= 0; --m) {
     const int B = m & 1;
-    const double cm = lane_bcast(cvec, m);
+    const double nc = -cf[1 + m];                        // the pair's factor -c_m
     double t[R], bq[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      t[r] = l1[r] * im[r];
-      const double dm = m == 0 ? 0.0 : scr[((size_t)(m - 1) * R + r) * kFineThreads + tid];
-      bq[r] = (f[r] & F_P) ? y[r] + dm : 0.0;
+      t[r] = l1[r] * imr[r];                             // Lambda_m+1 / m
+      bq[r] = need_b(r) ? scr[((size_t)m * R + r) * kFineThreads + tid] : 0.0;   // q_m
     }
-    double* const tb = lb + B * kBndSlots;                 // t = Lambda / m boundary rows
-    double* const bb = lb + (2 + B) * kBndSlots;           // b = P q_m top rows
+    double* const tb = lb + B * kBndSlots;               // t boundary rows
+    double* const bb = lb + (2 + B) * kBndSlots;         // q_m top rows
     if (wave_on) {
       tb[top] = t[0];
       tb[bot] = t[R - 1];
@@ -482,63 +503,92 @@ __global__ __launch_bounds__(kFineThreads) void k_adj_fine(AdjTileArgs a) {
     }
     __syncthreads();
     if (wave_on) {
-      const double tS0 = tb[below], tN3 = tb[above], bN3 = bb[above];
+      double dNt[R + 1];                                 // dNt[r + 1] = t_r - t_r+1, dNt[0] = t_-1 - t_0
+      dNt[0] = tb[below] - t[0];
+      const double tN3 = tb[above], bN3 = bb[above];
+#pragma unroll
+      for (int r = 0; r < R; ++r) dNt[r + 1] = t[r] - (r + 1 < R ? t[r + 1] : tN3);
+      double ln[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        // pair (-c_m Lambda_m+1, P q_m) on cell (x, r)
-        const double t0 = t[r], t1 = lane_next(t0), t2 = r + 1 < R ? t[r + 1] : tN3, t3 = lane_next(t2);
-        const double b0 = bq[r], b1 = lane_next(b0), b2 = r + 1 < R ? bq[r + 1] : bN3, b3 = lane_next(b2);
-        acc[r] -= cm * side(r, t0, t1, t2, t3, b0, b1, b2, b3);
-        lw[r] -= cm * l1[r];
+        const double dEt = t[r] - lane_next(t[r]);
+        const double dEb = bq[r] - lane_next(bq[r]);
+        const double dNb = bq[r] - (r + 1 < R ? bq[r + 1] : bN3);
+        SH[r] += (nc * dEt) * dEb;
+        SV[r] += (nc * dNt[r + 1]) * dNb;
+        lw[r] += nc * l1[r];
+        const double dWn = lane_prev(dEt);             // every lane takes part in the DPP
+        const double cW = lane_prev(cE[r]);
+        const double st = cV[r] * -dNt[r] + (cV[r + 1] * dNt[r + 1] + (cW * -dWn + cE[r] * dEt));
+        ln[r] = pr[r] ? st : 0.0;                      // (P K) (Lambda_m+1 / m)
       }
       if (m > 0) {
-        const double bm = lane_bcast(bvec, m);
-        const double bm1 = m + 1 < p ? lane_bcast(bvec, m + 1) : 0.0;
-        double ln[R];
+        const double bm = L.beta[m];
+        const double bm1 = m + 1 < p ? L.beta[m + 1] : 0.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const double st = stencil(t, tS0, tN3, r);   // DPP: every lane takes part
-          const double kt = (f[r] & F_P) ? st : 0.0;
-          ln[r] = (1.0 + bm) * l1[r] - cm * kt - bm1 * l2[r];
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
+          const double lm = (1.0 + bm) * l1[r] + nc * ln[r] - bm1 * l2[r];   // Lambda_m
           l2[r] = l1[r];
-          l1[r] = ln[r];
+          l1[r] = lm;
         }
       }
     }
   }
-  // ---- pair (lw, (I - P) y)
+  // ---- pair (lw, (I - P) y), then the cell sums
   {
-    double aw[R], v[R];
+    double aw[R], vv[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      aw[r] = lw[r] * im[r];
-      v[r] = (f[r] & F_P) ? 0.0 : y[r];
+      aw[r] = lw[r] * imr[r];
+      const bool ok = wave_on && col_on && yb + r < RY && gyb + r < L.nyn;
+      vv[r] = (ok && !pr[r]) ? y_g[(gyb + r) * ld + gx] : 0.0;
     }
     // buffers of the parity not read in the last reverse step (m = 0 used parity 0)
     double* const tb = lb + kBndSlots;
     double* const bb = lb + 3 * kBndSlots;
     if (wave_on) {
       tb[top] = aw[0];
-      bb[top] = v[0];
+      bb[top] = vv[0];
     }
     __syncthreads();
     if (wave_on) {
       const double aN3 = tb[above], vN3 = bb[above];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const double a0 = aw[r], a1 = lane_next(a0), a2 = r + 1 < R ? aw[r + 1] : aN3, a3 = lane_next(a2);
-        const double b0 = v[r], b1 = lane_next(b0), b2 = r + 1 < R ? v[r + 1] : vN3, b3 = lane_next(b2);
-        acc[r] += side(r, a0, a1, a2, a3, b0, b1, b2, b3);
+        const double dEa = aw[r] - lane_next(aw[r]), dEv = vv[r] - lane_next(vv[r]);
+        const double dNa = aw[r] - (r + 1 < R ? aw[r + 1] : aN3), dNv = vv[r] - (r + 1 < R ? vv[r + 1] : vN3);
+        SH[r] += dEa * dEv;
+        SV[r] += dNa * dNv;
       }
     }
   }
+  // cell (x, r): its bottom edge is this node's east edge, its top edge the east
+  // edge of the node above (the next wavefront's row 0 for r = 3), its left and
+  // right edges the north edges of this node and of the east neighbour
+  double* const sb = lb;   // buffer 0 (last read before the previous barrier): SH of each row 0
+  if (wave_on) sb[top] = SH[0];
+  __syncthreads();
   double* __restrict__ Gs = a.G + (size_t)s * a.sstride;
+  if (wave_on) {
+    // the cell geometry is read again here rather than kept in registers
+    // through both sweeps (the opaque copy of the level view stops the
+    // compiler from reusing the first reads)
+    const double* hxp = L.hx;
+    const double* hyp = L.hy;
+    const double* ihxp = L.inv2hx;
+    const double* ihyp = L.inv2hy;
+    asm volatile("" : "+s"(hxp), "+s"(hyp), "+s"(ihxp), "+s"(ihyp));
+    const double gxE = hxp[gxc], gihE = ihxp[gxc];
+    const double shN = sb[above];
 #pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (own & (1u << r)) Gs[(size_t)(gyb + r) * ld + gx] += acc[r];
+    for (int r = 0; r < R; ++r) {
+      const int g = min(gyb + r, L.nyn - 1);
+      const double svE = lane_next(SV[r]);
+      const double acc = hyp[g] * gihE * (SH[r] + (r + 1 < R ? SH[r + 1] : shN)) +
+                         gxE * ihyp[g] * (SV[r] + svE);
+      if (own & (1u << r)) Gs[(size_t)(gyb + r) * ld + gx] += acc;
+    }
+  }
 }
 
 // Cells without a node of P: with lw / m = gamma f mu (gamma from the substep
@@ -653,11 +703,11 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
   if (r != LTS_OK) return r;
 
   // ---- backward
-  // fused form on rect fine tiles: per-(sample, tile) scratch for d_1 .. d_p-1
+  // fused form on rect fine tiles: per-(sample, tile) scratch for q_0 .. q_p-1
   const TilingDev& T = lv.tiling;
   const bool fused = T.rect && T.n_fine > 0;
   if (fused)
-    LTS_HIP(c, c->adjscr.ensure(std::max<size_t>((size_t)T.n_fine * n * (size_t)std::max(p - 1, 1) *
+    LTS_HIP(c, c->adjscr.ensure(std::max<size_t>((size_t)T.n_fine * n * (size_t)p *
                                                  (4 * kFineThreads) * sizeof(double), 8)));
   double* MU[2] = {arr(imu0), arr(imu1)};
   k_adj_mu_init<<<grid(Lv.ld, n), blk, 0, c->stream>>>(a, d_nsteps, MU[0], MU[1]);

@@ -460,7 +460,7 @@ lts_status lts_backward(lts_ctx c, int32_t level, const lts_samples* S, const do
   // sub-batches sized so the checkpoint workspace stays below ~48 GiB
   const int n_ck = (st.nsteps[0] + K - 1) / K;
   const double per_sample = (2.0 * n_ck + K + 2.0 * lv->H.p + 8.0) * (double)lv->nodes * 8.0 +
-                            (lv->tiling.rect ? (double)lv->tiling.n_fine * std::max(lv->H.p - 1, 1) *
+                            (lv->tiling.rect ? (double)lv->tiling.n_fine * lv->H.p *
                                                    (4.0 * kFineThreads) * 8.0 : 0.0);
   const int chunk = std::max(1, std::min(n, (int)(48.0 * (1ull << 30) / per_sample)));
   const int p1 = lv->H.p + 1;
