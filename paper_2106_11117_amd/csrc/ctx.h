@@ -14,7 +14,8 @@
 
 namespace lts {
 
-// Grow-only device buffer owned by a context.
+// Device buffer owned by a context: grows on demand, freed by release() or
+// with the context.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -36,6 +37,11 @@ struct DevBuf {
   template <class T>
   T* as() const {
     return static_cast<T*>(p);
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
   }
 };
 

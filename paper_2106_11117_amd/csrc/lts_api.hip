@@ -457,12 +457,20 @@ lts_status lts_backward(lts_ctx c, int32_t level, const lts_samples* S, const do
   LTS_HIP(c, c->dldq.ensure((size_t)n * 8));
   LTS_HIP(c, c->gout.ensure((size_t)n * nb * 8));
   LTS_HIP(c, hipMemcpyAsync(c->dldq.p, dls.data(), (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
-  // sub-batches sized so the checkpoint workspace stays below ~48 GiB
+  // Sub-batches sized to the device: the checkpoints, the segment and the
+  // fused scratch of one sub-batch take at most 60 % of the free memory (this
+  // context's own adjoint buffers counted as free), in equal sub-batches.
+  // Fewer sub-batches mean fewer, fuller launches.
   const int n_ck = (st.nsteps[0] + K - 1) / K;
   const double per_sample = (2.0 * n_ck + K + 2.0 * lv->H.p + 8.0) * (double)lv->nodes * 8.0 +
                             (lv->tiling.rect ? (double)lv->tiling.n_fine * lv->H.p *
                                                    (4.0 * kFineThreads) * 8.0 : 0.0);
-  const int chunk = std::max(1, std::min(n, (int)(48.0 * (1ull << 30) / per_sample)));
+  size_t mem_free = 0, mem_total = 0;
+  LTS_HIP(c, hipMemGetInfo(&mem_free, &mem_total));
+  const double avail = 0.6 * ((double)mem_free + (double)c->adj.bytes + (double)c->adjscr.bytes);
+  const int fit = std::max(1, std::min(n, (int)(avail / per_sample)));
+  const int n_sub = (n + fit - 1) / fit;
+  const int chunk = (n + n_sub - 1) / n_sub;
   const int p1 = lv->H.p + 1;
   for (int s0 = 0; s0 < n; s0 += chunk) {
     const int m = std::min(chunk, n - s0);
@@ -475,6 +483,12 @@ lts_status lts_backward(lts_ctx c, int32_t level, const lts_samples* S, const do
   std::vector<double> g((size_t)n * nb), gs((size_t)n * nb);
   LTS_HIP(c, hipMemcpyAsync(gs.data(), c->gout.p, gs.size() * 8, hipMemcpyDeviceToHost, c->stream));
   LTS_HIP(c, hipStreamSynchronize(c->stream));
+  // a large workspace is not kept between calls (it would starve other users
+  // of the device); small ones are reused
+  if (c->adj.bytes + c->adjscr.bytes > (size_t)48 << 30) {
+    c->adj.release();
+    c->adjscr.release();
+  }
   for (int t = 0; t < n; ++t)
     std::copy(&gs[(size_t)t * nb], &gs[(size_t)t * nb] + nb, &g[(size_t)st.perm[t] * nb]);
   const hipMemcpyKind k = S->ptr_kind == LTS_PTR_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
