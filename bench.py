@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0
 # the algorithmic bytes on the profiled launches (all samples active), applied
 # to the average launch's 1.7105e9 algorithmic bytes.  Valid only for the
 # step-kernel sources the counters were taken with.
-TRAFFIC = {"bytes_per_launch": 1.389 * 1.7105e9,
-           "sources_sha256": "b41339ff007b0fe0a462fbb0bd406879c259636b6a182eb3f740204c1d7009e7"}
+TRAFFIC = {"bytes_per_launch": 1.380 * 1.7105e9,
+           "sources_sha256": "dcf5cfec1500655f4e639f3909079dae007beea83f4c9f9d6febab34cb31924d"}
 STEP_SOURCES = ("lts_fused.hip", "fused.h", "device.h", "lts_step.hip")
 WORKLOAD = ("unit square 512x512 base refined 8x in (0.48,0.52): 442225 DOFs, |P|=204081, p=8, "
             "nu=0.01, 256 samples, 4x4 blocks sigma=0.25, T=1, FP64")

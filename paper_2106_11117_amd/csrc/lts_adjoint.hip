@@ -446,7 +446,12 @@ __global__ __launch_bounds__(kFineThreads) void k_adj_fine(AdjTileArgs a) {
     const double b = m > 0 ? L.beta[m] : 0.0;
     const double* rb = B == 0 ? q0b : q1b;
     double* wb = B == 0 ? q1b : q0b;
-    if (wave_on) {
+    // q_m+1 is needed within p-1-m rows of the tile interior (the contraction
+    // reads q at the interior's rows and one beyond); wavefronts whose rows all
+    // lie farther out skip the substep (rows left stale are read only by rows
+    // outside the next band)
+    const int reach = p - 1 - m;
+    if (wave_on && gyb + R > iy0 - reach && gyb < iy1 + reach) {
       double dN[R + 1];
       dN[0] = rb[below] - q[0];
 #pragma unroll
@@ -502,7 +507,10 @@ __global__ __launch_bounds__(kFineThreads) void k_adj_fine(AdjTileArgs a) {
       bb[top] = bq[0];
     }
     __syncthreads();
-    if (wave_on) {
+    // Lambda_m is needed within m rows of the tile interior (at least one:
+    // the contraction reads the interior's rows and one beyond)
+    const int reach = m > 1 ? m : 1;
+    if (wave_on && gyb + R > iy0 - reach && gyb < iy1 + reach) {
       double dNt[R + 1];                                 // dNt[r + 1] = t_r - t_r+1, dNt[0] = t_-1 - t_0
       dNt[0] = tb[below] - t[0];
       const double tN3 = tb[above], bN3 = bb[above];
