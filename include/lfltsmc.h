@@ -276,7 +276,8 @@ lts_status lts_batch_run(lts_ctx ctx, const lts_job* jobs, int32_t n_jobs, int32
 lts_status lts_autotune(lts_ctx ctx, int32_t level);
 
 /* Pin the fine-tile shape of `level` to tile_x x tile_y grid nodes in rect
- * mode (rect = 1: each region held as a zero-padded rectangle in LDS) or
+ * mode (rect = 1: each region handled as a zero-padded rectangle of up to
+ * 64 x 64 nodes, one lane per column, state in registers) or
  * compact mode (rect = 0: the region's F+ nodes compacted with neighbour
  * indices), with the tile-grid origin chosen to minimise region overhead.
  * Later solves use it and lts_batch_run does not re-tune the level (a later

@@ -71,12 +71,5 @@ __device__ __forceinline__ float lane_next(float v) {
 __device__ __forceinline__ float lane_prev(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
 }
-// Broadcast lane m's value of v (m wavefront-uniform).
-__device__ __forceinline__ double lane_bcast(double v, int m) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), m);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), m);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
 
 }  // namespace lts

@@ -29,7 +29,7 @@ static_assert(kCoarseRows <= 16, "coarse row mask is 16 bits");
 struct TilingHost {
   int TX = 0, TY = 0;
   int ox = 0, oy = 0;               // origin of the tile grid
-  bool rect = false;                // region stored as a zero-padded rectangle in LDS
+  bool rect = false;                // region handled as a zero-padded rectangle (lane = column)
   int pitch = 0;                    // rect mode: LDS row pitch (slots)
   int n_fine = 0, n_coarse = 0, wg_per_sample = 0;   // wg_per_sample: fine + coarse workgroups
   double halo_ratio = 1.0;          // region lanes / F+ nodes

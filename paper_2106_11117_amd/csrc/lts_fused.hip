@@ -3,29 +3,31 @@
 // update formulas).
 //
 // Work decomposition, shared by all samples of a level (host-built tiling):
-//  * coarse items: 64 grid columns x CR rows.  One wavefront per item, one
-//    lane per column walking down the rows; it updates the DOFs outside F+
-//    (no P neighbour there, so w = A_u u and u_n+1 = 2u_n - u_n-1 + 2 a_p w).
+//  * coarse items: 64 grid columns x 16 rows.  One workgroup of four
+//    wavefronts per item, lane = column, wavefront v = rows 4v .. 4v+3; all
+//    its reads are issued in one batch, east / west neighbours come by DPP.
+//    It updates the DOFs outside F+ (no P neighbour there, so w = A_u u and
+//    u_n+1 = 2u_n - u_n-1 + 2 a_p w).
 //  * fine tiles: a rectangle of the node grid; its "region" is the rectangle
-//    grown by p nodes in each direction (only F+ nodes of it take part).  One
-//    workgroup runs all p substeps with the P-masked q = u + d of the region
-//    in LDS (double buffered, one barrier per substep) and the per-node state
-//    (u, d_m, d_m-1, w and the scaled edge coefficients) in registers.  Rect
-//    mode keeps the region in LDS as a zero-padded rectangle with one lane per
-//    node, so the four neighbours of a node sit at fixed offsets (+-1,
-//    +-pitch) from its slot and a lane finds its node by arithmetic; compact
-//    mode (used when the rectangle does not fit, e.g. large p) assigns lanes
-//    to the region's F+ nodes only and stores them compacted with per-node
-//    neighbour indices.  Values near the region border are wrong after a few
-//    substeps (missing neighbours read 0) but the error front moves one node
-//    per substep, so after p substeps the tile is exact; only its nodes are
-//    written back.
+//    grown by p nodes in each direction, clipped to the grid and to the F+
+//    bounding box grown by one.  One workgroup runs all p substeps of the
+//    region.  Rect mode (regions up to 64 x 64, p <= 64): lane = column,
+//    wavefront v = rows 4v .. 4v+3, the per-node state (P u_n, d_m, d_m-1, w,
+//    q and the scaled edge coefficients) in registers, east / west neighbours
+//    by DPP and only the rows at wavefront boundaries exchanged through LDS
+//    (double buffered, one barrier per substep).  Compact mode (regions that
+//    do not fit, e.g. large p) assigns lanes to the region's F+ nodes only and
+//    keeps them compacted in LDS with per-node neighbour indices.  Values near
+//    the region border are wrong after a few substeps (missing neighbours read
+//    0) but the error front moves one node per substep, so after p substeps
+//    the tile is exact; only its nodes are written back.
 // Coarse items and fine tiles are two kernels launched back to back on the
 // stream (they write disjoint nodes and only read u_n): the coarse kernel uses
 // no LDS beyond the sample's coefficient table, so it runs at high occupancy,
-// and each fine workgroup owns a whole CU's LDS.  Workgroup ids are remapped
-// so that each of the 8 XCDs works through a contiguous range of (sample,
-// work item): halo rows and the shared level arrays stay in that XCD's L2.
+// and each fine workgroup fills a CU's register file.  Workgroup ids are
+// remapped so that each of the 8 XCDs works through a contiguous range of
+// (sample, work item): halo rows and the shared level arrays stay in that
+// XCD's L2.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
