@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # to the average launch's 1.7105e9 algorithmic bytes.  Valid only for the
 # step-kernel sources the counters were taken with.
 TRAFFIC = {"bytes_per_launch": 1.380 * 1.7105e9,
-           "sources_sha256": "e3c2abc6be797dad202b2b9a21319e9136bcd92ff25fdff74bc9aa181e5381db"}
+           "sources_sha256": "73a93e7d0ddfd046f4af04a8bc98951145ab7a52fd3cc6eb785f48af471180f6"}
 STEP_SOURCES = ("lts_fused.hip", "fused.h", "device.h", "lts_step.hip")
 WORKLOAD = ("unit square 512x512 base refined 8x in (0.48,0.52): 442225 DOFs, |P|=204081, p=8, "
             "nu=0.01, 256 samples, 4x4 blocks sigma=0.25, T=1, FP64")

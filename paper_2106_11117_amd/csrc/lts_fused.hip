@@ -504,9 +504,25 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __rest
     }
     if (m + 1 < p) __syncthreads();
   };
-  for (int m = 0; m < p; m += 2) {
-    substep(m, std::integral_constant<int, 0>{});
-    if (m + 1 < p) substep(m + 1, std::integral_constant<int, 1>{});
+  // fully unrolled for the common refinement ratios (constant substep index:
+  // no loop control, scheduling across substeps), a loop otherwise
+  auto unrolled = [&](auto Pc) {
+    constexpr int PP = decltype(Pc)::value;
+#pragma unroll
+    for (int m = 0; m < PP; m += 2) {
+      substep(m, std::integral_constant<int, 0>{});
+      substep(m + 1, std::integral_constant<int, 1>{});
+    }
+  };
+  if (p == 8) {
+    unrolled(std::integral_constant<int, 8>{});
+  } else if (p == 4) {
+    unrolled(std::integral_constant<int, 4>{});
+  } else {
+    for (int m = 0; m < p; m += 2) {
+      substep(m, std::integral_constant<int, 0>{});
+      if (m + 1 < p) substep(m + 1, std::integral_constant<int, 1>{});
+    }
   }
   T d[R];
 #pragma unroll
