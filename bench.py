@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # to the average launch's 1.7105e9 algorithmic bytes.  Valid only for the
 # step-kernel sources the counters were taken with.
 TRAFFIC = {"bytes_per_launch": 1.380 * 1.7105e9,
-           "sources_sha256": "73a93e7d0ddfd046f4af04a8bc98951145ab7a52fd3cc6eb785f48af471180f6"}
+           "sources_sha256": "a088c042330a9c47a599fa60c0038b5640d4e4477dd5c18efcb2a042e03310ef"}
 STEP_SOURCES = ("lts_fused.hip", "fused.h", "device.h", "lts_step.hip")
 WORKLOAD = ("unit square 512x512 base refined 8x in (0.48,0.52): 442225 DOFs, |P|=204081, p=8, "
             "nu=0.01, 256 samples, 4x4 blocks sigma=0.25, T=1, FP64")
@@ -228,6 +228,74 @@ def adjoint_bench(samples: int, K: int):
     ctx.close()
 
 
+BATCH_N = (4096, 1024, 256, 64, 16)       # samples per level of the multi-level throughput run
+
+
+def batch_bench(plain: bool):
+    """Form 2 throughput on the graded L-shape hierarchy (5 levels, h = 1/16 ..
+    1/256, p = 64, 8x8 blocks sigma 0.3, T = 2): the samples of all levels
+    (N_l = 4096, 1024, 256, 64, 16) advanced together by lts_batch_run, with and
+    without graph capture, against one lts_forward call per level and, with
+    --plain, the one-launch-per-sample form.  Autotuning is setup, outside the
+    timed region; every form must return the same QoIs."""
+    import numpy as np
+
+    import paper_2106_11117_amd as P
+
+    ctx = P.Context(0)
+    ids = [ctx.add_rect_level(P.graded_L_rule(nb)) for nb in MLMC_BASES]
+    rule = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), width=0.05, T=2.0)
+    t0 = time.perf_counter()
+    for lid in ids:
+        ctx.autotune(lid)
+    setup = time.perf_counter() - t0
+    jobs, levels = [], []
+    dof_upd = alg_bytes = 0.0
+    for lev, (lid, n) in enumerate(zip(ids, BATCH_N)):
+        info = ctx.level_info(lid)
+        smp = P.gen_samples(0, lev, 0, n, rule, info["h"])
+        jobs.append((lid, smp["kappa"], smp["x0"], smp["n_steps"], smp["dt"], 0.05))
+        steps = float(smp["n_steps"].sum())
+        per_step = (info["n_dof"] - info["n_P"]) + info["p"] * info["n_P"]
+        dof_upd += steps * per_step
+        alg_bytes += steps * 24.0 * info["n_dof"]
+        levels.append({"dofs": info["n_dof"], "P": info["n_P"], "p": info["p"], "samples": n,
+                       "sum_n_steps": int(steps)})
+
+    def median_time(fn, reps):
+        ts, out = [], None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            out = fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), out
+
+    ctx.batch_run(jobs, graph=True)                      # warm-up; captures the graph
+    t_graph, q_graph = median_time(lambda: ctx.batch_run(jobs, graph=True), 3)
+    t_batch, q_batch = median_time(lambda: ctx.batch_run(jobs, graph=False), 3)
+    per_level = lambda **kw: np.concatenate([np.asarray(ctx.forward(j[0], *j[1:5], width=j[5], **kw))
+                                             for j in jobs])
+    t_level, q_level = median_time(per_level, 3)
+    out = {"metric": "batched multi-level LF-LTS throughput (form 2), graded L-shape hierarchy",
+           "unit": "DOF-updates/s", "higher_is_better": True, "data": "synthetic (Philox seed 0)", "dtype": "f64",
+           "config": {"workload": "graded L-shape, 5 levels h = 1/16..1/256, 6 graded layers (h_min = h/64, "
+                                  "p = 64), 8x8 blocks sigma 0.3, T = 2", "levels": levels},
+           "setup_autotune_s": setup,
+           "batched_graph": {"s": t_graph, "dof_updates_per_s": dof_upd / t_graph,
+                             "hbm_frac_algorithmic": alg_bytes / t_graph / (HBM_PEAK_GBS * 1e9)},
+           "batched_no_graph": {"s": t_batch, "dof_updates_per_s": dof_upd / t_batch},
+           "one_forward_per_level": {"s": t_level, "dof_updates_per_s": dof_upd / t_level},
+           "q_equal": bool(np.array_equal(np.asarray(q_graph), np.asarray(q_batch)) and
+                           np.array_equal(np.asarray(q_graph), q_level))}
+    if plain:
+        t_plain, q_plain = median_time(lambda: per_level(plain=True), 1)
+        out["plain"] = {"s": t_plain, "dof_updates_per_s": dof_upd / t_plain,
+                        "speedup_batched_graph_vs_plain": t_plain / t_graph}
+        out["q_equal"] = out["q_equal"] and bool(np.array_equal(np.asarray(q_graph), q_plain))
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def copy_check(mib: int):
     """Four device-to-device copies of `mib` MiB (read mib, write mib each): the
     reference point that turns the FETCH_SIZE / WRITE_SIZE counters of a profiled
@@ -259,7 +327,13 @@ def main():
                     help="only time the discrete adjoint against the forward solve (K = 64)")
     ap.add_argument("--mlmc", action="store_true",
                     help="only run the MLMC wall-time comparison (graded L-shape, Algorithm 1)")
+    ap.add_argument("--batch", action="store_true",
+                    help="only time the batched multi-level form on the graded L-shape hierarchy "
+                         "(with --plain: also the one-launch-per-sample form)")
     args = ap.parse_args()
+    if args.batch:
+        batch_bench(args.plain)
+        return
     if args.adjoint:
         adjoint_bench(args.samples, 64)
         return

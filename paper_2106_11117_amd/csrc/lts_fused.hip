@@ -58,6 +58,15 @@ struct StepArgs {
   double* B1;
 };
 
+// What changes from step to step: the state buffers and the start-up flag.
+// Kept apart from the job data so that the batched kernels read a job's
+// record in place (a copy would hide that its pointers address global memory).
+struct StepState {
+  const double* Ucur;   // u_n of sample s at Ucur + s*sstride
+  double* Uold;         // u_n-1 in, u_n+1 out
+  int startup;
+};
+
 // Launch-time data of a batched launch over several jobs (levels).
 struct MultiArgs {
   const StepArgs* __restrict__ jobs;   // static per-job data (device table)
@@ -76,7 +85,8 @@ namespace {
 // holding a DOF outside F+, w = 16-bit mask of such rows; lanes and wavefronts
 // without such a DOF return at once.
 template <class T>
-__device__ __forceinline__ void coarse_body(const StepArgs& a, double* __restrict__ lk, int s, int item) {
+__device__ __forceinline__ void coarse_body(const StepArgs& a, const StepState& st, double* __restrict__ lk, int s,
+                                            int item) {
   const LevelView& L = a.L;
   const int4 it = a.citems[item];
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -93,10 +103,10 @@ __device__ __forceinline__ void coarse_body(const StepArgs& a, double* __restric
   const int i = min(max(i0 + lane, 1), L.nxn - 2);   // geometry column
   const int j0 = (it.x >> 16) + 4 * wv;               // rows j0 .. j0 + 3
   const int ld = L.ld;
-  const T* __restrict__ u = reinterpret_cast<const T*>(a.Ucur) + (size_t)s * a.sstride;
-  T* __restrict__ uo = reinterpret_cast<T*>(a.Uold) + (size_t)s * a.sstride;
+  const T* __restrict__ u = reinterpret_cast<const T*>(st.Ucur) + (size_t)s * a.sstride;
+  T* __restrict__ uo = reinterpret_cast<T*>(st.Uold) + (size_t)s * a.sstride;
   const T ap = (T)a.coef[(size_t)s * (L.p + 1)];
-  const bool startup = a.startup;
+  const bool startup = st.startup;
   constexpr int R = 4;
   // ---- one batch of reads (with the sample's kappa table); rows off the grid
   //      are clamped and never used
@@ -193,7 +203,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse(StepArgs a) {
   if (Lid >= G) return;
   int item, s;
   coarse_order(Lid, a.n_coarse, a.active, item, s);
-  coarse_body<T>(a, lk, a.s0 + s, item);
+  coarse_body<T>(a, StepState{a.Ucur, a.Uold, a.startup}, lk, a.s0 + s, item);
 }
 
 // Job of a batched launch: the job whose workgroup range holds Lid.
@@ -203,13 +213,36 @@ __device__ __forceinline__ int find_job(const MultiArgs& m, int Lid) {
   return j;
 }
 
-__device__ __forceinline__ StepArgs job_args(const MultiArgs& m, int j) {
-  StepArgs a = m.jobs[j];
+// A pointer field of a job record loaded as a global-address-space pointer.
+// Copied as plain pointers out of device memory, the job's pointers would be
+// addressed as flat pointers (slower accesses, 64-bit addresses in vector
+// registers); loaded with the global type, the compiler keeps global accesses.
+#define LTS_GPTR(f) \
+  ((decltype(+(f)))(*(__attribute__((address_space(1))) std::remove_pointer_t<decltype(+(f))>* const*)(&(f))))
+
+__device__ __forceinline__ StepArgs job_record(const StepArgs& a) {
+  StepArgs b;
+  b.L.nxn = a.L.nxn; b.L.nyn = a.L.nyn; b.L.ld = a.L.ld; b.L.p = a.L.p; b.L.nb = a.L.nb;
+  b.L.hx = LTS_GPTR(a.L.hx); b.L.hy = LTS_GPTR(a.L.hy);
+  b.L.inv2hx = LTS_GPTR(a.L.inv2hx); b.L.inv2hy = LTS_GPTR(a.L.inv2hy);
+  b.L.x = LTS_GPTR(a.L.x); b.L.y = LTS_GPTR(a.L.y);
+  b.L.cblk = LTS_GPTR(a.L.cblk); b.L.flags = LTS_GPTR(a.L.flags); b.L.ninfo = LTS_GPTR(a.L.ninfo);
+  b.L.invm = LTS_GPTR(a.L.invm); b.L.qoiw = LTS_GPTR(a.L.qoiw);
+  b.L.beta = LTS_GPTR(a.L.beta); b.L.beta_half = LTS_GPTR(a.L.beta_half);
+  b.ent = LTS_GPTR(a.ent); b.tiles = LTS_GPTR(a.tiles); b.rtiles = LTS_GPTR(a.rtiles);
+  b.citems = LTS_GPTR(a.citems);
+  b.n_fine = a.n_fine; b.n_coarse = a.n_coarse; b.wg_per_sample = a.wg_per_sample;
+  b.per_xcd = a.per_xcd; b.active = a.active;
+  b.kappa = LTS_GPTR(a.kappa); b.coef = LTS_GPTR(a.coef);
+  b.Ucur = nullptr; b.Uold = nullptr;                 // per step: StepState
+  b.sstride = a.sstride; b.startup = 0; b.s0 = a.s0;
+  b.B0 = LTS_GPTR(a.B0); b.B1 = LTS_GPTR(a.B1);
+  return b;
+}
+
+__device__ __forceinline__ StepState job_state(const MultiArgs& m, const StepArgs& a) {
   const bool odd = m.step & 1;
-  a.Ucur = odd ? a.B1 : a.B0;
-  a.Uold = odd ? a.B0 : a.B1;
-  a.startup = m.step == 0;
-  return a;
+  return StepState{odd ? a.B1 : a.B0, odd ? a.B0 : a.B1, m.step == 0};
 }
 
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_multi(MultiArgs m) {
@@ -217,22 +250,22 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_multi(MultiArgs m) {
   const int Lid = (int)(blockIdx.x & 7) * m.per_xcd + (int)(blockIdx.x >> 3);
   if (Lid >= m.wg_off[m.n_jobs]) return;
   const int j = find_job(m, Lid);
-  const StepArgs a = job_args(m, j);
+  const StepArgs a = job_record(m.jobs[j]);
   const int local = Lid - m.wg_off[j];
   const int act = (m.wg_off[j + 1] - m.wg_off[j]) / a.n_coarse;   // active samples of the job
   int item, s;
   coarse_order(local, a.n_coarse, act, item, s);
-  coarse_body<double>(a, lk, s, item);
+  coarse_body<double>(a, job_state(m, a), lk, s, item);
 }
 
 template <class T>
-__device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const double* __restrict__ lk,
+__device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepState& st, const double* __restrict__ lk,
                                                   T* __restrict__ lq, int s, int tile) {
   const LevelView& L = a.L;
   const int2 tl = a.tiles[tile];
   const int len = tl.y;
-  const T* __restrict__ u_g = reinterpret_cast<const T*>(a.Ucur) + (size_t)s * a.sstride;
-  T* __restrict__ uo_g = reinterpret_cast<T*>(a.Uold) + (size_t)s * a.sstride;
+  const T* __restrict__ u_g = reinterpret_cast<const T*>(st.Ucur) + (size_t)s * a.sstride;
+  T* __restrict__ uo_g = reinterpret_cast<T*>(st.Uold) + (size_t)s * a.sstride;
   const double* __restrict__ cf = a.coef + (size_t)s * (L.p + 1);
 
   T u[kNPT], d[kNPT], dp[kNPT], w[kNPT], aE[kNPT], aW[kNPT], aN[kNPT], aS[kNPT];
@@ -310,7 +343,7 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const doubl
   for (int r = 0; r < kNPT; ++r) {
     if (kk[r] < 0 || !((unsigned)ew[r] >> 31)) continue;
     const size_t k = (size_t)kk[r];
-    uo_g[k] = a.startup ? (u[r] + d[r]) : ((T)2 * u[r] - uo_g[k] + (T)2 * d[r]);
+    uo_g[k] = st.startup ? (u[r] + d[r]) : ((T)2 * u[r] - uo_g[k] + (T)2 * d[r]);
   }
 }
 
@@ -334,7 +367,7 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const doubl
 // substep error front as for q alone, so the tile interior (at distance >= p
 // from the border) stays exact.
 template <class T>
-__device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __restrict__ lk,
+__device__ __forceinline__ void fine_tile_rect(const StepArgs& a, const StepState& st, double* __restrict__ lk,
                                                T* __restrict__ lq, T* __restrict__ ls, int s, int tile) {
   constexpr int R = 4;                                  // rows per lane
   constexpr int W = 64;                                 // boundary-row buffer pitch
@@ -350,10 +383,10 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, double* __rest
   const bool wave_on = yb < RY;                         // wavefront holds region rows
   const int gx = x0 + x;
   const bool col_on = x < RX && gx < L.nxn;
-  const T* __restrict__ u_g = reinterpret_cast<const T*>(a.Ucur) + (size_t)s * a.sstride;
-  T* __restrict__ uo_g = reinterpret_cast<T*>(a.Uold) + (size_t)s * a.sstride;
+  const T* __restrict__ u_g = reinterpret_cast<const T*>(st.Ucur) + (size_t)s * a.sstride;
+  T* __restrict__ uo_g = reinterpret_cast<T*>(st.Uold) + (size_t)s * a.sstride;
   const double* __restrict__ cf = a.coef + (size_t)s * (L.p + 1);
-  const bool startup = a.startup;
+  const bool startup = st.startup;
   const int ld = L.ld;
   const int p = L.p;                                    // <= 64 in rect mode
 
@@ -543,10 +576,10 @@ __global__ __launch_bounds__(kFineThreads) void k_fine(StepArgs a) {
   if (Lid >= G) return;
   const int s = a.s0 + Lid / a.n_fine;
   if (RECT) {
-    fine_tile_rect<T>(a, lk, lq, ls, s, Lid % a.n_fine);
+    fine_tile_rect<T>(a, StepState{a.Ucur, a.Uold, a.startup}, lk, lq, ls, s, Lid % a.n_fine);
   } else {
     load_kappa(a, s, lk);
-    fine_tile_compact<T>(a, lk, lq, s, Lid % a.n_fine);
+    fine_tile_compact<T>(a, StepState{a.Ucur, a.Uold, a.startup}, lk, lq, s, Lid % a.n_fine);
   }
 }
 
@@ -558,14 +591,15 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_multi(MultiArgs m) {
   const int Lid = (int)(blockIdx.x & 7) * m.per_xcd + (int)(blockIdx.x >> 3);
   if (Lid >= m.wg_off[m.n_jobs]) return;
   const int j = find_job(m, Lid);
-  const StepArgs a = job_args(m, j);
+  const StepArgs a = job_record(m.jobs[j]);
+  const StepState st = job_state(m, a);
   const int local = Lid - m.wg_off[j];
   const int s = local / a.n_fine;
   if (RECT) {
-    fine_tile_rect<double>(a, lk, lq, ls, s, local % a.n_fine);
+    fine_tile_rect<double>(a, st, lk, lq, ls, s, local % a.n_fine);
   } else {
     load_kappa(a, s, lk);
-    fine_tile_compact<double>(a, lk, lq, s, local % a.n_fine);
+    fine_tile_compact<double>(a, st, lk, lq, s, local % a.n_fine);
   }
 }
 
