@@ -581,10 +581,8 @@ __global__ __launch_bounds__(kFineThreads) void k_adj_fine(AdjTileArgs a) {
     // the cell geometry is read again here rather than kept in registers
     // through both sweeps (the opaque copy of the level view stops the
     // compiler from reusing the first reads)
-    const double* hxp = L.hx;
-    const double* hyp = L.hy;
-    const double* ihxp = L.inv2hx;
-    const double* ihyp = L.inv2hy;
+    using gptr = const __attribute__((address_space(1))) double*;   // keeps global accesses
+    gptr hxp = (gptr)L.hx, hyp = (gptr)L.hy, ihxp = (gptr)L.inv2hx, ihyp = (gptr)L.inv2hy;
     asm volatile("" : "+s"(hxp), "+s"(hyp), "+s"(ihxp), "+s"(ihyp));
     const double gxE = hxp[gxc], gihE = ihxp[gxc];
     const double shN = sb[above];
