@@ -19,6 +19,7 @@ constexpr int kRectH = 4 * (kFineThreads / 64);     // rect mode: region rows (4
 constexpr int kBndRows = 2 * (kFineThreads / 64) + 2;   // rect mode: boundary rows + 2 zero rows
 constexpr int kBndSlots = kBndRows * 64;                 // rect mode: slots of one buffer
 constexpr int kLdsSlots = 2 * kBndSlots > kRegionCap + 1 ? 2 * kBndSlots : kRegionCap + 1;
+constexpr int kCompactSlots = 2 * (kRegionCap + 1);   // compact mode: two q buffers with a zero slot
 constexpr int kCoarseGroup = 32;                    // samples per group in the coarse launch order
 constexpr int kCoarseThreads = 256;                 // coarse workgroup: one item, 4 rows per wavefront
 constexpr int kMaxAdjP = 64;                        // largest p supported by the adjoint
@@ -34,7 +35,7 @@ struct TilingHost {
   int n_fine = 0, n_coarse = 0, wg_per_sample = 0;   // wg_per_sample: fine + coarse workgroups
   double halo_ratio = 1.0;          // region lanes / F+ nodes
   std::vector<int4> ent;            // compact mode: region entries (see lts_fused.hip)
-  std::vector<int2> tiles;          // compact mode: (offset, length)
+  std::vector<int4> tiles;          // compact mode: offset, length, interior columns, rows (packed)
   std::vector<int4> rtiles;         // rect mode: region rectangle and tile interior (packed)
   std::vector<int4> citems;         // coarse items: origin, column mask, row mask
 };

@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <type_traits>
 #include <vector>
@@ -43,7 +44,7 @@ namespace lts {
 struct StepArgs {
   LevelView L;
   const int4* __restrict__ ent;      // region entries of all fine tiles
-  const int2* __restrict__ tiles;    // compact mode: (offset, length) per fine tile
+  const int4* __restrict__ tiles;    // compact mode: offset, length, ix0 | ix1 << 16, iy0 | iy1 << 16
   const int4* __restrict__ rtiles;   // rect mode: packed region / interior per fine tile
   const int4* __restrict__ citems;   // per coarse item: origin, column mask, row mask
   int n_fine, n_coarse, wg_per_sample, per_xcd, active;
@@ -258,18 +259,29 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_multi(MultiArgs m) {
   coarse_body<double>(a, job_state(m, a), lk, s, item);
 }
 
+// Compact mode.  The region's nodes (the F+ nodes within Manhattan distance p
+// of the tile, ordered by that distance) are spread over the lanes, kNPT per
+// lane, with their neighbours' entry indices; q lives in LDS in two buffers
+// (substep m reads one and writes the other: one barrier per substep).  A node
+// at distance D can influence the tile only after D more substeps, so substep
+// m updates only the nodes within p - 1 - m: with the distance ordering those
+// form a prefix of the entries and the wavefronts past it skip the substep.
 template <class T>
 __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepState& st, const double* __restrict__ lk,
                                                   T* __restrict__ lq, int s, int tile) {
   const LevelView& L = a.L;
-  const int2 tl = a.tiles[tile];
+  const int4 tl = a.tiles[tile];
   const int len = tl.y;
+  const int ix0 = tl.z & 0xFFFF, ix1 = tl.z >> 16, iy0 = tl.w & 0xFFFF, iy1 = tl.w >> 16;
+  const int p = L.p;
   const T* __restrict__ u_g = reinterpret_cast<const T*>(st.Ucur) + (size_t)s * a.sstride;
   T* __restrict__ uo_g = reinterpret_cast<T*>(st.Uold) + (size_t)s * a.sstride;
   const double* __restrict__ cf = a.coef + (size_t)s * (L.p + 1);
+  T* const q0 = lq;                    // q of the even substeps' inputs
+  T* const q1 = lq + (kRegionCap + 1);  // and of the odd ones'; slot len of each holds 0
 
   T u[kNPT], d[kNPT], dp[kNPT], w[kNPT], aE[kNPT], aW[kNPT], aN[kNPT], aS[kNPT];
-  int ew[kNPT], ns[kNPT], kk[kNPT];
+  int ew[kNPT], ns[kNPT], kk[kNPT], dd[kNPT];
 #pragma unroll
   for (int r = 0; r < kNPT; ++r) {
     const int e = threadIdx.x + r * kFineThreads;
@@ -281,6 +293,7 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepS
     ew[r] = 0;
     ns[r] = 0;
     kk[r] = -1;
+    dd[r] = p;
     if (e < len) {
       const int4 en = a.ent[tl.x + e];
       const size_t k = (size_t)en.x;
@@ -288,56 +301,53 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepS
       kk[r] = en.x;
       ew[r] = en.y;
       ns[r] = en.z;
-      double cE, cW, cN, cS;
-      edge_coefs(L, lk, i, j, cE, cW, cN, cS);
-      const double im = L.invm[k];
-      aE[r] = (T)(im * cE);
-      aW[r] = (T)(im * cW);
-      aN[r] = (T)(im * cN);
-      aS[r] = (T)(im * cS);
+      dd[r] = max(max(ix0 - i, i - (ix1 - 1)), 0) + max(max(iy0 - j, j - (iy1 - 1)), 0);
       const bool pi = (en.y >> 15) & 1;
       const T uc = u_g[k];
       u[r] = uc;
-      // w = A_u (I - P) u_n
-      const T vi = pi ? (T)0 : uc;
-      const T vE = (L.flags[k + 1] & F_P) ? (T)0 : u_g[k + 1];
-      const T vW = (L.flags[k - 1] & F_P) ? (T)0 : u_g[k - 1];
-      const T vN = (L.flags[k + L.ld] & F_P) ? (T)0 : u_g[k + L.ld];
-      const T vS = (L.flags[k - L.ld] & F_P) ? (T)0 : u_g[k - L.ld];
-      w[r] = aE[r] * (vi - vE) + aW[r] * (vi - vW) + aN[r] * (vi - vN) + aS[r] * (vi - vS);
-      lq[e] = pi ? uc : (T)0;
+      q0[e] = pi ? uc : (T)0;
+      if (dd[r] < p) {                 // updated in some substep
+        double cE, cW, cN, cS;
+        edge_coefs(L, lk, i, j, cE, cW, cN, cS);
+        const double im = L.invm[k];
+        aE[r] = (T)(im * cE);
+        aW[r] = (T)(im * cW);
+        aN[r] = (T)(im * cN);
+        aS[r] = (T)(im * cS);
+        // w = A_u (I - P) u_n
+        const T vi = pi ? (T)0 : uc;
+        const T vE = (L.flags[k + 1] & F_P) ? (T)0 : u_g[k + 1];
+        const T vW = (L.flags[k - 1] & F_P) ? (T)0 : u_g[k - 1];
+        const T vN = (L.flags[k + L.ld] & F_P) ? (T)0 : u_g[k + L.ld];
+        const T vS = (L.flags[k - L.ld] & F_P) ? (T)0 : u_g[k - L.ld];
+        w[r] = aE[r] * (vi - vE) + aW[r] * (vi - vW) + aN[r] * (vi - vN) + aS[r] * (vi - vS);
+      }
     }
   }
-  if (threadIdx.x == 0) lq[len] = (T)0;   // slot read for absent / non-P neighbours
+  if (threadIdx.x == 0) q0[len] = q1[len] = (T)0;   // slot read for absent / non-P neighbours
   __syncthreads();
 
-  const int p = L.p;
   for (int m = 0; m < p; ++m) {
     const T c = (T)cf[1 + m];   // c1 for m = 0, c2_m otherwise
     const T b = m > 0 ? (T)L.beta[m] : (T)0;
+    const T* rq = (m & 1) ? q1 : q0;
+    T* wq = (m & 1) ? q0 : q1;
+    const int reach = p - 1 - m;
 #pragma unroll
     for (int r = 0; r < kNPT; ++r) {
-      if (kk[r] < 0) continue;
+      if (kk[r] < 0 || dd[r] > reach) continue;
       const bool pi = (ew[r] >> 15) & 1;
       const T qi = pi ? u[r] + d[r] : (T)0;
-      const T qE = lq[ew[r] & 0x7FFF], qW = lq[(ew[r] >> 16) & 0x7FFF];
-      const T qN = lq[ns[r] & 0x7FFF], qS = lq[(ns[r] >> 16) & 0x7FFF];
+      const T qE = rq[ew[r] & 0x7FFF], qW = rq[(ew[r] >> 16) & 0x7FFF];
+      const T qN = rq[ns[r] & 0x7FFF], qS = rq[(ns[r] >> 16) & 0x7FFF];
       const T apq = aE[r] * (qi - qE) + aW[r] * (qi - qW) + aN[r] * (qi - qN) + aS[r] * (qi - qS);
       const T rr = w[r] + apq;
       const T dn = (m == 0) ? -c * rr : ((T)1 + b) * d[r] - b * dp[r] - c * rr;
       dp[r] = d[r];
       d[r] = dn;
+      if (m + 1 < p) wq[threadIdx.x + r * kFineThreads] = pi ? u[r] + dn : (T)0;
     }
-    if (m + 1 < p) {
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < kNPT; ++r) {
-        if (kk[r] < 0) continue;
-        const int e = threadIdx.x + r * kFineThreads;
-        lq[e] = ((ew[r] >> 15) & 1) ? u[r] + d[r] : (T)0;
-      }
-      __syncthreads();
-    }
+    if (m + 1 < p) __syncthreads();
   }
 #pragma unroll
   for (int r = 0; r < kNPT; ++r) {
@@ -568,7 +578,7 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, const StepStat
 
 template <bool RECT, class T>
 __global__ __launch_bounds__(kFineThreads) void k_fine(StepArgs a) {
-  __shared__ T lq[kLdsSlots];
+  __shared__ T lq[RECT ? kLdsSlots : kCompactSlots];
   __shared__ T ls[RECT ? 4 * kFineThreads : 1];   // rect mode: final-update term per node
   __shared__ double lk[256];
   const int G = a.n_fine * a.active;
@@ -585,7 +595,7 @@ __global__ __launch_bounds__(kFineThreads) void k_fine(StepArgs a) {
 
 template <bool RECT>
 __global__ __launch_bounds__(kFineThreads) void k_fine_multi(MultiArgs m) {
-  __shared__ double lq[kLdsSlots];
+  __shared__ double lq[RECT ? kLdsSlots : kCompactSlots];
   __shared__ double ls[RECT ? 4 * kFineThreads : 1];
   __shared__ double lk[256];
   const int Lid = (int)(blockIdx.x & 7) * m.per_xcd + (int)(blockIdx.x >> 3);
@@ -667,12 +677,25 @@ std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int
         n_region += (size_t)rx * ry;
         continue;
       }
-      std::fill(loc.begin(), loc.end(), -1);
-      int len = 0;
+      // region: the F+ nodes at Manhattan distance <= p from the tile (an error
+      // made at the region border moves one node per substep, so farther nodes
+      // cannot reach the tile), ordered by that distance: the nodes a substep
+      // still needs are then a prefix, and whole wavefronts drop out
+      const int ix0 = std::max(tx, 0), ix1 = std::min(tx + TX, nxn);
+      const int iy0 = std::max(ty, 0), iy1 = std::min(ty + TY, nyn);
+      auto dist = [&](int i, int j) {
+        return std::max(std::max(ix0 - i, i - (ix1 - 1)), 0) + std::max(std::max(iy0 - j, j - (iy1 - 1)), 0);
+      };
+      std::vector<std::array<int, 3>> nodes;   // (distance, j, i), row-major within a distance
       for (int j = std::max(y0, 0); j < std::min(y0 + RY, nyn); ++j)
         for (int i = std::max(x0, 0); i < std::min(x0 + RX, nxn); ++i)
-          if (fl(i, j) & LTS_NODE_FPLUS) loc[(size_t)(j - y0) * RX + (i - x0)] = len++;
+          if ((fl(i, j) & LTS_NODE_FPLUS) && dist(i, j) <= p) nodes.push_back({dist(i, j), j, i});
+      std::stable_sort(nodes.begin(), nodes.end(),
+                       [](const std::array<int, 3>& a, const std::array<int, 3>& b) { return a[0] < b[0]; });
+      const int len = (int)nodes.size();
       if (len > kRegionCap) return "fine tile region exceeds the workgroup capacity";
+      std::fill(loc.begin(), loc.end(), -1);
+      for (int l = 0; l < len; ++l) loc[(size_t)(nodes[l][1] - y0) * RX + (nodes[l][2] - x0)] = l;
       const int off = (int)T.ent.size();
       auto nb = [&](int i, int j) -> int {
         if (i < x0 || j < y0 || i >= x0 + RX || j >= y0 + RY || i < 0 || j < 0 || i >= nxn || j >= nyn)
@@ -681,20 +704,19 @@ std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int
         if (l < 0 || !(fl(i, j) & LTS_NODE_P)) return len;
         return l;
       };
-      for (int j = std::max(y0, 0); j < std::min(y0 + RY, nyn); ++j)
-        for (int i = std::max(x0, 0); i < std::min(x0 + RX, nxn); ++i) {
-          if (!(fl(i, j) & LTS_NODE_FPLUS)) continue;
-          const bool interior = i >= tx && i < tx + TX && j >= ty && j < ty + TY;
-          const bool isP = fl(i, j) & LTS_NODE_P;
-          int4 e;
-          e.x = j * ld + i;
-          e.y = nb(i + 1, j) | (isP ? 0x8000 : 0) | (nb(i - 1, j) << 16) | (interior ? (int)0x80000000u : 0);
-          e.z = nb(i, j + 1) | (nb(i, j - 1) << 16);
-          e.w = i | (j << 16);
-          T.ent.push_back(e);
-          if (interior) ++n_fplus;
-        }
-      T.tiles.push_back(make_int2(off, len));
+      for (const auto& nd : nodes) {
+        const int j = nd[1], i = nd[2];
+        const bool interior = nd[0] == 0;
+        const bool isP = fl(i, j) & LTS_NODE_P;
+        int4 e;
+        e.x = j * ld + i;
+        e.y = nb(i + 1, j) | (isP ? 0x8000 : 0) | (nb(i - 1, j) << 16) | (interior ? (int)0x80000000u : 0);
+        e.z = nb(i, j + 1) | (nb(i, j - 1) << 16);
+        e.w = i | (j << 16);
+        T.ent.push_back(e);
+        if (interior) ++n_fplus;
+      }
+      T.tiles.push_back(make_int4(off, len, ix0 | ix1 << 16, iy0 | iy1 << 16));
       n_region += len;
     }
   // coarse items: 64 columns x kCoarseRows rows holding a DOF outside F+, with
@@ -730,13 +752,13 @@ lts_status upload_tiling(lts_ctx c, const TilingHost& T, TilingDev& D) {
   static uint64_t gen_counter = 0;
   D.gen = ++gen_counter;
   LTS_HIP(c, D.ent.ensure(std::max<size_t>(T.ent.size() * sizeof(int4), 16)));
-  LTS_HIP(c, D.tiles.ensure(std::max<size_t>(T.tiles.size() * sizeof(int2), 8)));
+  LTS_HIP(c, D.tiles.ensure(std::max<size_t>(T.tiles.size() * sizeof(int4), 16)));
   LTS_HIP(c, D.rtiles.ensure(std::max<size_t>(T.rtiles.size() * sizeof(int4), 16)));
   LTS_HIP(c, D.citems.ensure(std::max<size_t>(T.citems.size() * sizeof(int4), 16)));
   if (!T.ent.empty())
     LTS_HIP(c, hipMemcpy(D.ent.p, T.ent.data(), T.ent.size() * sizeof(int4), hipMemcpyHostToDevice));
   if (!T.tiles.empty())
-    LTS_HIP(c, hipMemcpy(D.tiles.p, T.tiles.data(), T.tiles.size() * sizeof(int2), hipMemcpyHostToDevice));
+    LTS_HIP(c, hipMemcpy(D.tiles.p, T.tiles.data(), T.tiles.size() * sizeof(int4), hipMemcpyHostToDevice));
   if (!T.rtiles.empty())
     LTS_HIP(c, hipMemcpy(D.rtiles.p, T.rtiles.data(), T.rtiles.size() * sizeof(int4), hipMemcpyHostToDevice));
   if (!T.citems.empty())
@@ -798,7 +820,7 @@ lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const 
   StepArgs a;
   a.L = lv.view();
   a.ent = T.ent.as<int4>();
-  a.tiles = T.tiles.as<int2>();
+  a.tiles = T.tiles.as<int4>();
   a.citems = T.citems.as<int4>();
   a.n_fine = T.n_fine;
   a.n_coarse = T.n_coarse;
@@ -879,7 +901,7 @@ void job_record(const DevLevel& lv, const TilingDev& T, const double* d_kappa, c
   StepArgs a{};
   a.L = lv.view();
   a.ent = T.ent.as<int4>();
-  a.tiles = T.tiles.as<int2>();
+  a.tiles = T.tiles.as<int4>();
   a.citems = T.citems.as<int4>();
   a.n_fine = T.n_fine;
   a.n_coarse = T.n_coarse;
