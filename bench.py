@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # to the average launch's 1.7105e9 algorithmic bytes.  Valid only for the
 # step-kernel sources the counters were taken with.
 TRAFFIC = {"bytes_per_launch": 1.380 * 1.7105e9,
-           "sources_sha256": "c43d8487f7e6684621249d8d85a71c36a8865677b1b86fb756e7412bc0b086a3"}
+           "sources_sha256": "de1830600556ca3887946e2dc6e0f2802e897312c7b2022d02fdfed4c9187ce5"}
 STEP_SOURCES = ("lts_fused.hip", "fused.h", "device.h", "lts_step.hip")
 WORKLOAD = ("unit square 512x512 base refined 8x in (0.48,0.52): 442225 DOFs, |P|=204081, p=8, "
             "nu=0.01, 256 samples, 4x4 blocks sigma=0.25, T=1, FP64")

@@ -159,6 +159,8 @@ lts_status upload_tiling(lts_ctx c, const TilingHost& T, TilingDev& D);
 
 // Tile-size candidates (TX, TY) tried for the fused step, in order.
 const std::vector<std::pair<int, int>>& tile_candidates();
+// The same for one level, led by one tile over the whole level.
+std::vector<std::pair<int, int>> level_tile_candidates(const HostLevel& H);
 
 // Grid origins tried for a tile size (0 and aligned to the F+ bounding box).
 std::vector<std::pair<int, int>> tile_origins(const HostLevel& H, int TX, int TY);

@@ -43,7 +43,7 @@ std::map<uint64_t, TuneChoice>& tune_cache() {
 
 // Time candidate tilings of `lv` on synthetic samples (unit coefficient,
 // centred pulse, CFL step) and keep the fastest.  Candidates: every tile size
-// of tile_candidates() with the grid origin at 0 and aligned to F+, rect mode
+// of level_tile_candidates() with the grid origin at 0 and aligned to F+, rect mode
 // where it fits, else compact mode; at most 12, ranked by region overhead.
 lts_status autotune_level(lts_ctx c, DevLevel& lv) {
   const uint64_t key = shape_key(lv.H);
@@ -61,7 +61,7 @@ lts_status autotune_level(lts_ctx c, DevLevel& lv) {
     }
   }
   for (int mode = 1; mode >= 0 && cands.empty(); --mode)
-    for (auto& tc : tile_candidates())
+    for (auto& tc : level_tile_candidates(lv.H))
       for (auto& org : tile_origins(lv.H, tc.first, tc.second)) {
         TilingHost T;
         if (build_tiling(lv.H, lv.ld, tc.first, tc.second, org.first, org.second, mode == 1, T).empty())

@@ -774,6 +774,14 @@ const std::vector<std::pair<int, int>>& tile_candidates() {
   return v;
 }
 
+std::vector<std::pair<int, int>> level_tile_candidates(const HostLevel& H) {
+  // first one tile over the whole level: where the level's F+ fits one
+  // workgroup it has no halo at all (compact mode; small levels with large p)
+  std::vector<std::pair<int, int>> v{{H.nxn, H.nyn}};
+  for (const auto& t : tile_candidates()) v.push_back(t);
+  return v;
+}
+
 std::vector<std::pair<int, int>> tile_origins(const HostLevel& H, int TX, int TY) {
   int fx = H.nxn, fy = H.nyn;
   for (int j = 0; j < H.nyn; ++j)
@@ -793,7 +801,7 @@ lts_status default_tiling(lts_ctx c, DevLevel& lv) {
   TilingHost best;
   bool have = false;
   for (int mode = 1; mode >= 0 && !have; --mode)
-    for (auto& tc : tile_candidates())
+    for (auto& tc : level_tile_candidates(lv.H))
       for (auto& org : tile_origins(lv.H, tc.first, tc.second)) {
         TilingHost T;
         if (!build_tiling(lv.H, lv.ld, tc.first, tc.second, org.first, org.second, mode == 1, T).empty())
