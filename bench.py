@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # to the average launch's 1.7105e9 algorithmic bytes.  Valid only for the
 # step-kernel sources the counters were taken with.
 TRAFFIC = {"bytes_per_launch": 1.380 * 1.7105e9,
-           "sources_sha256": "de1830600556ca3887946e2dc6e0f2802e897312c7b2022d02fdfed4c9187ce5"}
+           "sources_sha256": "866ff4bffe0da78062df9d084d7ca9d442e4d7c1422557b0b6bd8d571cc960d6"}
 STEP_SOURCES = ("lts_fused.hip", "fused.h", "device.h", "lts_step.hip")
 WORKLOAD = ("unit square 512x512 base refined 8x in (0.48,0.52): 442225 DOFs, |P|=204081, p=8, "
             "nu=0.01, 256 samples, 4x4 blocks sigma=0.25, T=1, FP64")
@@ -312,6 +312,31 @@ def copy_check(mib: int):
                       "bytes_written_per_copy": n * 8}), flush=True)
 
 
+def stream_check(mib: int = 2048, reps: int = 10):
+    """Achieved HBM rates of plain torch streaming kernels over `mib` MiB fp64
+    arrays: a copy (1 read, 1 write), c = a + 2b (2 reads, 1 write, the coarse
+    sweep's mix) and a sum (1 read).  The practical ceiling beside the 8 TB/s peak."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.ones_like(a)
+    c = torch.empty_like(a)
+    out = {"stream_check_mib": mib}
+    for name, f, nbytes in (("copy_1r1w", lambda: c.copy_(a), 16 * n),
+                            ("axpy_2r1w", lambda: torch.add(a, b, alpha=2.0, out=c), 24 * n),
+                            ("sum_1r", lambda: torch.sum(a), 8 * n)):
+        f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_GBps"] = round(nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -323,6 +348,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-stepping run")
     ap.add_argument("--copy-check", type=int, default=0, metavar="MIB",
                     help="only run 4 plain device copies of MIB MiB (calibrates HBM byte counters)")
+    ap.add_argument("--stream-check", action="store_true",
+                    help="only time plain torch copy / axpy / sum kernels (practical HBM rates)")
     ap.add_argument("--adjoint", action="store_true",
                     help="only time the discrete adjoint against the forward solve (K = 64)")
     ap.add_argument("--mlmc", action="store_true",
@@ -342,6 +369,9 @@ def main():
         return
     if args.copy_check:
         copy_check(args.copy_check)
+        return
+    if args.stream_check:
+        stream_check()
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the workload is one GPU's "

@@ -50,6 +50,7 @@ struct TilingDev {
   bool rect = false;
   int pitch = 0;
   double halo_ratio = 1.0;
+  double wg_work = 0.0;  // mean region nodes x substeps of one fine workgroup
   uint64_t gen = 0;     // distinct for every upload (keys captured graphs)
   DevBuf ent, tiles, rtiles, citems;
 };

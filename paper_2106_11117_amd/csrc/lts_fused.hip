@@ -68,11 +68,15 @@ struct StepState {
   int startup;
 };
 
-// Launch-time data of a batched launch over several jobs (levels).
+// Launch-time data of a batched launch over several jobs (levels).  Each
+// job's workgroups are split into 8 contiguous chunks, one per XCD, and every
+// XCD runs its chunks of the jobs in the order given by `order`.
 struct MultiArgs {
   const StepArgs* __restrict__ jobs;   // static per-job data (device table)
-  int n_jobs, per_xcd, step;
-  int wg_off[kMaxJobs + 1];            // prefix sums of the jobs' workgroup counts
+  int n_jobs, step;
+  int order[kMaxJobs];                 // job at launch position q
+  int wg_n[kMaxJobs];                  // workgroups of the job at position q
+  int chunk_off[kMaxJobs + 1];         // prefix sums over positions of ceil(wg_n / 8)
 };
 
 namespace {
@@ -207,11 +211,21 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse(StepArgs a) {
   coarse_body<T>(a, StepState{a.Ucur, a.Uold, a.startup}, lk, a.s0 + s, item);
 }
 
-// Job of a batched launch: the job whose workgroup range holds Lid.
-__device__ __forceinline__ int find_job(const MultiArgs& m, int Lid) {
-  int j = 0;
-  while (j + 1 < m.n_jobs && Lid >= m.wg_off[j + 1]) ++j;
-  return j;
+// Job and job-local workgroup index of this workgroup in a batched launch;
+// false for the workgroups past a job's count in its last chunk.  The hardware
+// hands workgroup b to XCD b mod 8, so XCD x runs, for each launch position in
+// turn, chunk x of that job: every XCD gets an equal share of every job (jobs
+// differ in cost per workgroup by a large factor), and neighbouring tiles of a
+// sample stay in one XCD's L2.
+__device__ __forceinline__ bool multi_slot(const MultiArgs& m, int& j, int& local, int& n) {
+  const int x = (int)(blockIdx.x & 7), k = (int)(blockIdx.x >> 3);
+  int q = 0;
+  while (q + 1 < m.n_jobs && k >= m.chunk_off[q + 1]) ++q;
+  const int per = m.chunk_off[q + 1] - m.chunk_off[q];
+  j = m.order[q];
+  n = m.wg_n[q];
+  local = x * per + (k - m.chunk_off[q]);
+  return k < m.chunk_off[m.n_jobs] && local < n;
 }
 
 // A pointer field of a job record loaded as a global-address-space pointer.
@@ -248,12 +262,10 @@ __device__ __forceinline__ StepState job_state(const MultiArgs& m, const StepArg
 
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_multi(MultiArgs m) {
   __shared__ double lk[256];
-  const int Lid = (int)(blockIdx.x & 7) * m.per_xcd + (int)(blockIdx.x >> 3);
-  if (Lid >= m.wg_off[m.n_jobs]) return;
-  const int j = find_job(m, Lid);
+  int j, local, n;
+  if (!multi_slot(m, j, local, n)) return;
   const StepArgs a = job_record(m.jobs[j]);
-  const int local = Lid - m.wg_off[j];
-  const int act = (m.wg_off[j + 1] - m.wg_off[j]) / a.n_coarse;   // active samples of the job
+  const int act = n / a.n_coarse;                      // active samples of the job
   int item, s;
   coarse_order(local, a.n_coarse, act, item, s);
   coarse_body<double>(a, job_state(m, a), lk, s, item);
@@ -598,12 +610,10 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_multi(MultiArgs m) {
   __shared__ double lq[RECT ? kLdsSlots : kCompactSlots];
   __shared__ double ls[RECT ? 4 * kFineThreads : 1];
   __shared__ double lk[256];
-  const int Lid = (int)(blockIdx.x & 7) * m.per_xcd + (int)(blockIdx.x >> 3);
-  if (Lid >= m.wg_off[m.n_jobs]) return;
-  const int j = find_job(m, Lid);
+  int j, local, n;
+  if (!multi_slot(m, j, local, n)) return;
   const StepArgs a = job_record(m.jobs[j]);
   const StepState st = job_state(m, a);
-  const int local = Lid - m.wg_off[j];
   const int s = local / a.n_fine;
   if (RECT) {
     fine_tile_rect<double>(a, st, lk, lq, ls, s, local % a.n_fine);
@@ -737,6 +747,7 @@ std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int
   T.n_coarse = (int)T.citems.size();
   T.wg_per_sample = T.n_fine + T.n_coarse;
   T.halo_ratio = n_fplus ? (double)n_region / n_fplus : 1.0;
+  T.wg_work = T.n_fine ? (double)n_region / T.n_fine * p : 0.0;
   return "";
 }
 
@@ -747,6 +758,7 @@ lts_status upload_tiling(lts_ctx c, const TilingHost& T, TilingDev& D) {
   D.n_coarse = T.n_coarse;
   D.wg_per_sample = T.wg_per_sample;
   D.halo_ratio = T.halo_ratio;
+  D.wg_work = T.wg_work;
   D.rect = T.rect;
   D.pitch = T.pitch;
   static uint64_t gen_counter = 0;
@@ -879,18 +891,23 @@ lts_status launch_multi_step(lts_ctx c, const StepArgs* d_jobs, const std::vecto
   m.n_jobs = nj;
   m.step = step;
   auto go = [&](int kind) {
-    m.wg_off[0] = 0;
-    for (int j = 0; j < nj; ++j) {
+    // fine launches: the jobs with the costliest workgroups first, so that
+    // the cheap ones fill in at the end
+    for (int j = 0; j < nj; ++j) m.order[j] = j;
+    if (kind > 0)
+      std::stable_sort(m.order, m.order + nj, [&](int x, int y) { return T[x]->wg_work > T[y]->wg_work; });
+    m.chunk_off[0] = 0;
+    for (int q = 0; q < nj; ++q) {
+      const int j = m.order[q];
       int w = 0;
       if (kind == 0) w = T[j]->n_coarse;
       else if (kind == 1) w = T[j]->rect ? T[j]->n_fine : 0;
       else w = T[j]->rect ? 0 : T[j]->n_fine;
-      m.wg_off[j + 1] = m.wg_off[j] + w * active[j];
+      m.wg_n[q] = w * active[j];
+      m.chunk_off[q + 1] = m.chunk_off[q] + (m.wg_n[q] + 7) / 8;
     }
-    const int G = m.wg_off[nj];
-    if (G == 0) return;
-    m.per_xcd = (G + 7) / 8;
-    const dim3 grid((unsigned)(8 * m.per_xcd));
+    if (m.chunk_off[nj] == 0) return;
+    const dim3 grid((unsigned)(8 * m.chunk_off[nj]));
     if (kind == 0)
       k_coarse_multi<<<grid, dim3(kCoarseThreads), 0, stream>>>(m);
     else if (kind == 1)
