@@ -141,7 +141,7 @@ typedef struct {
   int32_t p, n_blocks;
   double h, nu;
   double delta, omega;            /* stabilized Chebyshev constants (Sec. 3.3) */
-  int32_t tile_x, tile_y;         /* fine-tile shape in use (grid nodes) */
+  int32_t tile_x, tile_y;         /* fine-tile shape in use (grid nodes; 0, 0: adaptive) */
   int32_t tile_rect, tuned;       /* rectangular LDS region; chosen by the autotuner */
   double halo_ratio;              /* nodes of all fine-tile regions / |F+| */
   double tuned_ms;                /* measured step time per sample of the tuned tiling */
@@ -280,11 +280,14 @@ lts_status lts_autotune(lts_ctx ctx, int32_t level);
  * 64 x 64 nodes, one lane per column, state in registers) or
  * compact mode (rect = 0: the region's F+ nodes compacted with neighbour
  * indices), with the tile-grid origin chosen to minimise region overhead.
+ * tile_x = tile_y = 0 with rect = 0 selects the adaptive compact tiling: the
+ * F+ set is bisected recursively until each part's region fits a workgroup
+ * (long tiles along thin bands of F+).
  * Later solves use it and lts_batch_run does not re-tune the level (a later
  * lts_autotune does).  A tiling decides which workgroup updates a node, not
  * the arithmetic applied to it.  Errors: LTS_ERR_ARG (no such
- * level, sizes outside 1..4096, or the region does not fit the workgroup or
- * its LDS), LTS_ERR_HIP. */
+ * level, sizes outside 1..4096 other than the adaptive 0 x 0, or the region
+ * does not fit the workgroup or its LDS), LTS_ERR_HIP. */
 lts_status lts_set_tiling(lts_ctx ctx, int32_t level, int32_t tile_x, int32_t tile_y, int32_t rect);
 
 /* ------------------------------------------------------------------------ */

@@ -41,6 +41,8 @@ struct TilingHost {
   std::vector<int4> citems;         // coarse items: origin, column mask, row mask
 };
 
+// Tiling of a level: TX x TY tiles with grid origin (ox, oy), or with TX = TY
+// = 0 the adaptive compact tiling.
 std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int oy, bool rect,
                          TilingHost& T);
 

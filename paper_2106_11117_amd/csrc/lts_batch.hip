@@ -43,8 +43,9 @@ std::map<uint64_t, TuneChoice>& tune_cache() {
 
 // Time candidate tilings of `lv` on synthetic samples (unit coefficient,
 // centred pulse, CFL step) and keep the fastest.  Candidates: every tile size
-// of level_tile_candidates() with the grid origin at 0 and aligned to F+, rect mode
-// where it fits, else compact mode; at most 12, ranked by region overhead.
+// of level_tile_candidates() with the grid origin at 0 and aligned to F+, in
+// rect mode where it fits and in compact mode; the six best-ranked of each mode
+// by region overhead (12 in all).
 lts_status autotune_level(lts_ctx c, DevLevel& lv) {
   const uint64_t key = shape_key(lv.H);
   auto hit = tune_cache().find(key);
@@ -60,24 +61,38 @@ lts_status autotune_level(lts_ctx c, DevLevel& lv) {
       return LTS_OK;
     }
   }
-  for (int mode = 1; mode >= 0 && cands.empty(); --mode)
+  std::vector<TilingHost> by_mode[2];
+  for (int mode = 1; mode >= 0; --mode)
     for (auto& tc : level_tile_candidates(lv.H))
       for (auto& org : tile_origins(lv.H, tc.first, tc.second)) {
         TilingHost T;
         if (build_tiling(lv.H, lv.ld, tc.first, tc.second, org.first, org.second, mode == 1, T).empty())
-          cands.push_back(std::move(T));
+          by_mode[mode].push_back(std::move(T));
       }
+  // the best-ranked candidates of each mode, 12 in all
+  for (int mode = 1; mode >= 0; --mode) {
+    auto& v = by_mode[mode];
+    std::sort(v.begin(), v.end(), [](const TilingHost& a, const TilingHost& b) {
+      return a.halo_ratio * (1.0 + 0.01 * a.wg_per_sample) < b.halo_ratio * (1.0 + 0.01 * b.wg_per_sample);
+    });
+  }
+  for (int k = 0; k < 12; ++k) {
+    const int mode = k % 2 ? 0 : 1, idx = k / 2;
+    if (idx < (int)by_mode[mode].size()) cands.push_back(std::move(by_mode[mode][idx]));
+  }
+  for (int mode = 1; mode >= 0 && cands.size() < 12; --mode)
+    for (size_t idx = 6; idx < by_mode[mode].size() && cands.size() < 12; ++idx)
+      cands.push_back(std::move(by_mode[mode][idx]));
   if (cands.empty()) {
     c->err = "no fine-tile size fits the workgroup capacity for this level";
     return LTS_ERR_ARG;
   }
-  std::sort(cands.begin(), cands.end(), [](const TilingHost& a, const TilingHost& b) {
-    return a.halo_ratio * (1.0 + 0.01 * a.wg_per_sample) < b.halo_ratio * (1.0 + 0.01 * b.wg_per_sample);
-  });
-  if (cands.size() > 12) cands.resize(12);
-  // synthetic batch large enough to fill the device
-  const int wg = std::max(1, cands[0].wg_per_sample);
-  const int S = std::max(4, std::min(64, (4 * 256 + wg - 1) / wg));
+  // synthetic batch that fills the device with every candidate (at least 1024
+  // fine workgroups), within 1 GiB of states
+  int min_wg = 1 << 30;
+  for (const auto& T : cands) min_wg = std::min(min_wg, std::max(1, T.n_fine));
+  const int s_mem = (int)std::max<size_t>(4, (size_t(1) << 30) / (16 * std::max<size_t>(lv.nodes, 1)));
+  const int S = std::max(4, std::min({(1024 + min_wg - 1) / min_wg, s_mem, 4096}));
   const int nb = lv.H.n_blocks, p = lv.H.p;
   std::vector<double> kappa((size_t)S * nb, 1.0), x0((size_t)2 * S), coef((size_t)S * (p + 1));
   const double dt = 0.2 * lv.H.h;
@@ -151,7 +166,9 @@ extern "C" lts_status lts_set_tiling(lts_ctx c, int32_t level, int32_t tile_x, i
   if (!c) return LTS_ERR_ARG;
   c->err.clear();
   if (level < 0 || level >= (int32_t)c->levels.size()) return arg_fail(c, "no such level");
-  if (tile_x < 1 || tile_y < 1 || tile_x > 4096 || tile_y > 4096) return arg_fail(c, "tile size out of range");
+  const bool adaptive = tile_x == 0 && tile_y == 0 && rect == 0;
+  if (!adaptive && (tile_x < 1 || tile_y < 1 || tile_x > 4096 || tile_y > 4096))
+    return arg_fail(c, "tile size out of range");
   if (rect != 0 && rect != 1) return arg_fail(c, "rect must be 0 or 1");
   DevLevel& lv = *c->levels[level];
   TilingHost best;

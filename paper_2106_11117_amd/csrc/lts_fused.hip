@@ -32,7 +32,9 @@
 
 #include <algorithm>
 #include <array>
+#include <cmath>
 #include <cstring>
+#include <functional>
 #include <type_traits>
 #include <vector>
 
@@ -641,11 +643,179 @@ std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int
   auto fl = [&](int i, int j) -> uint8_t { return H.flags[(size_t)j * nxn + i]; };
   const int RX = TX + 2 * p, RY = TY + 2 * p;
   std::vector<int32_t> loc;
-  if (rect)
-    T.pitch = kRectW;
-  else
-    loc.resize((size_t)RX * RY);
+  if (rect) T.pitch = kRectW;
   size_t n_region = 0, n_fplus = 0;
+  // Compact mode, one tile with interior [ix0, ix1) x [iy0, iy1): its region
+  // is the F+ nodes at Manhattan distance <= p from the interior (an error made
+  // at the region border moves one node per substep, so farther nodes cannot
+  // reach the interior), ordered by that distance: the nodes a substep still
+  // needs are then a prefix, and whole wavefronts drop out.
+  auto dist_to = [](int i, int j, int ix0, int ix1, int iy0, int iy1) {
+    return std::max(std::max(ix0 - i, i - (ix1 - 1)), 0) + std::max(std::max(iy0 - j, j - (iy1 - 1)), 0);
+  };
+  auto add_compact = [&](int ix0, int ix1, int iy0, int iy1) -> std::string {
+    const int x0 = ix0 - p, y0 = iy0 - p, RX = ix1 - ix0 + 2 * p, RY = iy1 - iy0 + 2 * p;
+    std::vector<std::array<int, 3>> nodes;   // (distance, j, i), row-major within a distance
+    for (int j = std::max(y0, 0); j < std::min(y0 + RY, nyn); ++j)
+      for (int i = std::max(x0, 0); i < std::min(x0 + RX, nxn); ++i) {
+        const int d = dist_to(i, j, ix0, ix1, iy0, iy1);
+        if ((fl(i, j) & LTS_NODE_FPLUS) && d <= p) nodes.push_back({d, j, i});
+      }
+    std::stable_sort(nodes.begin(), nodes.end(),
+                     [](const std::array<int, 3>& a, const std::array<int, 3>& b) { return a[0] < b[0]; });
+    const int len = (int)nodes.size();
+    if (len > kRegionCap) return "fine tile region exceeds the workgroup capacity";
+    loc.assign((size_t)RX * RY, -1);
+    for (int l = 0; l < len; ++l) loc[(size_t)(nodes[l][1] - y0) * RX + (nodes[l][2] - x0)] = l;
+    const int off = (int)T.ent.size();
+    auto nb = [&](int i, int j) -> int {
+      if (i < x0 || j < y0 || i >= x0 + RX || j >= y0 + RY || i < 0 || j < 0 || i >= nxn || j >= nyn)
+        return len;
+      const int l = loc[(size_t)(j - y0) * RX + (i - x0)];
+      if (l < 0 || !(fl(i, j) & LTS_NODE_P)) return len;
+      return l;
+    };
+    for (const auto& nd : nodes) {
+      const int j = nd[1], i = nd[2];
+      const bool interior = nd[0] == 0;
+      const bool isP = fl(i, j) & LTS_NODE_P;
+      int4 e;
+      e.x = j * ld + i;
+      e.y = nb(i + 1, j) | (isP ? 0x8000 : 0) | (nb(i - 1, j) << 16) | (interior ? (int)0x80000000u : 0);
+      e.z = nb(i, j + 1) | (nb(i, j - 1) << 16);
+      e.w = i | (j << 16);
+      T.ent.push_back(e);
+      if (interior) ++n_fplus;
+    }
+    T.tiles.push_back(make_int4(off, len, ix0 | ix1 << 16, iy0 | iy1 << 16));
+    n_region += len;
+    return "";
+  };
+  // Adaptive tiling (compact mode, TX = TY = 0): the grid is bisected
+  // recursively, each box shrunk to the bounding box of its F+ nodes, until the
+  // region of a box fits one workgroup.  A cut is chosen among 16 positions per
+  // axis (F+ quantiles and even spacing) by the total region of the tiles that
+  // plain median bisection would then make of the two halves; this keeps the
+  // cuts across thin bands of F+, whose tiles end up long along the band.
+  // Region sizes come from per-row prefix counts of F+ (O(rows) per box).
+  const bool adaptive = TX == 0 && TY == 0;
+  std::vector<int> rpre, cpre;                                   // F+ prefix counts per row / column
+  auto rcount = [&](int j, int a, int b) { return rpre[(size_t)j * (nxn + 1) + b] - rpre[(size_t)j * (nxn + 1) + a]; };
+  auto ccount = [&](int i, int a, int b) { return cpre[(size_t)i * (nyn + 1) + b] - cpre[(size_t)i * (nyn + 1) + a]; };
+  if (adaptive) {
+    rpre.assign((size_t)nyn * (nxn + 1), 0);
+    cpre.assign((size_t)nxn * (nyn + 1), 0);
+    for (int j = 0; j < nyn; ++j)
+      for (int i = 0; i < nxn; ++i) {
+        const int f = (fl(i, j) & LTS_NODE_FPLUS) ? 1 : 0;
+        rpre[(size_t)j * (nxn + 1) + i + 1] = rpre[(size_t)j * (nxn + 1) + i] + f;
+        cpre[(size_t)i * (nyn + 1) + j + 1] = cpre[(size_t)i * (nyn + 1) + j] + f;
+      }
+  }
+  struct Box { int x0, x1, y0, y1; };
+  auto shrink = [&](Box b, Box& out) {                           // F+ bounding box inside b
+    int y0 = b.y0, y1 = b.y1, x0 = b.x0, x1 = b.x1;
+    while (y0 < y1 && rcount(y0, b.x0, b.x1) == 0) ++y0;
+    while (y1 > y0 && rcount(y1 - 1, b.x0, b.x1) == 0) --y1;
+    if (y0 >= y1) return false;
+    while (x0 < x1 && ccount(x0, y0, y1) == 0) ++x0;
+    while (x1 > x0 && ccount(x1 - 1, y0, y1) == 0) --x1;
+    out = Box{x0, x1, y0, y1};
+    return true;
+  };
+  auto fast_region = [&](const Box& b) {                         // F+ within Manhattan distance p
+    size_t n = 0;
+    for (int j = std::max(b.y0 - p, 0); j < std::min(b.y1 + p, nyn); ++j) {
+      const int dy = std::max(std::max(b.y0 - j, j - (b.y1 - 1)), 0);
+      n += rcount(j, std::max(b.x0 - (p - dy), 0), std::min(b.x1 + (p - dy), nxn));
+    }
+    return n;
+  };
+  constexpr size_t kNoFit = size_t(1) << 40;
+  auto halves = [](const Box& b, int axis, int c, Box& A, Box& B) {
+    A = b;
+    B = b;
+    if (axis == 0) A.x1 = B.x0 = c;
+    else A.y1 = B.y0 = c;
+  };
+  auto line_counts = [&](const Box& b, int axis) {               // F+ per column (axis 0) or row
+    std::vector<int> v;
+    if (axis == 0)
+      for (int i = b.x0; i < b.x1; ++i) v.push_back(ccount(i, b.y0, b.y1));
+    else
+      for (int j = b.y0; j < b.y1; ++j) v.push_back(rcount(j, b.x0, b.x1));
+    return v;
+  };
+  auto quantile_cut = [](const std::vector<int>& cnt, int lo, double f) {   // in [lo + 1, lo + n - 1]
+    const int n = (int)cnt.size();
+    long long tot = 0;
+    for (int v : cnt) tot += v;
+    long long acc = cnt[0];
+    int c = lo + 1;                                              // halves [lo, c) and [c, lo + n)
+    while (c < lo + n - 1 && (double)acc < f * (double)tot) acc += cnt[++c - lo - 1];
+    return c;
+  };
+  // total region of the tiles that median bisection makes of box b
+  std::function<size_t(const Box&)> median_total = [&](const Box& b0) -> size_t {
+    Box b;
+    if (!shrink(b0, b)) return 0;
+    const size_t r = fast_region(b);
+    if (r <= (size_t)kRegionCap) return r;
+    size_t best = kNoFit;
+    Box bA{}, bB{};
+    for (int axis = 0; axis < 2; ++axis) {
+      const int lo = axis == 0 ? b.x0 : b.y0, hi = axis == 0 ? b.x1 : b.y1;
+      if (hi - lo < 2) continue;
+      Box A, B, sA, sB;
+      halves(b, axis, quantile_cut(line_counts(b, axis), lo, 0.5), A, B);
+      const size_t cost = (shrink(A, sA) ? fast_region(sA) : 0) + (shrink(B, sB) ? fast_region(sB) : 0);
+      if (cost < best) {
+        best = cost;
+        bA = A;
+        bB = B;
+      }
+    }
+    if (best == kNoFit) return kNoFit;
+    const size_t ta = median_total(bA), tb = median_total(bB);
+    return ta >= kNoFit || tb >= kNoFit ? kNoFit : ta + tb;
+  };
+  std::function<std::string(const Box&)> bisect = [&](const Box& b0) -> std::string {
+    Box b;
+    if (!shrink(b0, b)) return "";
+    if (fast_region(b) <= (size_t)kRegionCap) return add_compact(b.x0, b.x1, b.y0, b.y1);
+    size_t best = kNoFit;
+    Box bA{}, bB{};
+    for (int axis = 0; axis < 2; ++axis) {
+      const int lo = axis == 0 ? b.x0 : b.y0, hi = axis == 0 ? b.x1 : b.y1;
+      if (hi - lo < 2) continue;
+      const std::vector<int> cnt = line_counts(b, axis);
+      std::vector<int> cuts;
+      for (int k = 1; k <= 8; ++k) {
+        cuts.push_back(quantile_cut(cnt, lo, k / 9.0));
+        cuts.push_back(std::min(std::max(lo + (hi - lo) * k / 9, lo + 1), hi - 1));
+      }
+      std::sort(cuts.begin(), cuts.end());
+      cuts.erase(std::unique(cuts.begin(), cuts.end()), cuts.end());
+      for (int c : cuts) {
+        Box A, B;
+        halves(b, axis, c, A, B);
+        const size_t ta = median_total(A), tb = median_total(B);
+        const size_t cost = ta >= kNoFit || tb >= kNoFit ? kNoFit : ta + tb;
+        if (cost < best) {
+          best = cost;
+          bA = A;
+          bB = B;
+        }
+      }
+    }
+    if (best == kNoFit) return "fine tile region exceeds the workgroup capacity";
+    std::string e = bisect(bA);
+    if (!e.empty()) return e;
+    return bisect(bB);
+  };
+  if (adaptive && rect) return "the adaptive tiling is compact mode only";
+  if (!adaptive && (TX < 1 || TY < 1)) return "tile size out of range";
+  if (!adaptive)
   for (int ty = oy - ((oy + TY - 1) / TY) * TY; ty < nyn; ty += TY)
     for (int tx = ox - ((ox + TX - 1) / TX) * TX; tx < nxn; tx += TX) {
       bool any = false;
@@ -687,48 +857,14 @@ std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int
         n_region += (size_t)rx * ry;
         continue;
       }
-      // region: the F+ nodes at Manhattan distance <= p from the tile (an error
-      // made at the region border moves one node per substep, so farther nodes
-      // cannot reach the tile), ordered by that distance: the nodes a substep
-      // still needs are then a prefix, and whole wavefronts drop out
-      const int ix0 = std::max(tx, 0), ix1 = std::min(tx + TX, nxn);
-      const int iy0 = std::max(ty, 0), iy1 = std::min(ty + TY, nyn);
-      auto dist = [&](int i, int j) {
-        return std::max(std::max(ix0 - i, i - (ix1 - 1)), 0) + std::max(std::max(iy0 - j, j - (iy1 - 1)), 0);
-      };
-      std::vector<std::array<int, 3>> nodes;   // (distance, j, i), row-major within a distance
-      for (int j = std::max(y0, 0); j < std::min(y0 + RY, nyn); ++j)
-        for (int i = std::max(x0, 0); i < std::min(x0 + RX, nxn); ++i)
-          if ((fl(i, j) & LTS_NODE_FPLUS) && dist(i, j) <= p) nodes.push_back({dist(i, j), j, i});
-      std::stable_sort(nodes.begin(), nodes.end(),
-                       [](const std::array<int, 3>& a, const std::array<int, 3>& b) { return a[0] < b[0]; });
-      const int len = (int)nodes.size();
-      if (len > kRegionCap) return "fine tile region exceeds the workgroup capacity";
-      std::fill(loc.begin(), loc.end(), -1);
-      for (int l = 0; l < len; ++l) loc[(size_t)(nodes[l][1] - y0) * RX + (nodes[l][2] - x0)] = l;
-      const int off = (int)T.ent.size();
-      auto nb = [&](int i, int j) -> int {
-        if (i < x0 || j < y0 || i >= x0 + RX || j >= y0 + RY || i < 0 || j < 0 || i >= nxn || j >= nyn)
-          return len;
-        const int l = loc[(size_t)(j - y0) * RX + (i - x0)];
-        if (l < 0 || !(fl(i, j) & LTS_NODE_P)) return len;
-        return l;
-      };
-      for (const auto& nd : nodes) {
-        const int j = nd[1], i = nd[2];
-        const bool interior = nd[0] == 0;
-        const bool isP = fl(i, j) & LTS_NODE_P;
-        int4 e;
-        e.x = j * ld + i;
-        e.y = nb(i + 1, j) | (isP ? 0x8000 : 0) | (nb(i - 1, j) << 16) | (interior ? (int)0x80000000u : 0);
-        e.z = nb(i, j + 1) | (nb(i, j - 1) << 16);
-        e.w = i | (j << 16);
-        T.ent.push_back(e);
-        if (interior) ++n_fplus;
-      }
-      T.tiles.push_back(make_int4(off, len, ix0 | ix1 << 16, iy0 | iy1 << 16));
-      n_region += len;
+      const std::string e = add_compact(std::max(tx, 0), std::min(tx + TX, nxn), std::max(ty, 0),
+                                        std::min(ty + TY, nyn));
+      if (!e.empty()) return e;
     }
+  if (adaptive) {
+    const std::string e = bisect(Box{0, nxn, 0, nyn});
+    if (!e.empty()) return e;
+  }
   // coarse items: 64 columns x kCoarseRows rows holding a DOF outside F+, with
   // the masks of such columns and rows
   for (int ty = 0; ty < nyn; ty += kCoarseRows)
@@ -788,13 +924,15 @@ const std::vector<std::pair<int, int>>& tile_candidates() {
 
 std::vector<std::pair<int, int>> level_tile_candidates(const HostLevel& H) {
   // first one tile over the whole level: where the level's F+ fits one
-  // workgroup it has no halo at all (compact mode; small levels with large p)
-  std::vector<std::pair<int, int>> v{{H.nxn, H.nyn}};
+  // workgroup it has no halo at all (compact mode; small levels with large p);
+  // then the adaptive tiling (0, 0: compact mode only)
+  std::vector<std::pair<int, int>> v{{H.nxn, H.nyn}, {0, 0}};
   for (const auto& t : tile_candidates()) v.push_back(t);
   return v;
 }
 
 std::vector<std::pair<int, int>> tile_origins(const HostLevel& H, int TX, int TY) {
+  if (TX < 1 || TY < 1) return {{0, 0}};              // adaptive tiling: no grid origin
   int fx = H.nxn, fy = H.nyn;
   for (int j = 0; j < H.nyn; ++j)
     for (int i = 0; i < H.nxn; ++i)
@@ -893,12 +1031,14 @@ lts_status launch_multi_step(lts_ctx c, const StepArgs* d_jobs, const std::vecto
   auto go = [&](int kind) {
     // fine launches: the jobs with the costliest workgroups first, so that
     // the cheap ones fill in at the end
-    for (int j = 0; j < nj; ++j) m.order[j] = j;
+    int pos[kMaxJobs];                                 // job at launch position q
+    for (int j = 0; j < nj; ++j) pos[j] = j;
     if (kind > 0)
-      std::stable_sort(m.order, m.order + nj, [&](int x, int y) { return T[x]->wg_work > T[y]->wg_work; });
+      std::stable_sort(pos, pos + nj, [&](int x, int y) { return T[x]->wg_work > T[y]->wg_work; });
     m.chunk_off[0] = 0;
     for (int q = 0; q < nj; ++q) {
-      const int j = m.order[q];
+      const int j = pos[q];
+      m.order[q] = j;
       int w = 0;
       if (kind == 0) w = T[j]->n_coarse;
       else if (kind == 1) w = T[j]->rect ? T[j]->n_fine : 0;

@@ -282,3 +282,33 @@ def test_fine_tile_modes_and_shapes(ctx, graded):
     for rect in (True, False):
         with pytest.raises(P.LtsError):
             ctx.set_tiling(big, 200, 200, rect)
+
+
+@pytest.mark.parametrize("graded", [False, True])
+def test_adaptive_tiling(ctx, graded):
+    """The adaptive compact tiling (recursive bisection of F+): same QoIs, bit
+    for bit, as a uniform compact tiling (a tiling only decides which workgroup
+    updates a node), oracle parity, and rect mode refused."""
+    lid, lv, s = _fp32_case(ctx, graded)
+    ops = fem.operators(lv)
+    ctx.set_tiling(lid, *((16, 16) if graded else (48, 48)), False)
+    qu = ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"])
+    info = ctx.set_tiling(lid, 0, 0, False)
+    assert (info["tile_x"], info["tile_y"], info["tile_rect"]) == (0, 0, 0)
+    qa = ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"])
+    assert np.array_equal(qa, qu)
+    for k in range(len(qa)):
+        qo, sc = oracle_solve(ops, lv, s["kappa"][k], s["x0"][k], int(s["n_steps"][k]), s["dt"][k])
+        check(qa[k], qo, sc)
+    with pytest.raises(P.LtsError):
+        ctx.set_tiling(lid, 0, 0, True)
+
+
+def test_adaptive_tiling_halo(ctx):
+    """On a graded L-shape level (F+ a cross of thin bands, p = 64) the adaptive
+    tiling needs far fewer region nodes than square tiles."""
+    lid = ctx.add_rect_level(P.graded_L_rule(256))
+    square = ctx.set_tiling(lid, 40, 40, False)["halo_ratio"]
+    adaptive = ctx.set_tiling(lid, 0, 0, False)["halo_ratio"]
+    print(f"halo ratio: 40 x 40 tiles {square:.3f}, adaptive {adaptive:.3f}")
+    assert adaptive < 0.6 * square
