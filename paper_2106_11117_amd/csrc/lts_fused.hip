@@ -275,11 +275,15 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_multi(MultiArgs m) {
 
 // Compact mode.  The region's nodes (the F+ nodes within Manhattan distance p
 // of the tile, ordered by that distance) are spread over the lanes, kNPT per
-// lane, with their neighbours' entry indices; q lives in LDS in two buffers
-// (substep m reads one and writes the other: one barrier per substep).  A node
-// at distance D can influence the tile only after D more substeps, so substep
-// m updates only the nodes within p - 1 - m: with the distance ordering those
-// form a prefix of the entries and the wavefronts past it skip the substep.
+// lane; q lives in LDS in two buffers (substep m reads one and writes the
+// other: one barrier per substep).  A node at distance D can influence the tile
+// only after D more substeps, so substep m updates only the nodes within
+// p - 1 - m: with the distance ordering those form a prefix of the entries and
+// the wavefronts past it skip the substep.  An entry is x = grid index | P flag
+// << 31, y = E | W << 16, z = N | S << 16 (neighbour slots; slot len holds 0
+// for an absent or non-P neighbour), w = i | j << 16.  Each lane turns its
+// neighbour slots into LDS byte addresses once; the substeps run in pairs so
+// that the two buffers and the roles of the increment registers are fixed.
 template <class T>
 __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepState& st, const double* __restrict__ lk,
                                                   T* __restrict__ lq, int s, int tile) {
@@ -294,31 +298,33 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepS
   T* const q0 = lq;                    // q of the even substeps' inputs
   T* const q1 = lq + (kRegionCap + 1);  // and of the odd ones'; slot len of each holds 0
 
-  T u[kNPT], d[kNPT], dp[kNPT], w[kNPT], aE[kNPT], aW[kNPT], aN[kNPT], aS[kNPT];
-  int ew[kNPT], ns[kNPT], kk[kNPT], dd[kNPT];
+  T u[kNPT], pm[kNPT], d0[kNPT], d1[kNPT], w[kNPT], aE[kNPT], aW[kNPT], aN[kNPT], aS[kNPT];
+  uint32_t ad[kNPT][4];                // LDS byte offsets of the E, W, N, S neighbours
+  int kk[kNPT], dd[kNPT];
 #pragma unroll
   for (int r = 0; r < kNPT; ++r) {
     const int e = threadIdx.x + r * kFineThreads;
-    d[r] = (T)0;
-    dp[r] = (T)0;
-    u[r] = (T)0;
-    w[r] = (T)0;
+    d0[r] = d1[r] = (T)0;
+    u[r] = pm[r] = w[r] = (T)0;
     aE[r] = aW[r] = aN[r] = aS[r] = (T)0;
-    ew[r] = 0;
-    ns[r] = 0;
-    kk[r] = -1;
-    dd[r] = p;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) ad[r][t] = (uint32_t)(len * sizeof(T));
+    kk[r] = 0;
+    dd[r] = p;                         // never updated, never written
     if (e < len) {
       const int4 en = a.ent[tl.x + e];
-      const size_t k = (size_t)en.x;
+      const size_t k = (size_t)(en.x & 0x7FFFFFFF);
+      const bool pi = en.x < 0;
       const int i = en.w & 0xFFFF, j = en.w >> 16;
-      kk[r] = en.x;
-      ew[r] = en.y;
-      ns[r] = en.z;
+      kk[r] = (int)k;
+      ad[r][0] = (uint32_t)(en.y & 0xFFFF) * sizeof(T);
+      ad[r][1] = ((uint32_t)en.y >> 16) * sizeof(T);
+      ad[r][2] = (uint32_t)(en.z & 0xFFFF) * sizeof(T);
+      ad[r][3] = ((uint32_t)en.z >> 16) * sizeof(T);
       dd[r] = max(max(ix0 - i, i - (ix1 - 1)), 0) + max(max(iy0 - j, j - (iy1 - 1)), 0);
-      const bool pi = (en.y >> 15) & 1;
       const T uc = u_g[k];
       u[r] = uc;
+      pm[r] = pi ? (T)1 : (T)0;
       q0[e] = pi ? uc : (T)0;
       if (dd[r] < p) {                 // updated in some substep
         double cE, cW, cN, cS;
@@ -341,33 +347,47 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepS
   if (threadIdx.x == 0) q0[len] = q1[len] = (T)0;   // slot read for absent / non-P neighbours
   __syncthreads();
 
-  for (int m = 0; m < p; ++m) {
-    const T c = (T)cf[1 + m];   // c1 for m = 0, c2_m otherwise
+  // Substep m: d_m+1 = (1 + beta_m) d_m - beta_m d_m-1 - c_m (w + A_u q_m) with
+  // d_0 = d_-1 = 0 and beta_0 = 0 (so m = 0 gives -c_0 (w + A_u q_0)), and
+  // q_m+1 = P (u_n + d_m+1).  At even m, d0 holds d_m and d1 d_m-1 (overwritten
+  // by d_m+1); at odd m the roles swap.
+  auto substep = [&](int m, auto Bc) {
+    constexpr int B = decltype(Bc)::value;
+    T* dc = B == 0 ? d0 : d1;          // d_m
+    T* dq = B == 0 ? d1 : d0;          // d_m-1 in, d_m+1 out
+    const T c = (T)cf[1 + m];          // c1 for m = 0, c2_m otherwise
     const T b = m > 0 ? (T)L.beta[m] : (T)0;
-    const T* rq = (m & 1) ? q1 : q0;
-    T* wq = (m & 1) ? q0 : q1;
+    const char* rq = reinterpret_cast<const char*>(B == 0 ? q0 : q1);
+    T* wq = B == 0 ? q1 : q0;
     const int reach = p - 1 - m;
 #pragma unroll
     for (int r = 0; r < kNPT; ++r) {
-      if (kk[r] < 0 || dd[r] > reach) continue;
-      const bool pi = (ew[r] >> 15) & 1;
-      const T qi = pi ? u[r] + d[r] : (T)0;
-      const T qE = rq[ew[r] & 0x7FFF], qW = rq[(ew[r] >> 16) & 0x7FFF];
-      const T qN = rq[ns[r] & 0x7FFF], qS = rq[(ns[r] >> 16) & 0x7FFF];
+      if (dd[r] > reach) continue;
+      const T qi = pm[r] * (u[r] + dc[r]);
+      const T qE = *reinterpret_cast<const T*>(rq + ad[r][0]);
+      const T qW = *reinterpret_cast<const T*>(rq + ad[r][1]);
+      const T qN = *reinterpret_cast<const T*>(rq + ad[r][2]);
+      const T qS = *reinterpret_cast<const T*>(rq + ad[r][3]);
       const T apq = aE[r] * (qi - qE) + aW[r] * (qi - qW) + aN[r] * (qi - qN) + aS[r] * (qi - qS);
       const T rr = w[r] + apq;
-      const T dn = (m == 0) ? -c * rr : ((T)1 + b) * d[r] - b * dp[r] - c * rr;
-      dp[r] = d[r];
-      d[r] = dn;
-      if (m + 1 < p) wq[threadIdx.x + r * kFineThreads] = pi ? u[r] + dn : (T)0;
+      const T dn = ((T)1 + b) * dc[r] - b * dq[r] - c * rr;
+      dq[r] = dn;
+      if (m + 1 < p) wq[threadIdx.x + r * kFineThreads] = pm[r] * (u[r] + dn);
     }
     if (m + 1 < p) __syncthreads();
+  };
+  int m = 0;
+  for (; m + 1 < p; m += 2) {
+    substep(m, std::integral_constant<int, 0>{});
+    substep(m + 1, std::integral_constant<int, 1>{});
   }
+  if (m < p) substep(m, std::integral_constant<int, 0>{});
+  const T* dfin = (p & 1) ? d1 : d0;   // d_p
 #pragma unroll
   for (int r = 0; r < kNPT; ++r) {
-    if (kk[r] < 0 || !((unsigned)ew[r] >> 31)) continue;
+    if (dd[r] != 0) continue;          // written back by the tile that owns the node
     const size_t k = (size_t)kk[r];
-    uo_g[k] = st.startup ? (u[r] + d[r]) : ((T)2 * u[r] - uo_g[k] + (T)2 * d[r]);
+    uo_g[k] = st.startup ? (u[r] + dfin[r]) : ((T)2 * u[r] - uo_g[k] + (T)2 * dfin[r]);
   }
 }
 
@@ -680,8 +700,8 @@ std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int
       const bool interior = nd[0] == 0;
       const bool isP = fl(i, j) & LTS_NODE_P;
       int4 e;
-      e.x = j * ld + i;
-      e.y = nb(i + 1, j) | (isP ? 0x8000 : 0) | (nb(i - 1, j) << 16) | (interior ? (int)0x80000000u : 0);
+      e.x = (j * ld + i) | (isP ? (int)0x80000000u : 0);
+      e.y = nb(i + 1, j) | (nb(i - 1, j) << 16);
       e.z = nb(i, j + 1) | (nb(i, j - 1) << 16);
       e.w = i | (j << 16);
       T.ent.push_back(e);
