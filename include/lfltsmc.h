@@ -166,6 +166,27 @@ lts_status lts_level_arrays(lts_ctx ctx, int32_t level, double* x, double* y, ui
 lts_status lts_rect_level_host(const lts_rect_rule* rule, lts_level_info* info, double* x, double* y,
                                uint8_t* node_flags, double* mass, double* qoi_w, int32_t* cell_block);
 
+typedef struct {
+  int32_t n_fine, n_coarse;       /* fine-tile and coarse-item workgroups per sample */
+  int32_t tile_x, tile_y, tile_rect;
+  int32_t max_region;             /* nodes (rect mode: lanes) of the largest fine-tile region */
+  int32_t regions_exact;          /* 1: every region holds all F+ nodes within Manhattan
+                                     distance p of its tile (compact mode: exactly those) */
+  double halo_ratio;              /* nodes of all fine-tile regions / |F+| */
+} lts_tiling_info;
+
+/* Host only (no device): the fine-tile tiling that lts_set_tiling(level,
+ * tile_x, tile_y, rect) picks for the level lts_build_rect_level builds from
+ * `rule` (tile_x = tile_y = 0, rect = 0: the adaptive tiling), and which tile
+ * writes each node back.  A node at distance d from a tile reaches it after d
+ * substeps, so a region must hold the F+ nodes within distance p of its tile
+ * (Algorithm 2 runs p substeps on F+ only).  info is required; owner may be
+ * NULL or hold [ny_nodes*nx_nodes]: the index of the fine tile that writes the
+ * node back, -1 where no tile does, -2 where more than one would.  Errors:
+ * LTS_ERR_ARG (bad rule, sizes, or a tiling that does not fit). */
+lts_status lts_tiling_host(const lts_rect_rule* rule, int32_t tile_x, int32_t tile_y, int32_t rect,
+                           lts_tiling_info* info, int32_t* owner);
+
 /* Stabilized Chebyshev constants of Sec. 3.3 for (p, nu): delta = 1 + nu/p^2,
  * omega = 2 T_p'(delta)/T_p(delta); beta[k] = T_{k-1}(delta)/T_{k+1}(delta) and
  * beta_half[k] = T_k(delta)/T_{k+1}(delta) for k = 1..p-1 (arrays of length p,

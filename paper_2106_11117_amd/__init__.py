@@ -16,7 +16,7 @@ from ._lib import (LTS_BATCH_GRAPH, LTS_FP32_STEP, LTS_FP64, LTS_MLMC_BATCHED, L
                    LTS_NODE_DOF, LTS_NODE_FPLUS, LTS_NODE_P, LTS_PTR_DEVICE, LTS_PTR_HOST,
                    LTS_RULE_BOX, LTS_RULE_GRADED_L, LtsError)
 
-__all__ = ["Context", "gen_samples", "philox", "rect_level_host", "cheb_constants", "sample_rule", "box_rule", "graded_L_rule", "LtsError",
+__all__ = ["Context", "gen_samples", "philox", "rect_level_host", "tiling_host", "cheb_constants", "sample_rule", "box_rule", "graded_L_rule", "LtsError",
            "LTS_FP64", "LTS_FP32_STEP", "LTS_BATCH_GRAPH", "LTS_MLMC_BATCHED", "LTS_MLMC_PLAIN",
            "LTS_NODE_DOF", "LTS_NODE_P", "LTS_NODE_FPLUS", "LtsQoI"]
 
@@ -96,6 +96,21 @@ def rect_level_host(rule) -> dict:
                                    _ip(cb)))
     d = {k: getattr(info, k) for k, _ in _lib.LevelInfo._fields_}
     d.update({"x": x, "y": y, "flags": flags, "mass": mass, "qoi_w": qw, "cell_block": cb})
+    return d
+
+
+def tiling_host(rule, tile_x, tile_y, rect) -> dict:
+    """Host only: the fine-tile tiling lts_set_tiling would pick for the level of
+    `rule` (0, 0, rect=False: adaptive) with the tile that writes each node back
+    (`owner`, [ny, nx]: -1 none, -2 more than one)."""
+    lib = _lib.load()
+    lv = rect_level_host(rule)
+    owner = np.zeros((lv["ny_nodes"], lv["nx_nodes"]), dtype=np.int32)
+    info = _lib.TilingInfo()
+    _check(lib.lts_tiling_host(C.byref(rule), tile_x, tile_y, 1 if rect else 0, C.byref(info), _ip(owner)))
+    d = {k: getattr(info, k) for k, _ in _lib.TilingInfo._fields_}
+    d["owner"] = owner
+    d["flags"] = lv["flags"]
     return d
 
 

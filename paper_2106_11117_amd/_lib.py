@@ -52,6 +52,12 @@ class LevelInfo(C.Structure):
                 ("halo_ratio", C.c_double), ("tuned_ms", C.c_double)]
 
 
+class TilingInfo(C.Structure):
+    _fields_ = [("n_fine", C.c_int32), ("n_coarse", C.c_int32), ("tile_x", C.c_int32),
+                ("tile_y", C.c_int32), ("tile_rect", C.c_int32), ("max_region", C.c_int32),
+                ("regions_exact", C.c_int32), ("halo_ratio", C.c_double)]
+
+
 class SampleRule(C.Structure):
     _fields_ = [("n_blocks", C.c_int32), ("sigma", C.c_double), ("px_lo", C.c_double),
                 ("px_hi", C.c_double), ("py_lo", C.c_double), ("py_hi", C.c_double),
@@ -101,6 +107,8 @@ SIGNATURES = [
     ("lts_philox4x64_10", C.c_int32, [u64p, u64p, u64p]),
     ("lts_rect_level_host", C.c_int32, [C.POINTER(RectRule), C.POINTER(LevelInfo), dp, dp, u8p, dp, dp,
                                         ip]),
+    ("lts_tiling_host", C.c_int32, [C.POINTER(RectRule), C.c_int32, C.c_int32, C.c_int32,
+                                    C.POINTER(TilingInfo), ip]),
     ("lts_cheb_constants", C.c_int32, [C.c_int32, C.c_double, C.c_double, dp, dp, dp, dp, dp]),
     ("lts_forward", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Samples), C.c_int32, C.c_void_p]),
     ("lts_forward_plain", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Samples), C.c_int32, C.c_void_p]),

@@ -358,6 +358,97 @@ lts_status lts_rect_level_host(const lts_rect_rule* r, lts_level_info* info, dou
   return LTS_OK;
 }
 
+lts_status lts_tiling_host(const lts_rect_rule* r, int32_t tile_x, int32_t tile_y, int32_t rect,
+                           lts_tiling_info* info, int32_t* owner) {
+  if (!r || !info) return LTS_ERR_ARG;
+  const bool adaptive = tile_x == 0 && tile_y == 0 && rect == 0;
+  if (!adaptive && (tile_x < 1 || tile_y < 1 || tile_x > 4096 || tile_y > 4096)) return LTS_ERR_ARG;
+  if (rect != 0 && rect != 1) return LTS_ERR_ARG;
+  std::vector<double> xs, ys;
+  std::vector<uint8_t> act, fine, qoi;
+  std::vector<int32_t> blk;
+  double h = 0;
+  int p = 0, nb = 0;
+  if (!build_rect_desc(*r, xs, ys, act, blk, fine, qoi, h, p, nb).empty()) return LTS_ERR_ARG;
+  lts_grid_desc d{};
+  d.nx_cells = (int32_t)xs.size() - 1;
+  d.ny_cells = (int32_t)ys.size() - 1;
+  d.x = xs.data(); d.y = ys.data();
+  d.cell_active = act.data(); d.cell_block = blk.data(); d.cell_fine = fine.data(); d.cell_qoi = qoi.data();
+  d.n_blocks = nb; d.h = h; d.p = p; d.nu = r->nu;
+  HostLevel H;
+  if (!build_level_from_desc(d, H).empty()) return LTS_ERR_ARG;
+  const int ld = (H.nxn + kPitchAlign - 1) / kPitchAlign * kPitchAlign;
+  // the origin lts_set_tiling would take
+  TilingHost T;
+  bool have = false;
+  for (auto& org : tile_origins(H, tile_x, tile_y)) {
+    TilingHost C;
+    if (!build_tiling(H, ld, tile_x, tile_y, org.first, org.second, rect == 1, C).empty()) continue;
+    if (!have || C.halo_ratio * C.n_fine < T.halo_ratio * T.n_fine) {
+      T = std::move(C);
+      have = true;
+    }
+  }
+  if (!have) return LTS_ERR_ARG;
+  const int nx = H.nxn, ny = H.nyn;
+  auto fplus = [&](int i, int j) { return (H.flags[(size_t)j * nx + i] & LTS_NODE_FPLUS) != 0; };
+  auto dist = [](int i, int j, int x0, int x1, int y0, int y1) {
+    return std::max(std::max(x0 - i, i - (x1 - 1)), 0) + std::max(std::max(y0 - j, j - (y1 - 1)), 0);
+  };
+  std::vector<int32_t> own((size_t)nx * ny, -1);
+  auto claim = [&](int i, int j, int t) {
+    int32_t& o = own[(size_t)j * nx + i];
+    o = o == -1 ? t : -2;
+  };
+  bool exact = true;
+  int max_region = 0;
+  if (T.rect) {
+    for (int t = 0; t < T.n_fine; ++t) {
+      const int4 q = T.rtiles[t];
+      const int rx0 = q.x & 0xFFFF, ry0 = q.x >> 16, rx1 = rx0 + (q.y & 0xFFFF), ry1 = ry0 + (q.y >> 16);
+      const int x0 = q.z & 0xFFFF, x1 = q.z >> 16, y0 = q.w & 0xFFFF, y1 = q.w >> 16;
+      max_region = std::max(max_region, (rx1 - rx0) * (ry1 - ry0));
+      for (int j = std::max(y0 - p, 0); j < std::min(y1 + p, ny); ++j)
+        for (int i = std::max(x0 - p, 0); i < std::min(x1 + p, nx); ++i) {
+          if (!fplus(i, j)) continue;
+          const int dd = dist(i, j, x0, x1, y0, y1);
+          if (dd <= p && (i < rx0 || i >= rx1 || j < ry0 || j >= ry1)) exact = false;
+          if (dd == 0) claim(i, j, t);
+        }
+    }
+  } else {
+    std::vector<int32_t> mark((size_t)nx * ny, -1);
+    for (int t = 0; t < T.n_fine; ++t) {
+      const int4 q = T.tiles[t];
+      const int x0 = q.z & 0xFFFF, x1 = q.z >> 16, y0 = q.w & 0xFFFF, y1 = q.w >> 16;
+      max_region = std::max(max_region, q.y);
+      int want = 0;
+      for (int j = std::max(y0 - p, 0); j < std::min(y1 + p, ny); ++j)
+        for (int i = std::max(x0 - p, 0); i < std::min(x1 + p, nx); ++i)
+          if (fplus(i, j) && dist(i, j, x0, x1, y0, y1) <= p) ++want;
+      if (want != q.y) exact = false;
+      for (int e = 0; e < q.y; ++e) {
+        const int4 en = T.ent[(size_t)q.x + e];
+        const int i = en.w & 0xFFFF, j = en.w >> 16;
+        if (!fplus(i, j) || dist(i, j, x0, x1, y0, y1) > p || mark[(size_t)j * nx + i] == t) exact = false;
+        mark[(size_t)j * nx + i] = t;
+        if (dist(i, j, x0, x1, y0, y1) == 0) claim(i, j, t);
+      }
+    }
+  }
+  info->n_fine = T.n_fine;
+  info->n_coarse = T.n_coarse;
+  info->tile_x = T.TX;
+  info->tile_y = T.TY;
+  info->tile_rect = T.rect ? 1 : 0;
+  info->max_region = max_region;
+  info->regions_exact = exact ? 1 : 0;
+  info->halo_ratio = T.halo_ratio;
+  if (owner) std::memcpy(owner, own.data(), own.size() * sizeof(int32_t));
+  return LTS_OK;
+}
+
 lts_status lts_cheb_constants(int32_t p, double nu, double dt, double* delta, double* omega,
                               double* beta, double* beta_half, double* coef) {
   if (p < 1 || p > 256 || !(nu >= 0.0 && nu <= 1.0)) return LTS_ERR_ARG;

@@ -139,3 +139,41 @@ def test_context_without_gpu_fails_cleanly():
         pytest.skip("a GPU is present")
     with pytest.raises(P.LtsError):
         P.Context(0)
+
+
+@pytest.mark.parametrize("rule,tile,rect", [
+    ("box32", (48, 48), True), ("box32", (16, 16), False), ("box32", (0, 0), False),
+    ("box64", (24, 40), True), ("box64", (0, 0), False),
+    ("L64", (0, 0), False), ("L256", (40, 40), False), ("L256", (0, 0), False), ("L512", (0, 0), False),
+])
+def test_tiling_partitions_fplus(rule, tile, rect):
+    """Every fine tiling (rect, uniform compact, adaptive) writes each F+ node
+    back from exactly one tile and no other node, and each region holds every F+
+    node within Manhattan distance p of its tile (the nodes that can reach the
+    tile in p substeps), within one workgroup."""
+    r = {"box32": P.box_rule(32), "box64": P.box_rule(64), "L64": P.graded_L_rule(64),
+         "L256": P.graded_L_rule(256), "L512": P.graded_L_rule(512)}[rule]
+    t = P.tiling_host(r, *tile, rect)
+    fplus = (t["flags"] & P.LTS_NODE_FPLUS) != 0
+    assert (t["owner"][fplus] >= 0).all()
+    assert (t["owner"][~fplus] == -1).all()
+    assert t["regions_exact"] == 1
+    assert 1 <= t["max_region"] <= 4096
+    assert t["owner"].max() == t["n_fine"] - 1
+    assert (t["tile_x"], t["tile_y"], t["tile_rect"]) == (*tile, int(rect))
+
+
+def test_adaptive_tiling_cuts_across_bands():
+    """On the graded L-shape (F+ a cross of thin bands, p = 64) the adaptive
+    tiling needs less than half the region nodes of square tiles; a level whose
+    F+ fits one workgroup gets a single tile; rect mode has no adaptive form."""
+    sq = P.tiling_host(P.graded_L_rule(256), 40, 40, False)["halo_ratio"]
+    ad = P.tiling_host(P.graded_L_rule(256), 0, 0, False)["halo_ratio"]
+    assert ad < 0.5 * sq, (ad, sq)
+    assert P.tiling_host(P.graded_L_rule(512), 0, 0, False)["halo_ratio"] < 2.1
+    one = P.tiling_host(P.graded_L_rule(64), 0, 0, False)
+    assert one["n_fine"] == 1 and one["halo_ratio"] == 1.0
+    with pytest.raises(P.LtsError):
+        P.tiling_host(P.graded_L_rule(64), 0, 0, True)
+    with pytest.raises(P.LtsError):
+        P.tiling_host(P.graded_L_rule(64), 0, 8, False)
