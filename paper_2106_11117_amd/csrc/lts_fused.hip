@@ -301,9 +301,18 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepS
   T u[kNPT], pm[kNPT], d0[kNPT], d1[kNPT], w[kNPT], aE[kNPT], aW[kNPT], aN[kNPT], aS[kNPT];
   uint32_t ad[kNPT][4];                // LDS byte offsets of the E, W, N, S neighbours
   int kk[kNPT], dd[kNPT];
+  // The lane's entries are read in one batch (a lane past the region end reads
+  // the last entry again and ignores it); then, node by node, everything an
+  // entry indexes: u and 1/m of the node, u and the flags of its four
+  // neighbours (an F+ node is an interior DOF, so they exist, and their values
+  // are read with their flags and masked afterwards), the blocks of its four
+  // cells and the cell sizes.
+  int4 en[kNPT];
+#pragma unroll
+  for (int r = 0; r < kNPT; ++r) en[r] = a.ent[tl.x + min((int)threadIdx.x + r * kFineThreads, len - 1)];
+  const int ld = L.ld;
 #pragma unroll
   for (int r = 0; r < kNPT; ++r) {
-    const int e = threadIdx.x + r * kFineThreads;
     d0[r] = d1[r] = (T)0;
     u[r] = pm[r] = w[r] = (T)0;
     aE[r] = aW[r] = aN[r] = aS[r] = (T)0;
@@ -311,37 +320,39 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepS
     for (int t = 0; t < 4; ++t) ad[r][t] = (uint32_t)(len * sizeof(T));
     kk[r] = 0;
     dd[r] = p;                         // never updated, never written
+    const int e = threadIdx.x + r * kFineThreads;
     if (e < len) {
-      const int4 en = a.ent[tl.x + e];
-      const size_t k = (size_t)(en.x & 0x7FFFFFFF);
-      const bool pi = en.x < 0;
-      const int i = en.w & 0xFFFF, j = en.w >> 16;
+      const size_t k = (size_t)(en[r].x & 0x7FFFFFFF);
+      const bool pi = en[r].x < 0;
+      const int i = en[r].w & 0xFFFF, j = en[r].w >> 16;
       kk[r] = (int)k;
-      ad[r][0] = (uint32_t)(en.y & 0xFFFF) * sizeof(T);
-      ad[r][1] = ((uint32_t)en.y >> 16) * sizeof(T);
-      ad[r][2] = (uint32_t)(en.z & 0xFFFF) * sizeof(T);
-      ad[r][3] = ((uint32_t)en.z >> 16) * sizeof(T);
+      ad[r][0] = (uint32_t)(en[r].y & 0xFFFF) * sizeof(T);
+      ad[r][1] = ((uint32_t)en[r].y >> 16) * sizeof(T);
+      ad[r][2] = (uint32_t)(en[r].z & 0xFFFF) * sizeof(T);
+      ad[r][3] = ((uint32_t)en[r].z >> 16) * sizeof(T);
       dd[r] = max(max(ix0 - i, i - (ix1 - 1)), 0) + max(max(iy0 - j, j - (iy1 - 1)), 0);
       const T uc = u_g[k];
+      const T uE = u_g[k + 1], uW = u_g[k - 1], uN = u_g[k + ld], uS = u_g[k - ld];
+      const uint8_t fE = L.flags[k + 1], fW = L.flags[k - 1], fN = L.flags[k + ld], fS = L.flags[k - ld];
+      const double im = L.invm[k];
+      double cE, cW, cN, cS;
+      edge_coefs(L, lk, i, j, cE, cW, cN, cS);
       u[r] = uc;
       pm[r] = pi ? (T)1 : (T)0;
       q0[e] = pi ? uc : (T)0;
-      if (dd[r] < p) {                 // updated in some substep
-        double cE, cW, cN, cS;
-        edge_coefs(L, lk, i, j, cE, cW, cN, cS);
-        const double im = L.invm[k];
-        aE[r] = (T)(im * cE);
-        aW[r] = (T)(im * cW);
-        aN[r] = (T)(im * cN);
-        aS[r] = (T)(im * cS);
-        // w = A_u (I - P) u_n
-        const T vi = pi ? (T)0 : uc;
-        const T vE = (L.flags[k + 1] & F_P) ? (T)0 : u_g[k + 1];
-        const T vW = (L.flags[k - 1] & F_P) ? (T)0 : u_g[k - 1];
-        const T vN = (L.flags[k + L.ld] & F_P) ? (T)0 : u_g[k + L.ld];
-        const T vS = (L.flags[k - L.ld] & F_P) ? (T)0 : u_g[k - L.ld];
-        w[r] = aE[r] * (vi - vE) + aW[r] * (vi - vW) + aN[r] * (vi - vN) + aS[r] * (vi - vS);
-      }
+      // coefficients (zero for a node no substep updates) and w = A_u (I - P) u_n,
+      // formed without a branch so that all of the node's reads go out together
+      const double imu = dd[r] < p ? im : 0.0;
+      aE[r] = (T)(imu * cE);
+      aW[r] = (T)(imu * cW);
+      aN[r] = (T)(imu * cN);
+      aS[r] = (T)(imu * cS);
+      const T vi = pi ? (T)0 : uc;
+      const T vE = (fE & F_P) ? (T)0 : uE;
+      const T vW = (fW & F_P) ? (T)0 : uW;
+      const T vN = (fN & F_P) ? (T)0 : uN;
+      const T vS = (fS & F_P) ? (T)0 : uS;
+      w[r] = aE[r] * (vi - vE) + aW[r] * (vi - vW) + aN[r] * (vi - vN) + aS[r] * (vi - vS);
     }
   }
   if (threadIdx.x == 0) q0[len] = q1[len] = (T)0;   // slot read for absent / non-P neighbours
