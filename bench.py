@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # to the average launch's 1.7105e9 algorithmic bytes.  Valid only for the
 # step-kernel sources the counters were taken with.
 TRAFFIC = {"bytes_per_launch": 1.380 * 1.7105e9,
-           "sources_sha256": "958714ba4bf0e29fc7baff073ff0ba400981bfcef0149498aded7bc63a8145c1"}
+           "sources_sha256": "984d044be9b7abf329be89d9f3d8f17904396b8a5e2833e63e54825c92795e66"}
 STEP_SOURCES = ("lts_fused.hip", "fused.h", "device.h", "lts_step.hip")
 WORKLOAD = ("unit square 512x512 base refined 8x in (0.48,0.52): 442225 DOFs, |P|=204081, p=8, "
             "nu=0.01, 256 samples, 4x4 blocks sigma=0.25, T=1, FP64")

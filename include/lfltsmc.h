@@ -172,6 +172,9 @@ typedef struct {
   int32_t max_region;             /* nodes (rect mode: lanes) of the largest fine-tile region */
   int32_t regions_exact;          /* 1: every region holds all F+ nodes within Manhattan
                                      distance p of its tile (compact mode: exactly those) */
+  int32_t threads;                /* threads of a fine workgroup: 1024 in rect mode; in compact
+                                     mode the fewest of 256, 512, 1024 whose lanes (4 nodes
+                                     each) hold the largest region */
   double halo_ratio;              /* nodes of all fine-tile regions / |F+| */
 } lts_tiling_info;
 

@@ -55,7 +55,7 @@ class LevelInfo(C.Structure):
 class TilingInfo(C.Structure):
     _fields_ = [("n_fine", C.c_int32), ("n_coarse", C.c_int32), ("tile_x", C.c_int32),
                 ("tile_y", C.c_int32), ("tile_rect", C.c_int32), ("max_region", C.c_int32),
-                ("regions_exact", C.c_int32), ("halo_ratio", C.c_double)]
+                ("regions_exact", C.c_int32), ("threads", C.c_int32), ("halo_ratio", C.c_double)]
 
 
 class SampleRule(C.Structure):

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <memory>
 #include <string>
@@ -51,6 +52,7 @@ struct TilingDev {
   int pitch = 0;
   double halo_ratio = 1.0;
   double wg_work = 0.0;  // mean region nodes x substeps of one fine workgroup
+  int nt = kFineThreads; // compact mode: threads of a fine workgroup
   uint64_t gen = 0;     // distinct for every upload (keys captured graphs)
   DevBuf ent, tiles, rtiles, citems;
 };
@@ -87,6 +89,7 @@ struct lts_error {
 
 struct lts_ctx_s {
   int device = 0;
+  int n_cu = 256;                 // compute units of the device
   hipStream_t stream = nullptr;
   bool own_stream = false;
   std::string err;
@@ -157,6 +160,17 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
                           double* d_out, int s_base);
 
 lts_status upload_tiling(lts_ctx c, const TilingHost& T, TilingDev& D);
+
+// Threads of the compact fine workgroups of a launch with `active` samples on
+// tiling T.  A small workgroup (T.nt < 1024) shares its CU with others: more
+// throughput when the launch has workgroups to spare, a longer step when it
+// has at most one or two per CU.  Every size gives the same results.
+inline int compact_threads(const TilingDev& T, int active, int n_cu) {
+  const long long w = (long long)active * T.n_fine;
+  if (w <= n_cu) return kFineThreads;
+  if (w <= 2LL * n_cu) return std::max(T.nt, 512);
+  return T.nt;
+}
 
 // Tile-size candidates (TX, TY) tried for the fused step, in order.
 const std::vector<std::pair<int, int>>& tile_candidates();

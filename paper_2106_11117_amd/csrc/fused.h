@@ -35,6 +35,8 @@ struct TilingHost {
   int n_fine = 0, n_coarse = 0, wg_per_sample = 0;   // wg_per_sample: fine + coarse workgroups
   double halo_ratio = 1.0;          // region lanes / F+ nodes
   double wg_work = 0.0;             // mean region nodes x substeps of one fine workgroup
+  int nt = kFineThreads;            // compact mode: threads of a fine workgroup (256, 512 or 1024),
+                                    // the fewest whose kNPT nodes per lane hold the largest region
   std::vector<int4> ent;            // compact mode: region entries (see lts_fused.hip)
   std::vector<int4> tiles;          // compact mode: offset, length, interior columns, rows (packed)
   std::vector<int4> rtiles;         // rect mode: region rectangle and tile interior (packed)

@@ -218,6 +218,9 @@ lts_status lts_create(lts_ctx* out, int32_t hip_device, void* hip_stream) {
     delete c;
     return LTS_ERR_HIP;
   }
+  int n_cu = 0;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && n_cu > 0)
+    c->n_cu = n_cu;
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {
@@ -444,6 +447,7 @@ lts_status lts_tiling_host(const lts_rect_rule* r, int32_t tile_x, int32_t tile_
   info->tile_rect = T.rect ? 1 : 0;
   info->max_region = max_region;
   info->regions_exact = exact ? 1 : 0;
+  info->threads = T.rect ? kFineThreads : T.nt;
   info->halo_ratio = T.halo_ratio;
   if (owner) std::memcpy(owner, own.data(), own.size() * sizeof(int32_t));
   return LTS_OK;

@@ -284,9 +284,10 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_multi(MultiArgs m) {
 // for an absent or non-P neighbour), w = i | j << 16.  Each lane turns its
 // neighbour slots into LDS byte addresses once; the substeps run in pairs so
 // that the two buffers and the roles of the increment registers are fixed.
-template <class T>
+template <class T, int NT>
 __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepState& st, const double* __restrict__ lk,
                                                   T* __restrict__ lq, int s, int tile) {
+  constexpr int kCap = NT * kNPT;      // region nodes this workgroup size holds
   const LevelView& L = a.L;
   const int4 tl = a.tiles[tile];
   const int len = tl.y;
@@ -296,7 +297,7 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepS
   T* __restrict__ uo_g = reinterpret_cast<T*>(st.Uold) + (size_t)s * a.sstride;
   const double* __restrict__ cf = a.coef + (size_t)s * (L.p + 1);
   T* const q0 = lq;                    // q of the even substeps' inputs
-  T* const q1 = lq + (kRegionCap + 1);  // and of the odd ones'; slot len of each holds 0
+  T* const q1 = lq + (kCap + 1);       // and of the odd ones'; slot len of each holds 0
 
   T u[kNPT], pm[kNPT], d0[kNPT], d1[kNPT], w[kNPT], aE[kNPT], aW[kNPT], aN[kNPT], aS[kNPT];
   uint32_t ad[kNPT][4];                // LDS byte offsets of the E, W, N, S neighbours
@@ -309,7 +310,7 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepS
   // cells and the cell sizes.
   int4 en[kNPT];
 #pragma unroll
-  for (int r = 0; r < kNPT; ++r) en[r] = a.ent[tl.x + min((int)threadIdx.x + r * kFineThreads, len - 1)];
+  for (int r = 0; r < kNPT; ++r) en[r] = a.ent[tl.x + min((int)threadIdx.x + r * NT, len - 1)];
   const int ld = L.ld;
 #pragma unroll
   for (int r = 0; r < kNPT; ++r) {
@@ -320,7 +321,7 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepS
     for (int t = 0; t < 4; ++t) ad[r][t] = (uint32_t)(len * sizeof(T));
     kk[r] = 0;
     dd[r] = p;                         // never updated, never written
-    const int e = threadIdx.x + r * kFineThreads;
+    const int e = threadIdx.x + r * NT;
     if (e < len) {
       const size_t k = (size_t)(en[r].x & 0x7FFFFFFF);
       const bool pi = en[r].x < 0;
@@ -383,7 +384,7 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepS
       const T rr = w[r] + apq;
       const T dn = ((T)1 + b) * dc[r] - b * dq[r] - c * rr;
       dq[r] = dn;
-      if (m + 1 < p) wq[threadIdx.x + r * kFineThreads] = pm[r] * (u[r] + dn);
+      if (m + 1 < p) wq[threadIdx.x + r * NT] = pm[r] * (u[r] + dn);
     }
     if (m + 1 < p) __syncthreads();
   };
@@ -634,8 +635,22 @@ __global__ __launch_bounds__(kFineThreads) void k_fine(StepArgs a) {
     fine_tile_rect<T>(a, StepState{a.Ucur, a.Uold, a.startup}, lk, lq, ls, s, Lid % a.n_fine);
   } else {
     load_kappa(a, s, lk);
-    fine_tile_compact<T>(a, StepState{a.Ucur, a.Uold, a.startup}, lk, lq, s, Lid % a.n_fine);
+    fine_tile_compact<T, kFineThreads>(a, StepState{a.Ucur, a.Uold, a.startup}, lk, lq, s, Lid % a.n_fine);
   }
+}
+
+// Compact tiles whose regions fit NT * kNPT < kRegionCap nodes: smaller
+// workgroups, several per CU.
+template <class T, int NT>
+__global__ __launch_bounds__(NT) void k_fine_small(StepArgs a) {
+  __shared__ T lq[2 * (NT * kNPT + 1)];
+  __shared__ double lk[256];
+  const int G = a.n_fine * a.active;
+  const int Lid = (int)(blockIdx.x & 7) * a.per_xcd + (int)(blockIdx.x >> 3);
+  if (Lid >= G) return;
+  const int s = a.s0 + Lid / a.n_fine;
+  load_kappa(a, s, lk);
+  fine_tile_compact<T, NT>(a, StepState{a.Ucur, a.Uold, a.startup}, lk, lq, s, Lid % a.n_fine);
 }
 
 template <bool RECT>
@@ -652,8 +667,20 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_multi(MultiArgs m) {
     fine_tile_rect<double>(a, st, lk, lq, ls, s, local % a.n_fine);
   } else {
     load_kappa(a, s, lk);
-    fine_tile_compact<double>(a, st, lk, lq, s, local % a.n_fine);
+    fine_tile_compact<double, kFineThreads>(a, st, lk, lq, s, local % a.n_fine);
   }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_fine_small_multi(MultiArgs m) {
+  __shared__ double lq[2 * (NT * kNPT + 1)];
+  __shared__ double lk[256];
+  int j, local, n;
+  if (!multi_slot(m, j, local, n)) return;
+  const StepArgs a = job_record(m.jobs[j]);
+  const int s = local / a.n_fine;
+  load_kappa(a, s, lk);
+  fine_tile_compact<double, NT>(a, job_state(m, a), lk, lq, s, local % a.n_fine);
 }
 
 }  // namespace
@@ -911,6 +938,11 @@ std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int
       if (cm) T.citems.push_back(make_int4(tx | ty << 16, (int)(uint32_t)cm, (int)(uint32_t)(cm >> 32), (int)rm));
     }
   T.n_fine = (int)(rect ? T.rtiles.size() : T.tiles.size());
+  if (!rect) {
+    int max_len = 0;
+    for (const int4& t : T.tiles) max_len = std::max(max_len, t.y);
+    T.nt = max_len <= 256 * kNPT ? 256 : max_len <= 512 * kNPT ? 512 : kFineThreads;
+  }
   T.n_coarse = (int)T.citems.size();
   T.wg_per_sample = T.n_fine + T.n_coarse;
   T.halo_ratio = n_fplus ? (double)n_region / n_fplus : 1.0;
@@ -926,6 +958,7 @@ lts_status upload_tiling(lts_ctx c, const TilingHost& T, TilingDev& D) {
   D.wg_per_sample = T.wg_per_sample;
   D.halo_ratio = T.halo_ratio;
   D.wg_work = T.wg_work;
+  D.nt = T.nt;
   D.rect = T.rect;
   D.pitch = T.pitch;
   static uint64_t gen_counter = 0;
@@ -1036,10 +1069,19 @@ lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const 
     const long long G = (long long)T.n_fine * active;
     a.per_xcd = (int)((G + 7) / 8);
     const dim3 grid((unsigned)(8LL * a.per_xcd));
+    const int nt = T.rect ? kFineThreads : compact_threads(T, active, c->n_cu);
     if (T.rect && fp32)
       k_fine<true, float><<<grid, dim3(kFineThreads), 0, stream>>>(a);
     else if (T.rect)
       k_fine<true, double><<<grid, dim3(kFineThreads), 0, stream>>>(a);
+    else if (nt == 256 && fp32)
+      k_fine_small<float, 256><<<grid, dim3(256), 0, stream>>>(a);
+    else if (nt == 256)
+      k_fine_small<double, 256><<<grid, dim3(256), 0, stream>>>(a);
+    else if (nt == 512 && fp32)
+      k_fine_small<float, 512><<<grid, dim3(512), 0, stream>>>(a);
+    else if (nt == 512)
+      k_fine_small<double, 512><<<grid, dim3(512), 0, stream>>>(a);
     else if (fp32)
       k_fine<false, float><<<grid, dim3(kFineThreads), 0, stream>>>(a);
     else
@@ -1073,7 +1115,8 @@ lts_status launch_multi_step(lts_ctx c, const StepArgs* d_jobs, const std::vecto
       int w = 0;
       if (kind == 0) w = T[j]->n_coarse;
       else if (kind == 1) w = T[j]->rect ? T[j]->n_fine : 0;
-      else w = T[j]->rect ? 0 : T[j]->n_fine;
+      else if (!T[j]->rect && compact_threads(*T[j], active[j], c->n_cu) == (kind == 2 ? kFineThreads : kind == 3 ? 512 : 256))
+        w = T[j]->n_fine;
       m.wg_n[q] = w * active[j];
       m.chunk_off[q + 1] = m.chunk_off[q] + (m.wg_n[q] + 7) / 8;
     }
@@ -1083,12 +1126,14 @@ lts_status launch_multi_step(lts_ctx c, const StepArgs* d_jobs, const std::vecto
       k_coarse_multi<<<grid, dim3(kCoarseThreads), 0, stream>>>(m);
     else if (kind == 1)
       k_fine_multi<true><<<grid, dim3(kFineThreads), 0, stream>>>(m);
-    else
+    else if (kind == 2)
       k_fine_multi<false><<<grid, dim3(kFineThreads), 0, stream>>>(m);
+    else if (kind == 3)
+      k_fine_small_multi<512><<<grid, dim3(512), 0, stream>>>(m);
+    else
+      k_fine_small_multi<256><<<grid, dim3(256), 0, stream>>>(m);
   };
-  go(0);
-  go(1);
-  go(2);
+  for (int kind = 0; kind < 5; ++kind) go(kind);
   return LTS_OK;
 }
 

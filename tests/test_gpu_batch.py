@@ -61,7 +61,41 @@ def test_batch_matches_per_level_solves_and_oracle(ctx):
         off += n
     for lid in (jobs[0][0], jobs[1][0], jobs[2][0]):
         info = ctx.level_info(lid)
-        assert info["tuned"] == 1 and info["tile_x"] > 0
+        assert info["tuned"] == 1 and info["halo_ratio"] >= 1.0
+        assert info["tile_x"] > 0 or (info["tile_y"] == 0 and info["tile_rect"] == 0)   # 0 x 0: adaptive
+
+
+def test_batch_compact_workgroup_sizes(ctx):
+    """Compact tilings whose regions fit 256-, 512- and 1024-thread workgroups,
+    with enough samples that the launches switch workgroup size as samples
+    finish (the small sizes while the launch has workgroups to spare): the
+    batched QoIs equal one solve per level bit for bit, and the oracle's."""
+    lg = ctx.add_rect_level(P.graded_L_rule(32))    # adaptive: 777-node region, 256 threads
+    l0 = ctx.add_rect_level(P.box_rule(32))          # adaptive: 1,273 nodes, 512 threads
+    l1 = ctx.add_rect_level(P.box_rule(64))          # adaptive: up to 4,060 nodes, 1024 threads
+    for lid in (lg, l0, l1):
+        ctx.set_tiling(lid, 0, 0, False)
+    rg = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), T=0.3)
+    r = P.sample_rule(T=0.2)
+    sg = P.gen_samples(1, 0, 0, 700, rg, 1 / 16)
+    s0 = P.gen_samples(1, 1, 0, 300, r, 1 / 32)
+    s1 = P.gen_samples(1, 2, 0, 40, r, 1 / 64)
+    jobs = [(lg, sg["kappa"], sg["x0"], sg["n_steps"], sg["dt"], 0.05),
+            (l0, s0["kappa"], s0["x0"], s0["n_steps"], s0["dt"], 0.05),
+            (l1, s1["kappa"], s1["x0"], s1["n_steps"], s1["dt"], 0.05)]
+    q = ctx.batch_run(jobs)
+    qg = ctx.batch_run(jobs, graph=True)
+    ql = np.concatenate([np.asarray(ctx.forward(j[0], *j[1:5], width=j[5])) for j in jobs])
+    assert np.array_equal(q, ql) and np.array_equal(qg, ql)
+    off = 0
+    for (lid, kap, x0, ns, dt, w), lv in zip(jobs, (mesh.graded_L_level(32), mesh.box_refined_level(32),
+                                                    mesh.box_refined_level(64))):
+        ops = fem.operators(lv)
+        for k in (0, len(ns) - 1):
+            u = lts.Solver(ops, kap[k]).run(lts.pulse(ops, x0[k], w), dt[k], int(ns[k]))
+            sc = float(ops.qoi_w @ np.abs(u))
+            assert abs(q[off + k] - float(lts.qoi(ops, u))) <= 1e-11 * sc
+        off += len(ns)
 
 
 def test_graph_replays_match_eager(ctx):

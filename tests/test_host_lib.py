@@ -161,6 +161,8 @@ def test_tiling_partitions_fplus(rule, tile, rect):
     assert 1 <= t["max_region"] <= 4096
     assert t["owner"].max() == t["n_fine"] - 1
     assert (t["tile_x"], t["tile_y"], t["tile_rect"]) == (*tile, int(rect))
+    # the workgroup holds the largest region at 4 nodes per lane, with no larger size to spare
+    assert t["max_region"] <= 4 * t["threads"] and (rect or t["threads"] == 256 or t["max_region"] > 2 * t["threads"])
 
 
 def test_adaptive_tiling_cuts_across_bands():
@@ -172,7 +174,11 @@ def test_adaptive_tiling_cuts_across_bands():
     assert ad < 0.5 * sq, (ad, sq)
     assert P.tiling_host(P.graded_L_rule(512), 0, 0, False)["halo_ratio"] < 2.1
     one = P.tiling_host(P.graded_L_rule(64), 0, 0, False)
-    assert one["n_fine"] == 1 and one["halo_ratio"] == 1.0
+    assert one["n_fine"] == 1 and one["halo_ratio"] == 1.0 and one["threads"] == 512
+    assert P.tiling_host(P.graded_L_rule(32), 0, 0, False)["threads"] == 256
+    assert P.tiling_host(P.box_rule(32), 0, 0, False)["threads"] == 512
+    assert P.tiling_host(P.box_rule(64), 48, 48, False)["threads"] == 512
+    assert P.tiling_host(P.box_rule(64), 0, 0, False)["threads"] == 1024
     with pytest.raises(P.LtsError):
         P.tiling_host(P.graded_L_rule(64), 0, 0, True)
     with pytest.raises(P.LtsError):
