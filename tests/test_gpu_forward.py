@@ -312,3 +312,22 @@ def test_adaptive_tiling_halo(ctx):
     adaptive = ctx.set_tiling(lid, 0, 0, False)["halo_ratio"]
     print(f"halo ratio: 40 x 40 tiles {square:.3f}, adaptive {adaptive:.3f}")
     assert adaptive < 0.6 * square
+
+
+@pytest.mark.parametrize("precision", [P.LTS_FP64, P.LTS_FP32_STEP])
+def test_compact_workgroup_size_does_not_change_results(ctx, precision):
+    """A sample's QoI does not depend on what it is batched with: the first
+    samples solved alone (1024-thread compact workgroups) and at the head of a
+    700-sample batch (256- and 512-thread workgroups while many are active)
+    agree bit for bit, in FP64 and in FP32 stepping."""
+    lid = ctx.add_rect_level(P.graded_L_rule(32))
+    info = ctx.set_tiling(lid, 0, 0, False)          # one 777-node region: 256-thread workgroups fit
+    assert info["tile_rect"] == 0
+    r = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), T=0.3)
+    s = P.gen_samples(2, 0, 0, 700, r, 1 / 16)
+    big = np.asarray(ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"], precision=precision))
+    k = 5
+    small = np.asarray(ctx.forward(lid, s["kappa"][:k], s["x0"][:k], s["n_steps"][:k], s["dt"][:k],
+                                   precision=precision))
+    assert np.array_equal(big[:k], small)
+    assert np.isfinite(big).all()
