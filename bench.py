@@ -187,6 +187,64 @@ def mlmc_bench(no_cpu: bool):
     ctx.close()
 
 
+def lf_bench():
+    """Standard leapfrog baseline (the cost comparison of Sec. 3.4 and the MLMC
+    comparisons of Sec. 4) on the graded L-shape hierarchy: every level against
+    its leapfrog twin (the same grid with P empty, stepping at dt/p everywhere).
+    Per level, one batched forward of the survey's sample mix on each, whose wall
+    time ratio is the measured C_l^LF / C_l^LTS, beside the ratio of DOF updates;
+    then Algorithm 1 on both hierarchies (batched + graph) at the MLMC eps."""
+    import numpy as np
+
+    import paper_2106_11117_amd as P
+
+    ctx = P.Context(0)
+    lts_ids = [ctx.add_rect_level(P.graded_L_rule(nb)) for nb in MLMC_BASES]
+    lf_ids = [ctx.add_rect_level(P.lf_rule(P.graded_L_rule(nb))) for nb in MLMC_BASES]
+    rule = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), width=0.05, T=2.0)
+    for lid in lts_ids + lf_ids:
+        ctx.autotune(lid)
+    levels = []
+    for lev, n in enumerate(BATCH_N):
+        row = {"level": lev, "samples": n}
+        for kind, lid in (("lts", lts_ids[lev]), ("lf", lf_ids[lev])):
+            info = ctx.level_info(lid)
+            s = P.gen_samples(0, lev, 0, n, rule, info["h"])
+            args = (s["kappa"], s["x0"], s["n_steps"], s["dt"])
+            ctx.forward(lid, *(a[:2] for a in args))                  # warm-up (2 samples)
+            t0 = time.perf_counter()
+            q = np.asarray(ctx.forward(lid, *args))
+            t = time.perf_counter() - t0
+            steps = float(s["n_steps"].sum())
+            upd = steps * ((info["n_dof"] - info["n_P"]) + info["p"] * info["n_P"])
+            row[kind] = {"s": t, "sum_n_steps": int(steps), "dof_updates": upd,
+                         "dof_updates_per_s": upd / t, "mean_Q": float(q.mean())}
+            print(f"level {lev} {kind}: {t:.3f} s", file=sys.stderr, flush=True)
+        row["measured_cost_ratio_lf_over_lts"] = row["lf"]["s"] / row["lts"]["s"]
+        row["dof_update_ratio_lf_over_lts"] = row["lf"]["dof_updates"] / row["lts"]["dof_updates"]
+        levels.append(row)
+    runs = []
+    for eps in MLMC_EPS:
+        res = {}
+        for kind, ids in (("lts", lts_ids), ("lf", lf_ids)):
+            t0 = time.perf_counter()
+            r = ctx.mlmc(ids, rule, eps=eps, N_init=MLMC_N_INIT, L_start=2)
+            res[kind] = {"s": time.perf_counter() - t0, "L": r["L"], "N": r["N"], "var": r["var"],
+                         "estimate": r["estimate"], "rmse": r["rmse"], "converged": r["converged"]}
+        res["eps"] = eps
+        res["speedup_lts_over_lf"] = res["lf"]["s"] / res["lts"]["s"]
+        runs.append(res)
+    out = {"metric": "LF-LTS against the standard leapfrog baseline (dt/p on every element): per-level cost "
+                     "and MLMC wall time at fixed RMSE", "unit": "s", "higher_is_better": False,
+           "data": "synthetic (Philox seed 0)",
+           "config": {"workload": "graded L-shape, 5 levels h = 1/16..1/256, 6 graded layers (h_min = h/64, "
+                                  "p = 64), 8x8 blocks sigma 0.3, T = 2; leapfrog twins with P empty, p = 1, "
+                                  "spacing h/64", "N_init": list(MLMC_N_INIT), "L_start": 2},
+           "levels": levels, "mlmc": runs}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def adjoint_bench(samples: int, K: int):
     """Discrete adjoint (backward LF-LTS) on the throughput workload: time of one
     lts_backward over the batch (checkpoints every K steps, forward states
@@ -348,6 +406,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-stepping run")
     ap.add_argument("--copy-check", type=int, default=0, metavar="MIB",
                     help="only run 4 plain device copies of MIB MiB (calibrates HBM byte counters)")
+    ap.add_argument("--lf", action="store_true",
+                    help="only compare LF-LTS with the standard leapfrog baseline (graded L-shape hierarchy)")
     ap.add_argument("--stream-check", action="store_true",
                     help="only time plain torch copy / axpy / sum kernels (practical HBM rates)")
     ap.add_argument("--adjoint", action="store_true",
@@ -372,6 +432,9 @@ def main():
         return
     if args.stream_check:
         stream_check()
+        return
+    if args.lf:
+        lf_bench()
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the workload is one GPU's "

@@ -104,7 +104,7 @@ typedef struct {
  * call order).  Errors: LTS_ERR_ARG (sizes, ordering, ids), LTS_ERR_OOM. */
 lts_status lts_add_level(lts_ctx ctx, const lts_grid_desc* desc, int32_t* level_id_out);
 
-enum { LTS_RULE_BOX = 0, LTS_RULE_GRADED_L = 1 };
+enum { LTS_RULE_BOX = 0, LTS_RULE_GRADED_L = 1, LTS_RULE_LF = 0x100 };
 
 /* Generated rectilinear levels (exact dyadic node coordinates).
  *  LTS_RULE_BOX: square [lo,hi]^2, n_base uniform cells per axis; per axis,
@@ -113,11 +113,16 @@ enum { LTS_RULE_BOX = 0, LTS_RULE_GRADED_L = 1 };
  *  LTS_RULE_GRADED_L: square [lo,hi]^2 minus the cells with midpoint x > 0,
  *    y < 0 (an L-shape with reentrant corner at the origin); per axis the two
  *    cells next to 0 are replaced by the nodes +-h 2^-j, j = 1..layers
- *    (Sec. 3.4: grading toward a reentrant corner).
+ *    (Sec. 3.5: grading toward a reentrant corner).
  * Both: fine cells have a leg shorter than h/2; blocks are an nbx x nby grid
  * over [lo,hi]^2 assigned by cell midpoint (block = by*nbx + bx); QoI cells
  * have their midpoint in the closed box [qx_lo,qx_hi] x [qy_lo,qy_hi];
- * p = 0 selects p = ceil(h / smallest cell leg). */
+ * p = 0 selects p = ceil(h / smallest cell leg).
+ * kind | LTS_RULE_LF: the standard leapfrog twin of that level (the baseline
+ * the paper compares LF-LTS with, Sec. 4): the same grid, blocks and QoI
+ * cells with no fine cells (P empty) and p = 1, so every step is one plain
+ * leapfrog step over all DOFs, and nominal spacing h/p (p of the LTS level),
+ * so that samples drawn for it step at dt/p on every element. */
 typedef struct {
   int32_t kind;
   double lo, hi;

@@ -3,7 +3,7 @@
 Rectilinear tensor grids, every cell [x_a, x_a+1] x [y_b, y_b+1] split along
 the diagonal (x_a, y_b)-(x_a+1, y_b+1) into two P1 triangles, as needed by the
 mass-lumped conforming discretization of Sec. 3.1 on the locally refined
-meshes of Sec. 3.2 (fixed refined box) and Sec. 3.4 (grading toward a
+meshes of Sec. 3.2 (fixed refined box) and Sec. 3.5 (grading toward a
 reentrant corner).
 
 Readings of the paper taken here (the paper does not fix them):
@@ -225,3 +225,16 @@ def graded_L_level(n_base: int, layers: int = 6, lo: float = -1.0, hi: float = 1
     lv = Level(xs=xs, ys=ys, h=h, cell_active=active, cell_block=block, cell_fine=fine,
                cell_qoi=qoi, n_blocks=blocks[0] * blocks[1], p=p, nu=nu)
     return _finish(lv)
+
+
+def lf_twin(lv: Level) -> Level:
+    """The standard leapfrog level that the cost comparison of Sec. 3.4 and the
+    experiments of Sec. 4 set against LF-LTS: the same grid, blocks and QoI
+    cells with no fine cells (P empty) and p = 1, so that Algorithm 2 is one
+    plain leapfrog step over all DOFs, and nominal spacing h/p, so that a
+    sample's step count (T c_max / (cfl h)) is that of the step dt/p which the
+    smallest elements need."""
+    tw = Level(xs=lv.xs.copy(), ys=lv.ys.copy(), h=lv.h / lv.p, cell_active=lv.cell_active.copy(),
+               cell_block=lv.cell_block.copy(), cell_fine=np.zeros_like(lv.cell_fine),
+               cell_qoi=lv.cell_qoi.copy(), n_blocks=lv.n_blocks, p=1, nu=lv.nu)
+    return _finish(tw)

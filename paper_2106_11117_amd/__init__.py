@@ -14,11 +14,11 @@ import numpy as np
 from . import _lib
 from ._lib import (LTS_BATCH_GRAPH, LTS_FP32_STEP, LTS_FP64, LTS_MLMC_BATCHED, LTS_MLMC_PLAIN,
                    LTS_NODE_DOF, LTS_NODE_FPLUS, LTS_NODE_P, LTS_PTR_DEVICE, LTS_PTR_HOST,
-                   LTS_RULE_BOX, LTS_RULE_GRADED_L, LtsError)
+                   LTS_RULE_BOX, LTS_RULE_GRADED_L, LTS_RULE_LF, LtsError)
 
-__all__ = ["Context", "gen_samples", "philox", "rect_level_host", "tiling_host", "cheb_constants", "sample_rule", "box_rule", "graded_L_rule", "LtsError",
+__all__ = ["Context", "gen_samples", "philox", "rect_level_host", "tiling_host", "lf_rule", "cheb_constants", "sample_rule", "box_rule", "graded_L_rule", "LtsError",
            "LTS_FP64", "LTS_FP32_STEP", "LTS_BATCH_GRAPH", "LTS_MLMC_BATCHED", "LTS_MLMC_PLAIN",
-           "LTS_NODE_DOF", "LTS_NODE_P", "LTS_NODE_FPLUS", "LtsQoI"]
+           "LTS_NODE_DOF", "LTS_NODE_P", "LTS_NODE_FPLUS", "LTS_RULE_LF", "LtsQoI"]
 
 
 def _dp(a):
@@ -43,6 +43,14 @@ def graded_L_rule(n_base, layers=6, lo=-1.0, hi=1.0, blocks=(8, 8), qoi=(0.5, 0.
     return _lib.RectRule(kind=LTS_RULE_GRADED_L, lo=lo, hi=hi, n_base=n_base, box_lo=0.0, box_hi=0.0,
                          ref=1, layers=layers, nbx=blocks[0], nby=blocks[1], qx_lo=qoi[0],
                          qx_hi=qoi[1], qy_lo=qoi[2], qy_hi=qoi[3], p=p, nu=nu)
+
+
+def lf_rule(rule) -> _lib.RectRule:
+    """The standard leapfrog twin of a rule's level: same grid, no fine cells,
+    p = 1, nominal spacing h/p (see LTS_RULE_LF)."""
+    r = _lib.RectRule.from_buffer_copy(rule)
+    r.kind = rule.kind | LTS_RULE_LF
+    return r
 
 
 def sample_rule(n_blocks=16, sigma=0.25, pulse=(0.2, 0.4, 0.2, 0.4), width=0.05, T=1.0,

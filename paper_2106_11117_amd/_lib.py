@@ -15,7 +15,7 @@ LTS_OK, LTS_ERR_ARG, LTS_ERR_HIP, LTS_ERR_OOM, LTS_ERR_UNSTABLE, LTS_ERR_STATE =
 LTS_FP64, LTS_FP32_STEP = 0, 1
 LTS_PTR_HOST, LTS_PTR_DEVICE = 0, 1
 LTS_NODE_DOF, LTS_NODE_P, LTS_NODE_FPLUS = 1, 2, 4
-LTS_RULE_BOX, LTS_RULE_GRADED_L = 0, 1
+LTS_RULE_BOX, LTS_RULE_GRADED_L, LTS_RULE_LF = 0, 1, 0x100
 LTS_BATCH_GRAPH = 1
 LTS_MLMC_BATCHED, LTS_MLMC_PLAIN = 0, 1
 LTS_MAX_LEVELS = 8

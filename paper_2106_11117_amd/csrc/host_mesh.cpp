@@ -162,10 +162,12 @@ std::string build_rect_desc(const lts_rect_rule& r, std::vector<double>& x, std:
   if (!(r.hi > r.lo)) return "rule: hi must exceed lo";
   if (r.n_base < 2 || r.n_base > 8192) return "rule: n_base must be in 2..8192";
   if (r.nbx < 1 || r.nby < 1 || r.nbx * r.nby > 255) return "rule: block grid must have 1..255 blocks";
-  if (r.kind == LTS_RULE_BOX) {
+  const int kind = r.kind & ~LTS_RULE_LF;
+  const bool lf = (r.kind & LTS_RULE_LF) != 0;
+  if (kind == LTS_RULE_BOX) {
     if (r.ref < 1 || r.ref > 64) return "rule: ref must be in 1..64";
     x = axis_box(r.lo, r.hi, r.n_base, r.box_lo, r.box_hi, r.ref);
-  } else if (r.kind == LTS_RULE_GRADED_L) {
+  } else if (kind == LTS_RULE_GRADED_L) {
     if (r.layers < 1 || r.layers > 20) return "rule: layers must be in 1..20";
     if (!axis_graded(r.lo, r.hi, r.n_base, r.layers, x)) return "rule: graded axis needs 0 as an interior node";
   } else {
@@ -187,7 +189,7 @@ std::string build_rect_desc(const lts_rect_rule& r, std::vector<double>& x, std:
       const double hx = x[a + 1] - x[a], hy = y[b + 1] - y[b];
       const double mx = 0.5 * (x[a] + x[a + 1]);
       const double my = 0.5 * (y[b] + y[b + 1]);
-      if (r.kind == LTS_RULE_GRADED_L) active[c] = !(mx > 0.0 && my < 0.0);
+      if (kind == LTS_RULE_GRADED_L) active[c] = !(mx > 0.0 && my < 0.0);
       int bx = (int)std::floor((mx - r.lo) / (r.hi - r.lo) * r.nbx);
       int by = (int)std::floor((my - r.lo) / (r.hi - r.lo) * r.nby);
       bx = std::min(bx, r.nbx - 1);
@@ -197,6 +199,11 @@ std::string build_rect_desc(const lts_rect_rule& r, std::vector<double>& x, std:
       qoi[c] = (r.qx_lo <= mx && mx <= r.qx_hi && r.qy_lo <= my && my <= r.qy_hi);
     }
   p = r.p > 0 ? r.p : (int)std::ceil(h / hmin);
+  if (lf) {                                  // standard leapfrog twin: no fine cells, step dt/p
+    std::fill(fine.begin(), fine.end(), (uint8_t)0);
+    h /= p;
+    p = 1;
+  }
   n_blocks = r.nbx * r.nby;
   return "";
 }

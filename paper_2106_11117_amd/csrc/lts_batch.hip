@@ -47,6 +47,13 @@ std::map<uint64_t, TuneChoice>& tune_cache() {
 // rect mode where it fits and in compact mode; the six best-ranked of each mode
 // by region overhead (12 in all).
 lts_status autotune_level(lts_ctx c, DevLevel& lv) {
+  if (lv.H.n_F == 0) {                       // no fine tiles (e.g. a leapfrog twin): nothing to tune
+    lts_status r = default_tiling(c, lv);
+    if (r != LTS_OK) return r;
+    lv.tuned = true;
+    lv.tuned_ms = 0.0;
+    return LTS_OK;
+  }
   const uint64_t key = shape_key(lv.H);
   auto hit = tune_cache().find(key);
   std::vector<TilingHost> cands;

@@ -196,3 +196,39 @@ def test_adjoint_repeat_call_large_workspace(ctx):
     q2, g2 = ctx.backward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"], np.ones(40), K=64)
     assert np.array_equal(g1, g2) and np.array_equal(q1, q2)
     assert np.max(np.abs(g1)) < 1.0          # dQ/dg is O(|Q|) here, about 1e-2
+
+
+@pytest.mark.parametrize("graded", [False, True])
+def test_lf_twin_forward_matches_oracle(ctx, graded):
+    """The standard leapfrog baseline (the level's twin: P empty, p = 1, the
+    coarse sweep alone at dt/p, no fine tiles) against the oracle."""
+    rule = P.graded_L_rule(32) if graded else P.box_rule(32)
+    tw = mesh.lf_twin(mesh.graded_L_level(32) if graded else mesh.box_refined_level(32))
+    lid = ctx.add_rect_level(P.lf_rule(rule))
+    info = ctx.level_info(lid)
+    assert info["n_P"] == 0 and info["n_Fplus"] == 0 and info["p"] == 1 and info["h"] == tw.h
+    r = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), T=0.3) if graded \
+        else P.sample_rule(T=0.3)
+    s = P.gen_samples(0, 0, 0, 4, r, info["h"])
+    q = ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"])
+    ops = fem.operators(tw)
+    for k in range(2):
+        u = lts.Solver(ops, s["kappa"][k]).run(lts.pulse(ops, s["x0"][k]), s["dt"][k], int(s["n_steps"][k]))
+        sc = float(ops.qoi_w @ np.abs(u))
+        assert abs(q[k] - float(lts.qoi(ops, u))) <= 1e-11 * sc
+
+
+def test_mlmc_lf_baseline_matches_oracle(ctx):
+    """Algorithm 1 on the leapfrog twins of a three-level box-refined hierarchy:
+    the same L, N_l and estimate as the oracle's."""
+    T = 0.25
+    levels = [8, 16, 32]
+    ids = [ctx.add_rect_level(P.lf_rule(P.box_rule(nb))) for nb in levels]
+    res = ctx.mlmc(ids, P.sample_rule(T=T), eps=2e-4, seed=0, N_init=(16, 8, 4), L_start=2)
+    ops = [fem.operators(mesh.lf_twin(mesh.box_refined_level(nb))) for nb in levels]
+    ores = mlmc.mlmc(ops, rng.SampleRule(T=T), eps=2e-4, seed=0, N_init=(16, 8, 4))
+    assert res["L"] == ores.L and res["N"] == ores.N
+    scale = max(abs(m) for m in ores.mean)
+    assert abs(res["estimate"] - ores.estimate) <= 1e-11 * scale
+    for l in range(res["L"] + 1):
+        assert res["cost"][l] == ores.cost[l]

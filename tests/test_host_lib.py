@@ -101,6 +101,17 @@ def test_graded_L_level_bit_exact(n_base):
     _compare_level(P.graded_L_rule(n_base), mesh.graded_L_level(n_base))
 
 
+@pytest.mark.parametrize("graded", [False, True])
+def test_lf_twin_level_bit_exact(graded):
+    """The leapfrog twin rule (LTS_RULE_LF) builds the oracle's twin: no fine
+    cells, p = 1, spacing h/p, everything else as the LTS level."""
+    rule, lv = (P.graded_L_rule(64), mesh.graded_L_level(64)) if graded else (P.box_rule(32), mesh.box_refined_level(32))
+    tw = mesh.lf_twin(lv)
+    _compare_level(P.lf_rule(rule), tw)
+    d = P.rect_level_host(P.lf_rule(rule))
+    assert d["h"] == tw.h and d["n_P"] == 0 and d["n_Fplus"] == 0 and d["p"] == 1
+
+
 @pytest.mark.parametrize("p,nu", [(1, 0.0), (2, 0.01), (4, 0.01), (8, 0.01), (19, 0.3), (64, 0.01)])
 def test_cheb_constants_match_oracle(p, nu):
     lib = P.cheb_constants(p, nu, dt=0.0123)

@@ -373,6 +373,37 @@ def test_plain_leapfrog_unstable_at_lts_step():
     assert np.max(np.abs(u)) < 10 * np.max(np.abs(u0))
 
 
+@pytest.mark.parametrize("graded", [False, True])
+def test_lf_twin_is_plain_leapfrog_at_dt_over_p(graded):
+    """The standard leapfrog twin of a level (Sec. 3.4): the same grid with P
+    empty and p = 1. Its spacing h/p makes a sample take p times the steps of
+    the LTS level (up to the ceiling), LF-LTS on it is the plain leapfrog
+    scheme, and that step is stable: dt^2 lambda_max(M^-1 K(kappa)) < 4."""
+    lv = mesh.graded_L_level(32) if graded else mesh.box_refined_level(32)
+    tw = mesh.lf_twin(lv)
+    assert tw.p == 1 and not tw.Pmask.any() and tw.h == lv.h / lv.p
+    assert np.array_equal(tw.dof, lv.dof) and np.array_equal(tw.mass, lv.mass)
+    assert np.array_equal(tw.qoi_w, lv.qoi_w)
+    ops = fem.operators(tw)
+    assert not tw.Fplus.any()
+    rule = rng.SampleRule(n_blocks=64, sigma=0.3, pulse_box=(-0.8, -0.4, 0.4, 0.8), T=2.0) if graded \
+        else rng.SampleRule()
+    smp = rng.draw(0, 0, 1, rule)
+    n, dt = rng.steps_for(smp, rule, tw.h)
+    n0, _ = rng.steps_for(smp, rule, lv.h)
+    assert lv.p * (n0 - 1) < n <= lv.p * n0
+    s = lts.Solver(ops, smp.kappa)
+    u0 = lts.pulse(ops, smp.x0)
+    u1 = s.run(u0, dt, 300)
+    u2 = s.run_lf(u0, dt, 300)
+    assert np.max(np.abs(u1 - u2)) < 1e-11 * np.max(np.abs(u2))
+    K = fem.stiffness(fem.element_data(tw), smp.kappa)
+    sq = 1.0 / np.sqrt(ops.m)
+    S = (K.multiply(sq[:, None])).multiply(sq[None, :]).toarray()
+    lam = np.linalg.eigvalsh(0.5 * (S + S.T)).max()
+    assert dt * dt * lam < 4.0
+
+
 # ---------------------------------------------------------------------------
 # MLMC pieces
 # ---------------------------------------------------------------------------
