@@ -330,23 +330,29 @@ lts_status lts_level_arrays(lts_ctx c, int32_t level, double* x, double* y, uint
   return LTS_OK;
 }
 
-lts_status lts_rect_level_host(const lts_rect_rule* r, lts_level_info* info, double* x, double* y,
-                               uint8_t* flags, double* mass, double* qoi_w, int32_t* cell_block) {
-  if (!r || !info) return LTS_ERR_ARG;
+// The host level of a rule (no device involved); "" on success.
+static std::string host_level_of_rule(const lts_rect_rule& r, HostLevel& H) {
   std::vector<double> xs, ys;
   std::vector<uint8_t> act, fine, qoi;
   std::vector<int32_t> blk;
   double h = 0;
   int p = 0, nb = 0;
-  if (!build_rect_desc(*r, xs, ys, act, blk, fine, qoi, h, p, nb).empty()) return LTS_ERR_ARG;
+  std::string e = build_rect_desc(r, xs, ys, act, blk, fine, qoi, h, p, nb);
+  if (!e.empty()) return e;
   lts_grid_desc d{};
   d.nx_cells = (int32_t)xs.size() - 1;
   d.ny_cells = (int32_t)ys.size() - 1;
   d.x = xs.data(); d.y = ys.data();
   d.cell_active = act.data(); d.cell_block = blk.data(); d.cell_fine = fine.data(); d.cell_qoi = qoi.data();
-  d.n_blocks = nb; d.h = h; d.p = p; d.nu = r->nu;
+  d.n_blocks = nb; d.h = h; d.p = p; d.nu = r.nu;
+  return build_level_from_desc(d, H);
+}
+
+lts_status lts_rect_level_host(const lts_rect_rule* r, lts_level_info* info, double* x, double* y,
+                               uint8_t* flags, double* mass, double* qoi_w, int32_t* cell_block) {
+  if (!r || !info) return LTS_ERR_ARG;
   HostLevel H;
-  if (!build_level_from_desc(d, H).empty()) return LTS_ERR_ARG;
+  if (!host_level_of_rule(*r, H).empty()) return LTS_ERR_ARG;
   info->nx_nodes = H.nxn; info->ny_nodes = H.nyn; info->n_dof = H.n_dof; info->n_P = H.n_P;
   info->n_Fplus = H.n_F; info->p = H.p; info->n_blocks = H.n_blocks; info->h = H.h; info->nu = H.nu;
   info->delta = H.delta; info->omega = H.omega;
@@ -367,20 +373,9 @@ lts_status lts_tiling_host(const lts_rect_rule* r, int32_t tile_x, int32_t tile_
   const bool adaptive = tile_x == 0 && tile_y == 0 && rect == 0;
   if (!adaptive && (tile_x < 1 || tile_y < 1 || tile_x > 4096 || tile_y > 4096)) return LTS_ERR_ARG;
   if (rect != 0 && rect != 1) return LTS_ERR_ARG;
-  std::vector<double> xs, ys;
-  std::vector<uint8_t> act, fine, qoi;
-  std::vector<int32_t> blk;
-  double h = 0;
-  int p = 0, nb = 0;
-  if (!build_rect_desc(*r, xs, ys, act, blk, fine, qoi, h, p, nb).empty()) return LTS_ERR_ARG;
-  lts_grid_desc d{};
-  d.nx_cells = (int32_t)xs.size() - 1;
-  d.ny_cells = (int32_t)ys.size() - 1;
-  d.x = xs.data(); d.y = ys.data();
-  d.cell_active = act.data(); d.cell_block = blk.data(); d.cell_fine = fine.data(); d.cell_qoi = qoi.data();
-  d.n_blocks = nb; d.h = h; d.p = p; d.nu = r->nu;
   HostLevel H;
-  if (!build_level_from_desc(d, H).empty()) return LTS_ERR_ARG;
+  if (!host_level_of_rule(*r, H).empty()) return LTS_ERR_ARG;
+  const int p = H.p;
   const int ld = (H.nxn + kPitchAlign - 1) / kPitchAlign * kPitchAlign;
   // the origin lts_set_tiling would take
   TilingHost T;
