@@ -76,7 +76,7 @@ lts_status lts_destroy(lts_ctx ctx);
 const char* lts_last_error(lts_ctx ctx);
 
 /* ------------------------------------------------------------------------ */
-/* Levels (Sec. 3.2-3.4: the mesh hierarchy with local refinement)           */
+/* Levels (Sec. 3.2-3.5: the mesh hierarchy with local refinement)           */
 /* ------------------------------------------------------------------------ */
 
 /* One level's mesh.  Cells are [x_a, x_a+1] x [y_b, y_b+1], a = 0..nx_cells-1,
