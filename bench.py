@@ -13,6 +13,12 @@ QoI and the per-level moment reduction.  Inputs (per-sample coefficients,
 pulse centres, step counts) are resident in HBM before the timed region.
 
 Prints one JSON line (see the repository's benchmark contract).
+
+Other modes (one JSON line each): --mlmc (Algorithm 1, batched + graph against
+the plain form and the CPU oracle), --batch [--plain] (all five graded L-shape
+levels in shared launches), --lf (LF-LTS against the standard leapfrog
+baseline), --adjoint (discrete adjoint against the forward solve),
+--stream-check and --copy-check (HBM reference rates and counter calibration).
 """
 from __future__ import annotations
 
