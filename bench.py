@@ -197,7 +197,7 @@ def lf_bench():
     """Standard leapfrog baseline (the cost comparison of Sec. 3.4 and the MLMC
     comparisons of Sec. 4) on the graded L-shape hierarchy: every level against
     its leapfrog twin (the same grid with P empty, stepping at dt/p everywhere).
-    Per level, one batched forward of the survey's sample mix on each, whose wall
+    Per level, one batched forward of N_l = 4096, 1024, 256, 64, 16 samples on each, whose wall
     time ratio is the measured C_l^LF / C_l^LTS, beside the ratio of DOF updates;
     then Algorithm 1 on both hierarchies (batched + graph) at the MLMC eps."""
     import numpy as np
