@@ -41,7 +41,7 @@ HBM_PEAK_GBS = 8000.0
 # to the average launch's 1.7105e9 algorithmic bytes.  Valid only for the
 # step-kernel sources the counters were taken with.
 TRAFFIC = {"bytes_per_launch": 1.380 * 1.7105e9,
-           "sources_sha256": "984d044be9b7abf329be89d9f3d8f17904396b8a5e2833e63e54825c92795e66"}
+           "sources_sha256": "3daece7f70cd93fdaa6d3cb792fc063896d9220cee6f34c7fd87c1bb1fdc6188"}
 STEP_SOURCES = ("lts_fused.hip", "fused.h", "device.h", "lts_step.hip")
 WORKLOAD = ("unit square 512x512 base refined 8x in (0.48,0.52): 442225 DOFs, |P|=204081, p=8, "
             "nu=0.01, 256 samples, 4x4 blocks sigma=0.25, T=1, FP64")
@@ -340,6 +340,10 @@ def batch_bench(plain: bool):
     per_level = lambda **kw: np.concatenate([np.asarray(ctx.forward(j[0], *j[1:5], width=j[5], **kw))
                                              for j in jobs])
     t_level, q_level = median_time(per_level, 3)
+    ctx.batch_run(jobs, graph=True, precision=P.LTS_FP32_STEP)       # warm-up; captures the graph
+    t_f32, q_f32 = median_time(lambda: ctx.batch_run(jobs, graph=True, precision=P.LTS_FP32_STEP), 3)
+    q64 = np.asarray(q_graph)
+    rel32 = np.abs(np.asarray(q_f32) - q64) / np.max(np.abs(q64))
     out = {"metric": "batched multi-level LF-LTS throughput (form 2), graded L-shape hierarchy",
            "unit": "DOF-updates/s", "higher_is_better": True, "data": "synthetic (Philox seed 0)", "dtype": "f64",
            "config": {"workload": "graded L-shape, 5 levels h = 1/16..1/256, 6 graded layers (h_min = h/64, "
@@ -349,6 +353,9 @@ def batch_bench(plain: bool):
                              "hbm_frac_algorithmic": alg_bytes / t_graph / (HBM_PEAK_GBS * 1e9)},
            "batched_no_graph": {"s": t_batch, "dof_updates_per_s": dof_upd / t_batch},
            "one_forward_per_level": {"s": t_level, "dof_updates_per_s": dof_upd / t_level},
+           "batched_graph_fp32_step": {"s": t_f32, "dof_updates_per_s": dof_upd / t_f32,
+                                       "qoi_max_err_rel_to_max_abs_q": float(rel32.max()),
+                                       "qoi_median_err_rel_to_max_abs_q": float(np.median(rel32))},
            "q_equal": bool(np.array_equal(np.asarray(q_graph), np.asarray(q_batch)) and
                            np.array_equal(np.asarray(q_graph), q_level))}
     if plain:

@@ -288,13 +288,14 @@ typedef struct {
   int32_t q_offset;               /* Q of sample s of this job goes to Q_out[q_offset + s] */
 } lts_job;
 
-enum { LTS_BATCH_GRAPH = 1 };     /* capture the step loop into HIP graphs and replay */
+enum { LTS_BATCH_GRAPH = 1,      /* capture the step loop into HIP graphs and replay */
+       LTS_BATCH_FP32 = 2 };      /* FP32 stepping as LTS_FP32_STEP; QoI sums in FP64 */
 
 /* Advance all jobs of all levels in shared launches: every launch advances
  * one step of every job that still has steps left, so uneven mesh sizes and
  * step counts share the device.  Fine-tile shapes come from the context's
  * autotuner (tuned once per level shape and cached).  FP64.
- * flags: 0 or LTS_BATCH_GRAPH.  Errors as lts_forward. */
+ * flags: LTS_BATCH_GRAPH and/or LTS_BATCH_FP32.  Errors as lts_forward. */
 lts_status lts_batch_run(lts_ctx ctx, const lts_job* jobs, int32_t n_jobs, int32_t flags,
                          double* Q_out);
 

@@ -260,9 +260,9 @@ class Context:
                                              C.byref(ca.s), precision, qfp, qcp, dqp))
         return qf, qc, dq
 
-    def batch_run(self, jobs, graph=False):
+    def batch_run(self, jobs, graph=False, precision=LTS_FP64):
         """jobs: list of (level, kappa, x0, n_steps, dt, width).  Returns the Q of all
-        jobs concatenated in job order."""
+        jobs concatenated in job order.  precision LTS_FP32_STEP steps in binary32."""
         args, cjobs, off = [], [], 0
         for (level, kappa, x0, ns, dt, width) in jobs:
             sa = _SampleArgs(kappa, x0, ns, dt, width)
@@ -271,7 +271,8 @@ class Context:
             off += sa.n
         arr = (_lib.Job * len(cjobs))(*cjobs)
         q, qp = args[0].out(off)
-        self._c(self.lib.lts_batch_run(self.h, arr, len(cjobs), LTS_BATCH_GRAPH if graph else 0, qp))
+        flags = (LTS_BATCH_GRAPH if graph else 0) | (_lib.LTS_BATCH_FP32 if precision == LTS_FP32_STEP else 0)
+        self._c(self.lib.lts_batch_run(self.h, arr, len(cjobs), flags, qp))
         return q
 
     def backward(self, level, kappa, x0, n_steps, dt, dLdQ, width=0.05, K=64):

@@ -17,6 +17,7 @@ LTS_PTR_HOST, LTS_PTR_DEVICE = 0, 1
 LTS_NODE_DOF, LTS_NODE_P, LTS_NODE_FPLUS = 1, 2, 4
 LTS_RULE_BOX, LTS_RULE_GRADED_L, LTS_RULE_LF = 0, 1, 0x100
 LTS_BATCH_GRAPH = 1
+LTS_BATCH_FP32 = 2
 LTS_MLMC_BATCHED, LTS_MLMC_PLAIN = 0, 1
 LTS_MAX_LEVELS = 8
 

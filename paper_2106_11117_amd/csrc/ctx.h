@@ -188,8 +188,9 @@ lts_status autotune_level(lts_ctx c, DevLevel& lv);
 
 // One batched step launch over several jobs (see lts_fused.hip).
 struct StepArgs;
+// With fp32 the jobs' state buffers hold binary32 values.
 lts_status launch_multi_step(lts_ctx c, const StepArgs* d_jobs, const std::vector<const TilingDev*>& T,
-                             const std::vector<int>& active, int step, hipStream_t stream);
+                             const std::vector<int>& active, int step, hipStream_t stream, bool fp32 = false);
 // Writes the static step record of one job (step_args_size() bytes) to `out`.
 void job_record(const DevLevel& lv, const TilingDev& T, const double* d_kappa, const double* d_coef,
                 double* B0, double* B1, size_t sstride, void* out);

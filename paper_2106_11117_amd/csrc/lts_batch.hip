@@ -208,7 +208,9 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
   if (!c) return LTS_ERR_ARG;
   c->err.clear();
   if (!jobs || n_jobs < 1 || n_jobs > kMaxJobs) return arg_fail(c, "n_jobs must be in 1..32");
-  if (flags & ~LTS_BATCH_GRAPH) return arg_fail(c, "unknown flags");
+  if (flags & ~(LTS_BATCH_GRAPH | LTS_BATCH_FP32)) return arg_fail(c, "unknown flags");
+  const bool fp32 = (flags & LTS_BATCH_FP32) != 0;
+  const size_t es = fp32 ? sizeof(float) : sizeof(double);   // bytes per state value
   const int kind = jobs[0].samples.ptr_kind;
   int total = 0;
   for (int j = 0; j < n_jobs; ++j) {
@@ -237,7 +239,7 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
     o_c[j] = tab; tab += align256(S.coef.size() * 8);
     o_n[j] = tab; tab += align256(S.nsteps.size() * 4);
     o_x[j] = tab; tab += align256(S.x0.size() * 8);
-    o_s[j] = sts; sts += align256((size_t)S.n * lv.nodes * 8) * 2;
+    o_s[j] = sts; sts += align256((size_t)S.n * lv.nodes * es) * 2;
     o_q[j] = qb; qb += align256((size_t)S.n * 8);
   }
   LTS_HIP(c, c->b_tab.ensure(std::max<size_t>(tab, 256)));
@@ -261,7 +263,7 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
       maxT = std::max(maxT, S.nsteps[0]);
     }
     double* B0 = (double*)(sb + o_s[j]);
-    double* B1 = (double*)(sb + o_s[j] + align256((size_t)S.n * lv.nodes * 8));
+    double* B1 = (double*)(sb + o_s[j] + align256((size_t)S.n * lv.nodes * es));
     job_record(lv, lv.tiling, (const double*)(tb + o_k[j]), (const double*)(tb + o_c[j]), B0, B1, lv.nodes,
                recs.data() + j * step_args_size());
     T[j] = &lv.tiling;
@@ -275,8 +277,9 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
       const DevLevel& lv = *c->levels[jobs[j].level];
       if (st[j].n == 0) continue;
       double* B0 = (double*)(sb + o_s[j]);
-      double* B1 = (double*)(sb + o_s[j] + align256((size_t)st[j].n * lv.nodes * 8));
-      if ((rr = init_states(c, lv, st[j].n, (const double*)(tb + o_x[j]), jobs[j].samples.width, B0, B1)) != LTS_OK)
+      double* B1 = (double*)(sb + o_s[j] + align256((size_t)st[j].n * lv.nodes * es));
+      if ((rr = init_states(c, lv, st[j].n, (const double*)(tb + o_x[j]), jobs[j].samples.width, B0, B1, fp32)) !=
+          LTS_OK)
         return rr;
     }
     std::vector<int> act(n_jobs);
@@ -284,14 +287,16 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
     for (int t = 0; t < maxT; ++t) {
       for (int j = 0; j < n_jobs; ++j)
         while (act[j] > 0 && st[j].nsteps[act[j] - 1] <= t) --act[j];
-      if ((rr = launch_multi_step(c, (const StepArgs*)c->b_jobs.p, T, act, t, c->stream)) != LTS_OK) return rr;
+      if ((rr = launch_multi_step(c, (const StepArgs*)c->b_jobs.p, T, act, t, c->stream, fp32)) != LTS_OK)
+        return rr;
     }
     for (int j = 0; j < n_jobs; ++j) {
       const DevLevel& lv = *c->levels[jobs[j].level];
       if (st[j].n == 0) continue;
       double* B0 = (double*)(sb + o_s[j]);
-      double* B1 = (double*)(sb + o_s[j] + align256((size_t)st[j].n * lv.nodes * 8));
-      if ((rr = qoi_device(c, lv, st[j].n, (const int*)(tb + o_n[j]), B0, B1, (double*)(qbp + o_q[j]))) != LTS_OK)
+      double* B1 = (double*)(sb + o_s[j] + align256((size_t)st[j].n * lv.nodes * es));
+      if ((rr = qoi_device(c, lv, st[j].n, (const int*)(tb + o_n[j]), B0, B1, (double*)(qbp + o_q[j]), fp32)) !=
+          LTS_OK)
         return rr;
     }
     return LTS_OK;
@@ -310,7 +315,7 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
   }
   if (flags & LTS_BATCH_GRAPH) {
     // key: job shapes, step counts and every device address baked into the graph
-    std::vector<uint64_t> key = {(uint64_t)n_jobs, (uint64_t)(uintptr_t)tb, (uint64_t)(uintptr_t)sb,
+    std::vector<uint64_t> key = {(uint64_t)n_jobs, (uint64_t)fp32, (uint64_t)(uintptr_t)tb, (uint64_t)(uintptr_t)sb,
                                  (uint64_t)(uintptr_t)qbp, (uint64_t)(uintptr_t)c->b_jobs.p};
     for (int j = 0; j < n_jobs; ++j) {
       key.push_back((uint64_t)jobs[j].level);

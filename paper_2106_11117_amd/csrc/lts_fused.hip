@@ -262,6 +262,7 @@ __device__ __forceinline__ StepState job_state(const MultiArgs& m, const StepArg
   return StepState{odd ? a.B1 : a.B0, odd ? a.B0 : a.B1, m.step == 0};
 }
 
+template <class T>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_multi(MultiArgs m) {
   __shared__ double lk[256];
   int j, local, n;
@@ -270,7 +271,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_multi(MultiArgs m) {
   const int act = n / a.n_coarse;                      // active samples of the job
   int item, s;
   coarse_order(local, a.n_coarse, act, item, s);
-  coarse_body<double>(a, job_state(m, a), lk, s, item);
+  coarse_body<T>(a, job_state(m, a), lk, s, item);
 }
 
 // Compact mode.  The region's nodes (the F+ nodes within Manhattan distance p
@@ -653,10 +654,10 @@ __global__ __launch_bounds__(NT) void k_fine_small(StepArgs a) {
   fine_tile_compact<T, NT>(a, StepState{a.Ucur, a.Uold, a.startup}, lk, lq, s, Lid % a.n_fine);
 }
 
-template <bool RECT>
+template <bool RECT, class T>
 __global__ __launch_bounds__(kFineThreads) void k_fine_multi(MultiArgs m) {
-  __shared__ double lq[RECT ? kLdsSlots : kCompactSlots];
-  __shared__ double ls[RECT ? 4 * kFineThreads : 1];
+  __shared__ T lq[RECT ? kLdsSlots : kCompactSlots];
+  __shared__ T ls[RECT ? 4 * kFineThreads : 1];
   __shared__ double lk[256];
   int j, local, n;
   if (!multi_slot(m, j, local, n)) return;
@@ -664,23 +665,23 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_multi(MultiArgs m) {
   const StepState st = job_state(m, a);
   const int s = local / a.n_fine;
   if (RECT) {
-    fine_tile_rect<double>(a, st, lk, lq, ls, s, local % a.n_fine);
+    fine_tile_rect<T>(a, st, lk, lq, ls, s, local % a.n_fine);
   } else {
     load_kappa(a, s, lk);
-    fine_tile_compact<double, kFineThreads>(a, st, lk, lq, s, local % a.n_fine);
+    fine_tile_compact<T, kFineThreads>(a, st, lk, lq, s, local % a.n_fine);
   }
 }
 
-template <int NT>
+template <class T, int NT>
 __global__ __launch_bounds__(NT) void k_fine_small_multi(MultiArgs m) {
-  __shared__ double lq[2 * (NT * kNPT + 1)];
+  __shared__ T lq[2 * (NT * kNPT + 1)];
   __shared__ double lk[256];
   int j, local, n;
   if (!multi_slot(m, j, local, n)) return;
   const StepArgs a = job_record(m.jobs[j]);
   const int s = local / a.n_fine;
   load_kappa(a, s, lk);
-  fine_tile_compact<double, NT>(a, job_state(m, a), lk, lq, s, local % a.n_fine);
+  fine_tile_compact<T, NT>(a, job_state(m, a), lk, lq, s, local % a.n_fine);
 }
 
 }  // namespace
@@ -1091,7 +1092,7 @@ lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const 
 }
 
 lts_status launch_multi_step(lts_ctx c, const StepArgs* d_jobs, const std::vector<const TilingDev*>& T,
-                             const std::vector<int>& active, int step, hipStream_t stream) {
+                             const std::vector<int>& active, int step, hipStream_t stream, bool fp32) {
   const int nj = (int)T.size();
   if (nj > kMaxJobs) {
     c->err = "too many jobs in one batch";
@@ -1122,16 +1123,29 @@ lts_status launch_multi_step(lts_ctx c, const StepArgs* d_jobs, const std::vecto
     }
     if (m.chunk_off[nj] == 0) return;
     const dim3 grid((unsigned)(8 * m.chunk_off[nj]));
-    if (kind == 0)
-      k_coarse_multi<<<grid, dim3(kCoarseThreads), 0, stream>>>(m);
-    else if (kind == 1)
-      k_fine_multi<true><<<grid, dim3(kFineThreads), 0, stream>>>(m);
-    else if (kind == 2)
-      k_fine_multi<false><<<grid, dim3(kFineThreads), 0, stream>>>(m);
-    else if (kind == 3)
-      k_fine_small_multi<512><<<grid, dim3(512), 0, stream>>>(m);
-    else
-      k_fine_small_multi<256><<<grid, dim3(256), 0, stream>>>(m);
+    if (fp32) {
+      if (kind == 0)
+        k_coarse_multi<float><<<grid, dim3(kCoarseThreads), 0, stream>>>(m);
+      else if (kind == 1)
+        k_fine_multi<true, float><<<grid, dim3(kFineThreads), 0, stream>>>(m);
+      else if (kind == 2)
+        k_fine_multi<false, float><<<grid, dim3(kFineThreads), 0, stream>>>(m);
+      else if (kind == 3)
+        k_fine_small_multi<float, 512><<<grid, dim3(512), 0, stream>>>(m);
+      else
+        k_fine_small_multi<float, 256><<<grid, dim3(256), 0, stream>>>(m);
+    } else {
+      if (kind == 0)
+        k_coarse_multi<double><<<grid, dim3(kCoarseThreads), 0, stream>>>(m);
+      else if (kind == 1)
+        k_fine_multi<true, double><<<grid, dim3(kFineThreads), 0, stream>>>(m);
+      else if (kind == 2)
+        k_fine_multi<false, double><<<grid, dim3(kFineThreads), 0, stream>>>(m);
+      else if (kind == 3)
+        k_fine_small_multi<double, 512><<<grid, dim3(512), 0, stream>>>(m);
+      else
+        k_fine_small_multi<double, 256><<<grid, dim3(256), 0, stream>>>(m);
+    }
   };
   for (int kind = 0; kind < 5; ++kind) go(kind);
   return LTS_OK;

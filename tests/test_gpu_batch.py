@@ -140,3 +140,25 @@ def test_batch_argument_errors(ctx):
     bad[1] = (99,) + bad[1][1:]
     with pytest.raises(P.LtsError):
         ctx.batch_run(bad)
+
+
+def test_batch_fp32_stepping(ctx):
+    """FP32 stepping in the batched form (LTS_BATCH_FP32): the same QoIs, bit for
+    bit, as FP32 stepping of one solve per level (with and without the graph),
+    within the FP32 error bound of the FP64 QoIs, and measurably not FP64."""
+    jobs = _jobs(ctx)
+    q32 = ctx.batch_run(jobs, precision=P.LTS_FP32_STEP)
+    q32g = ctx.batch_run(jobs, graph=True, precision=P.LTS_FP32_STEP)
+    q64 = ctx.batch_run(jobs)
+    ql = np.concatenate([np.asarray(ctx.forward(j[0], *j[1:5], width=j[5], precision=P.LTS_FP32_STEP))
+                         for j in jobs])
+    assert np.array_equal(q32, ql) and np.array_equal(q32g, ql)
+    off = 0
+    for (lid, kap, x0, ns, dt, w) in jobs:
+        p = ctx.level_info(lid)["p"]
+        n = len(ns)
+        scale = np.max(np.abs(q64[off:off + n]))
+        err = np.abs(q32[off:off + n] - q64[off:off + n])
+        assert np.all(err <= 4 * ns * p * 2.0 ** -24 * scale)      # loose form of the derived bound
+        assert np.max(err) > 1e-12 * scale                             # binary32 really ran
+        off += n
