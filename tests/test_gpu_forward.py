@@ -331,3 +331,25 @@ def test_compact_workgroup_size_does_not_change_results(ctx, precision):
                                    precision=precision))
     assert np.array_equal(big[:k], small)
     assert np.isfinite(big).all()
+
+
+def test_compact_mode_beyond_rect_p128(ctx):
+    """p = 128 (seven graded layers), beyond what rect mode allows: compact
+    tiles against the oracle, the batched form bit for bit against one solve,
+    and rect mode refused."""
+    lid = ctx.add_rect_level(P.graded_L_rule(16, layers=7))
+    info = ctx.level_info(lid)
+    assert info["p"] == 128 and info["tile_rect"] == 0
+    with pytest.raises(P.LtsError):
+        ctx.set_tiling(lid, 16, 16, True)
+    ctx.autotune(lid)
+    lv = mesh.graded_L_level(16, layers=7)
+    ops = fem.operators(lv)
+    r = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), T=0.4)
+    s = P.gen_samples(3, 0, 0, 6, r, lv.h)
+    q = ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"])
+    qb = ctx.batch_run([(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"], 0.05)], graph=True)
+    assert np.array_equal(np.asarray(q), np.asarray(qb))
+    for k in range(2):
+        qo, sc = oracle_solve(ops, lv, s["kappa"][k], s["x0"][k], int(s["n_steps"][k]), s["dt"][k])
+        check(q[k], qo, sc)
