@@ -95,7 +95,7 @@ struct lts_ctx_s {
   std::string err;
   std::vector<std::unique_ptr<lts::DevLevel>> levels;
   // workspace
-  lts::DevBuf kappa, coef, nsteps, x0, Qd, st0, st1, wbuf, qa, qb, red, adj, adjscr, dldq, gout;
+  lts::DevBuf kappa, coef, nsteps, x0, Qd, st0, st1, wbuf, qa, qb, red, adj, adjscr, dldq, gout, adjlist;
   // batched form: per-job tables, states, job records, captured graph
   lts::DevBuf b_tab, b_states, b_jobs, b_Q;
   hipGraphExec_t graph = nullptr;

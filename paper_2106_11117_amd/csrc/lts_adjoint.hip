@@ -39,21 +39,31 @@ struct AdjArgs {
   const double* __restrict__ coef;   // [S][p+1]
   size_t sstride;
   int s_active;                      // samples 0..s_active-1 take part
+  const int* __restrict__ plist;     // grid index j * ld + i of every node of P
+  int np;
+  const double* __restrict__ rho;    // rho[m], m = 1..p: Lambda_m = rho_m Lambda_p off P
 };
 
-// w = A_u (I - P) y at every DOF.
+// The P node of this thread (1D grid over the P list, z = sample); false past the end.
+__device__ __forceinline__ bool p_node(const AdjArgs& a, int& i, int& j, size_t& k) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.np || (int)blockIdx.z >= a.s_active) return false;
+  k = (size_t)a.plist[t];
+  j = (int)(k / (size_t)a.L.ld);
+  i = (int)(k - (size_t)j * a.L.ld);
+  return true;
+}
+
+// w = A_u (I - P) y at the nodes of P (the only nodes whose increments the
+// backward step reads: the pairs contract P q_m, and A_u P q_m reads P nodes).
 __global__ __launch_bounds__(256) void k_adj_w(AdjArgs a, const double* __restrict__ Y,
                                                double* __restrict__ W) {
   const int s = blockIdx.z;
-  if (s >= a.s_active) return;
   const LevelView& L = a.L;
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
-  if (i >= L.nxn || j >= L.nyn) return;
-  const size_t k = (size_t)j * L.ld + i, so = (size_t)s * a.sstride;
-  if (!(L.flags[k] & F_DOF)) {
-    W[so + k] = 0.0;
-    return;
-  }
+  int i, j;
+  size_t k;
+  if (!p_node(a, i, j, k)) return;
+  const size_t so = (size_t)s * a.sstride;
   const double* __restrict__ y = Y + so;
   double cE, cW, cN, cS;
   edge_coefs(L, a.kappa + (size_t)s * L.nb, i, j, cE, cW, cN, cS);
@@ -63,21 +73,17 @@ __global__ __launch_bounds__(256) void k_adj_w(AdjArgs a, const double* __restri
                            cS * (vi - v(k - L.ld)));
 }
 
-// d_m+1 from d_m (Dc, NULL: 0), d_m-1 (Dp, NULL: 0), w, at every DOF (m = 0 .. p-1).
+// d_m+1 from d_m (Dc, NULL: 0), d_m-1 (Dp, NULL: 0), w, at the nodes of P (m = 0 .. p-1).
 __global__ __launch_bounds__(256) void k_adj_sub(AdjArgs a, int m, const double* __restrict__ Y,
                                                  const double* __restrict__ Dc,
                                                  const double* __restrict__ Dp,
                                                  const double* __restrict__ W, double* __restrict__ Dn) {
   const int s = blockIdx.z;
-  if (s >= a.s_active) return;
   const LevelView& L = a.L;
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
-  if (i >= L.nxn || j >= L.nyn) return;
-  const size_t k = (size_t)j * L.ld + i, so = (size_t)s * a.sstride;
-  if (!(L.flags[k] & F_DOF)) {
-    Dn[so + k] = 0.0;
-    return;
-  }
+  int i, j;
+  size_t k;
+  if (!p_node(a, i, j, k)) return;
+  const size_t so = (size_t)s * a.sstride;
   const double* __restrict__ y = Y + so;
   const double* __restrict__ dc = Dc ? Dc + so : nullptr;
   double cE, cW, cN, cS;
@@ -112,22 +118,19 @@ __global__ __launch_bounds__(256) void k_adj_lam_init(AdjArgs a, double f, const
   LW[so + k] = 0.0;
 }
 
-// Lambda_m from Lambda_m+1 (L1) and Lambda_m+2 (L2, NULL: 0), m = p-1 .. 1;
-// lw -= c2_m Lambda_m+1.  For m = 0 only lw -= c1 Lambda_1 (Lout unused).
+// Lambda_m from Lambda_m+1 (L1) and Lambda_m+2 (L2, NULL: 0), m = p-1 .. 1,
+// and lw -= c2_m Lambda_m+1, at the nodes of P; for m = 0 only lw -= c1
+// Lambda_1 (Lout unused).  Off P no stencil acts, so Lambda_m = rho_m Lambda_p
+// there (rho from the beta recursion alone) and the stencil reads it from Lp.
 __global__ __launch_bounds__(256) void k_adj_rev(AdjArgs a, int m, const double* __restrict__ L1,
                                                  const double* __restrict__ L2, double* __restrict__ Lout,
-                                                 double* __restrict__ LW) {
+                                                 double* __restrict__ LW, const double* __restrict__ Lp) {
   const int s = blockIdx.z;
-  if (s >= a.s_active) return;
   const LevelView& L = a.L;
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y;
-  if (i >= L.nxn || j >= L.nyn) return;
-  const size_t k = (size_t)j * L.ld + i, so = (size_t)s * a.sstride;
-  const uint8_t f = L.flags[k];
-  if (!(f & F_DOF)) {
-    if (m > 0) Lout[so + k] = 0.0;
-    return;
-  }
+  int i, j;
+  size_t k;
+  if (!p_node(a, i, j, k)) return;
+  const size_t so = (size_t)s * a.sstride;
   const double* cf = a.coef + (size_t)s * (L.p + 1);
   const double* __restrict__ l1 = L1 + so;
   const double lam = l1[k];
@@ -137,11 +140,15 @@ __global__ __launch_bounds__(256) void k_adj_rev(AdjArgs a, int m, const double*
   }
   const double c2 = cf[1 + m];
   LW[so + k] -= c2 * lam;
-  double kt = 0.0;   // (K (Lambda / m))_k at P rows
-  if (f & F_P) {
+  double kt;   // (K (Lambda / m))_k
+  {
     double cE, cW, cN, cS;
     edge_coefs(L, a.kappa + (size_t)s * L.nb, i, j, cE, cW, cN, cS);
-    auto t = [&](size_t kk) { return l1[kk] * L.invm[kk]; };   // invm = 0 on Dirichlet nodes
+    const double r1 = a.rho[m + 1];
+    const double* __restrict__ lp = Lp + so;
+    auto t = [&](size_t kk) {   // invm = 0 on Dirichlet nodes
+      return ((L.flags[kk] & F_P) ? l1[kk] : r1 * lp[kk]) * L.invm[kk];
+    };
     const double ti = t(k);
     kt = cE * (ti - t(k + 1)) + cW * (ti - t(k - 1)) + cN * (ti - t(k + L.ld)) + cS * (ti - t(k - L.ld));
   }
@@ -184,23 +191,35 @@ __global__ __launch_bounds__(256) void k_adj_contract(AdjArgs a, ContractArgs c,
     return gx * ((a0 - a1) * (b0 - b1) + (a2 - a3) * (b2 - b3)) +
            gy * ((a0 - a2) * (b0 - b2) + (a1 - a3) * (b1 - b3));
   };
+  // Lambda_m and lw are kept at the nodes of P only; off P, Lambda_m = rho_m
+  // Lambda_p and lw = gamma Lambda_p with gamma = -(c1 rho_1 + sum_m c2_m rho_m+1)
+  const double* __restrict__ lp = c.Lam[L.p] + so;
+  double gam = -cf[1] * a.rho[1];
+  for (int m = 1; m < L.p; ++m) gam -= cf[1 + m] * a.rho[m + 1];
   double acc = 0.0;
   // (lw, (I - P) y)
   {
     const double* lw = LW + so;
-    acc += side(lw[n00] * im00, lw[n10] * im10, lw[n01] * im01, lw[n11] * im11, p00 ? 0.0 : y00,
-                p10 ? 0.0 : y10, p01 ? 0.0 : y01, p11 ? 0.0 : y11);
+    auto lwv = [&](size_t n, bool pn) { return pn ? lw[n] : gam * lp[n]; };
+    acc += side(lwv(n00, p00) * im00, lwv(n10, p10) * im10, lwv(n01, p01) * im01, lwv(n11, p11) * im11,
+                p00 ? 0.0 : y00, p10 ? 0.0 : y10, p01 ? 0.0 : y01, p11 ? 0.0 : y11);
   }
-  // (-c1 Lambda_1, P y) and (-c2_m Lambda_m+1, P (y + d_m)), m = 1..p-1
-  for (int m = 0; m < L.p; ++m) {
-    const double cm = m == 0 ? cf[1] : cf[1 + m];
-    const double* la = c.Lam[m + 1] + so;
-    const double* dm = m == 0 ? nullptr : c.D[m] + so;
-    const double q00 = p00 ? y00 + (dm ? dm[n00] : 0.0) : 0.0;
-    const double q10 = p10 ? y10 + (dm ? dm[n10] : 0.0) : 0.0;
-    const double q01 = p01 ? y01 + (dm ? dm[n01] : 0.0) : 0.0;
-    const double q11 = p11 ? y11 + (dm ? dm[n11] : 0.0) : 0.0;
-    acc -= cm * side(la[n00] * im00, la[n10] * im10, la[n01] * im01, la[n11] * im11, q00, q10, q01, q11);
+  // (-c1 Lambda_1, P y) and (-c2_m Lambda_m+1, P (y + d_m)), m = 1..p-1: zero
+  // unless a corner is in P
+  if (p00 || p10 || p01 || p11) {
+    for (int m = 0; m < L.p; ++m) {
+      const double cm = m == 0 ? cf[1] : cf[1 + m];
+      const double rm = a.rho[m + 1];
+      const double* la = c.Lam[m + 1] + so;
+      auto lav = [&](size_t n, bool pn) { return pn ? la[n] : rm * lp[n]; };
+      const double* dm = m == 0 ? nullptr : c.D[m] + so;
+      const double q00 = p00 ? y00 + (dm ? dm[n00] : 0.0) : 0.0;
+      const double q10 = p10 ? y10 + (dm ? dm[n10] : 0.0) : 0.0;
+      const double q01 = p01 ? y01 + (dm ? dm[n01] : 0.0) : 0.0;
+      const double q11 = p11 ? y11 + (dm ? dm[n11] : 0.0) : 0.0;
+      acc -= cm * side(lav(n00, p00) * im00, lav(n10, p10) * im10, lav(n01, p01) * im01, lav(n11, p11) * im11,
+                       q00, q10, q01, q11);
+    }
   }
   G[so + kc] += acc;
 }
@@ -676,6 +695,29 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
   a.kappa = d_kappa;
   a.coef = d_coef;
   a.sstride = ss;
+  // the general backward step works on the nodes of P (list) and uses
+  // Lambda_m = rho_m Lambda_p elsewhere: rho_p = 1, rho_p+1 = 0,
+  // rho_m = (1 + beta_m) rho_m+1 - beta_m+1 rho_m+2 (beta_p := 0)
+  {
+    std::vector<int> pl;
+    for (int j = 0; j < lv.H.nyn; ++j)
+      for (int i = 0; i < lv.H.nxn; ++i)
+        if (lv.H.flags[(size_t)j * lv.H.nxn + i] & LTS_NODE_P) pl.push_back(j * lv.ld + i);
+    std::vector<double> rho((size_t)p + 2, 0.0);
+    rho[p] = 1.0;
+    for (int m = p - 1; m >= 1; --m)
+      rho[m] = (1.0 + lv.H.beta[m]) * rho[m + 1] - (m + 1 < p ? lv.H.beta[m + 1] : 0.0) * rho[m + 2];
+    LTS_HIP(c, c->adjlist.ensure(std::max<size_t>(pl.size() * sizeof(int) + rho.size() * sizeof(double) + 8, 16)));
+    double* d_rho = c->adjlist.as<double>();
+    int* d_pl = reinterpret_cast<int*>(d_rho + rho.size());
+    LTS_HIP(c, hipMemcpyAsync(d_rho, rho.data(), rho.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if (!pl.empty())
+      LTS_HIP(c, hipMemcpyAsync(d_pl, pl.data(), pl.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    LTS_HIP(c, hipStreamSynchronize(c->stream));   // host vectors end with this scope
+    a.rho = d_rho;
+    a.plist = d_pl;
+    a.np = (int)pl.size();
+  }
   const dim3 blk(BX, BY);
   auto grid = [&](int cols, int nz) { return dim3((cols + BX - 1) / BX, (Lv.nyn + BY - 1) / BY, nz); };
   // zero the whole workspace region used (cells of G, Lambda spare, ...)
@@ -775,17 +817,20 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
         }
         continue;
       }
-      // forward substeps of y
-      k_adj_w<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, y, arr(iw));
-      for (int m = 0; m < p; ++m)
-        k_adj_sub<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, m, y, m == 0 ? nullptr : arr(d0 + m - 1),
-                                                            m <= 1 ? nullptr : arr(d0 + m - 2), arr(iw),
-                                                            arr(d0 + m));
+      // forward substeps of y, at the nodes of P
+      const dim3 pgrid((unsigned)((a.np + 255) / 256), 1, (unsigned)act);
+      if (a.np > 0) {
+        k_adj_w<<<pgrid, 256, 0, c->stream>>>(a, y, arr(iw));
+        for (int m = 0; m < p; ++m)
+          k_adj_sub<<<pgrid, 256, 0, c->stream>>>(a, m, y, m == 0 ? nullptr : arr(d0 + m - 1),
+                                                   m <= 1 ? nullptr : arr(d0 + m - 2), arr(iw), arr(d0 + m));
+      }
       // reverse sweep
       k_adj_lam_init<<<grid(Lv.ld, act), blk, 0, c->stream>>>(a, f, mu1, arr(l0 + p - 1), arr(ilw));
-      for (int m = p - 1; m >= 0; --m)
-        k_adj_rev<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, m, arr(l0 + m), m + 1 < p ? arr(l0 + m + 1) : nullptr,
-                                                            m > 0 ? arr(l0 + m - 1) : nullptr, arr(ilw));
+      if (a.np > 0)
+        for (int m = p - 1; m >= 0; --m)
+          k_adj_rev<<<pgrid, 256, 0, c->stream>>>(a, m, arr(l0 + m), m + 1 < p ? arr(l0 + m + 1) : nullptr,
+                                                  m > 0 ? arr(l0 + m - 1) : nullptr, arr(ilw), arr(l0 + p - 1));
       k_adj_contract<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, ca, y, arr(ilw), arr(iG));
       // mu_n = 2 R mu_{n+1} - mu_{n+2}
       if (nn >= 1) {
