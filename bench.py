@@ -87,7 +87,14 @@ def cpu_baseline(steps_per_sample: int = 150):
     wall = time.perf_counter() - t0
     upd = sum(r[0] for r in res)
     busy = max(r[1] for r in res)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": upd / busy, "unit": "DOF-updates/s", "cores": procs, "kind": "oracle",
+            "host_cpu": model, "host_cpu_count": os.cpu_count(),
             "sample": f"samples 0..{procs - 1} of the same workload, first {steps_per_sample} coarse "
                       f"steps each (one process per core, scipy CSR, FP64); wall {wall:.1f} s incl. setup"}
 
