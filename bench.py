@@ -41,7 +41,7 @@ HBM_PEAK_GBS = 8000.0
 # to the average launch's 1.7105e9 algorithmic bytes.  Valid only for the
 # step-kernel sources the counters were taken with.
 TRAFFIC = {"bytes_per_launch": 1.380 * 1.7105e9,
-           "sources_sha256": "3daece7f70cd93fdaa6d3cb792fc063896d9220cee6f34c7fd87c1bb1fdc6188"}
+           "sources_sha256": "74a2597775bbc771b4f6ef8ab4ff7bcf50a7d8d62b79e695d5d4c98006a53a9f"}
 STEP_SOURCES = ("lts_fused.hip", "fused.h", "device.h", "lts_step.hip")
 WORKLOAD = ("unit square 512x512 base refined 8x in (0.48,0.52): 442225 DOFs, |P|=204081, p=8, "
             "nu=0.01, 256 samples, 4x4 blocks sigma=0.25, T=1, FP64")

@@ -16,18 +16,21 @@
 //    q and the scaled edge coefficients) in registers, east / west neighbours
 //    by DPP and only the rows at wavefront boundaries exchanged through LDS
 //    (double buffered, one barrier per substep).  Compact mode (regions that
-//    do not fit, e.g. large p) assigns lanes to the region's F+ nodes only and
-//    keeps them compacted in LDS with per-node neighbour indices.  Values near
-//    the region border are wrong after a few substeps (missing neighbours read
-//    0) but the error front moves one node per substep, so after p substeps
-//    the tile is exact; only its nodes are written back.
-// Coarse items and fine tiles are two kernels launched back to back on the
-// stream (they write disjoint nodes and only read u_n): the coarse kernel uses
-// no LDS beyond the sample's coefficient table, so it runs at high occupancy,
-// and each fine workgroup fills a CU's register file.  Workgroup ids are
-// remapped so that each of the 8 XCDs works through a contiguous range of
-// (sample, work item): halo rows and the shared level arrays stay in that
-// XCD's L2.
+//    do not fit, large p, or sparse F+) assigns lanes to the region's F+ nodes
+//    only and keeps them compacted in LDS with per-node neighbour slots; its
+//    tiles are rectangles of a uniform grid or of the adaptive bisection of
+//    F+, on 256-, 512- or 1024-thread workgroups (the fewest that hold the
+//    largest region; small ones only while a launch has workgroups to spare).
+//    Values near the region border are wrong after a few substeps (missing
+//    neighbours read 0) but the error front moves one node per substep, so
+//    after p substeps the tile is exact; only its nodes are written back.
+// Coarse items and fine tiles are separate kernels launched back to back on
+// the stream (they write disjoint nodes and only read u_n): the coarse kernel
+// uses no LDS beyond the sample's coefficient table, so it runs at high
+// occupancy, and a 1024-thread fine workgroup fills a CU's register file.
+// Workgroup ids are remapped so that each of the 8 XCDs works through a
+// contiguous range of (sample, work item) of a level (in a batched launch:
+// of every job): halo rows and the shared level arrays stay in that XCD's L2.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
