@@ -36,12 +36,12 @@ N_SAMPLES = 256
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per step launch (one k_coarse + one k_fine) from the FETCH_SIZE /
 # WRITE_SIZE counter runs, scaled by a plain copy kernel
-# (profiles/lts_step_kernels_C1_256samples_counters.md): counter bytes are 1.346x
+# (profiles/lts_step_kernels_C1_256samples_counters.md): counter bytes are 1.356x
 # the algorithmic bytes on the profiled launches (all samples active), applied
 # to the average launch's 1.7105e9 algorithmic bytes.  Valid only for the
 # step-kernel sources the counters were taken with.
-TRAFFIC = {"bytes_per_launch": 1.380 * 1.7105e9,
-           "sources_sha256": "74a2597775bbc771b4f6ef8ab4ff7bcf50a7d8d62b79e695d5d4c98006a53a9f"}
+TRAFFIC = {"bytes_per_launch": 1.356 * 1.7105e9,
+           "sources_sha256": "2d131e1700f8cd9ecfed30fe93d6529a6d68d5c6c0a795104f26e4ca11ecea46"}
 STEP_SOURCES = ("lts_fused.hip", "fused.h", "device.h", "lts_step.hip")
 WORKLOAD = ("unit square 512x512 base refined 8x in (0.48,0.52): 442225 DOFs, |P|=204081, p=8, "
             "nu=0.01, 256 samples, 4x4 blocks sigma=0.25, T=1, FP64")

@@ -20,7 +20,6 @@ constexpr int kBndRows = 2 * (kFineThreads / 64) + 2;   // rect mode: boundary r
 constexpr int kBndSlots = kBndRows * 64;                 // rect mode: slots of one buffer
 constexpr int kLdsSlots = 2 * kBndSlots > kRegionCap + 1 ? 2 * kBndSlots : kRegionCap + 1;
 constexpr int kCompactSlots = 2 * (kRegionCap + 1);   // compact mode: two q buffers with a zero slot
-constexpr int kCoarseGroup = 32;                    // samples per group in the coarse launch order
 constexpr int kCoarseThreads = 256;                 // coarse workgroup: one item, 4 rows per wavefront
 constexpr int kMaxAdjP = 64;                        // largest p supported by the adjoint
 constexpr int kMaxJobs = 32;                        // jobs of one batched launch

@@ -184,25 +184,22 @@ __device__ __forceinline__ void load_kappa(const StepArgs& a, int s, double* __r
   __syncthreads();
 }
 
-// Workgroup order over (item, sample): samples in groups of kCoarseGroup,
-// item-major inside a group, sample fastest.  Consecutive workgroups of an
-// XCD then share an item's mesh arrays in that XCD's L2 (kCoarseGroup times),
-// and the halo lines of neighbouring items of the same sample were loaded
-// shortly before (kCoarseGroup workgroups back horizontally, one item row of
-// groups vertically).
+// Workgroup order over (item, sample): the items are cut into 8 bands of
+// consecutive items (horizontal strips of the level, the last one ragged), and
+// each band is walked sample-major, items fastest.  A launch hands each XCD a
+// contiguous eighth of the order, so an XCD runs about one band: its workgroups
+// stream one sample's strip row after row (contiguous HBM lines), the band's
+// mesh arrays stay in that XCD's L2 for all samples, and the halo lines of an
+// item's neighbours were loaded shortly before (one workgroup back
+// horizontally, one item row vertically).  Every Lid < n_items * active maps to
+// a distinct (item, s).
 __device__ __forceinline__ void coarse_order(int Lid, int n_items, int active, int& item, int& s) {
-  const int full = active / kCoarseGroup;
-  const int span = n_items * kCoarseGroup;
-  if (Lid < full * span) {
-    const int g = Lid / span, rem = Lid - g * span;
-    item = rem / kCoarseGroup;
-    s = g * kCoarseGroup + rem % kCoarseGroup;
-  } else {
-    const int last = active - full * kCoarseGroup;   // ragged last group
-    const int rem = Lid - full * span;
-    item = rem / last;
-    s = full * kCoarseGroup + rem % last;
-  }
+  const int cb = (n_items + 7) / 8;                  // items per band
+  const int b = Lid / (cb * active);
+  const int nb = min(cb, n_items - b * cb);          // items in band b (>= 1)
+  const int rem = Lid - b * cb * active;
+  s = rem / nb;
+  item = b * cb + (rem - s * nb);
 }
 
 template <class T>
