@@ -41,7 +41,7 @@ HBM_PEAK_GBS = 8000.0
 # to the average launch's 1.7105e9 algorithmic bytes.  Valid only for the
 # step-kernel sources the counters were taken with.
 TRAFFIC = {"bytes_per_launch": 1.356 * 1.7105e9,
-           "sources_sha256": "2d131e1700f8cd9ecfed30fe93d6529a6d68d5c6c0a795104f26e4ca11ecea46"}
+           "sources_sha256": "24a94a3b6d1b1143802187c1078a9e3ea184aa0f7069a9cb7dfe2fce0c239659"}
 STEP_SOURCES = ("lts_fused.hip", "fused.h", "device.h", "lts_step.hip")
 WORKLOAD = ("unit square 512x512 base refined 8x in (0.48,0.52): 442225 DOFs, |P|=204081, p=8, "
             "nu=0.01, 256 samples, 4x4 blocks sigma=0.25, T=1, FP64")

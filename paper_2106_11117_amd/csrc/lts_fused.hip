@@ -31,6 +31,9 @@
 // Workgroup ids are remapped so that each of the 8 XCDs works through a
 // contiguous range of (sample, work item) of a level (in a batched launch:
 // of every job): halo rows and the shared level arrays stay in that XCD's L2.
+// For coarse items that range is about one horizontal band of the level's
+// items over all samples; for fine tiles, every tile of an eighth of the
+// samples.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
