@@ -92,16 +92,19 @@ class MLMCResult:
 
 
 def mlmc(ops_list, rule, eps: float, seed: int = 0, N_init=(256, 64, 16, 8, 4), alpha: float = 2.0,
-         L_start: int = 2, eval_dq=None):
+         L_start: int = 2, eval_dq=None, costs=None):
     """Algorithm 1 with eq. (optimal N_l) and the bias test against eps^2/2.
 
-    ``eval_dq(level, i) -> Delta Q`` may be supplied (defaults to the oracle solver)."""
+    ``eval_dq(level, i) -> Delta Q`` may be supplied (defaults to the oracle
+    solver), and so may the per-sample costs ``costs[l]`` = C_l (defaults to
+    the cost model on ``ops_list``; then ``ops_list`` may be any sequence
+    whose length is the number of levels)."""
     if eval_dq is None:
         def eval_dq(level, i):
             return delta_Q(ops_list, seed, level, i, rule)[2]
     Lmax = len(ops_list) - 1
     L = min(L_start, Lmax)
-    C = level_costs(ops_list, rule)
+    C = list(costs) if costs is not None else level_costs(ops_list, rule)
     N = [N_init[l] for l in range(L + 1)]
     dq = {l: [] for l in range(Lmax + 1)}
     grew = True

@@ -124,6 +124,33 @@ def test_mlmc_matches_oracle_algorithm(ctx):
     assert res["rmse"] ** 2 <= sum(v / n for v, n in zip(res["var"], res["N"])) + res["bias"] ** 2 + 1e-30
 
 
+def test_mlmc_level_growth_matches_oracle(ctx):
+    """Algorithm 1 started at L = 1 on a four-level box-refined hierarchy (16,
+    32, 64, 128 base cells, T = 0.4, eps = 5e-5): the bias test of eq.
+    (bias_est) fails at L = 1, so a level is added, and passes at L = 2 below
+    the top level.  GPU and oracle must take the same path: the same L, N_l,
+    bias, estimate and per-level moments."""
+    T, eps = 0.4, 5e-5
+    levels = [16, 32, 64, 128]
+    ids = [ctx.add_rect_level(P.box_rule(nb)) for nb in levels]
+    res = ctx.mlmc(ids, P.sample_rule(T=T), eps=eps, seed=0, N_init=(32, 16, 8, 4), L_start=1)
+    ops = [fem.operators(mesh.box_refined_level(nb)) for nb in levels]
+    ores = mlmc.mlmc(ops, rng.SampleRule(T=T), eps=eps, seed=0, N_init=(32, 16, 8, 4), L_start=1)
+    print(f"GPU L={res['L']} N={res['N']} bias={res['bias']:.6e}; oracle L={ores.L} N={ores.N} "
+          f"bias={ores.bias:.6e}", flush=True)
+    assert ores.L == 2 and res["L"] == 2
+    assert res["N"] == ores.N
+    scale = max(abs(m) for m in ores.mean)
+    assert abs(res["bias"] - ores.bias) <= 1e-11 * scale
+    assert abs(res["estimate"] - ores.estimate) <= 1e-11 * scale
+    for l in range(3):
+        assert abs(res["mean"][l] - ores.mean[l]) <= 1e-11 * scale
+        assert abs(res["var"][l] - ores.var[l]) <= 1e-9 * ores.var[l]
+        assert res["cost"][l] == ores.cost[l]
+    assert abs(res["rmse"] - ores.rmse) <= 1e-9 * ores.rmse
+    assert res["converged"]
+
+
 def test_mlmc_plain_equals_batched(ctx):
     T = 0.2
     ids = [ctx.add_rect_level(P.box_rule(nb)) for nb in (8, 16)]
