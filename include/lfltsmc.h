@@ -18,8 +18,9 @@
  *  - Every function returns lts_status: LTS_OK (0) or a negative code.  No
  *    function throws, aborts or exits.  After an error, lts_last_error(ctx)
  *    describes it (ctx-owned string, valid until the next call on ctx).
- *  - Arguments are validated on the host before any device work is queued;
- *    an LTS_ERR_ARG return leaves the context and every output untouched.
+ *  - Arguments are validated before any time step is launched (host arrays
+ *    on the host; device sample arrays by a checking gather kernel, see
+ *    lts_samples); an LTS_ERR_ARG return leaves every output untouched.
  *  - Caller arrays are only read during the call (meshes are copied in).
  *    Output arrays are caller-allocated.  The context owns all device
  *    workspace (level data, states, checkpoints, captured graphs).
@@ -244,14 +245,29 @@ lts_status lts_philox4x64_10(const uint64_t* ctr, const uint64_t* key, uint64_t*
 /* Forward solves (Algorithm 2 per sample, QoI at T)                         */
 /* ------------------------------------------------------------------------ */
 
+/* One batch of samples.  The coefficient is given either as kappa = c^2 or,
+ * with kappa NULL, as g = log c (Sec. 2.1: c = exp(g) with g piecewise
+ * constant on the blocks), in which case the library forms kappa = exp(2 g)
+ * on the device.
+ * Device arrays (LTS_PTR_DEVICE) are read on the device: kappa or g and x0 are
+ * gathered into the library's sorted order by a kernel that also checks them
+ * (an invalid value gives LTS_ERR_ARG before any time step is launched, the
+ * outputs untouched); only n_steps and dt are copied to the host, because the
+ * launch schedule (which samples still run at each step) and the per-sample
+ * step coefficients (a_p from an extended-precision recurrence) are planned
+ * there.  Device outputs are written by kernels on the context stream.  The
+ * inputs must be complete when the call is made: work on another stream that
+ * writes them must have finished or be ordered before the context stream
+ * (the Python binding waits for the caller's current torch stream). */
 typedef struct {
   int32_t n;                      /* number of samples, >= 0 */
   int32_t ptr_kind;               /* LTS_PTR_HOST or LTS_PTR_DEVICE for the arrays below */
-  const double* kappa;            /* [n][n_blocks of the level], > 0 */
-  const double* x0;               /* [n][2] pulse centres */
+  const double* kappa;            /* [n][n_blocks of the level], finite and > 0; or NULL (then g) */
+  const double* x0;               /* [n][2] pulse centres, finite */
   const int32_t* n_steps;         /* [n], >= 1 */
-  const double* dt;               /* [n], > 0 */
+  const double* dt;               /* [n], finite and > 0 */
   double width;                   /* pulse width, > 0 */
+  const double* g;                /* [n][n_blocks], finite; read only when kappa is NULL */
 } lts_samples;
 
 /* Solve every sample on `level` from t = 0 to n_steps*dt with stabilized

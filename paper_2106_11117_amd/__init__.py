@@ -135,27 +135,38 @@ def _is_torch(a):
     return type(a).__module__.startswith("torch")
 
 
-class _SampleArgs:
-    """Marshals kappa/x0/n_steps/dt (numpy -> host, torch cuda -> device)."""
+def _wait_caller_stream(t):
+    """Device inputs are read on the library's stream: wait for the work the
+    caller queued on torch's current stream (which produced them) first."""
+    import torch
+    torch.cuda.current_stream(t.device).synchronize()
 
-    def __init__(self, kappa, x0, n_steps, dt, width):
-        self.dev = _is_torch(kappa)
+
+class _SampleArgs:
+    """Marshals kappa (or g = log c when kappa is None) / x0 / n_steps / dt
+    (numpy -> host, torch cuda -> device)."""
+
+    def __init__(self, kappa, x0, n_steps, dt, width, g=None):
+        coef = kappa if kappa is not None else g
+        self.dev = _is_torch(coef)
         if self.dev:
             import torch
-            self.keep = [kappa.contiguous().to(torch.float64), x0.contiguous().to(torch.float64),
+            self.keep = [coef.contiguous().to(torch.float64), x0.contiguous().to(torch.float64),
                          n_steps.contiguous().to(torch.int32), dt.contiguous().to(torch.float64)]
             ptrs = [t.data_ptr() for t in self.keep]
             n = int(self.keep[3].numel())
+            _wait_caller_stream(self.keep[0])
         else:
-            self.keep = [np.ascontiguousarray(kappa, dtype=np.float64),
+            self.keep = [np.ascontiguousarray(coef, dtype=np.float64),
                          np.ascontiguousarray(x0, dtype=np.float64),
                          np.ascontiguousarray(n_steps, dtype=np.int32),
                          np.ascontiguousarray(dt, dtype=np.float64)]
             ptrs = [a.ctypes.data for a in self.keep]
             n = int(self.keep[3].size)
         self.n = n
+        kp, gp = (ptrs[0], None) if kappa is not None else (None, ptrs[0])
         self.s = _lib.Samples(n=n, ptr_kind=LTS_PTR_DEVICE if self.dev else LTS_PTR_HOST,
-                              kappa=ptrs[0], x0=ptrs[1], n_steps=ptrs[2], dt=ptrs[3], width=width)
+                              kappa=kp, x0=ptrs[1], n_steps=ptrs[2], dt=ptrs[3], width=width, g=gp)
 
     def out(self, count=None):
         count = self.n if count is None else count
@@ -242,8 +253,9 @@ class Context:
         return {"x": x, "y": y, "flags": flags, "mass": mass, "qoi_w": qw, "cell_block": cb}
 
     # --- solves -----------------------------------------------------------
-    def forward(self, level, kappa, x0, n_steps, dt, width=0.05, precision=LTS_FP64, plain=False):
-        sa = _SampleArgs(kappa, x0, n_steps, dt, width)
+    def forward(self, level, kappa, x0, n_steps, dt, width=0.05, precision=LTS_FP64, plain=False, g=None):
+        """Q of every sample; the coefficient is kappa = c^2, or g = log c with kappa=None."""
+        sa = _SampleArgs(kappa, x0, n_steps, dt, width, g)
         q, qp = sa.out()
         fn = self.lib.lts_forward_plain if plain else self.lib.lts_forward
         self._c(fn(self.h, level, C.byref(sa.s), precision, qp))
@@ -275,8 +287,9 @@ class Context:
         self._c(self.lib.lts_batch_run(self.h, arr, len(cjobs), flags, qp))
         return q
 
-    def backward(self, level, kappa, x0, n_steps, dt, dLdQ, width=0.05, K=64):
-        sa = _SampleArgs(kappa, x0, n_steps, dt, width)
+    def backward(self, level, kappa, x0, n_steps, dt, dLdQ, width=0.05, K=64, g=None):
+        """(Q, dL/dg) with L = sum_s dLdQ[s] Q_s; coefficient as in forward()."""
+        sa = _SampleArgs(kappa, x0, n_steps, dt, width, g)
         nb = self.level_info(level)["n_blocks"]
         q, qp = sa.out()
         if sa.dev:
@@ -285,6 +298,7 @@ class Context:
             gp = g.data_ptr()
             dl = dLdQ.contiguous().to(torch.float64)
             dlp = dl.data_ptr()
+            _wait_caller_stream(dl)
         else:
             g = np.zeros((sa.n, nb))
             gp = g.ctypes.data
@@ -297,6 +311,7 @@ class Context:
         out = np.zeros(3)
         if _is_torch(x):
             xt = x.contiguous().to(dtype=x.new_empty(0).double().dtype)
+            _wait_caller_stream(xt)
             self._c(self.lib.lts_moments(self.h, xt.data_ptr(), xt.numel(), LTS_PTR_DEVICE, _dp(out)))
         else:
             xa = np.ascontiguousarray(x, dtype=np.float64)
@@ -343,25 +358,26 @@ def _make_autograd():
     class LtsQoI(torch.autograd.Function):
         """Q[s] of the LF-LTS solves as a differentiable function of the block
         log-wave-speeds g[s, b] (kappa = c^2 = exp(2 g)).  Forward runs
-        lts_forward; backward runs the discrete adjoint lts_backward with the
-        incoming gradient as dL/dQ, returning dL/dg at fixed step counts and dt.
+        lts_forward (the library forms kappa = exp(2 g) on the device); backward
+        runs the discrete adjoint lts_backward with the incoming gradient as
+        dL/dQ, returning dL/dg at fixed step counts and dt.
 
         apply(g, ctx, level, x0, n_steps, dt, width=0.05, K=64): g float64 on the
         context's device, x0 [S, 2], n_steps [S] int32, dt [S] on the same device."""
 
         @staticmethod
         def forward(fctx, g, lctx, level, x0, n_steps, dt, width=0.05, K=64):
-            kappa = torch.exp(2.0 * g.detach())
-            q = lctx.forward(level, kappa, x0, n_steps, dt, width)
-            fctx.save_for_backward(kappa, x0, n_steps, dt)
+            gd = g.detach()
+            q = lctx.forward(level, None, x0, n_steps, dt, width, g=gd)
+            fctx.save_for_backward(gd, x0, n_steps, dt)
             fctx.lctx, fctx.level, fctx.width, fctx.K = lctx, level, width, K
             return q
 
         @staticmethod
         def backward(fctx, gq):
-            kappa, x0, n_steps, dt = fctx.saved_tensors
-            _, dg = fctx.lctx.backward(fctx.level, kappa, x0, n_steps, dt, gq.contiguous(), fctx.width,
-                                       fctx.K)
+            g, x0, n_steps, dt = fctx.saved_tensors
+            _, dg = fctx.lctx.backward(fctx.level, None, x0, n_steps, dt, gq.contiguous(), fctx.width, fctx.K,
+                                       g=g)
             return dg, None, None, None, None, None, None, None
 
     return LtsQoI

@@ -67,7 +67,7 @@ class SampleRule(C.Structure):
 
 class Samples(C.Structure):
     _fields_ = [("n", C.c_int32), ("ptr_kind", C.c_int32), ("kappa", C.c_void_p), ("x0", C.c_void_p),
-                ("n_steps", C.c_void_p), ("dt", C.c_void_p), ("width", C.c_double)]
+                ("n_steps", C.c_void_p), ("dt", C.c_void_p), ("width", C.c_double), ("g", C.c_void_p)]
 
 
 class Job(C.Structure):

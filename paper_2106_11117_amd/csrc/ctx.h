@@ -95,7 +95,7 @@ struct lts_ctx_s {
   std::string err;
   std::vector<std::unique_ptr<lts::DevLevel>> levels;
   // workspace
-  lts::DevBuf kappa, coef, nsteps, x0, Qd, st0, st1, wbuf, qa, qb, red, adj, adjscr, dldq, gout, adjlist;
+  lts::DevBuf kappa, coef, nsteps, x0, Qd, perm, flag, st0, st1, wbuf, qa, qb, red, adj, adjscr, dldq, gout, adjlist;
   // batched form: per-job tables, states, job records, captured graph
   lts::DevBuf b_tab, b_states, b_jobs, b_Q;
   hipGraphExec_t graph = nullptr;
@@ -124,16 +124,43 @@ inline lts_status arg_fail(lts_ctx c, const std::string& m) {
   return LTS_ERR_ARG;
 }
 
-// Host copies of a sample batch (validated, sorted by decreasing n_steps) plus
-// the per-sample step coefficient tables.
+// A sample batch staged for the device.  The host keeps what plans the
+// launches: the step counts and steps dt, sorted by decreasing step count
+// (stable), the permutation (sorted position -> caller index) and the
+// per-sample step coefficients (formed on the host: a_p comes from an
+// extended-precision recurrence).  For host arrays it also keeps sorted copies
+// of kappa (or g) and x0; device arrays are gathered on the device.
 struct Staged {
   int n = 0;
-  std::vector<double> kappa, x0, dt, coef;
+  int ptr_kind = LTS_PTR_HOST;
+  bool g_mode = false;                 // the caller passed g = log c, kappa = exp(2 g) on the device
+  std::vector<double> kappa, x0;       // host path only (kappa holds g in g_mode)
+  std::vector<double> dt, coef;
   std::vector<int> nsteps;
-  std::vector<int> perm;   // sorted position -> caller index
+  std::vector<int> perm;               // sorted position -> caller index
+};
+// Device destinations of a staged batch (sorted order) and the device scratch
+// the staging uses (perm: n ints; flag: one int).
+struct StagedDev {
+  double* kappa;   // [n][nb]
+  double* x0;      // [n][2]
+  double* coef;    // [n][p+1]
+  int* nsteps;     // [n]
+  int* perm;       // [n]
+  int* flag;       // [1]
 };
 lts_status stage_samples(lts_ctx c, const DevLevel& lv, const lts_samples* S, Staged& st);
-lts_status upload_staged(lts_ctx c, const Staged& st);
+// Writes the staged batch to `d` on the context stream; device kappa / g / x0
+// are gathered there by a kernel that also checks them (LTS_ERR_ARG if a value
+// is invalid; no step has been launched then).
+lts_status upload_staged(lts_ctx c, const DevLevel& lv, const Staged& st, const lts_samples* S,
+                         const StagedDev& d);
+// The context's own staging buffers for n samples (allocates on demand).
+lts_status ctx_staging(lts_ctx c, const DevLevel& lv, int n, StagedDev& d);
+// Q of the sorted batch at d_Q into the caller's Q_out (ptr_kind of the
+// batch): device outputs are scattered by a kernel, host outputs unpermuted on
+// the host.  LTS_ERR_UNSTABLE if a QoI is not finite.
+lts_status finish_Q(lts_ctx c, const Staged& st, const double* d_Q, const StagedDev& d, double* Q_out);
 
 // Forward solve of `n` samples on level `lv` (device arrays already staged):
 // implemented in the step source.
@@ -142,6 +169,14 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
                           const double* d_coef, const int* d_nsteps, const double* d_x0,
                           double width, const std::vector<int>& h_nsteps, int precision,
                           bool per_sample, double* d_Q);
+
+// The same solve on caller-provided state buffers B0, B1 (n * lv.nodes values
+// each, binary64 or, under LTS_FP32_STEP, binary32); allocates nothing on the
+// device (HIP events only when `timing`).
+lts_status forward_device_states(lts_ctx c, const DevLevel& lv, int n, const double* d_kappa,
+                                 const double* d_coef, const int* d_nsteps, const double* d_x0, double width,
+                                 const std::vector<int>& h_nsteps, int precision, bool per_sample, double* d_Q,
+                                 double* B0, double* B1, bool timing);
 
 lts_status moments_device(lts_ctx c, const double* d_x, int n, double* d_out3);
 

@@ -13,7 +13,102 @@ using namespace lts;
 
 namespace lts {
 
-// Host copies of a sample batch (validated) plus the per-sample step tables.
+namespace {
+
+// Sorted copies of a device batch: row t of the outputs is caller sample
+// perm[t].  kappa = exp(2 g) when the caller passed g (kappa NULL).  Invalid
+// values set bit 1 (coefficient) or bit 2 (pulse centre) of *bad.
+__global__ __launch_bounds__(256) void k_gather_samples(const double* __restrict__ kappa,
+                                                        const double* __restrict__ g,
+                                                        const double* __restrict__ x0,
+                                                        const int* __restrict__ perm, int n, int nb,
+                                                        double* __restrict__ kout, double* __restrict__ xout,
+                                                        int* __restrict__ bad) {
+  const long long tot = (long long)n * (nb + 2);
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int t = (int)(e / (nb + 2)), b = (int)(e - (long long)t * (nb + 2));
+    const size_t s = (size_t)perm[t];
+    if (b < nb) {
+      const double k = kappa ? kappa[s * nb + b] : exp(2.0 * g[s * nb + b]);
+      if (!(k > 0.0) || !isfinite(k)) atomicOr(bad, 1);
+      kout[(size_t)t * nb + b] = k;
+    } else {
+      const double v = x0[2 * s + (b - nb)];
+      if (!isfinite(v)) atomicOr(bad, 2);
+      xout[2 * (size_t)t + (b - nb)] = v;
+    }
+  }
+}
+
+// kappa = exp(2 g) in place (host batches given as g, already sorted).
+__global__ __launch_bounds__(256) void k_exp2(double* __restrict__ v, long long n, int* __restrict__ bad) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    const double k = exp(2.0 * v[e]);
+    if (!(k > 0.0) || !isfinite(k)) atomicOr(bad, 1);
+    v[e] = k;
+  }
+}
+
+// out[perm[t]] = Q[t]; bit 1 of *bad for a non-finite value.
+__global__ __launch_bounds__(256) void k_scatter_q(const double* __restrict__ Q, const int* __restrict__ perm, int n,
+                                                   double* __restrict__ out, int* __restrict__ bad) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double q = Q[t];
+  out[perm[t]] = q;
+  if (!isfinite(q)) atomicOr(bad, 1);
+}
+
+// out[perm[t]][b] = rows[t][b]; bit 1 of *bad for a non-finite value.
+__global__ __launch_bounds__(256) void k_scatter_rows(const double* __restrict__ rows, const int* __restrict__ perm,
+                                                      int n, int nb, double* __restrict__ out, int* __restrict__ bad) {
+  const long long tot = (long long)n * nb;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    const int t = (int)(e / nb), b = (int)(e - (long long)t * nb);
+    const double v = rows[e];
+    out[(size_t)perm[t] * nb + b] = v;
+    if (!isfinite(v)) atomicOr(bad, 1);
+  }
+}
+
+// out[t] = x[perm[t]].
+__global__ __launch_bounds__(256) void k_gather_vec(const double* __restrict__ x, const int* __restrict__ perm, int n,
+                                                    double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) out[t] = x[perm[t]];
+}
+
+// d = a - b (the coupled difference of Sec. 2.2), optionally copying a and b.
+__global__ __launch_bounds__(256) void k_coupled_diff(const double* __restrict__ a, const double* __restrict__ b, int n,
+                                                      double* __restrict__ qa, double* __restrict__ qb,
+                                                      double* __restrict__ d) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  if (qa) qa[t] = a[t];
+  if (qb) qb[t] = b[t];
+  if (d) d[t] = a[t] - b[t];
+}
+
+__global__ void k_zero_flag(int* __restrict__ f) { *f = 0; }
+
+int grid_for(long long work) { return (int)std::max(1LL, std::min((work + 255) / 256, 4096LL)); }
+
+}  // namespace
+
+// Reads a value of a possibly device-resident caller array to the host on
+// the context stream.
+static lts_status read_in(lts_ctx c, void* dst, const void* src, size_t bytes, int ptr_kind) {
+  if (bytes == 0) return LTS_OK;
+  if (ptr_kind == LTS_PTR_DEVICE) {
+    LTS_HIP(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c->stream));
+    LTS_HIP(c, hipStreamSynchronize(c->stream));
+  } else {
+    std::memcpy(dst, src, bytes);
+  }
+  return LTS_OK;
+}
+
 lts_status stage_samples(lts_ctx c, const DevLevel& lv, const lts_samples* S, Staged& st) {
   if (!S) return arg_fail(c, "samples is NULL");
   if (S->n < 0) return arg_fail(c, "samples.n must be >= 0");
@@ -21,66 +116,127 @@ lts_status stage_samples(lts_ctx c, const DevLevel& lv, const lts_samples* S, St
     return arg_fail(c, "samples.ptr_kind must be LTS_PTR_HOST or LTS_PTR_DEVICE");
   if (!(S->width > 0.0) || !std::isfinite(S->width)) return arg_fail(c, "samples.width must be > 0");
   const int n = S->n, nb = lv.H.n_blocks, p = lv.H.p;
+  st = Staged();
   st.n = n;
-  st.kappa.resize((size_t)n * nb);
-  st.x0.resize((size_t)n * 2);
-  st.dt.resize(n);
-  st.nsteps.resize(n);
-  if (n > 0) {
-    if (!S->kappa || !S->x0 || !S->n_steps || !S->dt) return arg_fail(c, "NULL sample array");
-    const hipMemcpyKind k = S->ptr_kind == LTS_PTR_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
-    LTS_HIP(c, hipMemcpy(st.kappa.data(), S->kappa, st.kappa.size() * 8, k));
-    LTS_HIP(c, hipMemcpy(st.x0.data(), S->x0, st.x0.size() * 8, k));
-    LTS_HIP(c, hipMemcpy(st.dt.data(), S->dt, st.dt.size() * 8, k));
-    LTS_HIP(c, hipMemcpy(st.nsteps.data(), S->n_steps, st.nsteps.size() * 4, k));
-  }
+  st.ptr_kind = S->ptr_kind;
+  st.g_mode = S->kappa == nullptr;
+  if (n == 0) return LTS_OK;
+  if ((!S->kappa && !S->g) || !S->x0 || !S->n_steps || !S->dt) return arg_fail(c, "NULL sample array");
+  LTS_HIP(c, hipSetDevice(c->device));
+  std::vector<double> dt(n);
+  std::vector<int> ns(n);
+  lts_status r;
+  if ((r = read_in(c, ns.data(), S->n_steps, (size_t)n * 4, S->ptr_kind)) != LTS_OK) return r;
+  if ((r = read_in(c, dt.data(), S->dt, (size_t)n * 8, S->ptr_kind)) != LTS_OK) return r;
   for (int s = 0; s < n; ++s) {
-    if (!(st.dt[s] > 0.0) || !std::isfinite(st.dt[s])) return arg_fail(c, "dt must be finite and > 0");
-    if (st.nsteps[s] < 1) return arg_fail(c, "n_steps must be >= 1");
-    if (!std::isfinite(st.x0[2 * s]) || !std::isfinite(st.x0[2 * s + 1])) return arg_fail(c, "x0 must be finite");
-    for (int b = 0; b < nb; ++b) {
-      const double k = st.kappa[(size_t)s * nb + b];
-      if (!(k > 0.0) || !std::isfinite(k)) return arg_fail(c, "kappa must be finite and > 0");
-    }
+    if (!(dt[s] > 0.0) || !std::isfinite(dt[s])) return arg_fail(c, "dt must be finite and > 0");
+    if (ns[s] < 1) return arg_fail(c, "n_steps must be >= 1");
   }
   // sort by decreasing step count (stable): running samples form a prefix
   st.perm.resize(n);
   for (int s = 0; s < n; ++s) st.perm[s] = s;
-  std::stable_sort(st.perm.begin(), st.perm.end(),
-                   [&](int a, int b) { return st.nsteps[a] > st.nsteps[b]; });
-  {
-    std::vector<double> k2(st.kappa.size()), x2(st.x0.size()), d2(n);
-    std::vector<int> n2(n);
-    for (int t = 0; t < n; ++t) {
-      const int s = st.perm[t];
-      std::copy(&st.kappa[(size_t)s * nb], &st.kappa[(size_t)s * nb] + nb, &k2[(size_t)t * nb]);
-      x2[2 * t] = st.x0[2 * s];
-      x2[2 * t + 1] = st.x0[2 * s + 1];
-      d2[t] = st.dt[s];
-      n2[t] = st.nsteps[s];
-    }
-    st.kappa.swap(k2);
-    st.x0.swap(x2);
-    st.dt.swap(d2);
-    st.nsteps.swap(n2);
+  std::stable_sort(st.perm.begin(), st.perm.end(), [&](int a, int b) { return ns[a] > ns[b]; });
+  st.dt.resize(n);
+  st.nsteps.resize(n);
+  for (int t = 0; t < n; ++t) {
+    st.dt[t] = dt[st.perm[t]];
+    st.nsteps[t] = ns[st.perm[t]];
   }
   st.coef.resize((size_t)n * (p + 1));
-  for (int s = 0; s < n; ++s) step_coefficients(lv.H, st.dt[s], &st.coef[(size_t)s * (p + 1)]);
+  for (int t = 0; t < n; ++t) step_coefficients(lv.H, st.dt[t], &st.coef[(size_t)t * (p + 1)]);
+  if (S->ptr_kind == LTS_PTR_HOST) {
+    const double* kin = st.g_mode ? S->g : S->kappa;
+    st.kappa.resize((size_t)n * nb);
+    st.x0.resize((size_t)n * 2);
+    for (int t = 0; t < n; ++t) {
+      const int s = st.perm[t];
+      for (int b = 0; b < nb; ++b) {
+        const double k = kin[(size_t)s * nb + b];
+        if (st.g_mode ? !std::isfinite(k) : (!(k > 0.0) || !std::isfinite(k)))
+          return arg_fail(c, st.g_mode ? "g must be finite" : "kappa must be finite and > 0");
+        st.kappa[(size_t)t * nb + b] = k;
+      }
+      st.x0[2 * t] = S->x0[2 * s];
+      st.x0[2 * t + 1] = S->x0[2 * s + 1];
+      if (!std::isfinite(st.x0[2 * t]) || !std::isfinite(st.x0[2 * t + 1])) return arg_fail(c, "x0 must be finite");
+    }
+  }
   return LTS_OK;
 }
 
-lts_status upload_staged(lts_ctx c, const Staged& st) {
-  const size_t n = st.n;
-  LTS_HIP(c, c->kappa.ensure(std::max<size_t>(st.kappa.size() * 8, 8)));
-  LTS_HIP(c, c->coef.ensure(std::max<size_t>(st.coef.size() * 8, 8)));
-  LTS_HIP(c, c->nsteps.ensure(std::max<size_t>(n * 4, 4)));
-  LTS_HIP(c, c->x0.ensure(std::max<size_t>(n * 16, 16)));
-  LTS_HIP(c, c->Qd.ensure(std::max<size_t>(n * 8, 8)));
+lts_status upload_staged(lts_ctx c, const DevLevel& lv, const Staged& st, const lts_samples* S,
+                         const StagedDev& d) {
+  const int n = st.n, nb = lv.H.n_blocks, p1 = lv.H.p + 1;
   if (n == 0) return LTS_OK;
-  LTS_HIP(c, hipMemcpyAsync(c->kappa.p, st.kappa.data(), st.kappa.size() * 8, hipMemcpyHostToDevice, c->stream));
-  LTS_HIP(c, hipMemcpyAsync(c->coef.p, st.coef.data(), st.coef.size() * 8, hipMemcpyHostToDevice, c->stream));
-  LTS_HIP(c, hipMemcpyAsync(c->nsteps.p, st.nsteps.data(), n * 4, hipMemcpyHostToDevice, c->stream));
-  LTS_HIP(c, hipMemcpyAsync(c->x0.p, st.x0.data(), n * 16, hipMemcpyHostToDevice, c->stream));
+  hipStream_t q = c->stream;
+  LTS_HIP(c, hipMemcpyAsync(d.coef, st.coef.data(), (size_t)n * p1 * 8, hipMemcpyHostToDevice, q));
+  LTS_HIP(c, hipMemcpyAsync(d.nsteps, st.nsteps.data(), (size_t)n * 4, hipMemcpyHostToDevice, q));
+  const bool dev = st.ptr_kind == LTS_PTR_DEVICE;
+  if (!dev && !st.g_mode) {
+    // host batch with kappa: checked on the host, no device check needed
+    LTS_HIP(c, hipMemcpyAsync(d.kappa, st.kappa.data(), st.kappa.size() * 8, hipMemcpyHostToDevice, q));
+    LTS_HIP(c, hipMemcpyAsync(d.x0, st.x0.data(), st.x0.size() * 8, hipMemcpyHostToDevice, q));
+    return LTS_OK;
+  }
+  k_zero_flag<<<1, 1, 0, q>>>(d.flag);
+  if (dev) {
+    LTS_HIP(c, hipMemcpyAsync(d.perm, st.perm.data(), (size_t)n * 4, hipMemcpyHostToDevice, q));
+    k_gather_samples<<<grid_for((long long)n * (nb + 2)), 256, 0, q>>>(S->kappa, S->kappa ? nullptr : S->g, S->x0,
+                                                                     d.perm, n, nb, d.kappa, d.x0, d.flag);
+  } else {
+    LTS_HIP(c, hipMemcpyAsync(d.kappa, st.kappa.data(), st.kappa.size() * 8, hipMemcpyHostToDevice, q));
+    LTS_HIP(c, hipMemcpyAsync(d.x0, st.x0.data(), st.x0.size() * 8, hipMemcpyHostToDevice, q));
+    k_exp2<<<grid_for((long long)n * nb), 256, 0, q>>>(d.kappa, (long long)n * nb, d.flag);
+  }
+  LTS_HIP(c, hipGetLastError());
+  int bad = 0;
+  LTS_HIP(c, hipMemcpyAsync(&bad, d.flag, 4, hipMemcpyDeviceToHost, q));
+  LTS_HIP(c, hipStreamSynchronize(q));
+  if (bad & 1) return arg_fail(c, st.g_mode ? "g must be finite (and exp(2 g) finite)" : "kappa must be finite and > 0");
+  if (bad & 2) return arg_fail(c, "x0 must be finite");
+  return LTS_OK;
+}
+
+lts_status ctx_staging(lts_ctx c, const DevLevel& lv, int n, StagedDev& d) {
+  const size_t m = std::max(n, 1);
+  LTS_HIP(c, c->kappa.ensure(m * lv.H.n_blocks * 8));
+  LTS_HIP(c, c->coef.ensure(m * (lv.H.p + 1) * 8));
+  LTS_HIP(c, c->nsteps.ensure(m * 4));
+  LTS_HIP(c, c->x0.ensure(m * 16));
+  LTS_HIP(c, c->Qd.ensure(m * 8));
+  LTS_HIP(c, c->perm.ensure(m * 4));
+  LTS_HIP(c, c->flag.ensure(256));
+  d = StagedDev{c->kappa.as<double>(), c->x0.as<double>(), c->coef.as<double>(), c->nsteps.as<int>(),
+                c->perm.as<int>(), c->flag.as<int>()};
+  return LTS_OK;
+}
+
+lts_status finish_Q(lts_ctx c, const Staged& st, const double* d_Q, const StagedDev& d, double* Q_out) {
+  const int n = st.n;
+  if (n == 0) return LTS_OK;
+  hipStream_t q = c->stream;
+  bool finite = true;
+  if (st.ptr_kind == LTS_PTR_DEVICE) {
+    k_zero_flag<<<1, 1, 0, q>>>(d.flag);
+    k_scatter_q<<<(n + 255) / 256, 256, 0, q>>>(d_Q, d.perm, n, Q_out, d.flag);
+    LTS_HIP(c, hipGetLastError());
+    int bad = 0;
+    LTS_HIP(c, hipMemcpyAsync(&bad, d.flag, 4, hipMemcpyDeviceToHost, q));
+    LTS_HIP(c, hipStreamSynchronize(q));
+    finite = bad == 0;
+  } else {
+    std::vector<double> qs(n);
+    LTS_HIP(c, hipMemcpyAsync(qs.data(), d_Q, (size_t)n * 8, hipMemcpyDeviceToHost, q));
+    LTS_HIP(c, hipStreamSynchronize(q));
+    for (int t = 0; t < n; ++t) {
+      Q_out[st.perm[t]] = qs[t];
+      finite = finite && std::isfinite(qs[t]);
+    }
+  }
+  if (!finite) {
+    c->err = "non-finite QoI (unstable sample)";
+    return LTS_ERR_UNSTABLE;
+  }
   return LTS_OK;
 }
 
@@ -159,28 +315,6 @@ const DevLevel* get_level(lts_ctx c, int32_t level) {
   return c->levels[level].get();
 }
 
-lts_status finish_Q(lts_ctx c, const Staged& st, int ptr_kind, double* Q_out) {
-  const int n = st.n;
-  std::vector<double> qs(n), q(n);
-  if (n > 0) LTS_HIP(c, hipMemcpyAsync(qs.data(), c->Qd.p, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
-  LTS_HIP(c, hipStreamSynchronize(c->stream));
-  for (int t = 0; t < n; ++t) q[st.perm[t]] = qs[t];
-  if (n > 0) {
-    if (ptr_kind == LTS_PTR_DEVICE) {
-      LTS_HIP(c, hipMemcpyAsync(Q_out, q.data(), (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
-      LTS_HIP(c, hipStreamSynchronize(c->stream));
-    } else {
-      std::memcpy(Q_out, q.data(), (size_t)n * 8);
-    }
-  }
-  for (int s = 0; s < n; ++s)
-    if (!std::isfinite(q[s])) {
-      c->err = "non-finite QoI (unstable sample)";
-      return LTS_ERR_UNSTABLE;
-    }
-  return LTS_OK;
-}
-
 lts_status forward_impl(lts_ctx c, int32_t level, const lts_samples* S, int32_t precision,
                         double* Q_out, bool per_sample) {
   if (!c) return LTS_ERR_ARG;
@@ -192,14 +326,15 @@ lts_status forward_impl(lts_ctx c, int32_t level, const lts_samples* S, int32_t 
   Staged st;
   lts_status r = stage_samples(c, *lv, S, st);
   if (r != LTS_OK) return r;
+  if (st.n == 0) return LTS_OK;
   LTS_HIP(c, hipSetDevice(c->device));
-  if ((r = upload_staged(c, st)) != LTS_OK) return r;
-  if (st.n > 0) {
-    r = forward_device(c, *lv, st.n, c->kappa.as<double>(), c->coef.as<double>(), c->nsteps.as<int>(),
-                       c->x0.as<double>(), S->width, st.nsteps, precision, per_sample, c->Qd.as<double>());
-    if (r != LTS_OK) return r;
-  }
-  return finish_Q(c, st, S->ptr_kind, Q_out);
+  StagedDev d;
+  if ((r = ctx_staging(c, *lv, st.n, d)) != LTS_OK) return r;
+  if ((r = upload_staged(c, *lv, st, S, d)) != LTS_OK) return r;
+  r = forward_device(c, *lv, st.n, d.kappa, d.coef, d.nsteps, d.x0, S->width, st.nsteps, precision, per_sample,
+                     c->Qd.as<double>());
+  if (r != LTS_OK) return r;
+  return finish_Q(c, st, c->Qd.as<double>(), d, Q_out);
 }
 
 }  // namespace
@@ -500,6 +635,7 @@ lts_status lts_forward_coupled(lts_ctx c, int32_t lf, int32_t lc, const lts_samp
   double *tf = nullptr, *tc = nullptr;
   lts_status r;
   if (dev) {
+    LTS_HIP(c, hipSetDevice(c->device));
     LTS_HIP(c, c->red.ensure(std::max<size_t>(16 * (size_t)n, 16)));
     tf = c->red.as<double>();
     tc = tf + n;
@@ -509,17 +645,17 @@ lts_status lts_forward_coupled(lts_ctx c, int32_t lf, int32_t lc, const lts_samp
   }
   if ((r = lts_forward(c, lf, F, precision, tf)) != LTS_OK) return r;
   if ((r = lts_forward(c, lc, C, precision, tc)) != LTS_OK) return r;
+  if (n == 0) return LTS_OK;
   if (dev) {
-    LTS_HIP(c, hipMemcpy(hf.data(), tf, (size_t)n * 8, hipMemcpyDeviceToHost));
-    LTS_HIP(c, hipMemcpy(hc.data(), tc, (size_t)n * 8, hipMemcpyDeviceToHost));
-  }
-  std::vector<double> d(n);
-  for (int s = 0; s < n; ++s) d[s] = hf[s] - hc[s];
-  const hipMemcpyKind k = dev ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
-  if (n > 0) {
-    if (Qf) LTS_HIP(c, hipMemcpy(Qf, hf.data(), (size_t)n * 8, k));
-    if (Qc) LTS_HIP(c, hipMemcpy(Qc, hc.data(), (size_t)n * 8, k));
-    if (dQ) LTS_HIP(c, hipMemcpy(dQ, d.data(), (size_t)n * 8, k));
+    k_coupled_diff<<<(n + 255) / 256, 256, 0, c->stream>>>(tf, tc, n, Qf, Qc, dQ);
+    LTS_HIP(c, hipGetLastError());
+    LTS_HIP(c, hipStreamSynchronize(c->stream));
+  } else {
+    for (int s = 0; s < n; ++s) {
+      if (Qf) Qf[s] = hf[s];
+      if (Qc) Qc[s] = hc[s];
+      if (dQ) dQ[s] = hf[s] - hc[s];
+    }
   }
   return LTS_OK;
 }
@@ -539,14 +675,20 @@ lts_status lts_backward(lts_ctx c, int32_t level, const lts_samples* S, const do
   const int n = st.n, nb = lv->H.n_blocks;
   if (n == 0) return LTS_OK;
   LTS_HIP(c, hipSetDevice(c->device));
-  std::vector<double> dl(n), dls(n);
-  LTS_HIP(c, hipMemcpy(dl.data(), dLdQ, (size_t)n * 8,
-                       S->ptr_kind == LTS_PTR_DEVICE ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
-  for (int t = 0; t < n; ++t) dls[t] = dl[st.perm[t]];
-  if ((r = upload_staged(c, st)) != LTS_OK) return r;
+  StagedDev d;
+  if ((r = ctx_staging(c, *lv, n, d)) != LTS_OK) return r;
+  if ((r = upload_staged(c, *lv, st, S, d)) != LTS_OK) return r;
   LTS_HIP(c, c->dldq.ensure((size_t)n * 8));
   LTS_HIP(c, c->gout.ensure((size_t)n * nb * 8));
-  LTS_HIP(c, hipMemcpyAsync(c->dldq.p, dls.data(), (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
+  if (st.ptr_kind == LTS_PTR_DEVICE) {
+    k_gather_vec<<<(n + 255) / 256, 256, 0, c->stream>>>(dLdQ, d.perm, n, c->dldq.as<double>());
+    LTS_HIP(c, hipGetLastError());
+  } else {
+    std::vector<double> dls(n);
+    for (int t = 0; t < n; ++t) dls[t] = dLdQ[st.perm[t]];
+    LTS_HIP(c, hipMemcpyAsync(c->dldq.p, dls.data(), (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
+    LTS_HIP(c, hipStreamSynchronize(c->stream));   // dls is released at the end of this scope
+  }
   // Sub-batches sized to the device: the checkpoints, the segment and the
   // fused scratch of one sub-batch take at most 60 % of the free memory (this
   // context's own adjoint buffers counted as free), in equal sub-batches.
@@ -565,30 +707,43 @@ lts_status lts_backward(lts_ctx c, int32_t level, const lts_samples* S, const do
   for (int s0 = 0; s0 < n; s0 += chunk) {
     const int m = std::min(chunk, n - s0);
     std::vector<int> ns(st.nsteps.begin() + s0, st.nsteps.begin() + s0 + m);
-    r = adjoint_device(c, *lv, m, c->kappa.as<double>() + (size_t)s0 * nb, c->coef.as<double>() + (size_t)s0 * p1,
-                       c->nsteps.as<int>() + s0, c->x0.as<double>() + 2 * (size_t)s0, S->width, ns, K,
-                       c->dldq.as<double>() + s0, c->Qd.as<double>() + s0, c->gout.as<double>(), s0);
+    r = adjoint_device(c, *lv, m, d.kappa + (size_t)s0 * nb, d.coef + (size_t)s0 * p1, d.nsteps + s0,
+                       d.x0 + 2 * (size_t)s0, S->width, ns, K, c->dldq.as<double>() + s0, c->Qd.as<double>() + s0,
+                       c->gout.as<double>(), s0);
     if (r != LTS_OK) return r;
   }
-  std::vector<double> g((size_t)n * nb), gs((size_t)n * nb);
-  LTS_HIP(c, hipMemcpyAsync(gs.data(), c->gout.p, gs.size() * 8, hipMemcpyDeviceToHost, c->stream));
-  LTS_HIP(c, hipStreamSynchronize(c->stream));
+  bool finite = true;
+  if (st.ptr_kind == LTS_PTR_DEVICE) {
+    k_zero_flag<<<1, 1, 0, c->stream>>>(d.flag);
+    k_scatter_rows<<<grid_for((long long)n * nb), 256, 0, c->stream>>>(c->gout.as<double>(), d.perm, n, nb, dQ_dg_out,
+                                                                     d.flag);
+    LTS_HIP(c, hipGetLastError());
+    int bad = 0;
+    LTS_HIP(c, hipMemcpyAsync(&bad, d.flag, 4, hipMemcpyDeviceToHost, c->stream));
+    LTS_HIP(c, hipStreamSynchronize(c->stream));
+    finite = bad == 0;
+  } else {
+    std::vector<double> gs((size_t)n * nb);
+    LTS_HIP(c, hipMemcpyAsync(gs.data(), c->gout.p, gs.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    LTS_HIP(c, hipStreamSynchronize(c->stream));
+    for (int t = 0; t < n; ++t)
+      for (int b = 0; b < nb; ++b) {
+        const double v = gs[(size_t)t * nb + b];
+        dQ_dg_out[(size_t)st.perm[t] * nb + b] = v;
+        finite = finite && std::isfinite(v);
+      }
+  }
   // a large workspace is not kept between calls (it would starve other users
   // of the device); small ones are reused
   if (c->adj.bytes + c->adjscr.bytes > (size_t)48 << 30) {
     c->adj.release();
     c->adjscr.release();
   }
-  for (int t = 0; t < n; ++t)
-    std::copy(&gs[(size_t)t * nb], &gs[(size_t)t * nb] + nb, &g[(size_t)st.perm[t] * nb]);
-  const hipMemcpyKind k = S->ptr_kind == LTS_PTR_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
-  LTS_HIP(c, hipMemcpy(dQ_dg_out, g.data(), g.size() * 8, k));
-  for (double v : g)
-    if (!std::isfinite(v)) {
-      c->err = "non-finite gradient (unstable sample)";
-      return LTS_ERR_UNSTABLE;
-    }
-  if (Q_out) return finish_Q(c, st, S->ptr_kind, Q_out);
+  if (!finite) {
+    c->err = "non-finite gradient (unstable sample)";
+    return LTS_ERR_UNSTABLE;
+  }
+  if (Q_out) return finish_Q(c, st, c->Qd.as<double>(), d, Q_out);
   return LTS_OK;
 }
 
@@ -598,12 +753,11 @@ lts_status lts_moments(lts_ctx c, const double* x, int32_t n, int32_t ptr_kind, 
   if (!out || (n > 0 && !x) || n < 0) return arg_fail(c, "bad moments arguments");
   if (ptr_kind != LTS_PTR_HOST && ptr_kind != LTS_PTR_DEVICE) return arg_fail(c, "bad ptr_kind");
   LTS_HIP(c, hipSetDevice(c->device));
-  LTS_HIP(c, c->red.ensure(std::max<size_t>((size_t)n * 8 + 64, 64)));
-  double* dx = c->red.as<double>() + 8;
-  if (n > 0)
-    LTS_HIP(c, hipMemcpyAsync(dx, x, (size_t)n * 8,
-                              ptr_kind == LTS_PTR_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                              c->stream));
+  const bool dev = ptr_kind == LTS_PTR_DEVICE;
+  LTS_HIP(c, c->red.ensure(std::max<size_t>(dev ? 64 : (size_t)n * 8 + 64, 64)));
+  const double* dx = dev ? x : c->red.as<double>() + 8;   // device input is read in place
+  if (n > 0 && !dev)
+    LTS_HIP(c, hipMemcpyAsync(c->red.as<double>() + 8, x, (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
   lts_status r = moments_device(c, dx, n, c->red.as<double>());
   if (r != LTS_OK) return r;
   LTS_HIP(c, hipMemcpyAsync(out, c->red.p, 24, hipMemcpyDeviceToHost, c->stream));

@@ -230,17 +230,18 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
     if (!lv.tuned && !lv.pinned && (r = autotune_level(c, lv)) != LTS_OK) return r;
   }
   // device layout: per-job tables, states, Q
-  std::vector<size_t> o_k(n_jobs), o_c(n_jobs), o_n(n_jobs), o_x(n_jobs), o_s(n_jobs), o_q(n_jobs);
-  size_t tab = 0, sts = 0, qb = 0;
+  std::vector<size_t> o_k(n_jobs), o_c(n_jobs), o_n(n_jobs), o_x(n_jobs), o_p(n_jobs), o_s(n_jobs), o_q(n_jobs);
+  size_t tab = 256, sts = 0, qb = 0;                   // the first 256 bytes: the staging flag
   for (int j = 0; j < n_jobs; ++j) {
     const DevLevel& lv = *c->levels[jobs[j].level];
-    const Staged& S = st[j];
-    o_k[j] = tab; tab += align256(S.kappa.size() * 8);
-    o_c[j] = tab; tab += align256(S.coef.size() * 8);
-    o_n[j] = tab; tab += align256(S.nsteps.size() * 4);
-    o_x[j] = tab; tab += align256(S.x0.size() * 8);
-    o_s[j] = sts; sts += align256((size_t)S.n * lv.nodes * es) * 2;
-    o_q[j] = qb; qb += align256((size_t)S.n * 8);
+    const size_t n = (size_t)st[j].n;
+    o_k[j] = tab; tab += align256(n * lv.H.n_blocks * 8);
+    o_c[j] = tab; tab += align256(n * (lv.H.p + 1) * 8);
+    o_n[j] = tab; tab += align256(n * 4);
+    o_x[j] = tab; tab += align256(n * 16);
+    o_p[j] = tab; tab += align256(n * 4);
+    o_s[j] = sts; sts += align256(n * lv.nodes * es) * 2;
+    o_q[j] = qb; qb += align256(n * 8);
   }
   LTS_HIP(c, c->b_tab.ensure(std::max<size_t>(tab, 256)));
   LTS_HIP(c, c->b_states.ensure(std::max<size_t>(sts, 256)));
@@ -249,6 +250,10 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
   char* tb = c->b_tab.as<char>();
   char* sb = c->b_states.as<char>();
   char* qbp = c->b_Q.as<char>();
+  auto staged_dev = [&](int j) {
+    return StagedDev{(double*)(tb + o_k[j]), (double*)(tb + o_x[j]), (double*)(tb + o_c[j]), (int*)(tb + o_n[j]),
+                     (int*)(tb + o_p[j]), (int*)tb};
+  };
   std::vector<char> recs(step_args_size() * n_jobs);
   std::vector<const TilingDev*> T(n_jobs);
   int maxT = 0;
@@ -256,10 +261,7 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
     const DevLevel& lv = *c->levels[jobs[j].level];
     const Staged& S = st[j];
     if (S.n > 0) {
-      LTS_HIP(c, hipMemcpyAsync(tb + o_k[j], S.kappa.data(), S.kappa.size() * 8, hipMemcpyHostToDevice, c->stream));
-      LTS_HIP(c, hipMemcpyAsync(tb + o_c[j], S.coef.data(), S.coef.size() * 8, hipMemcpyHostToDevice, c->stream));
-      LTS_HIP(c, hipMemcpyAsync(tb + o_n[j], S.nsteps.data(), S.nsteps.size() * 4, hipMemcpyHostToDevice, c->stream));
-      LTS_HIP(c, hipMemcpyAsync(tb + o_x[j], S.x0.data(), S.x0.size() * 8, hipMemcpyHostToDevice, c->stream));
+      if ((r = upload_staged(c, lv, S, &jobs[j].samples, staged_dev(j))) != LTS_OK) return r;
       maxT = std::max(maxT, S.nsteps[0]);
     }
     double* B0 = (double*)(sb + o_s[j]);
@@ -363,31 +365,14 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
       c->last.alg_bytes += (double)v * 24.0 * lv.H.n_dof;
     }
   }
-  // results: per job in sorted order -> caller order at q_offset
-  std::vector<double> q(total, 0.0);
+  // results: per job in sorted order -> caller order at q_offset (only the
+  // ranges the jobs own are written)
   bool bad = false;
   for (int j = 0; j < n_jobs; ++j) {
-    const int n = st[j].n;
-    if (n == 0) continue;
-    std::vector<double> qs(n);
-    LTS_HIP(c, hipMemcpyAsync(qs.data(), qbp + o_q[j], (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
-    LTS_HIP(c, hipStreamSynchronize(c->stream));
-    for (int t = 0; t < n; ++t) {
-      q[jobs[j].q_offset + st[j].perm[t]] = qs[t];
-      bad |= !std::isfinite(qs[t]);
-    }
-  }
-  if (total > 0) {
-    if (kind == LTS_PTR_DEVICE) {
-      // only the ranges the jobs own are written
-      for (int j = 0; j < n_jobs; ++j)
-        if (st[j].n > 0)
-          LTS_HIP(c, hipMemcpy(Q_out + jobs[j].q_offset, q.data() + jobs[j].q_offset, (size_t)st[j].n * 8,
-                               hipMemcpyHostToDevice));
-    } else {
-      for (int j = 0; j < n_jobs; ++j)
-        if (st[j].n > 0) std::memcpy(Q_out + jobs[j].q_offset, q.data() + jobs[j].q_offset, (size_t)st[j].n * 8);
-    }
+    if (st[j].n == 0) continue;
+    r = finish_Q(c, st[j], (const double*)(qbp + o_q[j]), staged_dev(j), Q_out + jobs[j].q_offset);
+    if (r == LTS_ERR_UNSTABLE) bad = true;
+    else if (r != LTS_OK) return r;
   }
   if (bad) {
     c->err = "non-finite QoI (unstable sample)";

@@ -128,16 +128,24 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
   // Samples arrive sorted by decreasing step count, so the samples still
   // running at step `step` are a prefix of the batch.  FP32 stepping keeps
   // binary32 states (sstride elements of 4 bytes per sample) in the same buffers.
-  const bool fp32 = precision == LTS_FP32_STEP;
-  const size_t sstride = lv.nodes;
-  const size_t bytes = (size_t)n * sstride * (fp32 ? sizeof(float) : sizeof(double));
+  const size_t bytes = (size_t)n * lv.nodes * (precision == LTS_FP32_STEP ? sizeof(float) : sizeof(double));
   LTS_HIP(c, c->st0.ensure(bytes));
   LTS_HIP(c, c->st1.ensure(bytes));
-  double* B[2] = {c->st0.as<double>(), c->st1.as<double>()};
+  return forward_device_states(c, lv, n, d_kappa, d_coef, d_nsteps, d_x0, width, h_nsteps, precision, per_sample,
+                               d_Q, c->st0.as<double>(), c->st1.as<double>(), c->timing);
+}
+
+lts_status forward_device_states(lts_ctx c, const DevLevel& lv, int n, const double* d_kappa,
+                                 const double* d_coef, const int* d_nsteps, const double* d_x0, double width,
+                                 const std::vector<int>& h_nsteps, int precision, bool per_sample, double* d_Q,
+                                 double* B0, double* B1, bool timing) {
+  const bool fp32 = precision == LTS_FP32_STEP;
+  const size_t sstride = lv.nodes;
+  double* B[2] = {B0, B1};
   const int maxn = h_nsteps[0];
 
   hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
-  if (c->timing) {
+  if (timing) {
     while (c->ev_pool.size() < 4) {
       hipEvent_t e;
       LTS_HIP(c, hipEventCreate(&e));
@@ -148,7 +156,7 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
   }
   lts_status r = init_states(c, lv, n, d_x0, width, B[0], B[1], fp32);
   if (r != LTS_OK) return r;
-  if (c->timing) LTS_HIP(c, hipEventRecord(e1, c->stream));
+  if (timing) LTS_HIP(c, hipEventRecord(e1, c->stream));
   int64_t launches = 0;
   if (per_sample) {
     for (int s = 0; s < n; ++s)
@@ -169,7 +177,7 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
     }
   }
   LTS_HIP(c, hipGetLastError());
-  if (c->timing) LTS_HIP(c, hipEventRecord(e2, c->stream));
+  if (timing) LTS_HIP(c, hipEventRecord(e2, c->stream));
   if ((r = qoi_device(c, lv, n, d_nsteps, B[0], B[1], d_Q, fp32)) != LTS_OK) return r;
   double dofu = 0.0, algb = 0.0;
   const double per_step = (double)(lv.H.n_dof - lv.H.n_P) + (double)lv.H.p * lv.H.n_P;
@@ -181,7 +189,7 @@ lts_status forward_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
   c->last.dof_updates = dofu;
   c->last.alg_bytes = algb;
   c->last.step_launches = launches;
-  if (c->timing) {
+  if (timing) {
     LTS_HIP(c, hipEventRecord(e3, c->stream));
     LTS_HIP(c, hipEventSynchronize(e3));
     float ta = 0, tb = 0;
