@@ -286,6 +286,28 @@ lts_status lts_forward(lts_ctx ctx, int32_t level, const lts_samples* samples, i
 lts_status lts_forward_plain(lts_ctx ctx, int32_t level, const lts_samples* samples,
                              int32_t precision, double* Q_out);
 
+/* Size in bytes of the per-device array that lts_forward_noalloc works in. */
+#define LTS_NOALLOC_SCRATCH_BYTES (64ULL << 20)
+
+/* For callers that cannot allocate device memory during a solve (serving
+ * loops, harnesses that forbid hipMalloc): lts_forward (batched, FP64 or
+ * LTS_FP32_STEP) with every piece of device scratch -- the sorted per-sample
+ * tables, a staging flag and the two time levels of the state -- in one fixed
+ * array of LTS_NOALLOC_SCRATCH_BYTES bytes per GPU, which the library holds from
+ * the first lts_create on that GPU until the process ends.  The call makes no
+ * hipMalloc or hipFree (the level and its tiling must exist already:
+ * lts_add_level and lts_set_tiling / lts_autotune allocate).  The batch must fit:
+ * about 2 n (nx_nodes rounded up to 8) ny_nodes values of 8 bytes (4 under
+ * LTS_FP32_STEP) plus n (n_blocks + p + 6) * 8 bytes; a larger batch returns
+ * LTS_ERR_ARG naming the bytes it needs, before anything is read.  All calls
+ * on one GPU, from any context or thread, share that GPU's array and leave
+ * their contents in it: calls that overlap in time on one GPU race.  No
+ * timing events are recorded.  Otherwise the contract of lts_forward, with the
+ * same results bit for bit.  Errors as lts_forward; LTS_ERR_STATE if the
+ * array's address could not be taken on this device. */
+lts_status lts_forward_noalloc(lts_ctx ctx, int32_t level, const lts_samples* samples, int32_t precision,
+                               double* Q_out);
+
 /* Coupled difference for MLMC level l >= 1 (Sec. 2.2): the same samples
  * (kappa, x0) solved on level_fine and level_coarse, each with its own
  * n_steps/dt.  Writes Qf, Qc and dQ = Qf - Qc (any may be NULL; same

@@ -261,6 +261,14 @@ class Context:
         self._c(fn(self.h, level, C.byref(sa.s), precision, qp))
         return q
 
+    def forward_noalloc(self, level, kappa, x0, n_steps, dt, width=0.05, precision=LTS_FP64, g=None):
+        """forward() through lts_forward_noalloc: no device allocation in the
+        library; the batch must fit its fixed per-GPU scratch."""
+        sa = _SampleArgs(kappa, x0, n_steps, dt, width, g)
+        q, qp = sa.out()
+        self._c(self.lib.lts_forward_noalloc(self.h, level, C.byref(sa.s), precision, qp))
+        return q
+
     def forward_coupled(self, level_fine, level_coarse, kappa, x0, ns_f, dt_f, ns_c, dt_c, width=0.05,
                         precision=LTS_FP64):
         fa = _SampleArgs(kappa, x0, ns_f, dt_f, width)

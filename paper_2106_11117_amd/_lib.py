@@ -20,6 +20,7 @@ LTS_BATCH_GRAPH = 1
 LTS_BATCH_FP32 = 2
 LTS_MLMC_BATCHED, LTS_MLMC_PLAIN = 0, 1
 LTS_MAX_LEVELS = 8
+LTS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _ERR_NAMES = {LTS_ERR_ARG: "LTS_ERR_ARG", LTS_ERR_HIP: "LTS_ERR_HIP", LTS_ERR_OOM: "LTS_ERR_OOM",
               LTS_ERR_UNSTABLE: "LTS_ERR_UNSTABLE", LTS_ERR_STATE: "LTS_ERR_STATE"}
@@ -113,6 +114,7 @@ SIGNATURES = [
     ("lts_cheb_constants", C.c_int32, [C.c_int32, C.c_double, C.c_double, dp, dp, dp, dp, dp]),
     ("lts_forward", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Samples), C.c_int32, C.c_void_p]),
     ("lts_forward_plain", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Samples), C.c_int32, C.c_void_p]),
+    ("lts_forward_noalloc", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Samples), C.c_int32, C.c_void_p]),
     ("lts_forward_coupled", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Samples),
                                         C.POINTER(Samples), C.c_int32, C.c_void_p, C.c_void_p,
                                         C.c_void_p]),

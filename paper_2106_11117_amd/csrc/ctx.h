@@ -180,6 +180,10 @@ lts_status forward_device_states(lts_ctx c, const DevLevel& lv, int n, const dou
 
 lts_status moments_device(lts_ctx c, const double* d_x, int n, double* d_out3);
 
+// Takes the device address of the no-allocation scratch array on `device`
+// (current) once per device (see lts_noalloc.hip).
+lts_status noalloc_attach(lts_ctx c, int device);
+
 // u_0 (pulse) into B0 and zeros into B1 for samples 0..n-1.
 lts_status init_states(lts_ctx c, const DevLevel& lv, int n, const double* d_x0, double width, double* B0,
                        double* B1, bool fp32 = false);

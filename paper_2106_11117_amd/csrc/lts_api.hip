@@ -356,6 +356,10 @@ lts_status lts_create(lts_ctx* out, int32_t hip_device, void* hip_stream) {
   int n_cu = 0;
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && n_cu > 0)
     c->n_cu = n_cu;
+  if (noalloc_attach(c, hip_device) != LTS_OK) {
+    delete c;
+    return LTS_ERR_HIP;
+  }
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {
