@@ -1,0 +1,56 @@
+"""Oracle solves run in worker processes by the GPU parity tests (test
+infrastructure: calls only the oracle).  Each job is a plain tuple so that it
+can be sent to a spawned process; results are plain dicts."""
+from __future__ import annotations
+
+import multiprocessing as mp
+import os
+
+import numpy as np
+
+from oracle import adjoint, fem, lts, mesh, rng
+
+GRADED_RULE = dict(n_blocks=64, sigma=0.3, pulse_box=(-0.8, -0.4, 0.4, 0.8))
+
+
+def graded_level(base, lf=False):
+    lv = mesh.graded_L_level(base)
+    return mesh.lf_twin(lv) if lf else lv
+
+
+def solve(job):
+    """('fwd', base, sample_level, i, T, lf) -> Q, sum w|u|, n_steps of that
+    sample on the graded L-shape level with `base` cells across (its leapfrog
+    twin when lf)."""
+    _, base, slevel, i, T, lf = job
+    lv = graded_level(base, lf)
+    ops = fem.operators(lv)
+    rule = rng.SampleRule(T=T, **GRADED_RULE)
+    smp = rng.draw(0, slevel, i, rule)
+    n, dt = rng.steps_for(smp, rule, lv.h)
+    u = lts.Solver(ops, smp.kappa).run(lts.pulse(ops, smp.x0), dt, n)
+    return {"Q": float(lts.qoi(ops, u)), "abs_wu": float(ops.qoi_w @ np.abs(u)), "n_steps": n}
+
+
+def grad(job):
+    """('adj', base, sample_level, i, T, K) -> Q and dQ/dg of that sample by the
+    oracle's checkpointed discrete adjoint."""
+    _, base, slevel, i, T, K = job
+    lv = mesh.graded_L_level(base)
+    ops = fem.operators(lv)
+    rule = rng.SampleRule(T=T, **GRADED_RULE)
+    smp = rng.draw(0, slevel, i, rule)
+    n, dt = rng.steps_for(smp, rule, lv.h)
+    Q, _, g = adjoint.gradient(ops, smp.kappa, lts.pulse(ops, smp.x0), dt, n, K=K)
+    return {"Q": float(Q), "g": np.asarray(g).tolist(), "n_steps": n}
+
+
+def _run(job):
+    return solve(job) if job[0] == "fwd" else grad(job)
+
+
+def run_all(jobs):
+    """All jobs in parallel worker processes (spawned: they touch no GPU state)."""
+    procs = max(1, min(len(jobs), 16, os.cpu_count() or 1))
+    with mp.get_context("spawn").Pool(procs) as pool:
+        return pool.map(_run, jobs, chunksize=1)
