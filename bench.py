@@ -12,7 +12,13 @@ every LF-LTS time step of every sample (coarse sweep + p local substeps), the
 QoI and the per-level moment reduction.  Inputs (per-sample coefficients,
 pulse centres, step counts) are resident in HBM before the timed region.
 
-Prints one JSON line (see the repository's benchmark contract).
+Prints one JSON line (see the repository's benchmark contract).  After the
+timed throughput run the same line also carries, measured outside the timed
+region, the rest of the metric on the graded L-shape hierarchy (5 levels,
+p = 64, T = 2): Algorithm 1 at eps = 1e-4, batched + graph against the plain
+one-launch-per-sample form at identical N_l ("mlmc_graded_L"), and the batched
+multi-level throughput with N_l = 4096, 1024, 256, 64, 16 ("batch_graded_L").
+--no-extra leaves them out.
 
 Other modes (one JSON line each): --mlmc (Algorithm 1, batched + graph against
 the plain form and the CPU oracle), --batch [--plain] (all five graded L-shape
@@ -36,12 +42,12 @@ N_SAMPLES = 256
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per step launch (one k_coarse + one k_fine) from the FETCH_SIZE /
 # WRITE_SIZE counter runs, scaled by a plain copy kernel
-# (profiles/lts_step_kernels_C1_256samples_counters.md): counter bytes are 1.356x
+# (profiles/lts_step_kernels_C1_256samples_counters.md): counter bytes are 1.354x
 # the algorithmic bytes on the profiled launches (all samples active), applied
 # to the average launch's 1.7105e9 algorithmic bytes.  Valid only for the
 # step-kernel sources the counters were taken with.
-TRAFFIC = {"bytes_per_launch": 1.356 * 1.7105e9,
-           "sources_sha256": "24a94a3b6d1b1143802187c1078a9e3ea184aa0f7069a9cb7dfe2fce0c239659"}
+TRAFFIC = {"bytes_per_launch": 1.354 * 1.7105e9,
+           "sources_sha256": "e1e18a9620022f5012495692689bd8174d73dcc37f258de76e657c8784d85f51"}
 STEP_SOURCES = ("lts_fused.hip", "fused.h", "device.h", "lts_step.hip")
 WORKLOAD = ("unit square 512x512 base refined 8x in (0.48,0.52): 442225 DOFs, |P|=204081, p=8, "
             "nu=0.01, 256 samples, 4x4 blocks sigma=0.25, T=1, FP64")
@@ -128,7 +134,7 @@ def _mlmc_cpu_worker(args):
     return lvl, (time.perf_counter() - t0) / steps
 
 
-def mlmc_bench(no_cpu: bool):
+def mlmc_bench(no_cpu: bool, eps_list=MLMC_EPS, emit: bool = True):
     """Algorithm 1 on the graded L-shape hierarchy (h = 1/16 .. 1/256, p = 64, 8x8
     blocks sigma 0.3, T = 2) at the workload's eps = 1e-3 and a tighter 1e-4: wall
     time of the batched + graph form and of the plain form (one launch per sample
@@ -159,7 +165,7 @@ def mlmc_bench(no_cpu: bool):
     setup = time.perf_counter() - t0
     info = [ctx.level_info(l) for l in ids]
     runs = []
-    for eps in MLMC_EPS:
+    for eps in eps_list:
         t0 = time.perf_counter()
         rb = ctx.mlmc(ids, rule, eps=eps, N_init=MLMC_N_INIT, L_start=2)
         wall_b = time.perf_counter() - t0
@@ -196,8 +202,10 @@ def mlmc_bench(no_cpu: bool):
                "sample": "oracle seconds per coarse step timed on every level (4 samples x 10 steps, one "
                          "process per core), times each run's step counts for the same N_l, divided by "
                          "the cores (an extrapolation, not a full oracle run)"}}
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
     ctx.close()
+    return out
 
 
 def lf_bench():
@@ -302,7 +310,7 @@ def adjoint_bench(samples: int, K: int):
 BATCH_N = (4096, 1024, 256, 64, 16)       # samples per level of the multi-level throughput run
 
 
-def batch_bench(plain: bool):
+def batch_bench(plain: bool, fp32: bool = True, emit: bool = True):
     """Form 2 throughput on the graded L-shape hierarchy (5 levels, h = 1/16 ..
     1/256, p = 64, 8x8 blocks sigma 0.3, T = 2): the samples of all levels
     (N_l = 4096, 1024, 256, 64, 16) advanced together by lts_batch_run, with and
@@ -347,10 +355,11 @@ def batch_bench(plain: bool):
     per_level = lambda **kw: np.concatenate([np.asarray(ctx.forward(j[0], *j[1:5], width=j[5], **kw))
                                              for j in jobs])
     t_level, q_level = median_time(per_level, 3)
-    ctx.batch_run(jobs, graph=True, precision=P.LTS_FP32_STEP)       # warm-up; captures the graph
-    t_f32, q_f32 = median_time(lambda: ctx.batch_run(jobs, graph=True, precision=P.LTS_FP32_STEP), 3)
     q64 = np.asarray(q_graph)
-    rel32 = np.abs(np.asarray(q_f32) - q64) / np.max(np.abs(q64))
+    if fp32:
+        ctx.batch_run(jobs, graph=True, precision=P.LTS_FP32_STEP)       # warm-up; captures the graph
+        t_f32, q_f32 = median_time(lambda: ctx.batch_run(jobs, graph=True, precision=P.LTS_FP32_STEP), 3)
+        rel32 = np.abs(np.asarray(q_f32) - q64) / np.max(np.abs(q64))
     out = {"metric": "batched multi-level LF-LTS throughput (form 2), graded L-shape hierarchy",
            "unit": "DOF-updates/s", "higher_is_better": True, "data": "synthetic (Philox seed 0)", "dtype": "f64",
            "config": {"workload": "graded L-shape, 5 levels h = 1/16..1/256, 6 graded layers (h_min = h/64, "
@@ -360,9 +369,10 @@ def batch_bench(plain: bool):
                              "hbm_frac_algorithmic": alg_bytes / t_graph / (HBM_PEAK_GBS * 1e9)},
            "batched_no_graph": {"s": t_batch, "dof_updates_per_s": dof_upd / t_batch},
            "one_forward_per_level": {"s": t_level, "dof_updates_per_s": dof_upd / t_level},
-           "batched_graph_fp32_step": {"s": t_f32, "dof_updates_per_s": dof_upd / t_f32,
-                                       "qoi_max_err_rel_to_max_abs_q": float(rel32.max()),
-                                       "qoi_median_err_rel_to_max_abs_q": float(np.median(rel32))},
+           "batched_graph_fp32_step": None if not fp32 else {
+               "s": t_f32, "dof_updates_per_s": dof_upd / t_f32,
+               "qoi_max_err_rel_to_max_abs_q": float(rel32.max()),
+               "qoi_median_err_rel_to_max_abs_q": float(np.median(rel32))},
            "q_equal": bool(np.array_equal(np.asarray(q_graph), np.asarray(q_batch)) and
                            np.array_equal(np.asarray(q_graph), q_level))}
     if plain:
@@ -370,8 +380,10 @@ def batch_bench(plain: bool):
         out["plain"] = {"s": t_plain, "dof_updates_per_s": dof_upd / t_plain,
                         "speedup_batched_graph_vs_plain": t_plain / t_graph}
         out["q_equal"] = out["q_equal"] and bool(np.array_equal(np.asarray(q_graph), q_plain))
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
     ctx.close()
+    return out
 
 
 def copy_check(mib: int):
@@ -424,6 +436,8 @@ def main():
     ap.add_argument("--plain", action="store_true", help="time the one-launch-per-sample form")
     ap.add_argument("--samples", type=int, default=N_SAMPLES)
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-stepping run")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the MLMC and multi-level batched runs that follow the throughput line")
     ap.add_argument("--copy-check", type=int, default=0, metavar="MIB",
                     help="only run 4 plain device copies of MIB MiB (calibrates HBM byte counters)")
     ap.add_argument("--lf", action="store_true",
@@ -552,8 +566,27 @@ def main():
         "fp32_step": fp32,
         "mean_Q": float(m[1]), "var_Q": float(m[2] / max(m[0] - 1, 1)),
     }
-    print(json.dumps(out), flush=True)
     ctx.close()
+    if not args.no_extra:
+        # the rest of the metric, outside the timed region above: MLMC wall time at
+        # fixed RMSE (batched + graph against the plain form, identical N_l) and the
+        # batched multi-level throughput, both on the graded L-shape hierarchy
+        t0 = time.perf_counter()
+        mb = mlmc_bench(True, (1e-4,), emit=False)
+        bb = batch_bench(False, fp32=False, emit=False)
+        r = mb["runs"][0]
+        out["mlmc_graded_L"] = {k: r[k] for k in ("eps", "batched_graph_s", "plain_s", "speedup_vs_plain", "L",
+                                                  "N", "estimate", "rmse", "converged")}
+        out["mlmc_graded_L"]["workload"] = mb["config"]["workload"]
+        out["batch_graded_L"] = {"workload": bb["config"]["workload"],
+                                 "samples_per_level": [lv["samples"] for lv in bb["config"]["levels"]],
+                                 "batched_graph_s": bb["batched_graph"]["s"],
+                                 "dof_updates_per_s": bb["batched_graph"]["dof_updates_per_s"],
+                                 "hbm_frac_algorithmic": bb["batched_graph"]["hbm_frac_algorithmic"],
+                                 "one_forward_per_level_s": bb["one_forward_per_level"]["s"],
+                                 "q_equal": bb["q_equal"]}
+        out["extra_wall_s"] = time.perf_counter() - t0
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

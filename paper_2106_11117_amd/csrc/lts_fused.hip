@@ -450,6 +450,17 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, const StepStat
   const int ld = L.ld;
   const int p = L.p;                                    // <= 64 in rect mode
 
+  // ---- the substep scalars of the unrolled refinement ratios (p = 4, 8),
+  //      read before anything else: the substeps then wait on LDS only
+  constexpr int kPre = 8;
+  double c_pre[kPre], b_pre[kPre];
+  if (p == 4 || p == 8) {
+#pragma unroll
+    for (int m = 0; m < kPre; ++m) {
+      c_pre[m] = m < p ? cf[1 + m] : 0.0;
+      b_pre[m] = m > 0 && m < p ? L.beta[m] : 0.0;
+    }
+  }
   // ---- one batch of global reads (nothing read here decides another read)
   const double kv = tid < L.nb ? a.kappa[(size_t)s * L.nb + tid] : 0.0;
   const int gxc = min(gx, L.nxn - 1);                  // column, in bounds off the grid
@@ -466,6 +477,9 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, const StepStat
     ihy[q] = L.inv2hy[g];
     ni[q] = L.ninfo[g * ld + gxc];
   }
+  // u_n-1 enters only the update of the written-back nodes: it is read at the
+  // tile interior only (the halo is 43 % of a 64 x 64 region at p = 8)
+  const bool col_in = gx >= ix0 && gx < ix1;
   T u[R], uo[R];
   double im[R];
   uint32_t f[R];
@@ -475,7 +489,8 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, const StepStat
     const int k = ok ? (gyb + r) * ld + gx : ld + 1;
     u[r] = ok ? u_g[k] : (T)0;
     im[r] = L.invm[k];
-    uo[r] = startup ? (T)0 : uo_g[k];
+    const bool in = ok && col_in && gyb + r >= iy0 && gyb + r < iy1;
+    uo[r] = (startup || !in) ? (T)0 : uo_g[k];
     f[r] = ok ? ni[r + 1] & 0xFFu : 0u;
   }
   // ---- LDS: kappa table (zero past the last block, so that the missing cells
@@ -518,7 +533,6 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, const StepStat
     double cV[R + 1];
 #pragma unroll
     for (int c = 0; c <= R; ++c) cV[c] = (kE[c] * hxE + kW[c] * hxW) * ihy[c];
-    const bool col_in = gx >= ix0 && gx < ix1;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const bool fp = f[r] & F_FPLUS;
@@ -554,12 +568,14 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, const StepStat
   T d0[R], d1[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) d0[r] = d1[r] = (T)0;
-  auto substep = [&](int m, auto Bc) {
+  auto substep = [&](int m, auto Bc, auto Pc) {
     constexpr int B = decltype(Bc)::value;
+    constexpr bool PRE = decltype(Pc)::value;
     T* dc = B == 0 ? d0 : d1;       // d_m
     T* dq = B == 0 ? d1 : d0;       // d_m-1 in, d_m+1 out
-    const T c = (T)cf[1 + m];             // c1 for m = 0, c2_m otherwise (scalar loads)
-    const T b = m > 0 ? (T)L.beta[m] : (T)0;   // beta_m
+    // c1 for m = 0, c2_m otherwise, and beta_m (preloaded, or scalar loads)
+    const T c = PRE ? (T)c_pre[m] : (T)cf[1 + m];
+    const T b = PRE ? (T)b_pre[m] : m > 0 ? (T)L.beta[m] : (T)0;
     // d_m+1 is needed only within distance p-1-m of the tile interior (it
     // reaches the interior through p-1-m more stencil applications); a
     // wavefront whose rows all lie farther out skips the substep.  Rows it
@@ -575,12 +591,19 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, const StepStat
       // neighbour (one DPP shift), the south one minus the north one of the
       // row below.
       T dN[R + 1];                                     // dN[r + 1] = q_r - q_r+1, dN[0] = q_-1 - q_0
-      dN[0] = rb[below] - q[0];
+      const T qb = rb[below], qa = rb[above];          // LDS: the neighbouring wavefronts' rows
+      __builtin_amdgcn_sched_barrier(0);               // issue the LDS read before the inner rows
 #pragma unroll
-      for (int r = 0; r < R; ++r) dN[r + 1] = q[r] - (r + 1 < R ? q[r + 1] : rb[above]);
+      for (int r = 0; r + 1 < R; ++r) dN[r + 1] = q[r] - q[r + 1];
       T qn[R];
+      // the inner rows first: they need no LDS value, so the LDS read of the
+      // boundary rows completes behind their arithmetic
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
+      for (int k = 0; k < R; ++k) {
+        const int r = k + 1 < R - 1 ? k + 1 : (k == R - 2 ? 0 : R - 1);   // 1, 2, .., R-2, 0, R-1
+        if (k == R - 2) __builtin_amdgcn_sched_barrier(0);   // the LDS values are used from here on
+        if (r == 0) dN[0] = qb - q[0];
+        if (r == R - 1) dN[R] = q[R - 1] - qa;
         const T dE = q[r] - lane_next(q[r]);
         const T dWn = lane_prev(dE);                   // q_x-1 - q_x
         const T rr = aS[r] * -dN[r] + (aN[r] * dN[r + 1] + (aW[r] * -dWn + (aE[r] * dE + w[r])));
@@ -601,10 +624,11 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, const StepStat
   // no loop control, scheduling across substeps), a loop otherwise
   auto unrolled = [&](auto Pc) {
     constexpr int PP = decltype(Pc)::value;
+    static_assert(PP <= kPre, "preloaded scalars");
 #pragma unroll
     for (int m = 0; m < PP; m += 2) {
-      substep(m, std::integral_constant<int, 0>{});
-      substep(m + 1, std::integral_constant<int, 1>{});
+      substep(m, std::integral_constant<int, 0>{}, std::true_type{});
+      substep(m + 1, std::integral_constant<int, 1>{}, std::true_type{});
     }
   };
   if (p == 8) {
@@ -613,8 +637,8 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, const StepStat
     unrolled(std::integral_constant<int, 4>{});
   } else {
     for (int m = 0; m < p; m += 2) {
-      substep(m, std::integral_constant<int, 0>{});
-      if (m + 1 < p) substep(m + 1, std::integral_constant<int, 1>{});
+      substep(m, std::integral_constant<int, 0>{}, std::false_type{});
+      if (m + 1 < p) substep(m + 1, std::integral_constant<int, 1>{}, std::false_type{});
     }
   }
   T d[R];

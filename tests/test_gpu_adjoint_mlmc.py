@@ -234,7 +234,7 @@ def test_lf_twin_forward_matches_oracle(ctx, graded):
     lid = ctx.add_rect_level(P.lf_rule(rule))
     info = ctx.level_info(lid)
     assert info["n_P"] == 0 and info["n_Fplus"] == 0 and info["p"] == 1 and info["h"] == tw.h
-    r = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), T=0.3) if graded \
+    r = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), T=2.0) if graded \
         else P.sample_rule(T=0.3)
     s = P.gen_samples(0, 0, 0, 4, r, info["h"])
     q = ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"])

@@ -31,7 +31,7 @@ def _jobs(ctx):
     l1 = ctx.add_rect_level(P.box_rule(64))
     lg = ctx.add_rect_level(P.graded_L_rule(32))
     r = P.sample_rule(T=0.4)
-    rg = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), T=0.3)
+    rg = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), T=2.0)
     s0 = P.gen_samples(0, 0, 0, 9, r, 1 / 32)
     s1 = P.gen_samples(0, 1, 0, 5, r, 1 / 64)
     sg = P.gen_samples(0, 2, 0, 3, rg, 1 / 16)
@@ -75,7 +75,7 @@ def test_batch_compact_workgroup_sizes(ctx):
     l1 = ctx.add_rect_level(P.box_rule(64))          # adaptive: up to 4,060 nodes, 1024 threads
     for lid in (lg, l0, l1):
         ctx.set_tiling(lid, 0, 0, False)
-    rg = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), T=0.3)
+    rg = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), T=2.0)
     r = P.sample_rule(T=0.2)
     sg = P.gen_samples(1, 0, 0, 700, rg, 1 / 16)
     s0 = P.gen_samples(1, 1, 0, 300, r, 1 / 32)

@@ -88,11 +88,11 @@ def test_c0_level1_coupled(ctx):
 
 
 def test_graded_L_p64(ctx):
-    """Reentrant-corner mesh (p = 64 substeps), short horizon."""
+    """Reentrant-corner mesh (p = 64 substeps) at the horizon T = 2."""
     lid = ctx.add_rect_level(P.graded_L_rule(32))
     lv = mesh.graded_L_level(32)
     ops = fem.operators(lv)
-    r = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), T=0.5)
+    r = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), T=2.0)
     s = P.gen_samples(0, 0, 0, 3, r, lv.h)
     q = ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"])
     for k in range(3):
@@ -227,7 +227,7 @@ def _fp32_case(ctx, graded):
     else:
         lid = ctx.add_rect_level(P.graded_L_rule(32))
         lv = mesh.graded_L_level(32)
-        r = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), T=0.5)
+        r = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), T=2.0)
         s = P.gen_samples(0, 0, 0, 3, r, lv.h)
     return lid, lv, s
 
@@ -323,7 +323,7 @@ def test_compact_workgroup_size_does_not_change_results(ctx, precision):
     lid = ctx.add_rect_level(P.graded_L_rule(32))
     info = ctx.set_tiling(lid, 0, 0, False)          # one 777-node region: 256-thread workgroups fit
     assert info["tile_rect"] == 0
-    r = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), T=0.3)
+    r = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), T=2.0)
     s = P.gen_samples(2, 0, 0, 700, r, 1 / 16)
     big = np.asarray(ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"], precision=precision))
     k = 5
@@ -345,7 +345,7 @@ def test_compact_mode_beyond_rect_p128(ctx):
     ctx.autotune(lid)
     lv = mesh.graded_L_level(16, layers=7)
     ops = fem.operators(lv)
-    r = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), T=0.4)
+    r = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), T=2.0)
     s = P.gen_samples(3, 0, 0, 6, r, lv.h)
     q = ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"])
     qb = ctx.batch_run([(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"], 0.05)], graph=True)
