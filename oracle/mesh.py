@@ -238,3 +238,83 @@ def lf_twin(lv: Level) -> Level:
                cell_block=lv.cell_block.copy(), cell_fine=np.zeros_like(lv.cell_fine),
                cell_qoi=lv.cell_qoi.copy(), n_blocks=lv.n_blocks, p=1, nu=lv.nu)
     return _finish(tw)
+
+
+# ---------------------------------------------------------------------------
+# Choice of the fine set on graded meshes (Sec. 3.5)
+# ---------------------------------------------------------------------------
+#
+# Sec. 3.5 takes the fine region D_f of a graded mesh as the union of the q
+# tiers of smallest elements; the time step of the coarse region is then set
+# by its own smallest elements (tier q+1), and q is chosen to minimise the LTS
+# cost, elements of D_f over h_1 plus elements of D_c over h_{q+1}
+# (eq. cost_waveeq_LTSgraded, optimum by eq. ddqS).
+#
+# Readings for the rectilinear geometric grading of graded_L_level: tier k
+# (k = 1..layers) holds the cells whose shorter leg is h 2^(k-1-layers) (tier 1
+# the smallest, h 2^-layers); cells whose shorter leg is h or longer are the
+# outer tier.  With q tiers fine, the fine cells are those with shorter leg
+# < h 2^(q-layers).  The coarse step of the level uses the spacing
+# H_q = 2 * (shortest coarse leg), and p_q = ceil(H_q / h_min): for
+# q = layers - 1 this is the workload's rule (fine cells with a leg < h/2,
+# H = h, p = ceil(h / h_min)), which is why the factor 2 is taken.  q = 0 has
+# no fine cells (plain leapfrog, p = 1).  The cost compared across q is the
+# DOF-update rate ((N - |P_q|) + p_q |P_q|) / H_q per unit time (the step
+# count is T c_max / (cfl H_q)); the smallest q wins a tie.
+
+def graded_L_tiers(n_base: int, q: int, layers: int = 6, lo: float = -1.0, hi: float = 1.0,
+                   blocks=(8, 8), qoi_box=(0.5, 0.9, 0.2, 0.6), nu: float = 0.01) -> Level:
+    """The graded L-shape level with the q smallest tiers fine (0 <= q <= layers)."""
+    if not 0 <= q <= layers:
+        raise ValueError("q must be in 0..layers")
+    xs = axis_graded(lo, hi, n_base, layers)
+    ys = xs.copy()
+    h = (hi - lo) / n_base
+    active, block, _, qoi = _cells(xs, ys, h, lambda mx, my: ~((mx > 0.0) & (my < 0.0)),
+                                   lo, hi, blocks[0], blocks[1], qoi_box)
+    HX, HY = np.meshgrid(np.diff(xs), np.diff(ys))
+    short = np.minimum(HX, HY)
+    fine = short < math.ldexp(h, q - layers)
+    coarse_short = short[active & ~fine]
+    H = 2.0 * float(coarse_short.min())
+    h_min = float(short[active].min())
+    lv = Level(xs=xs, ys=ys, h=H, cell_active=active, cell_block=block, cell_fine=fine,
+               cell_qoi=qoi, n_blocks=blocks[0] * blocks[1], p=1, nu=nu)
+    lv = _finish(lv)
+    if lv.Pmask.any():
+        lv.p = int(math.ceil(H / h_min))
+    return lv
+
+
+def lts_cost_rate(lv: Level) -> float:
+    """DOF updates per unit time and per unit T c_max / cfl: ((N - |P|) + p |P|) / H."""
+    n, nP = lv.n_dof, int(lv.Pmask.sum())
+    return ((n - nP) + lv.p * nP) / lv.h
+
+
+def qopt_tiers(n_base: int, layers: int = 6, **kw):
+    """(q_opt, costs): the number of fine tiers minimising the LTS cost rate."""
+    costs = [lts_cost_rate(graded_L_tiers(n_base, q, layers, **kw)) for q in range(layers + 1)]
+    q = min(range(layers + 1), key=lambda k: (costs[k], k))
+    return q, costs
+
+
+def cost_lts_graded_model(m: float, s: float, d: int, q: float) -> float:
+    """eq. cost_waveeq_LTSgraded: (m^(s+d) + m^s q^d ((q+1)^s - q^s - 1)) / ((q+1)^s - q^s),
+    the cost of one LTS solve on the radially graded mesh T_{m,s} with q fine layers."""
+    g = (q + 1.0) ** s - q ** s
+    return (m ** (s + d) + m ** s * q ** d * (g - 1.0)) / g
+
+
+def speedup_graded_model(m: float, s: float, d: int, q: float) -> float:
+    """eq. speedup_det_graded: C_LF / C_LTS = m^d ((q+1)^s - q^s) / (m^d + q^d ((q+1)^s - q^s - 1))."""
+    g = (q + 1.0) ** s - q ** s
+    return m ** d * g / (m ** d + q ** d * (g - 1.0))
+
+
+def ddq_speedup_graded_model(m: float, s: float, d: int, q: float) -> float:
+    """Left-hand side of eq. ddqS (proportional to the q-derivative of the speed-up)."""
+    g = (q + 1.0) ** s - q ** s
+    gs = (q + 1.0) ** (s - 1.0) - q ** (s - 1.0)
+    return (s * gs * (m ** d + q ** d * (g - 1.0))
+            - g * q ** (d - 1.0) * (d * (g - 1.0) + s * q * gs))

@@ -13,7 +13,9 @@ Readings: variances are computed two-pass with math.fsum instead of the
 single-pass sum-of-squares form (same value, no cancellation); C_l is the cost
 model of Sec. 3.3 counted in DOF updates per Delta Q_l sample with the
 nominal step dt = cfl*h (so that any two implementations choose the same
-N_l); the number of levels is capped by the given hierarchy.
+N_l); the number of levels is capped by the given hierarchy, which may build
+its levels on first use (LazyLevels), so that L grows beyond the levels that
+exist when Algorithm 1 starts.
 """
 from __future__ import annotations
 
@@ -78,6 +80,29 @@ def delta_Q(ops_list, seed: int, level: int, i: int, rule, width: float = 0.05):
     return qf, qc, qf - qc
 
 
+class LazyLevels:
+    """A level hierarchy whose level l is built by ``make(l)`` on first use,
+    l < n_max: Algorithm 1 adds a level whenever the bias test asks for one,
+    so the hierarchy need not exist in advance (Sec. 2.2)."""
+
+    def __init__(self, make, n_max: int):
+        self.make, self.n_max, self._lv = make, n_max, {}
+
+    def __len__(self):
+        return self.n_max
+
+    def __getitem__(self, l):
+        if not 0 <= l < self.n_max:
+            raise IndexError(l)
+        if l not in self._lv:
+            self._lv[l] = self.make(l)
+        return self._lv[l]
+
+    @property
+    def built(self):
+        return sorted(self._lv)
+
+
 @dataclass
 class MLMCResult:
     estimate: float
@@ -104,7 +129,18 @@ def mlmc(ops_list, rule, eps: float, seed: int = 0, N_init=(256, 64, 16, 8, 4), 
             return delta_Q(ops_list, seed, level, i, rule)[2]
     Lmax = len(ops_list) - 1
     L = min(L_start, Lmax)
-    C = list(costs) if costs is not None else level_costs(ops_list, rule)
+    solve_cost = {}
+
+    def cost_of(l):
+        """C_l, computed when level l is first used (ops_list may build levels lazily)."""
+        if costs is not None:
+            return costs[l]
+        for k in (l, l - 1):
+            if k >= 0 and k not in solve_cost:
+                solve_cost[k] = cost_per_solve(ops_list[k], rule)
+        return solve_cost[l] + (solve_cost[l - 1] if l > 0 else 0.0)
+
+    C = [cost_of(l) for l in range(L + 1)]
     N = [N_init[l] for l in range(L + 1)]
     dq = {l: [] for l in range(Lmax + 1)}
     grew = True
@@ -114,7 +150,7 @@ def mlmc(ops_list, rule, eps: float, seed: int = 0, N_init=(256, 64, 16, 8, 4), 
                 dq[l].append(eval_dq(l, i))
         mv = [mean_var(dq[l]) for l in range(L + 1)]
         V = [v for _, v in mv]
-        newN = optimal_N(eps, V, C[:L + 1])
+        newN = optimal_N(eps, V, C)
         grew = False
         for l in range(L + 1):
             if newN[l] > N[l]:
@@ -124,11 +160,12 @@ def mlmc(ops_list, rule, eps: float, seed: int = 0, N_init=(256, 64, 16, 8, 4), 
         if bias * bias >= 0.5 * eps * eps and L < Lmax:
             L += 1
             N.append(N_init[L])
+            C.append(cost_of(L))
             grew = True
     mv = [mean_var(dq[l][:N[l]]) for l in range(L + 1)]
     est = math.fsum(m for m, _ in mv)
     bias = bias_estimate(mv[L][0], alpha)
     var_est = math.fsum(v / n for (_, v), n in zip(mv, N))
     return MLMCResult(estimate=est, L=L, N=N, mean=[m for m, _ in mv], var=[v for _, v in mv],
-                      cost=C[:L + 1], bias=bias, rmse=math.sqrt(var_est + bias * bias),
+                      cost=C, bias=bias, rmse=math.sqrt(var_est + bias * bias),
                       samples={l: dq[l][:N[l]] for l in range(L + 1)})
