@@ -134,7 +134,7 @@ def _mlmc_cpu_worker(args):
     return lvl, (time.perf_counter() - t0) / steps
 
 
-def mlmc_bench(no_cpu: bool, eps_list=MLMC_EPS, emit: bool = True, plain: bool = True):
+def mlmc_bench(no_cpu: bool, eps_list=MLMC_EPS, emit: bool = True, plain: bool = True, fine_tiers=None):
     """Algorithm 1 on the graded L-shape hierarchy (h = 1/16 .. 1/256, p = 64, 8x8
     blocks sigma 0.3, T = 2) at the workload's eps = 1e-3 and a tighter 1e-4: wall
     time of the batched + graph form and of the plain form (one launch per sample
@@ -157,13 +157,15 @@ def mlmc_bench(no_cpu: bool, eps_list=MLMC_EPS, emit: bool = True, plain: bool =
     import paper_2106_11117_amd as P
 
     ctx = P.Context(0)
-    ids = [ctx.add_rect_level(P.graded_L_rule(nb)) for nb in MLMC_BASES]
+    ids = [ctx.add_rect_level(P.graded_L_rule(nb, fine_tiers=fine_tiers)) for nb in MLMC_BASES]
     rule = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), width=0.05, T=2.0)
     t0 = time.perf_counter()
     for lid in ids:
         ctx.autotune(lid)
     setup = time.perf_counter() - t0
     info = [ctx.level_info(l) for l in ids]
+    print("levels (h, p, |P|): " + ", ".join(f"({i['h']}, {i['p']}, {i['n_P']})" for i in info), file=sys.stderr,
+          flush=True)
     runs = []
     for eps in eps_list:
         t0 = time.perf_counter()
@@ -198,7 +200,9 @@ def mlmc_bench(no_cpu: bool, eps_list=MLMC_EPS, emit: bool = True, plain: bool =
                                   "(h_min = h/64, p = 64), 8x8 blocks sigma 0.3, T = 2, "
                                   "QoI [0.5,0.9]x[0.2,0.6]; eps absolute",
                       "N_init": list(MLMC_N_INIT), "L_start": 2,
-                      "dofs": [i["n_dof"] for i in info], "P": [i["n_P"] for i in info]},
+                      "fine_set": "leg < h/2" if fine_tiers is None else f"tiers {fine_tiers}",
+                      "dofs": [i["n_dof"] for i in info], "P": [i["n_P"] for i in info],
+                      "p": [i["p"] for i in info], "h_step": [i["h"] for i in info]},
            "setup_autotune_s": setup, "runs": runs,
            "cpu_oracle": None if per_step is None else {
                "seconds_per_step_by_level": [per_step[l] for l in range(len(ids))], "cores": procs,
@@ -454,6 +458,8 @@ def main():
                     help="only run the MLMC wall-time comparison (graded L-shape, Algorithm 1)")
     ap.add_argument("--eps", type=float, nargs="+", help="with --mlmc: the RMSE targets (default 1e-3 1e-4)")
     ap.add_argument("--no-plain", action="store_true", help="with --mlmc: skip the plain form")
+    ap.add_argument("--qopt", action="store_true",
+                    help="with --mlmc: fine sets of the q cost-optimal tiers (Sec. 3.5) instead of legs < h/2")
     ap.add_argument("--batch", action="store_true",
                     help="only time the batched multi-level form on the graded L-shape hierarchy "
                          "(with --plain: also the one-launch-per-sample form)")
@@ -465,7 +471,8 @@ def main():
         adjoint_bench(args.samples, 64)
         return
     if args.mlmc:
-        mlmc_bench(args.no_cpu, tuple(args.eps) if args.eps else MLMC_EPS, plain=not args.no_plain)
+        mlmc_bench(args.no_cpu, tuple(args.eps) if args.eps else MLMC_EPS, plain=not args.no_plain,
+                   fine_tiers="opt" if args.qopt else None)
         return
     if args.copy_check:
         copy_check(args.copy_check)

@@ -124,6 +124,19 @@ enum { LTS_RULE_BOX = 0, LTS_RULE_GRADED_L = 1, LTS_RULE_LF = 0x100 };
  * cells with no fine cells (P empty) and p = 1, so every step is one plain
  * leapfrog step over all DOFs, and nominal spacing h/p (p of the LTS level),
  * so that samples drawn for it step at dt/p on every element. */
+/* Fine set of a graded level (fine_rule of lts_rect_rule; Sec. 3.5).
+ *  LTS_FINE_HALF_H: cells with a leg shorter than h/2, step spacing h (the
+ *    workloads' rule; the only one for LTS_RULE_BOX).
+ *  LTS_FINE_TIERS: the fine_tiers = q smallest tiers, q in 0..layers.  Tier k
+ *    holds the cells whose shorter leg is h 2^(k-1-layers); the coarse step
+ *    uses the spacing H = 2 x (shortest coarse leg), so that the coarse time
+ *    step follows the smallest coarse elements, and p = ceil(H / h_min)
+ *    (p = 1 when q = 0: plain leapfrog).  q = layers - 1 is LTS_FINE_HALF_H.
+ *  LTS_FINE_QOPT: q chosen to minimise the DOF-update rate
+ *    ((N - |P_q|) + p_q |P_q|) / H_q, the LTS cost per unit time (the smallest
+ *    q on a tie); fine_tiers is ignored. */
+enum { LTS_FINE_HALF_H = 0, LTS_FINE_TIERS = 1, LTS_FINE_QOPT = 2 };
+
 typedef struct {
   int32_t kind;
   double lo, hi;
@@ -133,8 +146,10 @@ typedef struct {
   int32_t layers;
   int32_t nbx, nby;
   double qx_lo, qx_hi, qy_lo, qy_hi;
-  int32_t p;
+  int32_t p;                      /* > 0 overrides the p of the rule */
   double nu;
+  int32_t fine_rule;              /* LTS_FINE_* (0: LTS_FINE_HALF_H) */
+  int32_t fine_tiers;             /* q for LTS_FINE_TIERS */
 } lts_rect_rule;
 
 /* Build the level described by `rule` on the host, then lts_add_level it.
@@ -390,16 +405,20 @@ enum { LTS_MLMC_BATCHED = 0, LTS_MLMC_PLAIN = 1 };
 #define LTS_MAX_LEVELS 8
 
 typedef struct {
-  int32_t n_levels;               /* levels available, 1..LTS_MAX_LEVELS */
+  int32_t n_levels;               /* levels given in level_ids, 0..LTS_MAX_LEVELS */
   int32_t level_ids[LTS_MAX_LEVELS];
   lts_sample_rule rule;
   uint64_t seed;
   double eps;                     /* RMSE target */
   double alpha;                   /* bias decay rate of the bias estimate (2 in the paper) */
   int32_t L_start;                /* initial finest level (Algorithm 1 starts at 2) */
-  int32_t N_init[LTS_MAX_LEVELS]; /* initial sample counts */
+  int32_t N_init[LTS_MAX_LEVELS]; /* initial sample counts, >= 2 for every level that may be used */
   int32_t mode;                   /* LTS_MLMC_BATCHED or LTS_MLMC_PLAIN */
   int32_t max_total_samples;      /* safety cap (<= 0: none) */
+  int32_t n_levels_max;           /* > n_levels: levels n_levels .. n_levels_max-1 are built
+                                     from gen_rule when Algorithm 1 first needs them */
+  lts_rect_rule gen_rule;         /* level l of a generated hierarchy: gen_rule with
+                                     n_base = gen_rule.n_base * 2^l */
 } lts_mlmc_opts;
 
 typedef struct {
@@ -412,13 +431,17 @@ typedef struct {
   double bias;                    /* |mean Delta Q_L| / (2^alpha - 1) */
   double rmse;                    /* sqrt(sum V_l/N_l + bias^2) */
   int32_t converged;              /* 1 if the bias test passed at the final L */
-  double seconds;                 /* wall time of the solves */
+  double seconds;                 /* wall time of the solves (generated levels' set-up included) */
+  int32_t level_ids[LTS_MAX_LEVELS]; /* context level id of every level used (generated ones too) */
 } lts_mlmc_result;
 
-/* Algorithm 1: start with L = min(L_start, n_levels-1) and N_init; repeat
+/* Algorithm 1: start with L = min(L_start, Lmax) and N_init; repeat
  * {solve the missing Delta Q samples; estimate V_l; raise N_l to
  * ceil(2/eps^2 sqrt(V_l/C_l) sum sqrt(V C)); if the bias estimate exceeds
- * eps/sqrt(2) and a finer level exists, add it} until no N_l grew.
+ * eps/sqrt(2) and L < Lmax, add level L+1} until no N_l grew.
+ * Lmax + 1 = max(n_levels, n_levels_max): with n_levels_max > n_levels the
+ * hierarchy grows beyond the given levels, each new level built (and added to
+ * the context) only when the bias test asks for it.
  * C_l is the cost model in DOF updates per sample with the nominal step
  * cfl*h.  Errors: LTS_ERR_ARG, LTS_ERR_OOM, LTS_ERR_HIP, LTS_ERR_UNSTABLE. */
 lts_status lts_mlmc(lts_ctx ctx, const lts_mlmc_opts* opts, lts_mlmc_result* out);

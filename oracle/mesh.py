@@ -258,7 +258,8 @@ def lf_twin(lv: Level) -> Level:
 # H_q = 2 * (shortest coarse leg), and p_q = ceil(H_q / h_min): for
 # q = layers - 1 this is the workload's rule (fine cells with a leg < h/2,
 # H = h, p = ceil(h / h_min)), which is why the factor 2 is taken.  q = 0 has
-# no fine cells (plain leapfrog, p = 1).  The cost compared across q is the
+# no fine cells (plain leapfrog, p = 1: p is ceil(H / h_min) whenever an
+# active cell is fine).  The cost compared across q is the
 # DOF-update rate ((N - |P_q|) + p_q |P_q|) / H_q per unit time (the step
 # count is T c_max / (cfl H_q)); the smallest q wins a tie.
 
@@ -281,7 +282,7 @@ def graded_L_tiers(n_base: int, q: int, layers: int = 6, lo: float = -1.0, hi: f
     lv = Level(xs=xs, ys=ys, h=H, cell_active=active, cell_block=block, cell_fine=fine,
                cell_qoi=qoi, n_blocks=blocks[0] * blocks[1], p=1, nu=nu)
     lv = _finish(lv)
-    if lv.Pmask.any():
+    if (fine & active).any():
         lv.p = int(math.ceil(H / h_min))
     return lv
 

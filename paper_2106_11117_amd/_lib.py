@@ -19,6 +19,7 @@ LTS_RULE_BOX, LTS_RULE_GRADED_L, LTS_RULE_LF = 0, 1, 0x100
 LTS_BATCH_GRAPH = 1
 LTS_BATCH_FP32 = 2
 LTS_MLMC_BATCHED, LTS_MLMC_PLAIN = 0, 1
+LTS_FINE_HALF_H, LTS_FINE_TIERS, LTS_FINE_QOPT = 0, 1, 2
 LTS_MAX_LEVELS = 8
 LTS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -42,7 +43,8 @@ class RectRule(C.Structure):
                 ("box_lo", C.c_double), ("box_hi", C.c_double), ("ref", C.c_int32),
                 ("layers", C.c_int32), ("nbx", C.c_int32), ("nby", C.c_int32),
                 ("qx_lo", C.c_double), ("qx_hi", C.c_double), ("qy_lo", C.c_double),
-                ("qy_hi", C.c_double), ("p", C.c_int32), ("nu", C.c_double)]
+                ("qy_hi", C.c_double), ("p", C.c_int32), ("nu", C.c_double),
+                ("fine_rule", C.c_int32), ("fine_tiers", C.c_int32)]
 
 
 class LevelInfo(C.Structure):
@@ -80,14 +82,15 @@ class MLMCOpts(C.Structure):
                 ("rule", SampleRule), ("seed", C.c_uint64), ("eps", C.c_double),
                 ("alpha", C.c_double), ("L_start", C.c_int32),
                 ("N_init", C.c_int32 * LTS_MAX_LEVELS), ("mode", C.c_int32),
-                ("max_total_samples", C.c_int32)]
+                ("max_total_samples", C.c_int32), ("n_levels_max", C.c_int32), ("gen_rule", RectRule)]
 
 
 class MLMCResult(C.Structure):
     _fields_ = [("estimate", C.c_double), ("L", C.c_int32), ("N", C.c_int32 * LTS_MAX_LEVELS),
                 ("mean", C.c_double * LTS_MAX_LEVELS), ("var", C.c_double * LTS_MAX_LEVELS),
                 ("cost", C.c_double * LTS_MAX_LEVELS), ("bias", C.c_double), ("rmse", C.c_double),
-                ("converged", C.c_int32), ("seconds", C.c_double)]
+                ("converged", C.c_int32), ("seconds", C.c_double),
+                ("level_ids", C.c_int32 * LTS_MAX_LEVELS)]
 
 
 class Timing(C.Structure):

@@ -155,6 +155,48 @@ static bool axis_graded(double lo, double hi, int n, int layers, std::vector<dou
   return true;
 }
 
+// DOFs (nodes whose four cells are active) and the DOFs that are a vertex of
+// a fine cell, for per-cell flags on an nxc x nyc grid.
+static void count_dof_p(int nxc, int nyc, const std::vector<uint8_t>& active, const std::vector<uint8_t>& fine,
+                        long long& n_dof, long long& n_p) {
+  n_dof = n_p = 0;
+  auto cell = [&](const std::vector<uint8_t>& f, int a, int b) { return f[(size_t)b * nxc + a] != 0; };
+  for (int j = 1; j < nyc; ++j)
+    for (int i = 1; i < nxc; ++i) {
+      if (!(cell(active, i, j) && cell(active, i - 1, j) && cell(active, i, j - 1) && cell(active, i - 1, j - 1)))
+        continue;
+      ++n_dof;
+      if (cell(fine, i, j) || cell(fine, i - 1, j) || cell(fine, i, j - 1) || cell(fine, i - 1, j - 1)) ++n_p;
+    }
+}
+
+// Fine set of the q smallest tiers of a graded level (Sec. 3.5): tier k holds
+// the cells whose shorter leg is h 2^(k-1-layers), so the q smallest tiers are
+// the cells with shorter leg < h 2^(q-layers).  The coarse step uses the
+// spacing H = 2 x (shortest coarse leg) and p = ceil(H / h_min) (q = layers-1
+// gives the rule "a leg < h/2" with H = h); with no fine cell, p = 1.
+static void tier_fine_set(const std::vector<double>& x, const std::vector<double>& y,
+                          const std::vector<uint8_t>& active, double h, int layers, int q,
+                          std::vector<uint8_t>& fine, double& H, int& p) {
+  const int nxc = (int)x.size() - 1, nyc = (int)y.size() - 1;
+  const double thr = std::ldexp(h, q - layers);
+  double cmin = INFINITY, hmin = INFINITY;
+  bool any = false;
+  fine.assign((size_t)nxc * nyc, 0);
+  for (int b = 0; b < nyc; ++b)
+    for (int a = 0; a < nxc; ++a) {
+      const size_t c = (size_t)b * nxc + a;
+      const double sh = std::min(x[a + 1] - x[a], y[b + 1] - y[b]);
+      fine[c] = sh < thr;
+      if (!active[c]) continue;
+      hmin = std::min(hmin, sh);
+      if (fine[c]) any = true;
+      else cmin = std::min(cmin, sh);
+    }
+  H = 2.0 * cmin;
+  p = any ? (int)std::ceil(H / hmin) : 1;
+}
+
 std::string build_rect_desc(const lts_rect_rule& r, std::vector<double>& x, std::vector<double>& y,
                             std::vector<uint8_t>& active, std::vector<int32_t>& block,
                             std::vector<uint8_t>& fine, std::vector<uint8_t>& qoi, double& h, int& p,
@@ -199,6 +241,33 @@ std::string build_rect_desc(const lts_rect_rule& r, std::vector<double>& x, std:
       qoi[c] = (r.qx_lo <= mx && mx <= r.qx_hi && r.qy_lo <= my && my <= r.qy_hi);
     }
   p = r.p > 0 ? r.p : (int)std::ceil(h / hmin);
+  if (r.fine_rule != LTS_FINE_HALF_H) {
+    if (kind != LTS_RULE_GRADED_L) return "rule: tier fine sets need a graded level";
+    int q = r.fine_tiers;
+    if (r.fine_rule == LTS_FINE_QOPT) {
+      // q minimising the DOF-update rate ((N - |P_q|) + p_q |P_q|) / H_q, the
+      // cost of Sec. 3.4 per unit time; the smallest q on a tie
+      double best = INFINITY;
+      for (int k = 0; k <= r.layers; ++k) {
+        std::vector<uint8_t> f;
+        double Hk;
+        int pk;
+        tier_fine_set(x, y, active, h, r.layers, k, f, Hk, pk);
+        long long n, np;
+        count_dof_p(nxc, nyc, active, f, n, np);
+        const double rate = (double)((n - np) + (long long)pk * np) / Hk;
+        if (rate < best) {
+          best = rate;
+          q = k;
+        }
+      }
+    } else if (r.fine_rule != LTS_FINE_TIERS) {
+      return "rule: unknown fine_rule";
+    }
+    if (q < 0 || q > r.layers) return "rule: fine_tiers must be in 0..layers";
+    tier_fine_set(x, y, active, h, r.layers, q, fine, h, p);
+    if (r.p > 0) p = r.p;
+  }
   if (lf) {                                  // standard leapfrog twin: no fine cells, step dt/p
     std::fill(fine.begin(), fine.end(), (uint8_t)0);
     h /= p;

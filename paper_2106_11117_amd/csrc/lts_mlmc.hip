@@ -106,26 +106,54 @@ extern "C" lts_status lts_mlmc(lts_ctx c, const lts_mlmc_opts* op, lts_mlmc_resu
   if (!c) return LTS_ERR_ARG;
   c->err.clear();
   if (!op || !out) return arg_fail(c, "NULL argument");
-  const lts_mlmc_opts& o = *op;
-  if (o.n_levels < 1 || o.n_levels > LTS_MAX_LEVELS) return arg_fail(c, "n_levels out of range");
-  for (int l = 0; l < o.n_levels; ++l) {
+  lts_mlmc_opts o = *op;                    // level_ids grows with generated levels
+  const int n_total = std::max(o.n_levels, o.n_levels_max);
+  if (o.n_levels < 0 || n_total < 1 || n_total > LTS_MAX_LEVELS) return arg_fail(c, "n_levels out of range");
+  for (int l = 0; l < o.n_levels; ++l)
     if (o.level_ids[l] < 0 || o.level_ids[l] >= (int)c->levels.size()) return arg_fail(c, "bad level id");
+  for (int l = 0; l < n_total; ++l)
     if (o.N_init[l] < 2) return arg_fail(c, "N_init must be >= 2 (variance estimates)");
-  }
   if (!(o.eps > 0.0) || !(o.alpha > 0.0)) return arg_fail(c, "eps and alpha must be > 0");
-  const int Lmax = o.n_levels - 1;
-  int L = std::min(std::max(o.L_start, 0), Lmax);
-  // cost model C_l in DOF updates per Delta Q_l sample
-  std::vector<double> cs(o.n_levels), C(o.n_levels);
-  for (int l = 0; l < o.n_levels; ++l) cs[l] = solve_cost_model(c->levels[o.level_ids[l]]->H, o.rule);
-  for (int l = 0; l < o.n_levels; ++l) C[l] = l == 0 ? cs[0] : cs[l] + cs[l - 1];
-  std::vector<int64_t> N(o.n_levels, 0);
-  for (int l = 0; l <= L; ++l) N[l] = o.N_init[l];
-  std::vector<std::vector<double>> dq(o.n_levels);
-  std::vector<double> mean(o.n_levels, 0.0), var(o.n_levels, 0.0);
+  if (n_total > o.n_levels) {
+    // the generated levels must be valid rules (checked on the host, no device work)
+    for (int l = o.n_levels; l < n_total; ++l) {
+      lts_rect_rule g = o.gen_rule;
+      g.n_base = o.gen_rule.n_base << l;
+      lts_level_info info;
+      if (lts_rect_level_host(&g, &info, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr) != LTS_OK)
+        return arg_fail(c, "gen_rule does not build level " + std::to_string(l));
+    }
+  }
+  const int Lmax = n_total - 1;
   auto t0 = std::chrono::steady_clock::now();
-  bool grew = true;
+  // level l exists in the context (built from gen_rule on first use)
+  auto ensure_level = [&](int l) -> lts_status {
+    if (l < o.n_levels) return LTS_OK;
+    lts_rect_rule g = o.gen_rule;
+    g.n_base = o.gen_rule.n_base << l;
+    int32_t id = -1;
+    lts_status rr = lts_build_rect_level(c, &g, &id);
+    if (rr != LTS_OK) return rr;
+    o.level_ids[l] = id;
+    o.n_levels = l + 1;
+    return LTS_OK;
+  };
+  int L = std::min(std::max(o.L_start, 0), Lmax);
   lts_status r;
+  for (int l = 0; l <= L; ++l)
+    if ((r = ensure_level(l)) != LTS_OK) return r;
+  // cost model C_l in DOF updates per Delta Q_l sample, formed as levels are added
+  std::vector<double> cs(n_total, 0.0), C(n_total, 0.0);
+  auto add_cost = [&](int l) {
+    cs[l] = solve_cost_model(c->levels[o.level_ids[l]]->H, o.rule);
+    C[l] = l == 0 ? cs[0] : cs[l] + cs[l - 1];
+  };
+  for (int l = 0; l <= L; ++l) add_cost(l);
+  std::vector<int64_t> N(n_total, 0);
+  for (int l = 0; l <= L; ++l) N[l] = o.N_init[l];
+  std::vector<std::vector<double>> dq(n_total);
+  std::vector<double> mean(n_total, 0.0), var(n_total, 0.0);
+  bool grew = true;
   while (grew) {
     int64_t total = 0;
     for (int l = 0; l <= L; ++l) total += N[l];
@@ -160,6 +188,8 @@ extern "C" lts_status lts_mlmc(lts_ctx c, const lts_mlmc_opts* op, lts_mlmc_resu
     const double bias = std::fabs(mean[L]) / (std::pow(2.0, o.alpha) - 1.0);
     if (bias * bias >= 0.5 * o.eps * o.eps && L < Lmax) {
       ++L;
+      if ((r = ensure_level(L)) != LTS_OK) return r;
+      add_cost(L);
       N[L] = o.N_init[L];
       grew = true;
     }
@@ -174,6 +204,7 @@ extern "C" lts_status lts_mlmc(lts_ctx c, const lts_mlmc_opts* op, lts_mlmc_resu
     out->mean[l] = mean[l];
     out->var[l] = var[l];
     out->cost[l] = C[l];
+    out->level_ids[l] = o.level_ids[l];
   }
   const double bias = std::fabs(mean[L]) / (std::pow(2.0, o.alpha) - 1.0);
   out->estimate = est;

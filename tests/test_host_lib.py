@@ -194,3 +194,27 @@ def test_adaptive_tiling_cuts_across_bands():
         P.tiling_host(P.graded_L_rule(64), 0, 0, True)
     with pytest.raises(P.LtsError):
         P.tiling_host(P.graded_L_rule(64), 0, 8, False)
+
+
+@pytest.mark.parametrize("n_base,layers", [(8, 2), (32, 6), (64, 6)])
+def test_tier_fine_sets_match_oracle(n_base, layers):
+    """Graded levels whose fine set is the q smallest tiers (Sec. 3.5), and the q
+    chosen by the cost model: the library's host builder and the oracle agree
+    bit for bit (step spacing, p, flags, lumped mass, QoI weights) and choose
+    the same q."""
+    import numpy as np
+    from oracle import mesh
+    for q in list(range(layers + 1)) + ["opt"]:
+        d = P.rect_level_host(P.graded_L_rule(n_base, layers=layers, fine_tiers=q))
+        qq = mesh.qopt_tiers(n_base, layers=layers)[0] if q == "opt" else q
+        lv = mesh.graded_L_tiers(n_base, qq, layers=layers)
+        assert (d["h"], d["p"], d["n_dof"], d["n_P"]) == (lv.h, lv.p, lv.n_dof, int(lv.Pmask.sum())), q
+        assert np.array_equal((d["flags"] & P.LTS_NODE_P) != 0, lv.Pmask)
+        assert np.array_equal(d["mass"], lv.mass) and np.array_equal(d["qoi_w"], lv.qoi_w)
+    # the tier rule at q = layers - 1 is the default rule
+    a = P.rect_level_host(P.graded_L_rule(n_base, layers=layers))
+    b = P.rect_level_host(P.graded_L_rule(n_base, layers=layers, fine_tiers=layers - 1))
+    assert (a["h"], a["p"], a["n_P"]) == (b["h"], b["p"], b["n_P"])
+    assert np.array_equal(a["flags"], b["flags"])
+    with pytest.raises(P.LtsError):
+        P.rect_level_host(P.graded_L_rule(n_base, layers=layers, fine_tiers=layers + 1))
