@@ -157,7 +157,10 @@ def mlmc_bench(no_cpu: bool, eps_list=MLMC_EPS, emit: bool = True, plain: bool =
     import paper_2106_11117_amd as P
 
     ctx = P.Context(0)
-    ids = [ctx.add_rect_level(P.graded_L_rule(nb, fine_tiers=fine_tiers)) for nb in MLMC_BASES]
+    # the cost-optimal tiers with p <= 64: a larger p on the finest level leaves
+    # fine-tile regions (the F+ band within p of a tile) beyond one workgroup
+    ids = [ctx.add_rect_level(P.graded_L_rule(nb, fine_tiers=fine_tiers, p_max=64 if fine_tiers else 0))
+           for nb in MLMC_BASES]
     rule = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), width=0.05, T=2.0)
     t0 = time.perf_counter()
     for lid in ids:
@@ -200,7 +203,7 @@ def mlmc_bench(no_cpu: bool, eps_list=MLMC_EPS, emit: bool = True, plain: bool =
                                   "(h_min = h/64, p = 64), 8x8 blocks sigma 0.3, T = 2, "
                                   "QoI [0.5,0.9]x[0.2,0.6]; eps absolute",
                       "N_init": list(MLMC_N_INIT), "L_start": 2,
-                      "fine_set": "leg < h/2" if fine_tiers is None else f"tiers {fine_tiers}",
+                      "fine_set": "leg < h/2" if fine_tiers is None else f"tiers {fine_tiers}, p <= 64",
                       "dofs": [i["n_dof"] for i in info], "P": [i["n_P"] for i in info],
                       "p": [i["p"] for i in info], "h_step": [i["h"] for i in info]},
            "setup_autotune_s": setup, "runs": runs,

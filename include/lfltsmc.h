@@ -134,7 +134,9 @@ enum { LTS_RULE_BOX = 0, LTS_RULE_GRADED_L = 1, LTS_RULE_LF = 0x100 };
  *    (p = 1 when q = 0: plain leapfrog).  q = layers - 1 is LTS_FINE_HALF_H.
  *  LTS_FINE_QOPT: q chosen to minimise the DOF-update rate
  *    ((N - |P_q|) + p_q |P_q|) / H_q, the LTS cost per unit time (the smallest
- *    q on a tie); fine_tiers is ignored. */
+ *    q on a tie), among the q with p_q <= p_max when p_max > 0 (a fine-tile
+ *    region holds the F+ nodes within p of its tile, so very large p can leave
+ *    a level that no tile shape fits); fine_tiers is ignored. */
 enum { LTS_FINE_HALF_H = 0, LTS_FINE_TIERS = 1, LTS_FINE_QOPT = 2 };
 
 typedef struct {
@@ -150,6 +152,7 @@ typedef struct {
   double nu;
   int32_t fine_rule;              /* LTS_FINE_* (0: LTS_FINE_HALF_H) */
   int32_t fine_tiers;             /* q for LTS_FINE_TIERS */
+  int32_t p_max;                  /* LTS_FINE_QOPT: largest p allowed (0: none) */
 } lts_rect_rule;
 
 /* Build the level described by `rule` on the host, then lts_add_level it.
@@ -445,6 +448,21 @@ typedef struct {
  * C_l is the cost model in DOF updates per sample with the nominal step
  * cfl*h.  Errors: LTS_ERR_ARG, LTS_ERR_OOM, LTS_ERR_HIP, LTS_ERR_UNSTABLE. */
 lts_status lts_mlmc(lts_ctx ctx, const lts_mlmc_opts* opts, lts_mlmc_result* out);
+
+/* Algorithm 1 with the gradient of the QoI estimated alongside it: every
+ * sample of every level is solved by the backward LF-LTS (lts_backward with
+ * dL/dQ = 1, checkpoints every K_ckpt steps) on the fine and the coarse mesh,
+ * which gives Q_l, Q_l-1 (equal bit for bit to the forward solves, so L, N_l
+ * and *out are those of lts_mlmc) and dQ_l/dg, dQ_l-1/dg on the same sample.
+ * Per level l <= out->L and block b: grad_mean[l*n_blocks + b] and
+ * grad_var[l*n_blocks + b] are the mean and unbiased variance of
+ * dG_l = dQ_l/dg_b - dQ_l-1/dg_b (dQ_0/dg_b for l = 0), reduced on the device
+ * like lts_moments; grad_estimate[b] = sum_l grad_mean[l][b] estimates
+ * dE[Q]/dg_b.  Levels not used are set to 0.  Host arrays of n_blocks, and
+ * LTS_MAX_LEVELS x n_blocks.  Every used level needs p <= 64 (the adjoint's
+ * limit).  Errors as lts_mlmc and lts_backward. */
+lts_status lts_mlmc_grad(lts_ctx ctx, const lts_mlmc_opts* opts, int32_t K_ckpt, lts_mlmc_result* out,
+                         double* grad_estimate, double* grad_mean, double* grad_var);
 
 /* ------------------------------------------------------------------------ */
 /* Timing of the last forward call (for benchmarks)                          */

@@ -293,10 +293,13 @@ def lts_cost_rate(lv: Level) -> float:
     return ((n - nP) + lv.p * nP) / lv.h
 
 
-def qopt_tiers(n_base: int, layers: int = 6, **kw):
-    """(q_opt, costs): the number of fine tiers minimising the LTS cost rate."""
-    costs = [lts_cost_rate(graded_L_tiers(n_base, q, layers, **kw)) for q in range(layers + 1)]
-    q = min(range(layers + 1), key=lambda k: (costs[k], k))
+def qopt_tiers(n_base: int, layers: int = 6, p_max: int = 0, **kw):
+    """(q_opt, costs): the number of fine tiers minimising the LTS cost rate,
+    among the q whose p is at most p_max when p_max > 0 (q = 0 always is)."""
+    lvs = [graded_L_tiers(n_base, q, layers, **kw) for q in range(layers + 1)]
+    costs = [lts_cost_rate(lv) for lv in lvs]
+    ok = [q for q in range(layers + 1) if p_max <= 0 or lvs[q].p <= p_max]
+    q = min(ok, key=lambda k: (costs[k], k))
     return q, costs
 
 

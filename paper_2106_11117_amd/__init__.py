@@ -38,10 +38,11 @@ def box_rule(n_base, box=(0.45, 0.55), ref=4, lo=0.0, hi=1.0, blocks=(4, 4),
 
 
 def graded_L_rule(n_base, layers=6, lo=-1.0, hi=1.0, blocks=(8, 8), qoi=(0.5, 0.9, 0.2, 0.6),
-                  p=0, nu=0.01, fine_tiers=None) -> _lib.RectRule:
+                  p=0, nu=0.01, fine_tiers=None, p_max=0) -> _lib.RectRule:
     """L-shape [lo,hi]^2 minus the quadrant x > 0, y < 0, graded toward the corner.
     fine_tiers: None (cells with a leg < h/2), an int q (the q smallest tiers)
-    or "opt" (q by the LTS cost model; see LTS_FINE_QOPT)."""
+    or "opt" (q by the LTS cost model among the q with p <= p_max if p_max > 0;
+    see LTS_FINE_QOPT)."""
     rule, q = _lib.LTS_FINE_HALF_H, 0
     if fine_tiers == "opt":
         rule = _lib.LTS_FINE_QOPT
@@ -50,7 +51,7 @@ def graded_L_rule(n_base, layers=6, lo=-1.0, hi=1.0, blocks=(8, 8), qoi=(0.5, 0.
     return _lib.RectRule(kind=LTS_RULE_GRADED_L, lo=lo, hi=hi, n_base=n_base, box_lo=0.0, box_hi=0.0,
                          ref=1, layers=layers, nbx=blocks[0], nby=blocks[1], qx_lo=qoi[0],
                          qx_hi=qoi[1], qy_lo=qoi[2], qy_hi=qoi[3], p=p, nu=nu, fine_rule=rule,
-                         fine_tiers=q)
+                         fine_tiers=q, p_max=p_max)
 
 
 def lf_rule(rule) -> _lib.RectRule:
@@ -335,10 +336,12 @@ class Context:
         return out
 
     def mlmc(self, level_ids, rule, eps, seed=0, alpha=2.0, L_start=2, N_init=(256, 64, 16, 8, 4),
-             mode=LTS_MLMC_BATCHED, max_total_samples=0, gen_rule=None, n_levels_max=0):
+             mode=LTS_MLMC_BATCHED, max_total_samples=0, gen_rule=None, n_levels_max=0, grad_K=None):
         """Algorithm 1 (lts_mlmc).  With gen_rule and n_levels_max > len(level_ids)
         the hierarchy grows on demand: level l beyond the given ones is built from
-        gen_rule with n_base * 2^l when the bias test first asks for it."""
+        gen_rule with n_base * 2^l when the bias test first asks for it.  With
+        grad_K (checkpoint interval) the gradient dE[Q]/dg is estimated alongside
+        (lts_mlmc_grad): keys grad, grad_mean [L+1, nb], grad_var [L+1, nb]."""
         o = _lib.MLMCOpts()
         o.n_levels = len(level_ids)
         for k, l in enumerate(level_ids):
@@ -356,12 +359,20 @@ class Context:
         if gen_rule is not None:
             o.gen_rule = gen_rule
         r = _lib.MLMCResult()
-        self._c(self.lib.lts_mlmc(self.h, C.byref(o), C.byref(r)))
+        nb = rule.n_blocks
+        if grad_K is not None:
+            ge, gm, gv = np.zeros(nb), np.zeros((_lib.LTS_MAX_LEVELS, nb)), np.zeros((_lib.LTS_MAX_LEVELS, nb))
+            self._c(self.lib.lts_mlmc_grad(self.h, C.byref(o), grad_K, C.byref(r), _dp(ge), _dp(gm), _dp(gv)))
+        else:
+            self._c(self.lib.lts_mlmc(self.h, C.byref(o), C.byref(r)))
         L = r.L
-        return {"estimate": r.estimate, "L": L, "N": list(r.N[:L + 1]), "mean": list(r.mean[:L + 1]),
-                "var": list(r.var[:L + 1]), "cost": list(r.cost[:L + 1]), "bias": r.bias,
-                "rmse": r.rmse, "converged": bool(r.converged), "seconds": r.seconds,
-                "level_ids": list(r.level_ids[:L + 1])}
+        out = {"estimate": r.estimate, "L": L, "N": list(r.N[:L + 1]), "mean": list(r.mean[:L + 1]),
+               "var": list(r.var[:L + 1]), "cost": list(r.cost[:L + 1]), "bias": r.bias,
+               "rmse": r.rmse, "converged": bool(r.converged), "seconds": r.seconds,
+               "level_ids": list(r.level_ids[:L + 1])}
+        if grad_K is not None:
+            out.update(grad=ge, grad_mean=gm[:L + 1], grad_var=gv[:L + 1])
+        return out
 
     def set_timing(self, on=True):
         self._c(self.lib.lts_set_timing(self.h, 1 if on else 0))

@@ -44,7 +44,7 @@ class RectRule(C.Structure):
                 ("layers", C.c_int32), ("nbx", C.c_int32), ("nby", C.c_int32),
                 ("qx_lo", C.c_double), ("qx_hi", C.c_double), ("qy_lo", C.c_double),
                 ("qy_hi", C.c_double), ("p", C.c_int32), ("nu", C.c_double),
-                ("fine_rule", C.c_int32), ("fine_tiers", C.c_int32)]
+                ("fine_rule", C.c_int32), ("fine_tiers", C.c_int32), ("p_max", C.c_int32)]
 
 
 class LevelInfo(C.Structure):
@@ -128,6 +128,8 @@ SIGNATURES = [
     ("lts_backward", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Samples), C.c_void_p, C.c_int32,
                                  C.c_void_p, C.c_void_p]),
     ("lts_mlmc", C.c_int32, [C.c_void_p, C.POINTER(MLMCOpts), C.POINTER(MLMCResult)]),
+    ("lts_mlmc_grad", C.c_int32, [C.c_void_p, C.POINTER(MLMCOpts), C.c_int32, C.POINTER(MLMCResult), dp, dp,
+                                  dp]),
     ("lts_set_timing", C.c_int32, [C.c_void_p, C.c_int32]),
     ("lts_get_timing", C.c_int32, [C.c_void_p, C.POINTER(Timing)]),
 ]

@@ -179,6 +179,8 @@ lts_status forward_device_states(lts_ctx c, const DevLevel& lv, int n, const dou
                                  double* B0, double* B1, bool timing);
 
 lts_status moments_device(lts_ctx c, const double* d_x, int n, double* d_out3);
+// (n, mean, M2) of each column b of the row-major [n][nb] array into d_out[3 b .. 3 b + 2].
+lts_status moments_cols_device(lts_ctx c, const double* d_x, int n, int nb, double* d_out);
 
 // Takes the device address of the no-allocation scratch array on `device`
 // (current) once per device (see lts_noalloc.hip).

@@ -253,6 +253,7 @@ std::string build_rect_desc(const lts_rect_rule& r, std::vector<double>& x, std:
         double Hk;
         int pk;
         tier_fine_set(x, y, active, h, r.layers, k, f, Hk, pk);
+        if (r.p_max > 0 && pk > r.p_max) continue;
         long long n, np;
         count_dof_p(nxc, nyc, active, f, n, np);
         const double rate = (double)((n - np) + (long long)pk * np) / Hk;

@@ -100,9 +100,33 @@ lts_status solve_batches(lts_ctx c, const lts_mlmc_opts& o, std::vector<LevelBat
   return LTS_OK;
 }
 
-}  // namespace
+// Gradient form: the new samples of each level solved by the backward LF-LTS
+// on the fine and the coarse mesh (dL/dQ = 1), which returns each QoI (equal
+// bit for bit to the forward solve's) and dQ/dg; the rows of dG_l = dQ_l/dg -
+// dQ_l-1/dg are appended to dg[l].
+lts_status solve_batches_grad(lts_ctx c, const lts_mlmc_opts& o, std::vector<LevelBatch>& bs, int K,
+                              std::vector<std::vector<double>>& dg) {
+  lts_status r;
+  const int nb = o.rule.n_blocks;
+  for (auto& b : bs) {
+    if (b.n == 0) continue;
+    std::vector<double> ones(b.n, 1.0), gf((size_t)b.n * nb), gc((size_t)b.n * nb, 0.0);
+    lts_samples sf{b.n, LTS_PTR_HOST, b.kappa.data(), b.x0.data(), b.nsf.data(), b.dtf.data(), o.rule.width};
+    if ((r = lts_backward(c, o.level_ids[b.l], &sf, ones.data(), K, b.qf.data(), gf.data())) != LTS_OK) return r;
+    if (b.l > 0) {
+      lts_samples sc{b.n, LTS_PTR_HOST, b.kappa.data(), b.x0.data(), b.nsc.data(), b.dtc.data(), o.rule.width};
+      if ((r = lts_backward(c, o.level_ids[b.l - 1], &sc, ones.data(), K, b.qc.data(), gc.data())) != LTS_OK)
+        return r;
+    }
+    for (size_t k = 0; k < gf.size(); ++k) dg[b.l].push_back(gf[k] - gc[k]);
+  }
+  return LTS_OK;
+}
 
-extern "C" lts_status lts_mlmc(lts_ctx c, const lts_mlmc_opts* op, lts_mlmc_result* out) {
+// Algorithm 1 (see lts_mlmc); with dg != nullptr every sample is solved by the
+// backward form and the gradient differences are collected per level.
+lts_status mlmc_run(lts_ctx c, const lts_mlmc_opts* op, lts_mlmc_result* out, int K,
+                    std::vector<std::vector<double>>* dg) {
   if (!c) return LTS_ERR_ARG;
   c->err.clear();
   if (!op || !out) return arg_fail(c, "NULL argument");
@@ -166,7 +190,11 @@ extern "C" lts_status lts_mlmc(lts_ctx c, const lts_mlmc_opts* op, lts_mlmc_resu
       const int64_t have = (int64_t)dq[l].size();
       if ((r = draw_level(c, o, l, have, (int)(N[l] - have), bs[l])) != LTS_OK) return r;
     }
-    if ((r = solve_batches(c, o, bs)) != LTS_OK) return r;
+    if (dg) {
+      if ((r = solve_batches_grad(c, o, bs, K, *dg)) != LTS_OK) return r;
+    } else if ((r = solve_batches(c, o, bs)) != LTS_OK) {
+      return r;
+    }
     for (int l = 0; l <= L; ++l)
       for (int s = 0; s < bs[l].n; ++s) dq[l].push_back(bs[l].qf[s] - bs[l].qc[s]);
     for (int l = 0; l <= L; ++l) {
@@ -213,5 +241,53 @@ extern "C" lts_status lts_mlmc(lts_ctx c, const lts_mlmc_opts* op, lts_mlmc_resu
   out->rmse = std::sqrt(vsum + bias * bias);
   out->converged = bias * bias < 0.5 * o.eps * o.eps;
   out->seconds = secs;
+  if (dg) dg->resize(L + 1);
+  return LTS_OK;
+}
+
+}  // namespace
+
+extern "C" lts_status lts_mlmc(lts_ctx c, const lts_mlmc_opts* op, lts_mlmc_result* out) {
+  return mlmc_run(c, op, out, 0, nullptr);
+}
+
+extern "C" lts_status lts_mlmc_grad(lts_ctx c, const lts_mlmc_opts* op, int32_t K_ckpt, lts_mlmc_result* out,
+                                    double* grad_estimate, double* grad_mean, double* grad_var) {
+  if (!c) return LTS_ERR_ARG;
+  c->err.clear();
+  if (!op || !out || !grad_estimate || !grad_mean || !grad_var) return arg_fail(c, "NULL argument");
+  if (K_ckpt < 1 || K_ckpt > 4096) return arg_fail(c, "K_ckpt must be in 1..4096");
+  const int nb = op->rule.n_blocks;
+  if (nb < 2 || nb > 255) return arg_fail(c, "rule.n_blocks out of range");
+  std::vector<std::vector<double>> dg(LTS_MAX_LEVELS);
+  lts_status r = mlmc_run(c, op, out, K_ckpt, &dg);
+  if (r != LTS_OK) return r;
+  const int L = out->L;
+  // per level and block: mean and unbiased variance of dG on the device
+  size_t rows = 0;
+  for (int l = 0; l <= L; ++l) rows = std::max(rows, dg[l].size() / nb);
+  LTS_HIP(c, hipSetDevice(c->device));
+  LTS_HIP(c, c->red.ensure(std::max<size_t>((rows * nb + 3 * (size_t)nb) * 8, 64)));
+  double* dx = c->red.as<double>() + 3 * (size_t)nb;
+  std::vector<double> m3(3 * (size_t)nb);
+  for (int b = 0; b < nb; ++b) grad_estimate[b] = 0.0;
+  for (int l = 0; l < LTS_MAX_LEVELS; ++l)
+    for (int b = 0; b < nb; ++b) grad_mean[(size_t)l * nb + b] = grad_var[(size_t)l * nb + b] = 0.0;
+  for (int l = 0; l <= L; ++l) {
+    const int n = out->N[l];
+    if ((size_t)n * nb > dg[l].size()) {
+      c->err = "gradient rows missing";
+      return LTS_ERR_STATE;
+    }
+    LTS_HIP(c, hipMemcpyAsync(dx, dg[l].data(), (size_t)n * nb * 8, hipMemcpyHostToDevice, c->stream));
+    if ((r = moments_cols_device(c, dx, n, nb, c->red.as<double>())) != LTS_OK) return r;
+    LTS_HIP(c, hipMemcpyAsync(m3.data(), c->red.p, m3.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    LTS_HIP(c, hipStreamSynchronize(c->stream));
+    for (int b = 0; b < nb; ++b) {
+      grad_mean[(size_t)l * nb + b] = m3[3 * b + 1];
+      grad_var[(size_t)l * nb + b] = n > 1 ? m3[3 * b + 2] / (double)(n - 1) : 0.0;
+      grad_estimate[b] += m3[3 * b + 1];
+    }
+  }
   return LTS_OK;
 }

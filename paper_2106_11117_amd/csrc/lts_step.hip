@@ -117,7 +117,46 @@ __global__ __launch_bounds__(1024) void k_moments(const double* __restrict__ x, 
   }
 }
 
+// (n, mean, M2) of every column of a row-major [n][nb] array: one workgroup
+// per column, the same per-lane Welford updates and Chan merges as k_moments.
+__global__ __launch_bounds__(256) void k_moments_cols(const double* __restrict__ x, int n, int nb,
+                                                      double* __restrict__ out) {
+  const int b = blockIdx.x;
+  Mom m{0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const double v = x[(size_t)k * nb + b];
+    m.n += 1.0;
+    const double d = v - m.mean;
+    m.mean += d / m.n;
+    m.m2 += d * (v - m.mean);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    Mom t;
+    t.n = __shfl_down(m.n, o, 64);
+    t.mean = __shfl_down(m.mean, o, 64);
+    t.m2 = __shfl_down(m.m2, o, 64);
+    m = chan_merge(m, t);
+  }
+  __shared__ Mom part[4];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Mom r = part[0];
+    for (int w = 1; w < 4; ++w) r = chan_merge(r, part[w]);
+    out[3 * b] = r.n;
+    out[3 * b + 1] = r.mean;
+    out[3 * b + 2] = r.m2;
+  }
+}
+
 }  // namespace
+
+lts_status moments_cols_device(lts_ctx c, const double* d_x, int n, int nb, double* d_out) {
+  if (nb <= 0) return LTS_OK;
+  k_moments_cols<<<nb, 256, 0, c->stream>>>(d_x, n, nb, d_out);
+  LTS_HIP(c, hipGetLastError());
+  return LTS_OK;
+}
 
 // ---------------------------------------------------------------------------
 

@@ -218,3 +218,9 @@ def test_tier_fine_sets_match_oracle(n_base, layers):
     assert np.array_equal(a["flags"], b["flags"])
     with pytest.raises(P.LtsError):
         P.rect_level_host(P.graded_L_rule(n_base, layers=layers, fine_tiers=layers + 1))
+    # the cost-optimal choice among the tiers with p <= p_max
+    for p_max in (4, 16, 64):
+        d = P.rect_level_host(P.graded_L_rule(n_base, layers=layers, fine_tiers="opt", p_max=p_max))
+        q = mesh.qopt_tiers(n_base, layers=layers, p_max=p_max)[0]
+        lv = mesh.graded_L_tiers(n_base, q, layers=layers)
+        assert (d["h"], d["p"], d["n_P"]) == (lv.h, lv.p, int(lv.Pmask.sum())) and d["p"] <= p_max

@@ -174,3 +174,15 @@ def test_algorithm1_builds_levels_only_when_the_bias_test_asks():
     assert r1.L == 3 and lazy.built == [0, 1, 2, 3] and sorted(built) == [0, 1, 2, 3]
     r2 = mlmc.mlmc([make(l) for l in range(8)], rule, eps=eps, N_init=(8,) * 8, L_start=1, eval_dq=dq)
     assert (r1.L, r1.N, r1.estimate, r1.cost) == (r2.L, r2.N, r2.estimate, r2.cost)
+
+
+def test_qopt_with_a_cap_on_p():
+    """With p capped the choice is the cheapest tier level whose p fits: on the
+    finest workload level (512 cells across) the unconstrained optimum takes
+    all six tiers (p = 128), with p <= 64 it takes five (the workload's rule)."""
+    q, costs = mesh.qopt_tiers(512)
+    assert q == 6 and mesh.graded_L_tiers(512, 6).p == 128
+    qc, costs_c = mesh.qopt_tiers(512, p_max=64)
+    assert qc == 5 and costs_c == costs
+    ok = [k for k in range(7) if mesh.graded_L_tiers(512, k).p <= 64]
+    assert qc == min(ok, key=lambda k: costs[k])
