@@ -393,6 +393,10 @@ lts_status lts_add_level(lts_ctx c, const lts_grid_desc* d, int32_t* id_out) {
   auto D = std::make_unique<DevLevel>();
   std::string e = build_level_from_desc(*d, D->H);
   if (!e.empty()) return arg_fail(c, e);
+  // the step kernels index a sample's nodes with 32-bit row * pitch + column
+  const size_t pitch = ((size_t)D->H.nxn + kPitchAlign - 1) / kPitchAlign * kPitchAlign;
+  if (pitch * (size_t)D->H.nyn >= ((size_t)1 << 31))
+    return arg_fail(c, "grid too large: padded nodes per sample must stay below 2^31");
   LTS_HIP(c, hipSetDevice(c->device));
   lts_status r = upload_level(c, *D);
   if (r != LTS_OK) return r;

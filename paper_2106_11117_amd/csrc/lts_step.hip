@@ -44,8 +44,9 @@ __global__ __launch_bounds__(256) void k_init(LevelView L, const double* __restr
 }
 
 // ---------------------------------------------------------------------------
-// Q[s] = sum_k qoiw[k] u_k, one workgroup per sample, fixed summation order,
-// accumulated in binary64 also for binary32 states.
+// Q[s] = sum_k qoiw[k] u_k, one workgroup per sample, fixed summation order
+// (per-lane strided sums, wavefront shuffles, then the four wavefronts in
+// order), accumulated in binary64 also for binary32 states.
 template <class T>
 __global__ __launch_bounds__(256) void k_qoi(LevelView L, const int* __restrict__ nsteps,
                                              const T* __restrict__ B0, const T* __restrict__ B1,
@@ -57,14 +58,11 @@ __global__ __launch_bounds__(256) void k_qoi(LevelView L, const int* __restrict_
     const double w = L.qoiw[k];
     if (w != 0.0) acc += w * (double)u[k];
   }
-  __shared__ double red[256];
-  red[threadIdx.x] = acc;
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  __shared__ double part[4];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) Q[s] = red[0];
+  if (threadIdx.x == 0) Q[s] = (part[0] + part[1]) + (part[2] + part[3]);
 }
 
 // ---------------------------------------------------------------------------

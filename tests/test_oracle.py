@@ -597,3 +597,64 @@ def test_edge_form_stiffness():
     assert np.all(r[~boundary_row] == 0.0)
     # and Dirichlet couplings act like u = 0 outside: K 1 = sum of couplings to the boundary
     assert np.all(r[boundary_row] > 0.0)
+
+
+def test_edge_form_is_the_closer_binary64_evaluation_of_Kv():
+    """K v on a graded L-shape level (smallest cell h/64) for a smooth v, in exact
+    rational arithmetic from the binary64 edge weights c_ij (K_ii = sum_j c_ij,
+    Dirichlet neighbours included), against two binary64 evaluations of the same
+    matrix: the edge form sum_j c_ij (v_i - v_j) that the oracle and the kernels
+    use, and the assembled form K_ii v_i - sum_j c_ij v_j with the diagonal
+    summed in binary64, at the DOFs away from the Dirichlet boundary.  On a
+    locally nearly constant v the exact K v is small next to K_ii v_i,
+    and the assembled form's rounding of K_ii v_i swamps it; the edge form
+    stays within a few roundings of the exact value.  A constant v gives
+    exactly 0 in the edge form there."""
+    from fractions import Fraction
+    lv = mesh.graded_L_level(32)
+    ops = fem.operators(lv)
+    kap = np.exp(2.0 * np.linspace(-0.3, 0.3, lv.n_blocks))
+    E = fem.EdgeStiffness(ops.ed, kap)
+    ids = lv.dof_ids
+    X, Y = np.meshgrid(lv.xs, lv.ys)
+    px, py = X.ravel()[ids], Y.ravel()[ids]
+    n = ids.size
+    Ecoo = E.E.tocoo()
+    # edges: (i, j or -1, c); rows of E hold +1 at i and -1 at j
+    ends = {}
+    for r, c, v in zip(Ecoo.row, Ecoo.col, Ecoo.data):
+        ends.setdefault(int(r), [None, -1])[0 if v > 0 else 1] = int(c)
+    edges = [(ends[e][0], ends[e][1], float(E.w[e])) for e in range(E.w.size)]
+    # a smooth mode on top of a constant: locally nearly constant, as the
+    # smooth modes are on the h/64 cells
+    for v in (1.0 + 1e-3 * np.cos(px) * np.cos(py), np.full(n, 0.3)):
+        exact = [Fraction(0)] * n
+        diag = np.zeros(n)
+        for i, j, c in edges:
+            vj = Fraction(float(v[j])) if j >= 0 else Fraction(0)
+            d = Fraction(c) * (Fraction(float(v[i])) - vj)
+            exact[i] += d
+            diag[i] += c
+            if j >= 0:
+                exact[j] -= d
+                diag[j] += c
+        edge = E @ v
+        off = np.zeros(n)
+        for i, j, c in edges:
+            if j >= 0:
+                off[i] += c * v[j]
+                off[j] += c * v[i]
+        assembled = diag * v - off
+        ex = np.array([float(x) for x in exact])
+        # away from the Dirichlet boundary (next to it both forms round c_i0 v_i alike)
+        inner = np.ones(n, dtype=bool)
+        inner[[i for i, j, _ in edges if j < 0]] = False
+        scale = np.abs(diag * v)[inner].max()
+        err_edge = np.abs(edge - ex)[inner].max()
+        err_asm = np.abs(assembled - ex)[inner].max()
+        if np.all(v == v[0]):
+            assert np.all(edge[inner] == 0.0) and np.all(ex[inner] == 0.0)
+            assert err_asm > 0.0                       # the assembled diagonal leaves a residue
+        else:
+            assert err_edge <= 1e-15 * scale
+            assert err_edge * 10 <= err_asm, (err_edge, err_asm)
