@@ -23,6 +23,9 @@ and local time-stepping for wave propagation"):
 * ``mlmc``     -- QoI, coupled differences, two-pass moments, optimal N_l,
                   bias estimate, Algorithm 1 (Sec. 2.2).
 * ``adjoint``  -- discrete adjoint of the LF-LTS recurrence (dQ/d log c).
+* ``oned``     -- the one-dimensional workloads of Sec. 4.1 / 4.2 (Neumann
+                  data, random wave speed by a Karhunen-Loeve sum or a random
+                  jump) with the V = L^2(D)-valued QoI and its Algorithm 1.
 
 It shares no code with the HIP path and imports nothing from it.
 """
