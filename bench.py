@@ -23,7 +23,8 @@ multi-level throughput with N_l = 4096, 1024, 256, 64, 16 ("batch_graded_L").
 Other modes (one JSON line each): --mlmc (Algorithm 1, batched + graph against
 the plain form and the CPU oracle), --batch [--plain] (all five graded L-shape
 levels in shared launches), --lf (LF-LTS against the standard leapfrog
-baseline), --adjoint (discrete adjoint against the forward solve),
+baseline), --line (the one-dimensional workloads, LF-LTS against leapfrog),
+--adjoint (discrete adjoint against the forward solve),
 --stream-check and --copy-check (HBM reference rates and counter calibration).
 """
 from __future__ import annotations
@@ -397,6 +398,43 @@ def batch_bench(plain: bool, fp32: bool = True, emit: bool = True):
     return out
 
 
+LINE_EPS = {"kl": (5e-3, 2e-3, 1e-3), "jump": (5e-3, 2e-3, 1e-3)}
+
+
+def line_bench():
+    """The one-dimensional workloads of Sec. 4.1 (continuous random wave speed,
+    T = 11) and Sec. 4.2 (random jump, T = 6), Neumann data, Q = u(T) in
+    L^2(D): Algorithm 1 with LF-LTS against the standard leapfrog twins (the
+    same meshes, P empty, the step of the refined cells everywhere) at the
+    same RMSE targets, five levels H = 2^-4 .. 2^-8.  Wall time of each run,
+    L, N_l and the cost model sum N_l C_l of both (the paper's own measure)."""
+    import paper_2106_11117_amd as P
+
+    ctx = P.Context(0)
+    out = {"metric": "1D MLMC wall time at fixed RMSE, LF-LTS vs standard leapfrog (L^2(D)-valued QoI)",
+           "unit": "s", "higher_is_better": False, "data": "synthetic (Philox seed 0)", "runs": []}
+    for kind in ("kl", "jump"):
+        rule = P.line_sample_rule(kind)
+        lts_ids = [ctx.add_line_level(P.line_rule(kind, l)) for l in range(5)]
+        lf_ids = [ctx.add_line_level(P.line_rule(kind, l, lf=True)) for l in range(5)]
+        ctx.line_mlmc(lts_ids[:2], rule, eps=0.1, N_init=(4, 4), L_start=1)        # warm-up
+        for eps in LINE_EPS[kind]:
+            row = {"kind": kind, "eps": eps}
+            for name, ids in (("lts", lts_ids), ("lf", lf_ids)):
+                t0 = time.perf_counter()
+                r = ctx.line_mlmc(ids, rule, eps=eps, N_init=(32, 16, 8, 4, 4), L_start=2)
+                row[name] = {"s": time.perf_counter() - t0, "L": r["L"], "N": r["N"],
+                             "model_cost": float(sum(n * c for n, c in zip(r["N"], r["cost"]))),
+                             "rmse": r["rmse"], "converged": r["converged"]}
+                print(f"{kind} eps {eps} {name}: L {r['L']} N {r['N']} {row[name]['s']:.3f} s", file=sys.stderr,
+                      flush=True)
+            row["speedup_wall"] = row["lf"]["s"] / row["lts"]["s"]
+            row["speedup_model"] = row["lf"]["model_cost"] / row["lts"]["model_cost"]
+            out["runs"].append(row)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def copy_check(mib: int):
     """Four device-to-device copies of `mib` MiB (read mib, write mib each): the
     reference point that turns the FETCH_SIZE / WRITE_SIZE counters of a profiled
@@ -453,6 +491,8 @@ def main():
                     help="only run 4 plain device copies of MIB MiB (calibrates HBM byte counters)")
     ap.add_argument("--lf", action="store_true",
                     help="only compare LF-LTS with the standard leapfrog baseline (graded L-shape hierarchy)")
+    ap.add_argument("--line", action="store_true",
+                    help="only run the one-dimensional workloads' MLMC, LF-LTS against leapfrog")
     ap.add_argument("--stream-check", action="store_true",
                     help="only time plain torch copy / axpy / sum kernels (practical HBM rates)")
     ap.add_argument("--adjoint", action="store_true",
@@ -485,6 +525,9 @@ def main():
         return
     if args.lf:
         lf_bench()
+        return
+    if args.line:
+        line_bench()
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the workload is one GPU's "

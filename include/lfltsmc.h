@@ -465,6 +465,109 @@ lts_status lts_mlmc_grad(lts_ctx ctx, const lts_mlmc_opts* opts, int32_t K_ckpt,
                          double* grad_estimate, double* grad_mean, double* grad_var);
 
 /* ------------------------------------------------------------------------ */
+/* One-dimensional workloads (Sec. 4.1, 4.2): Neumann data, L^2(D)-valued QoI */
+/* ------------------------------------------------------------------------ */
+
+/* A level on an interval (lo, hi): uniform cells of size H, and every cell
+ * inside the closed interval [fine_lo, fine_hi] split into cells of size
+ * h_fine (H / h_fine an integer); P = the nodes of the fine cells, p =
+ * ceil(H / h_fine) (1 when H <= h_fine: plain leapfrog).  Homogeneous Neumann
+ * data: every node is a DOF; lumped masses sum |cell|/2.  The fine cells must
+ * form one interval with at most 64 nodes in P and its neighbours (their
+ * substeps run on one wavefront). */
+typedef struct {
+  double lo, hi, H;
+  double fine_lo, fine_hi, h_fine;
+  double nu;                      /* stabilization, 0 <= nu <= 1 */
+  int32_t lf;                     /* 1: the standard leapfrog twin (the same nodes, P empty,
+                                     p = 1, steps on the spacing h_fine of the refined cells) */
+} lts_line_rule;
+
+typedef struct {
+  int32_t n_nodes, n_P, p;
+  int32_t f0, n_fplus;            /* P and its neighbours: nodes f0 .. f0 + n_fplus - 1 */
+  double H, nu;
+} lts_line_info;
+
+#define LTS_LINE_KL_TERMS 100
+enum { LTS_LINE_KL = 0, LTS_LINE_JUMP = 1 };
+
+/* Random wave speed of a one-dimensional workload, kappa = c^2 per cell at the
+ * cell midpoint.  LTS_LINE_KL (Sec. 4.1): c^2(x) = 1 + sum_{k=1}^{100}
+ * (1/(4 pi^2 k^2)) (cos(k pi x/6) xi1_k + sin(k pi x/6) xi2_k), xi ~ U(-1, 1)
+ * i.i.d. (xi1_k = 2 u_{2k-2} - 1, xi2_k = 2 u_{2k-1} - 1 of the sample's
+ * stream).  LTS_LINE_JUMP (Sec. 4.2): c = c_left for x < xi, c_right from xi
+ * on, xi ~ U(jump_lo, jump_hi).  Streams as lts_gen_samples (purpose 0).
+ * u_0(x) = exp(-(x - pulse_x)^2 / pulse_w2), u_t(0) = 0; n_steps =
+ * ceil(T sqrt(max kappa) / (cfl H)), dt = T / n_steps. */
+typedef struct {
+  int32_t kind;
+  double jump_lo, jump_hi, c_left, c_right;
+  double pulse_x, pulse_w2;
+  double T, cfl;
+} lts_line_sample_rule;
+
+/* Build a one-dimensional level; ids count 0, 1, ... separately from the 2D
+ * levels.  Errors: LTS_ERR_ARG, LTS_ERR_OOM, LTS_ERR_HIP. */
+lts_status lts_build_line_level(lts_ctx ctx, const lts_line_rule* rule, int32_t* line_id);
+
+/* Host only: the level of `rule` (info required; x, mass [n_nodes] and P
+ * [n_nodes] may be NULL).  Errors: LTS_ERR_ARG. */
+lts_status lts_line_level_host(const lts_line_rule* rule, lts_line_info* info, double* x, double* mass,
+                               uint8_t* P);
+
+/* Host only: kappa [n][n_nodes - 1], n_steps [n], dt [n] of samples first ..
+ * first+n-1 of MLMC level sample_level on the level of `mesh` (any output may
+ * be NULL).  Errors: LTS_ERR_ARG. */
+lts_status lts_gen_line_samples(uint64_t seed, int32_t sample_level, int64_t first, int32_t n,
+                                const lts_line_sample_rule* rule, const lts_line_rule* mesh,
+                                double* kappa, int32_t* n_steps, double* dt);
+
+/* Solve n samples on line level `line_id` with stabilized LF-LTS
+ * (Algorithm 2, start-up u_1 = q_1(u_0)) and write u(T) at every node:
+ * U_out [n][n_nodes].  One workgroup per sample runs all its steps in one
+ * launch, the state in LDS, the substeps of F+ on one wavefront.  kappa,
+ * n_steps, dt and U_out have ptr_kind.  Errors: LTS_ERR_ARG, LTS_ERR_OOM,
+ * LTS_ERR_HIP, LTS_ERR_UNSTABLE (a non-finite u(T)). */
+lts_status lts_line_forward(lts_ctx ctx, int32_t line_id, int32_t n, int32_t ptr_kind, const double* kappa,
+                            const int32_t* n_steps, const double* dt, const lts_line_sample_rule* rule,
+                            double* U_out);
+
+typedef struct {
+  int32_t n_levels;               /* 1..LTS_MAX_LEVELS */
+  int32_t line_ids[LTS_MAX_LEVELS];
+  lts_line_sample_rule rule;
+  uint64_t seed;
+  double eps, alpha;
+  int32_t L_start;
+  int32_t N_init[LTS_MAX_LEVELS];
+} lts_line_mlmc_opts;
+
+typedef struct {
+  int32_t L;
+  int32_t N[LTS_MAX_LEVELS];
+  double var[LTS_MAX_LEVELS];       /* V_l = sum_i |Delta Q_l(i) - mean|_V^2 / (N_l - 1) */
+  double mean_norm[LTS_MAX_LEVELS]; /* |mean Delta Q_l|_V */
+  double cost[LTS_MAX_LEVELS];      /* cost model per Delta Q_l sample */
+  double bias, rmse;
+  int32_t converged;
+  int32_t n_nodes;                  /* nodes of the finest level used (length of the estimate) */
+  double seconds;
+} lts_line_mlmc_result;
+
+/* Algorithm 1 for the V = L^2(D)-valued QoI Q = u(T) (Sec. 2.1, 2.2):
+ * Delta Q_l = u_l - I u_{l-1} on mesh l (I the nodal interpolation onto the
+ * finer, nested mesh), |v|_V^2 = sum_i m_i v_i^2 with mesh l's lumped masses,
+ * V_l and the bias |mean Delta Q_L|_V / (2^alpha - 1) in that norm, N_l and L
+ * as lts_mlmc (C_l = ceil(T/(cfl H)) ((N - |P|) + p |P|) per solve).
+ * estimate [n_nodes of level L] receives sum_l I mean Delta Q_l on the finest
+ * mesh used (host array of at least the finest level's n_nodes).  The
+ * differences and their moments are formed on the device.  Errors as
+ * lts_line_forward. */
+lts_status lts_line_mlmc(lts_ctx ctx, const lts_line_mlmc_opts* opts, lts_line_mlmc_result* out,
+                         double* estimate);
+
+/* ------------------------------------------------------------------------ */
 /* Timing of the last forward call (for benchmarks)                          */
 /* ------------------------------------------------------------------------ */
 

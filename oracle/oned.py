@@ -62,9 +62,12 @@ class Line:
         return self.x.size
 
 
-def line_level(H: float, fine_box, h_f: float, lo: float = 0.0, hi: float = 6.0, nu: float = 0.01) -> Line:
+def line_level(H: float, fine_box, h_f: float, lo: float = 0.0, hi: float = 6.0, nu: float = 0.01,
+               lf: bool = False) -> Line:
     """Uniform cells of size H on (lo, hi); those inside the closed fine_box split
-    into cells of size h_f."""
+    into cells of size h_f.  lf: the standard leapfrog twin (the comparison of
+    Sec. 4): the same nodes with P empty, p = 1, and the step spacing H / p of
+    the refined cells."""
     nc = int(round((hi - lo) / H))
     xs = []
     refine = H > h_f
@@ -89,17 +92,21 @@ def line_level(H: float, fine_box, h_f: float, lo: float = 0.0, hi: float = 6.0,
     Pd[:-1][fine] = 1.0
     Pd[1:][fine] = 1.0
     lv.Pd = Pd
+    if lf and fine.any():
+        lv.Pd = np.zeros(x.size)
+        lv.H = H / p
+        lv.p = 1
     return lv
 
 
-def kl_level(l: int, nu: float = 0.01) -> Line:
+def kl_level(l: int, nu: float = 0.01, lf: bool = False) -> Line:
     """Level l of the continuous-wave-speed workload (Sec. 4.1)."""
-    return line_level(2.0 ** -(l + 4), (5.0 - 1.0 / 16, 5.0), 2.0 ** -8, nu=nu)
+    return line_level(2.0 ** -(l + 4), (5.0 - 1.0 / 16, 5.0), 2.0 ** -8, nu=nu, lf=lf)
 
 
-def jump_level(l: int, nu: float = 0.01) -> Line:
+def jump_level(l: int, nu: float = 0.01, lf: bool = False) -> Line:
     """Level l of the random-jump workload (Sec. 4.2)."""
-    return line_level(2.0 ** -(l + 4), (4.0 - 1.0 / 16, 4.0), 2.0 ** -9, nu=nu)
+    return line_level(2.0 ** -(l + 4), (4.0 - 1.0 / 16, 4.0), 2.0 ** -9, nu=nu, lf=lf)
 
 
 def midpoints(lv: Line) -> np.ndarray:

@@ -16,7 +16,7 @@ from ._lib import (LTS_BATCH_GRAPH, LTS_FP32_STEP, LTS_FP64, LTS_MLMC_BATCHED, L
                    LTS_NODE_DOF, LTS_NODE_FPLUS, LTS_NODE_P, LTS_PTR_DEVICE, LTS_PTR_HOST,
                    LTS_RULE_BOX, LTS_RULE_GRADED_L, LTS_RULE_LF, LtsError)
 
-__all__ = ["Context", "gen_samples", "philox", "rect_level_host", "tiling_host", "lf_rule", "cheb_constants", "sample_rule", "box_rule", "graded_L_rule", "LtsError",
+__all__ = ["Context", "gen_samples", "line_rule", "line_sample_rule", "line_level_host", "gen_line_samples", "philox", "rect_level_host", "tiling_host", "lf_rule", "cheb_constants", "sample_rule", "box_rule", "graded_L_rule", "LtsError",
            "LTS_FP64", "LTS_FP32_STEP", "LTS_BATCH_GRAPH", "LTS_MLMC_BATCHED", "LTS_MLMC_PLAIN",
            "LTS_NODE_DOF", "LTS_NODE_P", "LTS_NODE_FPLUS", "LTS_RULE_LF", "LtsQoI"]
 
@@ -138,6 +138,46 @@ def cheb_constants(p, nu, dt=1.0) -> dict:
     b, bh, cf = np.zeros(p), np.zeros(p), np.zeros(p + 1)
     _check(lib.lts_cheb_constants(p, nu, dt, C.byref(d), C.byref(w), _dp(b), _dp(bh), _dp(cf)))
     return {"delta": d.value, "omega": w.value, "beta": b, "beta_half": bh, "coef": cf}
+
+
+def line_rule(kind="kl", level=0, nu=0.01, lf=False) -> _lib.LineRule:
+    """Level `level` of a one-dimensional workload on (0, 6): kind "kl" (Sec. 4.1,
+    D_fine = [5 - 1/16, 5] at 2^-8) or "jump" (Sec. 4.2, [4 - 1/16, 4] at 2^-9),
+    coarse spacing H = 2^-(level+4); lf: its standard leapfrog twin."""
+    f = (5.0 - 1.0 / 16, 5.0, 2.0 ** -8) if kind == "kl" else (4.0 - 1.0 / 16, 4.0, 2.0 ** -9)
+    return _lib.LineRule(lo=0.0, hi=6.0, H=2.0 ** -(level + 4), fine_lo=f[0], fine_hi=f[1], h_fine=f[2], nu=nu,
+                         lf=1 if lf else 0)
+
+
+def line_sample_rule(kind="kl", T=None, cfl=0.5) -> _lib.LineSampleRule:
+    """The random wave speed, pulse and horizon of a one-dimensional workload
+    (T = 11 for "kl", 6 for "jump"; jump position uniform in [4 - 1/16, 4], c = 1 | 2)."""
+    return _lib.LineSampleRule(kind=_lib.LTS_LINE_KL if kind == "kl" else _lib.LTS_LINE_JUMP,
+                               jump_lo=4.0 - 1.0 / 16, jump_hi=4.0, c_left=1.0, c_right=2.0, pulse_x=3.0,
+                               pulse_w2=0.09, T=(11.0 if kind == "kl" else 6.0) if T is None else T, cfl=cfl)
+
+
+def line_level_host(rule) -> dict:
+    lib = _lib.load()
+    info = _lib.LineInfo()
+    _check(lib.lts_line_level_host(C.byref(rule), C.byref(info), None, None, None))
+    n = info.n_nodes
+    x, m, P = np.zeros(n), np.zeros(n), np.zeros(n, dtype=np.uint8)
+    _check(lib.lts_line_level_host(C.byref(rule), C.byref(info), _dp(x), _dp(m),
+                                   P.ctypes.data_as(C.POINTER(C.c_uint8))))
+    d = {k: getattr(info, k) for k, _ in _lib.LineInfo._fields_}
+    d.update(x=x, mass=m, P=P)
+    return d
+
+
+def gen_line_samples(seed, sample_level, first, n, rule, mesh) -> dict:
+    """Host: kappa [n, cells], n_steps [n], dt [n] of a one-dimensional workload."""
+    lib = _lib.load()
+    cells = line_level_host(mesh)["n_nodes"] - 1
+    kap, ns, dt = np.zeros((n, cells)), np.zeros(n, dtype=np.int32), np.zeros(n)
+    _check(lib.lts_gen_line_samples(C.c_uint64(seed), sample_level, first, n, C.byref(rule), C.byref(mesh),
+                                    _dp(kap), _ip(ns), _dp(dt)))
+    return {"kappa": kap, "n_steps": ns, "dt": dt}
 
 
 def _is_torch(a):
@@ -373,6 +413,55 @@ class Context:
         if grad_K is not None:
             out.update(grad=ge, grad_mean=gm[:L + 1], grad_var=gv[:L + 1])
         return out
+
+    # --- one-dimensional workloads -------------------------------------------
+    def add_line_level(self, rule) -> int:
+        lid = C.c_int32()
+        self._c(self.lib.lts_build_line_level(self.h, C.byref(rule), C.byref(lid)))
+        return lid.value
+
+    def line_forward(self, line_id, kappa, n_steps, dt, rule, n_nodes):
+        """u(T) [n, n_nodes] of every sample (numpy in, numpy out; torch in, torch out)."""
+        if _is_torch(kappa):
+            import torch
+            k = kappa.contiguous().to(torch.float64)
+            ns = n_steps.contiguous().to(torch.int32)
+            d = dt.contiguous().to(torch.float64)
+            _wait_caller_stream(k)
+            U = torch.empty((ns.numel(), n_nodes), dtype=torch.float64, device=k.device)
+            self._c(self.lib.lts_line_forward(self.h, line_id, ns.numel(), LTS_PTR_DEVICE, k.data_ptr(),
+                                              ns.data_ptr(), d.data_ptr(), C.byref(rule), U.data_ptr()))
+            return U
+        k = np.ascontiguousarray(kappa, dtype=np.float64)
+        ns = np.ascontiguousarray(n_steps, dtype=np.int32)
+        d = np.ascontiguousarray(dt, dtype=np.float64)
+        U = np.zeros((ns.size, n_nodes))
+        self._c(self.lib.lts_line_forward(self.h, line_id, ns.size, LTS_PTR_HOST, k.ctypes.data, ns.ctypes.data,
+                                          d.ctypes.data, C.byref(rule), U.ctypes.data))
+        return U
+
+    def line_mlmc(self, line_ids, rule, eps, seed=0, alpha=2.0, L_start=2, N_init=(64, 32, 16, 8, 4),
+                  max_nodes=4096):
+        """Algorithm 1 for the L^2(D)-valued QoI u(T) on one-dimensional levels."""
+        o = _lib.LineMLMCOpts()
+        o.n_levels = len(line_ids)
+        for k, l in enumerate(line_ids):
+            o.line_ids[k] = l
+        o.rule = rule
+        o.seed = seed
+        o.eps = eps
+        o.alpha = alpha
+        o.L_start = L_start
+        for k in range(_lib.LTS_MAX_LEVELS):
+            o.N_init[k] = N_init[k] if k < len(N_init) else N_init[-1]
+        r = _lib.LineMLMCResult()
+        est = np.zeros(max_nodes)
+        self._c(self.lib.lts_line_mlmc(self.h, C.byref(o), C.byref(r), _dp(est)))
+        L = r.L
+        return {"L": L, "N": list(r.N[:L + 1]), "var": list(r.var[:L + 1]),
+                "mean_norm": list(r.mean_norm[:L + 1]), "cost": list(r.cost[:L + 1]), "bias": r.bias,
+                "rmse": r.rmse, "converged": bool(r.converged), "seconds": r.seconds,
+                "estimate": est[:r.n_nodes].copy()}
 
     def set_timing(self, on=True):
         self._c(self.lib.lts_set_timing(self.h, 1 if on else 0))

@@ -20,6 +20,7 @@ LTS_BATCH_GRAPH = 1
 LTS_BATCH_FP32 = 2
 LTS_MLMC_BATCHED, LTS_MLMC_PLAIN = 0, 1
 LTS_FINE_HALF_H, LTS_FINE_TIERS, LTS_FINE_QOPT = 0, 1, 2
+LTS_LINE_KL, LTS_LINE_JUMP = 0, 1
 LTS_MAX_LEVELS = 8
 LTS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -93,6 +94,35 @@ class MLMCResult(C.Structure):
                 ("level_ids", C.c_int32 * LTS_MAX_LEVELS)]
 
 
+class LineRule(C.Structure):
+    _fields_ = [("lo", C.c_double), ("hi", C.c_double), ("H", C.c_double), ("fine_lo", C.c_double),
+                ("fine_hi", C.c_double), ("h_fine", C.c_double), ("nu", C.c_double), ("lf", C.c_int32)]
+
+
+class LineInfo(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_P", C.c_int32), ("p", C.c_int32), ("f0", C.c_int32),
+                ("n_fplus", C.c_int32), ("H", C.c_double), ("nu", C.c_double)]
+
+
+class LineSampleRule(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("jump_lo", C.c_double), ("jump_hi", C.c_double), ("c_left", C.c_double),
+                ("c_right", C.c_double), ("pulse_x", C.c_double), ("pulse_w2", C.c_double), ("T", C.c_double),
+                ("cfl", C.c_double)]
+
+
+class LineMLMCOpts(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("line_ids", C.c_int32 * LTS_MAX_LEVELS), ("rule", LineSampleRule),
+                ("seed", C.c_uint64), ("eps", C.c_double), ("alpha", C.c_double), ("L_start", C.c_int32),
+                ("N_init", C.c_int32 * LTS_MAX_LEVELS)]
+
+
+class LineMLMCResult(C.Structure):
+    _fields_ = [("L", C.c_int32), ("N", C.c_int32 * LTS_MAX_LEVELS), ("var", C.c_double * LTS_MAX_LEVELS),
+                ("mean_norm", C.c_double * LTS_MAX_LEVELS), ("cost", C.c_double * LTS_MAX_LEVELS),
+                ("bias", C.c_double), ("rmse", C.c_double), ("converged", C.c_int32), ("n_nodes", C.c_int32),
+                ("seconds", C.c_double)]
+
+
 class Timing(C.Structure):
     _fields_ = [("step_kernel_ms", C.c_double), ("step_launches", C.c_int64), ("total_ms", C.c_double),
                 ("dof_updates", C.c_double), ("alg_bytes", C.c_double)]
@@ -130,6 +160,13 @@ SIGNATURES = [
     ("lts_mlmc", C.c_int32, [C.c_void_p, C.POINTER(MLMCOpts), C.POINTER(MLMCResult)]),
     ("lts_mlmc_grad", C.c_int32, [C.c_void_p, C.POINTER(MLMCOpts), C.c_int32, C.POINTER(MLMCResult), dp, dp,
                                   dp]),
+    ("lts_build_line_level", C.c_int32, [C.c_void_p, C.POINTER(LineRule), ip]),
+    ("lts_line_level_host", C.c_int32, [C.POINTER(LineRule), C.POINTER(LineInfo), dp, dp, u8p]),
+    ("lts_gen_line_samples", C.c_int32, [C.c_uint64, C.c_int32, C.c_int64, C.c_int32, C.POINTER(LineSampleRule),
+                                         C.POINTER(LineRule), dp, ip, dp]),
+    ("lts_line_forward", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.POINTER(LineSampleRule), C.c_void_p]),
+    ("lts_line_mlmc", C.c_int32, [C.c_void_p, C.POINTER(LineMLMCOpts), C.POINTER(LineMLMCResult), dp]),
     ("lts_set_timing", C.c_int32, [C.c_void_p, C.c_int32]),
     ("lts_get_timing", C.c_int32, [C.c_void_p, C.POINTER(Timing)]),
 ]

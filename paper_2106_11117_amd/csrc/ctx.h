@@ -80,6 +80,12 @@ struct DevLevel {
   }
 };
 
+// A one-dimensional level on the device (Sec. 4.1, 4.2).
+struct LineDev {
+  LineHost H;
+  DevBuf x, invh, invm, pflag, beta;
+};
+
 struct lts_error {
   lts_status code;
   std::string msg;
@@ -94,6 +100,8 @@ struct lts_ctx_s {
   bool own_stream = false;
   std::string err;
   std::vector<std::unique_ptr<lts::DevLevel>> levels;
+  std::vector<std::unique_ptr<lts::LineDev>> lines;       // one-dimensional levels
+  lts::DevBuf l_kap, l_coef, l_ns, l_U, l_Uc, l_pa, l_pt, l_mass, l_mean, l_dev;   // their workspace
   // workspace
   lts::DevBuf kappa, coef, nsteps, x0, Qd, perm, flag, st0, st1, wbuf, qa, qb, red, adj, adjscr, dldq, gout, adjlist;
   // batched form: per-job tables, states, job records, captured graph

@@ -10,6 +10,8 @@
 
 namespace lts {
 
+constexpr int kLineKlTerms = LTS_LINE_KL_TERMS;
+
 // A level on the host: the rectilinear grid, per-cell data, and the derived
 // per-node data of the mass-lumped P1 discretization.
 struct HostLevel {
@@ -49,6 +51,34 @@ void step_coefficients(const HostLevel& L, double dt, double* out);
 
 // Philox4x64-10 (Salmon et al., SC'11).
 void philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+// u[0..n-1]: uniforms ((x >> 12) + 0.5) 2^-52 of the stream with key (seed, 0)
+// and counters (j, i, level, purpose), four per block j = 0, 1, ...
+void philox_uniforms(uint64_t seed, int64_t i, int32_t level, uint64_t purpose, int n, double* u);
+
+// A one-dimensional level (Sec. 4.1, 4.2): nodes, fine cells, lumped masses,
+// the projector P and the stabilized Chebyshev constants.
+struct LineHost {
+  std::vector<double> x;        // nodes
+  std::vector<uint8_t> fine;    // per cell
+  std::vector<double> mass;     // per node
+  std::vector<uint8_t> P;       // per node
+  double H = 0.0;
+  int p = 1;
+  double nu = 0.0;
+  int f0 = 0, nf = 0;           // F+ = nodes f0 .. f0+nf-1 (P and its neighbours; contiguous)
+  double delta = 1.0, omega = 2.0;
+  std::vector<double> beta, beta_half;
+};
+
+// Builds the level of `r`; "" on success.
+std::string build_line_level(const lts_line_rule& r, LineHost& L);
+
+// Per-sample cell coefficients kappa = c^2 [n][cells], step counts and dt for
+// samples first .. first+n-1 of MLMC level sample_level on level L.
+std::string gen_line_samples(uint64_t seed, int32_t sample_level, int64_t first, int32_t n,
+                             const lts_line_sample_rule& rule, const LineHost& L, double* kappa,
+                             int32_t* n_steps, double* dt);
 
 std::string gen_samples(uint64_t seed, int32_t sample_level, int64_t first_index, int32_t n,
                         const lts_sample_rule& rule, double h_mesh, double* g, double* kappa,

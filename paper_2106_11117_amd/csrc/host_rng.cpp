@@ -43,7 +43,7 @@ static inline double to_uniform(uint64_t x) {
   return ((double)(x >> 12) + 0.5) * 0x1p-52;
 }
 
-static void uniforms(uint64_t seed, int64_t i, int32_t level, uint64_t purpose, int n, double* u) {
+void philox_uniforms(uint64_t seed, int64_t i, int32_t level, uint64_t purpose, int n, double* u) {
   const uint64_t key[2] = {seed, 0};
   for (int j = 0; 4 * j < n; ++j) {
     const uint64_t ctr[4] = {(uint64_t)j, (uint64_t)i, (uint64_t)(uint32_t)level, purpose};
@@ -67,7 +67,7 @@ std::string gen_samples(uint64_t seed, int32_t sample_level, int64_t first_index
   double u[256], z[256];
   for (int s = 0; s < n; ++s) {
     const int64_t i = first_index + s;
-    uniforms(seed, i, sample_level, 0, nb, u);
+    philox_uniforms(seed, i, sample_level, 0, nb, u);
     for (int k = 0; k < nb; k += 2) {
       const double r = std::sqrt(-2.0 * std::log(u[k]));
       const double t = pi2 * u[k + 1];
@@ -83,7 +83,7 @@ std::string gen_samples(uint64_t seed, int32_t sample_level, int64_t first_index
       if (b == 0 || cb > cmax) cmax = cb;
     }
     double up[2];
-    uniforms(seed, i, sample_level, 1, 2, up);
+    philox_uniforms(seed, i, sample_level, 1, 2, up);
     if (x0) {
       x0[2 * s] = rule.px_lo + (rule.px_hi - rule.px_lo) * up[0];
       x0[2 * s + 1] = rule.py_lo + (rule.py_hi - rule.py_lo) * up[1];

@@ -224,3 +224,28 @@ def test_tier_fine_sets_match_oracle(n_base, layers):
         q = mesh.qopt_tiers(n_base, layers=layers, p_max=p_max)[0]
         lv = mesh.graded_L_tiers(n_base, q, layers=layers)
         assert (d["h"], d["p"], d["n_P"]) == (lv.h, lv.p, int(lv.Pmask.sum())) and d["p"] <= p_max
+
+
+@pytest.mark.parametrize("kind", ["kl", "jump"])
+def test_line_levels_and_samples_match_oracle(kind):
+    """One-dimensional workloads (Sec. 4.1, 4.2): the library's host builder and
+    sample generator agree with the oracle bit for bit on every level (nodes,
+    lumped masses, P, p) and on the per-cell kappa, step counts and dt."""
+    from oracle import oned
+    mk = oned.kl_level if kind == "kl" else oned.jump_level
+    T = 11.0 if kind == "kl" else 6.0
+    for l in range(5):
+        d = P.line_level_host(P.line_rule(kind, l))
+        lv = mk(l)
+        assert np.array_equal(d["x"], lv.x) and np.array_equal(d["mass"], lv.m)
+        assert np.array_equal(d["P"].astype(float), lv.Pd) and d["p"] == lv.p
+        s = P.gen_line_samples(3, l, 10, 3, P.line_sample_rule(kind), P.line_rule(kind, l))
+        for k in range(3):
+            kap = oned.cell_kappa(lv, kind, 3, l, 10 + k)
+            n, dt = oned.steps(lv, kap, T, 0.5)
+            assert np.array_equal(kap, s["kappa"][k]) and (n, dt) == (s["n_steps"][k], s["dt"][k])
+        t = P.line_level_host(P.line_rule(kind, l, lf=True))
+        tw = mk(l, lf=True)
+        assert (t["p"], t["H"], t["n_P"]) == (1, tw.H, 0) and np.array_equal(t["x"], tw.x)
+    with pytest.raises(P.LtsError):
+        P.line_level_host(P._lib.LineRule(lo=0.0, hi=6.0, H=0.07, fine_lo=5.0, fine_hi=5.0, h_fine=0.01, nu=0.01))
