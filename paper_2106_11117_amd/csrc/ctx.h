@@ -245,10 +245,11 @@ void job_record(const DevLevel& lv, const TilingDev& T, const double* d_kappa, c
                 double* B0, double* B1, size_t sstride, void* out);
 size_t step_args_size();
 
-// One fused step launch for samples s0 .. s0+active-1 (sorted order).  With
-// fp32 the state buffers hold binary32 values (stride sstride elements).
+// One fused step launch for samples s0 .. s0+active-1 (sorted order): reads
+// u_n from Ucur and u_n-1 from Uold, writes u_n+1 to Unew (NULL: into Uold).
+// With fp32 the state buffers hold binary32 values (stride sstride elements).
 lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const double* d_kappa,
                        const double* d_coef, const double* Ucur, double* Uold, size_t sstride, int s0,
-                       int active, int startup, hipStream_t stream, bool fp32 = false);
+                       int active, int startup, hipStream_t stream, bool fp32 = false, double* Unew = nullptr);
 
 }  // namespace lts

@@ -777,10 +777,9 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
       int act = 0;
       while (act < n && h_nsteps[act] > jn) ++act;
       if (act == 0) break;
-      const size_t ab = (size_t)act * ss * sizeof(double);
-      double* dst = arr(seg0 + (jn - k0) + 1);
-      LTS_HIP(c, hipMemcpyAsync(dst, arr(seg0 + (jn - k0) - 1), ab, hipMemcpyDeviceToDevice, c->stream));
-      r = launch_step(c, lv, lv.tiling, d_kappa, d_coef, arr(seg0 + (jn - k0)), dst, ss, 0, act, 0, c->stream);
+      // u_jn+1 out of place from u_jn and u_jn-1 (the segment keeps every state)
+      r = launch_step(c, lv, lv.tiling, d_kappa, d_coef, arr(seg0 + (jn - k0)), arr(seg0 + (jn - k0) - 1), ss, 0,
+                      act, 0, c->stream, false, arr(seg0 + (jn - k0) + 1));
       if (r != LTS_OK) return r;
     }
     for (int nn = k1; nn >= k0; --nn) {

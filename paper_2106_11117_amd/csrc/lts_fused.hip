@@ -59,7 +59,8 @@ struct StepArgs {
   const double* __restrict__ kappa;  // [S][nb] (sorted sample order)
   const double* __restrict__ coef;   // [S][p+1]
   const double* __restrict__ Ucur;   // u_n of sample s at Ucur + s*sstride
-  double* __restrict__ Uold;         // u_n-1 in, u_n+1 out
+  double* __restrict__ Uold;         // u_n-1 in
+  double* Unew;                      // u_n+1 out (Uold: in place)
   size_t sstride;
   int startup;
   int s0;                            // first sample of this launch
@@ -72,7 +73,8 @@ struct StepArgs {
 // record in place (a copy would hide that its pointers address global memory).
 struct StepState {
   const double* Ucur;   // u_n of sample s at Ucur + s*sstride
-  double* Uold;         // u_n-1 in, u_n+1 out
+  double* Uold;         // u_n-1 in
+  double* Unew;         // u_n+1 out (Uold for the in-place update)
   int startup;
 };
 
@@ -118,6 +120,7 @@ __device__ __forceinline__ void coarse_body(const StepArgs& a, const StepState& 
   const int ld = L.ld;
   const T* __restrict__ u = reinterpret_cast<const T*>(st.Ucur) + (size_t)s * a.sstride;
   T* __restrict__ uo = reinterpret_cast<T*>(st.Uold) + (size_t)s * a.sstride;
+  T* un = reinterpret_cast<T*>(st.Unew) + (size_t)s * a.sstride;
   const T ap = (T)a.coef[(size_t)s * (L.p + 1)];
   const bool startup = st.startup;
   constexpr int R = 4;
@@ -178,7 +181,7 @@ __device__ __forceinline__ void coarse_body(const StepArgs& a, const StepState& 
     const T w = (T)im[r] * ((T)cEg * (uC - ue[r]) + (T)cWg * (uC - uw[r]) + (T)cNg * (uC - uN) +
                             (T)cSg * (uC - uS));
     const T d = ap * w;
-    uo[(size_t)(j0 + r) * ld + i] = startup ? (uC + d) : ((T)2 * uC - uold[r] + (T)2 * d);
+    un[(size_t)(j0 + r) * ld + i] = startup ? (uC + d) : ((T)2 * uC - uold[r] + (T)2 * d);
   }
 }
 
@@ -213,7 +216,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse(StepArgs a) {
   if (Lid >= G) return;
   int item, s;
   coarse_order(Lid, a.n_coarse, a.active, item, s);
-  coarse_body<T>(a, StepState{a.Ucur, a.Uold, a.startup}, lk, a.s0 + s, item);
+  coarse_body<T>(a, StepState{a.Ucur, a.Uold, a.Unew, a.startup}, lk, a.s0 + s, item);
 }
 
 // Job and job-local workgroup index of this workgroup in a batched launch;
@@ -254,7 +257,7 @@ __device__ __forceinline__ StepArgs job_record(const StepArgs& a) {
   b.n_fine = a.n_fine; b.n_coarse = a.n_coarse; b.wg_per_sample = a.wg_per_sample;
   b.per_xcd = a.per_xcd; b.active = a.active;
   b.kappa = LTS_GPTR(a.kappa); b.coef = LTS_GPTR(a.coef);
-  b.Ucur = nullptr; b.Uold = nullptr;                 // per step: StepState
+  b.Ucur = nullptr; b.Uold = nullptr; b.Unew = nullptr;   // per step: StepState
   b.sstride = a.sstride; b.startup = 0; b.s0 = a.s0;
   b.B0 = LTS_GPTR(a.B0); b.B1 = LTS_GPTR(a.B1);
   return b;
@@ -262,7 +265,7 @@ __device__ __forceinline__ StepArgs job_record(const StepArgs& a) {
 
 __device__ __forceinline__ StepState job_state(const MultiArgs& m, const StepArgs& a) {
   const bool odd = m.step & 1;
-  return StepState{odd ? a.B1 : a.B0, odd ? a.B0 : a.B1, m.step == 0};
+  return StepState{odd ? a.B1 : a.B0, odd ? a.B0 : a.B1, odd ? a.B0 : a.B1, m.step == 0};
 }
 
 template <class T>
@@ -299,6 +302,7 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepS
   const int p = L.p;
   const T* __restrict__ u_g = reinterpret_cast<const T*>(st.Ucur) + (size_t)s * a.sstride;
   T* __restrict__ uo_g = reinterpret_cast<T*>(st.Uold) + (size_t)s * a.sstride;
+  T* uw_g = reinterpret_cast<T*>(st.Unew) + (size_t)s * a.sstride;
   const double* __restrict__ cf = a.coef + (size_t)s * (L.p + 1);
   T* const q0 = lq;                    // q of the even substeps' inputs
   T* const q1 = lq + (kCap + 1);       // and of the odd ones'; slot len of each holds 0
@@ -403,7 +407,7 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepS
   for (int r = 0; r < kNPT; ++r) {
     if (dd[r] != 0) continue;          // written back by the tile that owns the node
     const size_t k = (size_t)kk[r];
-    uo_g[k] = st.startup ? (u[r] + dfin[r]) : ((T)2 * u[r] - uo_g[k] + (T)2 * dfin[r]);
+    uw_g[k] = st.startup ? (u[r] + dfin[r]) : ((T)2 * u[r] - uo_g[k] + (T)2 * dfin[r]);
   }
 }
 
@@ -445,6 +449,7 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, const StepStat
   const bool col_on = x < RX && gx < L.nxn;
   const T* __restrict__ u_g = reinterpret_cast<const T*>(st.Ucur) + (size_t)s * a.sstride;
   T* __restrict__ uo_g = reinterpret_cast<T*>(st.Uold) + (size_t)s * a.sstride;
+  T* uw_g = reinterpret_cast<T*>(st.Unew) + (size_t)s * a.sstride;
   const double* __restrict__ cf = a.coef + (size_t)s * (L.p + 1);
   const bool startup = st.startup;
   const int ld = L.ld;
@@ -647,7 +652,7 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, const StepStat
   const T ds = startup ? (T)1 : (T)2;
 #pragma unroll
   for (int r = 0; r < R; ++r)
-    if (wmask & (1u << r)) uo_g[(gyb + r) * ld + gx] = ls[r * kFineThreads + tid] + ds * d[r];
+    if (wmask & (1u << r)) uw_g[(gyb + r) * ld + gx] = ls[r * kFineThreads + tid] + ds * d[r];
 }
 
 template <bool RECT, class T>
@@ -660,10 +665,11 @@ __global__ __launch_bounds__(kFineThreads) void k_fine(StepArgs a) {
   if (Lid >= G) return;
   const int s = a.s0 + Lid / a.n_fine;
   if (RECT) {
-    fine_tile_rect<T>(a, StepState{a.Ucur, a.Uold, a.startup}, lk, lq, ls, s, Lid % a.n_fine);
+    fine_tile_rect<T>(a, StepState{a.Ucur, a.Uold, a.Unew, a.startup}, lk, lq, ls, s, Lid % a.n_fine);
   } else {
     load_kappa(a, s, lk);
-    fine_tile_compact<T, kFineThreads>(a, StepState{a.Ucur, a.Uold, a.startup}, lk, lq, s, Lid % a.n_fine);
+    fine_tile_compact<T, kFineThreads>(a, StepState{a.Ucur, a.Uold, a.Unew, a.startup}, lk, lq, s,
+                                       Lid % a.n_fine);
   }
 }
 
@@ -678,7 +684,7 @@ __global__ __launch_bounds__(NT) void k_fine_small(StepArgs a) {
   if (Lid >= G) return;
   const int s = a.s0 + Lid / a.n_fine;
   load_kappa(a, s, lk);
-  fine_tile_compact<T, NT>(a, StepState{a.Ucur, a.Uold, a.startup}, lk, lq, s, Lid % a.n_fine);
+  fine_tile_compact<T, NT>(a, StepState{a.Ucur, a.Uold, a.Unew, a.startup}, lk, lq, s, Lid % a.n_fine);
 }
 
 template <bool RECT, class T>
@@ -1065,7 +1071,7 @@ lts_status default_tiling(lts_ctx c, DevLevel& lv) {
 
 lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const double* d_kappa,
                        const double* d_coef, const double* Ucur, double* Uold, size_t sstride, int s0,
-                       int active, int startup, hipStream_t stream, bool fp32) {
+                       int active, int startup, hipStream_t stream, bool fp32, double* Unew) {
   if (active <= 0) return LTS_OK;
   StepArgs a;
   a.L = lv.view();
@@ -1081,6 +1087,7 @@ lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const 
   a.coef = d_coef;
   a.Ucur = Ucur;
   a.Uold = Uold;
+  a.Unew = Unew ? Unew : Uold;
   a.sstride = sstride;
   a.startup = startup;
   a.s0 = s0;
@@ -1196,6 +1203,7 @@ void job_record(const DevLevel& lv, const TilingDev& T, const double* d_kappa, c
   a.B1 = B1;
   a.Ucur = B0;
   a.Uold = B1;
+  a.Unew = B1;
   std::memcpy(out, &a, sizeof(a));
 }
 
