@@ -364,6 +364,15 @@ def batch_bench(plain: bool, fp32: bool = True, emit: bool = True):
     ctx.batch_run(jobs, graph=True)                      # warm-up; captures the graph
     t_graph, q_graph = median_time(lambda: ctx.batch_run(jobs, graph=True), 3)
     t_batch, q_batch = median_time(lambda: ctx.batch_run(jobs, graph=False), 3)
+    persist = {}
+    for cap in (4, 1):                                   # the persistent form, S_b capped at 4 and at 1
+        ctx.batch_run(jobs, persist=True, sb_cap=cap)                   # warm-up
+        t_p, q_p = median_time(lambda: ctx.batch_run(jobs, persist=True, sb_cap=cap), 1)
+        persist[f"sb_cap_{cap}"] = {"s": t_p, "dof_updates_per_s": dof_upd / t_p,
+                                    "q_equal": bool(np.array_equal(np.asarray(q_p), np.asarray(q_graph)))}
+    ctx.batch_run(jobs, auto=True)                       # measures the forms on the first steps, caches the choice
+    t_auto, q_auto = median_time(lambda: ctx.batch_run(jobs, auto=True), 3)
+    tm = ctx.timing()
     per_level = lambda **kw: np.concatenate([np.asarray(ctx.forward(j[0], *j[1:5], width=j[5], **kw))
                                              for j in jobs])
     t_level, q_level = median_time(per_level, 3)
@@ -380,6 +389,11 @@ def batch_bench(plain: bool, fp32: bool = True, emit: bool = True):
            "batched_graph": {"s": t_graph, "dof_updates_per_s": dof_upd / t_graph,
                              "hbm_frac_algorithmic": alg_bytes / t_graph / (HBM_PEAK_GBS * 1e9)},
            "batched_no_graph": {"s": t_batch, "dof_updates_per_s": dof_upd / t_batch},
+           "batched_persistent": persist,
+           "batched_auto": {"s": t_auto, "dof_updates_per_s": dof_upd / t_auto,
+                            "form": {0: "step launches", 1: "graph", 2: "persistent"}[tm["batch_form"]],
+                            "sb_cap": tm["batch_sb_cap"],
+                            "q_equal": bool(np.array_equal(np.asarray(q_auto), np.asarray(q_graph)))},
            "one_forward_per_level": {"s": t_level, "dof_updates_per_s": dof_upd / t_level},
            "batched_graph_fp32_step": None if not fp32 else {
                "s": t_f32, "dof_updates_per_s": dof_upd / t_f32,

@@ -345,13 +345,33 @@ typedef struct {
 } lts_job;
 
 enum { LTS_BATCH_GRAPH = 1,      /* capture the step loop into HIP graphs and replay */
-       LTS_BATCH_FP32 = 2 };      /* FP32 stepping as LTS_FP32_STEP; QoI sums in FP64 */
+       LTS_BATCH_FP32 = 2,        /* FP32 stepping as LTS_FP32_STEP; QoI sums in FP64 */
+       LTS_BATCH_PERSIST = 4,     /* persistent form (below); excludes LTS_BATCH_GRAPH */
+       LTS_BATCH_SB1 = 8,         /* persistent form: S_b capped at 1 */
+       LTS_BATCH_SB2 = 16,        /* persistent form: S_b capped at 2 (neither: at 4) */
+       LTS_BATCH_SB_MASK = 24,
+       LTS_BATCH_AUTO = 32 };     /* choose the form by measurement (below) */
 
-/* Advance all jobs of all levels in shared launches: every launch advances
- * one step of every job that still has steps left, so uneven mesh sizes and
- * step counts share the device.  Fine-tile shapes come from the context's
- * autotuner (tuned once per level shape and cached).  FP64.
- * flags: LTS_BATCH_GRAPH and/or LTS_BATCH_FP32.  Errors as lts_forward. */
+/* Advance all jobs of all levels together (the MLMC cost sum_l N_l C_l of
+ * Sec. 2.2 spread over one device): uneven mesh sizes and step counts share
+ * the device.  Fine-tile shapes come from the context's autotuner (tuned once
+ * per level shape and cached).  FP64 unless LTS_BATCH_FP32.  Forms:
+ *  - default: one set of step launches per coarse step, each advancing every
+ *    job that still has steps left (LTS_BATCH_GRAPH: the launch sequence
+ *    captured once per job-list shape into a HIP graph and replayed);
+ *  - LTS_BATCH_PERSIST: one cooperative launch (one workgroup per CU) runs
+ *    all steps of all jobs, with a device-wide barrier after each step; a
+ *    workgroup runs a rect-mode fine tile, four coarse items, or S_b compact
+ *    tiles of one tile position for S_b consecutive samples side by side
+ *    (S_b = 1, 2 or 4: the largest whose tiles of 1024 / S_b threads hold the
+ *    level's regions, capped by LTS_BATCH_SB1 / LTS_BATCH_SB2).  A barrier
+ *    wait is bounded (lts_set_barrier_timeout): on expiry every workgroup
+ *    leaves and the call fails with LTS_ERR_STATE.  Needs cooperative launch.
+ *  - LTS_BATCH_AUTO: time the first steps of this job list (at most 48) in
+ *    the graph form and the persistent form with S_b caps 4, 2 and 1, and run
+ *    the whole batch in the fastest (the choice is cached per job-list shape;
+ *    lts_get_timing reports it).  Excludes the other form flags.
+ * Every form gives bit-identical QoIs.  Errors as lts_forward. */
 lts_status lts_batch_run(lts_ctx ctx, const lts_job* jobs, int32_t n_jobs, int32_t flags,
                          double* Q_out);
 
@@ -577,12 +597,20 @@ typedef struct {
   double total_ms;                /* HIP-event time of the whole device part */
   double dof_updates;             /* sum over samples of n_steps ((N - |P|) + p |P|) */
   double alg_bytes;               /* sum over samples of n_steps * 24 (12 in FP32) * N */
+  int32_t batch_form;             /* last lts_batch_run: 0 step launches, 1 graph, 2 persistent */
+  int32_t batch_sb_cap;           /* its S_b cap (persistent form), else 0 */
 } lts_timing;
 
 /* Enable (1) or disable (0) per-launch event timing (adds events around the
  * step kernel launches on the context stream). */
 lts_status lts_set_timing(lts_ctx ctx, int32_t enable);
 lts_status lts_get_timing(lts_ctx ctx, lts_timing* out);
+
+/* Bound on a persistent workgroup's wait at a step barrier, in milliseconds
+ * of the device's constant wall clock (default 2000; > 0).  A wait that runs
+ * out makes the whole launch leave and lts_batch_run fail with LTS_ERR_STATE.
+ * Errors: LTS_ERR_ARG. */
+lts_status lts_set_barrier_timeout(lts_ctx ctx, double ms);
 
 #ifdef __cplusplus
 }

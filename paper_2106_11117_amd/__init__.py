@@ -329,9 +329,12 @@ class Context:
                                              C.byref(ca.s), precision, qfp, qcp, dqp))
         return qf, qc, dq
 
-    def batch_run(self, jobs, graph=False, precision=LTS_FP64):
+    def batch_run(self, jobs, graph=False, precision=LTS_FP64, persist=False, sb_cap=4, auto=False):
         """jobs: list of (level, kappa, x0, n_steps, dt, width).  Returns the Q of all
-        jobs concatenated in job order.  precision LTS_FP32_STEP steps in binary32."""
+        jobs concatenated in job order.  precision LTS_FP32_STEP steps in binary32.
+        Form: per-step launches (default), their HIP graph (graph=True), one
+        persistent launch (persist=True, S_b capped at sb_cap in 1, 2, 4) or the
+        fastest of these by measurement (auto=True)."""
         args, cjobs, off = [], [], 0
         for (level, kappa, x0, ns, dt, width) in jobs:
             sa = _SampleArgs(kappa, x0, ns, dt, width)
@@ -341,8 +344,18 @@ class Context:
         arr = (_lib.Job * len(cjobs))(*cjobs)
         q, qp = args[0].out(off)
         flags = (LTS_BATCH_GRAPH if graph else 0) | (_lib.LTS_BATCH_FP32 if precision == LTS_FP32_STEP else 0)
+        if persist:
+            if sb_cap not in (1, 2, 4):
+                raise ValueError("sb_cap must be 1, 2 or 4")
+            flags |= _lib.LTS_BATCH_PERSIST | {1: _lib.LTS_BATCH_SB1, 2: _lib.LTS_BATCH_SB2, 4: 0}[sb_cap]
+        if auto:
+            flags |= _lib.LTS_BATCH_AUTO
         self._c(self.lib.lts_batch_run(self.h, arr, len(cjobs), flags, qp))
         return q
+
+    def set_barrier_timeout(self, ms):
+        """Bound (ms) on a persistent workgroup's wait at a step barrier."""
+        self._c(self.lib.lts_set_barrier_timeout(self.h, float(ms)))
 
     def backward(self, level, kappa, x0, n_steps, dt, dLdQ, width=0.05, K=64, g=None):
         """(Q, dL/dg) with L = sum_s dLdQ[s] Q_s; coefficient as in forward()."""

@@ -18,6 +18,11 @@ LTS_NODE_DOF, LTS_NODE_P, LTS_NODE_FPLUS = 1, 2, 4
 LTS_RULE_BOX, LTS_RULE_GRADED_L, LTS_RULE_LF = 0, 1, 0x100
 LTS_BATCH_GRAPH = 1
 LTS_BATCH_FP32 = 2
+LTS_BATCH_PERSIST = 4
+LTS_BATCH_SB1 = 8
+LTS_BATCH_SB2 = 16
+LTS_BATCH_SB_MASK = 24
+LTS_BATCH_AUTO = 32
 LTS_MLMC_BATCHED, LTS_MLMC_PLAIN = 0, 1
 LTS_FINE_HALF_H, LTS_FINE_TIERS, LTS_FINE_QOPT = 0, 1, 2
 LTS_LINE_KL, LTS_LINE_JUMP = 0, 1
@@ -125,7 +130,8 @@ class LineMLMCResult(C.Structure):
 
 class Timing(C.Structure):
     _fields_ = [("step_kernel_ms", C.c_double), ("step_launches", C.c_int64), ("total_ms", C.c_double),
-                ("dof_updates", C.c_double), ("alg_bytes", C.c_double)]
+                ("dof_updates", C.c_double), ("alg_bytes", C.c_double), ("batch_form", C.c_int32),
+                ("batch_sb_cap", C.c_int32)]
 
 
 # (name, restype, argtypes) of every exported entry point of include/lfltsmc.h
@@ -169,6 +175,7 @@ SIGNATURES = [
     ("lts_line_mlmc", C.c_int32, [C.c_void_p, C.POINTER(LineMLMCOpts), C.POINTER(LineMLMCResult), dp]),
     ("lts_set_timing", C.c_int32, [C.c_void_p, C.c_int32]),
     ("lts_get_timing", C.c_int32, [C.c_void_p, C.POINTER(Timing)]),
+    ("lts_set_barrier_timeout", C.c_int32, [C.c_void_p, C.c_double]),
 ]
 
 _lib = None

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -106,6 +107,12 @@ struct lts_ctx_s {
   lts::DevBuf kappa, coef, nsteps, x0, Qd, perm, flag, st0, st1, wbuf, qa, qb, red, adj, adjscr, dldq, gout, adjlist;
   // batched form: per-job tables, states, job records, captured graph
   lts::DevBuf b_tab, b_states, b_jobs, b_Q;
+  // persistent form: active-sample table, control words (unit counters,
+  // barrier arrivals, abort word), barrier wait bound and the wall-clock rate
+  lts::DevBuf b_act, p_ctl;
+  double barrier_ms = 2000.0;
+  int wall_khz = 100000;
+  std::map<std::vector<uint64_t>, std::pair<int, int>> batch_forms;   // LTS_BATCH_AUTO: form, S_b cap
   hipGraphExec_t graph = nullptr;
   std::vector<uint64_t> graph_key;
   bool timing = false;
@@ -240,6 +247,18 @@ struct StepArgs;
 // With fp32 the jobs' state buffers hold binary32 values.
 lts_status launch_multi_step(lts_ctx c, const StepArgs* d_jobs, const std::vector<const TilingDev*>& T,
                              const std::vector<int>& active, int step, hipStream_t stream, bool fp32 = false);
+// The persistent form: steps 0 .. n_steps-1 of every job in cooperative
+// launches of one workgroup per CU with a grid barrier after each step
+// (see lts_fused.hip).  act_host[t * n_jobs + j] = active samples of job j at
+// step t (its copy d_act on the device); sb[j] = 0 for a rect-mode job, else
+// S_b in {1, 2, 4}, the samples a workgroup runs side by side (compact tiles
+// of at most 1024 / S_b threads).  Waits for the launches; LTS_ERR_STATE if a
+// workgroup gave up at a barrier (c->barrier_ms).
+lts_status launch_persist(lts_ctx c, const StepArgs* d_jobs, const std::vector<const TilingDev*>& T,
+                          const std::vector<int>& act_host, const int* d_act, int n_steps, const std::vector<int>& sb,
+                          hipStream_t stream, bool fp32);
+// Largest S_b of a tiling: 0 in rect mode, else 1024 / (fewest threads holding its largest region).
+inline int persist_sb_max(const TilingDev& T) { return T.rect ? 0 : kFineThreads / T.nt; }
 // Writes the static step record of one job (step_args_size() bytes) to `out`.
 void job_record(const DevLevel& lv, const TilingDev& T, const double* d_kappa, const double* d_coef,
                 double* B0, double* B1, size_t sstride, void* out);

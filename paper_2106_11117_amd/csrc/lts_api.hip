@@ -356,6 +356,9 @@ lts_status lts_create(lts_ctx* out, int32_t hip_device, void* hip_stream) {
   int n_cu = 0;
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && n_cu > 0)
     c->n_cu = n_cu;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, hip_device) == hipSuccess && khz > 0)
+    c->wall_khz = khz;
   if (noalloc_attach(c, hip_device) != LTS_OK) {
     delete c;
     return LTS_ERR_HIP;
@@ -782,6 +785,14 @@ lts_status lts_set_timing(lts_ctx c, int32_t enable) {
 lts_status lts_get_timing(lts_ctx c, lts_timing* out) {
   if (!c || !out) return LTS_ERR_ARG;
   *out = c->last;
+  return LTS_OK;
+}
+
+lts_status lts_set_barrier_timeout(lts_ctx c, double ms) {
+  if (!c) return LTS_ERR_ARG;
+  c->err.clear();
+  if (!(ms > 0.0) || !std::isfinite(ms) || ms > 3.6e6) return arg_fail(c, "barrier timeout must be in (0, 3.6e6] ms");
+  c->barrier_ms = ms;
   return LTS_OK;
 }
 

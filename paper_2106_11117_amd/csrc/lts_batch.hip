@@ -208,7 +208,17 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
   if (!c) return LTS_ERR_ARG;
   c->err.clear();
   if (!jobs || n_jobs < 1 || n_jobs > kMaxJobs) return arg_fail(c, "n_jobs must be in 1..32");
-  if (flags & ~(LTS_BATCH_GRAPH | LTS_BATCH_FP32)) return arg_fail(c, "unknown flags");
+  if (flags & ~(LTS_BATCH_GRAPH | LTS_BATCH_FP32 | LTS_BATCH_PERSIST | LTS_BATCH_SB_MASK | LTS_BATCH_AUTO))
+    return arg_fail(c, "unknown flags");
+  const bool autof = (flags & LTS_BATCH_AUTO) != 0;
+  if (autof && (flags & (LTS_BATCH_GRAPH | LTS_BATCH_PERSIST | LTS_BATCH_SB_MASK)))
+    return arg_fail(c, "LTS_BATCH_AUTO excludes the other form flags");
+  bool persist = (flags & LTS_BATCH_PERSIST) != 0;
+  bool graph = (flags & LTS_BATCH_GRAPH) != 0;
+  if (persist && graph) return arg_fail(c, "LTS_BATCH_PERSIST and LTS_BATCH_GRAPH exclude each other");
+  const int sb_code = (flags & LTS_BATCH_SB_MASK) / LTS_BATCH_SB1;   // 0: largest S_b that fits
+  if (sb_code == 3 || (sb_code && !persist)) return arg_fail(c, "bad S_b cap");
+  int sb_cap = sb_code == 0 ? 4 : sb_code == 1 ? 1 : 2;
   const bool fp32 = (flags & LTS_BATCH_FP32) != 0;
   const size_t es = fp32 ? sizeof(float) : sizeof(double);   // bytes per state value
   const int kind = jobs[0].samples.ptr_kind;
@@ -273,7 +283,33 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
   LTS_HIP(c, hipMemcpyAsync(c->b_jobs.p, recs.data(), recs.size(), hipMemcpyHostToDevice, c->stream));
   LTS_HIP(c, hipStreamSynchronize(c->stream));   // host staging buffers may be released after this
 
-  auto record = [&]() -> lts_status {
+  // active samples of every job at every step (samples sorted by decreasing n_steps)
+  std::vector<int> act_tab((size_t)maxT * n_jobs);
+  {
+    std::vector<int> act(n_jobs);
+    for (int j = 0; j < n_jobs; ++j) act[j] = st[j].n;
+    for (int t = 0; t < maxT; ++t)
+      for (int j = 0; j < n_jobs; ++j) {
+        while (act[j] > 0 && st[j].nsteps[act[j] - 1] <= t) --act[j];
+        act_tab[(size_t)t * n_jobs + j] = act[j];
+      }
+  }
+  // S_b of every job under a cap (0 for rect mode)
+  auto sb_for = [&](int cap) {
+    std::vector<int> v(n_jobs, 0);
+    for (int j = 0; j < n_jobs; ++j)
+      if (!T[j]->rect) v[j] = std::max(1, std::min(persist_sb_max(*T[j]), cap));
+    return v;
+  };
+  if (persist || autof) {
+    LTS_HIP(c, c->b_act.ensure(std::max<size_t>(act_tab.size() * sizeof(int), 256)));
+    if (!act_tab.empty())
+      LTS_HIP(c, hipMemcpyAsync(c->b_act.p, act_tab.data(), act_tab.size() * sizeof(int), hipMemcpyHostToDevice,
+                                c->stream));
+  }
+
+  // steps 0 .. n_t-1 of every job (from the initial states), then the QoIs
+  auto record_n = [&](int n_t, bool with_qoi, bool use_persist, const std::vector<int>& sbv) -> lts_status {
     lts_status rr;
     for (int j = 0; j < n_jobs; ++j) {
       const DevLevel& lv = *c->levels[jobs[j].level];
@@ -284,15 +320,19 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
           LTS_OK)
         return rr;
     }
-    std::vector<int> act(n_jobs);
-    for (int j = 0; j < n_jobs; ++j) act[j] = st[j].n;
-    for (int t = 0; t < maxT; ++t) {
-      for (int j = 0; j < n_jobs; ++j)
-        while (act[j] > 0 && st[j].nsteps[act[j] - 1] <= t) --act[j];
-      if ((rr = launch_multi_step(c, (const StepArgs*)c->b_jobs.p, T, act, t, c->stream, fp32)) != LTS_OK)
+    if (use_persist) {
+      if ((rr = launch_persist(c, (const StepArgs*)c->b_jobs.p, T, act_tab, c->b_act.as<int>(), n_t, sbv, c->stream,
+                               fp32)) != LTS_OK)
         return rr;
+    } else {
+      std::vector<int> act(n_jobs);
+      for (int t = 0; t < n_t; ++t) {
+        for (int j = 0; j < n_jobs; ++j) act[j] = act_tab[(size_t)t * n_jobs + j];
+        if ((rr = launch_multi_step(c, (const StepArgs*)c->b_jobs.p, T, act, t, c->stream, fp32)) != LTS_OK)
+          return rr;
+      }
     }
-    for (int j = 0; j < n_jobs; ++j) {
+    for (int j = 0; j < n_jobs && with_qoi; ++j) {
       const DevLevel& lv = *c->levels[jobs[j].level];
       if (st[j].n == 0) continue;
       double* B0 = (double*)(sb + o_s[j]);
@@ -303,6 +343,79 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
     }
     return LTS_OK;
   };
+
+  if (autof && maxT > 0) {
+    // the form of this job-list shape: cached, or timed on its first steps
+    std::vector<uint64_t> key = {(uint64_t)n_jobs, (uint64_t)fp32};
+    for (int j = 0; j < n_jobs; ++j) {
+      key.push_back(c->levels[jobs[j].level]->tiling.gen);
+      key.push_back((uint64_t)st[j].n);
+    }
+    auto hit = c->batch_forms.find(key);
+    if (hit != c->batch_forms.end()) {
+      graph = hit->second.first == 1;
+      persist = hit->second.first == 2;
+      sb_cap = hit->second.second;
+    } else {
+      int sbm = 0;
+      for (int j = 0; j < n_jobs; ++j)
+        if (!T[j]->rect && T[j]->n_fine > 0) sbm = std::max(sbm, persist_sb_max(*T[j]));
+      std::vector<std::pair<int, int>> cand = {{1, 0}, {2, 4}};
+      if (sbm >= 4) cand.push_back({2, 2});
+      if (sbm >= 2) cand.push_back({2, 1});
+      const int K = std::min(maxT, 48);
+      hipEvent_t a0, a1;
+      LTS_HIP(c, hipEventCreate(&a0));
+      LTS_HIP(c, hipEventCreate(&a1));
+      double best = 1e300;
+      std::pair<int, int> win = cand[0];
+      lts_status rr = LTS_OK;
+      for (const auto& f : cand) {
+        hipGraphExec_t ge = nullptr;
+        if (f.first == 1) {
+          hipGraph_t g;
+          LTS_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+          rr = record_n(K, false, false, {});
+          hipError_t ec = hipStreamEndCapture(c->stream, &g);
+          if (rr != LTS_OK) break;
+          if (ec != hipSuccess) return hip_fail(c, ec, "hipStreamEndCapture");
+          ec = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(g);
+          if (ec != hipSuccess) return hip_fail(c, ec, "hipGraphInstantiate");
+        }
+        float ms = 0.f;
+        for (int rep = 0; rep < 2 && rr == LTS_OK; ++rep) {   // the second run is timed
+          LTS_HIP(c, hipEventRecord(a0, c->stream));
+          if (ge) {
+            hipError_t ec = hipGraphLaunch(ge, c->stream);
+            if (ec != hipSuccess) {
+              (void)hipGraphExecDestroy(ge);
+              return hip_fail(c, ec, "hipGraphLaunch");
+            }
+          } else {
+            rr = record_n(K, false, true, sb_for(f.second));
+          }
+          LTS_HIP(c, hipEventRecord(a1, c->stream));
+          LTS_HIP(c, hipEventSynchronize(a1));
+          LTS_HIP(c, hipEventElapsedTime(&ms, a0, a1));
+        }
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (rr != LTS_OK) break;
+        if (ms < best) {
+          best = ms;
+          win = f;
+        }
+      }
+      (void)hipEventDestroy(a0);
+      (void)hipEventDestroy(a1);
+      if (rr != LTS_OK) return rr;
+      c->batch_forms[key] = win;
+      graph = win.first == 1;
+      persist = win.first == 2;
+      sb_cap = win.second;
+    }
+  }
+  auto record = [&]() { return record_n(maxT, true, persist, sb_for(sb_cap)); };
 
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->timing) {
@@ -315,7 +428,7 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
     e1 = c->ev_pool[1];
     LTS_HIP(c, hipEventRecord(e0, c->stream));
   }
-  if (flags & LTS_BATCH_GRAPH) {
+  if (graph) {
     // key: job shapes, step counts and every device address baked into the graph
     std::vector<uint64_t> key = {(uint64_t)n_jobs, (uint64_t)fp32, (uint64_t)(uintptr_t)tb, (uint64_t)(uintptr_t)sb,
                                  (uint64_t)(uintptr_t)qbp, (uint64_t)(uintptr_t)c->b_jobs.p};
@@ -357,6 +470,8 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
     c->last.step_kernel_ms = ms;
     c->last.step_launches = maxT;
   }
+  c->last.batch_form = persist ? 2 : graph ? 1 : 0;
+  c->last.batch_sb_cap = persist ? sb_cap : 0;
   for (int j = 0; j < n_jobs; ++j) {
     const DevLevel& lv = *c->levels[jobs[j].level];
     const double per_step = (double)(lv.H.n_dof - lv.H.n_P) + (double)lv.H.p * lv.H.n_P;

@@ -34,6 +34,10 @@
 // For coarse items that range is about one horizontal band of the level's
 // items over all samples; for fine tiles, every tile of an eighth of the
 // samples.
+//
+// The same tile and item bodies also run inside k_persist, the persistent
+// form of the batched solve: one cooperative launch for all steps of all
+// jobs, a device-wide barrier after each step (see the comment there).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -99,16 +103,19 @@ namespace {
 // item descriptor is x = i0 | j0 << 16, (y, z) = 64-bit mask of the columns
 // holding a DOF outside F+, w = 16-bit mask of such rows; lanes and wavefronts
 // without such a DOF return at once.
+// tid: thread index within the item's 256 threads; on = false: the threads
+// read in bounds (item and s must be valid) but write nothing, and meet the
+// same workgroup barrier.
 template <class T>
 __device__ __forceinline__ void coarse_body(const StepArgs& a, const StepState& st, double* __restrict__ lk, int s,
-                                            int item) {
+                                            int item, int tid, bool on) {
   const LevelView& L = a.L;
   const int4 it = a.citems[item];
-  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t rows = ((uint32_t)it.w >> (4 * wv)) & 0xFu;
-  const int lane = threadIdx.x & 63;
+  const int lane = tid & 63;
   const uint64_t lm = (uint64_t)(uint32_t)it.y | (uint64_t)(uint32_t)it.z << 32;
-  const bool live = rows != 0 && ((lm >> lane) & 1);
+  const bool live = on && rows != 0 && ((lm >> lane) & 1);
   // Lane = column x0 + lane.  Values are read at the column clamped into the
   // grid (a live lane's column holds a DOF, 1 <= i <= nxn - 2; the boundary
   // columns hold u = 0), so the east / west neighbours of a live lane are the
@@ -126,7 +133,7 @@ __device__ __forceinline__ void coarse_body(const StepArgs& a, const StepState& 
   constexpr int R = 4;
   // ---- one batch of reads (with the sample's kappa table); rows off the grid
   //      are clamped and never used
-  const double kv = (int)threadIdx.x < L.nb ? a.kappa[(size_t)s * L.nb + threadIdx.x] : 0.0;
+  const double kv = tid < L.nb ? a.kappa[(size_t)s * L.nb + tid] : 0.0;
   const double hxE = L.hx[i], hxW = L.hx[i - 1], ihE = L.inv2hx[i], ihW = L.inv2hx[i - 1];
   T uc[R + 2], ued[R], uold[R];
   double im[R], hy[R + 1], ihy[R + 1];
@@ -152,7 +159,7 @@ __device__ __forceinline__ void coarse_body(const StepArgs& a, const StepState& 
     im[r] = L.invm[k];
     uold[r] = startup ? (T)0 : uo[k];
   }
-  if ((int)threadIdx.x < L.nb) lk[threadIdx.x] = kv;
+  if (tid < L.nb) lk[tid] = kv;
   __syncthreads();
   // east / west values of rows j0 .. j0+3 (every lane still active for DPP)
   T ue[R], uw[R];
@@ -216,7 +223,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse(StepArgs a) {
   if (Lid >= G) return;
   int item, s;
   coarse_order(Lid, a.n_coarse, a.active, item, s);
-  coarse_body<T>(a, StepState{a.Ucur, a.Uold, a.Unew, a.startup}, lk, a.s0 + s, item);
+  coarse_body<T>(a, StepState{a.Ucur, a.Uold, a.Unew, a.startup}, lk, a.s0 + s, item, (int)threadIdx.x, true);
 }
 
 // Job and job-local workgroup index of this workgroup in a batched launch;
@@ -277,7 +284,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_multi(MultiArgs m) {
   const int act = n / a.n_coarse;                      // active samples of the job
   int item, s;
   coarse_order(local, a.n_coarse, act, item, s);
-  coarse_body<T>(a, job_state(m, a), lk, s, item);
+  coarse_body<T>(a, job_state(m, a), lk, s, item, (int)threadIdx.x, true);
 }
 
 // Compact mode.  The region's nodes (the F+ nodes within Manhattan distance p
@@ -291,13 +298,16 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_multi(MultiArgs m) {
 // for an absent or non-P neighbour), w = i | j << 16.  Each lane turns its
 // neighbour slots into LDS byte addresses once; the substeps run in pairs so
 // that the two buffers and the roles of the increment registers are fixed.
+// tid: thread index within the tile's NT threads.  on = false: the threads
+// touch no global memory and meet the same workgroup barriers (a persistent
+// workgroup runs several tiles of one level side by side).
 template <class T, int NT>
 __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepState& st, const double* __restrict__ lk,
-                                                  T* __restrict__ lq, int s, int tile) {
+                                                  T* __restrict__ lq, int s, int tile, int tid, bool on) {
   constexpr int kCap = NT * kNPT;      // region nodes this workgroup size holds
   const LevelView& L = a.L;
   const int4 tl = a.tiles[tile];
-  const int len = tl.y;
+  const int len = on ? tl.y : 0;
   const int ix0 = tl.z & 0xFFFF, ix1 = tl.z >> 16, iy0 = tl.w & 0xFFFF, iy1 = tl.w >> 16;
   const int p = L.p;
   const T* __restrict__ u_g = reinterpret_cast<const T*>(st.Ucur) + (size_t)s * a.sstride;
@@ -318,7 +328,7 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepS
   // cells and the cell sizes.
   int4 en[kNPT];
 #pragma unroll
-  for (int r = 0; r < kNPT; ++r) en[r] = a.ent[tl.x + min((int)threadIdx.x + r * NT, len - 1)];
+  for (int r = 0; r < kNPT; ++r) en[r] = on ? a.ent[tl.x + min(tid + r * NT, len - 1)] : make_int4(0, 0, 0, 0);
   const int ld = L.ld;
 #pragma unroll
   for (int r = 0; r < kNPT; ++r) {
@@ -329,7 +339,7 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepS
     for (int t = 0; t < 4; ++t) ad[r][t] = (uint32_t)(len * sizeof(T));
     kk[r] = 0;
     dd[r] = p;                         // never updated, never written
-    const int e = threadIdx.x + r * NT;
+    const int e = tid + r * NT;
     if (e < len) {
       const size_t k = (size_t)(en[r].x & 0x7FFFFFFF);
       const bool pi = en[r].x < 0;
@@ -364,7 +374,7 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepS
       w[r] = aE[r] * (vi - vE) + aW[r] * (vi - vW) + aN[r] * (vi - vN) + aS[r] * (vi - vS);
     }
   }
-  if (threadIdx.x == 0) q0[len] = q1[len] = (T)0;   // slot read for absent / non-P neighbours
+  if (tid == 0) q0[len] = q1[len] = (T)0;            // slot read for absent / non-P neighbours
   __syncthreads();
 
   // Substep m: d_m+1 = (1 + beta_m) d_m - beta_m d_m-1 - c_m (w + A_u q_m) with
@@ -392,7 +402,7 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepS
       const T rr = w[r] + apq;
       const T dn = ((T)1 + b) * dc[r] - b * dq[r] - c * rr;
       dq[r] = dn;
-      if (m + 1 < p) wq[threadIdx.x + r * NT] = pm[r] * (u[r] + dn);
+      if (m + 1 < p) wq[tid + r * NT] = pm[r] * (u[r] + dn);
     }
     if (m + 1 < p) __syncthreads();
   };
@@ -430,9 +440,12 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepS
 // beyond it instead of the true values of v and q: the same one-node-per-
 // substep error front as for q alone, so the tile interior (at distance >= p
 // from the border) stays exact.
-template <class T>
+// UNROLL = false: the substep loop is never unrolled and no substep scalar is
+// preloaded (fewer scalar registers; the persistent kernel's choice).
+template <class T, bool UNROLL = true>
 __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, const StepState& st, double* __restrict__ lk,
-                                               T* __restrict__ lq, T* __restrict__ ls, int s, int tile) {
+                                               T* __restrict__ lq, T* __restrict__ ls, int s, int tile,
+                                               int tid_in = -1) {
   constexpr int R = 4;                                  // rows per lane
   constexpr int W = 64;                                 // boundary-row buffer pitch
   const LevelView& L = a.L;
@@ -440,7 +453,7 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, const StepStat
   const int x0 = td.x & 0xFFFF, y0 = td.x >> 16;
   const int RX = td.y & 0xFFFF, RY = td.y >> 16;
   const int ix0 = td.z & 0xFFFF, ix1 = td.z >> 16, iy0 = td.w & 0xFFFF, iy1 = td.w >> 16;
-  const int tid = threadIdx.x;
+  const int tid = tid_in < 0 ? (int)threadIdx.x : tid_in;
   const int x = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int yb = 4 * wv;                                // first row of this wavefront
@@ -459,7 +472,7 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, const StepStat
   //      read before anything else: the substeps then wait on LDS only
   constexpr int kPre = 8;
   double c_pre[kPre], b_pre[kPre];
-  if (p == 4 || p == 8) {
+  if (UNROLL && (p == 4 || p == 8)) {
 #pragma unroll
     for (int m = 0; m < kPre; ++m) {
       c_pre[m] = m < p ? cf[1 + m] : 0.0;
@@ -636,9 +649,9 @@ __device__ __forceinline__ void fine_tile_rect(const StepArgs& a, const StepStat
       substep(m + 1, std::integral_constant<int, 1>{}, std::true_type{});
     }
   };
-  if (p == 8) {
+  if (UNROLL && p == 8) {
     unrolled(std::integral_constant<int, 8>{});
-  } else if (p == 4) {
+  } else if (UNROLL && p == 4) {
     unrolled(std::integral_constant<int, 4>{});
   } else {
     for (int m = 0; m < p; m += 2) {
@@ -669,7 +682,7 @@ __global__ __launch_bounds__(kFineThreads) void k_fine(StepArgs a) {
   } else {
     load_kappa(a, s, lk);
     fine_tile_compact<T, kFineThreads>(a, StepState{a.Ucur, a.Uold, a.Unew, a.startup}, lk, lq, s,
-                                       Lid % a.n_fine);
+                                       Lid % a.n_fine, (int)threadIdx.x, true);
   }
 }
 
@@ -684,7 +697,8 @@ __global__ __launch_bounds__(NT) void k_fine_small(StepArgs a) {
   if (Lid >= G) return;
   const int s = a.s0 + Lid / a.n_fine;
   load_kappa(a, s, lk);
-  fine_tile_compact<T, NT>(a, StepState{a.Ucur, a.Uold, a.Unew, a.startup}, lk, lq, s, Lid % a.n_fine);
+  fine_tile_compact<T, NT>(a, StepState{a.Ucur, a.Uold, a.Unew, a.startup}, lk, lq, s, Lid % a.n_fine,
+                           (int)threadIdx.x, true);
 }
 
 template <bool RECT, class T>
@@ -701,7 +715,7 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_multi(MultiArgs m) {
     fine_tile_rect<T>(a, st, lk, lq, ls, s, local % a.n_fine);
   } else {
     load_kappa(a, s, lk);
-    fine_tile_compact<T, kFineThreads>(a, st, lk, lq, s, local % a.n_fine);
+    fine_tile_compact<T, kFineThreads>(a, st, lk, lq, s, local % a.n_fine, (int)threadIdx.x, true);
   }
 }
 
@@ -714,7 +728,231 @@ __global__ __launch_bounds__(NT) void k_fine_small_multi(MultiArgs m) {
   const StepArgs a = job_record(m.jobs[j]);
   const int s = local / a.n_fine;
   load_kappa(a, s, lk);
-  fine_tile_compact<T, NT>(a, job_state(m, a), lk, lq, s, local % a.n_fine);
+  fine_tile_compact<T, NT>(a, job_state(m, a), lk, lq, s, local % a.n_fine, (int)threadIdx.x, true);
+}
+
+// The thread index as a value the compiler cannot see through: everything a
+// loop iteration derives from it is recomputed there instead of being hoisted
+// out of the persistent loops and kept in registers across every unit.
+__device__ __forceinline__ int opaque_tid() {
+  int v;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "v"((int)threadIdx.x));
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent form: one cooperative launch of one 1024-thread workgroup per CU
+// advances every job through steps t0 .. t1-1, with a grid-wide barrier after
+// each step (the fine tiles of step t+1 read the halo that other workgroups
+// wrote in step t).
+//
+// Work of a step.  A unit is one workgroup's share: a rect-mode fine tile of
+// one sample; S_b = 1024 / nt compact tiles (nt = 256, 512 or 1024 threads
+// each) of one tile position for S_b consecutive samples, side by side in the
+// workgroup's thread groups; or four coarse items.  The workgroups form ng
+// groups (one per XCD: the hardware hands workgroup b to XCD b mod 8); each
+// group works through its own eighth of every job's units (the fine units of
+// the jobs in order of cost, then the coarse ones), as the per-step launches
+// split them, so that neighbouring tiles stay in one L2.  Inside a group the
+// units are handed out by an atomic counter: a workgroup takes the next index
+// before starting a unit.  An index past the end of step t belongs to a later
+// step; the workgroup keeps it across the barrier, so no index is lost and the
+// counter never needs a reset within the launch.
+//
+// The barrier counts arrivals in two levels: per group, and the last arrival
+// of a group at its k-th barrier of the launch (the k x group size-th) bumps a
+// global counter that every workgroup waits on (k x ng), so that no counter
+// takes more than one group's atomics.  Each workgroup makes its own stores
+// visible with a release fence at device scope before it arrives and acquires
+// after the wait.  The wait is bounded: a workgroup that waits longer than
+// spin_ticks of the constant wall clock (or kSpinMax polls) sets the abort
+// word, and every workgroup leaves at its next barrier, so the launch always
+// ends; the host then reports the abort.
+constexpr int kCtlUnit = 0, kCtlGroup = 256, kCtlGlobal = 512, kCtlAbort = 528, kCtlWords = 544;
+struct PersistArgs {
+  const StepArgs* __restrict__ jobs;
+  const int* __restrict__ act;       // [t][n_jobs]: active samples of job j at step t
+  unsigned* ctl;                     // words kCtlUnit + 16 x: unit counter of group x; kCtlGroup + 16 x:
+                                     // its barrier arrivals; kCtlGlobal: groups arrived; kCtlAbort
+  long long spin_ticks;
+  int n_jobs, t0, t1, ng;
+  int order[kMaxJobs];               // job at segment position q
+  int sb[kMaxJobs];                  // per job: 0 rect mode, else S_b (compact, 1024 / S_b threads per tile)
+  int nf[kMaxJobs], nc[kMaxJobs];    // per job: fine tiles and coarse items per sample
+};
+
+constexpr int kPersistThreads = 1024;
+constexpr unsigned kSpinMax = 1u << 24;
+constexpr int kPersistLds = 4 * (256 + 2 * (256 * kNPT + 1));   // doubles: the largest carve (4 x nt = 256)
+static_assert(kPersistLds >= 256 + kLdsSlots + 4 * kFineThreads, "rect mode carve");
+static_assert(kPersistLds >= 256 + kCompactSlots, "compact 1024 carve");
+static_assert(kPersistLds >= 2 * (256 + 2 * (512 * kNPT + 1)), "compact 512 carve");
+
+// k-th barrier of the launch for a workgroup of group x (ng groups; per_group
+// workgroups in group x).
+__device__ __forceinline__ bool step_barrier(unsigned* ctl, int x, unsigned per_group, unsigned ng, unsigned k,
+                                             long long spin_ticks, int* s_ok) {
+  // every wavefront's stores have reached the L2 before the workgroup barrier;
+  // one release fence then writes the L2 back for the other XCDs (a fence per
+  // wavefront would repeat that write-back sixteen times)
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned* glob = ctl + kCtlGlobal;
+    unsigned* abort_w = ctl + kCtlAbort;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned old = __hip_atomic_fetch_add(ctl + kCtlGroup + 16 * x, 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1u == k * per_group) __hip_atomic_fetch_add(glob, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = k * ng;
+    const long long t_start = wall_clock64();
+    int ok = 1;
+    for (unsigned n = 0;; ++n) {
+      if (__hip_atomic_load(glob, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+      if (__hip_atomic_load(abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+        ok = 0;
+        break;
+      }
+      if (wall_clock64() - t_start > spin_ticks || n >= kSpinMax) {
+        __hip_atomic_store(abort_w, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the other workgroups' stores after it
+    *s_ok = ok;
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
+template <class T, int NT>
+__device__ __forceinline__ void persist_compact(const StepArgs& a, const StepState& st, double* __restrict__ smem,
+                                                int act, int idx, int tid) {
+  constexpr int G = kPersistThreads / NT;               // S_b: samples side by side
+  constexpr int per = 256 + (2 * (NT * kNPT + 1) * (int)sizeof(T) + 7) / 8;   // doubles per thread group
+  const int gi = __builtin_amdgcn_readfirstlane(tid / NT), gt = tid % NT;   // groups are whole wavefronts
+  const int sg = idx / a.n_fine, tile = idx - sg * a.n_fine;
+  const int s = sg * G + gi;
+  const bool on = s < act;
+  const int sv = on ? s : sg * G;                        // a valid sample for the idle groups' scalars
+  double* lk = smem + gi * per;
+  T* lq = reinterpret_cast<T*>(lk + 256);
+  if (on)
+    for (int t = gt; t < a.L.nb; t += NT) lk[t] = a.kappa[(size_t)s * a.L.nb + t];
+  __syncthreads();
+  fine_tile_compact<T, NT>(a, st, lk, lq, sv, tile, gt, on);
+}
+
+template <class T>
+__global__ __launch_bounds__(kPersistThreads) void k_persist(PersistArgs pa) {
+  __shared__ double smem[kPersistLds];
+  __shared__ int seg_end[2 * kMaxJobs], seg_lo[2 * kMaxJobs], seg_act[2 * kMaxJobs];
+  __shared__ unsigned s_idx;
+  __shared__ int s_ok;
+  const int nj = pa.n_jobs, nseg = 2 * nj;
+  const int x = (int)(blockIdx.x % (unsigned)pa.ng);
+  const unsigned per_group = (gridDim.x - (unsigned)x + (unsigned)pa.ng - 1u) / (unsigned)pa.ng;
+  unsigned* cnt = pa.ctl + kCtlUnit + 16 * x;
+  if (threadIdx.x == 0) s_idx = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned base = 0;
+  // active samples of this lane's segment job at the current step (wavefront
+  // 0; the next step's are read before each barrier)
+  int a_cur = 0;
+  if (threadIdx.x < (unsigned)nseg) {
+    const int l = threadIdx.x;
+    a_cur = pa.act[(size_t)pa.t0 * nj + pa.order[l < nj ? l : l - nj]];
+  }
+  for (int t = pa.t0; t < pa.t1; ++t) {
+    const int tid = opaque_tid();
+    // segments of this step for group x: position q < nj the fine units of
+    // job order[q], q >= nj the coarse ones; units split into ng chunks
+    if (tid < 64) {
+      int len = 0, lo = 0, a = 0;
+      if (tid < nseg) {
+        const int q = tid < nj ? tid : tid - nj;
+        const int j = pa.order[q];
+        a = a_cur;
+        int units;
+        if (tid < nj) {
+          const int g = pa.sb[j] > 0 ? pa.sb[j] : 1;
+          units = pa.nf[j] * ((a + g - 1) / g);
+        } else {
+          units = (pa.nc[j] * a + 3) / 4;
+        }
+        const int ch = (units + pa.ng - 1) / pa.ng;
+        lo = min(x * ch, units);
+        len = min(lo + ch, units) - lo;
+      }
+      int v = len;                                      // inclusive scan over the wavefront
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int w = __builtin_amdgcn_ds_bpermute((tid - o) << 2, v);   // lane tid - o (wraps; masked)
+        if (tid >= o) v += w;
+      }
+      if (tid < nseg) {
+        seg_end[tid] = v;
+        seg_lo[tid] = lo;
+        seg_act[tid] = a;
+      }
+    }
+    __syncthreads();
+    const unsigned U = (unsigned)__builtin_amdgcn_readfirstlane(seg_end[nseg - 1]);
+    unsigned g = __builtin_amdgcn_readfirstlane(s_idx);
+    while (g - base < U && g >= base) {
+      const int tid = opaque_tid();
+      const int u = (int)(g - base);
+      __syncthreads();                                   // everyone has read s_idx
+      unsigned nxt = 0;
+      if (tid == 0) nxt = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int k0 = 0, k1 = nseg - 1;                         // first segment with seg_end > u
+      while (k0 < k1) {
+        const int mid = (k0 + k1) >> 1;
+        if (seg_end[mid] > u) k1 = mid;
+        else k0 = mid + 1;
+      }
+      const int k = __builtin_amdgcn_readfirstlane(k0);
+      // uniform over the workgroup: scalar registers and scalar address arithmetic
+      const int idx = __builtin_amdgcn_readfirstlane(seg_lo[k] + u - (k > 0 ? seg_end[k - 1] : 0));
+      const int act = __builtin_amdgcn_readfirstlane(seg_act[k]);
+      const int j = pa.order[k < nj ? k : k - nj];
+      const StepArgs a = job_record(pa.jobs[j]);
+      const bool odd = t & 1;
+      const StepState st{odd ? a.B1 : a.B0, odd ? a.B0 : a.B1, odd ? a.B0 : a.B1, t == 0};
+      if (k >= nj) {
+        // four coarse items: slots 4 idx .. 4 idx + 3 of the job's (item, sample) order
+        const int gi = __builtin_amdgcn_readfirstlane(tid >> 8), slot = 4 * idx + gi;   // whole wavefronts
+        const bool on = slot < a.n_coarse * act;
+        int item = 0, s = 0;
+        if (on) coarse_order(slot, a.n_coarse, act, item, s);
+        coarse_body<T>(a, st, smem + 256 * gi, s, item, tid & 255, on);
+      } else if (pa.sb[j] == 0) {
+        const int s = idx / a.n_fine;
+        fine_tile_rect<T, false>(a, st, smem, reinterpret_cast<T*>(smem + 256),
+                                 reinterpret_cast<T*>(smem + 256) + kLdsSlots, s, idx - s * a.n_fine, tid);
+      } else if (pa.sb[j] == 4) {
+        persist_compact<T, 256>(a, st, smem, act, idx, tid);
+      } else if (pa.sb[j] == 2) {
+        persist_compact<T, 512>(a, st, smem, act, idx, tid);
+      } else {
+        persist_compact<T, 1024>(a, st, smem, act, idx, tid);
+      }
+      __syncthreads();                                   // LDS free for the next unit
+      if (tid == 0) s_idx = nxt;
+      __syncthreads();
+      g = __builtin_amdgcn_readfirstlane(s_idx);
+    }
+    base += U;
+    if (t + 1 < pa.t1) {
+      if (threadIdx.x < (unsigned)nseg) {
+        const int l = threadIdx.x;
+        a_cur = pa.act[(size_t)(t + 1) * nj + pa.order[l < nj ? l : l - nj]];
+      }
+      if (!step_barrier(pa.ctl, x, per_group, (unsigned)pa.ng, (unsigned)(t - pa.t0 + 1), pa.spin_ticks, &s_ok))
+        return;
+    }
+  }
 }
 
 }  // namespace
@@ -1182,6 +1420,98 @@ lts_status launch_multi_step(lts_ctx c, const StepArgs* d_jobs, const std::vecto
     }
   };
   for (int kind = 0; kind < 5; ++kind) go(kind);
+  return LTS_OK;
+}
+
+namespace {
+
+// Clear the persistent launch's counters; all: the abort word too.
+__global__ void k_persist_reset(unsigned* ctl, int all) {
+  for (int t = threadIdx.x; t < kCtlWords; t += blockDim.x)
+    if (t != kCtlAbort || all) ctl[t] = 0u;
+}
+
+}  // namespace
+
+lts_status launch_persist(lts_ctx c, const StepArgs* d_jobs, const std::vector<const TilingDev*>& T,
+                          const std::vector<int>& act_host, const int* d_act, int n_steps, const std::vector<int>& sb,
+                          hipStream_t stream, bool fp32) {
+  const int nj = (int)T.size();
+  if (nj < 1 || nj > kMaxJobs || (int)sb.size() != nj || (int)act_host.size() < n_steps * nj) {
+    c->err = "persistent launch: bad job table";
+    return LTS_ERR_ARG;
+  }
+  if (n_steps <= 0) return LTS_OK;
+  int coop = 0;
+  LTS_HIP(c, hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device));
+  if (!coop) {
+    c->err = "persistent launch: the device has no cooperative launch";
+    return LTS_ERR_STATE;
+  }
+  const void* fn = fp32 ? reinterpret_cast<const void*>(&k_persist<float>)
+                        : reinterpret_cast<const void*>(&k_persist<double>);
+  int per_cu = 0;
+  LTS_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kPersistThreads, 0));
+  if (per_cu < 1) {
+    c->err = "persistent launch: the kernel does not fit a compute unit";
+    return LTS_ERR_STATE;
+  }
+  const int grid = per_cu * c->n_cu;
+  PersistArgs pa{};
+  pa.jobs = d_jobs;
+  pa.act = d_act;
+  LTS_HIP(c, c->p_ctl.ensure(kCtlWords * sizeof(unsigned)));
+  pa.ctl = c->p_ctl.as<unsigned>();
+  pa.spin_ticks = (long long)(c->barrier_ms * (double)c->wall_khz);
+  pa.n_jobs = nj;
+  pa.ng = std::min(8, grid);
+  // fine segments: the costliest workgroups first, so that the cheap ones fill in at the end
+  for (int j = 0; j < nj; ++j) pa.order[j] = j;
+  std::stable_sort(pa.order, pa.order + nj, [&](int x, int y) { return T[x]->wg_work > T[y]->wg_work; });
+  for (int j = 0; j < nj; ++j) {
+    if (sb[j] != 0 && (T[j]->rect || (sb[j] != 1 && sb[j] != 2 && sb[j] != 4) || sb[j] > persist_sb_max(*T[j]))) {
+      c->err = "persistent launch: S_b does not fit the tiling";
+      return LTS_ERR_ARG;
+    }
+    if (sb[j] == 0 && !T[j]->rect && T[j]->n_fine > 0) {
+      c->err = "persistent launch: compact tiling needs S_b >= 1";
+      return LTS_ERR_ARG;
+    }
+    pa.sb[j] = sb[j];
+    pa.nf[j] = T[j]->n_fine;
+    pa.nc[j] = T[j]->n_coarse;
+  }
+  k_persist_reset<<<1, 256, 0, stream>>>(pa.ctl, 1);
+  // launches of consecutive steps whose units keep every group counter below 2^30
+  int t0 = 0;
+  while (t0 < n_steps) {
+    long long units = 0;
+    int t1 = t0;
+    while (t1 < n_steps) {
+      long long u = 0;
+      for (int j = 0; j < nj; ++j) {
+        const long long a = act_host[(size_t)t1 * nj + j];
+        const int g = sb[j] > 0 ? sb[j] : 1;
+        u += (long long)T[j]->n_fine * ((a + g - 1) / g) + ((long long)T[j]->n_coarse * a + 3) / 4 + pa.ng;
+      }
+      if (t1 > t0 && units + u >= (1LL << 30)) break;
+      units += u;
+      ++t1;
+    }
+    if (t0 > 0) k_persist_reset<<<1, 256, 0, stream>>>(pa.ctl, 0);
+    pa.t0 = t0;
+    pa.t1 = t1;
+    void* args[] = {&pa};
+    LTS_HIP(c, hipLaunchCooperativeKernel(fn, dim3((unsigned)grid), dim3(kPersistThreads), args, 0, stream));
+    t0 = t1;
+  }
+  unsigned abort_w = 0;
+  LTS_HIP(c, hipMemcpyAsync(&abort_w, pa.ctl + kCtlAbort, sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+  LTS_HIP(c, hipStreamSynchronize(stream));
+  if (abort_w != 0u) {
+    c->err = "persistent launch: a workgroup waited longer than the barrier limit; results are invalid";
+    return LTS_ERR_STATE;
+  }
   return LTS_OK;
 }
 
