@@ -47,8 +47,8 @@ HBM_PEAK_GBS = 8000.0
 # the algorithmic bytes on the profiled launches (all samples active), applied
 # to the average launch's 1.7105e9 algorithmic bytes.  Valid only for the
 # step-kernel sources the counters were taken with.
-TRAFFIC = {"bytes_per_launch": 1.354 * 1.7105e9,
-           "sources_sha256": "e1e18a9620022f5012495692689bd8174d73dcc37f258de76e657c8784d85f51"}
+TRAFFIC = {"bytes_per_launch": 1.3537 * 1.7105e9,
+           "sources_sha256": "12ac1e43d2db4c15b72f6e95208f84436d18ac3fbb763fab0909fd0787b77e60"}
 STEP_SOURCES = ("lts_fused.hip", "fused.h", "device.h", "lts_step.hip")
 WORKLOAD = ("unit square 512x512 base refined 8x in (0.48,0.52): 442225 DOFs, |P|=204081, p=8, "
             "nu=0.01, 256 samples, 4x4 blocks sigma=0.25, T=1, FP64")
