@@ -12,6 +12,9 @@ and local time-stepping for wave propagation"):
 * ``mesh``     -- rectilinear level meshes (tensor grids split into P1
                   triangles), Dirichlet mask, coefficient blocks, fine-element
                   flags, projector P (Sec. 3.3), lumped mass, QoI weights.
+* ``trimesh``  -- levels given as triangulations (nodes, counter-clockwise
+                  triangles, Dirichlet nodes, element blocks and fine flags,
+                  per-node QoI weights) with the same P1 operators.
 * ``fem``      -- general P1 assembly of K(kappa) and the lumped M
                   (Sec. 3.1, mass-lumped Galerkin system).
 * ``rng``      -- Philox4x64-10 samples via numpy's independent Philox,

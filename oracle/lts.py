@@ -91,9 +91,12 @@ def lf_step(A, z_n, z_nm1, dt):
 def pulse(ops: Operators, x0, width: float = 0.05) -> np.ndarray:
     """Nodal values of exp(-|x - x0|^2 / width^2) on the DOFs."""
     lv = ops.lv
-    X, Y = np.meshgrid(lv.xs, lv.ys)
-    ids = lv.dof_ids
-    px, py = X.ravel()[ids], Y.ravel()[ids]
+    if hasattr(lv, "dof_coords"):                 # a triangle-mesh level
+        px, py = lv.dof_coords()
+    else:
+        X, Y = np.meshgrid(lv.xs, lv.ys)
+        ids = lv.dof_ids
+        px, py = X.ravel()[ids], Y.ravel()[ids]
     r2 = (px - x0[0]) ** 2 + (py - x0[1]) ** 2
     return np.exp(-r2 / (width * width))
 
