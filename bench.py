@@ -415,6 +415,55 @@ def batch_bench(plain: bool, fp32: bool = True, emit: bool = True):
 LINE_EPS = {"kl": (5e-3, 2e-3, 1e-3), "jump": (5e-3, 2e-3, 1e-3)}
 
 
+def mesh_bench(samples: int = 64, T: float = 0.25):
+    """Levels given as triangulations (lts_add_mesh): the unit square with 512
+    cells across refined 8x in the cells meeting (0.48, 0.52), every interior
+    node jittered by up to 0.1 of its spacing and the cells split along
+    alternating diagonals (442,225 DOFs, |P| = 204,081, p = 8: the C1 sizes
+    on an unstructured mesh), `samples` samples to T; the same samples on the
+    C1 grid level by the grid path.  Wall time with the samples' inputs
+    staged; build and first-call costs outside the timed region."""
+    import numpy as np
+
+    import paper_2106_11117_amd as P
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import meshgen
+
+    ctx = P.Context(0)
+    m = meshgen.criss_cross(n=N_BASE, ref=REF, box=BOX, jitter=0.1)
+    t0 = time.perf_counter()
+    mid = ctx.add_mesh(m)
+    build = time.perf_counter() - t0
+    info = ctx.mesh_info(mid)
+    lid = ctx.add_rect_level(P.box_rule(N_BASE, box=BOX, ref=REF, nu=0.01))
+    ctx.autotune(lid)
+    s = P.gen_samples(0, 0, 0, samples, P.sample_rule(T=T), 1.0 / N_BASE)
+    args = (s["kappa"], s["x0"], s["n_steps"], s["dt"])
+    ctx.mesh_forward(mid, *(a[:2] for a in args))                   # warm-up
+    ctx.forward(lid, *(a[:2] for a in args))
+    t0 = time.perf_counter()
+    qm = np.asarray(ctx.mesh_forward(mid, *args))
+    tm = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    qg = np.asarray(ctx.forward(lid, *args))
+    tg = time.perf_counter() - t0
+    per_step = (info["n_dof"] - info["n_P"]) + info["p"] * info["n_P"]
+    upd = float(s["n_steps"].sum()) * per_step
+    out = {"metric": "LF-LTS DOF-updates/s on a triangle mesh (lts_mesh_forward) vs the tensor-grid path",
+           "unit": "DOF-updates/s", "higher_is_better": True, "data": "synthetic (Philox seed 0)", "dtype": "f64",
+           "config": {"workload": "unit square 512 base refined 8x in (0.48,0.52), nodes jittered 0.1, "
+                                  "alternating diagonals", "samples": samples, "T": T,
+                      "sum_n_steps": int(s["n_steps"].sum())},
+           "mesh": {k: info[k] for k in ("n_dof", "n_P", "n_Fplus", "n_edges", "max_degree", "n_tiles",
+                                         "max_region", "halo_ratio")},
+           "build_s": build,
+           "mesh_path": {"s": tm, "dof_updates_per_s": upd / tm,
+                         "q_finite": bool(np.all(np.isfinite(qm)))},
+           "grid_path_c1": {"s": tg, "dof_updates_per_s": upd / tg}}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def line_bench():
     """The one-dimensional workloads of Sec. 4.1 (continuous random wave speed,
     T = 11) and Sec. 4.2 (random jump, T = 6), Neumann data, Q = u(T) in
@@ -505,6 +554,8 @@ def main():
                     help="only run 4 plain device copies of MIB MiB (calibrates HBM byte counters)")
     ap.add_argument("--lf", action="store_true",
                     help="only compare LF-LTS with the standard leapfrog baseline (graded L-shape hierarchy)")
+    ap.add_argument("--mesh", action="store_true",
+                    help="the triangle-mesh path on a C1-sized unstructured mesh against the grid path")
     ap.add_argument("--line", action="store_true",
                     help="only run the one-dimensional workloads' MLMC, LF-LTS against leapfrog")
     ap.add_argument("--stream-check", action="store_true",
@@ -539,6 +590,9 @@ def main():
         return
     if args.lf:
         lf_bench()
+        return
+    if args.mesh:
+        mesh_bench()
         return
     if args.line:
         line_bench()

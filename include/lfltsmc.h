@@ -214,6 +214,65 @@ typedef struct {
 lts_status lts_tiling_host(const lts_rect_rule* rule, int32_t tile_x, int32_t tile_y, int32_t rect,
                            lts_tiling_info* info, int32_t* owner);
 
+/* ------------------------------------------------------------------------ */
+/* Levels given as triangulations (Sec. 3.1: conforming P1 elements with     */
+/* mass lumping on a triangle mesh)                                          */
+/* ------------------------------------------------------------------------ */
+
+/* One level as a triangle mesh.  Element T contributes kappa_T |T| G_T^T G_T
+ * to the stiffness (G_T: gradients of the barycentric coordinates) and |T|/3
+ * to the lumped mass of each vertex; kappa_T = kappa of block tri_block[T].
+ * A node is a DOF iff it is not Dirichlet; every DOF must be a vertex of a
+ * triangle.  P (Sec. 3.3) marks the DOFs that are vertices of a fine element,
+ * F+ the DOFs of P and those coupled to P by a nonzero stiffness entry.  All
+ * arrays are caller-owned and copied by lts_add_mesh. */
+typedef struct {
+  int32_t n_nodes, n_tris;
+  int32_t n_blocks;               /* 1..255 */
+  const double* xy;               /* [n_nodes][2], finite */
+  const int32_t* tri;             /* [n_tris][3] node ids, counter-clockwise (positive area);
+                                     every edge in at most two triangles */
+  const uint8_t* dirichlet;       /* [n_nodes]: 1 = homogeneous Dirichlet node (u = 0); NULL = none */
+  const int32_t* tri_block;       /* [n_tris] in [0, n_blocks) */
+  const uint8_t* tri_fine;        /* [n_tris]: 1 = element in D_fine; NULL = none */
+  const double* qoi_w;            /* [n_nodes]: Q = sum over DOFs of qoi_w[i] u_i(T) (the entries of
+                                     Dirichlet nodes are not used); NULL = all 0 */
+  double h;                       /* coarse spacing: the step rule dt = cfl h / max c uses it */
+  int32_t p;                      /* local substeps, 1..64 */
+  double nu;                      /* stabilization, 0 <= nu <= 1 */
+} lts_mesh_desc;
+
+/* Sizes of a triangle-mesh level.  A fine tile's region holds the F+ DOFs
+ * within graph distance p of its DOFs (at most LTS_MESH_REGION_CAP; an F+ DOF
+ * may have at most LTS_MESH_MAX_DEGREE stiffness neighbours). */
+#define LTS_MESH_REGION_CAP 2048
+#define LTS_MESH_MAX_DEGREE 12
+typedef struct {
+  int32_t n_nodes, n_tris, n_dof, n_P, n_Fplus;
+  int32_t n_edges;                /* directed stiffness couplings of the DOF rows (Dirichlet neighbours incl.) */
+  int32_t max_degree;             /* largest number of neighbours of an F+ DOF */
+  int32_t n_tiles, max_region;    /* fine tiles and the largest region */
+  int32_t p, n_blocks;
+  double h, nu, delta, omega;
+  double halo_ratio;              /* region nodes of all tiles / |F+| */
+} lts_mesh_info;
+
+/* Copy a triangle-mesh level into ctx and return its id (0, 1, ... in call
+ * order; mesh ids are separate from the ids of lts_add_level).  Errors:
+ * LTS_ERR_ARG (sizes, orientation, indices, a non-manifold edge, a DOF in no
+ * triangle, an F+ DOF with more than LTS_MESH_MAX_DEGREE neighbours, a region
+ * that exceeds LTS_MESH_REGION_CAP even for a one-DOF tile), LTS_ERR_OOM. */
+lts_status lts_add_mesh(lts_ctx ctx, const lts_mesh_desc* desc, int32_t* mesh_id_out);
+
+/* Sizes of mesh `mesh`.  Errors: LTS_ERR_ARG. */
+lts_status lts_mesh_info_get(lts_ctx ctx, int32_t mesh, lts_mesh_info* out);
+
+/* Host only: validate `desc` and build the level as lts_add_mesh does; info
+ * (required) and, per node (each may be NULL), node_flags [n_nodes]
+ * (LTS_NODE_* bits) and mass [n_nodes] (lumped mass, every node).
+ * Errors: as lts_add_mesh. */
+lts_status lts_mesh_host(const lts_mesh_desc* desc, lts_mesh_info* info, uint8_t* node_flags, double* mass);
+
 /* Stabilized Chebyshev constants of Sec. 3.3 for (p, nu): delta = 1 + nu/p^2,
  * omega = 2 T_p'(delta)/T_p(delta); beta[k] = T_{k-1}(delta)/T_{k+1}(delta) and
  * beta_half[k] = T_k(delta)/T_{k+1}(delta) for k = 1..p-1 (arrays of length p,
@@ -334,6 +393,18 @@ lts_status lts_forward_coupled(lts_ctx ctx, int32_t level_fine, int32_t level_co
                                const lts_samples* fine, const lts_samples* coarse,
                                int32_t precision, double* Qf_out, double* Qc_out, double* dQ_out);
 
+/* Algorithm 2 for every sample on mesh `mesh` (as lts_forward: pulse initial
+ * state exp(-|x - x0|^2 / width^2) at the DOFs, zero velocity, start-up step,
+ * n_steps coarse steps of dt; Q = sum qoi_w u(T)).  FP64 only (precision must
+ * be LTS_FP64).  Errors as lts_forward. */
+lts_status lts_mesh_forward(lts_ctx ctx, int32_t mesh, const lts_samples* samples, int32_t precision,
+                            double* Q_out);
+
+/* Coupled difference on two meshes (Sec. 2.2), as lts_forward_coupled. */
+lts_status lts_mesh_forward_coupled(lts_ctx ctx, int32_t mesh_fine, int32_t mesh_coarse,
+                                    const lts_samples* fine, const lts_samples* coarse, int32_t precision,
+                                    double* Qf_out, double* Qc_out, double* dQ_out);
+
 /* ------------------------------------------------------------------------ */
 /* Batched form: many (level, samples) jobs advanced together                */
 /* ------------------------------------------------------------------------ */
@@ -442,7 +513,13 @@ typedef struct {
                                      from gen_rule when Algorithm 1 first needs them */
   lts_rect_rule gen_rule;         /* level l of a generated hierarchy: gen_rule with
                                      n_base = gen_rule.n_base * 2^l */
+  int32_t level_kind;             /* LTS_LEVELS_GRID: level_ids from lts_add_level /
+                                     lts_build_rect_level; LTS_LEVELS_MESH: mesh ids from
+                                     lts_add_mesh (solved by lts_mesh_forward level by level;
+                                     no generated levels, no gradient) */
 } lts_mlmc_opts;
+
+enum { LTS_LEVELS_GRID = 0, LTS_LEVELS_MESH = 1 };
 
 typedef struct {
   double estimate;                /* sum_l mean(Delta Q_l) */

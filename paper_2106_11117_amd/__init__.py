@@ -16,7 +16,7 @@ from ._lib import (LTS_BATCH_GRAPH, LTS_FP32_STEP, LTS_FP64, LTS_MLMC_BATCHED, L
                    LTS_NODE_DOF, LTS_NODE_FPLUS, LTS_NODE_P, LTS_PTR_DEVICE, LTS_PTR_HOST,
                    LTS_RULE_BOX, LTS_RULE_GRADED_L, LTS_RULE_LF, LtsError)
 
-__all__ = ["Context", "gen_samples", "line_rule", "line_sample_rule", "line_level_host", "gen_line_samples", "philox", "rect_level_host", "tiling_host", "lf_rule", "cheb_constants", "sample_rule", "box_rule", "graded_L_rule", "LtsError",
+__all__ = ["Context", "gen_samples", "mesh_host", "line_rule", "line_sample_rule", "line_level_host", "gen_line_samples", "philox", "rect_level_host", "tiling_host", "lf_rule", "cheb_constants", "sample_rule", "box_rule", "graded_L_rule", "LtsError",
            "LTS_FP64", "LTS_FP32_STEP", "LTS_BATCH_GRAPH", "LTS_MLMC_BATCHED", "LTS_MLMC_PLAIN",
            "LTS_NODE_DOF", "LTS_NODE_P", "LTS_NODE_FPLUS", "LTS_RULE_LF", "LtsQoI"]
 
@@ -155,6 +155,40 @@ def line_sample_rule(kind="kl", T=None, cfl=0.5) -> _lib.LineSampleRule:
     return _lib.LineSampleRule(kind=_lib.LTS_LINE_KL if kind == "kl" else _lib.LTS_LINE_JUMP,
                                jump_lo=4.0 - 1.0 / 16, jump_hi=4.0, c_left=1.0, c_right=2.0, pulse_x=3.0,
                                pulse_w2=0.09, T=(11.0 if kind == "kl" else 6.0) if T is None else T, cfl=cfl)
+
+
+class _MeshArgs:
+    """Marshals a triangle mesh (dict or keyword arrays: xy [n, 2], tris [t, 3]
+    counter-clockwise, dirichlet [n] bool, tri_block [t], tri_fine [t] bool,
+    qoi_nodes [n], n_blocks, h, p, nu) into an lts_mesh_desc."""
+
+    def __init__(self, m):
+        self.keep = [np.ascontiguousarray(m["xy"], dtype=np.float64),
+                     np.ascontiguousarray(m["tris"], dtype=np.int32),
+                     np.ascontiguousarray(m["dirichlet"], dtype=np.uint8),
+                     np.ascontiguousarray(m["tri_block"], dtype=np.int32),
+                     np.ascontiguousarray(m["tri_fine"], dtype=np.uint8),
+                     np.ascontiguousarray(m["qoi_nodes"], dtype=np.float64)]
+        xy, tri, dr, tb, tf, qw = self.keep
+        self.n_nodes = len(xy)
+        self.d = _lib.MeshDesc(n_nodes=len(xy), n_tris=len(tri), n_blocks=int(m["n_blocks"]),
+                               xy=xy.ctypes.data, tri=tri.ctypes.data, dirichlet=dr.ctypes.data,
+                               tri_block=tb.ctypes.data, tri_fine=tf.ctypes.data, qoi_w=qw.ctypes.data,
+                               h=float(m["h"]), p=int(m["p"]), nu=float(m["nu"]))
+
+
+def mesh_host(m) -> dict:
+    """Host only: build a triangle-mesh level as lts_add_mesh does; its info,
+    per-node LTS_NODE_* flags and lumped masses."""
+    lib = _lib.load()
+    a = _MeshArgs(m)
+    info = _lib.MeshInfo()
+    flags = np.zeros(a.n_nodes, dtype=np.uint8)
+    mass = np.zeros(a.n_nodes)
+    _check(lib.lts_mesh_host(C.byref(a.d), C.byref(info), flags.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(mass)))
+    d = {k: getattr(info, k) for k, _ in _lib.MeshInfo._fields_}
+    d.update(flags=flags, mass=mass)
+    return d
 
 
 def line_level_host(rule) -> dict:
@@ -389,8 +423,10 @@ class Context:
         return out
 
     def mlmc(self, level_ids, rule, eps, seed=0, alpha=2.0, L_start=2, N_init=(256, 64, 16, 8, 4),
-             mode=LTS_MLMC_BATCHED, max_total_samples=0, gen_rule=None, n_levels_max=0, grad_K=None):
-        """Algorithm 1 (lts_mlmc).  With gen_rule and n_levels_max > len(level_ids)
+             mode=LTS_MLMC_BATCHED, max_total_samples=0, gen_rule=None, n_levels_max=0, grad_K=None,
+             meshes=False):
+        """Algorithm 1 (lts_mlmc); meshes=True: level_ids are triangle-mesh ids
+        (lts_add_mesh).  With gen_rule and n_levels_max > len(level_ids)
         the hierarchy grows on demand: level l beyond the given ones is built from
         gen_rule with n_base * 2^l when the bias test first asks for it.  With
         grad_K (checkpoint interval) the gradient dE[Q]/dg is estimated alongside
@@ -411,6 +447,7 @@ class Context:
         o.n_levels_max = n_levels_max
         if gen_rule is not None:
             o.gen_rule = gen_rule
+        o.level_kind = 1 if meshes else 0
         r = _lib.MLMCResult()
         nb = rule.n_blocks
         if grad_K is not None:
@@ -426,6 +463,36 @@ class Context:
         if grad_K is not None:
             out.update(grad=ge, grad_mean=gm[:L + 1], grad_var=gv[:L + 1])
         return out
+
+    # --- triangle-mesh levels ----------------------------------------------
+    def add_mesh(self, m) -> int:
+        """A level given as a triangulation (see _MeshArgs); returns its mesh id."""
+        a = _MeshArgs(m)
+        mid = C.c_int32()
+        self._c(self.lib.lts_add_mesh(self.h, C.byref(a.d), C.byref(mid)))
+        return mid.value
+
+    def mesh_info(self, mesh) -> dict:
+        info = _lib.MeshInfo()
+        self._c(self.lib.lts_mesh_info_get(self.h, mesh, C.byref(info)))
+        return {k: getattr(info, k) for k, _ in _lib.MeshInfo._fields_}
+
+    def mesh_forward(self, mesh, kappa, x0, n_steps, dt, width=0.05, g=None):
+        """Q of every sample on a triangle-mesh level (FP64)."""
+        sa = _SampleArgs(kappa, x0, n_steps, dt, width, g)
+        q, qp = sa.out()
+        self._c(self.lib.lts_mesh_forward(self.h, mesh, C.byref(sa.s), LTS_FP64, qp))
+        return q
+
+    def mesh_forward_coupled(self, mesh_fine, mesh_coarse, kappa, x0, ns_f, dt_f, ns_c, dt_c, width=0.05):
+        fa = _SampleArgs(kappa, x0, ns_f, dt_f, width)
+        ca = _SampleArgs(kappa, x0, ns_c, dt_c, width)
+        qf, qfp = fa.out()
+        qc, qcp = fa.out()
+        dq, dqp = fa.out()
+        self._c(self.lib.lts_mesh_forward_coupled(self.h, mesh_fine, mesh_coarse, C.byref(fa.s), C.byref(ca.s),
+                                                  LTS_FP64, qfp, qcp, dqp))
+        return qf, qc, dq
 
     # --- one-dimensional workloads -------------------------------------------
     def add_line_level(self, rule) -> int:

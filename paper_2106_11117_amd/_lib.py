@@ -23,6 +23,8 @@ LTS_BATCH_SB1 = 8
 LTS_BATCH_SB2 = 16
 LTS_BATCH_SB_MASK = 24
 LTS_BATCH_AUTO = 32
+LTS_MESH_REGION_CAP = 2048
+LTS_MESH_MAX_DEGREE = 12
 LTS_MLMC_BATCHED, LTS_MLMC_PLAIN = 0, 1
 LTS_FINE_HALF_H, LTS_FINE_TIERS, LTS_FINE_QOPT = 0, 1, 2
 LTS_LINE_KL, LTS_LINE_JUMP = 0, 1
@@ -74,6 +76,21 @@ class SampleRule(C.Structure):
                 ("width", C.c_double), ("T", C.c_double), ("cfl", C.c_double)]
 
 
+class MeshDesc(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_tris", C.c_int32), ("n_blocks", C.c_int32),
+                ("xy", C.c_void_p), ("tri", C.c_void_p), ("dirichlet", C.c_void_p), ("tri_block", C.c_void_p),
+                ("tri_fine", C.c_void_p), ("qoi_w", C.c_void_p), ("h", C.c_double), ("p", C.c_int32),
+                ("nu", C.c_double)]
+
+
+class MeshInfo(C.Structure):
+    _fields_ = [("n_nodes", C.c_int32), ("n_tris", C.c_int32), ("n_dof", C.c_int32), ("n_P", C.c_int32),
+                ("n_Fplus", C.c_int32), ("n_edges", C.c_int32), ("max_degree", C.c_int32),
+                ("n_tiles", C.c_int32), ("max_region", C.c_int32), ("p", C.c_int32), ("n_blocks", C.c_int32),
+                ("h", C.c_double), ("nu", C.c_double), ("delta", C.c_double), ("omega", C.c_double),
+                ("halo_ratio", C.c_double)]
+
+
 class Samples(C.Structure):
     _fields_ = [("n", C.c_int32), ("ptr_kind", C.c_int32), ("kappa", C.c_void_p), ("x0", C.c_void_p),
                 ("n_steps", C.c_void_p), ("dt", C.c_void_p), ("width", C.c_double), ("g", C.c_void_p)]
@@ -88,7 +105,8 @@ class MLMCOpts(C.Structure):
                 ("rule", SampleRule), ("seed", C.c_uint64), ("eps", C.c_double),
                 ("alpha", C.c_double), ("L_start", C.c_int32),
                 ("N_init", C.c_int32 * LTS_MAX_LEVELS), ("mode", C.c_int32),
-                ("max_total_samples", C.c_int32), ("n_levels_max", C.c_int32), ("gen_rule", RectRule)]
+                ("max_total_samples", C.c_int32), ("n_levels_max", C.c_int32), ("gen_rule", RectRule),
+                ("level_kind", C.c_int32)]
 
 
 class MLMCResult(C.Structure):
@@ -176,6 +194,12 @@ SIGNATURES = [
     ("lts_set_timing", C.c_int32, [C.c_void_p, C.c_int32]),
     ("lts_get_timing", C.c_int32, [C.c_void_p, C.POINTER(Timing)]),
     ("lts_set_barrier_timeout", C.c_int32, [C.c_void_p, C.c_double]),
+    ("lts_add_mesh", C.c_int32, [C.c_void_p, C.POINTER(MeshDesc), ip]),
+    ("lts_mesh_info_get", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(MeshInfo)]),
+    ("lts_mesh_host", C.c_int32, [C.POINTER(MeshDesc), C.POINTER(MeshInfo), u8p, dp]),
+    ("lts_mesh_forward", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Samples), C.c_int32, C.c_void_p]),
+    ("lts_mesh_forward_coupled", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Samples),
+                                             C.POINTER(Samples), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
 ]
 
 _lib = None

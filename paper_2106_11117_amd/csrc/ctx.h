@@ -87,6 +87,14 @@ struct LineDev {
   DevBuf x, invh, invm, pflag, beta;
 };
 
+// A triangle-mesh level on the device (Sec. 3.1 on a triangulation).
+struct TriDev {
+  TriHost H;
+  DevLevel shell;        // the header the sample staging reads (n_blocks, p, Chebyshev constants)
+  size_t ld = 0;         // state stride per sample (elements): n_dof + 1 rounded up
+  DevBuf dx, dy, invm, qoiw, dflag, rp, col, eblk, ewa, ewb, coarse, tiles, ent, tslot, beta;
+};
+
 struct lts_error {
   lts_status code;
   std::string msg;
@@ -102,6 +110,7 @@ struct lts_ctx_s {
   std::string err;
   std::vector<std::unique_ptr<lts::DevLevel>> levels;
   std::vector<std::unique_ptr<lts::LineDev>> lines;       // one-dimensional levels
+  std::vector<std::unique_ptr<lts::TriDev>> meshes;       // triangle-mesh levels
   lts::DevBuf l_kap, l_coef, l_ns, l_U, l_Uc, l_pa, l_pt, l_mass, l_mean, l_dev;   // their workspace
   // workspace
   lts::DevBuf kappa, coef, nsteps, x0, Qd, perm, flag, st0, st1, wbuf, qa, qb, red, adj, adjscr, dldq, gout, adjlist;

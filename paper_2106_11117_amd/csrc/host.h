@@ -84,6 +84,41 @@ std::string gen_samples(uint64_t seed, int32_t sample_level, int64_t first_index
                         const lts_sample_rule& rule, double h_mesh, double* g, double* kappa,
                         double* x0, int32_t* n_steps, double* dt);
 
+// A level given as a triangulation, built on the host.  DOFs are numbered
+// in Morton order of their coordinates; the state of a sample holds the n_dof
+// DOF values and a zero slot at index n_dof (the value of every Dirichlet
+// neighbour).
+constexpr int kTriRegionCap = LTS_MESH_REGION_CAP;
+constexpr int kTriMaxDeg = LTS_MESH_MAX_DEGREE;
+struct TriEnt {            // one node of a fine tile's region
+  int32_t dof;             // DOF index | 0x80000000 if the DOF is in P
+  int32_t row;             // first stiffness coupling of the DOF (CSR offset)
+  int32_t deg_dist;        // number of couplings | graph distance to the tile << 16
+  int32_t slot0;           // offset of the region slots of its couplings (tslot)
+};
+struct TriHost {
+  HostLevel shell;                       // n_blocks, h, p, nu and the Chebyshev constants only
+  int n_nodes = 0, n_tris = 0, n_dof = 0, n_P = 0, n_F = 0, max_deg = 0, max_region = 0;
+  std::vector<int32_t> node_dof;         // [n_nodes] DOF index or -1
+  std::vector<int32_t> dof_node;         // [n_dof]
+  std::vector<double> mass_node;         // [n_nodes] lumped mass
+  std::vector<uint8_t> node_flags;       // [n_nodes] LTS_NODE_* bits
+  std::vector<double> dx, dy, invm, qoiw;   // [n_dof]
+  std::vector<uint8_t> dflag;            // [n_dof + 1] bit 0: P, bit 1: F+ (the zero slot: 0)
+  std::vector<int32_t> rp, col;          // CSR over the DOFs; col = n_dof for a Dirichlet neighbour
+  std::vector<int32_t> eblk;             // block of the first | second triangle << 8 (255: none)
+  std::vector<double> ewa, ewb;          // -|T| grad(l_i).grad(l_j) of those triangles (0: none)
+  std::vector<int32_t> coarse;           // DOFs outside F+, increasing
+  std::vector<int32_t> tiles;            // [n_tiles + 1] offsets of the tiles' regions in ent
+  std::vector<TriEnt> ent;               // region nodes, tile by tile, by increasing distance
+  std::vector<uint16_t> tslot;           // per region node and coupling: the neighbour's region
+                                         // index if it is in P and in the region, else the region size
+  double halo_ratio = 1.0;
+};
+
+// Validates `d` and builds T; "" on success.
+std::string build_tri(const lts_mesh_desc& d, TriHost& T);
+
 // Cost model of one solve in DOF updates: ceil(T/(cfl h)) ((N - |P|) + p |P|).
 double solve_cost_model(const HostLevel& L, const lts_sample_rule& rule);
 

@@ -21,12 +21,19 @@ struct LevelBatch {
   std::vector<int32_t> nsf, nsc;
 };
 
+// The host header of level l of the hierarchy (grid level or triangle mesh):
+// block count, spacing h, p and the sizes the cost model reads.
+const HostLevel& level_header(lts_ctx c, const lts_mlmc_opts& o, int l) {
+  if (o.level_kind == LTS_LEVELS_MESH) return c->meshes[o.level_ids[l]]->H.shell;
+  return c->levels[o.level_ids[l]]->H;
+}
+
 lts_status draw_level(lts_ctx c, const lts_mlmc_opts& o, int l, int64_t first, int n, LevelBatch& b) {
   b.l = l;
   b.n = n;
-  const DevLevel& fine = *c->levels[o.level_ids[l]];
+  const HostLevel& fine = level_header(c, o, l);
   const int nb = o.rule.n_blocks;
-  if (fine.H.n_blocks != nb) {
+  if (fine.n_blocks != nb) {
     c->err = "rule.n_blocks differs from the level's block count";
     return LTS_ERR_ARG;
   }
@@ -38,10 +45,10 @@ lts_status draw_level(lts_ctx c, const lts_mlmc_opts& o, int l, int64_t first, i
   b.nsc.resize(n);
   b.qf.assign(n, 0.0);
   b.qc.assign(n, 0.0);
-  std::string e = gen_samples(o.seed, l, first, n, o.rule, fine.H.h, nullptr, b.kappa.data(), b.x0.data(),
+  std::string e = gen_samples(o.seed, l, first, n, o.rule, fine.h, nullptr, b.kappa.data(), b.x0.data(),
                               b.nsf.data(), b.dtf.data());
   if (e.empty() && l > 0)
-    e = gen_samples(o.seed, l, first, n, o.rule, c->levels[o.level_ids[l - 1]]->H.h, nullptr, nullptr, nullptr,
+    e = gen_samples(o.seed, l, first, n, o.rule, level_header(c, o, l - 1).h, nullptr, nullptr, nullptr,
                     b.nsc.data(), b.dtc.data());
   if (!e.empty()) {
     c->err = e;
@@ -55,6 +62,19 @@ lts_status draw_level(lts_ctx c, const lts_mlmc_opts& o, int l, int64_t first, i
 // level in one graph-captured lts_batch_run.
 lts_status solve_batches(lts_ctx c, const lts_mlmc_opts& o, std::vector<LevelBatch>& bs) {
   lts_status r;
+  if (o.level_kind == LTS_LEVELS_MESH) {
+    // triangle meshes: one batched solve per level and mesh
+    for (auto& b : bs) {
+      if (b.n == 0) continue;
+      lts_samples sf{b.n, LTS_PTR_HOST, b.kappa.data(), b.x0.data(), b.nsf.data(), b.dtf.data(), o.rule.width};
+      if ((r = lts_mesh_forward(c, o.level_ids[b.l], &sf, LTS_FP64, b.qf.data())) != LTS_OK) return r;
+      if (b.l > 0) {
+        lts_samples sc{b.n, LTS_PTR_HOST, b.kappa.data(), b.x0.data(), b.nsc.data(), b.dtc.data(), o.rule.width};
+        if ((r = lts_mesh_forward(c, o.level_ids[b.l - 1], &sc, LTS_FP64, b.qc.data())) != LTS_OK) return r;
+      }
+    }
+    return LTS_OK;
+  }
   if (o.mode == LTS_MLMC_PLAIN) {
     for (auto& b : bs) {
       if (b.n == 0) continue;
@@ -133,8 +153,13 @@ lts_status mlmc_run(lts_ctx c, const lts_mlmc_opts* op, lts_mlmc_result* out, in
   lts_mlmc_opts o = *op;                    // level_ids grows with generated levels
   const int n_total = std::max(o.n_levels, o.n_levels_max);
   if (o.n_levels < 0 || n_total < 1 || n_total > LTS_MAX_LEVELS) return arg_fail(c, "n_levels out of range");
+  if (o.level_kind != LTS_LEVELS_GRID && o.level_kind != LTS_LEVELS_MESH) return arg_fail(c, "bad level_kind");
+  const bool meshes = o.level_kind == LTS_LEVELS_MESH;
+  if (meshes && (n_total > o.n_levels || dg))
+    return arg_fail(c, "triangle-mesh hierarchies are given in full and have no gradient form");
   for (int l = 0; l < o.n_levels; ++l)
-    if (o.level_ids[l] < 0 || o.level_ids[l] >= (int)c->levels.size()) return arg_fail(c, "bad level id");
+    if (o.level_ids[l] < 0 || o.level_ids[l] >= (int)(meshes ? c->meshes.size() : c->levels.size()))
+      return arg_fail(c, "bad level id");
   for (int l = 0; l < n_total; ++l)
     if (o.N_init[l] < 2) return arg_fail(c, "N_init must be >= 2 (variance estimates)");
   if (!(o.eps > 0.0) || !(o.alpha > 0.0)) return arg_fail(c, "eps and alpha must be > 0");
@@ -169,7 +194,7 @@ lts_status mlmc_run(lts_ctx c, const lts_mlmc_opts* op, lts_mlmc_result* out, in
   // cost model C_l in DOF updates per Delta Q_l sample, formed as levels are added
   std::vector<double> cs(n_total, 0.0), C(n_total, 0.0);
   auto add_cost = [&](int l) {
-    cs[l] = solve_cost_model(c->levels[o.level_ids[l]]->H, o.rule);
+    cs[l] = solve_cost_model(level_header(c, o, l), o.rule);
     C[l] = l == 0 ? cs[0] : cs[l] + cs[l - 1];
   };
   for (int l = 0; l <= L; ++l) add_cost(l);

@@ -1,0 +1,172 @@
+"""GPU parity of LF-LTS on levels given as triangulations (lts_add_mesh,
+lts_mesh_forward, lts_mesh_forward_coupled) against the oracle's triangle-mesh
+operators and Algorithm 2 (Sec. 3.1, 3.3), on unstructured meshes (jittered
+criss-cross grids with node degrees 4 and 8; Delaunay meshes with a dense
+disk of fine elements), on one and on many fine tiles."""
+import numpy as np
+import pytest
+
+import meshgen
+import paper_2106_11117_amd as P
+from oracle import lts, rng, trimesh
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    _torch()
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def _oracle(m, smp_list, T, width=0.05):
+    tl = trimesh.tri_level(m["xy"], m["tris"], m["dirichlet"], m["tri_block"], m["tri_fine"], m["qoi_nodes"],
+                           m["n_blocks"], m["h"], m["p"], m["nu"])
+    ops = trimesh.operators(tl)
+    out = []
+    for smp, n, dt in smp_list:
+        u = lts.Solver(ops, smp.kappa).run(lts.pulse(ops, smp.x0, width), dt, n)
+        out.append((float(lts.qoi(ops, u)), float(ops.qoi_w @ np.abs(u))))
+    return out
+
+
+def _samples(n, T, h, first=0):
+    rule = rng.SampleRule(T=T)
+    smps = [rng.draw(0, 0, first + i, rule) for i in range(n)]
+    lst = [(s,) + rng.steps_for(s, rule, h) for s in smps]
+    kap = np.stack([s.kappa for s in smps])
+    x0 = np.stack([s.x0 for s in smps])
+    ns = np.array([t[1] for t in lst], dtype=np.int32)
+    dt = np.array([t[2] for t in lst])
+    return lst, kap, x0, ns, dt
+
+
+CASES = {
+    "criss_cross": (lambda: meshgen.criss_cross(), 9, 0.6),
+    "criss_cross_p2": (lambda: meshgen.criss_cross(n=12, ref=2, jitter=0.25, seed=1), 5, 0.8),
+    "delaunay": (lambda: meshgen.delaunay_disk(), 9, 0.6),
+    "leapfrog": (lambda: dict(meshgen.criss_cross(), tri_fine=np.zeros(1568, bool), p=1), 3, 0.6),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_mesh_forward_matches_oracle(ctx, name):
+    make, n, T = CASES[name]
+    m = make()
+    mid = ctx.add_mesh(m)
+    info = ctx.mesh_info(mid)
+    assert info["n_tiles"] >= (1 if info["n_Fplus"] else 0)
+    lst, kap, x0, ns, dt = _samples(n, T, m["h"])
+    q = ctx.mesh_forward(mid, kap, x0, ns, dt)
+    ref = _oracle(m, lst, T)
+    for i, (qo, sc) in enumerate(ref):
+        assert abs(q[i] - qo) <= 1e-11 * sc, (name, i, q[i], qo)
+
+
+def test_mesh_many_tiles_matches_oracle(ctx):
+    """F+ of 10,873 DOFs in several tiles (regions within the cap): two samples
+    against the oracle."""
+    m = meshgen.criss_cross(n=48, ref=4, box=(0.3, 0.7))
+    mid = ctx.add_mesh(m)
+    info = ctx.mesh_info(mid)
+    assert info["n_tiles"] > 1 and info["max_region"] <= P._lib.LTS_MESH_REGION_CAP
+    lst, kap, x0, ns, dt = _samples(2, 0.4, m["h"], first=7)
+    q = ctx.mesh_forward(mid, kap, x0, ns, dt)
+    for i, (qo, sc) in enumerate(_oracle(m, lst, 0.4)):
+        assert abs(q[i] - qo) <= 1e-11 * sc, (i, q[i], qo)
+
+
+def test_grid_level_as_triangles_matches_grid_path(ctx):
+    """The rectilinear 32-base box level, solved by the grid path and handed to
+    lts_add_mesh as its triangle list (same diagonal split, cell blocks, fine
+    flags and QoI weights): the same QoIs up to rounding order."""
+    rule = P.box_rule(32)
+    lid = ctx.add_rect_level(rule)
+    h = P.rect_level_host(rule)
+    x, y, cb = h["x"], h["y"], h["cell_block"]
+    nx, ny = len(x), len(y)
+    X, Y = np.meshgrid(x, y)
+    xy = np.stack([X.ravel(), Y.ravel()], 1)
+    tris, blocks, fine = [], [], []
+    hx, hy = np.diff(x), np.diff(y)
+    for b in range(ny - 1):
+        for a in range(nx - 1):
+            n00 = b * nx + a
+            tris += [(n00, n00 + 1, n00 + nx + 1), (n00, n00 + nx + 1, n00 + nx)]
+            blocks += [cb[b, a]] * 2
+            f = min(hx[a], hy[b]) < 0.5 * h["h"]
+            fine += [f, f]
+    m = {"xy": xy, "tris": np.array(tris), "dirichlet": (h["flags"].ravel() & 1) == 0,
+         "tri_block": np.array(blocks), "tri_fine": np.array(fine), "qoi_nodes": h["qoi_w"].ravel(),
+         "n_blocks": h["n_blocks"], "h": h["h"], "p": h["p"], "nu": h["nu"]}
+    mid = ctx.add_mesh(m)
+    mi = ctx.mesh_info(mid)
+    assert (mi["n_dof"], mi["n_P"], mi["n_Fplus"]) == (h["n_dof"], h["n_P"], h["n_Fplus"])
+    s = P.gen_samples(0, 0, 0, 6, P.sample_rule(T=0.5), h["h"])
+    qg = ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"])
+    qm = ctx.mesh_forward(mid, s["kappa"], s["x0"], s["n_steps"], s["dt"])
+    scale = np.max(np.abs(qg))
+    assert np.max(np.abs(qm - qg)) <= 1e-12 * scale
+
+
+def test_mesh_coupled_device_pointers_and_edges(ctx):
+    torch = _torch()
+    mf, mc = meshgen.criss_cross(n=16, seed=3), meshgen.criss_cross(n=8, seed=3)
+    f, c = ctx.add_mesh(mf), ctx.add_mesh(mc)
+    lst, kap, x0, nsf, dtf = _samples(5, 0.5, mf["h"])
+    _, _, _, nsc, dtc = _samples(5, 0.5, mc["h"])
+    qf, qc, dq = ctx.mesh_forward_coupled(f, c, kap, x0, nsf, dtf, nsc, dtc)
+    assert np.array_equal(qf, ctx.mesh_forward(f, kap, x0, nsf, dtf))
+    assert np.array_equal(qc, ctx.mesh_forward(c, kap, x0, nsc, dtc))
+    assert np.array_equal(dq, qf - qc)
+    d = torch.device("cuda:0")
+    T = lambda a: torch.tensor(a, device=d)
+    qfd, qcd, dqd = ctx.mesh_forward_coupled(f, c, T(kap), T(x0), T(nsf), T(dtf), T(nsc), T(dtc))
+    assert np.array_equal(qfd.cpu().numpy(), qf) and np.array_equal(dqd.cpu().numpy(), dq)
+    # g = log c in place of kappa, on the device
+    qg = ctx.mesh_forward(f, None, T(x0), T(nsf), T(dtf), g=T(0.5 * np.log(kap)))
+    assert np.max(np.abs(qg.cpu().numpy() - qf)) <= 1e-13 * np.max(np.abs(qf))
+    # empty batch, wrong precision, unknown mesh
+    e = ctx.mesh_forward(f, kap[:0], x0[:0], nsf[:0], dtf[:0])
+    assert len(e) == 0
+    with pytest.raises(P.LtsError):
+        ctx.mesh_info(99)
+    with pytest.raises(P.LtsError):                           # triangle meshes step in FP64 only
+        P._check(ctx.lib.lts_mesh_forward(ctx.h, f, None, P.LTS_FP32_STEP, None), ctx.h)
+
+
+def test_mlmc_on_a_triangle_mesh_hierarchy(ctx):
+    """Algorithm 1 over three unstructured meshes (jittered criss-cross grids
+    with 8, 16 and 32 cells across, refined 2x in a box): the same L, N_l,
+    estimate, moments and cost model as the oracle's Algorithm 1 on the
+    oracle's triangle-mesh operators."""
+    from oracle import mlmc
+    ms = [meshgen.criss_cross(n=8 << l, ref=2, box=(0.4, 0.6), jitter=0.1, seed=l) for l in range(3)]
+    ids = [ctx.add_mesh(m) for m in ms]
+    rule = P.sample_rule(T=0.5)
+    eps, N_init = 2e-3, (24, 12, 6)
+    res = ctx.mlmc(ids, rule, eps=eps, N_init=N_init, L_start=1, meshes=True)
+    ops = []
+    for m in ms:
+        tl = trimesh.tri_level(m["xy"], m["tris"], m["dirichlet"], m["tri_block"], m["tri_fine"], m["qoi_nodes"],
+                               m["n_blocks"], m["h"], m["p"], m["nu"])
+        ops.append(trimesh.operators(tl))
+    ores = mlmc.mlmc(ops, rng.SampleRule(T=0.5), eps=eps, N_init=N_init, L_start=1)
+    assert res["L"] == ores.L and res["N"] == ores.N
+    scale = max(abs(v) for v in ores.mean)
+    assert abs(res["estimate"] - ores.estimate) <= 1e-11 * scale
+    for l in range(res["L"] + 1):
+        assert abs(res["mean"][l] - ores.mean[l]) <= 1e-11 * scale
+        assert abs(res["var"][l] - ores.var[l]) <= 1e-9 * ores.var[l]
+        assert res["cost"][l] == ores.cost[l]
+    with pytest.raises(P.LtsError):
+        ctx.mlmc(ids, rule, eps=eps, N_init=N_init, L_start=1, meshes=True, grad_K=16)
