@@ -319,6 +319,39 @@ def adjoint_bench(samples: int, K: int):
     ctx.close()
 
 
+def adjoint_graded_bench(K: int = 64):
+    """Discrete adjoint on the graded L-shape levels (compact tilings, p = 64,
+    T = 2): lts_backward against lts_forward on the same samples, level 2 with
+    64 samples and level 3 with 16 (K = 64)."""
+    import numpy as np
+
+    import paper_2106_11117_amd as P
+
+    ctx = P.Context(0)
+    rule = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), width=0.05, T=2.0)
+    out = {"metric": "discrete adjoint time relative to the forward solve, graded L-shape (compact tiles, p = 64)",
+           "unit": "s", "higher_is_better": False, "data": "synthetic (Philox seed 0)", "K_ckpt": K, "runs": []}
+    for lev, nb, S in ((2, 128, 64), (3, 256, 16)):
+        lid = ctx.add_rect_level(P.graded_L_rule(nb))
+        ctx.autotune(lid)
+        info = ctx.level_info(lid)
+        s = P.gen_samples(0, lev, 0, S, rule, info["h"])
+        args = (s["kappa"], s["x0"], s["n_steps"], s["dt"])
+        ctx.forward(lid, *(a[:2] for a in args))
+        ctx.backward(lid, *(a[:1] for a in args), np.ones(1), K=K)      # warm-up
+        t0 = time.perf_counter()
+        qf = np.asarray(ctx.forward(lid, *args))
+        tf = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        q, g = ctx.backward(lid, *args, np.ones(S), K=K)
+        tb = time.perf_counter() - t0
+        out["runs"].append({"level": lev, "dofs": info["n_dof"], "P": info["n_P"], "samples": S,
+                            "tile_rect": info["tile_rect"], "forward_s": tf, "backward_s": tb,
+                            "backward_over_forward": tb / tf, "qoi_equal_to_forward": bool(np.array_equal(q, qf))})
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 BATCH_N = (4096, 1024, 256, 64, 16)       # samples per level of the multi-level throughput run
 
 
@@ -560,6 +593,8 @@ def main():
                     help="only run the one-dimensional workloads' MLMC, LF-LTS against leapfrog")
     ap.add_argument("--stream-check", action="store_true",
                     help="only time plain torch copy / axpy / sum kernels (practical HBM rates)")
+    ap.add_argument("--adjoint-graded", action="store_true",
+                    help="the discrete adjoint on graded L-shape levels 2 and 3 (compact tiles) against the forward")
     ap.add_argument("--adjoint", action="store_true",
                     help="only time the discrete adjoint against the forward solve (K = 64)")
     ap.add_argument("--mlmc", action="store_true",
@@ -574,6 +609,9 @@ def main():
     args = ap.parse_args()
     if args.batch:
         batch_bench(args.plain)
+        return
+    if args.adjoint_graded:
+        adjoint_graded_bench()
         return
     if args.adjoint:
         adjoint_bench(args.samples, 64)

@@ -266,6 +266,16 @@ lts_status launch_multi_step(lts_ctx c, const StepArgs* d_jobs, const std::vecto
 lts_status launch_persist(lts_ctx c, const StepArgs* d_jobs, const std::vector<const TilingDev*>& T,
                           const std::vector<int>& act_host, const int* d_act, int n_steps, const std::vector<int>& sb,
                           hipStream_t stream, bool fp32);
+// The adjoint's substep sweeps of one backward step on a compact tiling (FP64;
+// samples 0 .. active-1): reverse = false recomputes d_1 .. d_p of y = Y at
+// the nodes of P into D1 + (m-1)*astride; reverse = true runs the reverse
+// sweep from Lambda_p = f M mu (mu = MU; rho_m as in lts_adjoint.hip) and
+// writes Lambda_1 .. Lambda_p-1 into Lam1 + (m-1)*astride and lw into LW, at
+// the nodes of P (per sample at + s*sstride).
+lts_status launch_adj_compact(lts_ctx c, const DevLevel& lv, const TilingDev& T, const double* d_kappa,
+                              const double* d_coef, const double* Y, const double* MU, double* D1, double* Lam1,
+                              double* LW, const double* rho, size_t astride, size_t sstride, int active, double f,
+                              bool reverse, hipStream_t stream);
 // Largest S_b of a tiling: 0 in rect mode, else 1024 / (fewest threads holding its largest region).
 inline int persist_sb_max(const TilingDev& T) { return T.rect ? 0 : kFineThreads / T.nt; }
 // Writes the static step record of one job (step_args_size() bytes) to `out`.

@@ -18,6 +18,11 @@
 // Forward states are checkpointed every K steps (pairs (u_k, u_k+1)) and
 // recomputed one segment at a time with the forward step kernels; mu is
 // advanced by the forward step kernels too (the recurrence is the same).
+// Per backward step: on rect tilings the fused k_adj_fine (below) and
+// k_adj_cells; on compact tilings the two substep sweeps run per compact
+// tile (launch_adj_compact in lts_fused.hip) and k_adj_contract contracts;
+// the per-substep kernels over the list of P nodes remain for levels
+// without fine tiles.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -810,6 +815,23 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
         ta.per_xcd = (int)((Gw + 7) / 8);
         if (Gw > 0) k_adj_fine<<<dim3((unsigned)(8LL * ta.per_xcd)), dim3(kFineThreads), 0, c->stream>>>(ta);
         k_adj_cells<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, y, mu1, f, arr(iG));
+        if (nn >= 1) {
+          r = launch_step(c, lv, lv.tiling, d_kappa, d_coef, mu1, mu2, ss, 0, act, 0, c->stream);
+          if (r != LTS_OK) return r;
+        }
+        continue;
+      }
+      if (!T.rect && T.n_fine > 0) {
+        // compact tiles: Lambda_p everywhere, then one launch per sweep
+        // (d_1 .. d_p, then Lambda_1 .. Lambda_p-1 and lw, at the nodes of P)
+        k_adj_lam_init<<<grid(Lv.ld, act), blk, 0, c->stream>>>(a, f, mu1, arr(l0 + p - 1), arr(ilw));
+        r = launch_adj_compact(c, lv, T, d_kappa, d_coef, y, nullptr, arr(d0), nullptr, nullptr, nullptr, one, ss,
+                               act, f, false, c->stream);
+        if (r != LTS_OK) return r;
+        r = launch_adj_compact(c, lv, T, d_kappa, d_coef, y, mu1, nullptr, arr(l0), arr(ilw), a.rho, one, ss, act,
+                               f, true, c->stream);
+        if (r != LTS_OK) return r;
+        k_adj_contract<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, ca, y, arr(ilw), arr(iG));
         if (nn >= 1) {
           r = launch_step(c, lv, lv.tiling, d_kappa, d_coef, mu1, mu2, ss, 0, act, 0, c->stream);
           if (r != LTS_OK) return r;

@@ -80,6 +80,8 @@ struct StepState {
   double* Uold;         // u_n-1 in
   double* Unew;         // u_n+1 out (Uold for the in-place update)
   int startup;
+  double* Dout = nullptr;   // adjoint recompute: d_m+1 of sample s at Dout + m*dstride + s*sstride
+  size_t dstride = 0;
 };
 
 // Launch-time data of a batched launch over several jobs (levels).  Each
@@ -301,7 +303,9 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_multi(MultiArgs m) {
 // tid: thread index within the tile's NT threads.  on = false: the threads
 // touch no global memory and meet the same workgroup barriers (a persistent
 // workgroup runs several tiles of one level side by side).
-template <class T, int NT>
+// ADJ (the adjoint's recompute of a step, FP64): every increment d_m+1 of the
+// tile's own nodes of P goes to st.Dout and u_n+1 is not written.
+template <class T, int NT, bool ADJ = false>
 __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepState& st, const double* __restrict__ lk,
                                                   T* __restrict__ lq, int s, int tile, int tid, bool on) {
   constexpr int kCap = NT * kNPT;      // region nodes this workgroup size holds
@@ -403,6 +407,8 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepS
       const T dn = ((T)1 + b) * dc[r] - b * dq[r] - c * rr;
       dq[r] = dn;
       if (m + 1 < p) wq[tid + r * NT] = pm[r] * (u[r] + dn);
+      if (ADJ && dd[r] == 0 && pm[r] != (T)0)
+        st.Dout[(size_t)m * st.dstride + (size_t)s * a.sstride + (size_t)kk[r]] = (double)dn;
     }
     if (m + 1 < p) __syncthreads();
   };
@@ -412,12 +418,143 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepS
     substep(m + 1, std::integral_constant<int, 1>{});
   }
   if (m < p) substep(m, std::integral_constant<int, 0>{});
+  if (ADJ) return;
   const T* dfin = (p & 1) ? d1 : d0;   // d_p
 #pragma unroll
   for (int r = 0; r < kNPT; ++r) {
     if (dd[r] != 0) continue;          // written back by the tile that owns the node
     const size_t k = (size_t)kk[r];
     uw_g[k] = st.startup ? (u[r] + dfin[r]) : ((T)2 * u[r] - uo_g[k] + (T)2 * dfin[r]);
+  }
+}
+
+// Reverse sweep of the adjoint on one compact tile (FP64).  For y = u_n and
+// mu = mu_n+1 with Lambda_p = f M mu, Lambda_p+1 = 0:
+//   Lambda_m = (1 + beta_m) Lambda_m+1 - c2_m P K (Lambda_m+1 / m) - beta_m+1 Lambda_m+2
+// at the nodes of P (m = p-1 .. 1), and lw = -c1 Lambda_1 - sum_{m=1}^{p-1} c2_m Lambda_m+1.
+// Off P no stencil acts, so Lambda_m / m = rho_m f mu there: a neighbour that is
+// not in P is read as rho_m+1 f mu from global memory (loaded once), a
+// neighbour in P from LDS (two buffers of Lambda / m).  Lambda_m at a node at
+// distance D is exact when D <= m (it reads Lambda_m+1 within D + 1 <= p), so
+// step m updates the distance prefix D <= m, and the tile's own nodes of P
+// store Lambda_1 .. Lambda_p-1 and lw.
+struct AdjRevArgs {
+  const double* __restrict__ MU;     // mu_n+1 of sample s at MU + s*sstride
+  double* __restrict__ Lam1;         // Lambda_m of sample s at Lam1 + (m-1)*astride + s*sstride
+  double* __restrict__ LW;
+  const double* __restrict__ rho;    // rho_m, m = 1..p
+  size_t astride;
+  double f;
+};
+
+template <int NT>
+__device__ __forceinline__ void adj_rev_compact(const StepArgs& a, const AdjRevArgs& x, const double* __restrict__ lk,
+                                                double* __restrict__ lq, int s, int tile) {
+  constexpr int kCap = NT * kNPT;
+  const int tid = threadIdx.x;
+  const LevelView& L = a.L;
+  const int4 tl = a.tiles[tile];
+  const int len = tl.y;
+  const int ix0 = tl.z & 0xFFFF, ix1 = tl.z >> 16, iy0 = tl.w & 0xFFFF, iy1 = tl.w >> 16;
+  const int p = L.p;
+  const size_t so = (size_t)s * a.sstride;
+  const double* __restrict__ mu = x.MU + so;
+  const double* __restrict__ cf = a.coef + (size_t)s * (p + 1);
+  double* const t0 = lq;                // Lambda / m of the even steps' inputs (m + 1 = p, p - 2, ...)
+  double* const t1 = lq + (kCap + 1);   // and of the odd ones'; slot len of each holds 0
+  double l1[kNPT], l2[kNPT], im[kNPT], lw[kNPT], cE[kNPT], cW[kNPT], cN[kNPT], cS[kNPT];
+  uint32_t pmask = 0;                  // bit r: region node r of this lane is in P
+  double co[kNPT];                     // sum over the neighbours off P of c_k f mu_k (rho-free)
+  uint32_t ad[kNPT][4];
+  int kk[kNPT], dd[kNPT];
+  int4 en[kNPT];
+#pragma unroll
+  for (int r = 0; r < kNPT; ++r) en[r] = a.ent[tl.x + min(tid + r * NT, len - 1)];
+  const int ld = L.ld;
+#pragma unroll
+  for (int r = 0; r < kNPT; ++r) {
+    l1[r] = l2[r] = im[r] = lw[r] = 0.0;
+    cE[r] = cW[r] = cN[r] = cS[r] = co[r] = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) ad[r][t] = (uint32_t)(len * sizeof(double));
+    kk[r] = 0;
+    dd[r] = p + 1;                     // never updated, never written
+    const int e = tid + r * NT;
+    if (e < len) {
+      const size_t k = (size_t)(en[r].x & 0x7FFFFFFF);
+      const bool pi = en[r].x < 0;
+      const int i = en[r].w & 0xFFFF, j = en[r].w >> 16;
+      kk[r] = (int)k;
+      ad[r][0] = (uint32_t)(en[r].y & 0xFFFF) * sizeof(double);
+      ad[r][1] = ((uint32_t)en[r].y >> 16) * sizeof(double);
+      ad[r][2] = (uint32_t)(en[r].z & 0xFFFF) * sizeof(double);
+      ad[r][3] = ((uint32_t)en[r].z >> 16) * sizeof(double);
+      dd[r] = max(max(ix0 - i, i - (ix1 - 1)), 0) + max(max(iy0 - j, j - (iy1 - 1)), 0);
+      const uint8_t fE = L.flags[k + 1], fW = L.flags[k - 1], fN = L.flags[k + ld], fS = L.flags[k - ld];
+      const double mk = mu[k], mE = mu[k + 1], mW = mu[k - 1], mN = mu[k + ld], mS = mu[k - ld];
+      double ce, cw, cn, cs;
+      edge_coefs(L, lk, i, j, ce, cw, cn, cs);
+      cE[r] = ce;
+      cW[r] = cw;
+      cN[r] = cn;
+      cS[r] = cs;
+      co[r] = ce * ((fE & F_P) ? 0.0 : x.f * mE) + cw * ((fW & F_P) ? 0.0 : x.f * mW) +
+              cn * ((fN & F_P) ? 0.0 : x.f * mN) + cs * ((fS & F_P) ? 0.0 : x.f * mS);
+      im[r] = L.invm[k];
+      if (pi) pmask |= 1u << r;
+      l1[r] = pi && im[r] != 0.0 ? x.f * mk / im[r] : 0.0;   // Lambda_p
+      t0[e] = pi ? x.f * mk : 0.0;                            // Lambda_p / m
+    }
+  }
+  if (tid == 0) t0[len] = t1[len] = 0.0;
+  __syncthreads();
+  // Step m (m = p-1 .. 1): Lambda_m from Lambda_m+1 (l1 in, out) and
+  // Lambda_m+2 (l2), reading Lambda_m+1 / m of the neighbours in P from
+  // buffer B and writing Lambda_m / m to the other.  The roles of l1 / l2 and
+  // of the buffers alternate, fixed per call.
+  auto step = [&](int m, auto Bc) {
+    constexpr int B = decltype(Bc)::value;
+    double* lc = B == 0 ? l1 : l2;     // Lambda_m+1
+    double* lo = B == 0 ? l2 : l1;     // Lambda_m+2 in, Lambda_m out
+    const char* rq = reinterpret_cast<const char*>(B == 0 ? t0 : t1);
+    double* wq = B == 0 ? t1 : t0;
+    const double c2 = cf[1 + m];
+    const double bm = L.beta[m];
+    const double bm1 = m + 1 < p ? L.beta[m + 1] : 0.0;
+    const double r1 = x.rho[m + 1];
+#pragma unroll
+    for (int r = 0; r < kNPT; ++r) {
+      if (dd[r] > m || !(pmask & (1u << r))) continue;
+      const double lam = lc[r];
+      lw[r] -= c2 * lam;
+      const double ti = lam * im[r];
+      // neighbours in P from LDS (0 for the others), those off P through co
+      const double tE = *reinterpret_cast<const double*>(rq + ad[r][0]);
+      const double tW = *reinterpret_cast<const double*>(rq + ad[r][1]);
+      const double tN = *reinterpret_cast<const double*>(rq + ad[r][2]);
+      const double tS = *reinterpret_cast<const double*>(rq + ad[r][3]);
+      const double kt = cE[r] * (ti - tE) + cW[r] * (ti - tW) + cN[r] * (ti - tN) + cS[r] * (ti - tS) - r1 * co[r];
+      const double ln = (1.0 + bm) * lam - c2 * kt - bm1 * lo[r];
+      lo[r] = ln;
+      if (m > 1) wq[tid + r * NT] = ln * im[r];
+      if (dd[r] == 0) x.Lam1[(size_t)(m - 1) * x.astride + so + (size_t)kk[r]] = ln;
+    }
+    if (m > 1) __syncthreads();
+  };
+  int m = p - 1;
+  for (; m >= 2; m -= 2) {
+    step(m, std::integral_constant<int, 0>{});
+    step(m - 1, std::integral_constant<int, 1>{});
+  }
+  if (m == 1) step(1, std::integral_constant<int, 0>{});
+  // Lambda_1 is in l2 when p - 1 is odd (p even), else in l1
+  const bool in_l2 = ((p - 1) & 1) != 0;
+  const double c1 = cf[1];
+#pragma unroll
+  for (int r = 0; r < kNPT; ++r) {
+    if (dd[r] != 0 || !(pmask & (1u << r))) continue;
+    const double lam1 = p == 1 ? l1[r] : (in_l2 ? l2[r] : l1[r]);
+    x.LW[so + (size_t)kk[r]] = lw[r] - c1 * lam1;
   }
 }
 
@@ -738,6 +875,34 @@ __device__ __forceinline__ int opaque_tid() {
   int v;
   asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "v"((int)threadIdx.x));
   return v;
+}
+
+// The adjoint's two substep sweeps of one backward step on compact tiles:
+// the forward recompute (the increments d_1 .. d_p at the nodes of P) and the
+// reverse sweep (Lambda_1 .. Lambda_p-1 and lw at the nodes of P).  One
+// workgroup per (sample, tile); each tile writes its own nodes of P.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_adj_fsweep(StepArgs a, StepState st) {
+  __shared__ double lq[2 * (NT * kNPT + 1)];
+  __shared__ double lk[256];
+  const int G = a.n_fine * a.active;
+  const int Lid = (int)(blockIdx.x & 7) * a.per_xcd + (int)(blockIdx.x >> 3);
+  if (Lid >= G) return;
+  const int s = Lid / a.n_fine;
+  load_kappa(a, s, lk);
+  fine_tile_compact<double, NT, true>(a, st, lk, lq, s, Lid % a.n_fine, (int)threadIdx.x, true);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_adj_rsweep(StepArgs a, AdjRevArgs x) {
+  __shared__ double lq[2 * (NT * kNPT + 1)];
+  __shared__ double lk[256];
+  const int G = a.n_fine * a.active;
+  const int Lid = (int)(blockIdx.x & 7) * a.per_xcd + (int)(blockIdx.x >> 3);
+  if (Lid >= G) return;
+  const int s = Lid / a.n_fine;
+  load_kappa(a, s, lk);
+  adj_rev_compact<NT>(a, x, lk, lq, s, Lid % a.n_fine);
 }
 
 // ---------------------------------------------------------------------------
@@ -1511,6 +1676,58 @@ lts_status launch_persist(lts_ctx c, const StepArgs* d_jobs, const std::vector<c
   if (abort_w != 0u) {
     c->err = "persistent launch: a workgroup waited longer than the barrier limit; results are invalid";
     return LTS_ERR_STATE;
+  }
+  return LTS_OK;
+}
+
+lts_status launch_adj_compact(lts_ctx c, const DevLevel& lv, const TilingDev& T, const double* d_kappa,
+                              const double* d_coef, const double* Y, const double* MU, double* D1, double* Lam1,
+                              double* LW, const double* rho, size_t astride, size_t sstride, int active, double f,
+                              bool reverse, hipStream_t stream) {
+  if (active <= 0 || T.n_fine == 0) return LTS_OK;
+  if (T.rect) {
+    c->err = "compact adjoint sweep on a rect tiling";
+    return LTS_ERR_STATE;
+  }
+  StepArgs a{};
+  a.L = lv.view();
+  a.ent = T.ent.as<int4>();
+  a.tiles = T.tiles.as<int4>();
+  a.citems = T.citems.as<int4>();
+  a.rtiles = T.rtiles.as<int4>();
+  a.n_fine = T.n_fine;
+  a.n_coarse = T.n_coarse;
+  a.wg_per_sample = T.wg_per_sample;
+  a.active = active;
+  a.kappa = d_kappa;
+  a.coef = d_coef;
+  a.Ucur = Y;
+  a.Uold = D1;
+  a.Unew = D1;
+  a.sstride = sstride;
+  a.startup = 0;
+  a.s0 = 0;
+  const long long G = (long long)T.n_fine * active;
+  a.per_xcd = (int)((G + 7) / 8);
+  const dim3 grid((unsigned)(8LL * a.per_xcd));
+  if (!reverse) {
+    StepState st{Y, D1, D1, 0};
+    st.Dout = D1;
+    st.dstride = astride;
+    if (T.nt == 256) k_adj_fsweep<256><<<grid, dim3(256), 0, stream>>>(a, st);
+    else if (T.nt == 512) k_adj_fsweep<512><<<grid, dim3(512), 0, stream>>>(a, st);
+    else k_adj_fsweep<1024><<<grid, dim3(1024), 0, stream>>>(a, st);
+  } else {
+    AdjRevArgs x;
+    x.MU = MU;
+    x.Lam1 = Lam1;
+    x.LW = LW;
+    x.rho = rho;
+    x.astride = astride;
+    x.f = f;
+    if (T.nt == 256) k_adj_rsweep<256><<<grid, dim3(256), 0, stream>>>(a, x);
+    else if (T.nt == 512) k_adj_rsweep<512><<<grid, dim3(512), 0, stream>>>(a, x);
+    else k_adj_rsweep<1024><<<grid, dim3(1024), 0, stream>>>(a, x);
   }
   return LTS_OK;
 }
