@@ -92,15 +92,16 @@ __device__ __forceinline__ void load_kappa_groups(const TriStep& a, int nb, int 
   }
 }
 
-// Coarse DOFs: blockIdx.x = 256 DOFs of the coarse list, blockIdx.y = kTriS
-// consecutive active samples.
+// Coarse DOFs: blockIdx.x = kTriS consecutive active samples (fastest, so
+// that the blocks of one group of DOFs run together and share its coupling
+// data in L2), blockIdx.y = 256 DOFs of the coarse list.
 __global__ __launch_bounds__(256) void k_tri_coarse(TriView v, TriStep a) {
   __shared__ double lk[kTriS][256];
-  const int s0 = blockIdx.y * kTriS;
+  const int s0 = blockIdx.x * kTriS;
   const int ns = min(kTriS, a.active - s0);
   load_kappa_groups<kTriS>(a, v.nb, s0, ns, lk);
   __syncthreads();
-  const int c = blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y * 256 + threadIdx.x;
   if (c >= v.n_coarse) return;
   const int i = v.coarse[c];
   const int e0 = v.rp[i], e1 = v.rp[i + 1];
@@ -136,12 +137,18 @@ __global__ __launch_bounds__(256) void k_tri_coarse(TriView v, TriStep a) {
 // and, per coupling, the scaled coefficient and the LDS byte offset of the
 // neighbour's q (the zero slot for a neighbour that is not in P or not in the
 // region).
+// DEG: the level's largest F+ degree rounded up to 6, 8, 10 or 12 (the
+// coupling arrays and loops are that long).
+template <int DEG>
 __global__ __launch_bounds__(kTriNT) void k_tri_fine(TriView v, TriStep a) {
   __shared__ double lk[256];
   __shared__ double qb[2 * (kTriRegionCap + 1)];
   const int G = v.n_tiles * a.active;
   const int Lid = (int)(blockIdx.x & 7) * a.per_xcd + (int)(blockIdx.x >> 3);
   if (Lid >= G) return;
+  // sample-major: the tiles of one sample run back to back on one XCD, whose
+  // L2 then holds the halo values a tile shares with its neighbours (measured
+  // faster than tile-major, which would share the coupling data instead)
   const int s = Lid / v.n_tiles, tile = Lid - s * v.n_tiles;
   for (int t = threadIdx.x; t < 256; t += kTriNT) lk[t] = t < v.nb ? a.kappa[(size_t)s * v.nb + t] : 0.0;
   __syncthreads();
@@ -155,8 +162,8 @@ __global__ __launch_bounds__(kTriNT) void k_tri_fine(TriView v, TriStep a) {
   const int tid = threadIdx.x;
 
   double u[kTriNPT], pm[kTriNPT], d0[kTriNPT], d1[kTriNPT], w[kTriNPT];
-  double ac[kTriNPT][kTriMaxDeg];
-  uint32_t ad[kTriNPT][kTriMaxDeg];
+  double ac[kTriNPT][DEG];
+  uint32_t ad[kTriNPT][DEG];
   int kk[kTriNPT], dd[kTriNPT];
 #pragma unroll
   for (int r = 0; r < kTriNPT; ++r) {
@@ -165,7 +172,7 @@ __global__ __launch_bounds__(kTriNT) void k_tri_fine(TriView v, TriStep a) {
     kk[r] = 0;
     dd[r] = p;                                          // never updated, never written
 #pragma unroll
-    for (int k = 0; k < kTriMaxDeg; ++k) {
+    for (int k = 0; k < DEG; ++k) {
       ac[r][k] = 0.0;
       ad[r][k] = (uint32_t)len * 8u;
     }
@@ -184,7 +191,7 @@ __global__ __launch_bounds__(kTriNT) void k_tri_fine(TriView v, TriStep a) {
     const double vi = isP ? 0.0 : uc;
     double wr = 0.0;
 #pragma unroll
-    for (int k = 0; k < kTriMaxDeg; ++k) {
+    for (int k = 0; k < DEG; ++k) {
       if (k >= deg) continue;
       const int o = en.y + k;
       const int j = v.col[o];
@@ -221,7 +228,7 @@ __global__ __launch_bounds__(kTriNT) void k_tri_fine(TriView v, TriStep a) {
       const double qi = pm[r] * (u[r] + dc[r]);
       double apq = 0.0;
 #pragma unroll
-      for (int k = 0; k < kTriMaxDeg; ++k)
+      for (int k = 0; k < DEG; ++k)
         apq += ac[r][k] * (qi - *reinterpret_cast<const double*>(rq + ad[r][k]));
       const double dn = (1.0 + b) * dc[r] - b * dq[r] - c * (w[r] + apq);
       dq[r] = dn;
@@ -360,12 +367,17 @@ lts_status tri_solve(lts_ctx c, TriDev& M, const Staged& st, const StagedDev& d,
     a.startup = t == 0;
     a.per_xcd = 0;
     if (v.n_coarse > 0)
-      k_tri_coarse<<<dim3((unsigned)((v.n_coarse + 255) / 256), (unsigned)((act + kTriS - 1) / kTriS)), 256, 0, q>>>(v,
+      k_tri_coarse<<<dim3((unsigned)((act + kTriS - 1) / kTriS), (unsigned)((v.n_coarse + 255) / 256)), 256, 0, q>>>(v,
                                                                                                                   a);
     if (v.n_tiles > 0) {
       const long long G = (long long)v.n_tiles * act;
       a.per_xcd = (int)((G + 7) / 8);
-      k_tri_fine<<<(unsigned)(8LL * a.per_xcd), kTriNT, 0, q>>>(v, a);
+      const int md = M.H.max_deg;
+      const dim3 g((unsigned)(8LL * a.per_xcd));
+      if (md <= 6) k_tri_fine<6><<<g, kTriNT, 0, q>>>(v, a);
+      else if (md <= 8) k_tri_fine<8><<<g, kTriNT, 0, q>>>(v, a);
+      else if (md <= 10) k_tri_fine<10><<<g, kTriNT, 0, q>>>(v, a);
+      else k_tri_fine<12><<<g, kTriNT, 0, q>>>(v, a);
     }
   }
   LTS_HIP(c, hipGetLastError());
