@@ -29,13 +29,15 @@ def _qoi_nodes(xy, box=(0.6, 0.8, 0.6, 0.8)):
     return np.where(inside, 1.0 / max(int(inside.sum()), 1), 0.0)
 
 
-def criss_cross(n: int = 16, box=(0.375, 0.625), ref: int = 4, jitter: float = 0.15, seed: int = 0) -> dict:
+def criss_cross(n: int = 16, box=(0.375, 0.625), ref: int = 4, jitter: float = 0.15, seed: int = 0,
+                qoi_box=(0.6, 0.8, 0.6, 0.8)) -> dict:
     """Unit square, n cells per axis; per axis the cells meeting the open box are
     split into `ref` parts.  Interior nodes move by up to `jitter` of the
     smaller adjacent spacing in each coordinate; cell (a, b) is split along
     the diagonal through its lower-left corner when a + b is even, else the
     other one.  Fine elements: those of cells narrower than 1/(2n) in some
-    direction.  p = ref.  Dirichlet: the boundary nodes."""
+    direction.  p = ref.  Dirichlet: the boundary nodes.  QoI: the mean of the
+    nodal values in qoi_box."""
     rng = np.random.default_rng(seed)
     edges = []
     for k in range(n):
@@ -71,7 +73,7 @@ def criss_cross(n: int = 16, box=(0.375, 0.625), ref: int = 4, jitter: float = 0
     bnd = np.zeros((m, m), dtype=bool)
     bnd[0, :] = bnd[-1, :] = bnd[:, 0] = bnd[:, -1] = True
     return {"xy": xy, "tris": tris, "dirichlet": bnd.ravel(), "tri_block": _blocks(xy, tris),
-            "tri_fine": np.asarray(fine, dtype=bool), "qoi_nodes": _qoi_nodes(xy), "n_blocks": 16,
+            "tri_fine": np.asarray(fine, dtype=bool), "qoi_nodes": _qoi_nodes(xy, qoi_box), "n_blocks": 16,
             "h": h, "p": ref, "nu": 0.01}
 
 

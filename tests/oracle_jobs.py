@@ -1,5 +1,5 @@
 """Oracle solves run in worker processes by the GPU parity tests (test
-infrastructure: calls only the oracle).  Each job is a plain tuple so that it
+infrastructure: calls only the oracle and the seeded input generators).  Each job is a plain tuple so that it
 can be sent to a spawned process; results are plain dicts."""
 from __future__ import annotations
 
@@ -58,8 +58,26 @@ def grad(job):
     return {"Q": float(Q), "g": np.asarray(g).tolist(), "n_steps": n}
 
 
+def solve_tri(job):
+    """('tri', criss_cross kwargs, sample index, T) -> Q, sum w|u|, n_steps of that
+    sample (rule: 16 blocks, sigma 0.25, seed 0, MLMC level 0) on the triangle
+    mesh tests/meshgen.py builds from the kwargs."""
+    import meshgen
+    from oracle import trimesh
+    _, kw, i, T = job
+    m = meshgen.criss_cross(**kw)
+    tl = trimesh.tri_level(m["xy"], m["tris"], m["dirichlet"], m["tri_block"], m["tri_fine"], m["qoi_nodes"],
+                           m["n_blocks"], m["h"], m["p"], m["nu"])
+    ops = trimesh.operators(tl)
+    rule = rng.SampleRule(T=T)
+    smp = rng.draw(0, 0, i, rule)
+    n, dt = rng.steps_for(smp, rule, tl.h)
+    u = lts.Solver(ops, smp.kappa).run(lts.pulse(ops, smp.x0), dt, n)
+    return {"Q": float(lts.qoi(ops, u)), "abs_wu": float(ops.qoi_w @ np.abs(u)), "n_steps": n}
+
+
 def _run(job):
-    return {"fwd": solve, "fwdq": solve_tiers, "adj": grad}[job[0]](job)
+    return {"fwd": solve, "fwdq": solve_tiers, "adj": grad, "tri": solve_tri}[job[0]](job)
 
 
 def run_all(jobs):

@@ -170,3 +170,25 @@ def test_mlmc_on_a_triangle_mesh_hierarchy(ctx):
         assert res["cost"][l] == ores.cost[l]
     with pytest.raises(P.LtsError):
         ctx.mlmc(ids, rule, eps=eps, N_init=N_init, L_start=1, meshes=True, grad_K=16)
+
+
+def test_mesh_full_size_sampled_vs_oracle(ctx):
+    """The C1-sized unstructured mesh of bench.py --mesh (442,225 DOFs, p = 8,
+    hundreds of fine tiles with regions up to 2,047 DOFs) in its bench launch
+    configuration (64 samples in one call), to a short horizon with the QoI
+    over the pulse's path and the refined band ([0.3, 0.55]^2, so that Q is
+    O(0.1), not a numerical tail): the first and last samples against the
+    oracle, solved one by one in worker processes."""
+    import oracle_jobs
+    kw = dict(n=512, ref=8, box=(0.48, 0.52), jitter=0.1, qoi_box=(0.3, 0.55, 0.3, 0.55))
+    m = meshgen.criss_cross(**kw)
+    mid = ctx.add_mesh(m)
+    info = ctx.mesh_info(mid)
+    assert info["n_dof"] == 442225 and info["n_P"] == 204081 and info["n_tiles"] > 100
+    T = 0.05
+    lst, kap, x0, ns, dt = _samples(64, T, m["h"])
+    q = ctx.mesh_forward(mid, kap, x0, ns, dt)
+    ref = oracle_jobs.run_all([("tri", kw, i, T) for i in (0, 63)])
+    for i, r in zip((0, 63), ref):
+        assert int(ns[i]) == r["n_steps"]
+        assert abs(q[i] - r["Q"]) <= 1e-11 * r["abs_wu"], (i, q[i], r["Q"])
