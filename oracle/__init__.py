@@ -26,6 +26,9 @@ and local time-stepping for wave propagation"):
 * ``mlmc``     -- QoI, coupled differences, two-pass moments, optimal N_l,
                   bias estimate, Algorithm 1 (Sec. 2.2).
 * ``adjoint``  -- discrete adjoint of the LF-LTS recurrence (dQ/d log c).
+* ``mlts``     -- multi-level LTS (Sec. 3.5, closing remark): Algorithm 2
+                  nested once per tier of element sizes, each tier with its
+                  own ratio p_j (a reading; the paper names the method only).
 * ``oned``     -- the one-dimensional workloads of Sec. 4.1 / 4.2 (Neumann
                   data, random wave speed by a Karhunen-Loeve sum or a random
                   jump) with the V = L^2(D)-valued QoI and its Algorithm 1.
