@@ -406,6 +406,72 @@ lts_status lts_mesh_forward_coupled(lts_ctx ctx, int32_t mesh_fine, int32_t mesh
                                     double* Qf_out, double* Qc_out, double* dQ_out);
 
 /* ------------------------------------------------------------------------ */
+/* Multi-level local time stepping (Sec. 3.5, closing remark)                */
+/* ------------------------------------------------------------------------ */
+
+/* Tiers of ever smaller elements inside D_fine, each advancing with its own
+ * step: Algorithm 2 nested once per tier (the paper names the multi-level
+ * method without stating it; this nesting is the library's reading).  Tier j
+ * (1..n_tiers) has the fine set S_j = the cells of tier >= j (S_1 = D_fine),
+ * P_j = the DOFs that are vertices of a cell of S_j, and the ratio p_j.  Tier j
+ * covers a time sigma_j (sigma_1 = dt) with the p_j stages of Algorithm 2's
+ * stabilized recurrence for (p_j, nu), in increment form with the force
+ * Phi_m = F + A P_j e_m; each stage's leapfrog half step from rest, of time
+ * sigma_j+1 = sigma_j (2 / (omega_j delta_j))^1/2 (= sigma_j / p_j when nu = 0),
+ * is taken by tier j+1 with the force Phi_m as its F; the innermost tier takes
+ * it directly.  The step is u_n+1 = 2 u_n - u_n-1 + 2 e (e: tier 1's increment
+ * for F = A u_n), the start-up u_1 = u_0 + e.  One tier with p_1 = p is
+ * Algorithm 2.
+ * cell_tier: [ny_cells*nx_cells], 0 for a coarse or inactive cell, else the
+ * deepest tier (1..n_tiers) whose set holds the cell; it must be >= 1 exactly on
+ * the active fine cells.  NULL selects the halving rule: an active fine cell
+ * has tier 1 + #{j in 2..n_tiers : shorter leg < h 2^-j} (on the graded
+ * L-shape with p_j = 2, every tier then steps at the coarse cells' ratio of
+ * step to leg). */
+#define LTS_MLTS_MAX_TIERS 5
+#define LTS_MLTS_MAX_P 16
+typedef struct {
+  int32_t n_tiers;                        /* 1..LTS_MLTS_MAX_TIERS */
+  int32_t p[LTS_MLTS_MAX_TIERS];          /* p_1 .. p_n_tiers, each 1..LTS_MLTS_MAX_P */
+  const uint8_t* cell_tier;               /* caller-owned, copied; or NULL */
+} lts_mlts_desc;
+
+typedef struct {
+  int32_t n_tiers;
+  int32_t p[LTS_MLTS_MAX_TIERS];
+  int32_t n_P[LTS_MLTS_MAX_TIERS];        /* |P_j| */
+  int32_t phases;                         /* exchange phases per step: sum_j (p_1 .. p_j-1)(p_j - 1),
+                                             also the radius of the fine tiles' regions */
+  int32_t n_tiles, max_region, threads;   /* the tiling of the MLTS step (regions of F+ nodes within
+                                             Manhattan distance `phases`, two per lane) */
+  double halo_ratio;                      /* region nodes of all tiles / |F+| */
+  double updates_per_step;                /* DOF updates of one step of one sample:
+                                             (N - |P_1|) + sum_j (p_1 .. p_j)(|P_j| - |P_j+1|) */
+} lts_mlts_info;
+
+/* Attach tiers to rectilinear level `level` (replacing earlier ones) and build
+ * the tiling of the MLTS step.  Errors: LTS_ERR_ARG (n_tiers or p out of
+ * range, a cell_tier value beyond n_tiers or inconsistent with the fine cells,
+ * a region beyond 2048 nodes), LTS_ERR_OOM. */
+lts_status lts_set_mlts(lts_ctx ctx, int32_t level, const lts_mlts_desc* desc);
+
+/* Sizes of the tiers attached to `level`.  Errors: LTS_ERR_ARG (no such level),
+ * LTS_ERR_STATE (no tiers attached). */
+lts_status lts_mlts_info_get(lts_ctx ctx, int32_t level, lts_mlts_info* out);
+
+/* Host only: the tiers lts_set_mlts would attach to the level of `rule`; info
+ * (required) and node_tier [ny_nodes*nx_nodes] (may be NULL): the largest j
+ * with the node in P_j, 0 off P_1.  Errors: as lts_set_mlts. */
+lts_status lts_mlts_host(const lts_rect_rule* rule, const lts_mlts_desc* desc, lts_mlts_info* info,
+                         uint8_t* node_tier);
+
+/* Solve every sample on `level` with its tiers (contract of lts_forward: pulse
+ * initial state, n_steps steps of dt, Q = sum qoi_w u(T)).  FP64 only.
+ * Errors as lts_forward; LTS_ERR_STATE if no tiers are attached. */
+lts_status lts_mlts_forward(lts_ctx ctx, int32_t level, const lts_samples* samples, int32_t precision,
+                            double* Q_out);
+
+/* ------------------------------------------------------------------------ */
 /* Batched form: many (level, samples) jobs advanced together                */
 /* ------------------------------------------------------------------------ */
 

@@ -191,6 +191,42 @@ def mesh_host(m) -> dict:
     return d
 
 
+def _mlts_desc(ps, cell_tier):
+    """lts_mlts_desc for ratios ps (tier 1 first) and cell tiers [ny_cells, nx_cells]
+    (uint8) or None (the halving rule); returns (desc, keep-alive array)."""
+    ps = [int(v) for v in ps]
+    d = _lib.MltsDesc()
+    d.n_tiers = len(ps)
+    for j, v in enumerate(ps[:_lib.LTS_MLTS_MAX_TIERS]):
+        d.p[j] = v
+    ct = None
+    if cell_tier is not None:
+        ct = np.ascontiguousarray(cell_tier, dtype=np.uint8)
+        d.cell_tier = ct.ctypes.data
+    return d, ct
+
+
+def _mlts_dict(info) -> dict:
+    n = info.n_tiers
+    return {"n_tiers": n, "p": list(info.p)[:n], "n_P": list(info.n_P)[:n], "phases": info.phases,
+            "n_tiles": info.n_tiles, "max_region": info.max_region, "threads": info.threads,
+            "halo_ratio": info.halo_ratio, "updates_per_step": info.updates_per_step}
+
+
+def mlts_host(rule, ps, cell_tier=None) -> dict:
+    """Host only: the tiers lts_set_mlts would attach to the level of `rule`,
+    with node_tier [ny_nodes, nx_nodes] (largest j with the node in P_j)."""
+    lib = _lib.load()
+    lv = rect_level_host(rule)
+    d, keep = _mlts_desc(ps, cell_tier)
+    info = _lib.MltsInfo()
+    nt = np.zeros((lv["ny_nodes"], lv["nx_nodes"]), dtype=np.uint8)
+    _check(lib.lts_mlts_host(C.byref(rule), C.byref(d), C.byref(info), nt.ctypes.data_as(C.POINTER(C.c_uint8))))
+    out = _mlts_dict(info)
+    out["node_tier"] = nt
+    return out
+
+
 def line_level_host(rule) -> dict:
     lib = _lib.load()
     info = _lib.LineInfo()
@@ -493,6 +529,27 @@ class Context:
         self._c(self.lib.lts_mesh_forward_coupled(self.h, mesh_fine, mesh_coarse, C.byref(fa.s), C.byref(ca.s),
                                                   LTS_FP64, qfp, qcp, dqp))
         return qf, qc, dq
+
+    # --- multi-level LTS ------------------------------------------------------
+    def set_mlts(self, level, ps, cell_tier=None) -> dict:
+        """Attach tiers with ratios ps (tier 1 first) to a rectilinear level;
+        cell_tier [ny_cells, nx_cells] or None for the halving rule.  Returns
+        lts_mlts_info as a dict."""
+        d, keep = _mlts_desc(ps, cell_tier)
+        self._c(self.lib.lts_set_mlts(self.h, level, C.byref(d)))
+        return self.mlts_info(level)
+
+    def mlts_info(self, level) -> dict:
+        info = _lib.MltsInfo()
+        self._c(self.lib.lts_mlts_info_get(self.h, level, C.byref(info)))
+        return _mlts_dict(info)
+
+    def mlts_forward(self, level, kappa, x0, n_steps, dt, width=0.05, g=None):
+        """Q of every sample with the level's tiers (FP64)."""
+        sa = _SampleArgs(kappa, x0, n_steps, dt, width, g)
+        q, qp = sa.out()
+        self._c(self.lib.lts_mlts_forward(self.h, level, C.byref(sa.s), LTS_FP64, qp))
+        return q
 
     # --- one-dimensional workloads -------------------------------------------
     def add_line_level(self, rule) -> int:

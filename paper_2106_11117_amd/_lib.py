@@ -24,6 +24,8 @@ LTS_BATCH_SB2 = 16
 LTS_BATCH_SB_MASK = 24
 LTS_BATCH_AUTO = 32
 LTS_MESH_REGION_CAP = 2048
+LTS_MLTS_MAX_TIERS = 5
+LTS_MLTS_MAX_P = 16
 LTS_MESH_MAX_DEGREE = 12
 LTS_MLMC_BATCHED, LTS_MLMC_PLAIN = 0, 1
 LTS_FINE_HALF_H, LTS_FINE_TIERS, LTS_FINE_QOPT = 0, 1, 2
@@ -89,6 +91,17 @@ class MeshInfo(C.Structure):
                 ("n_tiles", C.c_int32), ("max_region", C.c_int32), ("p", C.c_int32), ("n_blocks", C.c_int32),
                 ("h", C.c_double), ("nu", C.c_double), ("delta", C.c_double), ("omega", C.c_double),
                 ("halo_ratio", C.c_double)]
+
+
+class MltsDesc(C.Structure):
+    _fields_ = [("n_tiers", C.c_int32), ("p", C.c_int32 * LTS_MLTS_MAX_TIERS), ("cell_tier", C.c_void_p)]
+
+
+class MltsInfo(C.Structure):
+    _fields_ = [("n_tiers", C.c_int32), ("p", C.c_int32 * LTS_MLTS_MAX_TIERS),
+                ("n_P", C.c_int32 * LTS_MLTS_MAX_TIERS), ("phases", C.c_int32), ("n_tiles", C.c_int32),
+                ("max_region", C.c_int32), ("threads", C.c_int32), ("halo_ratio", C.c_double),
+                ("updates_per_step", C.c_double)]
 
 
 class Samples(C.Structure):
@@ -200,6 +213,10 @@ SIGNATURES = [
     ("lts_mesh_forward", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Samples), C.c_int32, C.c_void_p]),
     ("lts_mesh_forward_coupled", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Samples),
                                              C.POINTER(Samples), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("lts_set_mlts", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(MltsDesc)]),
+    ("lts_mlts_info_get", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(MltsInfo)]),
+    ("lts_mlts_host", C.c_int32, [C.c_void_p, C.POINTER(MltsDesc), C.POINTER(MltsInfo), u8p]),
+    ("lts_mlts_forward", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(Samples), C.c_int32, C.c_void_p]),
 ]
 
 _lib = None

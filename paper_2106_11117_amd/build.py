@@ -19,7 +19,7 @@ OUT = os.path.join(PKG, "liblfltsmc.so")
 BUILD = os.path.join(PKG, "_build")
 
 HOST_SRC = ["host_mesh.cpp", "host_rng.cpp", "host_line.cpp", "host_tri.cpp"]
-DEV_SRC = ["lts_api.hip", "lts_step.hip", "lts_fused.hip", "lts_adjoint.hip", "lts_mlmc.hip", "lts_batch.hip", "lts_noalloc.hip", "lts_line.hip", "lts_tri.hip"]
+DEV_SRC = ["lts_api.hip", "lts_step.hip", "lts_fused.hip", "lts_adjoint.hip", "lts_mlmc.hip", "lts_batch.hip", "lts_noalloc.hip", "lts_line.hip", "lts_tri.hip", "lts_mlts.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -58,6 +58,22 @@ struct TilingDev {
   DevBuf ent, tiles, rtiles, citems;
 };
 
+// Tiers of the multi-level step attached to a level (lts_set_mlts; see
+// lts_mlts.hip).
+struct MltsDev {
+  int T = 0, K = 0;                        // tiers, exchange phases per step (= region radius)
+  int p[LTS_MLTS_MAX_TIERS] = {};
+  int nP[LTS_MLTS_MAX_TIERS] = {};         // |P_j|
+  int max_region = 0, nt = 1024;
+  double updates = 0.0;                    // DOF updates of one step of one sample
+  double omega[LTS_MLTS_MAX_TIERS] = {}, delta[LTS_MLTS_MAX_TIERS] = {};
+  double beta[LTS_MLTS_MAX_TIERS][LTS_MLTS_MAX_P] = {};   // beta_m of tier j, beta_0 = 0
+  TilingDev tiling;                        // compact tiles, regions of radius K
+  DevBuf ptier;                            // per node: largest j with the node in P_j (0 off P_1)
+  DevBuf c0;                               // per sample of a solve: the innermost half-step coefficient
+  std::vector<double> c0_host;             // its host copy
+};
+
 struct DevLevel {
   HostLevel H;
   TilingDev tiling;     // fused-step tiling in use
@@ -67,6 +83,7 @@ struct DevLevel {
   int ld = 0;           // row pitch (elements) of node/cell arrays and states
   size_t nodes = 0;     // nyn * ld
   DevBuf hx, hy, inv2hx, inv2hy, x, y, cblk, flags, ninfo, invm, qoiw, beta, beta_half;
+  std::unique_ptr<MltsDev> mlts;   // tiers of the multi-level step, if attached
   // compact lists of DOFs (flat padded index), used by reductions
   LevelView view() const {
     LevelView v;
@@ -289,5 +306,9 @@ size_t step_args_size();
 lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const double* d_kappa,
                        const double* d_coef, const double* Ucur, double* Uold, size_t sstride, int s0,
                        int active, int startup, hipStream_t stream, bool fp32 = false, double* Unew = nullptr);
+// The coarse-item launch of launch_step alone (FP64): the DOFs outside F+.
+lts_status launch_coarse(lts_ctx c, const DevLevel& lv, const TilingDev& T, const double* d_kappa,
+                         const double* d_coef, const double* Ucur, double* Uold, size_t sstride, int active,
+                         int startup, hipStream_t stream);
 
 }  // namespace lts

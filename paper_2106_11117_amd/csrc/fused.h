@@ -43,8 +43,9 @@ struct TilingHost {
 };
 
 // Tiling of a level: TX x TY tiles with grid origin (ox, oy), or with TX = TY
-// = 0 the adaptive compact tiling.
+// = 0 the adaptive compact tiling.  Compact regions hold at most `cap` nodes;
+// their radius is H.p.
 std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int oy, bool rect,
-                         TilingHost& T);
+                         TilingHost& T, int cap = kRegionCap);
 
 }  // namespace lts

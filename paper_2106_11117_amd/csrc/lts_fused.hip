@@ -1126,7 +1126,7 @@ __global__ __launch_bounds__(kPersistThreads) void k_persist(PersistArgs pa) {
 // Host: tiling of a level for a fine-tile rectangle of TX x TY nodes.
 
 std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int oy, bool rect,
-                         TilingHost& T) {
+                         TilingHost& T, int cap) {
   T = TilingHost();
   T.TX = TX;
   T.TY = TY;
@@ -1159,7 +1159,7 @@ std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int
     std::stable_sort(nodes.begin(), nodes.end(),
                      [](const std::array<int, 3>& a, const std::array<int, 3>& b) { return a[0] < b[0]; });
     const int len = (int)nodes.size();
-    if (len > kRegionCap) return "fine tile region exceeds the workgroup capacity";
+    if (len > cap) return "fine tile region exceeds the workgroup capacity";
     loc.assign((size_t)RX * RY, -1);
     for (int l = 0; l < len; ++l) loc[(size_t)(nodes[l][1] - y0) * RX + (nodes[l][2] - x0)] = l;
     const int off = (int)T.ent.size();
@@ -1255,7 +1255,7 @@ std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int
     Box b;
     if (!shrink(b0, b)) return 0;
     const size_t r = fast_region(b);
-    if (r <= (size_t)kRegionCap) return r;
+    if (r <= (size_t)cap) return r;
     size_t best = kNoFit;
     Box bA{}, bB{};
     for (int axis = 0; axis < 2; ++axis) {
@@ -1277,7 +1277,7 @@ std::string build_tiling(const HostLevel& H, int ld, int TX, int TY, int ox, int
   std::function<std::string(const Box&)> bisect = [&](const Box& b0) -> std::string {
     Box b;
     if (!shrink(b0, b)) return "";
-    if (fast_region(b) <= (size_t)kRegionCap) return add_compact(b.x0, b.x1, b.y0, b.y1);
+    if (fast_region(b) <= (size_t)cap) return add_compact(b.x0, b.x1, b.y0, b.y1);
     size_t best = kNoFit;
     Box bA{}, bB{};
     for (int axis = 0; axis < 2; ++axis) {
@@ -1525,6 +1525,28 @@ lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const 
     else
       k_fine<false, double><<<grid, dim3(kFineThreads), 0, stream>>>(a);
   }
+  return LTS_OK;
+}
+
+lts_status launch_coarse(lts_ctx c, const DevLevel& lv, const TilingDev& T, const double* d_kappa,
+                         const double* d_coef, const double* Ucur, double* Uold, size_t sstride, int active,
+                         int startup, hipStream_t stream) {
+  if (active <= 0 || T.n_coarse <= 0) return LTS_OK;
+  StepArgs a{};
+  a.L = lv.view();
+  a.citems = T.citems.as<int4>();
+  a.n_coarse = T.n_coarse;
+  a.active = active;
+  a.kappa = d_kappa;
+  a.coef = d_coef;
+  a.Ucur = Ucur;
+  a.Uold = Uold;
+  a.Unew = Uold;
+  a.sstride = sstride;
+  a.startup = startup;
+  const long long G = (long long)T.n_coarse * active;
+  a.per_xcd = (int)((G + 7) / 8);
+  k_coarse<double><<<dim3((unsigned)(8LL * a.per_xcd)), dim3(kCoarseThreads), 0, stream>>>(a);
   return LTS_OK;
 }
 

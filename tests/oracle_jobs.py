@@ -76,8 +76,25 @@ def solve_tri(job):
     return {"Q": float(lts.qoi(ops, u)), "abs_wu": float(ops.qoi_w @ np.abs(u)), "n_steps": n}
 
 
+def solve_mlts(job):
+    """('mlts', base, sample_level, i, T, ps) -> as solve(), with multi-level
+    LTS (oracle/mlts.py) on the graded L-shape level, tiers by the halving
+    rule with ratios ps."""
+    from oracle import mlts
+    _, base, slevel, i, T, ps = job
+    lv = mesh.graded_L_level(base)
+    ops = fem.operators(lv)
+    ct = mlts.tiers_by_leg(lv, len(ps))
+    rule = rng.SampleRule(T=T, **GRADED_RULE)
+    smp = rng.draw(0, slevel, i, rule)
+    n, dt = rng.steps_for(smp, rule, lv.h)
+    s = mlts.MltsSolver(ops, smp.kappa, mlts.tier_projectors(lv, ct, len(ps)), ps)
+    u = s.run(lts.pulse(ops, smp.x0), dt, n)
+    return {"Q": float(lts.qoi(ops, u)), "abs_wu": float(ops.qoi_w @ np.abs(u)), "n_steps": n}
+
+
 def _run(job):
-    return {"fwd": solve, "fwdq": solve_tiers, "adj": grad, "tri": solve_tri}[job[0]](job)
+    return {"fwd": solve, "fwdq": solve_tiers, "adj": grad, "tri": solve_tri, "mlts": solve_mlts}[job[0]](job)
 
 
 def run_all(jobs):
