@@ -352,6 +352,58 @@ def adjoint_graded_bench(K: int = 64):
     ctx.close()
 
 
+def mlts_bench(T: float = 2.0):
+    """Multi-level LTS (lts_mlts_forward: five tiers by halving legs, p_j = 2)
+    against the single-tier LTS solve (lts_forward, p = 64, autotuned tiling)
+    on the graded L-shape levels 2-4 at the workload's horizon T = 2, the same
+    samples for both (level 2: 64, level 3: 64, level 4: 16).  Wall time with
+    the inputs staged, the step kernels' event time, DOF updates per step
+    (each scheme's own count), and the largest QoI difference (time
+    discretisation) relative to max |Q|."""
+    import numpy as np
+
+    import paper_2106_11117_amd as P
+
+    ctx = P.Context(0)
+    ctx.set_timing(True)
+    rule = P.sample_rule(n_blocks=64, sigma=0.3, pulse=(-0.8, -0.4, 0.4, 0.8), width=0.05, T=T)
+    out = {"metric": "multi-level LTS vs single-tier LTS wall time, graded L-shape (T = 2)",
+           "unit": "s", "higher_is_better": False, "data": "synthetic (Philox seed 0)", "dtype": "f64",
+           "tiers": [2, 2, 2, 2, 2], "runs": []}
+    for lev, nb, S in ((2, 128, 64), (3, 256, 64), (4, 512, 16)):
+        lid = ctx.add_rect_level(P.graded_L_rule(nb))
+        ctx.autotune(lid)
+        info = ctx.level_info(lid)
+        mi = ctx.set_mlts(lid, [2, 2, 2, 2, 2])
+        s = P.gen_samples(0, lev, 0, S, rule, info["h"])
+        args = (s["kappa"], s["x0"], s["n_steps"], s["dt"])
+        ctx.forward(lid, *(a[:2] for a in args))                 # warm-up
+        ctx.mlts_forward(lid, *(a[:2] for a in args))
+        t0 = time.perf_counter()
+        ql = np.asarray(ctx.forward(lid, *args))
+        tl = time.perf_counter() - t0
+        kl = ctx.timing()["step_kernel_ms"]
+        t0 = time.perf_counter()
+        qm = np.asarray(ctx.mlts_forward(lid, *args))
+        tm = time.perf_counter() - t0
+        km = ctx.timing()["step_kernel_ms"]
+        steps = float(s["n_steps"].sum())
+        upd_l = (info["n_dof"] - info["n_P"]) + info["p"] * info["n_P"]
+        print(f"level {lev}: lts {tl:.3f} s, mlts {tm:.3f} s", flush=True)
+        out["runs"].append({
+            "level": lev, "dofs": info["n_dof"], "samples": S, "sum_n_steps": int(steps),
+            "n_P_tiers": mi["n_P"], "mlts_tiles": mi["n_tiles"], "mlts_halo_ratio": mi["halo_ratio"],
+            "mlts_max_region": mi["max_region"], "lts_halo_ratio": info["halo_ratio"],
+            "lts": {"s": tl, "step_kernel_ms": kl, "updates_per_step": upd_l,
+                    "dof_updates_per_s": steps * upd_l / tl},
+            "mlts": {"s": tm, "step_kernel_ms": km, "updates_per_step": mi["updates_per_step"],
+                     "dof_updates_per_s": steps * mi["updates_per_step"] / tm},
+            "speedup": tl / tm,
+            "max_dq_over_max_q": float(np.max(np.abs(qm - ql)) / np.max(np.abs(ql)))})
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 BATCH_N = (4096, 1024, 256, 64, 16)       # samples per level of the multi-level throughput run
 
 
@@ -593,6 +645,8 @@ def main():
                     help="only run the one-dimensional workloads' MLMC, LF-LTS against leapfrog")
     ap.add_argument("--stream-check", action="store_true",
                     help="only time plain torch copy / axpy / sum kernels (practical HBM rates)")
+    ap.add_argument("--mlts", action="store_true",
+                    help="multi-level LTS against single-tier LTS on the graded L-shape levels 2-4")
     ap.add_argument("--adjoint-graded", action="store_true",
                     help="the discrete adjoint on graded L-shape levels 2 and 3 (compact tiles) against the forward")
     ap.add_argument("--adjoint", action="store_true",
@@ -609,6 +663,9 @@ def main():
     args = ap.parse_args()
     if args.batch:
         batch_bench(args.plain)
+        return
+    if args.mlts:
+        mlts_bench()
         return
     if args.adjoint_graded:
         adjoint_graded_bench()
