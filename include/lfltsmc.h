@@ -582,10 +582,14 @@ typedef struct {
   int32_t level_kind;             /* LTS_LEVELS_GRID: level_ids from lts_add_level /
                                      lts_build_rect_level; LTS_LEVELS_MESH: mesh ids from
                                      lts_add_mesh (solved by lts_mesh_forward level by level;
-                                     no generated levels, no gradient) */
+                                     no generated levels, no gradient); LTS_LEVELS_MLTS: grid
+                                     levels with tiers attached (lts_set_mlts), solved by
+                                     lts_mlts_forward level by level, the cost model counting
+                                     the multi-level updates ceil(T/(cfl h)) x updates_per_step
+                                     (no generated levels, no gradient) */
 } lts_mlmc_opts;
 
-enum { LTS_LEVELS_GRID = 0, LTS_LEVELS_MESH = 1 };
+enum { LTS_LEVELS_GRID = 0, LTS_LEVELS_MESH = 1, LTS_LEVELS_MLTS = 2 };
 
 typedef struct {
   double estimate;                /* sum_l mean(Delta Q_l) */

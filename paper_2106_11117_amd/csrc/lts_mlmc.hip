@@ -62,15 +62,19 @@ lts_status draw_level(lts_ctx c, const lts_mlmc_opts& o, int l, int64_t first, i
 // level in one graph-captured lts_batch_run.
 lts_status solve_batches(lts_ctx c, const lts_mlmc_opts& o, std::vector<LevelBatch>& bs) {
   lts_status r;
-  if (o.level_kind == LTS_LEVELS_MESH) {
-    // triangle meshes: one batched solve per level and mesh
+  if (o.level_kind == LTS_LEVELS_MESH || o.level_kind == LTS_LEVELS_MLTS) {
+    // triangle meshes, multi-level LTS: one batched solve per level and mesh
+    const bool mesh = o.level_kind == LTS_LEVELS_MESH;
+    auto solve = [&](int32_t id, const lts_samples* S, double* q) {
+      return mesh ? lts_mesh_forward(c, id, S, LTS_FP64, q) : lts_mlts_forward(c, id, S, LTS_FP64, q);
+    };
     for (auto& b : bs) {
       if (b.n == 0) continue;
       lts_samples sf{b.n, LTS_PTR_HOST, b.kappa.data(), b.x0.data(), b.nsf.data(), b.dtf.data(), o.rule.width};
-      if ((r = lts_mesh_forward(c, o.level_ids[b.l], &sf, LTS_FP64, b.qf.data())) != LTS_OK) return r;
+      if ((r = solve(o.level_ids[b.l], &sf, b.qf.data())) != LTS_OK) return r;
       if (b.l > 0) {
         lts_samples sc{b.n, LTS_PTR_HOST, b.kappa.data(), b.x0.data(), b.nsc.data(), b.dtc.data(), o.rule.width};
-        if ((r = lts_mesh_forward(c, o.level_ids[b.l - 1], &sc, LTS_FP64, b.qc.data())) != LTS_OK) return r;
+        if ((r = solve(o.level_ids[b.l - 1], &sc, b.qc.data())) != LTS_OK) return r;
       }
     }
     return LTS_OK;
@@ -153,13 +157,16 @@ lts_status mlmc_run(lts_ctx c, const lts_mlmc_opts* op, lts_mlmc_result* out, in
   lts_mlmc_opts o = *op;                    // level_ids grows with generated levels
   const int n_total = std::max(o.n_levels, o.n_levels_max);
   if (o.n_levels < 0 || n_total < 1 || n_total > LTS_MAX_LEVELS) return arg_fail(c, "n_levels out of range");
-  if (o.level_kind != LTS_LEVELS_GRID && o.level_kind != LTS_LEVELS_MESH) return arg_fail(c, "bad level_kind");
-  const bool meshes = o.level_kind == LTS_LEVELS_MESH;
-  if (meshes && (n_total > o.n_levels || dg))
-    return arg_fail(c, "triangle-mesh hierarchies are given in full and have no gradient form");
-  for (int l = 0; l < o.n_levels; ++l)
+  if (o.level_kind != LTS_LEVELS_GRID && o.level_kind != LTS_LEVELS_MESH && o.level_kind != LTS_LEVELS_MLTS)
+    return arg_fail(c, "bad level_kind");
+  const bool meshes = o.level_kind == LTS_LEVELS_MESH, tiers = o.level_kind == LTS_LEVELS_MLTS;
+  if ((meshes || tiers) && (n_total > o.n_levels || dg))
+    return arg_fail(c, "triangle-mesh and multi-level LTS hierarchies are given in full and have no gradient form");
+  for (int l = 0; l < o.n_levels; ++l) {
     if (o.level_ids[l] < 0 || o.level_ids[l] >= (int)(meshes ? c->meshes.size() : c->levels.size()))
       return arg_fail(c, "bad level id");
+    if (tiers && !c->levels[o.level_ids[l]]->mlts) return arg_fail(c, "a level has no tiers attached (lts_set_mlts)");
+  }
   for (int l = 0; l < n_total; ++l)
     if (o.N_init[l] < 2) return arg_fail(c, "N_init must be >= 2 (variance estimates)");
   if (!(o.eps > 0.0) || !(o.alpha > 0.0)) return arg_fail(c, "eps and alpha must be > 0");
@@ -194,7 +201,9 @@ lts_status mlmc_run(lts_ctx c, const lts_mlmc_opts* op, lts_mlmc_result* out, in
   // cost model C_l in DOF updates per Delta Q_l sample, formed as levels are added
   std::vector<double> cs(n_total, 0.0), C(n_total, 0.0);
   auto add_cost = [&](int l) {
-    cs[l] = solve_cost_model(level_header(c, o, l), o.rule);
+    const HostLevel& H = level_header(c, o, l);
+    cs[l] = tiers ? std::ceil(o.rule.T / (o.rule.cfl * H.h)) * c->levels[o.level_ids[l]]->mlts->updates
+                  : solve_cost_model(H, o.rule);
     C[l] = l == 0 ? cs[0] : cs[l] + cs[l - 1];
   };
   for (int l = 0; l <= L; ++l) add_cost(l);

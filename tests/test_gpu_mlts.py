@@ -136,3 +136,57 @@ def test_device_pointers_g_and_errors(ctx):
         P._check(ctx.lib.lts_mlts_forward(ctx.h, lid, None, P.LTS_FP32_STEP, None), ctx.h)
     with pytest.raises(P.LtsError):
         ctx.mlts_info(99)
+
+
+def test_mlmc_with_multi_level_lts(ctx):
+    """Algorithm 1 over graded levels with 16, 32 and 64 cells across, each
+    with the five tiers (LTS_LEVELS_MLTS), T = 0.5 and the QoI over
+    [-0.35,0.05]x[0.05,0.45] next to the graded corner: the same L, N_l,
+    estimate, moments and cost model as the oracle's Algorithm 1 with the
+    oracle's multi-level LTS solves and the multi-level update count as cost."""
+    import math
+
+    from oracle import mlmc
+    bases, qb = (16, 32, 64), (-0.35, 0.05, 0.05, 0.45)
+    ids = []
+    for b in bases:
+        lid = ctx.add_rect_level(P.graded_L_rule(b, qoi=qb))
+        ctx.set_mlts(lid, PS)
+        ids.append(lid)
+    eps, N_init = 2e-4, (24, 12, 6)
+    res = ctx.mlmc(ids, _rule(0.5), eps=eps, N_init=N_init, L_start=1, mlts=True)
+    ops = [fem.operators(mesh.graded_L_level(b, qoi_box=qb)) for b in bases]
+    Ps = [mlts.tier_projectors(o.lv, mlts.tiers_by_leg(o.lv, 5), 5) for o in ops]
+    orule = rng.SampleRule(T=0.5, n_blocks=64, sigma=0.3, pulse_box=(-0.8, -0.4, 0.4, 0.8))
+
+    def q(l, smp):
+        n, dt = rng.steps_for(smp, orule, ops[l].lv.h)
+        u = mlts.MltsSolver(ops[l], smp.kappa, Ps[l], PS).run(lts.pulse(ops[l], smp.x0), dt, n)
+        return float(lts.qoi(ops[l], u))
+
+    def eval_dq(l, i):
+        smp = rng.draw(0, l, i, orule)
+        return q(l, smp) - (q(l - 1, smp) if l > 0 else 0.0)
+
+    cs = []
+    for o, Pl in zip(ops, Ps):
+        nP = [int(v.sum()) for v in Pl]
+        upd, rate = o.lv.n_dof - nP[0], 1
+        for j in range(5):
+            rate *= PS[j]
+            upd += rate * (nP[j] - (nP[j + 1] if j + 1 < 5 else 0))
+        cs.append(math.ceil(orule.T / (orule.cfl * o.lv.h)) * upd)
+    costs = [cs[0]] + [cs[l] + cs[l - 1] for l in (1, 2)]
+    print("oracle Algorithm 1 with multi-level LTS", flush=True)
+    ores = mlmc.mlmc(ops, orule, eps=eps, N_init=N_init, L_start=1, eval_dq=eval_dq, costs=costs)
+    assert ores.L == 2
+    assert res["L"] == ores.L and res["N"] == ores.N
+    assert res["cost"] == [float(c) for c in ores.cost[:ores.L + 1]]
+    scale = max(abs(v) for v in ores.mean)
+    assert abs(res["estimate"] - ores.estimate) <= 1e-11 * scale
+    for l in range(res["L"] + 1):
+        assert abs(res["mean"][l] - ores.mean[l]) <= 1e-11 * scale
+        assert abs(res["var"][l] - ores.var[l]) <= 1e-9 * ores.var[l]
+    with pytest.raises(P.LtsError):                    # a level without tiers
+        lid = ctx.add_rect_level(P.graded_L_rule(16, qoi=qb))
+        ctx.mlmc([lid] + ids[1:], _rule(0.5), eps=eps, N_init=N_init, L_start=1, mlts=True)
