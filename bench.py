@@ -359,7 +359,9 @@ def mlts_bench(T: float = 2.0):
     samples for both (level 2: 64, level 3: 64, level 4: 16).  Wall time with
     the inputs staged, the step kernels' event time, DOF updates per step
     (each scheme's own count), and the largest QoI difference (time
-    discretisation) relative to max |Q|."""
+    discretisation) relative to max |Q|.  Then Algorithm 1 on the five-level
+    hierarchy at the MLMC benchmark's eps with either scheme: wall time, L,
+    N_l and the cost model sum_l N_l C_l."""
     import numpy as np
 
     import paper_2106_11117_amd as P
@@ -400,6 +402,29 @@ def mlts_bench(T: float = 2.0):
                      "dof_updates_per_s": steps * mi["updates_per_step"] / tm},
             "speedup": tl / tm,
             "max_dq_over_max_q": float(np.max(np.abs(qm - ql)) / np.max(np.abs(ql)))})
+    # Algorithm 1 on the five-level graded hierarchy: single-tier LTS (batched +
+    # graph) against multi-level LTS (one solve per level and mesh), same eps
+    ids = []
+    for nb in MLMC_BASES:
+        lid = ctx.add_rect_level(P.graded_L_rule(nb))
+        ctx.autotune(lid)
+        ctx.set_mlts(lid, [2, 2, 2, 2, 2])
+        ids.append(lid)
+    out["mlmc"] = []
+    for eps in MLMC_EPS:
+        t0 = time.perf_counter()
+        rl = ctx.mlmc(ids, rule, eps=eps, N_init=MLMC_N_INIT, L_start=2)
+        wl = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        rm = ctx.mlmc(ids, rule, eps=eps, N_init=MLMC_N_INIT, L_start=2, mlts=True)
+        wm = time.perf_counter() - t0
+        print(f"mlmc eps {eps}: lts {wl:.3f} s, mlts {wm:.3f} s", flush=True)
+        out["mlmc"].append({
+            "eps": eps,
+            "lts": {"s": wl, "L": rl["L"], "N": rl["N"], "estimate": rl["estimate"], "rmse": rl["rmse"],
+                    "cost_model": float(sum(n * c for n, c in zip(rl["N"], rl["cost"])))},
+            "mlts": {"s": wm, "L": rm["L"], "N": rm["N"], "estimate": rm["estimate"], "rmse": rm["rmse"],
+                     "cost_model": float(sum(n * c for n, c in zip(rm["N"], rm["cost"])))}})
     print(json.dumps(out), flush=True)
     ctx.close()
 
