@@ -487,7 +487,8 @@ enum { LTS_BATCH_GRAPH = 1,      /* capture the step loop into HIP graphs and re
        LTS_BATCH_SB1 = 8,         /* persistent form: S_b capped at 1 */
        LTS_BATCH_SB2 = 16,        /* persistent form: S_b capped at 2 (neither: at 4) */
        LTS_BATCH_SB_MASK = 24,
-       LTS_BATCH_AUTO = 32 };     /* choose the form by measurement (below) */
+       LTS_BATCH_AUTO = 32,       /* choose the form by measurement (below) */
+       LTS_BATCH_MLTS = 64 };     /* multi-level LTS on every job (below) */
 
 /* Advance all jobs of all levels together (the MLMC cost sum_l N_l C_l of
  * Sec. 2.2 spread over one device): uneven mesh sizes and step counts share
@@ -508,6 +509,11 @@ enum { LTS_BATCH_GRAPH = 1,      /* capture the step loop into HIP graphs and re
  *    the graph form and the persistent form with S_b caps 4, 2 and 1, and run
  *    the whole batch in the fastest (the choice is cached per job-list shape;
  *    lts_get_timing reports it).  Excludes the other form flags.
+ *  - LTS_BATCH_MLTS: every job is solved by multi-level LTS with its level's
+ *    tiers (lts_set_mlts; LTS_ERR_STATE for a level without), the coarse DOFs
+ *    and the fine tiles of all jobs in shared launches per step (with
+ *    LTS_BATCH_GRAPH captured and replayed); QoIs bit-identical to
+ *    lts_mlts_forward.  FP64; excludes LTS_BATCH_PERSIST and LTS_BATCH_AUTO.
  * Every form gives bit-identical QoIs.  Errors as lts_forward. */
 lts_status lts_batch_run(lts_ctx ctx, const lts_job* jobs, int32_t n_jobs, int32_t flags,
                          double* Q_out);
@@ -584,9 +590,11 @@ typedef struct {
                                      lts_add_mesh (solved by lts_mesh_forward level by level;
                                      no generated levels, no gradient); LTS_LEVELS_MLTS: grid
                                      levels with tiers attached (lts_set_mlts), solved by
-                                     lts_mlts_forward level by level, the cost model counting
-                                     the multi-level updates ceil(T/(cfl h)) x updates_per_step
-                                     (no generated levels, no gradient) */
+                                     multi-level LTS (batched: lts_batch_run with
+                                     LTS_BATCH_MLTS | LTS_BATCH_GRAPH; plain: lts_mlts_forward
+                                     level by level), the cost model counting the multi-level
+                                     updates ceil(T/(cfl h)) x updates_per_step (no generated
+                                     levels, no gradient) */
 } lts_mlmc_opts;
 
 enum { LTS_LEVELS_GRID = 0, LTS_LEVELS_MESH = 1, LTS_LEVELS_MLTS = 2 };

@@ -399,12 +399,13 @@ class Context:
                                              C.byref(ca.s), precision, qfp, qcp, dqp))
         return qf, qc, dq
 
-    def batch_run(self, jobs, graph=False, precision=LTS_FP64, persist=False, sb_cap=4, auto=False):
+    def batch_run(self, jobs, graph=False, precision=LTS_FP64, persist=False, sb_cap=4, auto=False, mlts=False):
         """jobs: list of (level, kappa, x0, n_steps, dt, width).  Returns the Q of all
         jobs concatenated in job order.  precision LTS_FP32_STEP steps in binary32.
         Form: per-step launches (default), their HIP graph (graph=True), one
         persistent launch (persist=True, S_b capped at sb_cap in 1, 2, 4) or the
-        fastest of these by measurement (auto=True)."""
+        fastest of these by measurement (auto=True).  mlts=True: multi-level LTS
+        on every job (its level's tiers), with or without the graph."""
         args, cjobs, off = [], [], 0
         for (level, kappa, x0, ns, dt, width) in jobs:
             sa = _SampleArgs(kappa, x0, ns, dt, width)
@@ -420,6 +421,8 @@ class Context:
             flags |= _lib.LTS_BATCH_PERSIST | {1: _lib.LTS_BATCH_SB1, 2: _lib.LTS_BATCH_SB2, 4: 0}[sb_cap]
         if auto:
             flags |= _lib.LTS_BATCH_AUTO
+        if mlts:
+            flags |= _lib.LTS_BATCH_MLTS
         self._c(self.lib.lts_batch_run(self.h, arr, len(cjobs), flags, qp))
         return q
 

@@ -23,6 +23,7 @@ LTS_BATCH_SB1 = 8
 LTS_BATCH_SB2 = 16
 LTS_BATCH_SB_MASK = 24
 LTS_BATCH_AUTO = 32
+LTS_BATCH_MLTS = 64
 LTS_MESH_REGION_CAP = 2048
 LTS_MLTS_MAX_TIERS = 5
 LTS_MLTS_MAX_P = 16

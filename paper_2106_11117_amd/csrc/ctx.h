@@ -72,6 +72,7 @@ struct MltsDev {
   DevBuf ptier;                            // per node: largest j with the node in P_j (0 off P_1)
   DevBuf c0;                               // per sample of a solve: the innermost half-step coefficient
   std::vector<double> c0_host;             // its host copy
+  DevBuf rec;                              // the job record of a single-level solve
 };
 
 struct DevLevel {
@@ -132,7 +133,7 @@ struct lts_ctx_s {
   // workspace
   lts::DevBuf kappa, coef, nsteps, x0, Qd, perm, flag, st0, st1, wbuf, qa, qb, red, adj, adjscr, dldq, gout, adjlist;
   // batched form: per-job tables, states, job records, captured graph
-  lts::DevBuf b_tab, b_states, b_jobs, b_Q;
+  lts::DevBuf b_tab, b_states, b_jobs, b_Q, b_mjobs;
   // persistent form: active-sample table, control words (unit counters,
   // barrier arrivals, abort word), barrier wait bound and the wall-clock rate
   lts::DevBuf b_act, p_ctl;
@@ -271,8 +272,20 @@ lts_status autotune_level(lts_ctx c, DevLevel& lv);
 // One batched step launch over several jobs (see lts_fused.hip).
 struct StepArgs;
 // With fp32 the jobs' state buffers hold binary32 values.
+// kinds = 1: the coarse-item launch only.
 lts_status launch_multi_step(lts_ctx c, const StepArgs* d_jobs, const std::vector<const TilingDev*>& T,
-                             const std::vector<int>& active, int step, hipStream_t stream, bool fp32 = false);
+                             const std::vector<int>& active, int step, hipStream_t stream, bool fp32 = false,
+                             int kinds = 5);
+// Multi-level LTS jobs (lts_mlts.hip): the size of a job's device record, a
+// record for samples 0 .. n-1 (sorted order) of level lv with their tables at
+// d_kappa, d_c0 and states B0, B1 (written to out), the innermost half-step
+// coefficients c0 of steps dt, and one fine-tile launch of every job for step
+// `step` (active[j] samples of job j; M[j] its tiers).
+size_t mlts_record_size();
+void mlts_record(const DevLevel& lv, const double* d_kappa, const double* d_c0, double* B0, double* B1, void* out);
+void mlts_c0(const MltsDev& M, const double* dt, int n, double* c0);
+lts_status launch_mlts(lts_ctx c, const void* d_jobs, const std::vector<const MltsDev*>& M,
+                       const std::vector<int>& active, int step, hipStream_t stream);
 // The persistent form: steps 0 .. n_steps-1 of every job in cooperative
 // launches of one workgroup per CU with a grid barrier after each step
 // (see lts_fused.hip).  act_host[t * n_jobs + j] = active samples of job j at

@@ -208,8 +208,12 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
   if (!c) return LTS_ERR_ARG;
   c->err.clear();
   if (!jobs || n_jobs < 1 || n_jobs > kMaxJobs) return arg_fail(c, "n_jobs must be in 1..32");
-  if (flags & ~(LTS_BATCH_GRAPH | LTS_BATCH_FP32 | LTS_BATCH_PERSIST | LTS_BATCH_SB_MASK | LTS_BATCH_AUTO))
+  if (flags &
+      ~(LTS_BATCH_GRAPH | LTS_BATCH_FP32 | LTS_BATCH_PERSIST | LTS_BATCH_SB_MASK | LTS_BATCH_AUTO | LTS_BATCH_MLTS))
     return arg_fail(c, "unknown flags");
+  const bool mlts = (flags & LTS_BATCH_MLTS) != 0;
+  if (mlts && (flags & (LTS_BATCH_FP32 | LTS_BATCH_PERSIST | LTS_BATCH_SB_MASK | LTS_BATCH_AUTO)))
+    return arg_fail(c, "LTS_BATCH_MLTS runs in FP64 and excludes the persistent and automatic forms");
   const bool autof = (flags & LTS_BATCH_AUTO) != 0;
   if (autof && (flags & (LTS_BATCH_GRAPH | LTS_BATCH_PERSIST | LTS_BATCH_SB_MASK)))
     return arg_fail(c, "LTS_BATCH_AUTO excludes the other form flags");
@@ -227,6 +231,10 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
     if (jobs[j].level < 0 || jobs[j].level >= (int32_t)c->levels.size()) return arg_fail(c, "bad level id");
     if (jobs[j].samples.ptr_kind != kind) return arg_fail(c, "all jobs must use the same ptr_kind");
     if (jobs[j].q_offset < 0) return arg_fail(c, "q_offset must be >= 0");
+    if (mlts && !c->levels[jobs[j].level]->mlts) {
+      c->err = "a job's level has no tiers attached (lts_set_mlts)";
+      return LTS_ERR_STATE;
+    }
     total = std::max(total, jobs[j].q_offset + std::max(jobs[j].samples.n, 0));
   }
   if (total > 0 && !Q_out) return arg_fail(c, "Q_out is NULL");
@@ -237,10 +245,11 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
   LTS_HIP(c, hipSetDevice(c->device));
   for (int j = 0; j < n_jobs; ++j) {
     DevLevel& lv = *c->levels[jobs[j].level];
-    if (!lv.tuned && !lv.pinned && (r = autotune_level(c, lv)) != LTS_OK) return r;
+    if (!mlts && !lv.tuned && !lv.pinned && (r = autotune_level(c, lv)) != LTS_OK) return r;
   }
   // device layout: per-job tables, states, Q
-  std::vector<size_t> o_k(n_jobs), o_c(n_jobs), o_n(n_jobs), o_x(n_jobs), o_p(n_jobs), o_s(n_jobs), o_q(n_jobs);
+  std::vector<size_t> o_k(n_jobs), o_c(n_jobs), o_n(n_jobs), o_x(n_jobs), o_p(n_jobs), o_s(n_jobs), o_q(n_jobs),
+      o_c0(n_jobs);
   size_t tab = 256, sts = 0, qb = 0;                   // the first 256 bytes: the staging flag
   for (int j = 0; j < n_jobs; ++j) {
     const DevLevel& lv = *c->levels[jobs[j].level];
@@ -250,6 +259,7 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
     o_n[j] = tab; tab += align256(n * 4);
     o_x[j] = tab; tab += align256(n * 16);
     o_p[j] = tab; tab += align256(n * 4);
+    o_c0[j] = tab; tab += mlts ? align256(n * 8) : 0;
     o_s[j] = sts; sts += align256(n * lv.nodes * es) * 2;
     o_q[j] = qb; qb += align256(n * 8);
   }
@@ -257,6 +267,7 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
   LTS_HIP(c, c->b_states.ensure(std::max<size_t>(sts, 256)));
   LTS_HIP(c, c->b_Q.ensure(std::max<size_t>(qb, 256)));
   LTS_HIP(c, c->b_jobs.ensure(step_args_size() * n_jobs));
+  if (mlts) LTS_HIP(c, c->b_mjobs.ensure(mlts_record_size() * n_jobs));
   char* tb = c->b_tab.as<char>();
   char* sb = c->b_states.as<char>();
   char* qbp = c->b_Q.as<char>();
@@ -264,8 +275,10 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
     return StagedDev{(double*)(tb + o_k[j]), (double*)(tb + o_x[j]), (double*)(tb + o_c[j]), (int*)(tb + o_n[j]),
                      (int*)(tb + o_p[j]), (int*)tb};
   };
-  std::vector<char> recs(step_args_size() * n_jobs);
+  std::vector<char> recs(step_args_size() * n_jobs), mrecs(mlts ? mlts_record_size() * n_jobs : 0);
+  std::vector<std::vector<double>> c0h(n_jobs);
   std::vector<const TilingDev*> T(n_jobs);
+  std::vector<const MltsDev*> Mv(mlts ? n_jobs : 0);
   int maxT = 0;
   for (int j = 0; j < n_jobs; ++j) {
     const DevLevel& lv = *c->levels[jobs[j].level];
@@ -279,8 +292,18 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
     job_record(lv, lv.tiling, (const double*)(tb + o_k[j]), (const double*)(tb + o_c[j]), B0, B1, lv.nodes,
                recs.data() + j * step_args_size());
     T[j] = &lv.tiling;
+    if (mlts) {
+      Mv[j] = lv.mlts.get();
+      c0h[j].resize(S.n);
+      mlts_c0(*lv.mlts, S.dt.data(), S.n, c0h[j].data());
+      if (S.n > 0)
+        LTS_HIP(c, hipMemcpyAsync(tb + o_c0[j], c0h[j].data(), (size_t)S.n * 8, hipMemcpyHostToDevice, c->stream));
+      mlts_record(lv, (const double*)(tb + o_k[j]), (const double*)(tb + o_c0[j]), B0, B1,
+                  mrecs.data() + j * mlts_record_size());
+    }
   }
   LTS_HIP(c, hipMemcpyAsync(c->b_jobs.p, recs.data(), recs.size(), hipMemcpyHostToDevice, c->stream));
+  if (mlts) LTS_HIP(c, hipMemcpyAsync(c->b_mjobs.p, mrecs.data(), mrecs.size(), hipMemcpyHostToDevice, c->stream));
   LTS_HIP(c, hipStreamSynchronize(c->stream));   // host staging buffers may be released after this
 
   // active samples of every job at every step (samples sorted by decreasing n_steps)
@@ -328,8 +351,10 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
       std::vector<int> act(n_jobs);
       for (int t = 0; t < n_t; ++t) {
         for (int j = 0; j < n_jobs; ++j) act[j] = act_tab[(size_t)t * n_jobs + j];
-        if ((rr = launch_multi_step(c, (const StepArgs*)c->b_jobs.p, T, act, t, c->stream, fp32)) != LTS_OK)
+        if ((rr = launch_multi_step(c, (const StepArgs*)c->b_jobs.p, T, act, t, c->stream, fp32, mlts ? 1 : 5)) !=
+            LTS_OK)
           return rr;
+        if (mlts && (rr = launch_mlts(c, c->b_mjobs.p, Mv, act, t, c->stream)) != LTS_OK) return rr;
       }
     }
     for (int j = 0; j < n_jobs && with_qoi; ++j) {
@@ -431,10 +456,12 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
   if (graph) {
     // key: job shapes, step counts and every device address baked into the graph
     std::vector<uint64_t> key = {(uint64_t)n_jobs, (uint64_t)fp32, (uint64_t)(uintptr_t)tb, (uint64_t)(uintptr_t)sb,
-                                 (uint64_t)(uintptr_t)qbp, (uint64_t)(uintptr_t)c->b_jobs.p};
+                                 (uint64_t)(uintptr_t)qbp, (uint64_t)(uintptr_t)c->b_jobs.p, (uint64_t)mlts,
+                                 (uint64_t)(uintptr_t)(mlts ? c->b_mjobs.p : nullptr)};
     for (int j = 0; j < n_jobs; ++j) {
       key.push_back((uint64_t)jobs[j].level);
       key.push_back(c->levels[jobs[j].level]->tiling.gen);
+      key.push_back(mlts ? c->levels[jobs[j].level]->mlts->tiling.gen : 0);
       key.push_back((uint64_t)st[j].n);
       key.push_back((uint64_t)(std::llround(jobs[j].samples.width * 1e15)));
       for (int v : st[j].nsteps) key.push_back((uint64_t)v);
@@ -474,7 +501,8 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
   c->last.batch_sb_cap = persist ? sb_cap : 0;
   for (int j = 0; j < n_jobs; ++j) {
     const DevLevel& lv = *c->levels[jobs[j].level];
-    const double per_step = (double)(lv.H.n_dof - lv.H.n_P) + (double)lv.H.p * lv.H.n_P;
+    const double per_step =
+        mlts ? lv.mlts->updates : (double)(lv.H.n_dof - lv.H.n_P) + (double)lv.H.p * lv.H.n_P;
     for (int v : st[j].nsteps) {
       c->last.dof_updates += (double)v * per_step;
       c->last.alg_bytes += (double)v * 24.0 * lv.H.n_dof;

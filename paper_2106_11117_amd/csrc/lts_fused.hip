@@ -1551,7 +1551,7 @@ lts_status launch_coarse(lts_ctx c, const DevLevel& lv, const TilingDev& T, cons
 }
 
 lts_status launch_multi_step(lts_ctx c, const StepArgs* d_jobs, const std::vector<const TilingDev*>& T,
-                             const std::vector<int>& active, int step, hipStream_t stream, bool fp32) {
+                             const std::vector<int>& active, int step, hipStream_t stream, bool fp32, int kinds) {
   const int nj = (int)T.size();
   if (nj > kMaxJobs) {
     c->err = "too many jobs in one batch";
@@ -1606,7 +1606,7 @@ lts_status launch_multi_step(lts_ctx c, const StepArgs* d_jobs, const std::vecto
         k_fine_small_multi<double, 256><<<grid, dim3(256), 0, stream>>>(m);
     }
   };
-  for (int kind = 0; kind < 5; ++kind) go(kind);
+  for (int kind = 0; kind < std::min(kinds, 5); ++kind) go(kind);
   return LTS_OK;
 }
 

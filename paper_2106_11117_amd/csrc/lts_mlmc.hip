@@ -58,12 +58,15 @@ lts_status draw_level(lts_ctx c, const lts_mlmc_opts& o, int l, int64_t first, i
 }
 
 // Solve the batches: plain form = one solve call per level and mesh with one
-// launch per sample and step; batched form = every fine and coarse job of every
-// level in one graph-captured lts_batch_run.
+// launch per sample and step (multi-level LTS: one solve per level and mesh);
+// batched form = every fine and coarse job of every level in one
+// graph-captured lts_batch_run.
 lts_status solve_batches(lts_ctx c, const lts_mlmc_opts& o, std::vector<LevelBatch>& bs) {
   lts_status r;
-  if (o.level_kind == LTS_LEVELS_MESH || o.level_kind == LTS_LEVELS_MLTS) {
-    // triangle meshes, multi-level LTS: one batched solve per level and mesh
+  const bool tiers = o.level_kind == LTS_LEVELS_MLTS;
+  if (o.level_kind == LTS_LEVELS_MESH || (tiers && o.mode == LTS_MLMC_PLAIN)) {
+    // triangle meshes, and the plain form of multi-level LTS: one solve per
+    // level and mesh
     const bool mesh = o.level_kind == LTS_LEVELS_MESH;
     auto solve = [&](int32_t id, const lts_samples* S, double* q) {
       return mesh ? lts_mesh_forward(c, id, S, LTS_FP64, q) : lts_mlts_forward(c, id, S, LTS_FP64, q);
@@ -110,7 +113,8 @@ lts_status solve_batches(lts_ctx c, const lts_mlmc_opts& o, std::vector<LevelBat
   }
   if (jobs.empty()) return LTS_OK;
   std::vector<double> q(off);
-  if ((r = lts_batch_run(c, jobs.data(), (int32_t)jobs.size(), LTS_BATCH_GRAPH, q.data())) != LTS_OK) return r;
+  const int32_t flags = LTS_BATCH_GRAPH | (tiers ? LTS_BATCH_MLTS : 0);
+  if ((r = lts_batch_run(c, jobs.data(), (int32_t)jobs.size(), flags, q.data())) != LTS_OK) return r;
   off = 0;
   for (auto& b : bs) {
     if (b.n == 0) continue;

@@ -48,20 +48,30 @@ constexpr int kMNPT = 2;                      // region nodes per lane
 constexpr int kMCap = kFineThreads * kMNPT;   // largest region
 constexpr int kMPitch = 8;                    // row pitch multiple of the device arrays
 
-struct MltsArgs {
+// A job's record in device memory: level, tiling, tiers, the samples' tables
+// and the two state buffers (step t reads B[t & 1], writes B[(t + 1) & 1]).
+struct MltsJob {
   LevelView L;
-  const int4* __restrict__ ent;
-  const int4* __restrict__ tiles;
-  const uint8_t* __restrict__ ptier;  // [nyn*ld] largest j + 1 with the node in P_j, 0 off P
-  const double* __restrict__ kappa;   // [S][nb] (sorted sample order)
-  const double* __restrict__ c0;      // [S] innermost half-step coefficient
-  const double* __restrict__ Ucur;    // u_n of sample s at Ucur + s*sstride
-  double* Uold;                       // u_n-1 in, u_n+1 out at the tiles' own nodes
+  const int4* ent;
+  const int4* tiles;
+  const uint8_t* ptier;               // [nyn*ld] largest j + 1 with the node in P_j, 0 off P
+  const double* kappa;                // [S][nb] (sorted sample order)
+  const double* c0;                   // [S] innermost half-step coefficient
+  double* B0;
+  double* B1;
   size_t sstride;
-  int n_fine, per_xcd, active, startup;
-  int T, K;
+  int n_fine, T, K, pad;
   int p[kMT];
   double beta[kMT][kMP];              // beta_m of tier j, beta[j][0] = 0
+};
+
+// One launch over the fine tiles of several jobs: job `order[q]` owns the
+// workgroups of launch position q, wg_n[q] of them, split into 8 contiguous
+// chunks (one per XCD) of ceil(wg_n / 8); chunk_off holds their prefix sums.
+struct MltsLaunch {
+  const MltsJob* jobs;
+  int n_jobs, step;
+  int order[kMaxJobs], wg_n[kMaxJobs], chunk_off[kMaxJobs + 1];
 };
 
 // The state of a lane's region nodes.
@@ -74,7 +84,7 @@ struct MLane {
 
 // Tier J over the force S.F[J]: leaves its increment in S.e[J].
 template <int NT, int J>
-__device__ __forceinline__ void tier_run(const MltsArgs& x, MLane& S, double* __restrict__ lq, int& ph,
+__device__ __forceinline__ void tier_run(const MltsJob& x, MLane& S, double* __restrict__ lq, int& ph,
                                          int& reach, double c0, int tid) {
   constexpr int kCap = NT * kMNPT;
   const int p = x.p[J];
@@ -132,26 +142,40 @@ __device__ __forceinline__ void tier_run(const MltsArgs& x, MLane& S, double* __
   }
 }
 
-// One workgroup per (sample, fine tile); the tile's region nodes (F+ nodes
-// within Manhattan distance K of the tile, by increasing distance) two per
-// lane.  Region entries as in the single-tier compact tiles.
+// The job and job-local workgroup of this workgroup; false past a job's count.
+// XCD x runs chunk x of every job in launch order, so neighbouring tiles of a
+// sample share that XCD's L2.
+__device__ __forceinline__ bool mlts_slot(const MltsLaunch& m, int& j, int& local) {
+  const int x = (int)(blockIdx.x & 7), k = (int)(blockIdx.x >> 3);
+  int q = 0;
+  while (q + 1 < m.n_jobs && k >= m.chunk_off[q + 1]) ++q;
+  const int per = m.chunk_off[q + 1] - m.chunk_off[q];
+  j = m.order[q];
+  local = x * per + (k - m.chunk_off[q]);
+  return k < m.chunk_off[m.n_jobs] && local < m.wg_n[q];
+}
+
+// One workgroup per (job, sample, fine tile); the tile's region nodes (F+
+// nodes within Manhattan distance K of the tile, by increasing distance) two
+// per lane.  Region entries as in the single-tier compact tiles.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_mlts(MltsArgs x) {
+__global__ __launch_bounds__(NT) void k_mlts(MltsLaunch m) {
   constexpr int kCap = NT * kMNPT;
   __shared__ double lq[2 * (kCap + 1)];
   __shared__ double lk[256];
-  const int G = x.n_fine * x.active;
-  const int Lid = (int)(blockIdx.x & 7) * x.per_xcd + (int)(blockIdx.x >> 3);
-  if (Lid >= G) return;
-  const int s = Lid / x.n_fine, tile = Lid - s * x.n_fine;
+  int jb, local;
+  if (!mlts_slot(m, jb, local)) return;
+  const MltsJob& x = m.jobs[jb];
+  const int s = local / x.n_fine, tile = local - s * x.n_fine;
   const LevelView& L = x.L;
   const int tid = (int)threadIdx.x;
   for (int t = tid; t < L.nb; t += NT) lk[t] = x.kappa[(size_t)s * L.nb + t];
   const int4 tl = x.tiles[tile];
   const int len = tl.y;
   const int ix0 = tl.z & 0xFFFF, ix1 = tl.z >> 16, iy0 = tl.w & 0xFFFF, iy1 = tl.w >> 16;
-  const double* __restrict__ u = x.Ucur + (size_t)s * x.sstride;
-  double* uo = x.Uold + (size_t)s * x.sstride;
+  const bool odd = m.step & 1, startup = m.step == 0;
+  const double* __restrict__ u = (odd ? x.B1 : x.B0) + (size_t)s * x.sstride;
+  double* uo = (odd ? x.B0 : x.B1) + (size_t)s * x.sstride;
   const int ld = L.ld;
   int4 en[kMNPT];
 #pragma unroll
@@ -202,7 +226,7 @@ __global__ __launch_bounds__(NT) void k_mlts(MltsArgs x) {
   for (int r = 0; r < kMNPT; ++r) {
     if (S.dd[r] != 0) continue;        // written back by the tile that owns the node
     const size_t k = (size_t)kk[r];
-    uo[k] = x.startup ? u0[r] + S.e[0][r] : 2.0 * u0[r] - uo[k] + 2.0 * S.e[0][r];
+    uo[k] = startup ? u0[r] + S.e[0][r] : 2.0 * u0[r] - uo[k] + 2.0 * S.e[0][r];
   }
 }
 
@@ -296,27 +320,23 @@ void fill_info(const MltsHost& M, lts_mlts_info* o) {
 
 int pitch_of(int nxn) { return (nxn + kMPitch - 1) / kMPitch * kMPitch; }
 
-// The innermost half-step coefficient for a step dt: c0 = sigma_T^2 / (omega_T
-// delta_T) with sigma_1 = dt, sigma_j+1^2 = sigma_j^2 2 / (omega_j delta_j).
-double innermost_c0(const MltsDev& M, double dt) {
-  long double s2 = (long double)dt * dt;
-  for (int j = 0; j + 1 < M.T; ++j) s2 *= 2.0L / ((long double)M.omega[j] * M.delta[j]);
-  return (double)(s2 / ((long double)M.omega[M.T - 1] * M.delta[M.T - 1]));
-}
-
 lts_status mlts_solve(lts_ctx c, const DevLevel& lv, const Staged& st, const StagedDev& d, double width) {
-  const MltsDev& M = *lv.mlts;
+  MltsDev& M = *lv.mlts;
   const int n = st.n;
   const size_t sstride = lv.nodes;
   LTS_HIP(c, c->st0.ensure((size_t)n * sstride * 8));
   LTS_HIP(c, c->st1.ensure((size_t)n * sstride * 8));
   double* B[2] = {c->st0.as<double>(), c->st1.as<double>()};
   hipStream_t q = c->stream;
-  std::vector<double>& c0 = lv.mlts->c0_host;       // kept until the next solve: the copy is asynchronous
-  c0.resize(n);
-  for (int s = 0; s < n; ++s) c0[s] = innermost_c0(M, st.dt[s]);
-  LTS_HIP(c, lv.mlts->c0.ensure((size_t)n * 8));
-  LTS_HIP(c, hipMemcpyAsync(lv.mlts->c0.p, c0.data(), (size_t)n * 8, hipMemcpyHostToDevice, q));
+  M.c0_host.resize(n);
+  mlts_c0(M, st.dt.data(), n, M.c0_host.data());
+  LTS_HIP(c, M.c0.ensure((size_t)n * 8));
+  LTS_HIP(c, M.rec.ensure(mlts_record_size()));
+  std::vector<char> rec(mlts_record_size());
+  mlts_record(lv, d.kappa, M.c0.as<double>(), B[0], B[1], rec.data());
+  LTS_HIP(c, hipMemcpyAsync(M.c0.p, M.c0_host.data(), (size_t)n * 8, hipMemcpyHostToDevice, q));
+  LTS_HIP(c, hipMemcpyAsync(M.rec.p, rec.data(), rec.size(), hipMemcpyHostToDevice, q));
+  LTS_HIP(c, hipStreamSynchronize(q));               // the host copies may be released
   lts_status r = init_states(c, lv, n, d.x0, width, B[0], B[1]);
   if (r != LTS_OK) return r;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -330,41 +350,16 @@ lts_status mlts_solve(lts_ctx c, const DevLevel& lv, const Staged& st, const Sta
     e1 = c->ev_pool[1];
     LTS_HIP(c, hipEventRecord(e0, q));
   }
-  MltsArgs x{};
-  x.L = lv.view();
-  x.ent = M.tiling.ent.as<int4>();
-  x.tiles = M.tiling.tiles.as<int4>();
-  x.ptier = M.ptier.as<uint8_t>();
-  x.kappa = d.kappa;
-  x.c0 = M.c0.as<double>();
-  x.sstride = sstride;
-  x.n_fine = M.tiling.n_fine;
-  x.T = M.T;
-  x.K = M.K;
-  for (int j = 0; j < M.T; ++j) {
-    x.p[j] = M.p[j];
-    for (int m = 0; m < kMP; ++m) x.beta[j][m] = M.beta[j][m];
-  }
-  int act = n;
+  const std::vector<const MltsDev*> Mv = {&M};
+  std::vector<int> act = {n};
   int64_t launches = 0;
   const int maxT = st.nsteps[0];
   for (int t = 0; t < maxT; ++t) {
-    while (act > 0 && st.nsteps[act - 1] <= t) --act;
-    if ((r = launch_coarse(c, lv, M.tiling, d.kappa, d.coef, B[t & 1], B[(t + 1) & 1], sstride, act, t == 0, q)) !=
-        LTS_OK)
+    while (act[0] > 0 && st.nsteps[act[0] - 1] <= t) --act[0];
+    if ((r = launch_coarse(c, lv, M.tiling, d.kappa, d.coef, B[t & 1], B[(t + 1) & 1], sstride, act[0], t == 0,
+                           q)) != LTS_OK)
       return r;
-    if (x.n_fine > 0) {
-      x.Ucur = B[t & 1];
-      x.Uold = B[(t + 1) & 1];
-      x.active = act;
-      x.startup = t == 0;
-      const long long G = (long long)x.n_fine * act;
-      x.per_xcd = (int)((G + 7) / 8);
-      const dim3 g((unsigned)(8LL * x.per_xcd));
-      if (M.nt == 256) k_mlts<256><<<g, 256, 0, q>>>(x);
-      else if (M.nt == 512) k_mlts<512><<<g, 512, 0, q>>>(x);
-      else k_mlts<kFineThreads><<<g, kFineThreads, 0, q>>>(x);
-    }
+    if ((r = launch_mlts(c, M.rec.p, Mv, act, t, q)) != LTS_OK) return r;
     ++launches;
   }
   LTS_HIP(c, hipGetLastError());
@@ -385,6 +380,70 @@ lts_status mlts_solve(lts_ctx c, const DevLevel& lv, const Staged& st, const Sta
 }
 
 }  // namespace
+
+size_t mlts_record_size() { return sizeof(MltsJob); }
+
+void mlts_record(const DevLevel& lv, const double* d_kappa, const double* d_c0, double* B0, double* B1, void* out) {
+  const MltsDev& M = *lv.mlts;
+  MltsJob x{};
+  x.L = lv.view();
+  x.ent = M.tiling.ent.as<int4>();
+  x.tiles = M.tiling.tiles.as<int4>();
+  x.ptier = M.ptier.as<uint8_t>();
+  x.kappa = d_kappa;
+  x.c0 = d_c0;
+  x.B0 = B0;
+  x.B1 = B1;
+  x.sstride = lv.nodes;
+  x.n_fine = M.tiling.n_fine;
+  x.T = M.T;
+  x.K = M.K;
+  for (int j = 0; j < M.T; ++j) {
+    x.p[j] = M.p[j];
+    for (int m = 0; m < kMP; ++m) x.beta[j][m] = M.beta[j][m];
+  }
+  std::memcpy(out, &x, sizeof x);
+}
+
+// The innermost half-step coefficient for steps dt: c0 = sigma_T^2 / (omega_T
+// delta_T) with sigma_1 = dt, sigma_j+1^2 = sigma_j^2 2 / (omega_j delta_j).
+void mlts_c0(const MltsDev& M, const double* dt, int n, double* c0) {
+  long double f = 1.0L / ((long double)M.omega[M.T - 1] * M.delta[M.T - 1]);
+  for (int j = 0; j + 1 < M.T; ++j) f *= 2.0L / ((long double)M.omega[j] * M.delta[j]);
+  for (int s = 0; s < n; ++s) c0[s] = (double)((long double)dt[s] * dt[s] * f);
+}
+
+lts_status launch_mlts(lts_ctx c, const void* d_jobs, const std::vector<const MltsDev*>& M,
+                       const std::vector<int>& active, int step, hipStream_t stream) {
+  const int nj = (int)M.size();
+  if (nj > kMaxJobs) {
+    c->err = "too many jobs in one batch";
+    return LTS_ERR_ARG;
+  }
+  // one launch per workgroup size; within it the costliest workgroups first
+  for (int nt : {kFineThreads, 512, 256}) {
+    MltsLaunch m{};
+    m.jobs = static_cast<const MltsJob*>(d_jobs);
+    m.step = step;
+    int pos[kMaxJobs], n = 0;
+    for (int j = 0; j < nj; ++j)
+      if (M[j]->nt == nt && M[j]->tiling.n_fine > 0 && active[j] > 0) pos[n++] = j;
+    if (n == 0) continue;
+    std::stable_sort(pos, pos + n, [&](int a, int b) { return M[a]->max_region * M[a]->K > M[b]->max_region * M[b]->K; });
+    m.n_jobs = n;
+    m.chunk_off[0] = 0;
+    for (int q = 0; q < n; ++q) {
+      m.order[q] = pos[q];
+      m.wg_n[q] = M[pos[q]]->tiling.n_fine * active[pos[q]];
+      m.chunk_off[q + 1] = m.chunk_off[q] + (m.wg_n[q] + 7) / 8;
+    }
+    const dim3 g((unsigned)(8 * m.chunk_off[n]));
+    if (nt == 256) k_mlts<256><<<g, 256, 0, stream>>>(m);
+    else if (nt == 512) k_mlts<512><<<g, 512, 0, stream>>>(m);
+    else k_mlts<kFineThreads><<<g, kFineThreads, 0, stream>>>(m);
+  }
+  return LTS_OK;
+}
 
 }  // namespace lts
 

@@ -190,3 +190,36 @@ def test_mlmc_with_multi_level_lts(ctx):
     with pytest.raises(P.LtsError):                    # a level without tiers
         lid = ctx.add_rect_level(P.graded_L_rule(16, qoi=qb))
         ctx.mlmc([lid] + ids[1:], _rule(0.5), eps=eps, N_init=N_init, L_start=1, mlts=True)
+
+
+def test_batched_form_is_bit_identical(ctx):
+    """LTS_BATCH_MLTS: jobs of graded levels 0-2 (with the tiers) and of the
+    box-refined level with given three-stage tiers in shared launches, with and
+    without the graph, give the QoIs of lts_mlts_forward bit for bit; a level
+    without tiers is refused."""
+    jobs, singles = [], []
+    for l, b in enumerate(BASES):
+        lid = ctx.add_rect_level(P.graded_L_rule(b))
+        ctx.set_mlts(lid, PS)
+        s = P.gen_samples(0, l, 0, (24, 9, 5)[l], _rule(0.5), ctx.level_info(lid)["h"])
+        jobs.append((lid, s["kappa"], s["x0"], s["n_steps"], s["dt"], 0.05))
+        singles.append(ctx.mlts_forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"]))
+    lv = mesh.box_refined_level(32, box=(0.4375, 0.5625))
+    mx = 0.5 * (lv.xs[:-1] + lv.xs[1:])
+    MX, MY = np.meshgrid(mx, mx)
+    ct = np.where(lv.cell_active & lv.cell_fine, np.where((abs(MX - 0.5) < 0.03) & (abs(MY - 0.5) < 0.03), 2, 1),
+                  0).astype(np.uint8)
+    lid = ctx.add_rect_level(P.box_rule(32, box=(0.4375, 0.5625)))
+    ctx.set_mlts(lid, [3, 2], ct)
+    s = P.gen_samples(0, 0, 0, 7, P.sample_rule(T=0.5), lv.h)
+    jobs.append((lid, s["kappa"], s["x0"], s["n_steps"], s["dt"], 0.05))
+    singles.append(ctx.mlts_forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"]))
+    want = np.concatenate(singles)
+    for graph in (False, True, True):                 # the second graph run replays the cached graph
+        q = ctx.batch_run(jobs, graph=graph, mlts=True)
+        assert np.array_equal(q, want)
+    plain = ctx.add_rect_level(P.graded_L_rule(32))
+    with pytest.raises(P.LtsError):
+        ctx.batch_run([(plain,) + jobs[0][1:]], mlts=True)
+    with pytest.raises(P.LtsError):
+        ctx.batch_run(jobs[:1], mlts=True, precision=P.LTS_FP32_STEP)
