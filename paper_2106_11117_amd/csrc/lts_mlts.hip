@@ -33,6 +33,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "ctx.h"
@@ -74,6 +75,48 @@ struct MltsLaunch {
   int order[kMaxJobs], wg_n[kMaxJobs], chunk_off[kMaxJobs + 1];
 };
 
+// A pointer field of a job record loaded as a global-address-space pointer, so
+// that the accesses through it stay global loads (a plain copy out of device
+// memory would be addressed as a flat pointer).
+#define MLTS_GPTR(f) \
+  ((decltype(+(f)))(*(__attribute__((address_space(1))) std::remove_pointer_t<decltype(+(f))>* const*)(&(f))))
+
+// What a workgroup uses of its job's record, in registers.
+struct MltsView {
+  LevelView L;
+  const int4* ent;
+  const int4* tiles;
+  const uint8_t* ptier;
+  const double* kappa;
+  const double* c0;
+  double* B0;
+  double* B1;
+  size_t sstride;
+  int n_fine, T, K;
+  int p[kMT];
+  const double* beta;                 // beta_m of tier j at beta[j * kMP + m] (the workgroup's LDS copy)
+};
+
+__device__ __forceinline__ MltsView job_view(const MltsJob& x) {
+  MltsView v;
+  v.L.nxn = x.L.nxn; v.L.nyn = x.L.nyn; v.L.ld = x.L.ld; v.L.p = x.L.p; v.L.nb = x.L.nb;
+  v.L.hx = MLTS_GPTR(x.L.hx); v.L.hy = MLTS_GPTR(x.L.hy);
+  v.L.inv2hx = MLTS_GPTR(x.L.inv2hx); v.L.inv2hy = MLTS_GPTR(x.L.inv2hy);
+  v.L.x = MLTS_GPTR(x.L.x); v.L.y = MLTS_GPTR(x.L.y);
+  v.L.cblk = MLTS_GPTR(x.L.cblk); v.L.flags = MLTS_GPTR(x.L.flags); v.L.ninfo = MLTS_GPTR(x.L.ninfo);
+  v.L.invm = MLTS_GPTR(x.L.invm); v.L.qoiw = MLTS_GPTR(x.L.qoiw);
+  v.L.beta = MLTS_GPTR(x.L.beta); v.L.beta_half = MLTS_GPTR(x.L.beta_half);
+  v.ent = MLTS_GPTR(x.ent); v.tiles = MLTS_GPTR(x.tiles); v.ptier = MLTS_GPTR(x.ptier);
+  v.kappa = MLTS_GPTR(x.kappa); v.c0 = MLTS_GPTR(x.c0);
+  v.B0 = MLTS_GPTR(x.B0); v.B1 = MLTS_GPTR(x.B1);
+  v.sstride = x.sstride;
+  v.n_fine = x.n_fine; v.T = x.T; v.K = x.K;
+#pragma unroll
+  for (int j = 0; j < kMT; ++j) v.p[j] = x.p[j];
+  v.beta = &x.beta[0][0];
+  return v;
+}
+
 // The state of a lane's region nodes.
 struct MLane {
   double F[kMT][kMNPT], e[kMT][kMNPT], ep[kMT][kMNPT];
@@ -84,7 +127,7 @@ struct MLane {
 
 // Tier J over the force S.F[J]: leaves its increment in S.e[J].
 template <int NT, int J>
-__device__ __forceinline__ void tier_run(const MltsJob& x, MLane& S, double* __restrict__ lq, int& ph,
+__device__ __forceinline__ void tier_run(const MltsView& x, MLane& S, double* __restrict__ lq, int& ph,
                                          int& reach, double c0, int tid) {
   constexpr int kCap = NT * kMNPT;
   const int p = x.p[J];
@@ -132,7 +175,7 @@ __device__ __forceinline__ void tier_run(const MltsJob& x, MLane& S, double* __r
 #pragma unroll
       for (int r = 0; r < kMNPT; ++r) Phi[r] = -c0 * Phi[r];
     }
-    const double b = x.beta[J][m];
+    const double b = x.beta[J * kMP + m];
 #pragma unroll
     for (int r = 0; r < kMNPT; ++r) {
       const double en = (1.0 + b) * (S.e[J][r] + Phi[r]) - b * S.ep[J][r];
@@ -163,9 +206,12 @@ __global__ __launch_bounds__(NT) void k_mlts(MltsLaunch m) {
   constexpr int kCap = NT * kMNPT;
   __shared__ double lq[2 * (kCap + 1)];
   __shared__ double lk[256];
+  __shared__ double lbeta[kMT * kMP];
   int jb, local;
   if (!mlts_slot(m, jb, local)) return;
-  const MltsJob& x = m.jobs[jb];
+  MltsView x = job_view(m.jobs[jb]);
+  for (int t = (int)threadIdx.x; t < kMT * kMP; t += NT) lbeta[t] = x.beta[t];
+  x.beta = lbeta;
   const int s = local / x.n_fine, tile = local - s * x.n_fine;
   const LevelView& L = x.L;
   const int tid = (int)threadIdx.x;
