@@ -166,7 +166,8 @@ typedef struct {
   double h, nu;
   double delta, omega;            /* stabilized Chebyshev constants (Sec. 3.3) */
   int32_t tile_x, tile_y;         /* fine-tile shape in use (grid nodes; 0, 0: adaptive) */
-  int32_t tile_rect, tuned;       /* rectangular LDS region; chosen by the autotuner */
+  int32_t tile_rect, tuned;       /* rectangular LDS region (2: coarse and fine in one launch);
+                                     chosen by the autotuner */
   double halo_ratio;              /* nodes of all fine-tile regions / |F+| */
   double tuned_ms;                /* measured step time per sample of the tuned tiling */
 } lts_level_info;
@@ -531,7 +532,9 @@ lts_status lts_autotune(lts_ctx ctx, int32_t level);
  * indices), with the tile-grid origin chosen to minimise region overhead.
  * tile_x = tile_y = 0 with rect = 0 selects the adaptive compact tiling: the
  * F+ set is bisected recursively until each part's region fits a workgroup
- * (long tiles along thin bands of F+).
+ * (long tiles along thin bands of F+).  rect = 2: rect mode with the coarse
+ * items and the fine tiles of a step in one launch (the autotuner times this
+ * form for its rect-mode winner; lts_level_info reports tile_rect = 2 then).
  * Later solves use it and lts_batch_run does not re-tune the level (a later
  * lts_autotune does).  A tiling decides which workgroup updates a node, not
  * the arithmetic applied to it.  Errors: LTS_ERR_ARG (no such

@@ -349,9 +349,10 @@ class Context:
         self._c(self.lib.lts_autotune(self.h, level))
         return self.level_info(level)
 
-    def set_tiling(self, level, tile_x, tile_y, rect=True):
-        """Pin the fine-tile shape and mode of a level (see lts_set_tiling)."""
-        self._c(self.lib.lts_set_tiling(self.h, level, tile_x, tile_y, 1 if rect else 0))
+    def set_tiling(self, level, tile_x, tile_y, rect=True, mix=False):
+        """Pin the fine-tile shape and mode of a level (see lts_set_tiling);
+        mix=True (rect mode): coarse items and fine tiles in one launch."""
+        self._c(self.lib.lts_set_tiling(self.h, level, tile_x, tile_y, (2 if mix else 1) if rect else 0))
         return self.level_info(level)
 
     def level_info(self, level) -> dict:

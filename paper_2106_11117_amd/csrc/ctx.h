@@ -54,6 +54,7 @@ struct TilingDev {
   double halo_ratio = 1.0;
   double wg_work = 0.0;  // mean region nodes x substeps of one fine workgroup
   int nt = kFineThreads; // compact mode: threads of a fine workgroup
+  bool mix = false;     // rect mode: coarse items and fine tiles in one launch (k_step_mix)
   uint64_t gen = 0;     // distinct for every upload (keys captured graphs)
   DevBuf ent, tiles, rtiles, citems;
 };

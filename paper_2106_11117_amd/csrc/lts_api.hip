@@ -454,7 +454,7 @@ lts_status lts_level_info_get(lts_ctx c, int32_t level, lts_level_info* out) {
   out->omega = H.omega;
   out->tile_x = lv->tiling.TX;
   out->tile_y = lv->tiling.TY;
-  out->tile_rect = lv->tiling.rect ? 1 : 0;
+  out->tile_rect = lv->tiling.rect ? (lv->tiling.mix ? 2 : 1) : 0;
   out->tuned = lv->tuned ? 1 : 0;
   out->halo_ratio = lv->tiling.halo_ratio;
   out->tuned_ms = lv->tuned_ms;

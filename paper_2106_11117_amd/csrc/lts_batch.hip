@@ -30,7 +30,7 @@ uint64_t shape_key(const HostLevel& H) {
 
 struct TuneChoice {
   int TX, TY, ox, oy;
-  bool rect;
+  bool rect, mix;
   double ms;
 };
 
@@ -63,6 +63,7 @@ lts_status autotune_level(lts_ctx c, DevLevel& lv) {
     if (build_tiling(lv.H, lv.ld, t.TX, t.TY, t.ox, t.oy, t.rect, T).empty()) {
       lts_status r = upload_tiling(c, T, lv.tiling);
       if (r != LTS_OK) return r;
+      lv.tiling.mix = t.mix;
       lv.tuned = true;
       lv.tuned_ms = t.ms;
       return LTS_OK;
@@ -124,10 +125,16 @@ lts_status autotune_level(lts_ctx c, DevLevel& lv) {
   LTS_HIP(c, hipEventCreate(&e1));
   double best = 1e300;
   int bi = 0;
+  bool best_mix = false;
   TilingDev Td;
-  for (size_t ci = 0; ci < cands.size(); ++ci) {
-    lts_status r = upload_tiling(c, cands[ci], Td);
+  // each candidate with separate coarse and fine launches; the winner, if in
+  // rect mode, also with both in one launch (k_step_mix)
+  for (size_t ci = 0; ci <= cands.size(); ++ci) {
+    const bool mix = ci == cands.size();
+    if (mix && !cands[bi].rect) break;
+    lts_status r = upload_tiling(c, cands[mix ? bi : ci], Td);
     if (r != LTS_OK) return r;
+    Td.mix = mix;
     if ((r = init_states(c, lv, S, c->x0.as<double>(), 0.05, B[0], B[1])) != LTS_OK) return r;
     constexpr int kWarm = 2, kTimed = 6;
     for (int t = 0; t < kWarm + kTimed; ++t) {
@@ -142,7 +149,8 @@ lts_status autotune_level(lts_ctx c, DevLevel& lv) {
     LTS_HIP(c, hipEventElapsedTime(&ms, e0, e1));
     if (ms < best) {
       best = ms;
-      bi = (int)ci;
+      if (mix) best_mix = true;
+      else bi = (int)ci;
     }
   }
   (void)hipEventDestroy(e0);
@@ -151,9 +159,10 @@ lts_status autotune_level(lts_ctx c, DevLevel& lv) {
   const TilingHost& W = cands[bi];
   lts_status r = upload_tiling(c, W, lv.tiling);
   if (r != LTS_OK) return r;
+  lv.tiling.mix = best_mix;
   lv.tuned = true;
   lv.tuned_ms = best / 6.0 / S;
-  tune_cache()[key] = TuneChoice{W.TX, W.TY, W.ox, W.oy, W.rect, lv.tuned_ms};
+  tune_cache()[key] = TuneChoice{W.TX, W.TY, W.ox, W.oy, W.rect, best_mix, lv.tuned_ms};
   return LTS_OK;
 }
 
@@ -176,14 +185,14 @@ extern "C" lts_status lts_set_tiling(lts_ctx c, int32_t level, int32_t tile_x, i
   const bool adaptive = tile_x == 0 && tile_y == 0 && rect == 0;
   if (!adaptive && (tile_x < 1 || tile_y < 1 || tile_x > 4096 || tile_y > 4096))
     return arg_fail(c, "tile size out of range");
-  if (rect != 0 && rect != 1) return arg_fail(c, "rect must be 0 or 1");
+  if (rect < 0 || rect > 2) return arg_fail(c, "rect must be 0, 1 or 2");
   DevLevel& lv = *c->levels[level];
   TilingHost best;
   bool have = false;
   std::string why;
   for (auto& org : tile_origins(lv.H, tile_x, tile_y)) {
     TilingHost T;
-    std::string e = build_tiling(lv.H, lv.ld, tile_x, tile_y, org.first, org.second, rect == 1, T);
+    std::string e = build_tiling(lv.H, lv.ld, tile_x, tile_y, org.first, org.second, rect >= 1, T);
     if (!e.empty()) {
       why = e;
       continue;
@@ -197,6 +206,7 @@ extern "C" lts_status lts_set_tiling(lts_ctx c, int32_t level, int32_t tile_x, i
   LTS_HIP(c, hipSetDevice(c->device));
   lts_status r = upload_tiling(c, best, lv.tiling);
   if (r != LTS_OK) return r;
+  lv.tiling.mix = rect == 2;
   lv.tuned = false;
   lv.pinned = true;
   lv.tuned_ms = 0.0;

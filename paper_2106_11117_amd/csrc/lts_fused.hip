@@ -823,6 +823,38 @@ __global__ __launch_bounds__(kFineThreads) void k_fine(StepArgs a) {
   }
 }
 
+// Coarse items and rect-mode fine tiles of one step in one launch of
+// 1024-thread workgroups: n_fw fine workgroups (tile, sample) and n_cw coarse
+// workgroups of four items each, interleaved evenly over the launch order, so
+// that the coarse items' HBM stream runs while other CUs do the fine tiles'
+// substeps (back to back, the coarse launch leaves the VALUs idle and the fine
+// launch leaves HBM idle).  Each XCD takes a contiguous part of the order, as
+// in the separate launches.
+template <class T>
+__global__ __launch_bounds__(kFineThreads) void k_step_mix(StepArgs a, int n_fw, int n_cw) {
+  __shared__ T lq[kLdsSlots];
+  __shared__ T ls[4 * kFineThreads];
+  __shared__ double lk[4 * 256];
+  const int N = n_fw + n_cw;
+  const int Lid = (int)(blockIdx.x & 7) * a.per_xcd + (int)(blockIdx.x >> 3);
+  if (Lid >= N) return;
+  const long long c0 = (long long)Lid * n_cw / N, c1 = (long long)(Lid + 1) * n_cw / N;
+  const StepState st{a.Ucur, a.Uold, a.Unew, a.startup};
+  const int tid = (int)threadIdx.x;
+  if (c1 > c0) {
+    // coarse workgroup c0: slots 4 c0 .. 4 c0 + 3 of the (item, sample) order
+    const int gi = __builtin_amdgcn_readfirstlane(tid >> 8), slot = 4 * (int)c0 + gi;   // whole wavefronts
+    const bool on = slot < a.n_coarse * a.active;
+    int item = 0, s = 0;
+    if (on) coarse_order(slot, a.n_coarse, a.active, item, s);
+    coarse_body<T>(a, st, lk + 256 * gi, a.s0 + s, item, tid & 255, on);
+  } else {
+    const int f = Lid - (int)c0;                       // fine workgroup: sample-major (sample, tile)
+    const int s = f / a.n_fine;
+    fine_tile_rect<T>(a, st, lk, lq, ls, a.s0 + s, f - s * a.n_fine);
+  }
+}
+
 // Compact tiles whose regions fit NT * kNPT < kRegionCap nodes: smaller
 // workgroups, several per CU.
 template <class T, int NT>
@@ -1397,6 +1429,7 @@ lts_status upload_tiling(lts_ctx c, const TilingHost& T, TilingDev& D) {
   D.wg_work = T.wg_work;
   D.nt = T.nt;
   D.rect = T.rect;
+  D.mix = false;
   D.pitch = T.pitch;
   static uint64_t gen_counter = 0;
   D.gen = ++gen_counter;
@@ -1494,6 +1527,17 @@ lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const 
   a.sstride = sstride;
   a.startup = startup;
   a.s0 = s0;
+  if (T.mix && T.rect && T.n_fine > 0) {
+    // coarse items and fine tiles in one launch
+    const int n_fw = T.n_fine * active, n_cw = (T.n_coarse * active + 3) / 4;
+    a.per_xcd = (n_fw + n_cw + 7) / 8;
+    const dim3 grid((unsigned)(8LL * a.per_xcd));
+    if (fp32)
+      k_step_mix<float><<<grid, dim3(kFineThreads), 0, stream>>>(a, n_fw, n_cw);
+    else
+      k_step_mix<double><<<grid, dim3(kFineThreads), 0, stream>>>(a, n_fw, n_cw);
+    return LTS_OK;
+  }
   if (T.n_coarse > 0) {
     const long long G = (long long)T.n_coarse * active;
     a.per_xcd = (int)((G + 7) / 8);

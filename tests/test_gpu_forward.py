@@ -269,6 +269,17 @@ def test_fine_tile_modes_and_shapes(ctx, graded):
         if ref is None:
             ref = q
         assert np.array_equal(q, ref), (tx, ty)
+    # coarse items and fine tiles in one launch: the same per-node arithmetic
+    ctx.set_tiling(lid, *shapes[0], True)
+    q32 = ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"], precision=P.LTS_FP32_STEP)
+    _, g = ctx.backward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"], np.ones(len(ref)), K=7)
+    assert ctx.set_tiling(lid, *shapes[0], True, mix=True)["tile_rect"] == 2
+    assert np.array_equal(ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"]), ref)
+    assert np.array_equal(ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"], plain=True), ref)
+    assert np.array_equal(ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"], precision=P.LTS_FP32_STEP),
+                          q32)
+    _, gm = ctx.backward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"], np.ones(len(ref)), K=7)
+    assert np.array_equal(gm, g)
     ctx.set_tiling(lid, *shapes[0], False)
     qc = ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"])
     for k in range(len(qc)):
