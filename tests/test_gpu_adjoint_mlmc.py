@@ -180,17 +180,36 @@ def test_autograd_function(ctx):
     assert torch.equal(g.grad, gref)
 
 
-def test_adjoint_c1_full_size_vs_finite_differences(ctx):
+def test_adjoint_c1_full_size_vs_oracle_and_finite_differences(ctx):
     """Full-size adjoint on the 512-base, 8x refined mesh (442,225 DOFs, p = 8,
-    checkpoints every 64 steps): dQ/dg of samples 0..3 against central differences
-    of the forward QoI (step 1e-6 in each of the 16 block values, n_steps and dt
-    held fixed: 128 forward solves in one batch), to 1e-5 of the largest entry."""
+    checkpoints every 64 steps), samples 0..3:
+    - Q and dQ/dg against the oracle's discrete adjoint on the same mesh and
+      samples (tests/golden/c1_adjoint.json, written by
+      tests/golden/make_c1_adjoint_golden.py, which calls only the oracle), to
+      1e-10 of the largest entry;
+    - dQ/dg against central differences of the forward QoI (step 1e-6 in each
+      of the 16 block values, n_steps and dt held fixed: 128 forward solves in
+      one batch), to 1e-5 of the largest entry."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c1_adjoint.json")))
     lid = ctx.add_rect_level(P.box_rule(512, box=(0.48, 0.52), ref=8))
     rule = P.sample_rule()
     s = P.gen_samples(0, 0, 0, 4, rule, 1 / 512)
     q, g = ctx.backward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"], np.ones(4), K=64)
     qf = ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"])
     assert np.array_equal(q, qf)
+    assert gold["K"] == 64
+    worst_o = 0.0
+    for ref in gold["samples"]:
+        k = ref["i"]
+        assert ref["n_steps"] == int(s["n_steps"][k]) and ref["dt"] == float(s["dt"][k])
+        go = np.asarray(ref["dQ_dg"])
+        e = np.max(np.abs(g[k] - go)) / np.max(np.abs(go))
+        worst_o = max(worst_o, e)
+        assert e <= 1e-10, (k, e)
+        assert abs(q[k] - ref["Q"]) <= 1e-10 * abs(ref["Q"]), (k, q[k], ref["Q"])
+    print(f"C1 adjoint vs the oracle's adjoint: worst relative error {worst_o:.3g}")
     eps = 1e-6
     gl = np.log(s["kappa"]) / 2
     kp, x0, ns, dt = [], [], [], []

@@ -223,3 +223,29 @@ def test_batched_form_is_bit_identical(ctx):
         ctx.batch_run([(plain,) + jobs[0][1:]], mlts=True)
     with pytest.raises(P.LtsError):
         ctx.batch_run(jobs[:1], mlts=True, precision=P.LTS_FP32_STEP)
+
+
+def test_graded_levels_3_4_at_T2_in_the_bench_configuration(ctx):
+    """The two finest graded levels (53,333 and 204,885 DOFs, 7 and 12 fine
+    tiles of up to 2,048 region nodes) in the launch configuration bench.py
+    --mlts times (64 and 16 samples in one call), first and last sample
+    against stored oracle values (tests/golden/mlts_gradedL_qoi.json, written
+    by tests/golden/make_mlts_golden.py, which calls only the oracle)."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "mlts_gradedL_qoi.json")))
+    assert gold["tiers"] == PS
+    bases, batch = {3: 256, 4: 512}, {3: 64, 4: 16}
+    for l in (3, 4):
+        lid = ctx.add_rect_level(P.graded_L_rule(bases[l]))
+        info = ctx.set_mlts(lid, PS)
+        assert info["n_tiles"] == (7 if l == 3 else 12)
+        s = P.gen_samples(0, l, 0, batch[l], _rule(), ctx.level_info(lid)["h"])
+        print(f"level {l}: {batch[l]} samples", flush=True)
+        q = ctx.mlts_forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"])
+        refs = [r for r in gold["samples"] if r["level"] == l]
+        assert len(refs) == 2
+        for ref in refs:
+            i = ref["i"]
+            assert ref["n_steps"] == int(s["n_steps"][i])
+            _check(q[i], ref)
