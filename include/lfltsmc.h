@@ -435,6 +435,8 @@ typedef struct {
   int32_t n_tiers;                        /* 1..LTS_MLTS_MAX_TIERS */
   int32_t p[LTS_MLTS_MAX_TIERS];          /* p_1 .. p_n_tiers, each 1..LTS_MLTS_MAX_P */
   const uint8_t* cell_tier;               /* caller-owned, copied; or NULL */
+  int32_t max_region;                     /* largest fine-tile region: 512, 1024 or 2048 nodes (workgroups
+                                             of 256, 512 or 1024 threads); 0 selects 2048 */
 } lts_mlts_desc;
 
 typedef struct {

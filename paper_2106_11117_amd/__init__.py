@@ -191,12 +191,14 @@ def mesh_host(m) -> dict:
     return d
 
 
-def _mlts_desc(ps, cell_tier):
-    """lts_mlts_desc for ratios ps (tier 1 first) and cell tiers [ny_cells, nx_cells]
-    (uint8) or None (the halving rule); returns (desc, keep-alive array)."""
+def _mlts_desc(ps, cell_tier, max_region=0):
+    """lts_mlts_desc for ratios ps (tier 1 first), cell tiers [ny_cells, nx_cells]
+    (uint8) or None (the halving rule) and the region cap (0: 2048); returns
+    (desc, keep-alive array)."""
     ps = [int(v) for v in ps]
     d = _lib.MltsDesc()
     d.n_tiers = len(ps)
+    d.max_region = int(max_region)
     for j, v in enumerate(ps[:_lib.LTS_MLTS_MAX_TIERS]):
         d.p[j] = v
     ct = None
@@ -213,12 +215,12 @@ def _mlts_dict(info) -> dict:
             "halo_ratio": info.halo_ratio, "updates_per_step": info.updates_per_step}
 
 
-def mlts_host(rule, ps, cell_tier=None) -> dict:
+def mlts_host(rule, ps, cell_tier=None, max_region=0) -> dict:
     """Host only: the tiers lts_set_mlts would attach to the level of `rule`,
     with node_tier [ny_nodes, nx_nodes] (largest j with the node in P_j)."""
     lib = _lib.load()
     lv = rect_level_host(rule)
-    d, keep = _mlts_desc(ps, cell_tier)
+    d, keep = _mlts_desc(ps, cell_tier, max_region)
     info = _lib.MltsInfo()
     nt = np.zeros((lv["ny_nodes"], lv["nx_nodes"]), dtype=np.uint8)
     _check(lib.lts_mlts_host(C.byref(rule), C.byref(d), C.byref(info), nt.ctypes.data_as(C.POINTER(C.c_uint8))))
@@ -536,11 +538,12 @@ class Context:
         return qf, qc, dq
 
     # --- multi-level LTS ------------------------------------------------------
-    def set_mlts(self, level, ps, cell_tier=None) -> dict:
+    def set_mlts(self, level, ps, cell_tier=None, max_region=0) -> dict:
         """Attach tiers with ratios ps (tier 1 first) to a rectilinear level;
-        cell_tier [ny_cells, nx_cells] or None for the halving rule.  Returns
+        cell_tier [ny_cells, nx_cells] or None for the halving rule; max_region
+        the fine-tile region cap (512, 1024, 2048; 0: 2048).  Returns
         lts_mlts_info as a dict."""
-        d, keep = _mlts_desc(ps, cell_tier)
+        d, keep = _mlts_desc(ps, cell_tier, max_region)
         self._c(self.lib.lts_set_mlts(self.h, level, C.byref(d)))
         return self.mlts_info(level)
 

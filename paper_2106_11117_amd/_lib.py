@@ -95,7 +95,8 @@ class MeshInfo(C.Structure):
 
 
 class MltsDesc(C.Structure):
-    _fields_ = [("n_tiers", C.c_int32), ("p", C.c_int32 * LTS_MLTS_MAX_TIERS), ("cell_tier", C.c_void_p)]
+    _fields_ = [("n_tiers", C.c_int32), ("p", C.c_int32 * LTS_MLTS_MAX_TIERS), ("cell_tier", C.c_void_p),
+                ("max_region", C.c_int32)]
 
 
 class MltsInfo(C.Structure):

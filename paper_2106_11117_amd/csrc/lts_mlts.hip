@@ -340,9 +340,11 @@ std::string build_mlts(const HostLevel& H, int ld, const lts_mlts_desc& d, MltsH
     cheb_constants(M.p[j], H.nu, M.delta[j], M.omega[j], b, bh);
     for (int m = 1; m < M.p[j]; ++m) M.beta[j][m] = b[m];
   }
+  const int cap = d.max_region == 0 ? kMCap : d.max_region;
+  if (cap != 512 && cap != 1024 && cap != kMCap) return "max_region must be 0, 512, 1024 or 2048";
   HostLevel Hr = H;
   Hr.p = std::max(M.K, 1);
-  std::string e = build_tiling(Hr, ld, 0, 0, 0, 0, false, M.tiling, kMCap);
+  std::string e = build_tiling(Hr, ld, 0, 0, 0, 0, false, M.tiling, cap);
   if (!e.empty()) return e;
   for (const int4& t : M.tiling.tiles) M.max_region = std::max(M.max_region, t.y);
   M.nt = M.max_region <= 256 * kMNPT ? 256 : M.max_region <= 512 * kMNPT ? 512 : kFineThreads;

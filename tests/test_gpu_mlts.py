@@ -104,6 +104,9 @@ def test_given_tiers_with_three_stages(ctx):
     T = 1.0
     s = P.gen_samples(0, 0, 0, 5, P.sample_rule(T=T), lv.h)
     q = ctx.mlts_forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"])
+    # smaller tiles on 256-thread workgroups: a tiling only decides which workgroup updates a node
+    assert ctx.set_mlts(lid, ps, ct, max_region=512)["threads"] == 256
+    assert np.array_equal(ctx.mlts_forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"]), q)
     ops = fem.operators(lv)
     Ps = mlts.tier_projectors(lv, ct, 2)
     rule = rng.SampleRule(T=T)

@@ -52,6 +52,15 @@ def test_given_cell_tiers_match_oracle():
     assert 0 < h["n_P"][1] < h["n_P"][0]
 
 
+def test_region_cap():
+    """Smaller region caps give more, smaller tiles on smaller workgroups."""
+    rule = P.box_rule(32, box=(0.4375, 0.5625))
+    big = P.mlts_host(rule, [2, 2])
+    small = P.mlts_host(rule, [2, 2], max_region=512)
+    assert small["max_region"] <= 512 and small["threads"] == 256
+    assert small["n_tiles"] > big["n_tiles"] and np.array_equal(small["node_tier"], big["node_tier"])
+
+
 def test_rejected_descriptions():
     rule = P.graded_L_rule(32)
     with pytest.raises(P.LtsError):
@@ -62,6 +71,10 @@ def test_rejected_descriptions():
         P.mlts_host(rule, [2, 17])
     with pytest.raises(P.LtsError):
         P.mlts_host(P.graded_L_rule(512), [16, 16, 16])   # regions of radius 4095 do not fit
+    with pytest.raises(P.LtsError):
+        P.mlts_host(rule, [2, 2], max_region=300)
+    with pytest.raises(P.LtsError):                       # radius 31 at the band crossing: above 1024 nodes
+        P.mlts_host(P.graded_L_rule(128), [2] * 5, max_region=1024)
     lv = mesh.graded_L_level(32)
     ct = mlts.tiers_by_leg(lv, 2).astype(np.uint8)
     bad = ct.copy()
