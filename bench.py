@@ -16,9 +16,10 @@ Prints one JSON line (see the repository's benchmark contract).  After the
 timed throughput run the same line also carries, measured outside the timed
 region, the rest of the metric on the graded L-shape hierarchy (5 levels,
 p = 64, T = 2): Algorithm 1 at eps = 1e-4, batched + graph against the plain
-one-launch-per-sample form at identical N_l ("mlmc_graded_L"), and the batched
-multi-level throughput with N_l = 4096, 1024, 256, 64, 16 ("batch_graded_L").
---no-extra leaves them out.
+one-launch-per-sample form at identical N_l ("mlmc_graded_L"), the batched
+multi-level throughput with N_l = 4096, 1024, 256, 64, 16 ("batch_graded_L"),
+and Algorithm 1 at eps = 1e-4 with multi-level LTS against single-tier LTS,
+both batched + graph ("mlts_mlmc_graded_L").  --no-extra leaves them out.
 
 Other modes (one JSON line each): --mlmc (Algorithm 1, batched + graph against
 the plain form and the CPU oracle), --batch [--plain] (all five graded L-shape
@@ -352,7 +353,7 @@ def adjoint_graded_bench(K: int = 64):
     ctx.close()
 
 
-def mlts_bench(T: float = 2.0):
+def mlts_bench(T: float = 2.0, per_level: bool = True, eps_list=MLMC_EPS, emit: bool = True):
     """Multi-level LTS (lts_mlts_forward: five tiers by halving legs, p_j = 2)
     against the single-tier LTS solve (lts_forward, p = 64, autotuned tiling)
     on the graded L-shape levels 2-4 at the workload's horizon T = 2, the same
@@ -372,7 +373,7 @@ def mlts_bench(T: float = 2.0):
     out = {"metric": "multi-level LTS vs single-tier LTS wall time, graded L-shape (T = 2)",
            "unit": "s", "higher_is_better": False, "data": "synthetic (Philox seed 0)", "dtype": "f64",
            "tiers": [2, 2, 2, 2, 2], "runs": []}
-    for lev, nb, S in ((2, 128, 64), (3, 256, 64), (4, 512, 16)):
+    for lev, nb, S in ((2, 128, 64), (3, 256, 64), (4, 512, 16)) if per_level else ():
         lid = ctx.add_rect_level(P.graded_L_rule(nb))
         ctx.autotune(lid)
         info = ctx.level_info(lid)
@@ -411,7 +412,7 @@ def mlts_bench(T: float = 2.0):
         ctx.set_mlts(lid, [2, 2, 2, 2, 2])
         ids.append(lid)
     out["mlmc"] = []
-    for eps in MLMC_EPS:
+    for eps in eps_list:
         t0 = time.perf_counter()
         rl = ctx.mlmc(ids, rule, eps=eps, N_init=MLMC_N_INIT, L_start=2)
         wl = time.perf_counter() - t0
@@ -425,8 +426,10 @@ def mlts_bench(T: float = 2.0):
                     "cost_model": float(sum(n * c for n, c in zip(rl["N"], rl["cost"])))},
             "mlts": {"s": wm, "L": rm["L"], "N": rm["N"], "estimate": rm["estimate"], "rmse": rm["rmse"],
                      "cost_model": float(sum(n * c for n, c in zip(rm["N"], rm["cost"])))}})
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
     ctx.close()
+    return out
 
 
 BATCH_N = (4096, 1024, 256, 64, 16)       # samples per level of the multi-level throughput run
@@ -816,11 +819,13 @@ def main():
     ctx.close()
     if not args.no_extra:
         # the rest of the metric, outside the timed region above: MLMC wall time at
-        # fixed RMSE (batched + graph against the plain form, identical N_l) and the
-        # batched multi-level throughput, both on the graded L-shape hierarchy
+        # fixed RMSE (batched + graph against the plain form, identical N_l), the
+        # batched multi-level throughput and MLMC with multi-level LTS, all on the
+        # graded L-shape hierarchy
         t0 = time.perf_counter()
         mb = mlmc_bench(True, (1e-4,), emit=False)
         bb = batch_bench(False, fp32=False, emit=False)
+        ml = mlts_bench(per_level=False, eps_list=(1e-4,), emit=False)["mlmc"][0]
         r = mb["runs"][0]
         out["mlmc_graded_L"] = {k: r[k] for k in ("eps", "batched_graph_s", "plain_s", "speedup_vs_plain", "L",
                                                   "N", "estimate", "rmse", "converged")}
@@ -832,6 +837,11 @@ def main():
                                  "hbm_frac_algorithmic": bb["batched_graph"]["hbm_frac_algorithmic"],
                                  "one_forward_per_level_s": bb["one_forward_per_level"]["s"],
                                  "q_equal": bb["q_equal"]}
+        out["mlts_mlmc_graded_L"] = {"eps": ml["eps"], "tiers": [2, 2, 2, 2, 2],
+                                     "single_tier_s": ml["lts"]["s"], "multi_level_s": ml["mlts"]["s"],
+                                     "speedup": ml["lts"]["s"] / ml["mlts"]["s"],
+                                     "N_single_tier": ml["lts"]["N"], "N_multi_level": ml["mlts"]["N"],
+                                     "cost_model_ratio": ml["lts"]["cost_model"] / ml["mlts"]["cost_model"]}
         out["extra_wall_s"] = time.perf_counter() - t0
     print(json.dumps(out), flush=True)
 
