@@ -139,6 +139,13 @@ def test_device_pointers_g_and_errors(ctx):
         P._check(ctx.lib.lts_mlts_forward(ctx.h, lid, None, P.LTS_FP32_STEP, None), ctx.h)
     with pytest.raises(P.LtsError):
         ctx.mlts_info(99)
+    # a level without fine cells (the leapfrog twin): no fine tiles, the coarse sweep alone
+    tw = ctx.add_rect_level(P.lf_rule(P.graded_L_rule(32)))
+    info = ctx.set_mlts(tw, [1])
+    assert info["n_tiles"] == 0 and info["n_P"] == [0]
+    st = P.gen_samples(0, 0, 0, 3, _rule(0.5), ctx.level_info(tw)["h"])
+    assert np.array_equal(ctx.mlts_forward(tw, st["kappa"], st["x0"], st["n_steps"], st["dt"]),
+                          ctx.forward(tw, st["kappa"], st["x0"], st["n_steps"], st["dt"]))
 
 
 def test_mlmc_with_multi_level_lts(ctx):
