@@ -598,8 +598,9 @@ typedef struct {
                                      multi-level LTS (batched: lts_batch_run with
                                      LTS_BATCH_MLTS | LTS_BATCH_GRAPH; plain: lts_mlts_forward
                                      level by level), the cost model counting the multi-level
-                                     updates ceil(T/(cfl h)) x updates_per_step (no generated
-                                     levels, no gradient) */
+                                     updates ceil(T/(cfl h)) x updates_per_step (no gradient) */
+  lts_mlts_desc gen_mlts;         /* LTS_LEVELS_MLTS with generated levels: the tiers attached
+                                     to each (cell_tier must be NULL: the halving rule) */
 } lts_mlmc_opts;
 
 enum { LTS_LEVELS_GRID = 0, LTS_LEVELS_MESH = 1, LTS_LEVELS_MLTS = 2 };

@@ -466,10 +466,11 @@ class Context:
 
     def mlmc(self, level_ids, rule, eps, seed=0, alpha=2.0, L_start=2, N_init=(256, 64, 16, 8, 4),
              mode=LTS_MLMC_BATCHED, max_total_samples=0, gen_rule=None, n_levels_max=0, grad_K=None,
-             meshes=False, mlts=False):
+             meshes=False, mlts=False, gen_mlts=None):
         """Algorithm 1 (lts_mlmc); meshes=True: level_ids are triangle-mesh ids
         (lts_add_mesh); mlts=True: grid levels with tiers attached, solved by
-        multi-level LTS (lts_set_mlts).  With gen_rule and n_levels_max > len(level_ids)
+        multi-level LTS (lts_set_mlts); gen_mlts: the tier ratios attached to
+        generated levels (halving rule).  With gen_rule and n_levels_max > len(level_ids)
         the hierarchy grows on demand: level l beyond the given ones is built from
         gen_rule with n_base * 2^l when the bias test first asks for it.  With
         grad_K (checkpoint interval) the gradient dE[Q]/dg is estimated alongside
@@ -491,6 +492,8 @@ class Context:
         if gen_rule is not None:
             o.gen_rule = gen_rule
         o.level_kind = 1 if meshes else 2 if mlts else 0
+        if gen_mlts is not None:
+            o.gen_mlts, _ = _mlts_desc(gen_mlts, None)
         r = _lib.MLMCResult()
         nb = rule.n_blocks
         if grad_K is not None:

@@ -121,7 +121,7 @@ class MLMCOpts(C.Structure):
                 ("alpha", C.c_double), ("L_start", C.c_int32),
                 ("N_init", C.c_int32 * LTS_MAX_LEVELS), ("mode", C.c_int32),
                 ("max_total_samples", C.c_int32), ("n_levels_max", C.c_int32), ("gen_rule", RectRule),
-                ("level_kind", C.c_int32)]
+                ("level_kind", C.c_int32), ("gen_mlts", MltsDesc)]
 
 
 class MLMCResult(C.Structure):

@@ -164,8 +164,11 @@ lts_status mlmc_run(lts_ctx c, const lts_mlmc_opts* op, lts_mlmc_result* out, in
   if (o.level_kind != LTS_LEVELS_GRID && o.level_kind != LTS_LEVELS_MESH && o.level_kind != LTS_LEVELS_MLTS)
     return arg_fail(c, "bad level_kind");
   const bool meshes = o.level_kind == LTS_LEVELS_MESH, tiers = o.level_kind == LTS_LEVELS_MLTS;
-  if ((meshes || tiers) && (n_total > o.n_levels || dg))
-    return arg_fail(c, "triangle-mesh and multi-level LTS hierarchies are given in full and have no gradient form");
+  if (meshes && (n_total > o.n_levels || dg))
+    return arg_fail(c, "triangle-mesh hierarchies are given in full and have no gradient form");
+  if (tiers && dg) return arg_fail(c, "multi-level LTS has no gradient form");
+  if (tiers && n_total > o.n_levels && o.gen_mlts.cell_tier)
+    return arg_fail(c, "gen_mlts of generated levels must use the halving rule (cell_tier NULL)");
   for (int l = 0; l < o.n_levels; ++l) {
     if (o.level_ids[l] < 0 || o.level_ids[l] >= (int)(meshes ? c->meshes.size() : c->levels.size()))
       return arg_fail(c, "bad level id");
@@ -182,6 +185,9 @@ lts_status mlmc_run(lts_ctx c, const lts_mlmc_opts* op, lts_mlmc_result* out, in
       lts_level_info info;
       if (lts_rect_level_host(&g, &info, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr) != LTS_OK)
         return arg_fail(c, "gen_rule does not build level " + std::to_string(l));
+      lts_mlts_info mi;
+      if (tiers && lts_mlts_host(&g, &o.gen_mlts, &mi, nullptr) != LTS_OK)
+        return arg_fail(c, "gen_mlts does not fit generated level " + std::to_string(l));
     }
   }
   const int Lmax = n_total - 1;
@@ -194,6 +200,7 @@ lts_status mlmc_run(lts_ctx c, const lts_mlmc_opts* op, lts_mlmc_result* out, in
     int32_t id = -1;
     lts_status rr = lts_build_rect_level(c, &g, &id);
     if (rr != LTS_OK) return rr;
+    if (tiers && (rr = lts_set_mlts(c, id, &o.gen_mlts)) != LTS_OK) return rr;
     o.level_ids[l] = id;
     o.n_levels = l + 1;
     return LTS_OK;

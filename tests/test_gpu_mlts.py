@@ -153,7 +153,8 @@ def test_mlmc_with_multi_level_lts(ctx):
     with the five tiers (LTS_LEVELS_MLTS), T = 0.5 and the QoI over
     [-0.35,0.05]x[0.05,0.45] next to the graded corner: the same L, N_l,
     estimate, moments and cost model as the oracle's Algorithm 1 with the
-    oracle's multi-level LTS solves and the multi-level update count as cost."""
+    oracle's multi-level LTS solves and the multi-level update count as cost;
+    the same results with levels 1-2 generated on demand."""
     import math
 
     from oracle import mlmc
@@ -197,6 +198,11 @@ def test_mlmc_with_multi_level_lts(ctx):
     for l in range(res["L"] + 1):
         assert abs(res["mean"][l] - ores.mean[l]) <= 1e-11 * scale
         assert abs(res["var"][l] - ores.var[l]) <= 1e-9 * ores.var[l]
+    # the same hierarchy with levels 1 and 2 built (and given their tiers) when Algorithm 1 first needs them
+    rg = ctx.mlmc(ids[:1], _rule(0.5), eps=eps, N_init=N_init, L_start=1, mlts=True,
+                  gen_rule=P.graded_L_rule(16, qoi=qb), n_levels_max=3, gen_mlts=PS)
+    for k in ("L", "N", "estimate", "mean", "var", "cost"):
+        assert rg[k] == res[k], k
     with pytest.raises(P.LtsError):                    # a level without tiers
         lid = ctx.add_rect_level(P.graded_L_rule(16, qoi=qb))
         ctx.mlmc([lid] + ids[1:], _rule(0.5), eps=eps, N_init=N_init, L_start=1, mlts=True)
