@@ -46,6 +46,8 @@ struct AdjArgs {
   int s_active;                      // samples 0..s_active-1 take part
   const int* __restrict__ plist;     // grid index j * ld + i of every node of P
   int np;
+  const int* __restrict__ clist;     // cell index jb * ld + ia of every active cell with a corner in P
+  int nc;
   const double* __restrict__ rho;    // rho[m], m = 1..p: Lambda_m = rho_m Lambda_p off P
 };
 
@@ -169,15 +171,29 @@ struct ContractArgs {
   const double* Lam[kMaxAdjP + 2];   // Lam[m] = Lambda_m, m = 1..p
 };
 
+// LIST: one thread per entry of a.clist (the cells with a corner in P), grid
+// (entries, samples); otherwise one thread per cell of the grid.
+template <bool LIST>
 __global__ __launch_bounds__(256) void k_adj_contract(AdjArgs a, ContractArgs c,
                                                       const double* __restrict__ Y,
                                                       const double* __restrict__ LW,
                                                       double* __restrict__ G) {
-  const int s = blockIdx.z;
-  if (s >= a.s_active) return;
   const LevelView& L = a.L;
-  const int ia = blockIdx.x * BX + threadIdx.x, jb = blockIdx.y * BY + threadIdx.y;
-  if (ia >= L.nxn - 1 || jb >= L.nyn - 1) return;
+  int s, ia, jb;
+  if (LIST) {
+    s = blockIdx.y;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (s >= a.s_active || t >= a.nc) return;
+    const int kc0 = a.clist[t];
+    jb = kc0 / L.ld;
+    ia = kc0 - jb * L.ld;
+  } else {
+    s = blockIdx.z;
+    if (s >= a.s_active) return;
+    ia = blockIdx.x * BX + threadIdx.x;
+    jb = blockIdx.y * BY + threadIdx.y;
+    if (ia >= L.nxn - 1 || jb >= L.nyn - 1) return;
+  }
   const size_t kc = (size_t)jb * L.ld + ia;          // cell (ia, jb)
   if (L.cblk[kc] == 255) return;
   const size_t so = (size_t)s * a.sstride;
@@ -704,24 +720,35 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
   // Lambda_m = rho_m Lambda_p elsewhere: rho_p = 1, rho_p+1 = 0,
   // rho_m = (1 + beta_m) rho_m+1 - beta_m+1 rho_m+2 (beta_p := 0)
   {
-    std::vector<int> pl;
+    std::vector<int> pl, cl;
     for (int j = 0; j < lv.H.nyn; ++j)
       for (int i = 0; i < lv.H.nxn; ++i)
         if (lv.H.flags[(size_t)j * lv.H.nxn + i] & LTS_NODE_P) pl.push_back(j * lv.ld + i);
+    auto isP = [&](int i, int j) { return (lv.H.flags[(size_t)j * lv.H.nxn + i] & LTS_NODE_P) != 0; };
+    for (int b = 0; b + 1 < lv.H.nyn; ++b)
+      for (int i = 0; i + 1 < lv.H.nxn; ++i)
+        if (lv.H.active[(size_t)b * lv.H.nxc + i] && (isP(i, b) || isP(i + 1, b) || isP(i, b + 1) || isP(i + 1, b + 1)))
+          cl.push_back(b * lv.ld + i);
     std::vector<double> rho((size_t)p + 2, 0.0);
     rho[p] = 1.0;
     for (int m = p - 1; m >= 1; --m)
       rho[m] = (1.0 + lv.H.beta[m]) * rho[m + 1] - (m + 1 < p ? lv.H.beta[m + 1] : 0.0) * rho[m + 2];
-    LTS_HIP(c, c->adjlist.ensure(std::max<size_t>(pl.size() * sizeof(int) + rho.size() * sizeof(double) + 8, 16)));
+    LTS_HIP(c, c->adjlist.ensure(std::max<size_t>(
+                   (pl.size() + cl.size()) * sizeof(int) + rho.size() * sizeof(double) + 8, 16)));
     double* d_rho = c->adjlist.as<double>();
     int* d_pl = reinterpret_cast<int*>(d_rho + rho.size());
+    int* d_cl = d_pl + pl.size();
     LTS_HIP(c, hipMemcpyAsync(d_rho, rho.data(), rho.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     if (!pl.empty())
       LTS_HIP(c, hipMemcpyAsync(d_pl, pl.data(), pl.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    if (!cl.empty())
+      LTS_HIP(c, hipMemcpyAsync(d_cl, cl.data(), cl.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
     LTS_HIP(c, hipStreamSynchronize(c->stream));   // host vectors end with this scope
     a.rho = d_rho;
     a.plist = d_pl;
     a.np = (int)pl.size();
+    a.clist = d_cl;
+    a.nc = (int)cl.size();
   }
   const dim3 blk(BX, BY);
   auto grid = [&](int cols, int nz) { return dim3((cols + BX - 1) / BX, (Lv.nyn + BY - 1) / BY, nz); };
@@ -831,7 +858,11 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
         r = launch_adj_compact(c, lv, T, d_kappa, d_coef, y, mu1, nullptr, arr(l0), arr(ilw), a.rho, one, ss, act,
                                f, true, c->stream);
         if (r != LTS_OK) return r;
-        k_adj_contract<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, ca, y, arr(ilw), arr(iG));
+        // the cells with a corner in P from their list; the others by the closed form
+        if (a.nc > 0)
+          k_adj_contract<true><<<dim3((unsigned)((a.nc + 255) / 256), (unsigned)act), 256, 0, c->stream>>>(
+              a, ca, y, arr(ilw), arr(iG));
+        k_adj_cells<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, y, mu1, f, arr(iG));
         if (nn >= 1) {
           r = launch_step(c, lv, lv.tiling, d_kappa, d_coef, mu1, mu2, ss, 0, act, 0, c->stream);
           if (r != LTS_OK) return r;
@@ -852,7 +883,7 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
         for (int m = p - 1; m >= 0; --m)
           k_adj_rev<<<pgrid, 256, 0, c->stream>>>(a, m, arr(l0 + m), m + 1 < p ? arr(l0 + m + 1) : nullptr,
                                                   m > 0 ? arr(l0 + m - 1) : nullptr, arr(ilw), arr(l0 + p - 1));
-      k_adj_contract<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, ca, y, arr(ilw), arr(iG));
+      k_adj_contract<false><<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, ca, y, arr(ilw), arr(iG));
       // mu_n = 2 R mu_{n+1} - mu_{n+2}
       if (nn >= 1) {
         r = launch_step(c, lv, lv.tiling, d_kappa, d_coef, mu1, mu2, ss, 0, act, 0, c->stream);
