@@ -171,20 +171,27 @@ struct ContractArgs {
   const double* Lam[kMaxAdjP + 2];   // Lam[m] = Lambda_m, m = 1..p
 };
 
-// LIST: one thread per entry of a.clist (the cells with a corner in P), grid
-// (entries, samples); otherwise one thread per cell of the grid.
+// LIST: the cells of a.clist (those with a corner in P), grid (entries /
+// (256 / kContractLanes), samples); each cell's pairs are split over
+// kContractLanes adjacent lanes (pair m on lane m mod kContractLanes: that many
+// times the loads in flight per cell) whose sums are added by lane shuffles.
+// Otherwise one thread per cell of the grid.
+constexpr int kContractLanes = 16;
 template <bool LIST>
 __global__ __launch_bounds__(256) void k_adj_contract(AdjArgs a, ContractArgs c,
                                                       const double* __restrict__ Y,
                                                       const double* __restrict__ LW,
                                                       double* __restrict__ G) {
+  constexpr int NG = LIST ? kContractLanes : 1;      // lanes per cell
   const LevelView& L = a.L;
-  int s, ia, jb;
+  int s, ia, jb, g = 0;
+  bool on = true;
   if (LIST) {
     s = blockIdx.y;
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (s >= a.s_active || t >= a.nc) return;
-    const int kc0 = a.clist[t];
+    const int t = blockIdx.x * (256 / NG) + (int)(threadIdx.x / NG);
+    g = (int)(threadIdx.x % NG);
+    on = s < a.s_active && t < a.nc;
+    const int kc0 = a.clist[on ? t : 0];
     jb = kc0 / L.ld;
     ia = kc0 - jb * L.ld;
   } else {
@@ -193,9 +200,11 @@ __global__ __launch_bounds__(256) void k_adj_contract(AdjArgs a, ContractArgs c,
     ia = blockIdx.x * BX + threadIdx.x;
     jb = blockIdx.y * BY + threadIdx.y;
     if (ia >= L.nxn - 1 || jb >= L.nyn - 1) return;
+    const size_t kc = (size_t)jb * L.ld + ia;
+    if (L.cblk[kc] == 255) return;
   }
+  if (LIST && s >= a.s_active) s = 0;                // whole block off: read in bounds, write nothing
   const size_t kc = (size_t)jb * L.ld + ia;          // cell (ia, jb)
-  if (L.cblk[kc] == 255) return;
   const size_t so = (size_t)s * a.sstride;
   const size_t n00 = kc, n10 = kc + 1, n01 = kc + L.ld, n11 = kc + L.ld + 1;
   const double gx = L.hy[jb] * L.inv2hx[ia];   // bottom and top legs
@@ -215,11 +224,11 @@ __global__ __launch_bounds__(256) void k_adj_contract(AdjArgs a, ContractArgs c,
   // Lambda_m and lw are kept at the nodes of P only; off P, Lambda_m = rho_m
   // Lambda_p and lw = gamma Lambda_p with gamma = -(c1 rho_1 + sum_m c2_m rho_m+1)
   const double* __restrict__ lp = c.Lam[L.p] + so;
-  double gam = -cf[1] * a.rho[1];
-  for (int m = 1; m < L.p; ++m) gam -= cf[1 + m] * a.rho[m + 1];
   double acc = 0.0;
-  // (lw, (I - P) y)
-  {
+  // (lw, (I - P) y), on the first lane of the cell
+  if (g == 0) {
+    double gam = -cf[1] * a.rho[1];
+    for (int m = 1; m < L.p; ++m) gam -= cf[1 + m] * a.rho[m + 1];
     const double* lw = LW + so;
     auto lwv = [&](size_t n, bool pn) { return pn ? lw[n] : gam * lp[n]; };
     acc += side(lwv(n00, p00) * im00, lwv(n10, p10) * im10, lwv(n01, p01) * im01, lwv(n11, p11) * im11,
@@ -228,7 +237,7 @@ __global__ __launch_bounds__(256) void k_adj_contract(AdjArgs a, ContractArgs c,
   // (-c1 Lambda_1, P y) and (-c2_m Lambda_m+1, P (y + d_m)), m = 1..p-1: zero
   // unless a corner is in P
   if (p00 || p10 || p01 || p11) {
-    for (int m = 0; m < L.p; ++m) {
+    for (int m = g; m < L.p; m += NG) {
       const double cm = m == 0 ? cf[1] : cf[1 + m];
       const double rm = a.rho[m + 1];
       const double* la = c.Lam[m + 1] + so;
@@ -242,7 +251,13 @@ __global__ __launch_bounds__(256) void k_adj_contract(AdjArgs a, ContractArgs c,
                        q00, q10, q01, q11);
     }
   }
-  G[so + kc] += acc;
+  if (LIST) {
+#pragma unroll
+    for (int o = 1; o < NG; o <<= 1) acc += __shfl_xor(acc, o);
+    if (g == 0 && on) G[so + kc] += acc;
+  } else {
+    G[so + kc] += acc;
+  }
 }
 
 // mu_N = M^-1 w into buffer N_s % 2, 0 into the other.
@@ -860,7 +875,8 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
         if (r != LTS_OK) return r;
         // the cells with a corner in P from their list; the others by the closed form
         if (a.nc > 0)
-          k_adj_contract<true><<<dim3((unsigned)((a.nc + 255) / 256), (unsigned)act), 256, 0, c->stream>>>(
+          k_adj_contract<true><<<dim3((unsigned)((a.nc + 256 / kContractLanes - 1) / (256 / kContractLanes)),
+                                      (unsigned)act), 256, 0, c->stream>>>(
               a, ca, y, arr(ilw), arr(iG));
         k_adj_cells<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, y, mu1, f, arr(iG));
         if (nn >= 1) {
