@@ -17,7 +17,10 @@
 // accumulation is deterministic.  dQ/dg_b = 2 kappa_b sum_{cells of b} dQ/dkappa_cell.
 // Forward states are checkpointed every K steps (pairs (u_k, u_k+1)) and
 // recomputed one segment at a time with the forward step kernels; mu is
-// advanced by the forward step kernels too (the recurrence is the same).
+// advanced by the forward step kernels too (the recurrence is the same),
+// except on rect tilings, where the sweep of k_adj_fine already holds
+// R^T Lambda_p = Lambda_p + K (lw / m) and gives mu_n at the F+ nodes (the
+// coarse items give the other DOFs).
 // Per backward step: on rect tilings the fused k_adj_fine (below) and
 // k_adj_cells; on compact tilings the two substep sweeps run per compact
 // tile (launch_adj_compact in lts_fused.hip) and k_adj_contract contracts;
@@ -315,6 +318,16 @@ __global__ __launch_bounds__(256) void k_adj_blocks(AdjArgs a, const double* __r
 // forward q_m at >= m, Lambda_m+1 at >= p - m - 1), which covers the corners of
 // all owned cells.
 //
+// With mu_n+2 given, it also writes mu_n = 2 R mu_n+1 - mu_n+2 at the F+ nodes
+// of the tile interior.  R is M-self-adjoint, so R mu = M^-1 R^T M mu, and the
+// sweep started from Lambda_p = f M mu_n+1 yields R^T Lambda_p = Lambda_p +
+// K (lw / m) (the last term from the derivative of every substep in y; off P,
+// lw = gamma Lambda_p is the coarse update's weight):
+//   mu_n = 2 mu_n+1 - mu_n+2 + (2/f) M^-1 K (lw / m),
+// with lw / m exact at distance >= p - 1 from the region border, i.e. on the
+// interior and its ring.  This replaces the forward substeps of a fine step
+// on mu.
+//
 // The contraction of a pair (a, b) on cell (x, y) is
 //   hy/(2 hx) [(a00 - a10)(b00 - b10) + (a01 - a11)(b01 - b11)]
 // + hx/(2 hy) [(a00 - a01)(b00 - b01) + (a10 - a11)(b10 - b11)]
@@ -332,6 +345,7 @@ struct AdjTileArgs {
   const double* __restrict__ coef;   // [S][p+1]
   const double* __restrict__ Y;      // y = u_n of sample s at Y + s*sstride
   const double* __restrict__ MU;     // mu_n+1
+  double* MU2;                       // mu_n+2 in, mu_n out at the F+ nodes of the tile interiors (NULL: no mu step)
   double* __restrict__ G;            // per-cell accumulators
   double* __restrict__ scr;          // q_0 .. q_p-1 per (sample, tile)
   size_t sstride;
@@ -597,31 +611,52 @@ __global__ __launch_bounds__(kFineThreads) void k_adj_fine(AdjTileArgs a) {
       }
     }
   }
-  // ---- pair (lw, (I - P) y), then the cell sums
+  // ---- pair (lw, (I - P) y), then the cell sums; the mu step at the F+ nodes
+  //      of the tile interior
   {
-    double aw[R], vv[R];
+    double aw[R], vv[R], m1[R], m2[R];
+    const bool col_in = gx >= ix0 && gx < ix1;
+    uint32_t wmask = 0;                                // bit r: mu_n is written at row r
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       aw[r] = lw[r] * imr[r];
       const bool ok = wave_on && col_on && yb + r < RY && gyb + r < L.nyn;
-      vv[r] = (ok && !pr[r]) ? y_g[(gyb + r) * ld + gx] : 0.0;
+      const int k = (gyb + r) * ld + gx;
+      vv[r] = (ok && !pr[r]) ? y_g[k] : 0.0;
+      const bool wr = a.MU2 && ok && col_in && gyb + r >= iy0 && gyb + r < iy1 && (f[r] & F_FPLUS);
+      if (wr) wmask |= 1u << r;
+      m1[r] = wr ? mu_g[k] : 0.0;
+      m2[r] = wr ? a.MU2[(size_t)s * a.sstride + k] : 0.0;
     }
     // buffers of the parity not read in the last reverse step (m = 0 used parity 0)
     double* const tb = lb + kBndSlots;
     double* const bb = lb + 3 * kBndSlots;
     if (wave_on) {
       tb[top] = aw[0];
+      tb[bot] = aw[R - 1];
       bb[top] = vv[0];
     }
     __syncthreads();
     if (wave_on) {
       const double aN3 = tb[above], vN3 = bb[above];
+      double dNs = tb[below] - aw[0];                  // lw / m of the row below minus this row's
+      const double g2 = 2.0 / a.f;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const double dEa = aw[r] - lane_next(aw[r]), dEv = vv[r] - lane_next(vv[r]);
         const double dNa = aw[r] - (r + 1 < R ? aw[r + 1] : aN3), dNv = vv[r] - (r + 1 < R ? vv[r + 1] : vN3);
         SH[r] += dEa * dEv;
         SV[r] += dNa * dNv;
+        if (a.MU2) {
+          // the one-step map is M-self-adjoint, so R mu_n+1 = M^-1 R^T M mu_n+1;
+          // with Lambda_p = f M mu_n+1 the sweep gives R^T Lambda_p = Lambda_p + K (lw / m)
+          const double dWa = lane_prev(dEa);             // every lane takes part in the DPP
+          const double cW = lane_prev(cE[r]);
+          const double ka = cV[r] * -dNs + (cV[r + 1] * dNa + (cW * -dWa + cE[r] * dEa));
+          if (wmask & (1u << r))
+            a.MU2[(size_t)s * a.sstride + (size_t)(gyb + r) * ld + gx] = 2.0 * m1[r] - m2[r] + g2 * imr[r] * ka;
+        }
+        dNs = dNa;
       }
     }
   }
@@ -853,12 +888,15 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
         ta.scr = c->adjscr.as<double>();
         ta.sstride = ss;
         ta.f = f;
+        // mu_n = 2 R mu_n+1 - mu_n+2: its F+ part by the tile kernel (from the
+        // sweep it runs anyway), the other DOFs by the coarse items
+        ta.MU2 = nn >= 1 ? mu2 : nullptr;
         const long long Gw = (long long)T.n_fine * act;
         ta.per_xcd = (int)((Gw + 7) / 8);
         if (Gw > 0) k_adj_fine<<<dim3((unsigned)(8LL * ta.per_xcd)), dim3(kFineThreads), 0, c->stream>>>(ta);
         k_adj_cells<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, y, mu1, f, arr(iG));
         if (nn >= 1) {
-          r = launch_step(c, lv, lv.tiling, d_kappa, d_coef, mu1, mu2, ss, 0, act, 0, c->stream);
+          r = launch_coarse(c, lv, lv.tiling, d_kappa, d_coef, mu1, mu2, ss, act, 0, c->stream);
           if (r != LTS_OK) return r;
         }
         continue;
