@@ -687,6 +687,49 @@ __global__ __launch_bounds__(kFineThreads) void k_adj_fine(AdjTileArgs a) {
   }
 }
 
+// lw = gamma Lambda_p off P (no stencil acts there):
+// gamma = -(c1 rho_1 + sum_{m=1}^{p-1} c2_m rho_m+1), rho_p = 1, rho_p+1 = 0,
+// rho_m = (1 + beta_m) rho_m+1 - beta_m+1 rho_m+2.
+__device__ double adj_gamma(const LevelView& L, const double* __restrict__ cf) {
+  const int p = L.p;
+  double r1 = 1.0, r2 = 0.0, gam = 0.0;            // rho_m+1, rho_m+2
+  for (int m = p - 1; m >= 1; --m) {
+    gam -= cf[1 + m] * r1;
+    const double bm1 = m + 1 < p ? L.beta[m + 1] : 0.0;
+    const double rm = (1.0 + L.beta[m]) * r1 - bm1 * r2;
+    r2 = r1;
+    r1 = rm;
+  }
+  return gam - cf[1] * r1;
+}
+
+// The F+ part of the mu step on compact tilings, from the reverse sweep's lw
+// (as in k_adj_fine: R mu = M^-1 R^T M mu and R^T Lambda_p = Lambda_p + K (lw / m)):
+//   mu_n = 2 mu_n+1 - mu_n+2 + (2/f) M^-1 K (lw / m)
+// at the F+ DOFs (list), with lw / m from the sweep on P and gamma f mu_n+1
+// elsewhere.  mu_n overwrites mu_n+2; the coarse items give the other DOFs.
+__global__ __launch_bounds__(256) void k_adj_mu_fplus(AdjArgs a, const int* __restrict__ flist, int nf, double f,
+                                                      const double* __restrict__ MU1,
+                                                      const double* __restrict__ LW, double* __restrict__ MU2) {
+  const int s = blockIdx.z;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nf || s >= a.s_active) return;
+  const LevelView& L = a.L;
+  const size_t k = (size_t)flist[t];
+  const int j = (int)(k / (size_t)L.ld), i = (int)(k - (size_t)j * L.ld);
+  const size_t so = (size_t)s * a.sstride;
+  const double gf = adj_gamma(L, a.coef + (size_t)s * (L.p + 1)) * f;
+  const double* __restrict__ mu = MU1 + so;
+  const double* __restrict__ lw = LW + so;
+  auto lwm = [&](size_t kk) { return (L.flags[kk] & F_P) ? lw[kk] * L.invm[kk] : gf * mu[kk]; };
+  double cE, cW, cN, cS;
+  edge_coefs(L, a.kappa + (size_t)s * L.nb, i, j, cE, cW, cN, cS);
+  const double c = lwm(k);
+  const double ka = cE * (c - lwm(k + 1)) + cW * (c - lwm(k - 1)) + cN * (c - lwm(k + L.ld)) +
+                    cS * (c - lwm(k - L.ld));
+  MU2[so + k] = 2.0 * mu[k] - MU2[so + k] + (2.0 / f) * L.invm[k] * ka;
+}
+
 // Cells without a node of P: with lw / m = gamma f mu (gamma from the substep
 // scalars), only the pair (lw, (I - P) y) = (lw, y) contributes.
 __global__ __launch_bounds__(256) void k_adj_cells(AdjArgs a, const double* __restrict__ Y,
@@ -701,19 +744,7 @@ __global__ __launch_bounds__(256) void k_adj_cells(AdjArgs a, const double* __re
   if (L.cblk[kc] == 255) return;
   const size_t n00 = kc, n10 = kc + 1, n01 = kc + L.ld, n11 = kc + L.ld + 1;
   if ((L.flags[n00] | L.flags[n10] | L.flags[n01] | L.flags[n11]) & F_P) return;
-  // gamma = -(c1 rho_1 + sum_{m=1}^{p-1} c2_m rho_m+1), rho_p = 1, rho_p+1 = 0,
-  // rho_m = (1 + beta_m) rho_m+1 - beta_m+1 rho_m+2
-  const double* cf = a.coef + (size_t)s * (L.p + 1);
-  const int p = L.p;
-  double r1 = 1.0, r2 = 0.0, gam = 0.0;            // rho_m+1, rho_m+2
-  for (int m = p - 1; m >= 1; --m) {
-    gam -= cf[1 + m] * r1;
-    const double bm1 = m + 1 < p ? L.beta[m + 1] : 0.0;
-    const double rm = (1.0 + L.beta[m]) * r1 - bm1 * r2;
-    r2 = r1;
-    r1 = rm;
-  }
-  gam -= cf[1] * r1;
+  const double gam = adj_gamma(L, a.coef + (size_t)s * (L.p + 1));
   const size_t so = (size_t)s * a.sstride;
   const double* __restrict__ y = Y + so;
   const double* __restrict__ mu = MU + so;
@@ -766,14 +797,19 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
   a.kappa = d_kappa;
   a.coef = d_coef;
   a.sstride = ss;
+  int* d_fl = nullptr;                          // F+ DOFs (list), for the mu step on compact tilings
+  int nfl = 0;
   // the general backward step works on the nodes of P (list) and uses
   // Lambda_m = rho_m Lambda_p elsewhere: rho_p = 1, rho_p+1 = 0,
   // rho_m = (1 + beta_m) rho_m+1 - beta_m+1 rho_m+2 (beta_p := 0)
   {
-    std::vector<int> pl, cl;
+    std::vector<int> pl, cl, fl;
     for (int j = 0; j < lv.H.nyn; ++j)
-      for (int i = 0; i < lv.H.nxn; ++i)
-        if (lv.H.flags[(size_t)j * lv.H.nxn + i] & LTS_NODE_P) pl.push_back(j * lv.ld + i);
+      for (int i = 0; i < lv.H.nxn; ++i) {
+        const uint8_t fg = lv.H.flags[(size_t)j * lv.H.nxn + i];
+        if (fg & LTS_NODE_P) pl.push_back(j * lv.ld + i);
+        if ((fg & LTS_NODE_DOF) && (fg & LTS_NODE_FPLUS)) fl.push_back(j * lv.ld + i);
+      }
     auto isP = [&](int i, int j) { return (lv.H.flags[(size_t)j * lv.H.nxn + i] & LTS_NODE_P) != 0; };
     for (int b = 0; b + 1 < lv.H.nyn; ++b)
       for (int i = 0; i + 1 < lv.H.nxn; ++i)
@@ -784,15 +820,19 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
     for (int m = p - 1; m >= 1; --m)
       rho[m] = (1.0 + lv.H.beta[m]) * rho[m + 1] - (m + 1 < p ? lv.H.beta[m + 1] : 0.0) * rho[m + 2];
     LTS_HIP(c, c->adjlist.ensure(std::max<size_t>(
-                   (pl.size() + cl.size()) * sizeof(int) + rho.size() * sizeof(double) + 8, 16)));
+                   (pl.size() + cl.size() + fl.size()) * sizeof(int) + rho.size() * sizeof(double) + 8, 16)));
     double* d_rho = c->adjlist.as<double>();
     int* d_pl = reinterpret_cast<int*>(d_rho + rho.size());
     int* d_cl = d_pl + pl.size();
+    d_fl = d_cl + cl.size();
+    nfl = (int)fl.size();
     LTS_HIP(c, hipMemcpyAsync(d_rho, rho.data(), rho.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     if (!pl.empty())
       LTS_HIP(c, hipMemcpyAsync(d_pl, pl.data(), pl.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
     if (!cl.empty())
       LTS_HIP(c, hipMemcpyAsync(d_cl, cl.data(), cl.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    if (!fl.empty())
+      LTS_HIP(c, hipMemcpyAsync(d_fl, fl.data(), fl.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
     LTS_HIP(c, hipStreamSynchronize(c->stream));   // host vectors end with this scope
     a.rho = d_rho;
     a.plist = d_pl;
@@ -918,7 +958,11 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
               a, ca, y, arr(ilw), arr(iG));
         k_adj_cells<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, y, mu1, f, arr(iG));
         if (nn >= 1) {
-          r = launch_step(c, lv, lv.tiling, d_kappa, d_coef, mu1, mu2, ss, 0, act, 0, c->stream);
+          // mu_n: the F+ DOFs from the sweep's lw, the others by the coarse items
+          if (nfl > 0)
+            k_adj_mu_fplus<<<dim3((unsigned)((nfl + 255) / 256), 1, (unsigned)act), 256, 0, c->stream>>>(
+                a, d_fl, nfl, f, mu1, arr(ilw), mu2);
+          r = launch_coarse(c, lv, lv.tiling, d_kappa, d_coef, mu1, mu2, ss, act, 0, c->stream);
           if (r != LTS_OK) return r;
         }
         continue;
