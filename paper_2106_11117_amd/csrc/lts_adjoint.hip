@@ -52,6 +52,15 @@ struct AdjArgs {
   const int* __restrict__ clist;     // cell index jb * ld + ia of every active cell with a corner in P
   int nc;
   const double* __restrict__ rho;    // rho[m], m = 1..p: Lambda_m = rho_m Lambda_p off P
+  double* gam;                       // [S]: lw = gamma Lambda_p off P
+  // k_adj_cells sums its cells per workgroup and block: slot of each cell's
+  // block in its workgroup (255: cell not handled there), slots per workgroup,
+  // block of each slot, and the sums over the steps [S][n_wg][max_slots]
+  const uint8_t* __restrict__ cslot;
+  const int* __restrict__ wslots;
+  const int* __restrict__ wblock;
+  double* gpart;
+  int n_wg, max_slots;
 };
 
 // The P node of this thread (1D grid over the P list, z = sample); false past the end.
@@ -286,10 +295,14 @@ __global__ __launch_bounds__(256) void k_adj_blocks(AdjArgs a, const double* __r
   const LevelView& L = a.L;
   __shared__ double part[256];
   const double* g = G + (size_t)s * a.sstride;
+  const double* gp = a.gpart + (size_t)s * a.n_wg * a.max_slots;
   for (int b = 0; b < L.nb; ++b) {
     double acc = 0.0;
     for (int c = threadIdx.x; c < (L.nyn - 1) * L.ld; c += blockDim.x)
       if (L.cblk[c] == b) acc += g[c];
+    for (int w = threadIdx.x; w < a.n_wg; w += blockDim.x)
+      for (int t = 0; t < a.wslots[w]; ++t)
+        if (a.wblock[(size_t)w * a.max_slots + t] == b) acc += gp[(size_t)w * a.max_slots + t];
     part[threadIdx.x] = acc;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
@@ -703,6 +716,11 @@ __device__ double adj_gamma(const LevelView& L, const double* __restrict__ cf) {
   return gam - cf[1] * r1;
 }
 
+__global__ __launch_bounds__(256) void k_adj_gamma(AdjArgs a, int n) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) a.gam[s] = adj_gamma(a.L, a.coef + (size_t)s * (a.L.p + 1));
+}
+
 // The F+ part of the mu step on compact tilings, from the reverse sweep's lw
 // (as in k_adj_fine: R mu = M^-1 R^T M mu and R^T Lambda_p = Lambda_p + K (lw / m)):
 //   mu_n = 2 mu_n+1 - mu_n+2 + (2/f) M^-1 K (lw / m)
@@ -718,7 +736,7 @@ __global__ __launch_bounds__(256) void k_adj_mu_fplus(AdjArgs a, const int* __re
   const size_t k = (size_t)flist[t];
   const int j = (int)(k / (size_t)L.ld), i = (int)(k - (size_t)j * L.ld);
   const size_t so = (size_t)s * a.sstride;
-  const double gf = adj_gamma(L, a.coef + (size_t)s * (L.p + 1)) * f;
+  const double gf = a.gam[s] * f;
   const double* __restrict__ mu = MU1 + so;
   const double* __restrict__ lw = LW + so;
   auto lwm = [&](size_t kk) { return (L.flags[kk] & F_P) ? lw[kk] * L.invm[kk] : gf * mu[kk]; };
@@ -731,29 +749,47 @@ __global__ __launch_bounds__(256) void k_adj_mu_fplus(AdjArgs a, const int* __re
 }
 
 // Cells without a node of P: with lw / m = gamma f mu (gamma from the substep
-// scalars), only the pair (lw, (I - P) y) = (lw, y) contributes.
+// scalars), only the pair (lw, (I - P) y) = (lw, y) contributes.  The cells of
+// a workgroup are summed per block (a few blocks per workgroup) and the sums
+// accumulate over the steps in gpart, so no per-cell accumulator is read and
+// written every step.
 __global__ __launch_bounds__(256) void k_adj_cells(AdjArgs a, const double* __restrict__ Y,
-                                                   const double* __restrict__ MU, double f,
-                                                   double* __restrict__ G) {
+                                                   const double* __restrict__ MU, double f) {
   const int s = blockIdx.z;
   if (s >= a.s_active) return;
   const LevelView& L = a.L;
   const int ia = blockIdx.x * BX + threadIdx.x, jb = blockIdx.y * BY + threadIdx.y;
-  if (ia >= L.nxn - 1 || jb >= L.nyn - 1) return;
-  const size_t kc = (size_t)jb * L.ld + ia;
-  if (L.cblk[kc] == 255) return;
-  const size_t n00 = kc, n10 = kc + 1, n01 = kc + L.ld, n11 = kc + L.ld + 1;
-  if ((L.flags[n00] | L.flags[n10] | L.flags[n01] | L.flags[n11]) & F_P) return;
-  const double gam = adj_gamma(L, a.coef + (size_t)s * (L.p + 1));
-  const size_t so = (size_t)s * a.sstride;
-  const double* __restrict__ y = Y + so;
-  const double* __restrict__ mu = MU + so;
-  const double gx = L.hy[jb] * L.inv2hx[ia], gy = L.hx[ia] * L.inv2hy[jb];
-  const double a0 = mu[n00], a1 = mu[n10], a2 = mu[n01], a3 = mu[n11];
-  const double b0 = y[n00], b1 = y[n10], b2 = y[n01], b3 = y[n11];
-  const double sd = gx * ((a0 - a1) * (b0 - b1) + (a2 - a3) * (b2 - b3)) +
-                    gy * ((a0 - a2) * (b0 - b2) + (a1 - a3) * (b1 - b3));
-  G[so + kc] += gam * f * sd;
+  double v = 0.0;
+  int q = 255;
+  if (ia < L.nxn - 1 && jb < L.nyn - 1) {
+    const size_t kc = (size_t)jb * L.ld + ia;
+    q = a.cslot[kc];
+    if (q != 255) {
+      const size_t n00 = kc, n10 = kc + 1, n01 = kc + L.ld, n11 = kc + L.ld + 1;
+      const size_t so = (size_t)s * a.sstride;
+      const double* __restrict__ y = Y + so;
+      const double* __restrict__ mu = MU + so;
+      const double gx = L.hy[jb] * L.inv2hx[ia], gy = L.hx[ia] * L.inv2hy[jb];
+      const double a0 = mu[n00], a1 = mu[n10], a2 = mu[n01], a3 = mu[n11];
+      const double b0 = y[n00], b1 = y[n10], b2 = y[n01], b3 = y[n11];
+      const double sd = gx * ((a0 - a1) * (b0 - b1) + (a2 - a3) * (b2 - b3)) +
+                        gy * ((a0 - a2) * (b0 - b2) + (a1 - a3) * (b1 - b3));
+      v = a.gam[s] * f * sd;
+    }
+  }
+  // per-slot workgroup sums: wavefront shuffles, then the four wavefronts in a fixed order
+  __shared__ double part[BY];
+  const int wg = blockIdx.y * gridDim.x + blockIdx.x;
+  const int ns = a.wslots[wg];
+  double* gp = a.gpart + ((size_t)s * a.n_wg + wg) * a.max_slots;
+  for (int t = 0; t < ns; ++t) {
+    double x = q == t ? v : 0.0;
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    if (threadIdx.x == 0) part[threadIdx.y] = x;
+    __syncthreads();
+    if (threadIdx.x == 0 && threadIdx.y == 0) gp[t] += (part[0] + part[1]) + (part[2] + part[3]);
+    __syncthreads();
+  }
 }
 
 // p[0 .. n-1] = v with a grid-stride loop: the workspace can hold more than
@@ -819,13 +855,55 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
     rho[p] = 1.0;
     for (int m = p - 1; m >= 1; --m)
       rho[m] = (1.0 + lv.H.beta[m]) * rho[m + 1] - (m + 1 < p ? lv.H.beta[m + 1] : 0.0) * rho[m + 2];
-    LTS_HIP(c, c->adjlist.ensure(std::max<size_t>(
-                   (pl.size() + cl.size() + fl.size()) * sizeof(int) + rho.size() * sizeof(double) + 8, 16)));
+    // k_adj_cells: per workgroup of its grid (BX x BY cells), the blocks of
+    // the cells it handles (active, no corner in P) get slots 0, 1, ...
+    const int gxw = (lv.H.nxn + BX - 1) / BX, gyw = (lv.H.nyn + BY - 1) / BY;
+    const int n_wg = gxw * gyw;
+    std::vector<uint8_t> cslot((size_t)(lv.H.nyn - 1) * lv.ld, 255);
+    std::vector<std::vector<int>> wbl(n_wg);
+    for (int wy = 0; wy < gyw; ++wy)
+      for (int wx = 0; wx < gxw; ++wx) {
+        std::vector<int>& bl = wbl[(size_t)wy * gxw + wx];
+        for (int jb = wy * BY; jb < std::min((wy + 1) * BY, lv.H.nyn - 1); ++jb)
+          for (int ia = wx * BX; ia < std::min((wx + 1) * BX, lv.H.nxn - 1); ++ia) {
+            const size_t ci = (size_t)jb * lv.H.nxc + ia;
+            if (!lv.H.active[ci] || isP(ia, jb) || isP(ia + 1, jb) || isP(ia, jb + 1) || isP(ia + 1, jb + 1)) continue;
+            const int b = lv.H.block[ci];
+            const size_t t = (size_t)(std::find(bl.begin(), bl.end(), b) - bl.begin());
+            if (t == bl.size()) bl.push_back(b);
+            cslot[(size_t)jb * lv.ld + ia] = (uint8_t)t;
+          }
+      }
+    int max_slots = 1;
+    for (const auto& bl : wbl) max_slots = std::max(max_slots, (int)bl.size());
+    std::vector<int> wslots(n_wg), wblock((size_t)n_wg * max_slots, -1);
+    for (int w = 0; w < n_wg; ++w) {
+      wslots[w] = (int)wbl[w].size();
+      for (size_t t = 0; t < wbl[w].size(); ++t) wblock[(size_t)w * max_slots + t] = wbl[w][t];
+    }
+    const size_t n_gp = (size_t)n * n_wg * max_slots;
+    LTS_HIP(c, c->adjlist.ensure(
+                   (rho.size() + n + n_gp) * sizeof(double) +
+                   (pl.size() + cl.size() + fl.size() + wslots.size() + wblock.size()) * sizeof(int) + cslot.size() + 16));
     double* d_rho = c->adjlist.as<double>();
-    int* d_pl = reinterpret_cast<int*>(d_rho + rho.size());
+    a.gam = d_rho + rho.size();
+    a.gpart = a.gam + n;
+    int* d_pl = reinterpret_cast<int*>(a.gpart + n_gp);
     int* d_cl = d_pl + pl.size();
     d_fl = d_cl + cl.size();
     nfl = (int)fl.size();
+    int* d_ws = d_fl + fl.size();
+    int* d_wb = d_ws + wslots.size();
+    uint8_t* d_cs = reinterpret_cast<uint8_t*>(d_wb + wblock.size());
+    a.cslot = d_cs;
+    a.wslots = d_ws;
+    a.wblock = d_wb;
+    a.n_wg = n_wg;
+    a.max_slots = max_slots;
+    LTS_HIP(c, hipMemcpyAsync(d_ws, wslots.data(), wslots.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    LTS_HIP(c, hipMemcpyAsync(d_wb, wblock.data(), wblock.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    LTS_HIP(c, hipMemcpyAsync(d_cs, cslot.data(), cslot.size(), hipMemcpyHostToDevice, c->stream));
+    k_fill<<<(unsigned)std::min<size_t>((n_gp + 255) / 256, 65536), 256, 0, c->stream>>>(a.gpart, n_gp, 0.0);
     LTS_HIP(c, hipMemcpyAsync(d_rho, rho.data(), rho.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
     if (!pl.empty())
       LTS_HIP(c, hipMemcpyAsync(d_pl, pl.data(), pl.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
@@ -881,6 +959,7 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
                                                  (4 * kFineThreads) * sizeof(double), 8)));
   double* MU[2] = {arr(imu0), arr(imu1)};
   k_adj_mu_init<<<grid(Lv.ld, n), blk, 0, c->stream>>>(a, d_nsteps, MU[0], MU[1]);
+  k_adj_gamma<<<(n + 255) / 256, 256, 0, c->stream>>>(a, n);
   ContractArgs ca;
   for (int m = 1; m <= p; ++m) ca.D[m] = arr(d0 + m - 1);
   ca.D[0] = nullptr;
@@ -934,7 +1013,7 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
         const long long Gw = (long long)T.n_fine * act;
         ta.per_xcd = (int)((Gw + 7) / 8);
         if (Gw > 0) k_adj_fine<<<dim3((unsigned)(8LL * ta.per_xcd)), dim3(kFineThreads), 0, c->stream>>>(ta);
-        k_adj_cells<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, y, mu1, f, arr(iG));
+        k_adj_cells<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, y, mu1, f);
         if (nn >= 1) {
           r = launch_coarse(c, lv, lv.tiling, d_kappa, d_coef, mu1, mu2, ss, act, 0, c->stream);
           if (r != LTS_OK) return r;
@@ -956,7 +1035,7 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
           k_adj_contract<true><<<dim3((unsigned)((a.nc + 256 / kContractLanes - 1) / (256 / kContractLanes)),
                                       (unsigned)act), 256, 0, c->stream>>>(
               a, ca, y, arr(ilw), arr(iG));
-        k_adj_cells<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, y, mu1, f, arr(iG));
+        k_adj_cells<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, y, mu1, f);
         if (nn >= 1) {
           // mu_n: the F+ DOFs from the sweep's lw, the others by the coarse items
           if (nfl > 0)
