@@ -390,9 +390,14 @@ def mlts_bench(T: float = 2.0, per_level: bool = True, eps_list=MLMC_EPS, emit: 
         qm = np.asarray(ctx.mlts_forward(lid, *args))
         tm = time.perf_counter() - t0
         km = ctx.timing()["step_kernel_ms"]
+        ctx.mlts_forward(lid, *(a[:2] for a in args), precision=P.LTS_FP32_STEP)
+        t0 = time.perf_counter()
+        q32 = np.asarray(ctx.mlts_forward(lid, *args, precision=P.LTS_FP32_STEP))
+        t32 = time.perf_counter() - t0
+        k32 = ctx.timing()["step_kernel_ms"]
         steps = float(s["n_steps"].sum())
         upd_l = (info["n_dof"] - info["n_P"]) + info["p"] * info["n_P"]
-        print(f"level {lev}: lts {tl:.3f} s, mlts {tm:.3f} s", flush=True)
+        print(f"level {lev}: lts {tl:.3f} s, mlts {tm:.3f} s, mlts fp32 {t32:.3f} s", flush=True)
         out["runs"].append({
             "level": lev, "dofs": info["n_dof"], "samples": S, "sum_n_steps": int(steps),
             "n_P_tiers": mi["n_P"], "mlts_tiles": mi["n_tiles"], "mlts_halo_ratio": mi["halo_ratio"],
@@ -401,6 +406,9 @@ def mlts_bench(T: float = 2.0, per_level: bool = True, eps_list=MLMC_EPS, emit: 
                     "dof_updates_per_s": steps * upd_l / tl},
             "mlts": {"s": tm, "step_kernel_ms": km, "updates_per_step": mi["updates_per_step"],
                      "dof_updates_per_s": steps * mi["updates_per_step"] / tm},
+            "mlts_fp32": {"s": t32, "step_kernel_ms": k32,
+                          "dof_updates_per_s": steps * mi["updates_per_step"] / t32,
+                          "max_dq_vs_fp64_over_max_q": float(np.max(np.abs(q32 - qm)) / np.max(np.abs(qm)))},
             "speedup": tl / tm,
             "max_dq_over_max_q": float(np.max(np.abs(qm - ql)) / np.max(np.abs(ql)))})
     # Algorithm 1 on the five-level graded hierarchy: single-tier LTS (batched +

@@ -469,7 +469,8 @@ lts_status lts_mlts_host(const lts_rect_rule* rule, const lts_mlts_desc* desc, l
                          uint8_t* node_tier);
 
 /* Solve every sample on `level` with its tiers (contract of lts_forward: pulse
- * initial state, n_steps steps of dt, Q = sum qoi_w u(T)).  FP64 only.
+ * initial state, n_steps steps of dt, Q = sum qoi_w u(T)).  precision: LTS_FP64,
+ * or LTS_FP32_STEP (states and stepping in FP32, the QoI summed in FP64).
  * Errors as lts_forward; LTS_ERR_STATE if no tiers are attached. */
 lts_status lts_mlts_forward(lts_ctx ctx, int32_t level, const lts_samples* samples, int32_t precision,
                             double* Q_out);
@@ -516,7 +517,8 @@ enum { LTS_BATCH_GRAPH = 1,      /* capture the step loop into HIP graphs and re
  *    tiers (lts_set_mlts; LTS_ERR_STATE for a level without), the coarse DOFs
  *    and the fine tiles of all jobs in shared launches per step (with
  *    LTS_BATCH_GRAPH captured and replayed); QoIs bit-identical to
- *    lts_mlts_forward.  FP64; excludes LTS_BATCH_PERSIST and LTS_BATCH_AUTO.
+ *    lts_mlts_forward in the same precision (FP32 stepping with
+ *    LTS_BATCH_FP32); excludes LTS_BATCH_PERSIST and LTS_BATCH_AUTO.
  * Every form gives bit-identical QoIs.  Errors as lts_forward. */
 lts_status lts_batch_run(lts_ctx ctx, const lts_job* jobs, int32_t n_jobs, int32_t flags,
                          double* Q_out);

@@ -555,11 +555,11 @@ class Context:
         self._c(self.lib.lts_mlts_info_get(self.h, level, C.byref(info)))
         return _mlts_dict(info)
 
-    def mlts_forward(self, level, kappa, x0, n_steps, dt, width=0.05, g=None):
-        """Q of every sample with the level's tiers (FP64)."""
+    def mlts_forward(self, level, kappa, x0, n_steps, dt, width=0.05, g=None, precision=LTS_FP64):
+        """Q of every sample with the level's tiers (FP64, or LTS_FP32_STEP)."""
         sa = _SampleArgs(kappa, x0, n_steps, dt, width, g)
         q, qp = sa.out()
-        self._c(self.lib.lts_mlts_forward(self.h, level, C.byref(sa.s), LTS_FP64, qp))
+        self._c(self.lib.lts_mlts_forward(self.h, level, C.byref(sa.s), precision, qp))
         return q
 
     # --- one-dimensional workloads -------------------------------------------

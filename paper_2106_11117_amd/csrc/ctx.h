@@ -286,7 +286,7 @@ size_t mlts_record_size();
 void mlts_record(const DevLevel& lv, const double* d_kappa, const double* d_c0, double* B0, double* B1, void* out);
 void mlts_c0(const MltsDev& M, const double* dt, int n, double* c0);
 lts_status launch_mlts(lts_ctx c, const void* d_jobs, const std::vector<const MltsDev*>& M,
-                       const std::vector<int>& active, int step, hipStream_t stream);
+                       const std::vector<int>& active, int step, hipStream_t stream, bool fp32 = false);
 // The persistent form: steps 0 .. n_steps-1 of every job in cooperative
 // launches of one workgroup per CU with a grid barrier after each step
 // (see lts_fused.hip).  act_host[t * n_jobs + j] = active samples of job j at
@@ -320,9 +320,10 @@ size_t step_args_size();
 lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const double* d_kappa,
                        const double* d_coef, const double* Ucur, double* Uold, size_t sstride, int s0,
                        int active, int startup, hipStream_t stream, bool fp32 = false, double* Unew = nullptr);
-// The coarse-item launch of launch_step alone (FP64): the DOFs outside F+.
+// The coarse-item launch of launch_step alone: the DOFs outside F+ (FP32
+// states when fp32, the buffers then holding floats).
 lts_status launch_coarse(lts_ctx c, const DevLevel& lv, const TilingDev& T, const double* d_kappa,
                          const double* d_coef, const double* Ucur, double* Uold, size_t sstride, int active,
-                         int startup, hipStream_t stream);
+                         int startup, hipStream_t stream, bool fp32 = false);
 
 }  // namespace lts

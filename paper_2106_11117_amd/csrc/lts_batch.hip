@@ -222,8 +222,8 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
       ~(LTS_BATCH_GRAPH | LTS_BATCH_FP32 | LTS_BATCH_PERSIST | LTS_BATCH_SB_MASK | LTS_BATCH_AUTO | LTS_BATCH_MLTS))
     return arg_fail(c, "unknown flags");
   const bool mlts = (flags & LTS_BATCH_MLTS) != 0;
-  if (mlts && (flags & (LTS_BATCH_FP32 | LTS_BATCH_PERSIST | LTS_BATCH_SB_MASK | LTS_BATCH_AUTO)))
-    return arg_fail(c, "LTS_BATCH_MLTS runs in FP64 and excludes the persistent and automatic forms");
+  if (mlts && (flags & (LTS_BATCH_PERSIST | LTS_BATCH_SB_MASK | LTS_BATCH_AUTO)))
+    return arg_fail(c, "LTS_BATCH_MLTS excludes the persistent and automatic forms");
   const bool autof = (flags & LTS_BATCH_AUTO) != 0;
   if (autof && (flags & (LTS_BATCH_GRAPH | LTS_BATCH_PERSIST | LTS_BATCH_SB_MASK)))
     return arg_fail(c, "LTS_BATCH_AUTO excludes the other form flags");
@@ -364,7 +364,7 @@ extern "C" lts_status lts_batch_run(lts_ctx c, const lts_job* jobs, int32_t n_jo
         if ((rr = launch_multi_step(c, (const StepArgs*)c->b_jobs.p, T, act, t, c->stream, fp32, mlts ? 1 : 5)) !=
             LTS_OK)
           return rr;
-        if (mlts && (rr = launch_mlts(c, c->b_mjobs.p, Mv, act, t, c->stream)) != LTS_OK) return rr;
+        if (mlts && (rr = launch_mlts(c, c->b_mjobs.p, Mv, act, t, c->stream, fp32)) != LTS_OK) return rr;
       }
     }
     for (int j = 0; j < n_jobs && with_qoi; ++j) {

@@ -1574,7 +1574,7 @@ lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const 
 
 lts_status launch_coarse(lts_ctx c, const DevLevel& lv, const TilingDev& T, const double* d_kappa,
                          const double* d_coef, const double* Ucur, double* Uold, size_t sstride, int active,
-                         int startup, hipStream_t stream) {
+                         int startup, hipStream_t stream, bool fp32) {
   if (active <= 0 || T.n_coarse <= 0) return LTS_OK;
   StepArgs a{};
   a.L = lv.view();
@@ -1590,7 +1590,10 @@ lts_status launch_coarse(lts_ctx c, const DevLevel& lv, const TilingDev& T, cons
   a.startup = startup;
   const long long G = (long long)T.n_coarse * active;
   a.per_xcd = (int)((G + 7) / 8);
-  k_coarse<double><<<dim3((unsigned)(8LL * a.per_xcd)), dim3(kCoarseThreads), 0, stream>>>(a);
+  if (fp32)
+    k_coarse<float><<<dim3((unsigned)(8LL * a.per_xcd)), dim3(kCoarseThreads), 0, stream>>>(a);
+  else
+    k_coarse<double><<<dim3((unsigned)(8LL * a.per_xcd)), dim3(kCoarseThreads), 0, stream>>>(a);
   return LTS_OK;
 }
 

@@ -117,44 +117,45 @@ __device__ __forceinline__ MltsView job_view(const MltsJob& x) {
   return v;
 }
 
-// The state of a lane's region nodes.
+// The state of a lane's region nodes (T = double, or float for FP32 stepping).
+template <class T>
 struct MLane {
-  double F[kMT][kMNPT], e[kMT][kMNPT], ep[kMT][kMNPT];
-  double aE[kMNPT], aW[kMNPT], aN[kMNPT], aS[kMNPT];
+  T F[kMT][kMNPT], e[kMT][kMNPT], ep[kMT][kMNPT];
+  T aE[kMNPT], aW[kMNPT], aN[kMNPT], aS[kMNPT];
   uint32_t ad[kMNPT][4];                // LDS byte offsets of the E, W, N, S neighbours
   int dd[kMNPT], tp[kMNPT];             // distance to the tile, tier of P
 };
 
 // Tier J over the force S.F[J]: leaves its increment in S.e[J].
-template <int NT, int J>
-__device__ __forceinline__ void tier_run(const MltsView& x, MLane& S, double* __restrict__ lq, int& ph,
-                                         int& reach, double c0, int tid) {
+template <class T, int NT, int J>
+__device__ __forceinline__ void tier_run(const MltsView& x, MLane<T>& S, T* __restrict__ lq, int& ph,
+                                         int& reach, T c0, int tid) {
   constexpr int kCap = NT * kMNPT;
   const int p = x.p[J];
 #pragma unroll
-  for (int r = 0; r < kMNPT; ++r) S.e[J][r] = S.ep[J][r] = 0.0;
+  for (int r = 0; r < kMNPT; ++r) S.e[J][r] = S.ep[J][r] = (T)0;
   for (int m = 0; m < p; ++m) {
-    double Phi[kMNPT];
+    T Phi[kMNPT];
 #pragma unroll
     for (int r = 0; r < kMNPT; ++r) Phi[r] = S.F[J][r];
     if (m > 0) {
       // publish P_J e_m of the nodes the next reach still reads, then read the
       // neighbours' values
-      double* buf = lq + (ph & 1) * (kCap + 1);
+      T* buf = lq + (ph & 1) * (kCap + 1);
 #pragma unroll
       for (int r = 0; r < kMNPT; ++r)
-        if (S.dd[r] <= reach) buf[tid + r * NT] = S.tp[r] > J ? S.e[J][r] : 0.0;
+        if (S.dd[r] <= reach) buf[tid + r * NT] = S.tp[r] > J ? S.e[J][r] : (T)0;
       __syncthreads();
       --reach;
       const char* rb = reinterpret_cast<const char*>(buf);
 #pragma unroll
       for (int r = 0; r < kMNPT; ++r) {
         if (S.dd[r] > reach) continue;
-        const double qi = S.tp[r] > J ? S.e[J][r] : 0.0;
-        const double qE = *reinterpret_cast<const double*>(rb + S.ad[r][0]);
-        const double qW = *reinterpret_cast<const double*>(rb + S.ad[r][1]);
-        const double qN = *reinterpret_cast<const double*>(rb + S.ad[r][2]);
-        const double qS = *reinterpret_cast<const double*>(rb + S.ad[r][3]);
+        const T qi = S.tp[r] > J ? S.e[J][r] : (T)0;
+        const T qE = *reinterpret_cast<const T*>(rb + S.ad[r][0]);
+        const T qW = *reinterpret_cast<const T*>(rb + S.ad[r][1]);
+        const T qN = *reinterpret_cast<const T*>(rb + S.ad[r][2]);
+        const T qS = *reinterpret_cast<const T*>(rb + S.ad[r][3]);
         Phi[r] += S.aE[r] * (qi - qE) + S.aW[r] * (qi - qW) + S.aN[r] * (qi - qN) + S.aS[r] * (qi - qS);
       }
       ++ph;
@@ -166,7 +167,7 @@ __device__ __forceinline__ void tier_run(const MltsView& x, MLane& S, double* __
         inner = true;
 #pragma unroll
         for (int r = 0; r < kMNPT; ++r) S.F[J + 1][r] = Phi[r];
-        tier_run<NT, J + 1>(x, S, lq, ph, reach, c0, tid);
+        tier_run<T, NT, J + 1>(x, S, lq, ph, reach, c0, tid);
 #pragma unroll
         for (int r = 0; r < kMNPT; ++r) Phi[r] = S.e[J + 1][r];
       }
@@ -175,10 +176,10 @@ __device__ __forceinline__ void tier_run(const MltsView& x, MLane& S, double* __
 #pragma unroll
       for (int r = 0; r < kMNPT; ++r) Phi[r] = -c0 * Phi[r];
     }
-    const double b = x.beta[J * kMP + m];
+    const T b = (T)x.beta[J * kMP + m];
 #pragma unroll
     for (int r = 0; r < kMNPT; ++r) {
-      const double en = (1.0 + b) * (S.e[J][r] + Phi[r]) - b * S.ep[J][r];
+      const T en = ((T)1 + b) * (S.e[J][r] + Phi[r]) - b * S.ep[J][r];
       S.ep[J][r] = S.e[J][r];
       S.e[J][r] = en;
     }
@@ -200,11 +201,13 @@ __device__ __forceinline__ bool mlts_slot(const MltsLaunch& m, int& j, int& loca
 
 // One workgroup per (job, sample, fine tile); the tile's region nodes (F+
 // nodes within Manhattan distance K of the tile, by increasing distance) two
-// per lane.  Region entries as in the single-tier compact tiles.
-template <int NT>
+// per lane.  Region entries as in the single-tier compact tiles.  T: the type
+// of the states and of the stepping arithmetic (the edge coefficients are
+// formed in FP64 and rounded once).
+template <class T, int NT>
 __global__ __launch_bounds__(NT) void k_mlts(MltsLaunch m) {
   constexpr int kCap = NT * kMNPT;
-  __shared__ double lq[2 * (kCap + 1)];
+  __shared__ T lq[2 * (kCap + 1)];
   __shared__ double lk[256];
   __shared__ double lbeta[kMT * kMP];
   int jb, local;
@@ -220,59 +223,59 @@ __global__ __launch_bounds__(NT) void k_mlts(MltsLaunch m) {
   const int len = tl.y;
   const int ix0 = tl.z & 0xFFFF, ix1 = tl.z >> 16, iy0 = tl.w & 0xFFFF, iy1 = tl.w >> 16;
   const bool odd = m.step & 1, startup = m.step == 0;
-  const double* __restrict__ u = (odd ? x.B1 : x.B0) + (size_t)s * x.sstride;
-  double* uo = (odd ? x.B0 : x.B1) + (size_t)s * x.sstride;
+  const T* __restrict__ u = reinterpret_cast<const T*>(odd ? x.B1 : x.B0) + (size_t)s * x.sstride;
+  T* uo = reinterpret_cast<T*>(odd ? x.B0 : x.B1) + (size_t)s * x.sstride;
   const int ld = L.ld;
   int4 en[kMNPT];
 #pragma unroll
   for (int r = 0; r < kMNPT; ++r) en[r] = x.ent[tl.x + min(tid + r * NT, len - 1)];
   __syncthreads();                     // lk
-  MLane S;
-  double u0[kMNPT];
+  MLane<T> S;
+  T u0[kMNPT];
   int kk[kMNPT];
 #pragma unroll
   for (int r = 0; r < kMNPT; ++r) {
 #pragma unroll
-    for (int j = 0; j < kMT; ++j) S.F[j][r] = S.e[j][r] = S.ep[j][r] = 0.0;
-    S.aE[r] = S.aW[r] = S.aN[r] = S.aS[r] = 0.0;
+    for (int j = 0; j < kMT; ++j) S.F[j][r] = S.e[j][r] = S.ep[j][r] = (T)0;
+    S.aE[r] = S.aW[r] = S.aN[r] = S.aS[r] = (T)0;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) S.ad[r][t] = (uint32_t)(len * sizeof(double));
+    for (int t = 0; t < 4; ++t) S.ad[r][t] = (uint32_t)(len * sizeof(T));
     S.dd[r] = 1 << 30;                 // a lane past the region end: never within reach
     S.tp[r] = 0;
-    u0[r] = 0.0;
+    u0[r] = (T)0;
     kk[r] = 0;
     const int e = tid + r * NT;
     if (e >= len) continue;
     const size_t k = (size_t)(en[r].x & 0x7FFFFFFF);
     const int i = en[r].w & 0xFFFF, j = en[r].w >> 16;
     kk[r] = (int)k;
-    S.ad[r][0] = (uint32_t)(en[r].y & 0xFFFF) * sizeof(double);
-    S.ad[r][1] = ((uint32_t)en[r].y >> 16) * sizeof(double);
-    S.ad[r][2] = (uint32_t)(en[r].z & 0xFFFF) * sizeof(double);
-    S.ad[r][3] = ((uint32_t)en[r].z >> 16) * sizeof(double);
+    S.ad[r][0] = (uint32_t)(en[r].y & 0xFFFF) * sizeof(T);
+    S.ad[r][1] = ((uint32_t)en[r].y >> 16) * sizeof(T);
+    S.ad[r][2] = (uint32_t)(en[r].z & 0xFFFF) * sizeof(T);
+    S.ad[r][3] = ((uint32_t)en[r].z >> 16) * sizeof(T);
     S.dd[r] = max(max(ix0 - i, i - (ix1 - 1)), 0) + max(max(iy0 - j, j - (iy1 - 1)), 0);
     S.tp[r] = x.ptier[k];
     double cE, cW, cN, cS;
     edge_coefs(L, lk, i, j, cE, cW, cN, cS);
     const double im = L.invm[k];
-    S.aE[r] = im * cE;
-    S.aW[r] = im * cW;
-    S.aN[r] = im * cN;
-    S.aS[r] = im * cS;
+    S.aE[r] = (T)(im * cE);
+    S.aW[r] = (T)(im * cW);
+    S.aN[r] = (T)(im * cN);
+    S.aS[r] = (T)(im * cS);
     // tier 0's force A u_n from global memory (a neighbour off the DOFs holds 0)
-    const double uc = u[k];
+    const T uc = u[k];
     S.F[0][r] = S.aE[r] * (uc - u[k + 1]) + S.aW[r] * (uc - u[k - 1]) + S.aN[r] * (uc - u[k + ld]) +
                 S.aS[r] * (uc - u[k - ld]);
     u0[r] = uc;
   }
-  if (tid == 0) lq[len] = lq[kCap + 1 + len] = 0.0;   // slot of absent and non-P neighbours
+  if (tid == 0) lq[len] = lq[kCap + 1 + len] = (T)0;   // slot of absent and non-P neighbours
   int ph = 0, reach = x.K;
-  tier_run<NT, 0>(x, S, lq, ph, reach, x.c0[s], tid);
+  tier_run<T, NT, 0>(x, S, lq, ph, reach, (T)x.c0[s], tid);
 #pragma unroll
   for (int r = 0; r < kMNPT; ++r) {
     if (S.dd[r] != 0) continue;        // written back by the tile that owns the node
     const size_t k = (size_t)kk[r];
-    uo[k] = startup ? u0[r] + S.e[0][r] : 2.0 * u0[r] - uo[k] + 2.0 * S.e[0][r];
+    uo[k] = startup ? u0[r] + S.e[0][r] : (T)2 * u0[r] - uo[k] + (T)2 * S.e[0][r];
   }
 }
 
@@ -368,12 +371,13 @@ void fill_info(const MltsHost& M, lts_mlts_info* o) {
 
 int pitch_of(int nxn) { return (nxn + kMPitch - 1) / kMPitch * kMPitch; }
 
-lts_status mlts_solve(lts_ctx c, const DevLevel& lv, const Staged& st, const StagedDev& d, double width) {
+lts_status mlts_solve(lts_ctx c, const DevLevel& lv, const Staged& st, const StagedDev& d, double width, bool fp32) {
   MltsDev& M = *lv.mlts;
   const int n = st.n;
   const size_t sstride = lv.nodes;
-  LTS_HIP(c, c->st0.ensure((size_t)n * sstride * 8));
-  LTS_HIP(c, c->st1.ensure((size_t)n * sstride * 8));
+  const size_t es = fp32 ? sizeof(float) : sizeof(double);   // bytes per state value
+  LTS_HIP(c, c->st0.ensure((size_t)n * sstride * es));
+  LTS_HIP(c, c->st1.ensure((size_t)n * sstride * es));
   double* B[2] = {c->st0.as<double>(), c->st1.as<double>()};
   hipStream_t q = c->stream;
   M.c0_host.resize(n);
@@ -385,7 +389,7 @@ lts_status mlts_solve(lts_ctx c, const DevLevel& lv, const Staged& st, const Sta
   LTS_HIP(c, hipMemcpyAsync(M.c0.p, M.c0_host.data(), (size_t)n * 8, hipMemcpyHostToDevice, q));
   LTS_HIP(c, hipMemcpyAsync(M.rec.p, rec.data(), rec.size(), hipMemcpyHostToDevice, q));
   LTS_HIP(c, hipStreamSynchronize(q));               // the host copies may be released
-  lts_status r = init_states(c, lv, n, d.x0, width, B[0], B[1]);
+  lts_status r = init_states(c, lv, n, d.x0, width, B[0], B[1], fp32);
   if (r != LTS_OK) return r;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->timing) {
@@ -405,9 +409,9 @@ lts_status mlts_solve(lts_ctx c, const DevLevel& lv, const Staged& st, const Sta
   for (int t = 0; t < maxT; ++t) {
     while (act[0] > 0 && st.nsteps[act[0] - 1] <= t) --act[0];
     if ((r = launch_coarse(c, lv, M.tiling, d.kappa, d.coef, B[t & 1], B[(t + 1) & 1], sstride, act[0], t == 0,
-                           q)) != LTS_OK)
+                           q, fp32)) != LTS_OK)
       return r;
-    if ((r = launch_mlts(c, M.rec.p, Mv, act, t, q)) != LTS_OK) return r;
+    if ((r = launch_mlts(c, M.rec.p, Mv, act, t, q, fp32)) != LTS_OK) return r;
     ++launches;
   }
   LTS_HIP(c, hipGetLastError());
@@ -424,7 +428,7 @@ lts_status mlts_solve(lts_ctx c, const DevLevel& lv, const Staged& st, const Sta
   c->last.dof_updates = dofu;
   c->last.alg_bytes = 0.0;
   c->last.step_launches = launches;
-  return qoi_device(c, lv, n, d.nsteps, B[0], B[1], c->Qd.as<double>());
+  return qoi_device(c, lv, n, d.nsteps, B[0], B[1], c->Qd.as<double>(), fp32);
 }
 
 }  // namespace
@@ -462,7 +466,7 @@ void mlts_c0(const MltsDev& M, const double* dt, int n, double* c0) {
 }
 
 lts_status launch_mlts(lts_ctx c, const void* d_jobs, const std::vector<const MltsDev*>& M,
-                       const std::vector<int>& active, int step, hipStream_t stream) {
+                       const std::vector<int>& active, int step, hipStream_t stream, bool fp32) {
   const int nj = (int)M.size();
   if (nj > kMaxJobs) {
     c->err = "too many jobs in one batch";
@@ -486,9 +490,15 @@ lts_status launch_mlts(lts_ctx c, const void* d_jobs, const std::vector<const Ml
       m.chunk_off[q + 1] = m.chunk_off[q] + (m.wg_n[q] + 7) / 8;
     }
     const dim3 g((unsigned)(8 * m.chunk_off[n]));
-    if (nt == 256) k_mlts<256><<<g, 256, 0, stream>>>(m);
-    else if (nt == 512) k_mlts<512><<<g, 512, 0, stream>>>(m);
-    else k_mlts<kFineThreads><<<g, kFineThreads, 0, stream>>>(m);
+    if (fp32) {
+      if (nt == 256) k_mlts<float, 256><<<g, 256, 0, stream>>>(m);
+      else if (nt == 512) k_mlts<float, 512><<<g, 512, 0, stream>>>(m);
+      else k_mlts<float, kFineThreads><<<g, kFineThreads, 0, stream>>>(m);
+    } else {
+      if (nt == 256) k_mlts<double, 256><<<g, 256, 0, stream>>>(m);
+      else if (nt == 512) k_mlts<double, 512><<<g, 512, 0, stream>>>(m);
+      else k_mlts<double, kFineThreads><<<g, kFineThreads, 0, stream>>>(m);
+    }
   }
   return LTS_OK;
 }
@@ -593,7 +603,7 @@ lts_status lts_mlts_forward(lts_ctx c, int32_t level, const lts_samples* S, int3
     c->err = "no tiers attached to this level (lts_set_mlts)";
     return LTS_ERR_STATE;
   }
-  if (precision != LTS_FP64) return arg_fail(c, "multi-level LTS runs in FP64 only");
+  if (precision != LTS_FP64 && precision != LTS_FP32_STEP) return arg_fail(c, "bad precision");
   if (S && S->n > 0 && !Q_out) return arg_fail(c, "Q_out is NULL");
   Staged st;
   lts_status r = stage_samples(c, lv, S, st);
@@ -603,7 +613,7 @@ lts_status lts_mlts_forward(lts_ctx c, int32_t level, const lts_samples* S, int3
   StagedDev d;
   if ((r = ctx_staging(c, lv, st.n, d)) != LTS_OK) return r;
   if ((r = upload_staged(c, lv, st, S, d)) != LTS_OK) return r;
-  if ((r = mlts_solve(c, lv, st, d, S->width)) != LTS_OK) return r;
+  if ((r = mlts_solve(c, lv, st, d, S->width, precision == LTS_FP32_STEP)) != LTS_OK) return r;
   return finish_Q(c, st, c->Qd.as<double>(), d, Q_out);
 }
 

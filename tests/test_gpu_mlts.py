@@ -51,6 +51,15 @@ def oracle():
     return {(j[1], j[2], j[3]): r for j, r in zip(jobs, res)}
 
 
+def _fp32_bound(n_steps, stages):
+    """FP32 stepping: every coarse step applies `stages` binary32 recurrence and
+    stencil updates to O(|u|) values (relative rounding 2^-24 each), which add up
+    at most linearly in the stable, non-dissipative recurrence: |dQ| <= 4 n_s
+    stages 2^-24 sum_i w_i |u_i| (the bound of the single-tier FP32 tests with p
+    replaced by the innermost stage count)."""
+    return 4.0 * n_steps * stages * 2.0 ** -24
+
+
 def _check(q, ref):
     e = abs(q - ref["Q"]) / ref["abs_wu"]
     assert e <= TOL, (q, ref["Q"], e)
@@ -73,6 +82,13 @@ def test_graded_levels_0_2_at_T2(ctx, oracle):
         # (about 1e-5 of Q in the oracle on level 0)
         ql = ctx.forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"])
         assert np.max(np.abs(q - ql)) < 1e-3 * np.max(np.abs(ql))
+        # FP32 stepping against the FP64 oracle within the derived bound: every
+        # coarse step applies prod p_j innermost stages of binary32 updates
+        q32 = ctx.mlts_forward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"], precision=P.LTS_FP32_STEP)
+        for i in ii:
+            ref = oracle[(BASES[l], l, i)]
+            e = abs(q32[i] - ref["Q"]) / ref["abs_wu"]
+            assert 1e-12 < e <= _fp32_bound(ref["n_steps"], int(np.prod(PS))), (l, i, e)
 
 
 def test_one_tier_is_the_single_tier_solve(ctx):
@@ -234,11 +250,16 @@ def test_batched_form_is_bit_identical(ctx):
     for graph in (False, True, True):                 # the second graph run replays the cached graph
         q = ctx.batch_run(jobs, graph=graph, mlts=True)
         assert np.array_equal(q, want)
+    # FP32 stepping: batched (with and without the graph) equals the plain form bit for bit
+    want32 = np.concatenate([np.asarray(ctx.mlts_forward(j[0], *j[1:5], precision=P.LTS_FP32_STEP)) for j in jobs])
+    for graph in (False, True, True):
+        assert np.array_equal(ctx.batch_run(jobs, graph=graph, mlts=True, precision=P.LTS_FP32_STEP), want32)
+    assert not np.array_equal(want32, want)
     plain = ctx.add_rect_level(P.graded_L_rule(32))
     with pytest.raises(P.LtsError):
         ctx.batch_run([(plain,) + jobs[0][1:]], mlts=True)
     with pytest.raises(P.LtsError):
-        ctx.batch_run(jobs[:1], mlts=True, precision=P.LTS_FP32_STEP)
+        ctx.batch_run(jobs[:1], mlts=True, auto=True)
 
 
 def test_graded_levels_3_4_at_T2_in_the_bench_configuration(ctx):
