@@ -18,9 +18,10 @@
 // Forward states are checkpointed every K steps (pairs (u_k, u_k+1)) and
 // recomputed one segment at a time with the forward step kernels; mu is
 // advanced by the forward step kernels too (the recurrence is the same),
-// except on rect tilings, where the sweep of k_adj_fine already holds
-// R^T Lambda_p = Lambda_p + K (lw / m) and gives mu_n at the F+ nodes (the
-// coarse items give the other DOFs).
+// except at the F+ DOFs of levels with fine tiles: there the reverse sweep
+// already holds R^T Lambda_p = Lambda_p + K (lw / m), which gives mu_n
+// (k_adj_fine on rect tilings, k_adj_mu_fplus on compact ones; the coarse
+// items give the other DOFs).
 // Per backward step: on rect tilings the fused k_adj_fine (below) and
 // k_adj_cells; on compact tilings the two substep sweeps run per compact
 // tile (launch_adj_compact in lts_fused.hip) and k_adj_contract contracts;
