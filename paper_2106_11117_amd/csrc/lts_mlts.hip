@@ -204,8 +204,11 @@ __device__ __forceinline__ bool mlts_slot(const MltsLaunch& m, int& j, int& loca
 // per lane.  Region entries as in the single-tier compact tiles.  T: the type
 // of the states and of the stepping arithmetic (the edge coefficients are
 // formed in FP64 and rounded once).
-template <class T, int NT>
-__global__ __launch_bounds__(NT) void k_mlts(MltsLaunch m) {
+// OCC: at most 64 VGPRs (8 wavefronts per SIMD), so that two 1024-thread
+// workgroups share a CU (FP32 only: it spills a few values, which pays only
+// when a launch has more workgroups than CUs).
+template <class T, int NT, bool OCC = false>
+__global__ __launch_bounds__(NT, OCC ? 8 : 1) void k_mlts(MltsLaunch m) {
   constexpr int kCap = NT * kMNPT;
   __shared__ T lq[2 * (kCap + 1)];
   __shared__ double lk[256];
@@ -491,8 +494,11 @@ lts_status launch_mlts(lts_ctx c, const void* d_jobs, const std::vector<const Ml
     }
     const dim3 g((unsigned)(8 * m.chunk_off[n]));
     if (fp32) {
+      long long wgs = 0;
+      for (int q = 0; q < n; ++q) wgs += m.wg_n[q];
       if (nt == 256) k_mlts<float, 256><<<g, 256, 0, stream>>>(m);
       else if (nt == 512) k_mlts<float, 512><<<g, 512, 0, stream>>>(m);
+      else if (wgs > c->n_cu) k_mlts<float, kFineThreads, true><<<g, kFineThreads, 0, stream>>>(m);
       else k_mlts<float, kFineThreads><<<g, kFineThreads, 0, stream>>>(m);
     } else {
       if (nt == 256) k_mlts<double, 256><<<g, 256, 0, stream>>>(m);
