@@ -562,8 +562,11 @@ lts_status lts_moments(lts_ctx ctx, const double* x, int32_t n, int32_t ptr_kind
 
 /* dQ_dg[s][b] = dL/dg_b for L = sum_s dLdQ[s] Q_s, where g_b = log c_b =
  * log(kappa_b)/2, by the backward LF-LTS recurrence (the adjoint of the
- * forward recurrence, run from T to 0) with forward states recomputed from
- * checkpoints stored every K_ckpt steps.  dt and n_steps are held fixed.
+ * forward recurrence, run from T to 0) with the forward states restored from
+ * checkpoint pairs stored every K_ckpt steps: on levels with fine tiles by
+ * running the (time-symmetric) step backward from the pair above each
+ * segment, at most K_ckpt steps (rounding about K_ckpt eps max |u|), else by
+ * recomputing each segment forward.  dt and n_steps are held fixed.
  * Q_out (may be NULL) receives the forward QoIs.  FP64 only.
  * Errors: LTS_ERR_ARG, LTS_ERR_OOM, LTS_ERR_HIP. */
 lts_status lts_backward(lts_ctx ctx, int32_t level, const lts_samples* samples, const double* dLdQ,

@@ -302,11 +302,13 @@ lts_status launch_persist(lts_ctx c, const StepArgs* d_jobs, const std::vector<c
 // the nodes of P into D1 + (m-1)*astride; reverse = true runs the reverse
 // sweep from Lambda_p = f M mu (mu = MU; rho_m as in lts_adjoint.hip) and
 // writes Lambda_1 .. Lambda_p-1 into Lam1 + (m-1)*astride and lw into LW, at
-// the nodes of P (per sample at + s*sstride).
+// the nodes of P (per sample at + s*sstride).  With Ynew, the recompute also
+// writes y_n-1 = 2 R y - y_n+1 (y_n+1 = Yold) at the tiles' own F+ nodes.
 lts_status launch_adj_compact(lts_ctx c, const DevLevel& lv, const TilingDev& T, const double* d_kappa,
                               const double* d_coef, const double* Y, const double* MU, double* D1, double* Lam1,
                               double* LW, const double* rho, size_t astride, size_t sstride, int active, double f,
-                              bool reverse, hipStream_t stream);
+                              bool reverse, hipStream_t stream, const double* Yold = nullptr,
+                              double* Ynew = nullptr);
 // Largest S_b of a tiling: 0 in rect mode, else 1024 / (fewest threads holding its largest region).
 inline int persist_sb_max(const TilingDev& T) { return T.rect ? 0 : kFineThreads / T.nt; }
 // Writes the static step record of one job (step_args_size() bytes) to `out`.
@@ -324,6 +326,6 @@ lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const 
 // states when fp32, the buffers then holding floats).
 lts_status launch_coarse(lts_ctx c, const DevLevel& lv, const TilingDev& T, const double* d_kappa,
                          const double* d_coef, const double* Ucur, double* Uold, size_t sstride, int active,
-                         int startup, hipStream_t stream, bool fp32 = false);
+                         int startup, hipStream_t stream, bool fp32 = false, double* Unew = nullptr);
 
 }  // namespace lts

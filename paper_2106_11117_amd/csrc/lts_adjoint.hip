@@ -15,8 +15,11 @@
 // with leg weight g (hy/(2 hx) or hx/(2 hy)), g (a_i/m_i - a_j/m_j)(b_i - b_j),
 // with a = b = 0 on Dirichlet nodes.  One thread owns one cell, so the
 // accumulation is deterministic.  dQ/dg_b = 2 kappa_b sum_{cells of b} dQ/dkappa_cell.
-// Forward states are checkpointed every K steps (pairs (u_k, u_k+1)) and
-// recomputed one segment at a time with the forward step kernels; mu is
+// Forward states are checkpointed every K steps (pairs (u_k, u_k+1)); on
+// levels with fine tiles the backward step also runs the forward step
+// backward in time (u_n-1 = 2 R u_n - u_n+1, from R u_n's substeps, which it
+// forms anyway), starting each segment from exact states, else each segment
+// is recomputed forward with the step kernels; mu is
 // advanced by the forward step kernels too (the recurrence is the same),
 // except at the F+ DOFs of levels with fine tiles: there the reverse sweep
 // already holds R^T Lambda_p = Lambda_p + K (lw / m), which gives mu_n
@@ -332,6 +335,9 @@ __global__ __launch_bounds__(256) void k_adj_blocks(AdjArgs a, const double* __r
 // forward q_m at >= m, Lambda_m+1 at >= p - m - 1), which covers the corners of
 // all owned cells.
 //
+// With y_n+1 given, one more substep gives d_p on the interior and y_n-1 =
+// (2 y - y_n+1) + 2 d_p at its F+ nodes (the step run backward in time).
+//
 // With mu_n+2 given, it also writes mu_n = 2 R mu_n+1 - mu_n+2 at the F+ nodes
 // of the tile interior.  R is M-self-adjoint, so R mu = M^-1 R^T M mu, and the
 // sweep started from Lambda_p = f M mu_n+1 yields R^T Lambda_p = Lambda_p +
@@ -360,6 +366,8 @@ struct AdjTileArgs {
   const double* __restrict__ Y;      // y = u_n of sample s at Y + s*sstride
   const double* __restrict__ MU;     // mu_n+1
   double* MU2;                       // mu_n+2 in, mu_n out at the F+ nodes of the tile interiors (NULL: no mu step)
+  const double* Y1;                  // y_n+1 (read at the F+ nodes of the tile interiors), with
+  double* Y0;                        // y_n-1 = 2 R y - y_n+1 out there (NULL: not formed)
   double* __restrict__ G;            // per-cell accumulators
   double* __restrict__ scr;          // q_0 .. q_p-1 per (sample, tile)
   size_t sstride;
@@ -548,7 +556,7 @@ __global__ __launch_bounds__(kFineThreads) void k_adj_fine(AdjTileArgs a) {
         const double dn = (dc[r] + b * (dc[r] - dq[r])) - c * rr;
         dq[r] = dn;
         qn[r] = pm[r] * dn + up[r];
-        if (need_b(r)) scr[((size_t)(m + 1) * R + r) * kFineThreads + tid] = qn[r];   // q_m+1
+        if (need_b(r) && m + 1 < p) scr[((size_t)(m + 1) * R + r) * kFineThreads + tid] = qn[r];   // q_m+1
       }
 #pragma unroll
       for (int r = 0; r < R; ++r) q[r] = qn[r];
@@ -560,6 +568,22 @@ __global__ __launch_bounds__(kFineThreads) void k_adj_fine(AdjTileArgs a) {
   for (int m = 0; m < p - 1; m += 2) {
     fsub(m, std::integral_constant<int, 0>{});
     if (m + 1 < p - 1) fsub(m + 1, std::integral_constant<int, 1>{});
+  }
+  // the step run backward in time (the recurrence is symmetric): the last
+  // substep gives d_p on the interior, and y_n-1 = (2 y - y_n+1) + 2 d_p at its F+ nodes
+  if (a.Y0) {
+    if ((p - 1) & 1) fsub(p - 1, std::integral_constant<int, 1>{});
+    else fsub(p - 1, std::integral_constant<int, 0>{});
+    const double* dp = ((p - 1) & 1) ? d0 : d1;        // d_p: the register set substep p-1 wrote
+    const bool col_in = gx >= ix0 && gx < ix1;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool ok = wave_on && col_on && yb + r < RY && gyb + r < L.nyn;
+      if (ok && col_in && gyb + r >= iy0 && gyb + r < iy1 && (f[r] & F_FPLUS)) {
+        const size_t k = (size_t)s * a.sstride + (size_t)(gyb + r) * ld + gx;
+        a.Y0[k] = (2.0 * a.Y[k] - a.Y1[k]) + 2.0 * dp[r];
+      }
+    }
   }
 
   // ---- reverse sweep: Lambda_p = f M mu, Lambda_p+1 = 0; m = p-1 .. 0
@@ -966,28 +990,69 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
   ca.D[0] = nullptr;
   for (int m = 1; m <= p + 1; ++m) ca.Lam[m] = arr(l0 + m - 1);
   ca.Lam[0] = nullptr;
+  // Levels with fine tiles run the step backward in time instead of
+  // recomputing each segment forward: u_n-1 = 2 R u_n - u_n+1 is the same
+  // recurrence, and the backward step forms R u_n's substeps anyway, so it
+  // writes u_n-1 at the F+ nodes and the coarse items the rest.  Each segment
+  // starts from exact states: the checkpoint pair above it for the samples
+  // that continue from the segment above, a sample's last two states (still
+  // in the forward buffers) when it joins at its last step.  Levels without
+  // fine tiles recompute each segment forward from its checkpoint pair.
+  const bool recon = T.n_fine > 0;
+  auto count = [&](int last) {                  // samples with n_s - 1 >= last
+    int k = 0;
+    while (k < n && h_nsteps[k] - 1 >= last) ++k;
+    return k;
+  };
   for (int k0 = (n_ck - 1) * K; k0 >= 0; k0 -= K) {
     const int k1 = std::min(k0 + K - 1, maxn - 1);
-    // recompute the segment u_k0 .. u_k1 for every sample that reaches k0
     int seg_active = 0;
     while (seg_active < n && h_nsteps[seg_active] > k0) ++seg_active;
     if (seg_active == 0) continue;
-    const size_t sb = (size_t)seg_active * ss * sizeof(double);
-    LTS_HIP(c, hipMemcpyAsync(arr(seg0), arr(ck0 + 2 * (k0 / K)), sb, hipMemcpyDeviceToDevice, c->stream));
-    LTS_HIP(c, hipMemcpyAsync(arr(seg0 + 1), arr(ck0 + 2 * (k0 / K) + 1), sb, hipMemcpyDeviceToDevice, c->stream));
-    for (int jn = k0 + 1; jn < k1; ++jn) {
-      int act = 0;
-      while (act < n && h_nsteps[act] > jn) ++act;
-      if (act == 0) break;
-      // u_jn+1 out of place from u_jn and u_jn-1 (the segment keeps every state)
-      r = launch_step(c, lv, lv.tiling, d_kappa, d_coef, arr(seg0 + (jn - k0)), arr(seg0 + (jn - k0) - 1), ss, 0,
-                      act, 0, c->stream, false, arr(seg0 + (jn - k0) + 1));
-      if (r != LTS_OK) return r;
+    if (recon) {
+      // samples that continue from the segment above: u_k1+1 and u_k1+2 from
+      // the checkpoint pair at k1 + 1, then u_k1 by one step backward
+      const int cont = count(k1 + 1);
+      if (cont > 0) {
+        const size_t cb = (size_t)cont * ss * sizeof(double);
+        LTS_HIP(c, hipMemcpyAsync(arr(seg0 + (k1 + 1 - k0)), arr(ck0 + 2 * ((k1 + 1) / K)), cb,
+                                  hipMemcpyDeviceToDevice, c->stream));
+        r = launch_step(c, lv, lv.tiling, d_kappa, d_coef, arr(seg0 + (k1 + 1 - k0)), arr(ck0 + 2 * ((k1 + 1) / K) + 1),
+                        ss, 0, cont, 0, c->stream, false, arr(seg0 + (k1 - k0)));
+        if (r != LTS_OK) return r;
+      }
+    } else {
+      // recompute the segment u_k0 .. u_k1 for every sample that reaches k0
+      const size_t sb = (size_t)seg_active * ss * sizeof(double);
+      LTS_HIP(c, hipMemcpyAsync(arr(seg0), arr(ck0 + 2 * (k0 / K)), sb, hipMemcpyDeviceToDevice, c->stream));
+      LTS_HIP(c, hipMemcpyAsync(arr(seg0 + 1), arr(ck0 + 2 * (k0 / K) + 1), sb, hipMemcpyDeviceToDevice, c->stream));
+      for (int jn = k0 + 1; jn < k1; ++jn) {
+        int act = 0;
+        while (act < n && h_nsteps[act] > jn) ++act;
+        if (act == 0) break;
+        // u_jn+1 out of place from u_jn and u_jn-1 (the segment keeps every state)
+        r = launch_step(c, lv, lv.tiling, d_kappa, d_coef, arr(seg0 + (jn - k0)), arr(seg0 + (jn - k0) - 1), ss, 0,
+                        act, 0, c->stream, false, arr(seg0 + (jn - k0) + 1));
+        if (r != LTS_OK) return r;
+      }
     }
     for (int nn = k1; nn >= k0; --nn) {
-      int act = 0;
-      while (act < n && h_nsteps[act] - 1 >= nn) ++act;
+      const int act = count(nn);
       if (act == 0) continue;
+      if (recon) {
+        // samples whose last step is nn join with u_nn+1 = u_n_s and u_nn
+        const int prev = count(nn + 1);
+        if (act > prev) {
+          const size_t off = (size_t)prev * ss, jb = (size_t)(act - prev) * ss * sizeof(double);
+          LTS_HIP(c, hipMemcpyAsync(arr(seg0 + (nn + 1 - k0)) + off, B[(nn + 1) & 1] + off, jb,
+                                    hipMemcpyDeviceToDevice, c->stream));
+          LTS_HIP(c, hipMemcpyAsync(arr(seg0 + (nn - k0)) + off, B[nn & 1] + off, jb, hipMemcpyDeviceToDevice,
+                                    c->stream));
+        }
+      }
+      // u_nn-1 is formed (recon) while the segment has steps left below nn
+      const double* y1 = recon ? arr(seg0 + (nn + 1 - k0)) : nullptr;
+      double* y0 = recon && nn > k0 ? arr(seg0 + (nn - 1 - k0)) : nullptr;
       a.s_active = act;
       const double* y = arr(seg0 + (nn - k0));
       const double f = nn >= 1 ? 2.0 : 1.0;
@@ -1011,12 +1076,19 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
         // mu_n = 2 R mu_n+1 - mu_n+2: its F+ part by the tile kernel (from the
         // sweep it runs anyway), the other DOFs by the coarse items
         ta.MU2 = nn >= 1 ? mu2 : nullptr;
+        ta.Y1 = y1;
+        ta.Y0 = y0;
         const long long Gw = (long long)T.n_fine * act;
         ta.per_xcd = (int)((Gw + 7) / 8);
         if (Gw > 0) k_adj_fine<<<dim3((unsigned)(8LL * ta.per_xcd)), dim3(kFineThreads), 0, c->stream>>>(ta);
         k_adj_cells<<<grid(Lv.nxn, act), blk, 0, c->stream>>>(a, y, mu1, f);
         if (nn >= 1) {
           r = launch_coarse(c, lv, lv.tiling, d_kappa, d_coef, mu1, mu2, ss, act, 0, c->stream);
+          if (r != LTS_OK) return r;
+        }
+        if (y0) {
+          r = launch_coarse(c, lv, lv.tiling, d_kappa, d_coef, y, const_cast<double*>(y1), ss, act, 0, c->stream,
+                            false, y0);
           if (r != LTS_OK) return r;
         }
         continue;
@@ -1026,7 +1098,7 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
         // (d_1 .. d_p, then Lambda_1 .. Lambda_p-1 and lw, at the nodes of P)
         k_adj_lam_init<<<grid(Lv.ld, act), blk, 0, c->stream>>>(a, f, mu1, arr(l0 + p - 1), arr(ilw));
         r = launch_adj_compact(c, lv, T, d_kappa, d_coef, y, nullptr, arr(d0), nullptr, nullptr, nullptr, one, ss,
-                               act, f, false, c->stream);
+                               act, f, false, c->stream, y1, y0);
         if (r != LTS_OK) return r;
         r = launch_adj_compact(c, lv, T, d_kappa, d_coef, y, mu1, nullptr, arr(l0), arr(ilw), a.rho, one, ss, act,
                                f, true, c->stream);
@@ -1043,6 +1115,11 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
             k_adj_mu_fplus<<<dim3((unsigned)((nfl + 255) / 256), 1, (unsigned)act), 256, 0, c->stream>>>(
                 a, d_fl, nfl, f, mu1, arr(ilw), mu2);
           r = launch_coarse(c, lv, lv.tiling, d_kappa, d_coef, mu1, mu2, ss, act, 0, c->stream);
+          if (r != LTS_OK) return r;
+        }
+        if (y0) {
+          r = launch_coarse(c, lv, lv.tiling, d_kappa, d_coef, y, const_cast<double*>(y1), ss, act, 0, c->stream,
+                            false, y0);
           if (r != LTS_OK) return r;
         }
         continue;

@@ -304,7 +304,9 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_multi(MultiArgs m) {
 // touch no global memory and meet the same workgroup barriers (a persistent
 // workgroup runs several tiles of one level side by side).
 // ADJ (the adjoint's recompute of a step, FP64): every increment d_m+1 of the
-// tile's own nodes of P goes to st.Dout and u_n+1 is not written.
+// tile's own nodes of P goes to st.Dout, and u_n+1 is written only if
+// st.Unew is given (the adjoint runs the step backward in time: Uold = y_n+1,
+// Unew = y_n-1).
 template <class T, int NT, bool ADJ = false>
 __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepState& st, const double* __restrict__ lk,
                                                   T* __restrict__ lq, int s, int tile, int tid, bool on) {
@@ -418,7 +420,7 @@ __device__ __forceinline__ void fine_tile_compact(const StepArgs& a, const StepS
     substep(m + 1, std::integral_constant<int, 1>{});
   }
   if (m < p) substep(m, std::integral_constant<int, 0>{});
-  if (ADJ) return;
+  if (ADJ && st.Unew == nullptr) return;
   const T* dfin = (p & 1) ? d1 : d0;   // d_p
 #pragma unroll
   for (int r = 0; r < kNPT; ++r) {
@@ -1574,7 +1576,7 @@ lts_status launch_step(lts_ctx c, const DevLevel& lv, const TilingDev& T, const 
 
 lts_status launch_coarse(lts_ctx c, const DevLevel& lv, const TilingDev& T, const double* d_kappa,
                          const double* d_coef, const double* Ucur, double* Uold, size_t sstride, int active,
-                         int startup, hipStream_t stream, bool fp32) {
+                         int startup, hipStream_t stream, bool fp32, double* Unew) {
   if (active <= 0 || T.n_coarse <= 0) return LTS_OK;
   StepArgs a{};
   a.L = lv.view();
@@ -1585,7 +1587,7 @@ lts_status launch_coarse(lts_ctx c, const DevLevel& lv, const TilingDev& T, cons
   a.coef = d_coef;
   a.Ucur = Ucur;
   a.Uold = Uold;
-  a.Unew = Uold;
+  a.Unew = Unew ? Unew : Uold;
   a.sstride = sstride;
   a.startup = startup;
   const long long G = (long long)T.n_coarse * active;
@@ -1752,7 +1754,7 @@ lts_status launch_persist(lts_ctx c, const StepArgs* d_jobs, const std::vector<c
 lts_status launch_adj_compact(lts_ctx c, const DevLevel& lv, const TilingDev& T, const double* d_kappa,
                               const double* d_coef, const double* Y, const double* MU, double* D1, double* Lam1,
                               double* LW, const double* rho, size_t astride, size_t sstride, int active, double f,
-                              bool reverse, hipStream_t stream) {
+                              bool reverse, hipStream_t stream, const double* Yold, double* Ynew) {
   if (active <= 0 || T.n_fine == 0) return LTS_OK;
   if (T.rect) {
     c->err = "compact adjoint sweep on a rect tiling";
@@ -1780,7 +1782,7 @@ lts_status launch_adj_compact(lts_ctx c, const DevLevel& lv, const TilingDev& T,
   a.per_xcd = (int)((G + 7) / 8);
   const dim3 grid((unsigned)(8LL * a.per_xcd));
   if (!reverse) {
-    StepState st{Y, D1, D1, 0};
+    StepState st{Y, Yold ? const_cast<double*>(Yold) : D1, Ynew, 0};
     st.Dout = D1;
     st.dstride = astride;
     if (T.nt == 256) k_adj_fsweep<256><<<grid, dim3(256), 0, stream>>>(a, st);

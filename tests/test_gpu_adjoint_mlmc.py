@@ -36,12 +36,16 @@ def _case(n_base=16, T=0.3, n=3, level=0):
 
 @pytest.mark.parametrize("K,rect", [(1, True), (7, True), (64, True), (7, False)])
 def test_adjoint_matches_oracle(ctx, K, rect):
-    """Fused backward step on rect fine tiles, and the general per-kernel form
-    (compact tiling), against the oracle adjoint."""
+    """Fused backward step on rect fine tiles, and the compact-tile form, against
+    the oracle adjoint, at T = 1, when the pulse has reached the QoI box (Q of
+    order 1e-3).  The forward states are run backward in time from exact
+    checkpoint pairs, whose rounding (about K eps max |u|) stays far below the
+    tolerance there; at T = 0.3 a sample whose Q is still a 3e-12 precursor
+    tail sees 1.7e-9 of its 7e-11 gradient at K = 64."""
     lid = ctx.add_rect_level(P.box_rule(16))
     if not rect:
         ctx.set_tiling(lid, 16, 16, False)
-    lv, ops, s = _case()
+    lv, ops, s = _case(T=1.0)
     dl = np.array([1.0, -0.5, 2.0])
     q, g = ctx.backward(lid, s["kappa"], s["x0"], s["n_steps"], s["dt"], dl, K=K)
     assert len(set(s["n_steps"].tolist())) > 1
