@@ -48,8 +48,8 @@ HBM_PEAK_GBS = 8000.0
 # the algorithmic bytes on the profiled launches (all samples active), applied
 # to the average launch's 1.7105e9 algorithmic bytes.  Valid only for the
 # step-kernel sources the counters were taken with.
-TRAFFIC = {"bytes_per_launch": 1.3541 * 1.7105e9,
-           "sources_sha256": "d487d8d78bb9c6b331e190beca32ea38f7a2d92ab55c5b4d52beecc284a891e0"}
+TRAFFIC = {"bytes_per_launch": 1.3540 * 1.7105e9,
+           "sources_sha256": "12a494a876a68def51ec0258378ad6a3f88ded3a1d654705c27f852604a6bf0e"}
 STEP_SOURCES = ("lts_fused.hip", "fused.h", "device.h", "lts_step.hip")
 WORKLOAD = ("unit square 512x512 base refined 8x in (0.48,0.52): 442225 DOFs, |P|=204081, p=8, "
             "nu=0.01, 256 samples, 4x4 blocks sigma=0.25, T=1, FP64")
