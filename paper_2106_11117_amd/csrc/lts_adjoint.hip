@@ -242,13 +242,15 @@ __global__ __launch_bounds__(256) void k_adj_contract(AdjArgs a, ContractArgs c,
   const double* __restrict__ lp = c.Lam[L.p] + so;
   double acc = 0.0;
   // (lw, (I - P) y), on the first lane of the cell
+  // Lambda_p / m at the corners off P, read once (the pairs take rho_m+1 times it there)
+  const double t00 = p00 ? 0.0 : lp[n00] * im00, t10 = p10 ? 0.0 : lp[n10] * im10,
+               t01 = p01 ? 0.0 : lp[n01] * im01, t11 = p11 ? 0.0 : lp[n11] * im11;
   if (g == 0) {
-    double gam = -cf[1] * a.rho[1];
-    for (int m = 1; m < L.p; ++m) gam -= cf[1 + m] * a.rho[m + 1];
+    const double gam = a.gam[s];
     const double* lw = LW + so;
-    auto lwv = [&](size_t n, bool pn) { return pn ? lw[n] : gam * lp[n]; };
-    acc += side(lwv(n00, p00) * im00, lwv(n10, p10) * im10, lwv(n01, p01) * im01, lwv(n11, p11) * im11,
-                p00 ? 0.0 : y00, p10 ? 0.0 : y10, p01 ? 0.0 : y01, p11 ? 0.0 : y11);
+    auto lwv = [&](size_t n, bool pn, double im, double tn) { return pn ? lw[n] * im : gam * tn; };
+    acc += side(lwv(n00, p00, im00, t00), lwv(n10, p10, im10, t10), lwv(n01, p01, im01, t01),
+                lwv(n11, p11, im11, t11), p00 ? 0.0 : y00, p10 ? 0.0 : y10, p01 ? 0.0 : y01, p11 ? 0.0 : y11);
   }
   // (-c1 Lambda_1, P y) and (-c2_m Lambda_m+1, P (y + d_m)), m = 1..p-1: zero
   // unless a corner is in P
@@ -257,14 +259,14 @@ __global__ __launch_bounds__(256) void k_adj_contract(AdjArgs a, ContractArgs c,
       const double cm = m == 0 ? cf[1] : cf[1 + m];
       const double rm = a.rho[m + 1];
       const double* la = c.Lam[m + 1] + so;
-      auto lav = [&](size_t n, bool pn) { return pn ? la[n] : rm * lp[n]; };
+      auto lav = [&](size_t n, bool pn, double im, double tn) { return pn ? la[n] * im : rm * tn; };
       const double* dm = m == 0 ? nullptr : c.D[m] + so;
       const double q00 = p00 ? y00 + (dm ? dm[n00] : 0.0) : 0.0;
       const double q10 = p10 ? y10 + (dm ? dm[n10] : 0.0) : 0.0;
       const double q01 = p01 ? y01 + (dm ? dm[n01] : 0.0) : 0.0;
       const double q11 = p11 ? y11 + (dm ? dm[n11] : 0.0) : 0.0;
-      acc -= cm * side(lav(n00, p00) * im00, lav(n10, p10) * im10, lav(n01, p01) * im01, lav(n11, p11) * im11,
-                       q00, q10, q01, q11);
+      acc -= cm * side(lav(n00, p00, im00, t00), lav(n10, p10, im10, t10), lav(n01, p01, im01, t01),
+                       lav(n11, p11, im11, t11), q00, q10, q01, q11);
     }
   }
   if (LIST) {
