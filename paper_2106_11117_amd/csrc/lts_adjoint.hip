@@ -183,8 +183,9 @@ __global__ __launch_bounds__(256) void k_adj_rev(AdjArgs a, int m, const double*
 
 // Per-cell accumulation of dQ/dkappa_cell over the derivative pairs of one step.
 struct ContractArgs {
-  const double* D[kMaxAdjP + 1];     // D[m] = d_m, m = 1..p (D[0] unused: d_0 = 0)
-  const double* Lam[kMaxAdjP + 2];   // Lam[m] = Lambda_m, m = 1..p
+  const double* D1;                  // d_m at D1 + (m-1)*astride, m = 1..p (d_0 = 0)
+  const double* L1;                  // Lambda_m at L1 + (m-1)*astride, m = 1..p
+  size_t astride;
 };
 
 // LIST: the cells of a.clist (those with a corner in P), grid (entries /
@@ -239,7 +240,7 @@ __global__ __launch_bounds__(256) void k_adj_contract(AdjArgs a, ContractArgs c,
   };
   // Lambda_m and lw are kept at the nodes of P only; off P, Lambda_m = rho_m
   // Lambda_p and lw = gamma Lambda_p with gamma = -(c1 rho_1 + sum_m c2_m rho_m+1)
-  const double* __restrict__ lp = c.Lam[L.p] + so;
+  const double* __restrict__ lp = c.L1 + (size_t)(L.p - 1) * c.astride + so;
   double acc = 0.0;
   // (lw, (I - P) y), on the first lane of the cell
   // Lambda_p / m at the corners off P, read once (the pairs take rho_m+1 times it there)
@@ -258,9 +259,9 @@ __global__ __launch_bounds__(256) void k_adj_contract(AdjArgs a, ContractArgs c,
     for (int m = g; m < L.p; m += NG) {
       const double cm = m == 0 ? cf[1] : cf[1 + m];
       const double rm = a.rho[m + 1];
-      const double* la = c.Lam[m + 1] + so;
+      const double* la = c.L1 + (size_t)m * c.astride + so;
       auto lav = [&](size_t n, bool pn, double im, double tn) { return pn ? la[n] * im : rm * tn; };
-      const double* dm = m == 0 ? nullptr : c.D[m] + so;
+      const double* dm = m == 0 ? nullptr : c.D1 + (size_t)(m - 1) * c.astride + so;
       const double q00 = p00 ? y00 + (dm ? dm[n00] : 0.0) : 0.0;
       const double q10 = p10 ? y10 + (dm ? dm[n10] : 0.0) : 0.0;
       const double q01 = p01 ? y01 + (dm ? dm[n01] : 0.0) : 0.0;
@@ -988,10 +989,9 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
   k_adj_mu_init<<<grid(Lv.ld, n), blk, 0, c->stream>>>(a, d_nsteps, MU[0], MU[1]);
   k_adj_gamma<<<(n + 255) / 256, 256, 0, c->stream>>>(a, n);
   ContractArgs ca;
-  for (int m = 1; m <= p; ++m) ca.D[m] = arr(d0 + m - 1);
-  ca.D[0] = nullptr;
-  for (int m = 1; m <= p + 1; ++m) ca.Lam[m] = arr(l0 + m - 1);
-  ca.Lam[0] = nullptr;
+  ca.D1 = arr(d0);
+  ca.L1 = arr(l0);
+  ca.astride = one;
   // Levels with fine tiles run the step backward in time instead of
   // recomputing each segment forward: u_n-1 = 2 R u_n - u_n+1 is the same
   // recurrence, and the backward step forms R u_n's substeps anyway, so it
