@@ -221,6 +221,16 @@ __global__ __launch_bounds__(256) void k_adj_contract(AdjArgs a, ContractArgs c,
     if (L.cblk[kc] == 255) return;
   }
   if (LIST && s >= a.s_active) s = 0;                // whole block off: read in bounds, write nothing
+  // LIST: the workgroup's sample is uniform; its pair factors c_m and rho_m+1 go to LDS
+  __shared__ double lcr[LIST ? 2 * kMaxAdjP : 1];
+  if (LIST) {
+    const double* cs = a.coef + (size_t)s * (L.p + 1);
+    for (int m = (int)threadIdx.x; m < L.p; m += (int)blockDim.x) {
+      lcr[2 * m] = cs[1 + m];                        // c1 for m = 0, c2_m otherwise
+      lcr[2 * m + 1] = a.rho[m + 1];
+    }
+    __syncthreads();
+  }
   const size_t kc = (size_t)jb * L.ld + ia;          // cell (ia, jb)
   const size_t so = (size_t)s * a.sstride;
   const size_t n00 = kc, n10 = kc + 1, n01 = kc + L.ld, n11 = kc + L.ld + 1;
@@ -257,8 +267,8 @@ __global__ __launch_bounds__(256) void k_adj_contract(AdjArgs a, ContractArgs c,
   // unless a corner is in P
   if (p00 || p10 || p01 || p11) {
     for (int m = g; m < L.p; m += NG) {
-      const double cm = m == 0 ? cf[1] : cf[1 + m];
-      const double rm = a.rho[m + 1];
+      const double cm = LIST ? lcr[2 * m] : cf[1 + m];
+      const double rm = LIST ? lcr[2 * m + 1] : a.rho[m + 1];
       const double* la = c.L1 + (size_t)m * c.astride + so;
       auto lav = [&](size_t n, bool pn, double im, double tn) { return pn ? la[n] * im : rm * tn; };
       const double* dm = m == 0 ? nullptr : c.D1 + (size_t)(m - 1) * c.astride + so;
