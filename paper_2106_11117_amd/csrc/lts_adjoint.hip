@@ -186,6 +186,8 @@ struct ContractArgs {
   const double* D1;                  // d_m at D1 + (m-1)*astride, m = 1..p (d_0 = 0)
   const double* L1;                  // Lambda_m at L1 + (m-1)*astride, m = 1..p
   size_t astride;
+  const double* MU;                  // mu_n+1 (list form: Lambda_p / m = f mu, no Lambda_p array)
+  double f;
 };
 
 // LIST: the cells of a.clist (those with a corner in P), grid (entries /
@@ -251,11 +253,14 @@ __global__ __launch_bounds__(256) void k_adj_contract(AdjArgs a, ContractArgs c,
   // Lambda_m and lw are kept at the nodes of P only; off P, Lambda_m = rho_m
   // Lambda_p and lw = gamma Lambda_p with gamma = -(c1 rho_1 + sum_m c2_m rho_m+1)
   const double* __restrict__ lp = c.L1 + (size_t)(L.p - 1) * c.astride + so;
+  const double* __restrict__ mu = LIST ? c.MU + so : nullptr;
+  // Lambda_p / m at a corner: f mu in the list form, else from the Lambda_p array
+  auto tp = [&](size_t n, double im) { return LIST ? c.f * mu[n] : lp[n] * im; };
   double acc = 0.0;
   // (lw, (I - P) y), on the first lane of the cell
   // Lambda_p / m at the corners off P, read once (the pairs take rho_m+1 times it there)
-  const double t00 = p00 ? 0.0 : lp[n00] * im00, t10 = p10 ? 0.0 : lp[n10] * im10,
-               t01 = p01 ? 0.0 : lp[n01] * im01, t11 = p11 ? 0.0 : lp[n11] * im11;
+  const double t00 = p00 ? 0.0 : tp(n00, im00), t10 = p10 ? 0.0 : tp(n10, im10),
+               t01 = p01 ? 0.0 : tp(n01, im01), t11 = p11 ? 0.0 : tp(n11, im11);
   if (g == 0) {
     const double gam = a.gam[s];
     const double* lw = LW + so;
@@ -270,7 +275,10 @@ __global__ __launch_bounds__(256) void k_adj_contract(AdjArgs a, ContractArgs c,
       const double cm = LIST ? lcr[2 * m] : cf[1 + m];
       const double rm = LIST ? lcr[2 * m + 1] : a.rho[m + 1];
       const double* la = c.L1 + (size_t)m * c.astride + so;
-      auto lav = [&](size_t n, bool pn, double im, double tn) { return pn ? la[n] * im : rm * tn; };
+      const bool last = LIST && m + 1 == L.p;            // Lambda_p: f mu at the corners in P too
+      auto lav = [&](size_t n, bool pn, double im, double tn) {
+        return pn ? (last ? c.f * mu[n] : la[n] * im) : rm * tn;
+      };
       const double* dm = m == 0 ? nullptr : c.D1 + (size_t)(m - 1) * c.astride + so;
       const double q00 = p00 ? y00 + (dm ? dm[n00] : 0.0) : 0.0;
       const double q10 = p10 ? y10 + (dm ? dm[n10] : 0.0) : 0.0;
@@ -1002,6 +1010,8 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
   ca.D1 = arr(d0);
   ca.L1 = arr(l0);
   ca.astride = one;
+  ca.MU = nullptr;
+  ca.f = 0.0;
   // Levels with fine tiles run the step backward in time instead of
   // recomputing each segment forward: u_n-1 = 2 R u_n - u_n+1 is the same
   // recurrence, and the backward step forms R u_n's substeps anyway, so it
@@ -1106,9 +1116,12 @@ lts_status adjoint_device(lts_ctx c, const DevLevel& lv, int n, const double* d_
         continue;
       }
       if (!T.rect && T.n_fine > 0) {
-        // compact tiles: Lambda_p everywhere, then one launch per sweep
-        // (d_1 .. d_p, then Lambda_1 .. Lambda_p-1 and lw, at the nodes of P)
-        k_adj_lam_init<<<grid(Lv.ld, act), blk, 0, c->stream>>>(a, f, mu1, arr(l0 + p - 1), arr(ilw));
+        // compact tiles: one launch per sweep (d_1 .. d_p, then Lambda_1 ..
+        // Lambda_p-1 and lw, at the nodes of P); no Lambda_p array: the sweep
+        // and the contraction take Lambda_p / m = f mu, and the reverse sweep
+        // sets lw at every node of P
+        ca.MU = mu1;
+        ca.f = f;
         r = launch_adj_compact(c, lv, T, d_kappa, d_coef, y, nullptr, arr(d0), nullptr, nullptr, nullptr, one, ss,
                                act, f, false, c->stream, y1, y0);
         if (r != LTS_OK) return r;
